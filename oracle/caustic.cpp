@@ -1,0 +1,1006 @@
+// FP64 CPU oracle of the bound-driven caustic estimator.
+//
+// TEST INFRASTRUCTURE ONLY: the plain, slow, obviously correct definition the
+// GPU library is checked against (see oracle.h).  Every polynomial of a box is
+// rebuilt from scratch from the box corners with the Bernstein toolkit of
+// bern.cpp; nothing is blocked, fused or cached beyond what the method states.
+//
+// Section references are to "Bernstein Bounds for Caustics" (Sec. 4: bounds
+// of specular paths; Sec. 5: bound-driven sampling; Sec. 6.1: implementation).
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <functional>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "bern.hpp"
+#include "oracle.h"
+
+namespace orc {
+
+static const double kInf = std::numeric_limits<double>::infinity();
+
+// ---------------------------------------------------------------- vectors
+struct V3 {
+  double x = 0, y = 0, z = 0;
+};
+static V3 v3(double x, double y, double z) { return V3{x, y, z}; }
+static V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+static V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+static V3 operator*(double s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
+static double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static V3 cross(V3 a, V3 b) { return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
+static double norm(V3 a) { return std::sqrt(dot(a, a)); }
+
+// ---------------------------------------------------------------- one tuple
+// Geometry of one (emitter, triangle) tuple for the single-vertex chains.
+// Barycentric parameterisation of the specular vertex (Sec. 4.3, Eqs. eq_xi, eq_ni):
+// x1 = p0 + u e1 + v e2,  n = n0 + u (n1 - n0) + v (n2 - n0) (un-normalised).
+struct Tuple {
+  int chain = 0;
+  double eta = 1.0;
+  V3 p0, e1, e2, n0, dn1, dn2;
+  V3 ng;           // unit geometric normal, oriented to agree with the vertex normals
+  double a1 = 0;   // |e1 x e2| = |dx1/du1|
+  V3 x0;           // point light
+  double I0 = 1;
+  V3 q0, f1, f2;   // receiver
+  double ak = 0;   // |f1 x f2| = 1 / |du_k/dx_k|
+  bool front = false;  // light strictly on the front side of the triangle plane
+};
+
+static V3 col(const double* a, int64_t n, int64_t i, int row) {
+  return v3(a[(row + 0) * n + i], a[(row + 1) * n + i], a[(row + 2) * n + i]);
+}
+
+static Tuple make_tuple(const orc_scene* s, int64_t tuple) {
+  Tuple c;
+  const int64_t n = s->n_tri;
+  const int64_t e = tuple / n, t = tuple % n;
+  c.chain = s->chain;
+  c.eta = s->eta;
+  const V3 p0 = col(s->pos, n, t, 0), p1 = col(s->pos, n, t, 3), p2 = col(s->pos, n, t, 6);
+  const V3 n0 = col(s->nrm, n, t, 0), n1 = col(s->nrm, n, t, 3), n2 = col(s->nrm, n, t, 6);
+  c.p0 = p0;
+  c.e1 = p1 - p0;
+  c.e2 = p2 - p0;
+  c.n0 = n0;
+  c.dn1 = n1 - n0;
+  c.dn2 = n2 - n0;
+  const V3 g = cross(c.e1, c.e2);
+  c.a1 = norm(g);
+  c.ng = (1.0 / c.a1) * g;
+  if (dot(c.ng, n0 + n1 + n2) < 0) c.ng = -1.0 * c.ng;
+  c.x0 = col(s->epos, s->n_emit, e, 0);
+  c.I0 = s->eI[e];
+  c.q0 = v3(s->q0[0], s->q0[1], s->q0[2]);
+  c.f1 = v3(s->f1[0], s->f1[1], s->f1[2]);
+  c.f2 = v3(s->f2[0], s->f2[1], s->f2[2]);
+  c.ak = norm(cross(c.f1, c.f2));
+  c.front = dot(c.x0 - p0, c.ng) > 0.0;
+  return c;
+}
+
+// ---------------------------------------------------------------- exact path evaluation
+// Forward-mode derivative in (u, v): value and the two partials.
+struct D {
+  double v = 0, a = 0, b = 0;
+};
+static D dc(double v) { return D{v, 0, 0}; }
+static D operator+(D x, D y) { return D{x.v + y.v, x.a + y.a, x.b + y.b}; }
+static D operator-(D x, D y) { return D{x.v - y.v, x.a - y.a, x.b - y.b}; }
+static D operator*(D x, D y) { return D{x.v * y.v, x.a * y.v + x.v * y.a, x.b * y.v + x.v * y.b}; }
+static D operator/(D x, D y) {
+  const double q = x.v / y.v;
+  return D{q, (x.a - q * y.a) / y.v, (x.b - q * y.b) / y.v};
+}
+static D dsqrt(D x) {
+  const double r = std::sqrt(x.v);
+  return D{r, x.a / (2 * r), x.b / (2 * r)};
+}
+struct DV {
+  D x, y, z;
+};
+static DV dv_lin(V3 base, V3 du, V3 dv, double u, double v) {
+  DV r;
+  r.x = D{base.x + u * du.x + v * dv.x, du.x, dv.x};
+  r.y = D{base.y + u * du.y + v * dv.y, du.y, dv.y};
+  r.z = D{base.z + u * du.z + v * dv.z, du.z, dv.z};
+  return r;
+}
+static DV dvc(V3 a) { return DV{dc(a.x), dc(a.y), dc(a.z)}; }
+static DV operator-(DV a, DV b) { return DV{a.x - b.x, a.y - b.y, a.z - b.z}; }
+static DV operator*(D s, DV a) { return DV{s * a.x, s * a.y, s * a.z}; }
+static D ddot(DV a, DV b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static DV dcross(DV a, DV b) {
+  return DV{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+struct PathEval {
+  double uk = 0, vk = 0, t = 0;
+  double J[2][2] = {{0, 0}, {0, 0}};
+  double detJ = 0, Ek = 0, beta = 0, dn = 0;
+  V3 x1;
+  bool admissible = false;
+};
+
+// The receiver vertex of the path through barycentric (u, v): outgoing direction
+// by the unnormalised reflection / refraction law (Sec. 4.3, Eq. eq_refr_rational),
+// receiver coordinates by the triple-product ratios of Eq. eq_rct, and the
+// irradiance of the path E_k = I0 dOmega0/dA1 |dx1/du1| |du1/du_k| |du_k/dx_k|
+// (Sec. 4.4, Eq. eq_dwda) with dOmega0/dA1 = |n_g . d0| / |d0|^3, visibility and
+// Fresnel factors dropped (each is at most one).
+static PathEval eval_path(const Tuple& c, double u, double v) {
+  PathEval r;
+  const DV x1 = dv_lin(c.p0, c.e1, c.e2, u, v);
+  const DV n = dv_lin(c.n0, c.dn1, c.dn2, u, v);
+  const DV d0 = x1 - dvc(c.x0);
+  const D nn = ddot(n, n), dn = ddot(d0, n);
+  DV dt;
+  if (c.chain == 0) {
+    dt = nn * d0 - (dc(2.0) * dn) * n;
+  } else {
+    const D dd = ddot(d0, d0);
+    const D beta = dc(1.0 - c.eta * c.eta) * nn * dd + dc(c.eta * c.eta) * dn * dn;
+    r.beta = beta.v;
+    if (!(beta.v > 0.0)) {
+      r.x1 = v3(x1.x.v, x1.y.v, x1.z.v);
+      return r;  // total internal reflection: no refracted path
+    }
+    const D sq = dsqrt(beta);
+    dt = dc(c.eta) * (nn * d0 - dn * n) - sq * n;
+  }
+  const DV s = x1 - dvc(c.q0);
+  const DV cc = dcross(dt, dvc(c.f2));
+  const D Q = ddot(cc, dvc(c.f1));
+  const D Pu = ddot(cc, s);
+  const D Pv = ddot(dcross(s, dvc(c.f1)), dt);
+  const D Tn = ddot(dcross(s, dvc(c.f1)), dvc(c.f2));
+  const D uk = Pu / Q, vk = Pv / Q, t = Tn / Q;
+  r.uk = uk.v;
+  r.vk = vk.v;
+  r.t = t.v;
+  r.J[0][0] = uk.a;
+  r.J[0][1] = uk.b;
+  r.J[1][0] = vk.a;
+  r.J[1][1] = vk.b;
+  r.detJ = uk.a * vk.b - uk.b * vk.a;
+  r.dn = dn.v;
+  r.x1 = v3(x1.x.v, x1.y.v, x1.z.v);
+  const V3 d = r.x1 - c.x0;
+  const double dl = norm(d);
+  r.Ek = c.I0 * std::fabs(dot(c.ng, d)) / (dl * dl * dl) * c.a1 / (std::fabs(r.detJ) * c.ak);
+  bool ok = c.front && u >= 0.0 && v >= 0.0 && u + v <= 1.0 && r.t > 0.0;
+  if (c.chain == 1) ok = ok && r.beta > 0.0 && r.dn < 0.0;
+  r.admissible = ok && std::isfinite(r.uk) && std::isfinite(r.vk);
+  return r;
+}
+
+// ---------------------------------------------------------------- polynomials of a box
+struct BV {
+  Bern x, y, z;
+};
+static BV lin3(V3 base, V3 du, V3 dv, double u0, double u1, double v0, double v1) {
+  return BV{linear_on_box(base.x, du.x, dv.x, u0, u1, v0, v1), linear_on_box(base.y, du.y, dv.y, u0, u1, v0, v1),
+            linear_on_box(base.z, du.z, dv.z, u0, u1, v0, v1)};
+}
+static Bern dotB(const BV& a, const BV& b) { return add(add(mul(a.x, b.x), mul(a.y, b.y)), mul(a.z, b.z)); }
+static Bern dotC(const BV& a, V3 k) { return add(add(scale(a.x, k.x), scale(a.y, k.y)), scale(a.z, k.z)); }
+static BV crossC(const BV& a, V3 k) {  // a x k, k constant
+  return BV{sub(scale(a.y, k.z), scale(a.z, k.y)), sub(scale(a.z, k.x), scale(a.x, k.z)),
+            sub(scale(a.x, k.y), scale(a.y, k.x))};
+}
+static BV mulSV(const Bern& s, const BV& a) { return BV{mul(s, a.x), mul(s, a.y), mul(s, a.z)}; }
+static BV subV(const BV& a, const BV& b) { return BV{sub(a.x, b.x), sub(a.y, b.y), sub(a.z, b.z)}; }
+static BV scaleV(const BV& a, double k) { return BV{scale(a.x, k), scale(a.y, k), scale(a.z, k)}; }
+
+// Secant of sqrt on [blo, bhi]: r(x) = a x + b through both end points.  sqrt is
+// concave, so sqrt(x) - r(x) >= 0 on the interval; its maximum is where the
+// slope of sqrt equals a, i.e. sqrt(x*) = (sqrt(blo) + sqrt(bhi)) / 2, which gives
+// delta_hi = (sqrt(bhi) - sqrt(blo))^2 / (4 (sqrt(blo) + sqrt(bhi))).  This is the
+// on-the-fly linear approximant with remainder bounds of Sec. 4.3 (the paper
+// leaves the closed form to its supplement; this is one valid choice).
+static void sqrt_secant(double blo, double bhi, double* a, double* b, double* dlo, double* dhi) {
+  const double sa = std::sqrt(blo), sb = std::sqrt(bhi);
+  *a = 1.0 / (sa + sb);
+  *b = sa * sb / (sa + sb);
+  *dlo = 0.0;
+  *dhi = (sb - sa) * (sb - sa) / (4.0 * (sa + sb));
+}
+
+struct BoxBound {
+  bool live = false;
+  double uk[4] = {0, 1, 0, 1};  // u_lo, u_hi, v_lo, v_hi (clipped to [0,1]^2)
+  double E[2] = {0, kInf};
+  bool universal = false;
+  bool settled = false;  // unclipped position bound inside [0,1]^2 and t > 0 proven
+};
+
+// Clip a ratio bound to [0,1]; false if the intersection is empty.
+static bool clip01(const RatioBound& rb, double* lo, double* hi) {
+  if (rb.kind == kDirect) {
+    *lo = std::max(rb.lo, 0.0);
+    *hi = std::min(rb.hi, 1.0);
+    return *lo <= *hi;
+  }
+  if (rb.kind == kSplit) {  // (-inf, L] U [H, inf)
+    const bool left = rb.lo >= 0.0, right = rb.hi <= 1.0;
+    if (!left && !right) return false;
+    *lo = left ? 0.0 : std::max(rb.hi, 0.0);
+    *hi = right ? 1.0 : std::min(rb.lo, 1.0);
+    return true;
+  }
+  *lo = 0.0;
+  *hi = 1.0;
+  return true;
+}
+
+// Bound of |f| from a ratio bound of f.
+static void abs_bound(const RatioBound& rb, double* lo, double* hi) {
+  if (rb.kind == kDirect) {
+    const double a = std::fabs(rb.lo), b = std::fabs(rb.hi);
+    *lo = (rb.lo <= 0.0 && rb.hi >= 0.0) ? 0.0 : std::min(a, b);
+    *hi = std::max(a, b);
+  } else if (rb.kind == kSplit) {
+    *hi = kInf;
+    *lo = (rb.lo >= 0.0 || rb.hi <= 0.0) ? 0.0 : std::min(-rb.lo, rb.hi);
+  } else {
+    *lo = 0.0;
+    *hi = kInf;
+  }
+}
+
+// Position and irradiance bound of one box of the barycentric domain of u1
+// (Sec. 4.2: U_k and [E_lo, E_hi] from coefficient ratios).
+static BoxBound bound_box(const Tuple& c, double u0, double u1, double v0, double v1, bool want_irr, int flags) {
+  BoxBound bb;
+  if (!c.front) return bb;
+  if (u0 + v0 >= 1.0) return bb;  // box lies outside the triangle u + v <= 1
+  const double wu = u1 - u0, wv = v1 - v0;
+  const BV x1 = lin3(c.p0, c.e1, c.e2, u0, u1, v0, v1);
+  const BV n = lin3(c.n0, c.dn1, c.dn2, u0, u1, v0, v1);
+  const BV d0 = lin3(c.p0 - c.x0, c.e1, c.e2, u0, u1, v0, v1);
+  const BV s = lin3(c.p0 - c.q0, c.e1, c.e2, u0, u1, v0, v1);
+  const Bern nn = dotB(n, n), dn = dotB(d0, n);
+  (void)x1;
+
+  Bern Pu, Pv, Q;
+  // rows of M for the irradiance bound: (Q, Pu, Pv) and their total u-, v-derivatives
+  Bern Qu, Qv, Puu, Puv, Pvu, Pvv;
+  if (c.chain == 0) {
+    // reflection: d~ = (n.n) d0 - 2 (d0.n) n
+    const BV dt = subV(mulSV(nn, d0), mulSV(scale(dn, 2.0), n));
+    const BV cc = crossC(dt, c.f2);
+    Pu = dotB(cc, s);
+    Pv = dotB(crossC(s, c.f1), dt);
+    Q = dotC(cc, c.f1);
+    if (want_irr) {
+      Qu = scale(deriv(Q, 0), 1.0 / wu);
+      Qv = scale(deriv(Q, 1), 1.0 / wv);
+      Puu = scale(deriv(Pu, 0), 1.0 / wu);
+      Puv = scale(deriv(Pu, 1), 1.0 / wv);
+      Pvu = scale(deriv(Pv, 0), 1.0 / wu);
+      Pvv = scale(deriv(Pv, 1), 1.0 / wv);
+    }
+  } else {
+    // refraction: d~ = eta ((n.n) d0 - (d0.n) n) - sqrt(beta) n,
+    // beta = (1 - eta^2)(n.n)(d0.d0) + eta^2 (d0.n)^2
+    double dnlo, dnhi;
+    coef_range(dn, &dnlo, &dnhi);
+    if (dnlo >= 0.0) return bb;  // light reaches the back of the shading normal everywhere
+    const double eta = c.eta;
+    const Bern beta = add(scale(mul(nn, dotB(d0, d0)), 1.0 - eta * eta), scale(mul(dn, dn), eta * eta));
+    double blo, bhi;
+    coef_range(beta, &blo, &bhi);
+    if (bhi <= 0.0) return bb;  // total internal reflection everywhere
+    if (blo <= 0.0) {           // the square root cannot be bounded here: universal bound
+      bb.live = true;
+      bb.universal = true;
+      return bb;
+    }
+    // remainder variable xi1 on axis 2: sqrt(beta) -> a beta + b + (1 - xi1) dlo + xi1 dhi
+    double a, b, dlo, dhi;
+    sqrt_secant(blo, bhi, &a, &b, &dlo, &dhi);
+    Bern rt = add(scale(beta, a), Bern::constant(b));
+    if (!(flags & 2)) rt = add(rt, affine_axis(2, dlo, dhi));
+    const BV dt0 = scaleV(subV(mulSV(nn, d0), mulSV(dn, n)), eta);
+    const BV c0 = crossC(dt0, c.f2), c1 = crossC(n, c.f2);
+    const BV sf1 = crossC(s, c.f1);
+    const Bern P0u = dotB(c0, s), P1u = dotB(c1, s);
+    const Bern P0v = dotB(sf1, dt0), P1v = dotB(sf1, n);
+    const Bern Q0 = dotC(c0, c.f1), Q1 = dotC(c1, c.f1);
+    Pu = sub(P0u, mul(rt, P1u));
+    Pv = sub(P0v, mul(rt, P1v));
+    Q = sub(Q0, mul(rt, Q1));
+    if (want_irr) {
+      // Derivative-aware remainder: d sqrt(beta)/du = beta_u w with
+      // w = 1/(2 sqrt(beta)) in [1/(2 sqrt(bhi)), 1/(2 sqrt(blo))], carried by a
+      // second remainder variable xi2 on axis 3 (4D superset of the true values).
+      Bern w = affine_axis(3, 0.5 / std::sqrt(bhi), 0.5 / std::sqrt(blo));
+      if (flags & 2) w = Bern::constant(a);
+      const Bern bu = scale(deriv(beta, 0), 1.0 / wu), bv = scale(deriv(beta, 1), 1.0 / wv);
+      const Bern wbu = mul(w, bu), wbv = mul(w, bv);
+      auto total = [&](const Bern& X0, const Bern& X1, int axis, double width, const Bern& wb) {
+        const Bern X0d = scale(deriv(X0, axis), 1.0 / width), X1d = scale(deriv(X1, axis), 1.0 / width);
+        return sub(sub(X0d, mul(rt, X1d)), mul(wb, X1));
+      };
+      Qu = total(Q0, Q1, 0, wu, wbu);
+      Qv = total(Q0, Q1, 1, wv, wbv);
+      Puu = total(P0u, P1u, 0, wu, wbu);
+      Puv = total(P0u, P1u, 1, wv, wbv);
+      Pvu = total(P0v, P1v, 0, wu, wbu);
+      Pvv = total(P0v, P1v, 1, wv, wbv);
+    }
+  }
+  // ray parameter t = ((x1 - q0) x f1) . f2 / Q must be positive somewhere
+  const Bern Tn = dotC(crossC(s, c.f1), c.f2);
+  const RatioBound tb = ratio_bound(Tn, Q);
+  if (tb.kind == kDirect && tb.hi <= 0.0) return bb;
+  // position bound U_k (Sec. 4.2)
+  const RatioBound ub = ratio_bound(Pu, Q), vb = ratio_bound(Pv, Q);
+  if (!clip01(ub, &bb.uk[0], &bb.uk[1])) return bb;
+  if (!clip01(vb, &bb.uk[2], &bb.uk[3])) return bb;
+  bb.universal = (ub.kind == kUnbounded) || (vb.kind == kUnbounded);
+  bb.settled = ub.kind == kDirect && vb.kind == kDirect && ub.lo >= 0.0 && ub.hi <= 1.0 && vb.lo >= 0.0 &&
+               vb.hi <= 1.0 && tb.kind == kDirect && tb.lo > 0.0;
+  bb.live = true;
+  if (!want_irr) return bb;
+  // irradiance bound: det(du_k/du1) = det M / Q^3 with
+  // M = [[Q, Pu, Pv], [Q_u, Pu_u, Pv_u], [Q_v, Pu_v, Pv_v]] (Sec. 4.4, Eq. eq_irr_term3a)
+  const Bern detM = add(sub(mul(Q, sub(mul(Puu, Pvv), mul(Pvu, Puv))), mul(Pu, sub(mul(Qu, Pvv), mul(Pvu, Qv)))),
+                        mul(Pv, sub(mul(Qu, Puv), mul(Puu, Qv))));
+  const Bern Q3 = mul(mul(Q, Q), Q);
+  double rlo, rhi;
+  abs_bound(ratio_bound(Q3, detM), &rlo, &rhi);
+  // dOmega0/dA1 = |g| / h^(3/2) with g = n_g . d0 and h = d0 . d0, bounded factor-wise
+  double glo, ghi, hlo, hhi;
+  coef_range(dotC(d0, c.ng), &glo, &ghi);
+  coef_range(dotB(d0, d0), &hlo, &hhi);
+  const double aglo = (glo <= 0.0 && ghi >= 0.0) ? 0.0 : std::min(std::fabs(glo), std::fabs(ghi));
+  const double aghi = std::max(std::fabs(glo), std::fabs(ghi));
+  const double Glo = aglo / std::pow(hhi, 1.5);
+  const double Ghi = hlo > 0.0 ? aghi / std::pow(hlo, 1.5) : kInf;
+  const double k = c.I0 * c.a1 / c.ak;
+  bb.E[0] = (Glo == 0.0 || rlo == 0.0) ? 0.0 : k * Glo * rlo;
+  bb.E[1] = (std::isinf(Ghi) || std::isinf(rhi)) ? kInf : k * Ghi * rhi;
+  return bb;
+}
+
+// ---------------------------------------------------------------- build
+struct Leaf {
+  int64_t tuple;
+  int32_t depth;
+  int64_t iu, iv;
+  double box[4];  // u0, u1, v0, v1
+  double uk[4];
+  double E[2];
+  bool universal;
+};
+
+struct Root {
+  int64_t tuple;
+  double box[4];
+};
+
+struct Build {
+  orc_params p;
+  int64_t n_tuples = 0, n_tri = 0;
+  std::vector<Root> roots;
+  std::vector<Leaf> leaves;
+  std::vector<int64_t> leaf_begin;  // per tuple, into leaves (size n_tuples + 1)
+  std::vector<std::map<int64_t, double>> cells;  // per grid cell: tuple -> E~
+  int64_t boxes = 0;
+  const orc_scene* scene = nullptr;  // borrowed
+  // deep copies so the build owns its geometry
+  std::vector<double> pos, nrm, epos, eI;
+  orc_scene sc{};
+};
+
+static void parallel_for(int64_t n, int n_threads, const std::function<void(int64_t, int)>& fn);
+
+// Domain initialisation (Sec. 6.1): breadth-first subdivision of [0,1]^2 keeping
+// boxes whose position bound meets the receiver.  A box whose whole position
+// bound already lies inside [0,1]^2 with the ray parameter proven positive is
+// settled: it is kept without further refinement.  Descent stops when every
+// kept box is settled, when more than init_pieces boxes would be kept, or after
+// init_levels levels; the root box is the bounding box of the kept boxes.
+static bool init_domain(const Tuple& c, const orc_params& p, double root[4], int64_t* boxes) {
+  struct B {
+    int level;
+    int64_t iu, iv;
+    bool settled;
+  };
+  auto test = [&](int level, int64_t iu, int64_t iv, B* out) {
+    const double w = std::ldexp(1.0, -level);
+    ++*boxes;
+    const BoxBound bb = bound_box(c, iu * w, (iu + 1) * w, iv * w, (iv + 1) * w, false, p.flags);
+    *out = B{level, iu, iv, bb.settled};
+    return bb.live;
+  };
+  B b0;
+  if (!test(0, 0, 0, &b0)) return false;
+  std::vector<B> cur{b0};
+  for (int L = 1; L <= p.init_levels; ++L) {
+    bool all_settled = true;
+    for (const B& b : cur) all_settled = all_settled && b.settled;
+    if (all_settled) break;
+    std::vector<B> next;
+    for (const B& b : cur) {
+      if (b.settled) {
+        next.push_back(b);
+        continue;
+      }
+      for (int a = 0; a < 2; ++a)
+        for (int d = 0; d < 2; ++d) {
+          B ch;
+          if (test(b.level + 1, 2 * b.iu + a, 2 * b.iv + d, &ch)) next.push_back(ch);
+        }
+    }
+    if (next.empty()) return false;
+    if (int64_t(next.size()) > p.init_pieces) break;
+    cur.swap(next);
+  }
+  root[0] = root[2] = kInf;
+  root[1] = root[3] = -kInf;
+  for (const B& b : cur) {
+    const double w = std::ldexp(1.0, -b.level);
+    root[0] = std::min(root[0], b.iu * w);
+    root[1] = std::max(root[1], (b.iu + 1) * w);
+    root[2] = std::min(root[2], b.iv * w);
+    root[3] = std::max(root[3], (b.iv + 1) * w);
+  }
+  return true;
+}
+
+// Adaptive subdivision (Sec. 6.1): split a box into four at its midpoint until
+// the clipped position bound is smaller than sigma, the irradiance bound is
+// tighter than the ratio alpha, or the depth cap is reached.
+static void subdivide(const Tuple& c, int64_t tuple, const double root[4], int depth, int64_t iu, int64_t iv,
+                      const orc_params& p, std::vector<Leaf>* out, int64_t* boxes) {
+  const double fu = (root[1] - root[0]) * std::ldexp(1.0, -depth);
+  const double fv = (root[3] - root[2]) * std::ldexp(1.0, -depth);
+  const double u0 = root[0] + iu * fu, u1 = root[0] + (iu + 1) * fu;
+  const double v0 = root[2] + iv * fv, v1 = root[2] + (iv + 1) * fv;
+  ++*boxes;
+  const BoxBound bb = bound_box(c, u0, u1, v0, v1, true, p.flags);
+  if (!bb.live) return;
+  const double area = (bb.uk[1] - bb.uk[0]) * (bb.uk[3] - bb.uk[2]);
+  bool stop = depth >= p.max_depth;
+  if (!(p.flags & 1)) {
+    stop = stop || area < p.sigma;
+    stop = stop || (bb.E[0] > 0.0 && std::isfinite(bb.E[1]) && bb.E[1] < p.alpha * bb.E[0]);
+  }
+  if (stop) {
+    Leaf l;
+    l.tuple = tuple;
+    l.depth = depth;
+    l.iu = iu;
+    l.iv = iv;
+    l.box[0] = u0;
+    l.box[1] = u1;
+    l.box[2] = v0;
+    l.box[3] = v1;
+    std::memcpy(l.uk, bb.uk, sizeof(l.uk));
+    l.E[0] = bb.E[0];
+    l.E[1] = bb.E[1];
+    l.universal = bb.universal;
+    out->push_back(l);
+    return;
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int d = 0; d < 2; ++d) subdivide(c, tuple, root, depth + 1, 2 * iu + a, 2 * iv + d, p, out, boxes);
+}
+
+static int cell_of(double x, int G) { return std::min(G - 1, int(std::floor(x * G))); }
+
+static Build* build_all(const orc_scene* s, const orc_params* p, int n_threads) {
+  Build* B = new Build;
+  B->p = *p;
+  // own a copy of the scene arrays
+  const int64_t n = s->n_tri;
+  B->pos.assign(s->pos, s->pos + 9 * n);
+  B->nrm.assign(s->nrm, s->nrm + 9 * n);
+  B->epos.assign(s->epos, s->epos + 3 * s->n_emit);
+  B->eI.assign(s->eI, s->eI + s->n_emit);
+  B->sc = *s;
+  B->sc.pos = B->pos.data();
+  B->sc.nrm = B->nrm.data();
+  B->sc.epos = B->epos.data();
+  B->sc.eI = B->eI.data();
+  B->scene = &B->sc;
+  B->n_tri = n;
+  B->n_tuples = n * s->n_emit;
+  const int64_t T = B->n_tuples;
+  std::vector<std::vector<Leaf>> per(T);
+  std::vector<int> has_root(T, 0);
+  std::vector<std::array<double, 4>> roots(T);
+  std::vector<int64_t> boxes(std::max(1, n_threads), 0);
+  parallel_for(T, n_threads, [&](int64_t t, int worker) {
+    const Tuple c = make_tuple(&B->sc, t);
+    if (!c.front) return;
+    double root[4];
+    if (!init_domain(c, *p, root, &boxes[worker])) return;
+    has_root[t] = 1;
+    std::memcpy(roots[t].data(), root, sizeof(root));
+    subdivide(c, t, root, 0, 0, 0, *p, &per[t], &boxes[worker]);
+  });
+  for (int64_t b : boxes) B->boxes += b;
+  B->leaf_begin.assign(T + 1, 0);
+  for (int64_t t = 0; t < T; ++t) {
+    if (has_root[t]) B->roots.push_back(Root{t, {roots[t][0], roots[t][1], roots[t][2], roots[t][3]}});
+    B->leaf_begin[t] = int64_t(B->leaves.size());
+    B->leaves.insert(B->leaves.end(), per[t].begin(), per[t].end());
+  }
+  B->leaf_begin[T] = int64_t(B->leaves.size());
+  // Bound storage (Sec. 6.1): splat each leaf's irradiance bound into every grid
+  // cell its closed position bound touches; per (cell, tuple) keep the maximum
+  // (Eq. eq_pertuple_b with m = 1).
+  const int G = p->grid_res;
+  B->cells.assign(size_t(G) * G, {});
+  for (const Leaf& l : B->leaves) {
+    const int cu0 = cell_of(l.uk[0], G), cu1 = cell_of(l.uk[1], G);
+    const int cv0 = cell_of(l.uk[2], G), cv1 = cell_of(l.uk[3], G);
+    for (int cu = cu0; cu <= cu1; ++cu)
+      for (int cv = cv0; cv <= cv1; ++cv) {
+        auto& m = B->cells[size_t(cu) * G + cv];
+        auto it = m.find(l.tuple);
+        if (it == m.end())
+          m.emplace(l.tuple, l.E[1]);
+        else
+          it->second = std::max(it->second, l.E[1]);
+      }
+  }
+  return B;
+}
+
+// ---------------------------------------------------------------- threads
+static void parallel_for(int64_t n, int n_threads, const std::function<void(int64_t, int)>& fn) {
+  if (n_threads <= 1 || n < 2) {
+    for (int64_t i = 0; i < n; ++i) fn(i, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  std::atomic<int64_t> next{0};
+  for (int w = 0; w < n_threads; ++w)
+    th.emplace_back([&, w]() {
+      for (;;) {
+        const int64_t i = next.fetch_add(1);
+        if (i >= n) break;
+        fn(i, w);
+      }
+    });
+  for (auto& t : th) t.join();
+}
+
+// ---------------------------------------------------------------- sampling
+// Bound-optimal probabilities (Sec. 5.4): P_T = min(gamma E~_T, 1) with gamma
+// fixed by the expected sample count.  W' = min(W, |U|); unbounded entries take
+// P = 1; the finite positive entries share max(W' - n_inf, 1) expected samples
+// (at most one each), solved exactly by water-filling over the entries sorted
+// in decreasing order; entries with E~ = 0 take P = 0.
+static void probabilities(const double* Et, int64_t n, double W, double* P) {
+  const double Wp = std::min(W, double(n));
+  int64_t n_inf = 0;
+  std::vector<int64_t> fin;
+  for (int64_t i = 0; i < n; ++i) {
+    if (std::isinf(Et[i])) {
+      P[i] = 1.0;
+      ++n_inf;
+    } else if (Et[i] > 0.0) {
+      fin.push_back(i);
+    } else {
+      P[i] = 0.0;
+    }
+  }
+  if (fin.empty()) return;
+  double Wf = std::max(Wp - double(n_inf), 1.0);
+  Wf = std::min(Wf, double(fin.size()));
+  if (Wf >= double(fin.size())) {
+    for (int64_t i : fin) P[i] = 1.0;
+    return;
+  }
+  std::vector<int64_t> ord = fin;
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return Et[a] > Et[b]; });
+  const int64_t m = int64_t(ord.size());
+  std::vector<double> tail(m + 1, 0.0);  // tail[k] = sum_{i >= k} E~_(i)
+  for (int64_t k = m - 1; k >= 0; --k) tail[k] = tail[k + 1] + Et[ord[k]];
+  int64_t k = 0;
+  double gamma = 0.0;
+  for (; k < m; ++k) {
+    gamma = (Wf - double(k)) / tail[k];
+    if (gamma * Et[ord[k]] <= 1.0) break;
+  }
+  for (int64_t i = 0; i < m; ++i) P[ord[i]] = i < k ? 1.0 : std::min(gamma * Et[ord[i]], 1.0);
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as easy
+// as 1, 2, 3", SC 2011): ten rounds of two 32x32->64 multiplies with the
+// published multipliers and Weyl key increments.
+static void philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = uint64_t(0xD2511F53u) * c0;
+    const uint64_t p1 = uint64_t(0xCD9E8D57u) * c2;
+    const uint32_t hi0 = uint32_t(p0 >> 32), lo0 = uint32_t(p0);
+    const uint32_t hi1 = uint32_t(p1 >> 32), lo1 = uint32_t(p1);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// The rng() of Alg. 1, keyed by (seed, index of the point in its request,
+// tuple), so a result never depends on how requests are batched.
+static double uniform(uint64_t seed, uint64_t point, uint32_t tuple) {
+  const uint32_t ctr[4] = {uint32_t(point), uint32_t(point >> 32), tuple, 0u};
+  const uint32_t key[2] = {uint32_t(seed), uint32_t(seed >> 32)};
+  uint32_t o[4];
+  philox(ctr, key, o);
+  return double(o[0] >> 8) * (1.0 / 16777216.0);
+}
+
+// ---------------------------------------------------------------- roots
+struct RootHit {
+  double u, v, Ek, res;
+};
+
+static double residual(const Tuple& c, const PathEval& e, double us, double vs) {
+  return norm((e.uk - us) * c.f1 + (e.vk - vs) * c.f2);
+}
+
+// Newton's method on u_k(u1) = u_k* in the local triangle domain (Sec. 6.1,
+// root-finding).  Returns true when it converged to an admissible path.
+static bool newton(const Tuple& c, double us, double vs, double u, double v, const double lim[4], int max_it,
+                   double tol_stop, double tol_accept, RootHit* hit) {
+  PathEval e = eval_path(c, u, v);
+  for (int it = 0; it < max_it; ++it) {
+    if (!std::isfinite(e.uk) || !std::isfinite(e.vk)) return false;
+    if (residual(c, e, us, vs) < tol_stop) break;
+    const double ru = e.uk - us, rv = e.vk - vs;
+    const double det = e.detJ;
+    if (det == 0.0 || !std::isfinite(det)) return false;
+    const double du = (e.J[1][1] * ru - e.J[0][1] * rv) / det;
+    const double dv = (-e.J[1][0] * ru + e.J[0][0] * rv) / det;
+    u -= du;
+    v -= dv;
+    if (!(u >= lim[0] && u <= lim[1] && v >= lim[2] && v <= lim[3])) return false;
+    e = eval_path(c, u, v);
+  }
+  const double res = residual(c, e, us, vs);
+  if (!(res < tol_accept) || !e.admissible) return false;
+  *hit = RootHit{u, v, e.Ek, res};
+  return true;
+}
+
+static bool receiver_coords(const Tuple& c, V3 x, double* us, double* vs) {
+  const V3 r = x - c.q0;
+  const double a = dot(c.f1, c.f1), b = dot(c.f1, c.f2), d = dot(c.f2, c.f2);
+  const double r1 = dot(c.f1, r), r2 = dot(c.f2, r);
+  const double det = a * d - b * b;
+  *us = (d * r1 - b * r2) / det;
+  *vs = (a * r2 - b * r1) / det;
+  return *us >= 0.0 && *us <= 1.0 && *vs >= 0.0 && *vs <= 1.0;
+}
+
+static void add_unique(std::vector<RootHit>* roots, const RootHit& h, double tol) {
+  for (const RootHit& r : *roots)
+    if (std::fabs(r.u - h.u) <= tol && std::fabs(r.v - h.v) <= tol) return;
+  roots->push_back(h);
+}
+
+// Brute force: multi-start Newton from every point (i/L, j/L), i + j <= L, of a
+// barycentric lattice; no bound is consulted.
+static std::vector<RootHit> brute_roots(const Tuple& c, double us, double vs, int lattice) {
+  std::vector<RootHit> roots;
+  if (!c.front) return roots;
+  const double lim[4] = {-2.0, 3.0, -2.0, 3.0};
+  for (int i = 0; i <= lattice; ++i)
+    for (int j = 0; i + j <= lattice; ++j) {
+      RootHit h;
+      if (newton(c, us, vs, double(i) / lattice, double(j) / lattice, lim, 50, 1e-13, 1e-9, &h))
+        add_unique(&roots, h, 1e-9);
+    }
+  return roots;
+}
+
+// Deterministic initialisation from the bounds: one Newton start at the centre
+// of every leaf of the tuple whose position bound contains u_k*; a start that
+// moves farther than one box width outside its box is abandoned.
+static std::vector<RootHit> leaf_roots(const Build& B, const Tuple& c, int64_t tuple, double us, double vs) {
+  std::vector<RootHit> roots;
+  for (int64_t k = B.leaf_begin[tuple]; k < B.leaf_begin[tuple + 1]; ++k) {
+    const Leaf& l = B.leaves[k];
+    if (!(us >= l.uk[0] && us <= l.uk[1] && vs >= l.uk[2] && vs <= l.uk[3])) continue;
+    const double wu = l.box[1] - l.box[0], wv = l.box[3] - l.box[2];
+    const double lim[4] = {l.box[0] - wu, l.box[1] + wu, l.box[2] - wv, l.box[3] + wv};
+    RootHit h;
+    if (newton(c, us, vs, 0.5 * (l.box[0] + l.box[1]), 0.5 * (l.box[2] + l.box[3]), lim, 20, 1e-13, 1e-6, &h))
+      add_unique(&roots, h, 1e-7);
+  }
+  return roots;
+}
+
+}  // namespace orc
+
+// ================================================================= C ABI
+using namespace orc;
+
+extern "C" {
+
+int orc_eval_path(const orc_scene* s, int64_t tuple, double u, double v, double* out) {
+  if (!s || !out || tuple < 0 || tuple >= s->n_tri * s->n_emit) return -1;
+  const Tuple c = make_tuple(s, tuple);
+  const PathEval e = eval_path(c, u, v);
+  out[0] = e.uk;
+  out[1] = e.vk;
+  out[2] = e.t;
+  out[3] = e.Ek;
+  out[4] = e.detJ;
+  out[5] = e.admissible ? 1.0 : 0.0;
+  out[6] = e.beta;
+  out[7] = e.x1.x;
+  out[8] = e.x1.y;
+  out[9] = e.x1.z;
+  return 0;
+}
+
+int orc_box_bound(const orc_scene* s, int64_t tuple, const double* box, int want_irr, double* out) {
+  if (!s || !box || !out || tuple < 0 || tuple >= s->n_tri * s->n_emit) return -1;
+  const Tuple c = make_tuple(s, tuple);
+  const BoxBound bb = bound_box(c, box[0], box[1], box[2], box[3], want_irr != 0, 0);
+  out[0] = bb.live ? 1.0 : 0.0;
+  for (int i = 0; i < 4; ++i) out[1 + i] = bb.uk[i];
+  out[5] = bb.E[0];
+  out[6] = bb.E[1];
+  out[7] = bb.universal ? 1.0 : 0.0;
+  return 0;
+}
+
+void* orc_build(const orc_scene* s, const orc_params* p, int n_threads) {
+  if (!s || !p || s->chain < 0 || s->chain > 1 || p->grid_res < 1) return nullptr;
+  return build_all(s, p, n_threads);
+}
+
+void orc_free(void* h) { delete static_cast<Build*>(h); }
+
+int64_t orc_n_leaves(const void* h) { return int64_t(static_cast<const Build*>(h)->leaves.size()); }
+
+int orc_get_leaves(const void* h, int64_t* tuple, int32_t* code, double* box, double* ukbox, double* E) {
+  const Build* B = static_cast<const Build*>(h);
+  for (size_t i = 0; i < B->leaves.size(); ++i) {
+    const Leaf& l = B->leaves[i];
+    if (tuple) tuple[i] = l.tuple;
+    if (code) {
+      code[3 * i] = l.depth;
+      code[3 * i + 1] = int32_t(l.iu);
+      code[3 * i + 2] = int32_t(l.iv);
+    }
+    for (int k = 0; k < 4; ++k) {
+      if (box) box[4 * i + k] = l.box[k];
+      if (ukbox) ukbox[4 * i + k] = l.uk[k];
+    }
+    if (E) {
+      E[2 * i] = l.E[0];
+      E[2 * i + 1] = l.E[1];
+    }
+  }
+  return 0;
+}
+
+int64_t orc_n_roots(const void* h) { return int64_t(static_cast<const Build*>(h)->roots.size()); }
+
+int orc_get_roots(const void* h, int64_t* tuple, double* box) {
+  const Build* B = static_cast<const Build*>(h);
+  for (size_t i = 0; i < B->roots.size(); ++i) {
+    tuple[i] = B->roots[i].tuple;
+    for (int k = 0; k < 4; ++k) box[4 * i + k] = B->roots[i].box[k];
+  }
+  return 0;
+}
+
+int orc_build_stats(const void* h, double* st) {
+  const Build* B = static_cast<const Build*>(h);
+  int64_t entries = 0, inf = 0, uni = 0, maxl = 0;
+  for (const auto& m : B->cells) entries += int64_t(m.size());
+  for (const Leaf& l : B->leaves) {
+    inf += std::isinf(l.E[1]) ? 1 : 0;
+    uni += l.universal ? 1 : 0;
+  }
+  for (int64_t t = 0; t < B->n_tuples; ++t) maxl = std::max(maxl, B->leaf_begin[t + 1] - B->leaf_begin[t]);
+  st[0] = double(B->n_tuples);
+  st[1] = double(B->roots.size());
+  st[2] = double(B->boxes);
+  st[3] = double(B->leaves.size());
+  st[4] = double(entries);
+  st[5] = double(inf);
+  st[6] = double(uni);
+  st[7] = double(maxl);
+  return 0;
+}
+
+int64_t orc_cell_list(const void* h, int32_t cu, int32_t cv, int64_t* tuples, double* Et, int64_t cap) {
+  const Build* B = static_cast<const Build*>(h);
+  const int G = B->p.grid_res;
+  if (cu < 0 || cv < 0 || cu >= G || cv >= G) return -1;
+  const auto& m = B->cells[size_t(cu) * G + cv];
+  int64_t k = 0;
+  for (const auto& kv : m) {
+    if (k < cap) {
+      tuples[k] = kv.first;
+      Et[k] = kv.second;
+    }
+    ++k;
+  }
+  return k;
+}
+
+int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t seed, int mode, double* E_out,
+              double* stats, int n_threads) {
+  const Build* B = static_cast<const Build*>(h);
+  if (!B || !pts || !E_out || n < 0 || !(W >= 1.0) || mode < 0 || mode > 3) return -1;
+  const int G = B->p.grid_res;
+  const bool exhaustive = (mode & 1) != 0, brute = (mode & 2) != 0;
+  const Tuple ref = make_tuple(B->scene, 0);
+  parallel_for(n, n_threads, [&](int64_t i, int) {
+    const V3 x = v3(pts[i], pts[n + i], pts[2 * n + i]);
+    double us, vs;
+    double* st = stats ? stats + 4 * i : nullptr;
+    if (st) st[0] = st[1] = st[2] = st[3] = 0.0;
+    E_out[i] = 0.0;
+    if (!receiver_coords(ref, x, &us, &vs)) return;
+    const auto& m = B->cells[size_t(cell_of(us, G)) * G + cell_of(vs, G)];
+    std::vector<int64_t> U;
+    std::vector<double> Et;
+    for (const auto& kv : m) {
+      U.push_back(kv.first);
+      Et.push_back(kv.second);
+    }
+    std::vector<double> P(U.size(), 1.0);
+    if (!exhaustive) probabilities(Et.data(), int64_t(U.size()), W, P.data());
+    double E = 0.0, mu2 = 0.0;
+    int64_t nS = 0, nroots = 0;
+    for (size_t k = 0; k < U.size(); ++k) {
+      if (P[k] > 0.0) mu2 += Et[k] * Et[k] / P[k];
+      const double r = uniform(seed, uint64_t(i), uint32_t(U[k]));
+      if (!(r < P[k])) continue;
+      ++nS;
+      const Tuple c = make_tuple(B->scene, U[k]);
+      const std::vector<RootHit> roots = brute ? brute_roots(c, us, vs, 64) : leaf_roots(*B, c, U[k], us, vs);
+      double ET = 0.0;
+      for (const RootHit& rh : roots) ET += rh.Ek;
+      nroots += int64_t(roots.size());
+      E += ET / P[k];
+    }
+    E_out[i] = E;
+    if (st) {
+      st[0] = double(U.size());
+      st[1] = double(nS);
+      st[2] = double(nroots);
+      st[3] = mu2;
+    }
+  });
+  return 0;
+}
+
+int orc_true_irradiance(const orc_scene* s, const double* pts, int64_t n, int lattice, double* E_out,
+                        int n_threads) {
+  if (!s || !pts || !E_out || n < 0 || lattice < 1) return -1;
+  const int64_t T = s->n_tri * s->n_emit;
+  const Tuple ref = make_tuple(s, 0);
+  parallel_for(n, n_threads, [&](int64_t i, int) {
+    const V3 x = v3(pts[i], pts[n + i], pts[2 * n + i]);
+    double us, vs;
+    E_out[i] = 0.0;
+    if (!receiver_coords(ref, x, &us, &vs)) return;
+    double E = 0.0;
+    for (int64_t t = 0; t < T; ++t) {
+      const Tuple c = make_tuple(s, t);
+      for (const RootHit& r : brute_roots(c, us, vs, lattice)) E += r.Ek;
+    }
+    E_out[i] = E;
+  });
+  return 0;
+}
+
+int64_t orc_tuple_roots(const orc_scene* s, int64_t tuple, const double* x, int lattice, double* roots,
+                        int64_t cap) {
+  if (!s || !x || tuple < 0 || tuple >= s->n_tri * s->n_emit) return -1;
+  const Tuple c = make_tuple(s, tuple);
+  double us, vs;
+  if (!receiver_coords(c, v3(x[0], x[1], x[2]), &us, &vs)) return 0;
+  const auto r = brute_roots(c, us, vs, lattice);
+  for (int64_t k = 0; k < int64_t(r.size()) && k < cap; ++k) {
+    roots[4 * k] = r[k].u;
+    roots[4 * k + 1] = r[k].v;
+    roots[4 * k + 2] = r[k].Ek;
+    roots[4 * k + 3] = r[k].res;
+  }
+  return int64_t(r.size());
+}
+
+int64_t orc_tuple_roots_leaves(const void* h, int64_t tuple, const double* x, double* roots, int64_t cap) {
+  const Build* B = static_cast<const Build*>(h);
+  if (!B || !x || tuple < 0 || tuple >= B->n_tuples) return -1;
+  const Tuple c = make_tuple(B->scene, tuple);
+  double us, vs;
+  if (!receiver_coords(c, v3(x[0], x[1], x[2]), &us, &vs)) return 0;
+  const auto r = leaf_roots(*B, c, tuple, us, vs);
+  for (int64_t k = 0; k < int64_t(r.size()) && k < cap; ++k) {
+    roots[4 * k] = r[k].u;
+    roots[4 * k + 1] = r[k].v;
+    roots[4 * k + 2] = r[k].Ek;
+    roots[4 * k + 3] = r[k].res;
+  }
+  return int64_t(r.size());
+}
+
+int orc_probabilities(const double* Et, int64_t n, double W, double* P) {
+  if ((!Et && n) || (!P && n) || n < 0 || !(W >= 1.0)) return -1;
+  probabilities(Et, n, W, P);
+  return 0;
+}
+
+void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox(ctr, key, out); }
+
+double orc_uniform(uint64_t seed, uint64_t point, uint32_t tuple) { return uniform(seed, point, tuple); }
+
+static Bern from_flat(const int32_t* d, const double* a) {
+  Bern b(Deg{d[0], d[1], d[2], d[3]});
+  for (size_t i = 0; i < b.size(); ++i) b.c[i] = a[i];
+  return b;
+}
+static void to_flat(const Bern& b, double* out) {
+  for (size_t i = 0; i < b.size(); ++i) out[i] = b.c[i];
+}
+
+int orc_bern_mul(const int32_t* da, const double* a, const int32_t* db, const double* b, double* out) {
+  to_flat(mul(from_flat(da, a), from_flat(db, b)), out);
+  return 0;
+}
+int orc_bern_elevate(const int32_t* da, const double* a, const int32_t* dto, double* out) {
+  to_flat(elevate(from_flat(da, a), Deg{dto[0], dto[1], dto[2], dto[3]}), out);
+  return 0;
+}
+int orc_bern_deriv(const int32_t* da, const double* a, int axis, double* out) {
+  to_flat(deriv(from_flat(da, a), axis), out);
+  return 0;
+}
+int orc_bern_split(const int32_t* da, const double* a, int axis, double t, double* left, double* right) {
+  Bern l, r;
+  split(from_flat(da, a), axis, t, &l, &r);
+  to_flat(l, left);
+  to_flat(r, right);
+  return 0;
+}
+double orc_bern_eval(const int32_t* da, const double* a, const double* x) {
+  return eval(from_flat(da, a), {x[0], x[1], x[2], x[3]});
+}
+int orc_ratio_bound(const int32_t* dp, const double* p, const int32_t* dq, const double* q, double* out) {
+  const RatioBound rb = ratio_bound(from_flat(dp, p), from_flat(dq, q));
+  out[0] = rb.kind;
+  out[1] = rb.lo;
+  out[2] = rb.hi;
+  return 0;
+}
+int orc_sqrt_secant(double blo, double bhi, double* out) {
+  if (!(blo > 0.0) || !(bhi >= blo)) return -1;
+  sqrt_secant(blo, bhi, &out[0], &out[1], &out[2], &out[3]);
+  return 0;
+}
+
+}  // extern "C"

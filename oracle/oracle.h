@@ -1,0 +1,119 @@
+/* C ABI of the FP64 CPU oracle of the bound-driven caustic estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, obviously correct CPU
+ * definition the GPU library is checked against.  Only the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark may load it; the product
+ * path never does.  It shares no code, header or constant with the HIP
+ * library (the two meet only through seeded inputs).
+ *
+ * Conventions: every array is FP64, structure-of-arrays, owned by the caller.
+ * Functions return 0 (or a count >= 0) on success and a negative value on bad
+ * arguments.  Tuples are numbered emitter * n_tri + triangle.
+ */
+#ifndef CAUSTIC_ORACLE_H
+#define CAUSTIC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t chain;     /* 0 = one reflection (R), 1 = one refraction (T), 2 = two reflections (RR) */
+  int64_t n_tri;     /* specular triangles of the first surface */
+  const double* pos; /* [9][n_tri]: p0.xyz, p1.xyz, p2.xyz */
+  const double* nrm; /* [9][n_tri]: n0.xyz, n1.xyz, n2.xyz (vertex normals) */
+  int64_t n_tri2;    /* RR: second surface */
+  const double* pos2;
+  const double* nrm2;
+  double eta;        /* T: ratio of indices of refraction, incident over transmitted */
+  double q0[3], f1[3], f2[3]; /* receiver x = q0 + u f1 + v f2, (u,v) in [0,1]^2 */
+  int64_t n_emit;
+  const double* epos; /* [3][n_emit] */
+  const double* eI;   /* [n_emit] intensities */
+} orc_scene;
+
+typedef struct {
+  int32_t max_depth;   /* subdivision depth cap, counted from the initialised root box */
+  double sigma;        /* stop when the clipped position-bound area is below sigma */
+  double alpha;        /* stop when E_hi / E_lo < alpha (E_lo > 0) */
+  int32_t grid_res;    /* G: receiver grid is G x G cells over [0,1]^2 */
+  int32_t init_pieces; /* domain initialisation keeps at most this many boxes */
+  int32_t init_levels; /* and descends at most this many levels */
+  int32_t flags;       /* bit 0: fixed depth (only the depth cap stops);
+                          bit 1: no remainder variable (ablation, T only) */
+} orc_params;
+
+/* Path evaluation at barycentric (u, v) of a tuple.  out[0..9] =
+ * u_k, v_k, t, E_k, detJ, admissible (0/1), beta (T), x1.x, x1.y, x1.z */
+int orc_eval_path(const orc_scene* s, int64_t tuple, double u, double v, double* out);
+
+/* Bound of one box [u0,u1]x[v0,v1] of a tuple's barycentric domain.
+ * out[0] = 1 if the box is live, 0 if it is culled;
+ * out[1..4] = u_lo, u_hi, v_lo, v_hi of the position bound clipped to [0,1]^2;
+ * out[5..6] = E_lo, E_hi (E_hi may be +inf); out[7] = 1 if the position bound
+ * was universal.  want_irr = 0 skips the irradiance bound (E = [0, inf)). */
+int orc_box_bound(const orc_scene* s, int64_t tuple, const double* box, int want_irr, double* out);
+
+/* Full precomputation: tuples, domain initialisation, adaptive subdivision,
+ * leaves and the receiver grid. */
+void* orc_build(const orc_scene* s, const orc_params* p, int n_threads);
+void orc_free(void* h);
+int64_t orc_n_leaves(const void* h);
+/* leaves: tuple[n], code[n][3] = depth, iu, iv (box index at that depth inside
+ * the tuple's root box), box[n][4] = u0,u1,v0,v1, ukbox[n][4] = u_lo,u_hi,v_lo,v_hi,
+ * E[n][2] = E_lo, E_hi */
+int orc_get_leaves(const void* h, int64_t* tuple, int32_t* code, double* box, double* ukbox, double* E);
+int64_t orc_n_roots(const void* h);
+/* root boxes after domain initialisation: tuple[n], box[n][4] */
+int orc_get_roots(const void* h, int64_t* tuple, double* box);
+/* stats[0..7] = tuples, live tuples, boxes bounded, leaves, grid entries,
+ * infinite-bound leaves, universal-position leaves, max leaves of one tuple */
+int orc_build_stats(const void* h, double* stats);
+/* The candidate list U of grid cell (cu, cv): tuples ascending with their
+ * per-tuple bound E~.  Returns the list length (writes at most cap entries). */
+int64_t orc_cell_list(const void* h, int32_t cu, int32_t cv, int64_t* tuples, double* Et, int64_t cap);
+
+/* Estimator of Alg. 1 at each shading point (points [3][n]).
+ * mode 0: sample with the bound-optimal probabilities, roots by Newton from the
+ *         covering leaves;  mode 1: exhaustive (every tuple of U with P = 1),
+ *         same roots;  mode 2/3: as 0/1 with brute-force roots.
+ * stats (nullable) [n][4] = |U|, |S|, roots found, sum over U of E~^2 / P. */
+int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t seed, int mode,
+              double* E_out, double* stats, int n_threads);
+
+/* Reference irradiance: brute-force roots of every admissible tuple, ignoring
+ * all bounds (multi-start Newton from a barycentric lattice of resolution
+ * `lattice`). */
+int orc_true_irradiance(const orc_scene* s, const double* pts, int64_t n, int lattice, double* E_out,
+                        int n_threads);
+/* Brute-force roots of one tuple at one shading point: roots[k][4] = u, v, E_k, residual. */
+int64_t orc_tuple_roots(const orc_scene* s, int64_t tuple, const double* x, int lattice, double* roots,
+                        int64_t cap);
+/* Roots of one tuple found from the covering leaves of a build. */
+int64_t orc_tuple_roots_leaves(const void* h, int64_t tuple, const double* x, double* roots, int64_t cap);
+
+/* Bound-optimal selection probabilities for a candidate list with bounds Et[n]
+ * and expected sample count W (Sec. 5.4 with the water-filling solve of gamma). */
+int orc_probabilities(const double* Et, int64_t n, double W, double* P);
+/* Counter-based generator Philox4x32-10 (Salmon et al., SC 2011). */
+void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out);
+/* The uniform in [0,1) drawn for (seed, point index, tuple). */
+double orc_uniform(uint64_t seed, uint64_t point, uint32_t tuple);
+
+/* Bernstein primitives exposed for unit tests; deg arrays have 4 entries. */
+int orc_bern_mul(const int32_t* da, const double* a, const int32_t* db, const double* b, double* out);
+int orc_bern_elevate(const int32_t* da, const double* a, const int32_t* dto, double* out);
+int orc_bern_deriv(const int32_t* da, const double* a, int axis, double* out);
+int orc_bern_split(const int32_t* da, const double* a, int axis, double t, double* left, double* right);
+double orc_bern_eval(const int32_t* da, const double* a, const double* x);
+/* out[0] = kind (0 direct [lo,hi], 1 split (-inf,lo]U[hi,inf), 2 unbounded), out[1] = lo, out[2] = hi */
+int orc_ratio_bound(const int32_t* dp, const double* p, const int32_t* dq, const double* q, double* out);
+/* Secant approximation of sqrt on [blo, bhi] (0 < blo <= bhi):
+ * out = a, b, delta_lo, delta_hi with sqrt(x) - (a x + b) in [delta_lo, delta_hi]. */
+int orc_sqrt_secant(double blo, double bhi, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,331 @@
+"""ctypes binding of the FP64 CPU oracle (liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: the plain, slow, obviously correct definition of the
+bound-driven caustic estimator that the GPU library is checked against.  Only
+tests, the smoke check and the CPU-baseline leg of the benchmark may import
+it.  It shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SOURCES = ["bern.cpp", "caustic.cpp"]
+
+CHAINS = {"R": 0, "T": 1, "RR": 2}
+
+
+def build(force=True):
+    """Compile liboracle.so with g++ (-O2, no SIMD intrinsics, FP64)."""
+    if not force and os.path.exists(LIB):
+        return LIB
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-o", LIB + ".tmp"]
+    cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        _lib = C.CDLL(LIB)
+        _declare(_lib)
+    return _lib
+
+
+class Scene(C.Structure):
+    _fields_ = [
+        ("chain", C.c_int32), ("n_tri", C.c_int64), ("pos", C.c_void_p), ("nrm", C.c_void_p),
+        ("n_tri2", C.c_int64), ("pos2", C.c_void_p), ("nrm2", C.c_void_p),
+        ("eta", C.c_double), ("q0", C.c_double * 3), ("f1", C.c_double * 3), ("f2", C.c_double * 3),
+        ("n_emit", C.c_int64), ("epos", C.c_void_p), ("eI", C.c_void_p),
+    ]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("max_depth", C.c_int32), ("sigma", C.c_double), ("alpha", C.c_double), ("grid_res", C.c_int32),
+        ("init_pieces", C.c_int32), ("init_levels", C.c_int32), ("flags", C.c_int32),
+    ]
+
+
+def _declare(L):
+    vp, i64, i32, d, u64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_uint64
+    sig = {
+        "orc_eval_path": (C.c_int, [vp, i64, d, d, vp]),
+        "orc_box_bound": (C.c_int, [vp, i64, vp, C.c_int, vp]),
+        "orc_build": (vp, [vp, vp, C.c_int]),
+        "orc_free": (None, [vp]),
+        "orc_n_leaves": (i64, [vp]),
+        "orc_get_leaves": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "orc_n_roots": (i64, [vp]),
+        "orc_get_roots": (C.c_int, [vp, vp, vp]),
+        "orc_build_stats": (C.c_int, [vp, vp]),
+        "orc_cell_list": (i64, [vp, i32, i32, vp, vp, i64]),
+        "orc_query": (C.c_int, [vp, vp, i64, d, u64, C.c_int, vp, vp, C.c_int]),
+        "orc_true_irradiance": (C.c_int, [vp, vp, i64, C.c_int, vp, C.c_int]),
+        "orc_tuple_roots": (i64, [vp, i64, vp, C.c_int, vp, i64]),
+        "orc_tuple_roots_leaves": (i64, [vp, i64, vp, vp, i64]),
+        "orc_probabilities": (C.c_int, [vp, i64, d, vp]),
+        "orc_philox4x32_10": (None, [vp, vp, vp]),
+        "orc_uniform": (d, [u64, u64, C.c_uint32]),
+        "orc_bern_mul": (C.c_int, [vp, vp, vp, vp, vp]),
+        "orc_bern_elevate": (C.c_int, [vp, vp, vp, vp]),
+        "orc_bern_deriv": (C.c_int, [vp, vp, C.c_int, vp]),
+        "orc_bern_split": (C.c_int, [vp, vp, C.c_int, d, vp, vp]),
+        "orc_bern_eval": (d, [vp, vp, vp]),
+        "orc_ratio_bound": (C.c_int, [vp, vp, vp, vp, vp]),
+        "orc_sqrt_secant": (C.c_int, [d, d, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class OracleScene:
+    """Holds FP64 copies of a scene dict (see paper_2504_19163_amd.scenes) and the
+    C struct pointing at them.  Inputs are the float32 scene values converted
+    exactly to FP64."""
+
+    def __init__(self, scene):
+        self.src = scene
+        self.pos = _f64(scene["pos"])
+        self.nrm = _f64(scene["nrm"])
+        self.epos = _f64(scene["epos"])
+        self.eI = _f64(scene["eI"])
+        self.pos2 = _f64(scene["pos2"]) if "pos2" in scene else None
+        self.nrm2 = _f64(scene["nrm2"]) if "nrm2" in scene else None
+        s = Scene()
+        s.chain = CHAINS[scene["chain"]]
+        s.n_tri = self.pos.shape[1]
+        s.pos = _ptr(self.pos)
+        s.nrm = _ptr(self.nrm)
+        s.n_tri2 = 0 if self.pos2 is None else self.pos2.shape[1]
+        s.pos2 = _ptr(self.pos2)
+        s.nrm2 = _ptr(self.nrm2)
+        s.eta = float(scene["eta"])
+        for k in ("q0", "f1", "f2"):
+            getattr(s, k)[:] = [float(x) for x in scene[k]]
+        s.n_emit = self.eI.shape[0]
+        s.epos = _ptr(self.epos)
+        s.eI = _ptr(self.eI)
+        self.c = s
+        self.n_tuples = s.n_tri * s.n_emit
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+
+def default_params(max_depth=4, sigma=1e-4, alpha=2.0, grid_res=512, init_pieces=100, init_levels=4, flags=0):
+    return dict(max_depth=max_depth, sigma=sigma, alpha=alpha, grid_res=grid_res,
+                init_pieces=init_pieces, init_levels=init_levels, flags=flags)
+
+
+def _params(p):
+    q = Params()
+    for k, v in p.items():
+        setattr(q, k, v)
+    return q
+
+
+def eval_path(osc, tuple_id, u, v):
+    out = np.zeros(10)
+    assert lib().orc_eval_path(osc.ref, int(tuple_id), float(u), float(v), _ptr(out)) == 0
+    return dict(uk=out[0], vk=out[1], t=out[2], Ek=out[3], detJ=out[4], admissible=bool(out[5]),
+                beta=out[6], x1=out[7:10].copy())
+
+
+def box_bound(osc, tuple_id, box, want_irr=True):
+    b = _f64(box)
+    out = np.zeros(8)
+    assert lib().orc_box_bound(osc.ref, int(tuple_id), _ptr(b), int(want_irr), _ptr(out)) == 0
+    return dict(live=bool(out[0]), uk=out[1:5].copy(), E=out[5:7].copy(), universal=bool(out[7]))
+
+
+class OracleBuild:
+    """Precomputation of the oracle: leaves, root boxes and the receiver grid."""
+
+    def __init__(self, osc, params=None, n_threads=None):
+        self.osc = osc
+        self.params = dict(default_params(), **(params or {}))
+        nt = n_threads or os.cpu_count() or 1
+        self._p = _params(self.params)
+        self.h = lib().orc_build(osc.ref, C.byref(self._p), int(nt))
+        if not self.h:
+            raise ValueError("oracle build rejected its arguments")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_free(self.h)
+            self.h = None
+
+    def leaves(self):
+        n = lib().orc_n_leaves(self.h)
+        tup = np.zeros(n, np.int64)
+        code = np.zeros((n, 3), np.int32)
+        box = np.zeros((n, 4))
+        uk = np.zeros((n, 4))
+        E = np.zeros((n, 2))
+        lib().orc_get_leaves(self.h, _ptr(tup), _ptr(code), _ptr(box), _ptr(uk), _ptr(E))
+        return dict(tuple=tup, code=code, box=box, uk=uk, E=E)
+
+    def roots(self):
+        n = lib().orc_n_roots(self.h)
+        tup = np.zeros(n, np.int64)
+        box = np.zeros((n, 4))
+        lib().orc_get_roots(self.h, _ptr(tup), _ptr(box))
+        return dict(tuple=tup, box=box)
+
+    def stats(self):
+        st = np.zeros(8)
+        lib().orc_build_stats(self.h, _ptr(st))
+        keys = ["tuples", "live_tuples", "boxes", "leaves", "grid_entries", "inf_leaves", "universal_leaves",
+                "max_leaves_per_tuple"]
+        return {k: int(v) for k, v in zip(keys, st)}
+
+    def cell_list(self, cu, cv):
+        n = lib().orc_cell_list(self.h, int(cu), int(cv), None, None, 0)
+        t = np.zeros(max(n, 1), np.int64)
+        e = np.zeros(max(n, 1))
+        lib().orc_cell_list(self.h, int(cu), int(cv), _ptr(t), _ptr(e), n)
+        return t[:n], e[:n]
+
+    def query(self, pts, W, seed, mode=0, n_threads=None):
+        p = _f64(pts)
+        n = p.shape[1]
+        E = np.zeros(n)
+        st = np.zeros((n, 4))
+        nt = n_threads or os.cpu_count() or 1
+        rc = lib().orc_query(self.h, _ptr(p), n, float(W), int(seed), int(mode), _ptr(E), _ptr(st), int(nt))
+        assert rc == 0
+        return E, st
+
+    def tuple_roots_leaves(self, tuple_id, x):
+        xx = _f64(x)
+        cap = 64
+        out = np.zeros((cap, 4))
+        n = lib().orc_tuple_roots_leaves(self.h, int(tuple_id), _ptr(xx), _ptr(out), cap)
+        return out[:min(n, cap)].copy()
+
+
+def true_irradiance(osc, pts, lattice=24, n_threads=None):
+    p = _f64(pts)
+    n = p.shape[1]
+    E = np.zeros(n)
+    nt = n_threads or os.cpu_count() or 1
+    assert lib().orc_true_irradiance(osc.ref, _ptr(p), n, int(lattice), _ptr(E), int(nt)) == 0
+    return E
+
+
+def tuple_roots(osc, tuple_id, x, lattice=24):
+    xx = _f64(x)
+    cap = 64
+    out = np.zeros((cap, 4))
+    n = lib().orc_tuple_roots(osc.ref, int(tuple_id), _ptr(xx), int(lattice), _ptr(out), cap)
+    return out[:min(n, cap)].copy()
+
+
+def probabilities(Et, W):
+    e = _f64(Et)
+    P = np.zeros_like(e)
+    assert lib().orc_probabilities(_ptr(e), e.size, float(W), _ptr(P)) == 0
+    return P
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    o = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(o))
+    return o
+
+
+def uniform(seed, point, tuple_id):
+    return lib().orc_uniform(int(seed), int(point), int(tuple_id))
+
+
+def _deg(d):
+    d = list(d) + [0] * (4 - len(d))
+    return np.ascontiguousarray(np.asarray(d, dtype=np.int32))
+
+
+def _n(d):
+    return int(np.prod(np.asarray(d) + 1))
+
+
+def bern_mul(da, a, db, b):
+    da, db = _deg(da), _deg(db)
+    a, b = _f64(a), _f64(b)
+    out = np.zeros(_n(da + db))
+    lib().orc_bern_mul(_ptr(da), _ptr(a), _ptr(db), _ptr(b), _ptr(out))
+    return da + db, out
+
+
+def bern_elevate(da, a, dto):
+    da, dto = _deg(da), _deg(dto)
+    a = _f64(a)
+    out = np.zeros(_n(dto))
+    lib().orc_bern_elevate(_ptr(da), _ptr(a), _ptr(dto), _ptr(out))
+    return dto, out
+
+
+def bern_deriv(da, a, axis):
+    da = _deg(da)
+    dd = da.copy()
+    dd[axis] = max(dd[axis] - 1, 0)
+    a = _f64(a)
+    out = np.zeros(_n(dd))
+    lib().orc_bern_deriv(_ptr(da), _ptr(a), int(axis), _ptr(out))
+    return dd, out
+
+
+def bern_split(da, a, axis, t=0.5):
+    da = _deg(da)
+    a = _f64(a)
+    l = np.zeros(_n(da))
+    r = np.zeros(_n(da))
+    lib().orc_bern_split(_ptr(da), _ptr(a), int(axis), float(t), _ptr(l), _ptr(r))
+    return l, r
+
+
+def bern_eval(da, a, x):
+    da = _deg(da)
+    xx = np.zeros(4)
+    xx[:len(x)] = x
+    a = _f64(a)
+    return lib().orc_bern_eval(_ptr(da), _ptr(a), _ptr(xx))
+
+
+def ratio_bound(dp, p, dq, q):
+    dp, dq = _deg(dp), _deg(dq)
+    p, q = _f64(p), _f64(q)
+    out = np.zeros(3)
+    lib().orc_ratio_bound(_ptr(dp), _ptr(p), _ptr(dq), _ptr(q), _ptr(out))
+    return int(out[0]), out[1], out[2]
+
+
+def sqrt_secant(blo, bhi):
+    out = np.zeros(4)
+    assert lib().orc_sqrt_secant(float(blo), float(bhi), _ptr(out)) == 0
+    return out
