@@ -1,0 +1,217 @@
+/* bbc — Bernstein-bound caustics on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the bound-driven caustic estimator of "Bernstein Bounds for
+ * Caustics" (arXiv 2504.19163).  Three stages run on one GPU:
+ *
+ *   1. For every (point emitter, specular triangle) tuple the receiver
+ *      position u_k(u1) and the path irradiance E_k(u1) are rational functions
+ *      of the barycentric coordinates u1 of the specular vertex (Sec. 4.3-4.4;
+ *      refraction replaces sqrt(beta) by a linear approximant plus remainder
+ *      variables, Sec. 4.3).
+ *   2. Each tuple's domain is subdivided adaptively and interval bounds of
+ *      u_k and E_k are read off the Bernstein coefficients of numerator and
+ *      denominator (Sec. 4.1, Eq. eq_bbound; Sec. 6.1 subdivision and domain
+ *      initialisation); the leaves are splatted into a receiver grid that
+ *      stores, per cell and tuple, the per-tuple bound E~ (Eq. eq_pertuple_b;
+ *      Sec. 6.1 bound storage).
+ *   3. Per shading point, the tuples of its cell are sampled with the
+ *      variance-bound-optimal probabilities P_T = min(gamma E~_T, 1)
+ *      (Sec. 5.4), the selected tuples are root-found by Newton iteration in
+ *      the triangle domain (Sec. 6.1), and Alg. 1 returns the unbiased
+ *      estimate sum_{T in S} E(T) / P_T.
+ *
+ * Arithmetic: FP32 with running error bounds so every bound is rounded
+ * outward; denominators whose Bernstein coefficients cannot be given a sign
+ * in FP32 are re-evaluated in FP64, and every accepted root is polished in
+ * FP64.
+ *
+ * Conventions
+ *  - Every entry point returns a bbc_status; 0 is success.  On failure
+ *    bbc_last_error() returns a thread-local message.  Arguments are validated
+ *    before any work is enqueued; no C++ exception crosses this ABI.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously on it; device outputs are valid once the
+ *    stream has been synchronised.
+ *  - Arrays are structure-of-arrays FP32.  A `memory` field says whether the
+ *    arrays of a struct are host (BBC_MEM_HOST) or device (BBC_MEM_DEVICE)
+ *    pointers; the library copies what it keeps, so inputs are only borrowed
+ *    for the duration of the call.
+ *  - Tuples are numbered emitter * n_tri + triangle.
+ */
+#ifndef BBC_H
+#define BBC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bbc_status;
+#define BBC_OK 0
+#define BBC_EINVAL (-1)       /* bad argument (null pointer, n < 0, spp < 1, degenerate receiver, eta <= 0) */
+#define BBC_ENOMEM (-2)       /* device or host allocation failed */
+#define BBC_EBUDGET (-3)      /* serving: a request can never fit the memory budget */
+#define BBC_EDEVICE (-4)      /* HIP runtime error; text in bbc_last_error() */
+#define BBC_EUNSUPPORTED (-5) /* chain type not available */
+#define BBC_EQUEUE (-6)       /* a device work queue or buffer overflowed its capacity */
+
+#define BBC_CHAIN_R 0  /* one specular reflection */
+#define BBC_CHAIN_T 1  /* one specular refraction */
+#define BBC_CHAIN_RR 2 /* two specular reflections */
+
+#define BBC_MEM_HOST 0
+#define BBC_MEM_DEVICE 1
+
+/* Specular casters and the planar receiver (symbols of Sec. 4.2, Table 1).
+ * pos: [9][n_tri] rows p0.x p0.y p0.z p1.x ... p2.z; nrm: [9][n_tri] vertex
+ * normals n0, n1, n2 (interpolated un-normalised, Eq. eq_ni).  The receiver is
+ * the parallelogram x = q0 + u f1 + v f2 with (u, v) in [0,1]^2, its texture
+ * space (Sec. 6.1, bound storage).  eta is the ratio of indices of refraction
+ * eta' (incident over transmitted side) used by BBC_CHAIN_T (Eq.
+ * eq_refr_rational); vertex normals must face the incident side. */
+typedef struct {
+  int32_t chain;  /* BBC_CHAIN_* */
+  int32_t memory; /* BBC_MEM_* for pos/nrm/pos2/nrm2 */
+  int64_t n_tri;
+  const float* pos;
+  const float* nrm;
+  int64_t n_tri2; /* BBC_CHAIN_RR: second specular surface */
+  const float* pos2;
+  const float* nrm2;
+  float eta;
+  float q0[3], f1[3], f2[3];
+} bbc_scene;
+
+/* Point emitters: pos [3][n], intensity I0 [n] (Sec. 4.4). */
+typedef struct {
+  int32_t memory; /* BBC_MEM_* for pos and I0 */
+  int64_t n;
+  const float* pos;
+  const float* I0;
+} bbc_emitters;
+
+/* Subdivision controls (Sec. 6.1).  Defaults: max_depth 8, sigma 1e-4,
+ * alpha 2 (single scattering), grid_res 512, init_pieces 100, init_levels 4. */
+typedef struct {
+  int32_t max_depth;   /* depth cap, counted from the initialised root box */
+  float sigma;         /* stop when the clipped position-bound area (in receiver units) < sigma */
+  float alpha;         /* stop when E_hi / E_lo < alpha (E_lo > 0) */
+  int32_t grid_res;    /* receiver grid is grid_res x grid_res cells over [0,1]^2 (1..4096) */
+  int32_t init_pieces; /* domain initialisation keeps at most this many boxes */
+  int32_t init_levels; /* and descends at most this many levels */
+  int32_t flags;       /* BBC_FLAG_* */
+} bbc_subdiv_params;
+#define BBC_FLAG_FIXED_DEPTH 1  /* only the depth cap stops subdivision (parity mode) */
+#define BBC_FLAG_NO_REMAINDER 2 /* refraction without remainder variables (ablation; bounds may be invalid) */
+
+typedef struct bbc_bounds bbc_bounds;
+
+/* Stage 1 and 2: build the bound hierarchy and receiver grid of a scene.
+ * The scene and emitter arrays are copied into library-owned device memory.
+ * *out receives an opaque handle owned by the library until bbc_free_bounds.
+ * Returns BBC_EQUEUE if a capacity in `params` order of magnitude is exceeded
+ * even after the library's automatic regrowth, BBC_EUNSUPPORTED for a chain
+ * this build does not handle. */
+bbc_status bbc_build_bounds(const bbc_scene* scene, const bbc_emitters* emitters, const bbc_subdiv_params* params,
+                            void* stream, bbc_bounds** out);
+
+/* Rebuild in place: same as bbc_build_bounds but reuses the device buffers of
+ * an existing handle (no allocation when capacities suffice). */
+bbc_status bbc_rebuild_bounds(bbc_bounds* b, const bbc_scene* scene, const bbc_emitters* emitters,
+                              const bbc_subdiv_params* params, void* stream);
+
+/* Release a handle; bbc_free_bounds(NULL) is a no-op. */
+bbc_status bbc_free_bounds(bbc_bounds* b);
+
+typedef struct {
+  int64_t n_tuples;       /* emitters x triangles */
+  int64_t n_live_tuples;  /* tuples with a root box after domain initialisation */
+  int64_t n_boxes;        /* boxes bounded during subdivision */
+  int64_t n_leaves;
+  int64_t n_grid_entries; /* (cell, tuple) records */
+  int64_t n_inf_leaves;   /* leaves with an infinite irradiance bound */
+  int64_t n_fp64_boxes;   /* boxes re-evaluated in FP64 (sign-uncertain denominators) */
+  int64_t device_bytes;   /* device memory held by the handle */
+  int32_t grid_res;
+  int32_t max_depth_reached;
+} bbc_bounds_info_t;
+bbc_status bbc_bounds_info(const bbc_bounds* b, bbc_bounds_info_t* out);
+
+/* Copy the leaves to host memory (arrays of length n_leaves, any may be NULL):
+ * tuple[n], code[n] (depth << 28 | iu << 14 | iv, the box index inside the
+ * tuple's root box), box[n][4] (u0,u1,v0,v1 of u1), ukbox[n][4] (u_lo,u_hi,
+ * v_lo,v_hi clipped to [0,1]^2), E[n][2] (E_lo, E_hi; E_hi may be +inf).
+ * Leaves are ordered by tuple, then code. */
+bbc_status bbc_export_leaves(const bbc_bounds* b, uint32_t* tuple, uint32_t* code, float* box, float* ukbox, float* E);
+
+/* Copy the receiver grid to host memory: offsets[grid_res^2 + 1], and
+ * n_grid_entries entries of (tuple, E~) sorted by tuple within each cell. */
+bbc_status bbc_export_grid(const bbc_bounds* b, uint32_t* offsets, uint32_t* tuple, float* Et);
+
+/* Per-query statistics (host struct, summed over the points of a call).
+ * sum_U, sum_S and sum_varbound are filled by the fused form only. */
+typedef struct {
+  int64_t n_points;
+  int64_t sum_U;       /* sum of |U| (candidate tuples) */
+  int64_t sum_S;       /* sum of |S| (selected tuples) */
+  int64_t n_roots;     /* accepted specular paths */
+  int64_t n_newton;    /* Newton starts (covering leaves of selected tuples) */
+  double sum_varbound; /* sum over points of sum_U E~^2 / P (Eq. eq_varbound_u), finite parts */
+  int64_t n_pairs;     /* (point, tuple) pairs root-found (= sum_S) */
+  int64_t n_iter_fp32; /* FP32 path evaluations (value + Jacobian) */
+  int64_t n_iter_fp64; /* FP64 path evaluations (value + Jacobian) */
+} bbc_query_stats;
+
+/* Stage 3: irradiance estimates at n shading points (Alg. 1).
+ * points_dev [3][n] FP32 device array of positions on the receiver plane;
+ * out_E_dev [n] FP32 device array.  spp is W, the expected number of sampled
+ * tuples per point (Sec. 5.4).  Result i depends only on (bounds, points[i],
+ * i, spp, seed): the Bernoulli draw for tuple T at point i is Philox4x32-10
+ * keyed by (seed, i, T).  Points off the receiver return 0.  stats_host may
+ * be NULL; when given, the call synchronises the stream to fill it. */
+bbc_status bbc_query_irradiance(const bbc_bounds* b, const float* points_dev, int64_t n, int32_t spp, uint64_t seed,
+                                float* out_E_dev, bbc_query_stats* stats_host, void* stream);
+
+/* Same with an execution mode:
+ *  BBC_QUERY_FUSED   one persistent kernel per call (default of bbc_query_irradiance)
+ *  BBC_QUERY_STAGED  one launch per stage: gather+gamma, selection, Newton, accumulation
+ *  BBC_QUERY_EXHAUSTIVE (or-ed in) every candidate tuple with P = 1 (position-only enumeration)
+ * point_index_base offsets the point index used by the random stream, so a
+ * request split into pieces draws exactly what it would draw whole. */
+#define BBC_QUERY_FUSED 0
+#define BBC_QUERY_STAGED 1
+#define BBC_QUERY_EXHAUSTIVE 16
+bbc_status bbc_query_irradiance_ex(const bbc_bounds* b, const float* points_dev, int64_t n, int32_t spp, uint64_t seed,
+                                   int64_t point_index_base, int32_t mode, float* out_E_dev, float* stats_dev,
+                                   bbc_query_stats* stats_host, void* stream);
+/* stats_dev (nullable) [n][4] FP32: |U|, |S|, roots, sum_U E~^2/P per point. */
+
+/* Launch-shape knobs (chosen by the autotuner; results never depend on them):
+ *  BBC_TUNE_QUERY_WAVES        fused query register budget: 2 (256 VGPRs) or 4 (128) waves per SIMD
+ *  BBC_TUNE_QUERY_GRID         fused query persistent workgroups (1..2^20)
+ *  BBC_TUNE_BUILD_GRID_PER_CU  subdivision persistent workgroups per compute unit (1..64)
+ *  BBC_TUNE_QUERY_TILE         fused query shading points per wave: 16, 32 or 64
+ *  BBC_TUNE_TIMING             1: record HIP events on the query stream around the
+ *                              query's dominant kernel (see bbc_query_kernel_ms)
+ * Applies to later calls on the handle; EINVAL for an unknown knob or value. */
+#define BBC_TUNE_QUERY_WAVES 1
+#define BBC_TUNE_QUERY_GRID 2
+#define BBC_TUNE_BUILD_GRID_PER_CU 3
+#define BBC_TUNE_QUERY_TILE 4
+#define BBC_TUNE_TIMING 5
+bbc_status bbc_set_tuning(bbc_bounds* b, int32_t knob, int64_t value);
+bbc_status bbc_get_tuning(const bbc_bounds* b, int32_t knob, int64_t* value);
+
+/* Duration in milliseconds of the dominant kernel of the last query on this
+ * handle (the fused kernel, or the staged form's Newton kernel), measured with
+ * HIP events on the query's stream; waits for that event.  EINVAL unless
+ * BBC_TUNE_TIMING is on and a query ran since. */
+bbc_status bbc_query_kernel_ms(const bbc_bounds* b, float* ms);
+
+/* Thread-local text of the last error. */
+const char* bbc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BBC_H */

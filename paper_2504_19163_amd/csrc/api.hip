@@ -1,0 +1,426 @@
+// Host side of the C ABI (include/bbc.h): argument validation, library-owned
+// device buffers, capacity regrowth, and the stage launch sequences.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace bbc {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+bbc_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? BBC_ENOMEM : BBC_EDEVICE;
+}
+
+static bbc_status invalid(const char* msg) {
+  set_error(msg);
+  return BBC_EINVAL;
+}
+
+bbc_status ensure(DevBuf& b, size_t bytes, Bounds* owner) {
+  if (bytes == 0) bytes = 4;
+  if (b.bytes >= bytes) return BBC_OK;
+  if (b.p) {
+    BBC_HIP(hipFree(b.p));
+    if (owner) owner->device_bytes -= int64_t(b.bytes);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation of " + std::to_string(bytes) + " bytes failed");
+    return BBC_ENOMEM;
+  }
+  b.p = p;
+  b.bytes = bytes;
+  if (owner) owner->device_bytes += int64_t(bytes);
+  return BBC_OK;
+}
+
+void release(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+static void release_all(Bounds* b) {
+  DevBuf* all[] = {&b->pos, &b->nrm, &b->epos, &b->eI, &b->counters, &b->root, &b->init_q, &b->l0f_q, &b->q[0],
+                   &b->q[1], &b->fq, &b->lt, &b->lc, &b->lu, &b->le, &b->gl_t, &b->gl_c, &b->gl_u, &b->gl_e, &b->st, &b->sc, &b->su, &b->se, &b->tcount,
+                   &b->toff, &b->tcur, &b->trip, &b->ccount, &b->coff, &b->ccur, &b->ut, &b->ue, &b->ucell, &b->gt, &b->ge,
+                   &b->scan_tmp, &b->trec,
+                   &b->qw_cell, &b->qw_gamma, &b->qw_cnt, &b->qw_off, &b->qw_pair_pt, &b->qw_pair_t,
+                   &b->qw_pair_p, &b->qw_pair_c, &b->qw_stats, &b->max_cell_dev, &b->qcounters};
+  for (DevBuf* d : all) release(*d);
+  b->device_bytes = 0;
+}
+
+static bbc_status copy_in(DevBuf& dst, const void* src, size_t bytes, int memory, Bounds* owner, hipStream_t s) {
+  bbc_status e = ensure(dst, bytes, owner);
+  if (e) return e;
+  BBC_HIP(hipMemcpyAsync(dst.p, src, bytes, memory == BBC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         s));
+  return BBC_OK;
+}
+
+static bbc_status validate(const bbc_scene* sc, const bbc_emitters* em, const bbc_subdiv_params* p) {
+  if (!sc || !em || !p) return invalid("null scene, emitters or params");
+  if (sc->chain != BBC_CHAIN_R && sc->chain != BBC_CHAIN_T) {
+    if (sc->chain == BBC_CHAIN_RR) {
+      set_error("two-vertex chains are not available in this build");
+      return BBC_EUNSUPPORTED;
+    }
+    return invalid("unknown chain type");
+  }
+  if (sc->memory != BBC_MEM_HOST && sc->memory != BBC_MEM_DEVICE) return invalid("scene memory flag");
+  if (em->memory != BBC_MEM_HOST && em->memory != BBC_MEM_DEVICE) return invalid("emitter memory flag");
+  if (sc->n_tri < 1 || !sc->pos || !sc->nrm) return invalid("scene needs n_tri >= 1 and pos/nrm arrays");
+  if (em->n < 1 || !em->pos || !em->I0) return invalid("emitters need n >= 1 and pos/I0 arrays");
+  if (double(sc->n_tri) * double(em->n) > 4294967000.0) return invalid("more than 2^32 tuples");
+  const double f1[3] = {sc->f1[0], sc->f1[1], sc->f1[2]}, f2[3] = {sc->f2[0], sc->f2[1], sc->f2[2]};
+  const double c[3] = {f1[1] * f2[2] - f1[2] * f2[1], f1[2] * f2[0] - f1[0] * f2[2], f1[0] * f2[1] - f1[1] * f2[0]};
+  const double ak = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  if (!(ak > 0.0) || !std::isfinite(ak)) return invalid("degenerate receiver (|f1 x f2| = 0)");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(sc->q0[k])) return invalid("receiver origin not finite");
+  if (sc->chain == BBC_CHAIN_T && !(sc->eta > 0.f && std::isfinite(sc->eta))) return invalid("eta must be > 0");
+  if (p->max_depth < 0 || p->max_depth > kMaxDepth) return invalid("max_depth must be in [0, 14]");
+  if (!(p->sigma >= 0.f) || !(p->alpha >= 1.f)) return invalid("sigma >= 0 and alpha >= 1 required");
+  if (p->grid_res < 1 || p->grid_res > 4096) return invalid("grid_res must be in [1, 4096]");
+  if (p->init_pieces < 1 || p->init_pieces > 256) return invalid("init_pieces must be in [1, 256]");
+  if (p->init_levels < 0 || p->init_levels > 12) return invalid("init_levels must be in [0, 12]");
+  if (p->flags & ~(BBC_FLAG_FIXED_DEPTH | BBC_FLAG_NO_REMAINDER)) return invalid("unknown flags");
+  return BBC_OK;
+}
+
+static bbc_status run_build(Bounds* b, hipStream_t s) {
+  const int64_t G = b->params.grid_res;
+  const int64_t ncell = G * G;
+  bbc_status e;
+  if (b->q_cap == 0) {
+    b->q_cap = size_t(std::max<int64_t>(4 * b->n_tuples, 1 << 20));
+    b->fq_cap = b->q_cap;
+    b->leaf_cap = b->q_cap;
+    b->trip_cap = size_t(32) << 20;
+  }
+  for (int attempt = 0; attempt < 5; ++attempt) {
+    if ((e = ensure(b->counters, sizeof(BuildCounters), b)) || (e = ensure(b->root, b->n_tuples * 16, b)) ||
+        (e = ensure(b->init_q, b->n_tuples * 4, b)) || (e = ensure(b->l0f_q, b->n_tuples * 4, b)) ||
+        (e = ensure(b->q[0], b->q_cap * 8, b)) || (e = ensure(b->q[1], b->q_cap * 8, b)) ||
+        (e = ensure(b->fq, b->fq_cap * 8, b)) || (e = ensure(b->lt, b->leaf_cap * 4, b)) ||
+        (e = ensure(b->lc, b->leaf_cap * 4, b)) || (e = ensure(b->lu, b->leaf_cap * 16, b)) ||
+        (e = ensure(b->le, b->leaf_cap * 8, b)) || (e = ensure(b->gl_t, b->leaf_cap * 4, b)) ||
+        (e = ensure(b->gl_c, b->leaf_cap * 4, b)) || (e = ensure(b->gl_u, b->leaf_cap * 16, b)) ||
+        (e = ensure(b->gl_e, b->leaf_cap * 8, b)) || (e = ensure(b->st, b->leaf_cap * 4, b)) ||
+        (e = ensure(b->sc, b->leaf_cap * 4, b)) || (e = ensure(b->su, b->leaf_cap * 16, b)) ||
+        (e = ensure(b->se, b->leaf_cap * 8, b)) || (e = ensure(b->tcount, b->n_tuples * 4, b)) ||
+        (e = ensure(b->toff, (b->n_tuples + 1) * 4, b)) || (e = ensure(b->tcur, b->n_tuples * 4, b)) ||
+        (e = ensure(b->trip, b->trip_cap * 12, b)) || (e = ensure(b->ccount, ncell * 4, b)) ||
+        (e = ensure(b->coff, (ncell + 1) * 4, b)) || (e = ensure(b->ccur, ncell * 4, b)) ||
+        (e = ensure(b->ut, b->trip_cap * 4, b)) || (e = ensure(b->ue, b->trip_cap * 4, b)) ||
+        (e = ensure(b->ucell, b->trip_cap * 4, b)) || (e = ensure(b->gt, b->trip_cap * 4, b)) ||
+        (e = ensure(b->ge, b->trip_cap * 4, b)) ||
+        (e = ensure(b->scan_tmp, scan_tmp_bytes(std::max(ncell, b->n_tuples)) + 64, b)) ||
+        (e = ensure(b->trec, size_t(b->n_tuples) * kRecFloats * 4, b)) ||
+        (e = ensure(b->max_cell_dev, 64, b)))
+      return e;
+    if ((e = launch_build(b, s))) return e;
+    if ((e = launch_record(b, s))) return e;
+    BBC_HIP(hipMemcpyAsync(&b->host, b->counters.p, sizeof(BuildCounters), hipMemcpyDeviceToHost, s));
+    uint32_t mc = 0;
+    BBC_HIP(hipMemcpyAsync(&mc, b->max_cell_dev.p, 4, hipMemcpyDeviceToHost, s));
+    BBC_HIP(hipStreamSynchronize(s));
+    const uint32_t ov = b->host.overflow;
+    if (!ov) {
+      b->n_leaves = b->host.n_leaves;
+      b->n_entries = b->host.n_triples;
+      b->max_cell = mc;
+      return BBC_OK;
+    }
+    if (ov & (1u | 2u | 8u)) {
+      b->q_cap *= 4;
+      b->fq_cap *= 4;
+      b->leaf_cap *= 4;
+    }
+    if (ov & 4u) b->trip_cap = std::max<size_t>(b->trip_cap * 2, size_t(b->host.n_triples) + 1024);
+    if (b->q_cap > (size_t(1) << 31) || b->trip_cap > (size_t(1) << 31)) break;
+  }
+  set_error("device work queues overflowed their maximum capacity");
+  return BBC_EQUEUE;
+}
+
+static bbc_status load_scene(Bounds* b, const bbc_scene* sc, const bbc_emitters* em, const bbc_subdiv_params* p,
+                             hipStream_t s) {
+  bbc_status e;
+  const size_t nt = size_t(sc->n_tri);
+  if ((e = copy_in(b->pos, sc->pos, nt * 9 * 4, sc->memory, b, s))) return e;
+  if ((e = copy_in(b->nrm, sc->nrm, nt * 9 * 4, sc->memory, b, s))) return e;
+  if ((e = copy_in(b->epos, em->pos, size_t(em->n) * 3 * 4, em->memory, b, s))) return e;
+  if ((e = copy_in(b->eI, em->I0, size_t(em->n) * 4, em->memory, b, s))) return e;
+  b->params = *p;
+  DevScene& d = b->scene;
+  d.chain = sc->chain;
+  d.n_tri = sc->n_tri;
+  d.pos = static_cast<const float*>(b->pos.p);
+  d.nrm = static_cast<const float*>(b->nrm.p);
+  d.n_emit = em->n;
+  d.epos = static_cast<const float*>(b->epos.p);
+  d.eI = static_cast<const float*>(b->eI.p);
+  d.eta = sc->chain == BBC_CHAIN_T ? sc->eta : 1.f;
+  for (int k = 0; k < 3; ++k) {
+    d.q0[k] = sc->q0[k];
+    d.f1[k] = sc->f1[k];
+    d.f2[k] = sc->f2[k];
+  }
+  b->n_tuples = sc->n_tri * em->n;
+  return BBC_OK;
+}
+
+static hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace bbc
+
+using namespace bbc;
+
+extern "C" {
+
+const char* bbc_last_error(void) { return g_err.c_str(); }
+
+bbc_status bbc_rebuild_bounds(bbc_bounds* h, const bbc_scene* scene, const bbc_emitters* emitters,
+                              const bbc_subdiv_params* params, void* stream) {
+  if (!h) return invalid("null bounds handle");
+  bbc_status e = validate(scene, emitters, params);
+  if (e) return e;
+  Bounds* b = reinterpret_cast<Bounds*>(h);
+  int dev = 0;
+  BBC_HIP(hipGetDevice(&dev));
+  if (dev != b->device) return invalid("current device differs from the handle's device");
+  const hipStream_t s = as_stream(stream);
+  if ((e = load_scene(b, scene, emitters, params, s))) return e;
+  return run_build(b, s);
+}
+
+bbc_status bbc_build_bounds(const bbc_scene* scene, const bbc_emitters* emitters, const bbc_subdiv_params* params,
+                            void* stream, bbc_bounds** out) {
+  if (!out) return invalid("null output handle pointer");
+  *out = nullptr;
+  bbc_status e = validate(scene, emitters, params);
+  if (e) return e;
+  Bounds* b = new (std::nothrow) Bounds();
+  if (!b) {
+    set_error("host allocation failed");
+    return BBC_ENOMEM;
+  }
+  BBC_HIP(hipGetDevice(&b->device));
+  const hipStream_t s = as_stream(stream);
+  if ((e = load_scene(b, scene, emitters, params, s)) || (e = run_build(b, s))) {
+    (void)hipStreamSynchronize(s);
+    release_all(b);
+    delete b;
+    return e;
+  }
+  *out = reinterpret_cast<bbc_bounds*>(b);
+  return BBC_OK;
+}
+
+bbc_status bbc_free_bounds(bbc_bounds* h) {
+  if (!h) return BBC_OK;
+  Bounds* b = reinterpret_cast<Bounds*>(h);
+  (void)hipDeviceSynchronize();
+  release_all(b);
+  if (b->ev[0]) (void)hipEventDestroy(b->ev[0]);
+  if (b->ev[1]) (void)hipEventDestroy(b->ev[1]);
+  delete b;
+  return BBC_OK;
+}
+
+bbc_status bbc_bounds_info(const bbc_bounds* h, bbc_bounds_info_t* out) {
+  if (!h || !out) return invalid("null argument");
+  const Bounds* b = reinterpret_cast<const Bounds*>(h);
+  out->n_tuples = b->n_tuples;
+  out->n_live_tuples = b->host.n_live;
+  out->n_boxes = int64_t(b->host.n_boxes) + int64_t(b->host.n_fp64);
+  out->n_leaves = b->n_leaves;
+  out->n_grid_entries = b->n_entries;
+  out->n_inf_leaves = b->host.n_inf;
+  out->n_fp64_boxes = int64_t(b->host.n_fp64) + int64_t(b->host.n_l0_fp64);
+  out->device_bytes = b->device_bytes;
+  out->grid_res = b->params.grid_res;
+  out->max_depth_reached = int32_t(b->host.max_depth);
+  return BBC_OK;
+}
+
+bbc_status bbc_export_leaves(const bbc_bounds* h, uint32_t* tuple, uint32_t* code, float* box, float* ukbox, float* E) {
+  if (!h) return invalid("null bounds handle");
+  const Bounds* b = reinterpret_cast<const Bounds*>(h);
+  const size_t n = size_t(b->n_leaves);
+  std::vector<uint32_t> t(n), c(n);
+  std::vector<float> u(4 * n), e(2 * n);
+  if (n) {
+    BBC_HIP(hipMemcpy(t.data(), b->st.p, n * 4, hipMemcpyDeviceToHost));
+    BBC_HIP(hipMemcpy(c.data(), b->sc.p, n * 4, hipMemcpyDeviceToHost));
+    BBC_HIP(hipMemcpy(u.data(), b->su.p, n * 16, hipMemcpyDeviceToHost));
+    BBC_HIP(hipMemcpy(e.data(), b->se.p, n * 8, hipMemcpyDeviceToHost));
+  }
+  if (tuple) std::memcpy(tuple, t.data(), n * 4);
+  if (code) std::memcpy(code, c.data(), n * 4);
+  if (ukbox) std::memcpy(ukbox, u.data(), n * 16);
+  if (E) std::memcpy(E, e.data(), n * 8);
+  if (box) {
+    std::vector<float> root(4 * size_t(b->n_tuples));
+    BBC_HIP(hipMemcpy(root.data(), b->root.p, root.size() * 4, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < n; ++i) {
+      const float* r = &root[4 * size_t(t[i])];
+      const int depth = int(c[i] >> 28);
+      const uint32_t iu = (c[i] >> kCodeBits) & ((1u << kCodeBits) - 1), iv = c[i] & ((1u << kCodeBits) - 1);
+      const float sc = std::ldexp(1.f, -depth);
+      const float fu = (r[1] - r[0]) * sc, fv = (r[3] - r[2]) * sc;
+      box[4 * i + 0] = r[0] + float(iu) * fu;
+      box[4 * i + 1] = r[0] + float(iu + 1) * fu;
+      box[4 * i + 2] = r[2] + float(iv) * fv;
+      box[4 * i + 3] = r[2] + float(iv + 1) * fv;
+    }
+  }
+  return BBC_OK;
+}
+
+bbc_status bbc_export_grid(const bbc_bounds* h, uint32_t* offsets, uint32_t* tuple, float* Et) {
+  if (!h) return invalid("null bounds handle");
+  const Bounds* b = reinterpret_cast<const Bounds*>(h);
+  const int64_t nc = int64_t(b->params.grid_res) * b->params.grid_res;
+  if (offsets) BBC_HIP(hipMemcpy(offsets, b->coff.p, size_t(nc + 1) * 4, hipMemcpyDeviceToHost));
+  if (tuple && b->n_entries) BBC_HIP(hipMemcpy(tuple, b->gt.p, size_t(b->n_entries) * 4, hipMemcpyDeviceToHost));
+  if (Et && b->n_entries) BBC_HIP(hipMemcpy(Et, b->ge.p, size_t(b->n_entries) * 4, hipMemcpyDeviceToHost));
+  return BBC_OK;
+}
+
+bbc_status bbc_query_irradiance_ex(const bbc_bounds* h, const float* points_dev, int64_t n, int32_t spp,
+                                   uint64_t seed, int64_t point_index_base, int32_t mode, float* out_E_dev,
+                                   float* stats_dev, bbc_query_stats* stats_host, void* stream) {
+  if (!h) return invalid("null bounds handle");
+  if (n < 0 || n > (int64_t(1) << 31)) return invalid("n must be in [0, 2^31]");
+  if (n > 0 && (!points_dev || !out_E_dev)) return invalid("null points or output");
+  if (spp < 1) return invalid("spp must be >= 1");
+  if (point_index_base < 0) return invalid("point_index_base must be >= 0");
+  const int form = mode & 15;
+  if ((form != BBC_QUERY_FUSED && form != BBC_QUERY_STAGED) || (mode & ~(15 | BBC_QUERY_EXHAUSTIVE)))
+    return invalid("unknown query mode");
+  Bounds* b = const_cast<Bounds*>(reinterpret_cast<const Bounds*>(h));
+  const hipStream_t s = as_stream(stream);
+  bbc_status e;
+  float* st = stats_dev;
+  DevBuf tmp_stats;
+  if (stats_host && !st && n > 0) {
+    if ((e = ensure(tmp_stats, size_t(n) * 16, nullptr))) return e;
+    st = static_cast<float*>(tmp_stats.p);
+  }
+  unsigned long long* ctr = nullptr;
+  if (stats_host) {
+    if ((e = ensure(b->qcounters, 64, b))) return e;
+    ctr = static_cast<unsigned long long*>(b->qcounters.p);
+    if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(ctr), 0u, 16, s))) return e;
+  }
+  if (form == BBC_QUERY_STAGED)
+    e = launch_query_staged(b, points_dev, n, spp, seed, point_index_base, mode, out_E_dev, nullptr, ctr, s);
+  else
+    e = launch_query(b, points_dev, n, spp, seed, point_index_base, mode, out_E_dev, st, ctr, s);
+  if (e) {
+    release(tmp_stats);
+    return e;
+  }
+  if (stats_host) {
+    std::memset(stats_host, 0, sizeof(*stats_host));
+    stats_host->n_points = n;
+    unsigned long long c[8] = {0};
+    BBC_HIP(hipMemcpyAsync(c, ctr, 64, hipMemcpyDeviceToHost, s));
+    BBC_HIP(hipStreamSynchronize(s));
+    stats_host->n_pairs = int64_t(c[0]);
+    stats_host->n_newton = int64_t(c[1]);
+    stats_host->n_iter_fp32 = int64_t(c[2]);
+    stats_host->n_iter_fp64 = int64_t(c[3]);
+    stats_host->n_roots = int64_t(c[4]);
+    if (form == BBC_QUERY_FUSED && n > 0) {
+      std::vector<float> hs(size_t(n) * 4);
+      BBC_HIP(hipMemcpyAsync(hs.data(), st, hs.size() * 4, hipMemcpyDeviceToHost, s));
+      BBC_HIP(hipStreamSynchronize(s));
+      for (int64_t i = 0; i < n; ++i) {
+        stats_host->sum_U += int64_t(hs[4 * i]);
+        stats_host->sum_S += int64_t(hs[4 * i + 1]);
+        stats_host->sum_varbound += hs[4 * i + 3];
+      }
+    }
+  }
+  release(tmp_stats);
+  return BBC_OK;
+}
+
+bbc_status bbc_set_tuning(bbc_bounds* h, int32_t knob, int64_t value) {
+  if (!h) return invalid("null bounds handle");
+  Bounds* b = reinterpret_cast<Bounds*>(h);
+  switch (knob) {
+    case BBC_TUNE_QUERY_WAVES:
+      if (value != 2 && value != 4) return invalid("query waves must be 2 or 4");
+      b->tune.query_waves = int(value);
+      return BBC_OK;
+    case BBC_TUNE_QUERY_GRID:
+      if (value < 1 || value > (1 << 20)) return invalid("query grid must be in [1, 2^20]");
+      b->tune.query_grid = int(value);
+      return BBC_OK;
+    case BBC_TUNE_BUILD_GRID_PER_CU:
+      if (value < 1 || value > 64) return invalid("build grid per CU must be in [1, 64]");
+      b->tune.build_grid_per_cu = int(value);
+      return BBC_OK;
+    case BBC_TUNE_QUERY_TILE:
+      if (value != 16 && value != 32 && value != 64) return invalid("query tile must be 16, 32 or 64");
+      b->tune.query_tile = int(value);
+      return BBC_OK;
+    case BBC_TUNE_TIMING:
+      if (value != 0 && value != 1) return invalid("timing must be 0 or 1");
+      if (value && !b->ev[0]) {
+        BBC_HIP(hipEventCreate(&b->ev[0]));
+        BBC_HIP(hipEventCreate(&b->ev[1]));
+      }
+      b->tune.timing = int(value);
+      return BBC_OK;
+    default:
+      return invalid("unknown tuning knob");
+  }
+}
+
+bbc_status bbc_get_tuning(const bbc_bounds* h, int32_t knob, int64_t* value) {
+  if (!h || !value) return invalid("null argument");
+  const Bounds* b = reinterpret_cast<const Bounds*>(h);
+  switch (knob) {
+    case BBC_TUNE_QUERY_WAVES: *value = b->tune.query_waves; return BBC_OK;
+    case BBC_TUNE_QUERY_GRID: *value = b->tune.query_grid; return BBC_OK;
+    case BBC_TUNE_BUILD_GRID_PER_CU: *value = b->tune.build_grid_per_cu; return BBC_OK;
+    case BBC_TUNE_QUERY_TILE: *value = b->tune.query_tile; return BBC_OK;
+    case BBC_TUNE_TIMING: *value = b->tune.timing; return BBC_OK;
+    default: return invalid("unknown tuning knob");
+  }
+}
+
+bbc_status bbc_query_kernel_ms(const bbc_bounds* h, float* ms) {
+  if (!h || !ms) return invalid("null argument");
+  const Bounds* b = reinterpret_cast<const Bounds*>(h);
+  if (!b->tune.timing || !b->ev_recorded) return invalid("no timed query on this handle (enable BBC_TUNE_TIMING)");
+  BBC_HIP(hipEventSynchronize(b->ev[1]));
+  BBC_HIP(hipEventElapsedTime(ms, b->ev[0], b->ev[1]));
+  return BBC_OK;
+}
+
+bbc_status bbc_query_irradiance(const bbc_bounds* b, const float* points_dev, int64_t n, int32_t spp, uint64_t seed,
+                                float* out_E_dev, bbc_query_stats* stats_host, void* stream) {
+  return bbc_query_irradiance_ex(b, points_dev, n, spp, seed, 0, BBC_QUERY_FUSED, out_E_dev, nullptr, stats_host,
+                                 stream);
+}
+
+}  // extern "C"

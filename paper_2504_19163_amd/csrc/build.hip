@@ -1,0 +1,307 @@
+// Stage 1-2 on the GPU: tuple culling, domain initialisation and adaptive
+// subdivision with Bernstein bounds (Sec. 4.1-4.4, Sec. 6.1).
+//
+// Work decomposition (one wave = one workgroup of 64 lanes per box, lanes
+// over the Bernstein coefficients of the box's polynomials in LDS):
+//   k_level0       every tuple's [0,1]^2 box, position bound only: culled /
+//                  settled (root box [0,1]^2) / needs refinement
+//   k_init         breadth-first domain initialisation of the unsettled tuples
+//   k_subdiv<L>    one launch per depth L; persistent waves stride over the
+//                  depth's queue: bound the box, emit a leaf or push its four
+//                  children to the next depth's queue
+//   *_fp64         the same decisions for boxes whose denominators could not
+//                  be given a sign in FP32
+// No host synchronisation happens between launches; every count lives in
+// device memory and every buffer has a capacity checked on the device.
+#include "box_r.hpp"
+#include "internal.hpp"
+
+namespace bbc {
+
+struct BuildArgs {
+  DevScene sc;
+  int64_t n_tuples;
+  int max_depth, init_levels, init_pieces, flags;
+  float sigma, alpha;
+  BuildCounters* C;
+  float4* root;
+  uint32_t* init_q;
+  uint32_t* l0f_q;
+  QItem* qin;
+  QItem* qout;
+  QItem* fq;
+  uint32_t q_cap, fq_cap, leaf_cap;
+  uint32_t* lt;
+  uint32_t* lc;
+  float4* lu;
+  float2* le;
+};
+
+__device__ __forceinline__ void push_root(const BuildArgs& a, uint32_t t, float4 box) {
+  a.root[t] = box;
+  const uint32_t i = atomicAdd(&a.C->qcount[0], 1u);
+  if (i < a.q_cap)
+    a.qout[i] = QItem{t, 0u};
+  else
+    atomicOr(&a.C->overflow, 1u);
+  atomicAdd(&a.C->n_live, 1u);
+}
+
+// Level 0: the whole parameter square of every tuple, position bound only.
+template <class T>
+__device__ void level0_one(const BuildArgs& a, uint32_t t, bool final, LdsRPos<T>& L, int lane) {
+  const TupleGeom<T> G = tuple_geom<T>(a.sc, t);
+  if (!G.front) return;
+  const BoxOut o = eval_box_r<T, false>(G, T(0), T(1), T(0), T(1), final, L, lane);
+  if (lane != 0) return;
+  if (o.status == 2) {
+    const uint32_t i = atomicAdd(&a.C->n_l0_fp64, 1u);
+    a.l0f_q[i] = t;  // capacity n_tuples: cannot overflow
+    return;
+  }
+  if (o.status == 0) return;
+  if (o.settled || a.init_levels == 0) {
+    push_root(a, t, make_float4(0.f, 1.f, 0.f, 1.f));
+  } else {
+    const uint32_t i = atomicAdd(&a.C->n_init, 1u);
+    a.init_q[i] = t;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_level0(BuildArgs a) {
+  __shared__ LdsRPos<float> L;
+  const int lane = threadIdx.x;
+  for (int64_t t = blockIdx.x; t < a.n_tuples; t += gridDim.x) {
+    level0_one<float>(a, uint32_t(t), false, L, lane);
+    wave_sync();
+  }
+}
+
+__global__ void __launch_bounds__(64) k_level0_fp64(BuildArgs a) {
+  __shared__ LdsRPos<double> L;
+  const int lane = threadIdx.x;
+  const uint32_t n = a.C->n_l0_fp64;
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    level0_one<double>(a, a.l0f_q[i], true, L, lane);
+    wave_sync();
+  }
+}
+
+// Domain initialisation (Sec. 6.1): breadth-first refinement of [0,1]^2 that
+// keeps boxes whose position bound meets the receiver; a box whose bound lies
+// wholly inside [0,1]^2 with the receiver ahead is settled and kept as is.
+// Stops when all kept boxes are settled, when more than init_pieces would be
+// kept, or after init_levels levels; the root is the kept boxes' bounding box.
+constexpr int kInitCap = 260;  // init_pieces <= 256, plus one parent's children
+struct InitBox {
+  uint32_t code;  // level << 28 | iu << 14 | iv
+  uint32_t settled;
+};
+
+__global__ void __launch_bounds__(64) k_init(BuildArgs a) {
+  __shared__ LdsRPos<float> Lf;
+  __shared__ LdsRPos<double> Ld;
+  __shared__ InitBox cur[kInitCap], nxt[kInitCap];
+  const int lane = threadIdx.x;
+  const uint32_t n = a.C->n_init;
+  for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const uint32_t t = a.init_q[it];
+    const TupleGeom<float> Gf = tuple_geom<float>(a.sc, t);
+    const TupleGeom<double> Gd = tuple_geom<double>(a.sc, t);
+    int ncur = 1;
+    if (lane == 0) cur[0] = InitBox{0u, 0u};
+    wave_sync();
+    bool dead = false;
+    for (int level = 1; level <= a.init_levels; ++level) {
+      bool all_settled = true;
+      for (int j = 0; j < ncur; ++j) all_settled = all_settled && cur[j].settled;
+      if (all_settled) break;
+      int nn = 0;
+      bool over = false;
+      for (int j = 0; j < ncur && !over; ++j) {
+        const InitBox b = cur[j];
+        if (b.settled) {
+          if (lane == 0) nxt[nn] = b;
+          ++nn;
+          over = nn > a.init_pieces;
+          continue;
+        }
+        const int bl = int(b.code >> 28);
+        const uint32_t iu = (b.code >> 14) & 0x3fffu, iv = b.code & 0x3fffu;
+        for (int ch = 0; ch < 4 && !over; ++ch) {
+          const uint32_t cu = 2 * iu + (ch >> 1), cv = 2 * iv + (ch & 1);
+          const int cl = bl + 1;
+          const float w = ldexpf(1.f, -cl);
+          wave_sync();
+          BoxOut o = eval_box_r<float, false>(Gf, cu * w, (cu + 1) * w, cv * w, (cv + 1) * w, false, Lf, lane);
+          if (o.status == 2) {
+            wave_sync();
+            const double wd = ldexp(1.0, -cl);
+            o = eval_box_r<double, false>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, true, Ld, lane);
+          }
+          if (o.status == 1) {
+            if (lane == 0) nxt[nn] = InitBox{uint32_t(cl) << 28 | cu << 14 | cv, o.settled ? 1u : 0u};
+            ++nn;
+            over = nn > a.init_pieces;
+          }
+        }
+      }
+      wave_sync();
+      if (over) break;
+      if (nn == 0) {
+        dead = true;
+        break;
+      }
+      for (int j = lane; j < nn; j += BBC_WAVE) cur[j] = nxt[j];
+      ncur = nn;
+      wave_sync();
+    }
+    if (!dead && lane == 0) {
+      float u0 = 1.f, u1 = 0.f, v0 = 1.f, v1 = 0.f;
+      for (int j = 0; j < ncur; ++j) {
+        const int bl = int(cur[j].code >> 28);
+        const float w = ldexpf(1.f, -bl);
+        const uint32_t iu = (cur[j].code >> 14) & 0x3fffu, iv = cur[j].code & 0x3fffu;
+        u0 = fminf(u0, iu * w);
+        u1 = fmaxf(u1, (iu + 1) * w);
+        v0 = fminf(v0, iv * w);
+        v1 = fmaxf(v1, (iv + 1) * w);
+      }
+      push_root(a, t, make_float4(u0, u1, v0, v1));
+    }
+    wave_sync();
+  }
+}
+
+// One box of the adaptive subdivision (Sec. 6.1): stop when the clipped
+// position bound's area is below sigma, when E_hi / E_lo < alpha, or at the
+// depth cap; otherwise split at the midpoint into four.
+template <class T>
+__device__ void subdiv_one(const BuildArgs& a, QItem it, int depth, bool final, LdsR<T>& L, int lane,
+                           uint32_t* n_boxes) {
+  const TupleGeom<T> G = tuple_geom<T>(a.sc, it.tuple);
+  const float4 r = a.root[it.tuple];
+  const uint32_t iu = it.code >> kCodeBits, iv = it.code & ((1u << kCodeBits) - 1);
+  const T fu = (T(r.y) - T(r.x)) * T(ldexpf(1.f, -depth)), fv = (T(r.w) - T(r.z)) * T(ldexpf(1.f, -depth));
+  const T u0 = T(r.x) + T(iu) * fu, u1 = T(r.x) + T(iu + 1) * fu;
+  const T v0 = T(r.z) + T(iv) * fv, v1 = T(r.z) + T(iv + 1) * fv;
+  const BoxOut o = eval_box_r<T, true>(G, u0, u1, v0, v1, final, L, lane);
+  ++*n_boxes;
+  if (lane != 0) return;
+  if (o.status == 2) {
+    const uint32_t i = atomicAdd(&a.C->fcount[depth], 1u);
+    if (i < a.fq_cap)
+      a.fq[i] = it;
+    else
+      atomicOr(&a.C->overflow, 8u);
+    return;
+  }
+  if (o.status == 0) return;
+  const float area = (o.uk[1] - o.uk[0]) * (o.uk[3] - o.uk[2]);
+  bool stop = depth >= a.max_depth;
+  if (!(a.flags & BBC_FLAG_FIXED_DEPTH)) {
+    stop = stop || area < a.sigma;
+    stop = stop || (o.E[0] > 0.f && isfinite(o.E[1]) && o.E[1] < a.alpha * o.E[0]);
+  }
+  if (stop) {
+    const uint32_t i = atomicAdd(&a.C->n_leaves, 1u);
+    if (i < a.leaf_cap) {
+      a.lt[i] = it.tuple;
+      a.lc[i] = uint32_t(depth) << 28 | it.code;
+      a.lu[i] = make_float4(o.uk[0], o.uk[1], o.uk[2], o.uk[3]);
+      a.le[i] = make_float2(o.E[0], o.E[1]);
+    } else {
+      atomicOr(&a.C->overflow, 2u);
+    }
+    if (isinf(o.E[1])) atomicAdd(&a.C->n_inf, 1u);
+    atomicMax(&a.C->max_depth, uint32_t(depth));
+    return;
+  }
+  const uint32_t i = atomicAdd(&a.C->qcount[depth + 1], 4u);
+  if (i + 4 <= a.q_cap) {
+    for (uint32_t ch = 0; ch < 4; ++ch)
+      a.qout[i + ch] = QItem{it.tuple, (2 * iu + (ch >> 1)) << kCodeBits | (2 * iv + (ch & 1))};
+  } else {
+    atomicOr(&a.C->overflow, 1u);
+  }
+}
+
+// Subdivision boxes carry the irradiance bound, whose denominator det M has
+// coefficients that cancel by two to five orders of magnitude; they are
+// evaluated in FP64, which on this GPU issues at the rate of unpacked FP32.
+__global__ void __launch_bounds__(64) k_subdiv(BuildArgs a, int depth) {
+  __shared__ LdsR<double> L;
+  const int lane = threadIdx.x;
+  const uint32_t n = min(a.C->qcount[depth], a.q_cap);
+  uint32_t boxes = 0;
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    subdiv_one<double>(a, a.qin[i], depth, true, L, lane, &boxes);
+    wave_sync();
+  }
+  if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+bbc_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return BBC_OK;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(blocks)), dim3(256), 0, s, p, v, n);
+  BBC_HIP(hipGetLastError());
+  return BBC_OK;
+}
+
+bbc_status launch_build(Bounds* b, hipStream_t s) {
+  BuildArgs a{};
+  a.sc = b->scene;
+  a.n_tuples = b->n_tuples;
+  a.max_depth = b->params.max_depth;
+  a.init_levels = b->params.init_levels;
+  a.init_pieces = b->params.init_pieces;
+  a.flags = b->params.flags;
+  a.sigma = b->params.sigma;
+  a.alpha = b->params.alpha;
+  a.C = static_cast<BuildCounters*>(b->counters.p);
+  a.root = static_cast<float4*>(b->root.p);
+  a.init_q = static_cast<uint32_t*>(b->init_q.p);
+  a.l0f_q = static_cast<uint32_t*>(b->l0f_q.p);
+  a.fq = static_cast<QItem*>(b->fq.p);
+  a.q_cap = uint32_t(b->q_cap);
+  a.fq_cap = uint32_t(b->fq_cap);
+  a.leaf_cap = uint32_t(b->leaf_cap);
+  a.lt = static_cast<uint32_t*>(b->lt.p);
+  a.lc = static_cast<uint32_t*>(b->lc.p);
+  a.lu = static_cast<float4*>(b->lu.p);
+  a.le = static_cast<float2*>(b->le.p);
+  int dev = 0;
+  BBC_HIP(hipGetDevice(&dev));
+  int n_cu = 256;
+  BBC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  const unsigned persistent = unsigned(n_cu) * unsigned(std::max(1, b->tune.build_grid_per_cu));
+
+  bbc_status st = launch_fill_u32(static_cast<uint32_t*>(b->counters.p), 0u, sizeof(BuildCounters) / 4, s);
+  if (st) return st;
+  a.qin = nullptr;
+  a.qout = static_cast<QItem*>(b->q[0].p);
+  const unsigned g0 = unsigned(std::min<int64_t>(b->n_tuples, int64_t(n_cu) * 64));
+  hipLaunchKernelGGL(k_level0, dim3(g0), dim3(64), 0, s, a);
+  BBC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_level0_fp64, dim3(persistent), dim3(64), 0, s, a);
+  BBC_HIP(hipGetLastError());
+  if (a.init_levels > 0) {
+    hipLaunchKernelGGL(k_init, dim3(persistent), dim3(64), 0, s, a);
+    BBC_HIP(hipGetLastError());
+  }
+  for (int d = 0; d <= a.max_depth; ++d) {
+    a.qin = static_cast<QItem*>(b->q[d & 1].p);
+    a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
+    hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, s, a, d);
+    BBC_HIP(hipGetLastError());
+  }
+  return BBC_OK;
+}
+
+}  // namespace bbc

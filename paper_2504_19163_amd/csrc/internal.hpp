@@ -1,0 +1,120 @@
+// Library-internal state of a bound hierarchy and the launch entry points of
+// the kernels (one translation unit per stage).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bbc.h"
+#include "geom_dev.hpp"
+
+namespace bbc {
+
+// Subdivision queue item: tuple id and the box index at the item's depth,
+// packed as iu << 14 | iv (depth <= 14).
+struct QItem {
+  uint32_t tuple;
+  uint32_t code;
+};
+
+constexpr int kCodeBits = 14;
+constexpr int kMaxDepth = 14;
+
+// Device counters of one build (zeroed by a fill kernel at the start).
+struct BuildCounters {
+  uint32_t n_init;                 // unsettled tuples queued for domain initialisation
+  uint32_t n_l0_fp64;              // level-0 boxes queued for FP64 re-evaluation
+  uint32_t n_leaves;
+  uint32_t n_boxes;
+  uint32_t n_fp64;
+  uint32_t n_live;                 // tuples with a root box
+  uint32_t overflow;               // bit flags: 1 queue, 2 leaves, 4 grid entries, 8 fp64 queue, 16 init
+  uint32_t max_depth;
+  uint32_t n_triples;
+  uint32_t n_inf;
+  uint32_t qcount[kMaxDepth + 2];  // items at each depth
+  uint32_t fcount[kMaxDepth + 2];  // FP64 items at each depth
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Launch-shape knobs chosen by the autotuner (bbc_set_tuning).
+struct Tuning {
+  int query_waves = 2;        // fused query: minimum waves per SIMD (register budget 256 / 128)
+  int query_grid = 256 * 64;  // fused query: persistent workgroups
+  int query_tile = 16;        // fused query: shading points per wave (16, 32 or 64)
+  int timing = 0;             // record events around the query's dominant kernel
+  int build_grid_per_cu = 16; // subdivision: persistent workgroups per CU
+};
+
+struct Bounds {
+  int device = 0;
+  Tuning tune;
+  bbc_subdiv_params params{};
+  DevScene scene{};       // device pointers into the buffers below
+  int64_t n_tuples = 0;
+  // scene copies
+  DevBuf pos, nrm, epos, eI;
+  // build work space
+  DevBuf counters;        // BuildCounters
+  DevBuf root;            // float4 [n_tuples]
+  DevBuf init_q;          // uint32 [n_tuples]
+  DevBuf l0f_q;           // uint32 [n_tuples]
+  DevBuf q[2];            // QItem ping-pong
+  DevBuf fq;              // QItem FP64 queue
+  size_t q_cap = 0, fq_cap = 0;
+  // leaves (unsorted, then grouped by tuple)
+  DevBuf lt, lc, lu, le;      // tuple u32, code u32, ukbox float4, E float2
+  DevBuf gl_t, gl_c, gl_u, gl_e;  // grouped by tuple
+  DevBuf st, sc, su, se;      // grouped by tuple, ordered by code
+  size_t leaf_cap = 0;
+  DevBuf tcount, toff, tcur;  // per-tuple counts / offsets [n_tuples + 1] / cursors
+  // receiver grid
+  DevBuf trip;                // triples: cell u32, tuple u32, E float
+  size_t trip_cap = 0;
+  DevBuf ccount, coff, ccur;  // per-cell counts / offsets [G*G + 1] / cursors
+  DevBuf ut, ue, ucell;       // entries grouped by cell (unsorted)
+  DevBuf gt, ge;              // entries: tuple u32, E~ float, sorted by tuple per cell
+  DevBuf scan_tmp;
+  DevBuf trec;                // packed per-tuple records for the query [n_tuples][32] float
+  // host copies of the final counts
+  BuildCounters host{};
+  int64_t n_leaves = 0, n_entries = 0, max_cell = 0;
+  int64_t device_bytes = 0;
+  // query work space (staged form), grown on demand
+  DevBuf qw_cell, qw_gamma, qw_cnt, qw_off, qw_pair_pt, qw_pair_t, qw_pair_p, qw_pair_c, qw_stats;
+  size_t qw_pts = 0, qw_pairs = 0;
+  DevBuf max_cell_dev;
+  DevBuf qcounters;           // 8 x u64 query work counters (filled when host stats are requested)
+  hipEvent_t ev[2] = {nullptr, nullptr};  // around the last query's dominant kernel
+  bool ev_recorded = false;
+};
+
+// error plumbing
+void set_error(const std::string& msg);
+bbc_status hip_fail(hipError_t e, const char* what);
+#define BBC_HIP(call)                                         \
+  do {                                                        \
+    hipError_t _e = (call);                                   \
+    if (_e != hipSuccess) return ::bbc::hip_fail(_e, #call);  \
+  } while (0)
+
+bbc_status ensure(DevBuf& b, size_t bytes, Bounds* owner);
+void release(DevBuf& b);
+
+// stage launchers (stream-ordered, no host synchronisation)
+bbc_status launch_build(Bounds* b, hipStream_t s);
+bbc_status launch_record(Bounds* b, hipStream_t s);
+bbc_status launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp, hipStream_t s);
+size_t scan_tmp_bytes(int64_t n);
+bbc_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+bbc_status launch_query(const Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
+                        int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t s);
+bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
+                               int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t s);
+
+}  // namespace bbc

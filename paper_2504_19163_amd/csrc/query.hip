@@ -1,0 +1,542 @@
+// Stage 3 on the GPU: bound-driven sampling of triangle tuples and Newton
+// root-finding per shading point (Sec. 5.3-5.4, Alg. 1; Sec. 6.1 root-finding).
+//
+// Fused form (k_query_fused): one wave per shading point.  The wave reads the
+// candidate list U of the point's grid cell (one entry per lane, chunks of
+// 64), solves gamma of P_T = min(gamma E~_T, 1) by water-filling with wave
+// reductions, draws each tuple's Bernoulli decision from Philox keyed by
+// (seed, point index, tuple), runs Newton for the selected tuples lane-
+// parallel (FP32 iterations, FP64 polish of every root) and reduces
+// sum E(T) / P_T in a fixed lane order.
+//
+// Staged form: the same stages as separate launches with their intermediate
+// results in HBM: gamma per point, selection count + scan + compaction into
+// (point, tuple, P) pairs, Newton per pair, accumulation per point.
+#include "internal.hpp"
+#include "path_dev.hpp"
+
+namespace bbc {
+
+struct QueryArgs {
+  DevScene sc;
+  int G;
+  const float* rec;
+  const float4* root;
+  const uint32_t* toff;
+  const uint32_t* lcode;
+  const float4* luk;
+  const uint32_t* coff;
+  const uint32_t* gt;
+  const float* ge;
+  const float* pts;
+  int64_t n;
+  float W;
+  uint64_t seed;
+  int64_t base;
+  int mode;
+  float* out;
+  float* stats;
+  unsigned long long* counters;  // nullable: pairs, starts, FP32 iterations, FP64 steps, roots
+};
+
+// Per-lane work counters, summed per wave into the optional device counters.
+struct WorkCount {
+  uint32_t pairs = 0, starts = 0, it32 = 0, it64 = 0, roots = 0;
+};
+
+__device__ __forceinline__ void flush_counts(const QueryArgs& a, WorkCount w) {
+  if (!a.counters) return;
+  const unsigned long long v[5] = {wave_sum(w.pairs), wave_sum(w.starts), wave_sum(w.it32), wave_sum(w.it64),
+                                   wave_sum(w.roots)};
+  if ((threadIdx.x % BBC_WAVE) == 0)
+    for (int k = 0; k < 5; ++k)
+      if (v[k]) atomicAdd(&a.counters[k], v[k]);
+}
+
+struct Target {
+  bool on;
+  float u, v;
+  double ud, vd;
+  uint32_t cell;
+};
+
+// Receiver texture coordinates of a shading point (least squares on the
+// receiver parallelogram) and its grid cell (Sec. 6.1 bound storage).
+__device__ __forceinline__ Target receiver_target(const QueryArgs& a, int64_t i) {
+  Target t;
+  const double x = a.pts[i], y = a.pts[a.n + i], z = a.pts[2 * a.n + i];
+  const double rx = x - a.sc.q0[0], ry = y - a.sc.q0[1], rz = z - a.sc.q0[2];
+  const double f1x = a.sc.f1[0], f1y = a.sc.f1[1], f1z = a.sc.f1[2];
+  const double f2x = a.sc.f2[0], f2y = a.sc.f2[1], f2z = a.sc.f2[2];
+  const double A = f1x * f1x + f1y * f1y + f1z * f1z, B = f1x * f2x + f1y * f2y + f1z * f2z;
+  const double D = f2x * f2x + f2y * f2y + f2z * f2z;
+  const double r1 = f1x * rx + f1y * ry + f1z * rz, r2 = f2x * rx + f2y * ry + f2z * rz;
+  const double det = A * D - B * B;
+  t.ud = (D * r1 - B * r2) / det;
+  t.vd = (A * r2 - B * r1) / det;
+  t.u = float(t.ud);
+  t.v = float(t.vd);
+  t.on = t.ud >= 0.0 && t.ud <= 1.0 && t.vd >= 0.0 && t.vd <= 1.0;
+  const int cu = min(a.G - 1, max(0, int(floor(t.ud * a.G))));
+  const int cv = min(a.G - 1, max(0, int(floor(t.vd * a.G))));
+  t.cell = uint32_t(cu) * uint32_t(a.G) + uint32_t(cv);
+  return t;
+}
+
+// Water-filling solve of gamma (Sec. 5.4): W' = min(W, |U|); unbounded entries
+// take P = 1, the finite positive entries share W_f = min(max(W' - n_inf, 1),
+// n_fin) expected samples with P = min(gamma E~, 1).  Iterates the saturated
+// set {gamma E~ >= 1}, which only grows, until it is stable.  Returns +inf when
+// every finite entry is taken with P = 1.  One thread per shading point.
+__device__ float solve_gamma(const float* Et, uint32_t nU, float W) {
+  uint32_t n_inf = 0, n_fin = 0;
+  float S = 0.f;
+  for (uint32_t j = 0; j < nU; ++j) {
+    const float e = Et[j];
+    n_inf += isinf(e) ? 1u : 0u;
+    if (isfinite(e) && e > 0.f) {
+      ++n_fin;
+      S += e;
+    }
+  }
+  const float Wp = fminf(W, float(nU));
+  const float Wf = fminf(fmaxf(Wp - float(n_inf), 1.f), float(n_fin));
+  if (n_fin == 0 || Wf >= float(n_fin)) return INFINITY;
+  float gamma = Wf / S;
+  uint32_t k = 0;
+  for (uint32_t iter = 0; iter <= n_fin; ++iter) {
+    uint32_t kn = 0;
+    float Sn = 0.f;
+    for (uint32_t j = 0; j < nU; ++j) {
+      const float e = Et[j];
+      if (isfinite(e) && e > 0.f) {
+        if (gamma * e >= 1.f)
+          ++kn;
+        else
+          Sn += e;
+      }
+    }
+    if (kn == k || !(Sn > 0.f)) break;
+    k = kn;
+    gamma = (Wf - float(k)) / Sn;
+  }
+  return gamma;
+}
+
+__device__ __forceinline__ float select_prob(float e, float gamma, bool exhaustive) {
+  if (exhaustive) return 1.f;
+  if (isinf(e)) return 1.f;
+  if (!(e > 0.f)) return 0.f;
+  return fminf(gamma * e, 1.f);
+}
+
+// Sum of the irradiance of every admissible path of tuple T that Newton finds
+// from the centres of T's leaves whose position bound contains the target
+// (deterministic initialisation, Sec. 6.1): FP32 iterations that abandon a
+// start leaving its box by more than one width, then two FP64 steps; a root is
+// accepted when its FP64 residual on the receiver is below 1e-6 scene units.
+__device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target& tg, WorkCount& wc) {
+  float rec[kRecFloats];
+  const float4* r4 = reinterpret_cast<const float4*>(a.rec + size_t(T) * kRecFloats);
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const float4 q = r4[k];
+    rec[4 * k] = q.x;
+    rec[4 * k + 1] = q.y;
+    rec[4 * k + 2] = q.z;
+    rec[4 * k + 3] = q.w;
+  }
+  const uint32_t lb = __float_as_uint(rec[22]), le = __float_as_uint(rec[23]);
+  if (lb == le) return 0.0;
+  const int chain = a.sc.chain;
+  const TupleGeom<float> Gf = tuple_geom_rec<float>(rec, a.sc);
+  const float rx = rec[24], ry = rec[25], rz = rec[26], rw = rec[27];
+  double ru0 = 0, rv0 = 0, ru1 = 0, rv1 = 0, ru2 = 0, rv2 = 0, ru3 = 0, rv3 = 0;
+  int nr = 0;
+  double ET = 0.0;
+  for (uint32_t k = lb; k < le; ++k) {
+    const float4 uk = a.luk[k];
+    if (!(tg.ud >= uk.x && tg.ud <= uk.y && tg.vd >= uk.z && tg.vd <= uk.w)) continue;
+    const uint32_t code = a.lcode[k];
+    const int depth = int(code >> 28);
+    const uint32_t iu = (code >> kCodeBits) & ((1u << kCodeBits) - 1), iv = code & ((1u << kCodeBits) - 1);
+    const float sc = ldexpf(1.f, -depth);
+    const float fu = (ry - rx) * sc, fv = (rw - rz) * sc;
+    const float u0 = rx + float(iu) * fu, v0 = rz + float(iv) * fv;
+    float u = u0 + 0.5f * fu, v = v0 + 0.5f * fv;
+    const float lu0 = u0 - fu, lu1 = u0 + 2.f * fu, lv0 = v0 - fv, lv1 = v0 + 2.f * fv;
+    ++wc.starts;
+    bool ok = true;
+    for (int it = 0; it < 20; ++it) {
+      ++wc.it32;  // FP32 path evaluations
+      const PathT<float> p = eval_path<float>(Gf, chain, u, v);
+      const float ru_ = p.uk - tg.u, rv_ = p.vk - tg.v;
+      if (!(isfinite(p.det)) || p.det == 0.f) { ok = false; break; }
+      const float du = (p.J11 * ru_ - p.J01 * rv_) / p.det;
+      const float dv = (-p.J10 * ru_ + p.J00 * rv_) / p.det;
+      u -= du;
+      v -= dv;
+      if (!(u >= lu0 && u <= lu1 && v >= lv0 && v <= lv1)) { ok = false; break; }
+      if (fabsf(du) + fabsf(dv) < 2e-7f) break;
+    }
+    if (!ok) continue;
+    {
+      // a start whose FP32 root lies clearly outside the triangle or behind the
+      // receiver cannot become admissible in the polish (margin 1e-3 >> FP32 error)
+      ++wc.it32;
+      const PathT<float> p = eval_path<float>(Gf, chain, u, v);
+      if (!(u >= -1e-3f && v >= -1e-3f && u + v <= 1.f + 1e-3f) || !(p.t > 0.f)) continue;
+    }
+    // FP64 polish: one Newton step from the FP32 root, a second only when the
+    // receiver residual still exceeds 1e-9 scene units
+    const TupleGeom<double> Gd = tuple_geom_rec<double>(rec, a.sc);
+    double ud = u, vd = v;
+    ++wc.it64;  // FP64 path evaluations
+    PathT<double> p = eval_path<double>(Gd, chain, ud, vd);
+    double res = 0.0;
+    for (int it = 0; it < 3; ++it) {
+      ++wc.it64;
+      const double ru_ = p.uk - tg.ud, rv_ = p.vk - tg.vd;
+      if (!(p.det != 0.0) || !isfinite(p.det)) break;
+      ud -= (p.J11 * ru_ - p.J01 * rv_) / p.det;
+      vd -= (-p.J10 * ru_ + p.J00 * rv_) / p.det;
+      p = eval_path<double>(Gd, chain, ud, vd);
+      res = residual<double>(Gd, p, tg.ud, tg.vd);
+      if (res < 1e-9) break;
+    }
+    if (!(res < 1e-6) || !admissible<double>(Gd, chain, p, ud, vd)) continue;
+    bool dup = false;
+    if (nr > 0) dup = dup || (fabs(ru0 - ud) <= 1e-7 && fabs(rv0 - vd) <= 1e-7);
+    if (nr > 1) dup = dup || (fabs(ru1 - ud) <= 1e-7 && fabs(rv1 - vd) <= 1e-7);
+    if (nr > 2) dup = dup || (fabs(ru2 - ud) <= 1e-7 && fabs(rv2 - vd) <= 1e-7);
+    if (nr > 3) dup = dup || (fabs(ru3 - ud) <= 1e-7 && fabs(rv3 - vd) <= 1e-7);
+    if (dup) continue;
+    if (nr == 0) { ru0 = ud; rv0 = vd; }
+    else if (nr == 1) { ru1 = ud; rv1 = vd; }
+    else if (nr == 2) { ru2 = ud; rv2 = vd; }
+    else if (nr == 3) { ru3 = ud; rv3 = vd; }
+    ++nr;
+    ET += path_irradiance<double>(Gd, p);
+    ++wc.roots;
+  }
+  return ET;
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, int lane) {
+  uint32_t inc = v;
+#pragma unroll
+  for (int d = 1; d < BBC_WAVE; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d, BBC_WAVE);
+    if (lane >= d) inc += o;
+  }
+  return inc - v;
+}
+
+// Fused form: one wave owns a tile of 64 consecutive shading points.  Lane =
+// point for the gather, the gamma solve and the Bernoulli draws; the selected
+// (point, tuple) pairs are compacted in LDS in point-then-entry order, Newton
+// runs lane = pair, and each lane sums its own pairs' contributions in entry
+// order, so the estimate is bit-identical to the staged form.
+constexpr int kPairCap = 512;
+
+template <int kWaves, int kTile>
+__global__ void __launch_bounds__(64, kWaves) k_query_fused(QueryArgs a) {
+  __shared__ uint32_t s_t[kPairCap];
+  __shared__ float s_p[kPairCap];
+  __shared__ uint8_t s_pt[kPairCap];
+  __shared__ uint8_t s_nr[kPairCap];
+  __shared__ double s_c[kPairCap];
+  __shared__ double s_ud[kTile], s_vd[kTile];
+  const int lane = threadIdx.x;
+  const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
+  const int64_t n_tiles = (a.n + kTile - 1) / kTile;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t i = tile * kTile + lane;
+    const bool valid = lane < kTile && i < a.n;
+    Target tg{};
+    uint32_t b = 0, nU = 0;
+    if (valid) {
+      tg = receiver_target(a, i);
+      if (tg.on) {
+        b = a.coff[tg.cell];
+        nU = a.coff[tg.cell + 1] - b;
+      }
+    }
+    if (lane < kTile) {
+      s_ud[lane] = tg.ud;
+      s_vd[lane] = tg.vd;
+    }
+    const float* Et = a.ge + b;
+    const uint32_t* Tt = a.gt + b;
+    const float gamma = (exhaustive || nU == 0) ? INFINITY : solve_gamma(Et, nU, a.W);
+    const uint64_t key = uint64_t(a.base + i);
+    uint32_t cnt = 0;
+    double mu2 = 0.0;
+    for (uint32_t j = 0; j < nU; ++j) {
+      const float e = Et[j];
+      const float P = select_prob(e, gamma, exhaustive);
+      if (P > 0.f && isfinite(e)) mu2 += double(e) * double(e) / double(P);
+      cnt += selection_uniform(a.seed, key, Tt[j]) < P ? 1u : 0u;
+    }
+    const uint32_t off = wave_excl_scan(cnt, lane);
+    const uint32_t total = __shfl(off + cnt, BBC_WAVE - 1, BBC_WAVE);
+    double E = 0.0;
+    uint32_t roots = 0, emitted = 0, cur = 0;
+    WorkCount wc;
+    for (uint32_t w0 = 0; w0 < total; w0 += kPairCap) {
+      // this lane's pairs whose global index falls in [w0, w0 + cap)
+      while (emitted < cnt && off + emitted < w0 + kPairCap) {
+        const float e = Et[cur];
+        const uint32_t T = Tt[cur];
+        const float P = select_prob(e, gamma, exhaustive);
+        if (selection_uniform(a.seed, key, T) < P) {
+          const uint32_t slot = off + emitted - w0;
+          s_t[slot] = T;
+          s_p[slot] = P;
+          s_pt[slot] = uint8_t(lane);
+          ++emitted;
+        }
+        ++cur;
+      }
+      __syncthreads();
+      const uint32_t nslots = min(uint32_t(kPairCap), total - w0);
+      for (uint32_t k = lane; k < nslots; k += BBC_WAVE) {
+        const int pt = s_pt[k];
+        Target t2;
+        t2.on = true;
+        t2.ud = s_ud[pt];
+        t2.vd = s_vd[pt];
+        t2.u = float(t2.ud);
+        t2.v = float(t2.vd);
+        const uint32_t r0 = wc.roots;
+        ++wc.pairs;
+        s_c[k] = tuple_irradiance(a, s_t[k], t2, wc) / double(s_p[k]);
+        s_nr[k] = uint8_t(min(wc.roots - r0, 255u));
+      }
+      __syncthreads();
+      const uint32_t lo = max(off, w0), hi = min(off + cnt, w0 + kPairCap);
+      for (uint32_t k = lo; k < hi; ++k) {
+        E += s_c[k - w0];
+        roots += s_nr[k - w0];
+      }
+      __syncthreads();
+    }
+    flush_counts(a, wc);
+    if (valid) {
+      a.out[i] = float(E);
+      if (a.stats) {
+        a.stats[4 * i + 0] = float(nU);
+        a.stats[4 * i + 1] = float(cnt);
+        a.stats[4 * i + 2] = float(roots);
+        a.stats[4 * i + 3] = float(mu2);
+      }
+    }
+  }
+}
+
+static QueryArgs make_args(const Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
+                           int32_t mode, float* out, float* stats, unsigned long long* counters) {
+  QueryArgs a{};
+  a.counters = counters;
+  a.sc = b->scene;
+  a.G = b->params.grid_res;
+  a.rec = static_cast<const float*>(b->trec.p);
+  a.root = static_cast<const float4*>(b->root.p);
+  a.toff = static_cast<const uint32_t*>(b->toff.p);
+  a.lcode = static_cast<const uint32_t*>(b->sc.p);
+  a.luk = static_cast<const float4*>(b->su.p);
+  a.coff = static_cast<const uint32_t*>(b->coff.p);
+  a.gt = static_cast<const uint32_t*>(b->gt.p);
+  a.ge = static_cast<const float*>(b->ge.p);
+  a.pts = pts;
+  a.n = n;
+  a.W = float(spp);
+  a.seed = seed;
+  a.base = base;
+  a.mode = mode;
+  a.out = out;
+  a.stats = stats;
+  return a;
+}
+
+bbc_status launch_query(const Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
+                        int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t s) {
+  if (n == 0) return BBC_OK;
+  const QueryArgs a = make_args(b, pts, n, spp, seed, base, mode, out, stats, counters);
+  const int tp = b->tune.query_tile;
+  const int64_t tiles = (n + tp - 1) / tp;
+  const unsigned grid = unsigned(std::min<int64_t>(tiles, int64_t(b->tune.query_grid)));
+  const bool w4 = b->tune.query_waves >= 4;
+  Bounds* mb = const_cast<Bounds*>(b);
+  if (b->tune.timing) BBC_HIP(hipEventRecord(mb->ev[0], s));
+#define BBC_FUSED(W, TP) hipLaunchKernelGGL((k_query_fused<W, TP>), dim3(grid), dim3(64), 0, s, a)
+  if (tp == 16) {
+    if (w4) BBC_FUSED(4, 16); else BBC_FUSED(2, 16);
+  } else if (tp == 32) {
+    if (w4) BBC_FUSED(4, 32); else BBC_FUSED(2, 32);
+  } else {
+    if (w4) BBC_FUSED(4, 64); else BBC_FUSED(2, 64);
+  }
+#undef BBC_FUSED
+  if (b->tune.timing) {
+    BBC_HIP(hipEventRecord(mb->ev[1], s));
+    mb->ev_recorded = true;
+  }
+  BBC_HIP(hipGetLastError());
+  return BBC_OK;
+}
+
+// ---------------------------------------------------------------- staged form
+struct StagedArgs {
+  QueryArgs q;
+  uint32_t* cell_b;   // [n] first entry of the point's cell (or 0)
+  uint32_t* cnt;      // [n] |U| then selection counts
+  float* gamma;       // [n]
+  uint32_t* off;      // [n + 1]
+  uint32_t* pair_pt;  // [pairs]
+  uint32_t* pair_t;
+  float* pair_p;
+  double* pair_c;
+  uint32_t pair_cap;
+};
+
+__global__ void k_stage_gamma(StagedArgs s) {
+  const QueryArgs& a = s.q;
+  const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x) {
+    const Target tg = receiver_target(a, i);
+    uint32_t b = 0, nU = 0;
+    float gamma = INFINITY;
+    if (tg.on) {
+      b = a.coff[tg.cell];
+      nU = a.coff[tg.cell + 1] - b;
+      if (!exhaustive && nU > 0) gamma = solve_gamma(a.ge + b, nU, a.W);
+    }
+    s.cell_b[i] = b;
+    s.gamma[i] = gamma;
+    s.cnt[i] = nU;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_stage_count(StagedArgs s, uint32_t* sel) {
+  const QueryArgs& a = s.q;
+  const int lane = threadIdx.x;
+  const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
+  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+    const uint32_t b = s.cell_b[i], nU = s.cnt[i];
+    const float gamma = s.gamma[i];
+    uint32_t c = 0;
+    for (uint32_t j = lane; j < nU; j += BBC_WAVE) {
+      const float P = select_prob(a.ge[b + j], gamma, exhaustive);
+      c += selection_uniform(a.seed, uint64_t(a.base + i), a.gt[b + j]) < P ? 1u : 0u;
+    }
+    c = wave_sum(c);
+    if (lane == 0) sel[i] = c;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
+  const QueryArgs& a = s.q;
+  const int lane = threadIdx.x;
+  const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
+  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+    const uint32_t b = s.cell_b[i], nU = s.cnt[i];
+    const float gamma = s.gamma[i];
+    uint32_t o = s.off[i];
+    for (uint32_t j0 = 0; j0 < nU; j0 += BBC_WAVE) {
+      const uint32_t j = j0 + lane;
+      bool take = false;
+      float P = 0.f;
+      uint32_t T = 0;
+      if (j < nU) {
+        T = a.gt[b + j];
+        P = select_prob(a.ge[b + j], gamma, exhaustive);
+        take = selection_uniform(a.seed, uint64_t(a.base + i), T) < P;
+      }
+      const uint64_t m = __ballot(take);
+      const uint32_t rank = __popcll(m & ((1ull << lane) - 1ull));
+      if (take && o + rank < s.pair_cap) {
+        s.pair_pt[o + rank] = uint32_t(i);
+        s.pair_t[o + rank] = T;
+        s.pair_p[o + rank] = P;
+      }
+      o += __popcll(m);
+    }
+  }
+}
+
+__global__ void k_stage_newton(StagedArgs s, const uint32_t* total) {
+  const QueryArgs& a = s.q;
+  const uint32_t np = min(*total, s.pair_cap);
+  WorkCount wc;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x) {
+    const int64_t i = s.pair_pt[k];
+    const Target tg = receiver_target(a, i);
+    ++wc.pairs;
+    s.pair_c[k] = tuple_irradiance(a, s.pair_t[k], tg, wc) / double(s.pair_p[k]);
+  }
+  flush_counts(a, wc);
+}
+
+__global__ void k_stage_accum(StagedArgs s) {
+  const QueryArgs& a = s.q;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x) {
+    double E = 0.0;
+    const uint32_t e = min(s.off[i + 1], s.pair_cap);
+    for (uint32_t k = s.off[i]; k < e; ++k) E += s.pair_c[k];
+    a.out[i] = float(E);
+  }
+}
+
+bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
+                               int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t st) {
+  if (n == 0) return BBC_OK;
+  const size_t pairs = size_t(n) * size_t(std::max<int64_t>(1, b->max_cell));
+  if (size_t(n) > b->qw_pts) {
+    bbc_status e;
+    if ((e = ensure(b->qw_cell, n * 4, b)) || (e = ensure(b->qw_gamma, n * 4, b)) ||
+        (e = ensure(b->qw_cnt, n * 4, b)) || (e = ensure(b->qw_off, (n + 1) * 4 + 8, b)) ||
+        (e = ensure(b->qw_stats, scan_tmp_bytes(n) + 64, b)))
+      return e;
+    b->qw_pts = size_t(n);
+  }
+  if (pairs > b->qw_pairs) {
+    bbc_status e;
+    if ((e = ensure(b->qw_pair_pt, pairs * 4, b)) || (e = ensure(b->qw_pair_t, pairs * 4, b)) ||
+        (e = ensure(b->qw_pair_p, pairs * 4, b)) || (e = ensure(b->qw_pair_c, pairs * 8, b)))
+      return e;
+    b->qw_pairs = pairs;
+  }
+  StagedArgs s{};
+  s.q = make_args(b, pts, n, spp, seed, base, mode, out, stats, counters);
+  s.cell_b = static_cast<uint32_t*>(b->qw_cell.p);
+  s.gamma = static_cast<float*>(b->qw_gamma.p);
+  s.cnt = static_cast<uint32_t*>(b->qw_cnt.p);
+  s.off = static_cast<uint32_t*>(b->qw_off.p);
+  s.pair_pt = static_cast<uint32_t*>(b->qw_pair_pt.p);
+  s.pair_t = static_cast<uint32_t*>(b->qw_pair_t.p);
+  s.pair_p = static_cast<float*>(b->qw_pair_p.p);
+  s.pair_c = static_cast<double*>(b->qw_pair_c.p);
+  s.pair_cap = uint32_t(std::min<size_t>(pairs, 0xffffffffu));
+  const unsigned grid = unsigned(std::min<int64_t>(n, 256 * 64));
+  hipLaunchKernelGGL(k_stage_gamma, dim3(unsigned(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, st, s);
+  // the selection counts overwrite cnt after it has been read by k_stage_count:
+  // count into the pair_t buffer's head first, then scan into off
+  uint32_t* sel = static_cast<uint32_t*>(b->qw_pair_pt.p);
+  hipLaunchKernelGGL(k_stage_count, dim3(grid), dim3(64), 0, st, s, sel);
+  bbc_status e = launch_scan_u32(sel, s.off, n, b->qw_stats.p, st);
+  if (e) return e;
+  hipLaunchKernelGGL(k_stage_fill, dim3(grid), dim3(64), 0, st, s);
+  const unsigned gp = unsigned(std::min<size_t>((pairs + 255) / 256, 8192));
+  if (b->tune.timing) BBC_HIP(hipEventRecord(b->ev[0], st));
+  hipLaunchKernelGGL(k_stage_newton, dim3(gp), dim3(256), 0, st, s, s.off + n);
+  if (b->tune.timing) {
+    BBC_HIP(hipEventRecord(b->ev[1], st));
+    b->ev_recorded = true;
+  }
+  hipLaunchKernelGGL(k_stage_accum, dim3(unsigned(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, st, s);
+  BBC_HIP(hipGetLastError());
+  return BBC_OK;
+}
+
+}  // namespace bbc
