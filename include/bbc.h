@@ -20,10 +20,13 @@
  *      the triangle domain (Sec. 6.1), and Alg. 1 returns the unbiased
  *      estimate sum_{T in S} E(T) / P_T.
  *
- * Arithmetic: FP32 with running error bounds so every bound is rounded
- * outward; denominators whose Bernstein coefficients cannot be given a sign
- * in FP32 are re-evaluated in FP64, and every accepted root is polished in
- * FP64.
+ * Arithmetic: every bound carries running error bounds and is rounded
+ * outward.  Position-only bounds (tuple classification, domain
+ * initialisation) run in FP32 and re-evaluate a box in FP64 when a
+ * denominator coefficient cannot be given a sign; subdivision boxes, whose
+ * irradiance denominator cancels by orders of magnitude, run in FP64 (the
+ * same issue rate as unpacked FP32 on this GPU).  Newton iterates in FP32 and
+ * every accepted root is polished and weighted in FP64.
  *
  * Conventions
  *  - Every entry point returns a bbc_status; 0 is success.  On failure
