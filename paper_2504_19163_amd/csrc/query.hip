@@ -166,35 +166,45 @@ __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target&
     float u = u0 + 0.5f * fu, v = v0 + 0.5f * fv;
     const float lu0 = u0 - fu, lu1 = u0 + 2.f * fu, lv0 = v0 - fv, lv1 = v0 + 2.f * fv;
     ++wc.starts;
+    // FP32 Newton until the step falls below 1e-5 or stagnates at FP32 noise
+    // level (below 1e-3 and no longer halving): for small triangles the FP32
+    // residual cannot resolve the root further, and the FP64 polish that
+    // follows runs to a receiver residual below 1e-9 (up to ten steps next to a
+    // fold, where convergence is only linear)
     bool ok = true;
+    float t_last = -1.f, prev = INFINITY;
     for (int it = 0; it < 20; ++it) {
       ++wc.it32;  // FP32 path evaluations
       const PathT<float> p = eval_path<float>(Gf, chain, u, v);
       const float ru_ = p.uk - tg.u, rv_ = p.vk - tg.v;
-      if (!(isfinite(p.det)) || p.det == 0.f) { ok = false; break; }
+      if (!(isfinite(p.det)) || p.det == 0.f) {
+        ok = false;
+        break;
+      }
       const float du = (p.J11 * ru_ - p.J01 * rv_) / p.det;
       const float dv = (-p.J10 * ru_ + p.J00 * rv_) / p.det;
       u -= du;
       v -= dv;
-      if (!(u >= lu0 && u <= lu1 && v >= lv0 && v <= lv1)) { ok = false; break; }
-      if (fabsf(du) + fabsf(dv) < 2e-7f) break;
+      t_last = p.t;
+      if (!(u >= lu0 && u <= lu1 && v >= lv0 && v <= lv1)) {
+        ok = false;
+        break;
+      }
+      const float step = fabsf(du) + fabsf(dv);
+      if (step < 1e-5f || (step < 1e-3f && step > 0.5f * prev)) break;
+      prev = step;
     }
     if (!ok) continue;
-    {
-      // a start whose FP32 root lies clearly outside the triangle or behind the
-      // receiver cannot become admissible in the polish (margin 1e-3 >> FP32 error)
-      ++wc.it32;
-      const PathT<float> p = eval_path<float>(Gf, chain, u, v);
-      if (!(u >= -1e-3f && v >= -1e-3f && u + v <= 1.f + 1e-3f) || !(p.t > 0.f)) continue;
-    }
-    // FP64 polish: one Newton step from the FP32 root, a second only when the
-    // receiver residual still exceeds 1e-9 scene units
+    // a start whose FP32 root lies clearly outside the triangle or behind the
+    // receiver cannot become admissible in the polish (margin 1e-3 >> FP32 error)
+    if (!(u >= -1e-3f && v >= -1e-3f && u + v <= 1.f + 1e-3f) || !(t_last > 0.f)) continue;
+    // FP64 polish
     const TupleGeom<double> Gd = tuple_geom_rec<double>(rec, a.sc);
     double ud = u, vd = v;
     ++wc.it64;  // FP64 path evaluations
     PathT<double> p = eval_path<double>(Gd, chain, ud, vd);
     double res = 0.0;
-    for (int it = 0; it < 3; ++it) {
+    for (int it = 0; it < 10; ++it) {
       ++wc.it64;
       const double ru_ = p.uk - tg.ud, rv_ = p.vk - tg.vd;
       if (!(p.det != 0.0) || !isfinite(p.det)) break;
@@ -465,7 +475,7 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
   }
 }
 
-__global__ void k_stage_newton(StagedArgs s, const uint32_t* total) {
+__global__ void __launch_bounds__(64) k_stage_newton(StagedArgs s, const uint32_t* total) {
   const QueryArgs& a = s.q;
   const uint32_t np = min(*total, s.pair_cap);
   WorkCount wc;
@@ -527,9 +537,9 @@ bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t s
   bbc_status e = launch_scan_u32(sel, s.off, n, b->qw_stats.p, st);
   if (e) return e;
   hipLaunchKernelGGL(k_stage_fill, dim3(grid), dim3(64), 0, st, s);
-  const unsigned gp = unsigned(std::min<size_t>((pairs + 255) / 256, 8192));
+  const unsigned gp = unsigned(std::min<size_t>((pairs + 63) / 64, 32768));
   if (b->tune.timing) BBC_HIP(hipEventRecord(b->ev[0], st));
-  hipLaunchKernelGGL(k_stage_newton, dim3(gp), dim3(256), 0, st, s, s.off + n);
+  hipLaunchKernelGGL(k_stage_newton, dim3(gp), dim3(64), 0, st, s, s.off + n);
   if (b->tune.timing) {
     BBC_HIP(hipEventRecord(b->ev[1], st));
     b->ev_recorded = true;
