@@ -151,8 +151,7 @@ bbc_status bbc_export_leaves(const bbc_bounds* b, uint32_t* tuple, uint32_t* cod
  * n_grid_entries entries of (tuple, E~) sorted by tuple within each cell. */
 bbc_status bbc_export_grid(const bbc_bounds* b, uint32_t* offsets, uint32_t* tuple, float* Et);
 
-/* Per-query statistics (host struct, summed over the points of a call).
- * sum_U, sum_S and sum_varbound are filled by the fused form only. */
+/* Per-query statistics (host struct, summed over the points of a call). */
 typedef struct {
   int64_t n_points;
   int64_t sum_U;       /* sum of |U| (candidate tuples) */
@@ -210,6 +209,96 @@ bbc_status bbc_get_tuning(const bbc_bounds* b, int32_t knob, int64_t* value);
  * HIP events on the query's stream; waits for that event.  EINVAL unless
  * BBC_TUNE_TIMING is on and a query ran since. */
 bbc_status bbc_query_kernel_ms(const bbc_bounds* b, float* ms);
+
+/* ------------------------------------------------------------------ serving
+ * A continuous-batching server over resident bound hierarchies (one per
+ * scene).  Requests of shading points are queued by bbc_server_submit; a
+ * scheduler thread inside the library admits the oldest waiting requests as
+ * soon as one of max_inflight batch slots is free and their device work space
+ * fits the memory budget, gathers every waiting request of the same scene
+ * (in arrival order, up to max_batch_points points and max_batch_requests
+ * requests) into one batch, and runs the staged query pipeline for the batch
+ * on the slot's own stream, so batches of different slots overlap on the
+ * device.  A batch's work space (points, results, per-point request index,
+ * and the staged pipeline's buffers sized for the worst case of every
+ * candidate tuple being selected) is carved from one device arena of
+ * hbm_budget_bytes allocated at creation.
+ *
+ * Each point keeps the random stream of its own request: the draw for tuple T
+ * at point i of a request is keyed by (request seed, point_index_base + i, T)
+ * exactly as in bbc_query_irradiance_ex, and each point's estimate is summed
+ * in the same order, so a request's result is bit-identical whether it runs
+ * alone, through bbc_query_irradiance_ex, or inside any mix of requests.
+ *
+ * The bounds handles are borrowed: keep them alive, and do not rebuild them,
+ * until bbc_server_destroy has returned.  All handles must live on the same
+ * device.  Calls on one server may come from several host threads. */
+typedef struct bbc_server bbc_server;
+
+#define BBC_SERVER_PAUSED 1 /* create paused: admit nothing until bbc_server_resume */
+
+typedef struct {
+  int64_t hbm_budget_bytes;   /* device arena for batch work space, >= 1 MiB */
+  int32_t max_inflight;       /* batch slots (one stream each), 1..16 */
+  int32_t max_batch_points;   /* points in one batch, 1..2^24; a request must fit one batch */
+  int32_t max_batch_requests; /* requests in one batch, 1..65535 */
+  int32_t queue_capacity;     /* waiting requests before submit returns BBC_EQUEUE, >= 1 */
+  int32_t mode;               /* 0 (sampled, Alg. 1) or BBC_QUERY_EXHAUSTIVE */
+  int32_t flags;              /* BBC_SERVER_PAUSED */
+} bbc_server_config;
+
+/* One request: n shading points [3][n] and n results, both host or both
+ * device memory (`memory`).  The arrays are borrowed until the request is
+ * complete; results are valid after bbc_server_wait or a poll that reports
+ * completion. */
+typedef struct {
+  int32_t memory;           /* BBC_MEM_HOST or BBC_MEM_DEVICE */
+  int32_t scene;            /* index into the bounds array given at creation */
+  int64_t n;                /* points, 0..max_batch_points */
+  const float* points;      /* [3][n] receiver-plane positions */
+  float* out;               /* [n] irradiance estimates */
+  int32_t spp;              /* W >= 1, the expected sample count per point */
+  uint64_t seed;
+  int64_t point_index_base; /* index of the first point in the random stream, >= 0 */
+} bbc_request;
+
+typedef struct {
+  int64_t submitted, completed, rejected; /* rejected: EBUDGET / EQUEUE / EINVAL at submit */
+  int64_t batches, points;                /* batches launched and points in them */
+  double mean_batch_points, mean_batch_requests;
+  double latency_p50_ms, latency_p99_ms, latency_max_ms; /* submit -> result ready, host monotonic clock */
+  double batch_gpu_ms;                    /* summed device time of the batches (copies included) */
+  int64_t arena_bytes, arena_peak_bytes;  /* budget and the largest part of it in use at once */
+  int32_t inflight_peak;                  /* largest number of batches in flight at once */
+  int32_t queue_peak;                     /* largest number of waiting requests */
+} bbc_server_counters;
+
+/* Create a server over n_bounds resident hierarchies (scene i = bounds[i]).
+ * EINVAL for a bad configuration, ENOMEM if the arena or the pinned staging
+ * buffers cannot be allocated.  *out is owned by the caller until
+ * bbc_server_destroy. */
+bbc_status bbc_server_create(bbc_bounds* const* bounds, int32_t n_bounds, const bbc_server_config* cfg,
+                             bbc_server** out);
+/* Queue one request; *ticket identifies it.  EBUDGET if it can never be
+ * admitted (more points than max_batch_points, or more work space than the
+ * whole arena); EQUEUE if queue_capacity requests are already waiting (nothing
+ * is queued, the caller may retry later); EINVAL for bad arguments. */
+bbc_status bbc_server_submit(bbc_server* s, const bbc_request* r, uint64_t* ticket);
+/* *done = 1 if the request is complete (then the ticket is retired and the
+ * return value is the request's own status), else 0 and BBC_OK.  EINVAL for
+ * an unknown or retired ticket. */
+bbc_status bbc_server_poll(bbc_server* s, uint64_t ticket, int32_t* done);
+/* Block until the request is complete; retires the ticket and returns its
+ * status.  latency_ms (nullable) receives submit-to-ready time. */
+bbc_status bbc_server_wait(bbc_server* s, uint64_t ticket, double* latency_ms);
+/* Start admitting requests (a server created with BBC_SERVER_PAUSED). */
+bbc_status bbc_server_resume(bbc_server* s);
+/* Counters and latency percentiles since creation or the last reset
+ * (reset != 0 clears them after reading). */
+bbc_status bbc_server_stats(bbc_server* s, bbc_server_counters* out, int32_t reset);
+/* Complete every queued request, stop the scheduler and free the server.
+ * NULL is a no-op. */
+bbc_status bbc_server_destroy(bbc_server* s);
 
 /* Thread-local text of the last error. */
 const char* bbc_last_error(void);

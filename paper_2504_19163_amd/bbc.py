@@ -23,8 +23,10 @@ QUERY_FUSED, QUERY_STAGED, QUERY_EXHAUSTIVE = 0, 1, 16
 EXPORTS = [
     "bbc_build_bounds", "bbc_rebuild_bounds", "bbc_free_bounds", "bbc_bounds_info", "bbc_export_leaves",
     "bbc_export_grid", "bbc_query_irradiance", "bbc_query_irradiance_ex", "bbc_set_tuning", "bbc_get_tuning",
-    "bbc_query_kernel_ms", "bbc_last_error",
+    "bbc_query_kernel_ms", "bbc_last_error", "bbc_server_create", "bbc_server_submit", "bbc_server_poll",
+    "bbc_server_wait", "bbc_server_resume", "bbc_server_stats", "bbc_server_destroy",
 ]
+SERVER_PAUSED = 1
 TUNE_QUERY_WAVES, TUNE_QUERY_GRID, TUNE_BUILD_GRID_PER_CU, TUNE_QUERY_TILE, TUNE_TIMING = 1, 2, 3, 4, 5
 
 
@@ -69,6 +71,30 @@ class QueryStats(C.Structure):
     ]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32), ("max_batch_points", C.c_int32),
+        ("max_batch_requests", C.c_int32), ("queue_capacity", C.c_int32), ("mode", C.c_int32), ("flags", C.c_int32),
+    ]
+
+
+class Request(C.Structure):
+    _fields_ = [
+        ("memory", C.c_int32), ("scene", C.c_int32), ("n", C.c_int64), ("points", C.c_void_p), ("out", C.c_void_p),
+        ("spp", C.c_int32), ("seed", C.c_uint64), ("point_index_base", C.c_int64),
+    ]
+
+
+class ServerCounters(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64), ("batches", C.c_int64),
+        ("points", C.c_int64), ("mean_batch_points", C.c_double), ("mean_batch_requests", C.c_double),
+        ("latency_p50_ms", C.c_double), ("latency_p99_ms", C.c_double), ("latency_max_ms", C.c_double),
+        ("batch_gpu_ms", C.c_double), ("arena_bytes", C.c_int64), ("arena_peak_bytes", C.c_int64),
+        ("inflight_peak", C.c_int32), ("queue_peak", C.c_int32),
+    ]
+
+
 _lib = None
 
 
@@ -92,6 +118,13 @@ def lib():
             "bbc_set_tuning": [vp, i32, i64],
             "bbc_get_tuning": [vp, i32, vp],
             "bbc_query_kernel_ms": [vp, vp],
+            "bbc_server_create": [vp, i32, vp, vp],
+            "bbc_server_submit": [vp, vp, vp],
+            "bbc_server_poll": [vp, u64, vp],
+            "bbc_server_wait": [vp, u64, vp],
+            "bbc_server_resume": [vp],
+            "bbc_server_stats": [vp, vp, i32],
+            "bbc_server_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -245,6 +278,94 @@ class Bounds:
         if host_stats:
             return out, st, {k: getattr(hs, k) for k, _ in QueryStats._fields_}
         return out, st
+
+
+class Server:
+    """Continuous-batching server over resident bounds (bbc_server_*).
+
+    submit() takes points as a numpy [3, n] float32 array (host request) or a
+    torch CUDA tensor (device request) and returns a ticket; the output array
+    is allocated here and kept alive until wait() returns it."""
+
+    def __init__(self, bounds, hbm_budget_bytes=8 << 30, max_inflight=4, max_batch_points=262144,
+                 max_batch_requests=4096, queue_capacity=4096, mode=0, paused=False):
+        self.bounds = list(bounds)  # keeps the handles alive
+        arr = (C.c_void_p * len(self.bounds))(*[b.h.value for b in self.bounds])
+        cfg = ServerConfig(int(hbm_budget_bytes), int(max_inflight), int(max_batch_points), int(max_batch_requests),
+                           int(queue_capacity), int(mode), SERVER_PAUSED if paused else 0)
+        h = C.c_void_p()
+        _check(lib().bbc_server_create(arr, len(self.bounds), C.byref(cfg), C.byref(h)), "bbc_server_create")
+        self.h = h
+        self._live = {}
+
+    def submit(self, scene, points, spp, seed, point_index_base=0):
+        """Queue a request; returns its ticket.  Raises BBCError (status
+        EBUDGET / EQUEUE / EINVAL) when it is not accepted."""
+        r = Request()
+        r.scene = int(scene)
+        r.spp = int(spp)
+        r.seed = int(seed)
+        r.point_index_base = int(point_index_base)
+        if isinstance(points, np.ndarray):
+            pts = np.ascontiguousarray(points, dtype=np.float32)
+            assert pts.ndim == 2 and pts.shape[0] == 3
+            out = np.zeros(pts.shape[1], np.float32)
+            r.memory = MEM_HOST
+            r.points = pts.ctypes.data
+            r.out = out.ctypes.data
+        else:
+            import torch
+            pts = points.contiguous()
+            assert pts.is_cuda and pts.dtype == torch.float32 and pts.dim() == 2 and pts.shape[0] == 3
+            out = torch.zeros(pts.shape[1], dtype=torch.float32, device=pts.device)
+            torch.cuda.current_stream().synchronize()  # inputs ready before the server's streams read them
+            r.memory = MEM_DEVICE
+            r.points = pts.data_ptr()
+            r.out = out.data_ptr()
+        r.n = pts.shape[1]
+        t = C.c_uint64()
+        _check(lib().bbc_server_submit(self.h, C.byref(r), C.byref(t)), "bbc_server_submit")
+        self._live[t.value] = (pts, out)
+        return t.value
+
+    def poll(self, ticket):
+        """(done, out or None)."""
+        d = C.c_int32()
+        st = lib().bbc_server_poll(self.h, C.c_uint64(ticket), C.byref(d))
+        if d.value:
+            pts, out = self._live.pop(ticket)
+            _check(st, "bbc_server_poll")
+            return True, out
+        _check(st, "bbc_server_poll")
+        return False, None
+
+    def wait(self, ticket):
+        """Block until the request is complete; returns (out, latency_ms)."""
+        lat = C.c_double()
+        st = lib().bbc_server_wait(self.h, C.c_uint64(ticket), C.byref(lat))
+        pts, out = self._live.pop(ticket)
+        _check(st, "bbc_server_wait")
+        return out, lat.value
+
+    def resume(self):
+        _check(lib().bbc_server_resume(self.h), "bbc_server_resume")
+
+    def stats(self, reset=False):
+        c = ServerCounters()
+        _check(lib().bbc_server_stats(self.h, C.byref(c), 1 if reset else 0), "bbc_server_stats")
+        return {k: getattr(c, k) for k, _ in ServerCounters._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().bbc_server_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 TUNING_FILE = os.path.join(HERE, "tuning.json")

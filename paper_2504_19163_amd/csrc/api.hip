@@ -57,8 +57,7 @@ static void release_all(Bounds* b) {
                    &b->q[1], &b->fq, &b->lt, &b->lc, &b->lu, &b->le, &b->gl_t, &b->gl_c, &b->gl_u, &b->gl_e, &b->st, &b->sc, &b->su, &b->se, &b->tcount,
                    &b->toff, &b->tcur, &b->trip, &b->ccount, &b->coff, &b->ccur, &b->ut, &b->ue, &b->ucell, &b->gt, &b->ge,
                    &b->scan_tmp, &b->trec,
-                   &b->qw_cell, &b->qw_gamma, &b->qw_cnt, &b->qw_off, &b->qw_pair_pt, &b->qw_pair_t,
-                   &b->qw_pair_p, &b->qw_pair_c, &b->qw_stats, &b->max_cell_dev, &b->qcounters};
+                   &b->qw_buf, &b->max_cell_dev, &b->qcounters};
   for (DevBuf* d : all) release(*d);
   b->device_bytes = 0;
 }
@@ -329,7 +328,7 @@ bbc_status bbc_query_irradiance_ex(const bbc_bounds* h, const float* points_dev,
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(ctr), 0u, 16, s))) return e;
   }
   if (form == BBC_QUERY_STAGED)
-    e = launch_query_staged(b, points_dev, n, spp, seed, point_index_base, mode, out_E_dev, nullptr, ctr, s);
+    e = launch_query_staged(b, points_dev, n, spp, seed, point_index_base, mode, out_E_dev, st, ctr, s);
   else
     e = launch_query(b, points_dev, n, spp, seed, point_index_base, mode, out_E_dev, st, ctr, s);
   if (e) {
@@ -347,7 +346,7 @@ bbc_status bbc_query_irradiance_ex(const bbc_bounds* h, const float* points_dev,
     stats_host->n_iter_fp32 = int64_t(c[2]);
     stats_host->n_iter_fp64 = int64_t(c[3]);
     stats_host->n_roots = int64_t(c[4]);
-    if (form == BBC_QUERY_FUSED && n > 0) {
+    if (n > 0) {
       std::vector<float> hs(size_t(n) * 4);
       BBC_HIP(hipMemcpyAsync(hs.data(), st, hs.size() * 4, hipMemcpyDeviceToHost, s));
       BBC_HIP(hipStreamSynchronize(s));

@@ -21,6 +21,16 @@ struct QItem {
 constexpr int kCodeBits = 14;
 constexpr int kMaxDepth = 14;
 
+// One request of a batched query launch: sampling parameters and where its
+// points start inside the batch.
+struct ReqDesc {
+  float W;
+  uint32_t pad;
+  uint64_t seed;
+  int64_t base;   // point index of the request's first point (Philox counter)
+  int64_t start;  // offset of the request's first point inside the batch
+};
+
 // Device counters of one build (zeroed by a fill kernel at the start).
 struct BuildCounters {
   uint32_t n_init;                 // unsettled tuples queued for domain initialisation
@@ -40,6 +50,22 @@ struct BuildCounters {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+};
+
+// Work space of one staged query launch, carved from one allocation (a
+// handle's own buffer or a serving batch's region of the arena).
+struct StagedWork {
+  uint32_t* cell = nullptr;
+  float* gamma = nullptr;
+  uint32_t* cnt = nullptr;
+  uint32_t* off = nullptr;
+  void* scan = nullptr;
+  uint32_t* pair_pt = nullptr;
+  uint32_t* pair_t = nullptr;
+  float* pair_p = nullptr;
+  double* pair_c = nullptr;
+  uint8_t* pair_nr = nullptr;
+  size_t pts = 0, pairs = 0;  // capacities
 };
 
 // Launch-shape knobs chosen by the autotuner (bbc_set_tuning).
@@ -85,9 +111,9 @@ struct Bounds {
   BuildCounters host{};
   int64_t n_leaves = 0, n_entries = 0, max_cell = 0;
   int64_t device_bytes = 0;
-  // query work space (staged form), grown on demand
-  DevBuf qw_cell, qw_gamma, qw_cnt, qw_off, qw_pair_pt, qw_pair_t, qw_pair_p, qw_pair_c, qw_stats;
-  size_t qw_pts = 0, qw_pairs = 0;
+  // query work space (staged form), one allocation grown on demand
+  DevBuf qw_buf;
+  StagedWork qw;
   DevBuf max_cell_dev;
   DevBuf qcounters;           // 8 x u64 query work counters (filled when host stats are requested)
   hipEvent_t ev[2] = {nullptr, nullptr};  // around the last query's dominant kernel
@@ -116,5 +142,17 @@ bbc_status launch_query(const Bounds* b, const float* pts, int64_t n, int32_t sp
                         int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t s);
 bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
                                int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t s);
+
+// Staged work space: worst-case pair count of n points (every entry of the
+// fullest cell selected), bytes for n points and that many pairs, and the
+// carving of one allocation of that size.
+size_t staged_pairs(const Bounds* b, int64_t n);
+size_t staged_bytes(int64_t n, size_t pairs);
+void staged_carve(void* base, int64_t n, size_t pairs, StagedWork& w);
+// Staged launch over a batch of requests: point i belongs to reqs[preq[i]].
+// Events (nullable) bracket the Newton kernel.
+bbc_status launch_query_batch(const Bounds* b, const float* pts, int64_t n, const uint16_t* preq,
+                              const ReqDesc* reqs, int32_t mode, float* out, const StagedWork& w, hipEvent_t ev0,
+                              hipEvent_t ev1, hipStream_t s);
 
 }  // namespace bbc

@@ -37,7 +37,25 @@ struct QueryArgs {
   float* out;
   float* stats;
   unsigned long long* counters;  // nullable: pairs, starts, FP32 iterations, FP64 steps, roots
+  // several requests in one launch (serving): point i belongs to request
+  // preq[i]; nullable, then every point uses W, seed and base above
+  const uint16_t* preq;
+  const ReqDesc* reqs;
 };
+
+struct PointReq {
+  float W;
+  uint64_t seed, key;
+};
+
+// Sampling parameters of point i: expected sample count, seed, and the point's
+// index inside its own request (the Philox counter), so a point draws the same
+// numbers whether its request runs alone or batched with others.
+__device__ __forceinline__ PointReq point_req(const QueryArgs& a, int64_t i) {
+  if (!a.preq) return PointReq{a.W, a.seed, uint64_t(a.base + i)};
+  const ReqDesc& r = a.reqs[a.preq[i]];
+  return PointReq{r.W, r.seed, uint64_t(r.base + (i - r.start))};
+}
 
 // Per-lane work counters, summed per wave into the optional device counters.
 struct WorkCount {
@@ -278,15 +296,16 @@ __global__ void __launch_bounds__(64, kWaves) k_query_fused(QueryArgs a) {
     }
     const float* Et = a.ge + b;
     const uint32_t* Tt = a.gt + b;
-    const float gamma = (exhaustive || nU == 0) ? INFINITY : solve_gamma(Et, nU, a.W);
-    const uint64_t key = uint64_t(a.base + i);
+    const PointReq pr = valid ? point_req(a, i) : PointReq{1.f, 0, 0};
+    const float gamma = (exhaustive || nU == 0) ? INFINITY : solve_gamma(Et, nU, pr.W);
+    const uint64_t key = pr.key;
     uint32_t cnt = 0;
     double mu2 = 0.0;
     for (uint32_t j = 0; j < nU; ++j) {
       const float e = Et[j];
       const float P = select_prob(e, gamma, exhaustive);
       if (P > 0.f && isfinite(e)) mu2 += double(e) * double(e) / double(P);
-      cnt += selection_uniform(a.seed, key, Tt[j]) < P ? 1u : 0u;
+      cnt += selection_uniform(pr.seed, key, Tt[j]) < P ? 1u : 0u;
     }
     const uint32_t off = wave_excl_scan(cnt, lane);
     const uint32_t total = __shfl(off + cnt, BBC_WAVE - 1, BBC_WAVE);
@@ -299,7 +318,7 @@ __global__ void __launch_bounds__(64, kWaves) k_query_fused(QueryArgs a) {
         const float e = Et[cur];
         const uint32_t T = Tt[cur];
         const float P = select_prob(e, gamma, exhaustive);
-        if (selection_uniform(a.seed, key, T) < P) {
+        if (selection_uniform(pr.seed, key, T) < P) {
           const uint32_t slot = off + emitted - w0;
           s_t[slot] = T;
           s_p[slot] = P;
@@ -400,13 +419,14 @@ bbc_status launch_query(const Bounds* b, const float* pts, int64_t n, int32_t sp
 struct StagedArgs {
   QueryArgs q;
   uint32_t* cell_b;   // [n] first entry of the point's cell (or 0)
-  uint32_t* cnt;      // [n] |U| then selection counts
+  uint32_t* cnt;      // [n] |U|
   float* gamma;       // [n]
-  uint32_t* off;      // [n + 1]
+  uint32_t* off;      // [n + 1] exclusive scan of the selection counts
   uint32_t* pair_pt;  // [pairs]
   uint32_t* pair_t;
   float* pair_p;
   double* pair_c;
+  uint8_t* pair_nr;   // [pairs] roots found per pair (written when stats are requested)
   uint32_t pair_cap;
 };
 
@@ -420,7 +440,7 @@ __global__ void k_stage_gamma(StagedArgs s) {
     if (tg.on) {
       b = a.coff[tg.cell];
       nU = a.coff[tg.cell + 1] - b;
-      if (!exhaustive && nU > 0) gamma = solve_gamma(a.ge + b, nU, a.W);
+      if (!exhaustive && nU > 0) gamma = solve_gamma(a.ge + b, nU, point_req(a, i).W);
     }
     s.cell_b[i] = b;
     s.gamma[i] = gamma;
@@ -436,9 +456,10 @@ __global__ void __launch_bounds__(64) k_stage_count(StagedArgs s, uint32_t* sel)
     const uint32_t b = s.cell_b[i], nU = s.cnt[i];
     const float gamma = s.gamma[i];
     uint32_t c = 0;
+    const PointReq pr = point_req(a, i);
     for (uint32_t j = lane; j < nU; j += BBC_WAVE) {
       const float P = select_prob(a.ge[b + j], gamma, exhaustive);
-      c += selection_uniform(a.seed, uint64_t(a.base + i), a.gt[b + j]) < P ? 1u : 0u;
+      c += selection_uniform(pr.seed, pr.key, a.gt[b + j]) < P ? 1u : 0u;
     }
     c = wave_sum(c);
     if (lane == 0) sel[i] = c;
@@ -452,6 +473,7 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
   for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
     const uint32_t b = s.cell_b[i], nU = s.cnt[i];
     const float gamma = s.gamma[i];
+    const PointReq pr = point_req(a, i);
     uint32_t o = s.off[i];
     for (uint32_t j0 = 0; j0 < nU; j0 += BBC_WAVE) {
       const uint32_t j = j0 + lane;
@@ -461,7 +483,7 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
       if (j < nU) {
         T = a.gt[b + j];
         P = select_prob(a.ge[b + j], gamma, exhaustive);
-        take = selection_uniform(a.seed, uint64_t(a.base + i), T) < P;
+        take = selection_uniform(pr.seed, pr.key, T) < P;
       }
       const uint64_t m = __ballot(take);
       const uint32_t rank = __popcll(m & ((1ull << lane) - 1ull));
@@ -483,70 +505,141 @@ __global__ void __launch_bounds__(64) k_stage_newton(StagedArgs s, const uint32_
     const int64_t i = s.pair_pt[k];
     const Target tg = receiver_target(a, i);
     ++wc.pairs;
+    const uint32_t r0 = wc.roots;
     s.pair_c[k] = tuple_irradiance(a, s.pair_t[k], tg, wc) / double(s.pair_p[k]);
+    if (a.stats) s.pair_nr[k] = uint8_t(min(wc.roots - r0, 255u));
   }
   flush_counts(a, wc);
 }
 
+// Sum of each point's contributions in pair order (entry order of its cell),
+// and the optional per-point statistics: |U|, |S|, roots, sum of E~^2 / P.
 __global__ void k_stage_accum(StagedArgs s) {
   const QueryArgs& a = s.q;
+  const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x) {
     double E = 0.0;
-    const uint32_t e = min(s.off[i + 1], s.pair_cap);
-    for (uint32_t k = s.off[i]; k < e; ++k) E += s.pair_c[k];
+    const uint32_t o0 = min(s.off[i], s.pair_cap), o1 = min(s.off[i + 1], s.pair_cap);
+    for (uint32_t k = o0; k < o1; ++k) E += s.pair_c[k];
     a.out[i] = float(E);
+    if (a.stats) {
+      uint32_t roots = 0;
+      for (uint32_t k = o0; k < o1; ++k) roots += s.pair_nr[k];
+      const uint32_t b = s.cell_b[i], nU = s.cnt[i];
+      const float gamma = s.gamma[i];
+      double mu2 = 0.0;
+      for (uint32_t j = 0; j < nU; ++j) {
+        const float e = a.ge[b + j];
+        const float P = select_prob(e, gamma, exhaustive);
+        if (P > 0.f && isfinite(e)) mu2 += double(e) * double(e) / double(P);
+      }
+      a.stats[4 * i + 0] = float(nU);
+      a.stats[4 * i + 1] = float(s.off[i + 1] - s.off[i]);
+      a.stats[4 * i + 2] = float(roots);
+      a.stats[4 * i + 3] = float(mu2);
+    }
   }
+}
+
+static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t staged_pairs(const Bounds* b, int64_t n) { return size_t(n) * size_t(std::max<int64_t>(1, b->max_cell)); }
+
+size_t staged_bytes(int64_t n, size_t pairs) {
+  const size_t un = size_t(std::max<int64_t>(n, 1)), up = std::max<size_t>(pairs, 1);
+  return 3 * align256(un * 4) + align256((un + 1) * 4 + 8) + align256(scan_tmp_bytes(int64_t(un)) + 64) +
+         3 * align256(up * 4) + align256(up * 8) + align256(up);
+}
+
+void staged_carve(void* base, int64_t n, size_t pairs, StagedWork& w) {
+  const size_t un = size_t(std::max<int64_t>(n, 1)), up = std::max<size_t>(pairs, 1);
+  char* p = static_cast<char*>(base);
+  auto take = [&](size_t bytes) {
+    void* r = p;
+    p += align256(bytes);
+    return r;
+  };
+  w.cell = static_cast<uint32_t*>(take(un * 4));
+  w.gamma = static_cast<float*>(take(un * 4));
+  w.cnt = static_cast<uint32_t*>(take(un * 4));
+  w.off = static_cast<uint32_t*>(take((un + 1) * 4 + 8));
+  w.scan = take(scan_tmp_bytes(int64_t(un)) + 64);
+  w.pair_pt = static_cast<uint32_t*>(take(up * 4));
+  w.pair_t = static_cast<uint32_t*>(take(up * 4));
+  w.pair_p = static_cast<float*>(take(up * 4));
+  w.pair_c = static_cast<double*>(take(up * 8));
+  w.pair_nr = static_cast<uint8_t*>(take(up));
+  w.pts = un;
+  w.pairs = up;
+}
+
+// The five stage launches of one staged query; events (nullable) bracket the
+// Newton kernel.
+static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pairs, hipEvent_t ev0, hipEvent_t ev1,
+                             hipStream_t st) {
+  const int64_t n = q.n;
+  StagedArgs s{};
+  s.q = q;
+  s.cell_b = w.cell;
+  s.gamma = w.gamma;
+  s.cnt = w.cnt;
+  s.off = w.off;
+  s.pair_pt = w.pair_pt;
+  s.pair_t = w.pair_t;
+  s.pair_p = w.pair_p;
+  s.pair_c = w.pair_c;
+  s.pair_nr = w.pair_nr;
+  s.pair_cap = uint32_t(std::min<size_t>(pairs, 0xffffffffu));
+  const unsigned grid = unsigned(std::min<int64_t>(n, 256 * 64));
+  const unsigned gpt = unsigned(std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_stage_gamma, dim3(gpt), dim3(256), 0, st, s);
+  // selection counts go to the head of the pair_pt buffer, are scanned into
+  // off, and are overwritten by the fill kernel afterwards
+  uint32_t* sel = w.pair_pt;
+  hipLaunchKernelGGL(k_stage_count, dim3(grid), dim3(64), 0, st, s, sel);
+  bbc_status e = launch_scan_u32(sel, s.off, n, w.scan, st);
+  if (e) return e;
+  hipLaunchKernelGGL(k_stage_fill, dim3(grid), dim3(64), 0, st, s);
+  const unsigned gp = unsigned(std::min<size_t>((pairs + 63) / 64, 32768));
+  if (ev0) BBC_HIP(hipEventRecord(ev0, st));
+  hipLaunchKernelGGL(k_stage_newton, dim3(gp), dim3(64), 0, st, s, s.off + n);
+  if (ev1) BBC_HIP(hipEventRecord(ev1, st));
+  hipLaunchKernelGGL(k_stage_accum, dim3(gpt), dim3(256), 0, st, s);
+  BBC_HIP(hipGetLastError());
+  return BBC_OK;
 }
 
 bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
                                int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t st) {
   if (n == 0) return BBC_OK;
-  const size_t pairs = size_t(n) * size_t(std::max<int64_t>(1, b->max_cell));
-  if (size_t(n) > b->qw_pts) {
-    bbc_status e;
-    if ((e = ensure(b->qw_cell, n * 4, b)) || (e = ensure(b->qw_gamma, n * 4, b)) ||
-        (e = ensure(b->qw_cnt, n * 4, b)) || (e = ensure(b->qw_off, (n + 1) * 4 + 8, b)) ||
-        (e = ensure(b->qw_stats, scan_tmp_bytes(n) + 64, b)))
-      return e;
-    b->qw_pts = size_t(n);
+  const size_t pairs = staged_pairs(b, n);
+  if (size_t(n) > b->qw.pts || pairs > b->qw.pairs) {
+    const int64_t np = std::max<int64_t>(n, int64_t(b->qw.pts));
+    const size_t pp = std::max(pairs, b->qw.pairs);
+    bbc_status e = ensure(b->qw_buf, staged_bytes(np, pp), b);
+    if (e) return e;
+    staged_carve(b->qw_buf.p, np, pp, b->qw);
   }
-  if (pairs > b->qw_pairs) {
-    bbc_status e;
-    if ((e = ensure(b->qw_pair_pt, pairs * 4, b)) || (e = ensure(b->qw_pair_t, pairs * 4, b)) ||
-        (e = ensure(b->qw_pair_p, pairs * 4, b)) || (e = ensure(b->qw_pair_c, pairs * 8, b)))
-      return e;
-    b->qw_pairs = pairs;
-  }
-  StagedArgs s{};
-  s.q = make_args(b, pts, n, spp, seed, base, mode, out, stats, counters);
-  s.cell_b = static_cast<uint32_t*>(b->qw_cell.p);
-  s.gamma = static_cast<float*>(b->qw_gamma.p);
-  s.cnt = static_cast<uint32_t*>(b->qw_cnt.p);
-  s.off = static_cast<uint32_t*>(b->qw_off.p);
-  s.pair_pt = static_cast<uint32_t*>(b->qw_pair_pt.p);
-  s.pair_t = static_cast<uint32_t*>(b->qw_pair_t.p);
-  s.pair_p = static_cast<float*>(b->qw_pair_p.p);
-  s.pair_c = static_cast<double*>(b->qw_pair_c.p);
-  s.pair_cap = uint32_t(std::min<size_t>(pairs, 0xffffffffu));
-  const unsigned grid = unsigned(std::min<int64_t>(n, 256 * 64));
-  hipLaunchKernelGGL(k_stage_gamma, dim3(unsigned(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, st, s);
-  // the selection counts overwrite cnt after it has been read by k_stage_count:
-  // count into the pair_t buffer's head first, then scan into off
-  uint32_t* sel = static_cast<uint32_t*>(b->qw_pair_pt.p);
-  hipLaunchKernelGGL(k_stage_count, dim3(grid), dim3(64), 0, st, s, sel);
-  bbc_status e = launch_scan_u32(sel, s.off, n, b->qw_stats.p, st);
+  const QueryArgs q = make_args(b, pts, n, spp, seed, base, mode, out, stats, counters);
+  const bool timed = b->tune.timing != 0;
+  bbc_status e = run_staged(q, b->qw, b->qw.pairs, timed ? b->ev[0] : nullptr, timed ? b->ev[1] : nullptr, st);
   if (e) return e;
-  hipLaunchKernelGGL(k_stage_fill, dim3(grid), dim3(64), 0, st, s);
-  const unsigned gp = unsigned(std::min<size_t>((pairs + 63) / 64, 32768));
-  if (b->tune.timing) BBC_HIP(hipEventRecord(b->ev[0], st));
-  hipLaunchKernelGGL(k_stage_newton, dim3(gp), dim3(64), 0, st, s, s.off + n);
-  if (b->tune.timing) {
-    BBC_HIP(hipEventRecord(b->ev[1], st));
-    b->ev_recorded = true;
-  }
-  hipLaunchKernelGGL(k_stage_accum, dim3(unsigned(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, st, s);
-  BBC_HIP(hipGetLastError());
+  if (timed) b->ev_recorded = true;
   return BBC_OK;
+}
+
+bbc_status launch_query_batch(const Bounds* b, const float* pts, int64_t n, const uint16_t* preq,
+                              const ReqDesc* reqs, int32_t mode, float* out, const StagedWork& w, hipEvent_t ev0,
+                              hipEvent_t ev1, hipStream_t st) {
+  if (n == 0) return BBC_OK;
+  if (size_t(n) > w.pts || staged_pairs(b, n) > w.pairs) {
+    set_error("batch work space smaller than the batch");
+    return BBC_EINVAL;
+  }
+  QueryArgs q = make_args(b, pts, n, 1, 0, 0, mode, out, nullptr, nullptr);
+  q.preq = preq;
+  q.reqs = reqs;
+  return run_staged(q, w, w.pairs, ev0, ev1, st);
 }
 
 }  // namespace bbc

@@ -102,11 +102,14 @@ def test_cfg1_grid_matches_oracle(bbc, orc, cfg1):
         assert np.all(e[fin] >= oe[fin] * (1 - 1e-12)) and np.all(e[fin] <= oe[fin] * (1 + BOUND_TOL))
 
 
+@pytest.mark.parametrize("form", ["fused", "staged"])
 @pytest.mark.parametrize("mode,omode,W", [("exhaustive", 1, 16), ("sample", 0, 16), ("sample", 0, 4), ("sample", 0, 1)])
-def test_cfg1_query_matches_oracle(bbc, orc, cfg1, mode, omode, W):
+def test_cfg1_query_matches_oracle(bbc, orc, cfg1, mode, omode, W, form):
     sc, osc, ds, B, Ob = cfg1
     pts = S.receiver_points(sc, 64)
-    m = bbc.QUERY_EXHAUSTIVE if mode == "exhaustive" else bbc.QUERY_FUSED
+    m = bbc.QUERY_FUSED if form == "fused" else bbc.QUERY_STAGED
+    if mode == "exhaustive":
+        m |= bbc.QUERY_EXHAUSTIVE
     E, st = B.query(torch.as_tensor(pts, device="cuda"), W, 7, mode=m, stats=True)
     E = E.cpu().numpy().astype(np.float64)
     st = st.cpu().numpy()
@@ -115,6 +118,8 @@ def test_cfg1_query_matches_oracle(bbc, orc, cfg1, mode, omode, W):
     assert np.array_equal(st[:, 1], ost[:, 1])  # |S|: identical Bernoulli decisions
     assert np.array_equal(st[:, 2], ost[:, 2])  # roots
     np.testing.assert_allclose(E, OE, rtol=EST_TOL, atol=1e-12)
+    fin = np.isfinite(ost[:, 3])  # the GPU statistic sums the finite terms only
+    np.testing.assert_allclose(st[fin, 3], ost[fin, 3], rtol=1e-5)  # sum over U of E~^2 / P
 
 
 def test_fused_equals_staged_and_tuning_is_invisible(bbc, cfg1):
