@@ -55,6 +55,125 @@ def relmse(est, ref):
     return float(np.mean((est - ref) ** 2 / (ref ** 2 + 1e-2)))
 
 
+def make_trace(n_req, n_scenes, seed):
+    """Request stream of the serving workload: sizes floor(exp U[ln 256, ln 65536])
+    points, spp uniform over {16, 32, 64, 128, 256}, scene uniform."""
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(np.exp(rng.uniform(np.log(256), np.log(65536), n_req))).astype(np.int64)
+    spp = rng.choice([16, 32, 64, 128, 256], n_req)
+    scene = rng.integers(0, n_scenes, n_req)
+    seeds = rng.integers(0, 2**62, n_req)
+    offs = rng.integers(0, 65536, n_req)
+    return [dict(n=int(sizes[k]), spp=int(spp[k]), scene=int(scene[k]), seed=int(seeds[k]),
+                 off=int(min(offs[k], 65536 - sizes[k]))) for k in range(n_req)]
+
+
+def _wait_until(t0, t):
+    while True:
+        dt = t - (time.perf_counter() - t0)
+        if dt <= 0:
+            return
+        if dt > 5e-4:
+            time.sleep(dt - 3e-4)
+
+
+def run_plain(bbc, torch, bounds, reqs, trace, outs, arrivals=None):
+    """One batch per request through the one-launch-per-stage path on one
+    stream, in arrival order; returns (makespan s, latencies ms)."""
+    lat = []
+    t0 = time.perf_counter()
+    for k, r in enumerate(trace):
+        if arrivals is not None:
+            _wait_until(t0, arrivals[k])
+        bounds[r["scene"]].query(reqs[k], r["spp"], r["seed"], mode=bbc.QUERY_STAGED, out=outs[k])
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        lat.append(1e3 * (t - (arrivals[k] if arrivals is not None else 0.0)))
+    return time.perf_counter() - t0, lat
+
+
+def run_served(bbc, srv, reqs, trace, arrivals=None):
+    """Submit the trace to the server (at the arrival times, or all at once)
+    and wait for every request; returns (makespan s, latencies ms, outputs)."""
+    import threading
+    tickets = [None] * len(trace)
+    res = [None] * len(trace)
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        for k in range(len(trace)):
+            ready.acquire()
+            res[k] = srv.wait(tickets[k])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for k, r in enumerate(trace):
+        if arrivals is not None:
+            _wait_until(t0, arrivals[k])
+        tickets[k] = srv.submit(r["scene"], reqs[k], r["spp"], r["seed"], sync_inputs=False)
+        ready.release()
+    th.join()
+    t1 = time.perf_counter()
+    return t1 - t0, [x[1] for x in res], [x[0] for x in res]
+
+
+def serving_section(bbc, S, torch, sphere_scene, sphere_bounds, n_req=1500, seed=5):
+    """Continuous batching vs the plain per-request path on one request
+    stream over device-resident bounds: the displaced sphere and a rippled
+    plane mirror of 131072 triangles (256 x 256 heightfield)."""
+    dev = torch.device("cuda:0")
+    pool = S.heightfield_mirror(256)
+    pool_B = bbc.Bounds(bbc.DeviceScene(pool), dict(max_depth=6, sigma=1e-4, alpha=2.0, grid_res=512))
+    scenes = [sphere_scene, pool]
+    bounds = [sphere_bounds, pool_B]
+    pools = [torch.as_tensor(S.random_points(sc, 65536, seed=77 + j), device=dev) for j, sc in enumerate(scenes)]
+    trace = make_trace(n_req, len(scenes), seed)
+    reqs = [pools[r["scene"]][:, r["off"]:r["off"] + r["n"]].contiguous() for r in trace]
+    n_pts = sum(r["n"] for r in trace)
+    outs = [torch.empty(r["n"], dtype=torch.float32, device=dev) for r in trace]
+    torch.cuda.synchronize()
+    run_plain(bbc, torch, bounds, reqs, trace[:50], outs)  # warm-up
+    t_plain, _ = run_plain(bbc, torch, bounds, reqs, trace, outs)
+    cap_req = n_req / t_plain
+    srv = bbc.Server(bounds, hbm_budget_bytes=64 << 30, max_inflight=4, max_batch_points=1 << 20,
+                     max_batch_requests=1024, queue_capacity=1 << 16)
+    try:
+        run_served(bbc, srv, reqs, trace[:50])  # warm-up
+        srv.stats(reset=True)
+        t_srv, _, got = run_served(bbc, srv, reqs, trace)
+        identical = all(torch.equal(g, o) for g, o in zip(got, outs))
+        st_cap = srv.stats(reset=True)
+        rng = np.random.default_rng(seed + 1)
+        sweep = []
+        for x in (0.5, 0.8, 1.0, 1.2, 2.0, 3.0):
+            rate = x * cap_req
+            arr = np.cumsum(rng.exponential(1.0 / rate, n_req))
+            tp, lp = run_plain(bbc, torch, bounds, reqs, trace, outs, arrivals=arr)
+            ts, ls, _ = run_served(bbc, srv, reqs, trace, arrivals=arr)
+            st = srv.stats(reset=True)
+            sweep.append({"rate_x_plain_capacity": x, "offered_req_s": round(rate, 1),
+                          "plain": {"queries_s": round(n_pts / tp, 1), "p50_ms": round(float(np.percentile(lp, 50)), 3),
+                                    "p99_ms": round(float(np.percentile(lp, 99)), 3)},
+                          "served": {"queries_s": round(n_pts / ts, 1), "p50_ms": round(float(np.percentile(ls, 50)), 3),
+                                     "p99_ms": round(float(np.percentile(ls, 99)), 3),
+                                     "mean_batch_requests": round(st["mean_batch_requests"], 2)}})
+    finally:
+        srv.close()
+        pool_B.free()
+    return {
+        "scenes": [sphere_scene["name"] if "name" in sphere_scene else "sphere", pool["name"]],
+        "requests": n_req, "points": int(n_pts), "inputs": "device-resident points and outputs",
+        "saturated": {"plain_queries_s": round(n_pts / t_plain, 1), "served_queries_s": round(n_pts / t_srv, 1),
+                      "speedup": round(t_plain / t_srv, 3), "plain_req_s": round(cap_req, 1),
+                      "served_req_s": round(n_req / t_srv, 1),
+                      "mean_batch_requests": round(st_cap["mean_batch_requests"], 2),
+                      "inflight_peak": st_cap["inflight_peak"]},
+        "results_identical_to_plain": bool(identical),
+        "poisson": sweep,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +181,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--form", choices=["auto", "fused", "staged"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -148,6 +268,9 @@ def main():
         "work": {"leaves": info["n_leaves"], "grid_entries": info["n_grid_entries"], "pairs": qs["n_pairs"],
                  "newton_starts": qs["n_newton"], "roots": qs["n_roots"]},
     }
+
+    if not args.no_serving:
+        out["serving"] = serving_section(bbc, S, torch, scene, B)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

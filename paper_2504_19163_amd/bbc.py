@@ -298,9 +298,11 @@ class Server:
         self.h = h
         self._live = {}
 
-    def submit(self, scene, points, spp, seed, point_index_base=0):
+    def submit(self, scene, points, spp, seed, point_index_base=0, sync_inputs=True):
         """Queue a request; returns its ticket.  Raises BBCError (status
-        EBUDGET / EQUEUE / EINVAL) when it is not accepted."""
+        EBUDGET / EQUEUE / EINVAL) when it is not accepted.  Device points must
+        be complete before the server's streams read them: sync_inputs=True
+        synchronises torch's current stream first."""
         r = Request()
         r.scene = int(scene)
         r.spp = int(spp)
@@ -317,8 +319,9 @@ class Server:
             import torch
             pts = points.contiguous()
             assert pts.is_cuda and pts.dtype == torch.float32 and pts.dim() == 2 and pts.shape[0] == 3
-            out = torch.zeros(pts.shape[1], dtype=torch.float32, device=pts.device)
-            torch.cuda.current_stream().synchronize()  # inputs ready before the server's streams read them
+            out = torch.empty(pts.shape[1], dtype=torch.float32, device=pts.device)
+            if sync_inputs:
+                torch.cuda.current_stream().synchronize()
             r.memory = MEM_DEVICE
             r.points = pts.data_ptr()
             r.out = out.data_ptr()

@@ -152,7 +152,14 @@ static bbc_status run_build(Bounds* b, hipStream_t s) {
     if (ov & 4u) b->trip_cap = std::max<size_t>(b->trip_cap * 2, size_t(b->host.n_triples) + 1024);
     if (b->q_cap > (size_t(1) << 31) || b->trip_cap > (size_t(1) << 31)) break;
   }
-  set_error("device work queues overflowed their maximum capacity");
+  const uint32_t ov = b->host.overflow;
+  std::string what;
+  if (ov & 1u) what += " subdivision queue;";
+  if (ov & 2u) what += " leaves;";
+  if (ov & 4u) what += " grid entries (" + std::to_string(b->host.n_triples) + " cell-tuple pairs);";
+  if (ov & 8u) what += " FP64 queue;";
+  if (ov & 16u) what += " domain initialisation;";
+  set_error("device work queues overflowed their maximum capacity:" + what);
   return BBC_EQUEUE;
 }
 
