@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--form", choices=["auto", "fused", "staged"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device-to-device tensor copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -213,6 +215,12 @@ def main():
         form = args.form
     mode = forms[form]
     B.set_tuning(bbc.TUNE_TIMING, 1)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(k):
         B.rebuild()
