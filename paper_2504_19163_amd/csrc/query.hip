@@ -221,7 +221,7 @@ __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target&
     double ud = u, vd = v;
     ++wc.it64;  // FP64 path evaluations
     PathT<double> p = eval_path<double>(Gd, chain, ud, vd);
-    double res = 0.0;
+    double res = INFINITY;
     for (int it = 0; it < 10; ++it) {
       ++wc.it64;
       const double ru_ = p.uk - tg.ud, rv_ = p.vk - tg.vd;
@@ -497,6 +497,8 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
   }
 }
 
+// Newton over the selected pairs, one lane per pair for the whole of its
+// starts.
 __global__ void __launch_bounds__(64) k_stage_newton(StagedArgs s, const uint32_t* total) {
   const QueryArgs& a = s.q;
   const uint32_t np = min(*total, s.pair_cap);
@@ -600,8 +602,8 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   bbc_status e = launch_scan_u32(sel, s.off, n, w.scan, st);
   if (e) return e;
   hipLaunchKernelGGL(k_stage_fill, dim3(grid), dim3(64), 0, st, s);
-  const unsigned gp = unsigned(std::min<size_t>((pairs + 63) / 64, 32768));
   if (ev0) BBC_HIP(hipEventRecord(ev0, st));
+  const unsigned gp = unsigned(std::min<size_t>((pairs + 63) / 64, 32768));
   hipLaunchKernelGGL(k_stage_newton, dim3(gp), dim3(64), 0, st, s, s.off + n);
   if (ev1) BBC_HIP(hipEventRecord(ev1, st));
   hipLaunchKernelGGL(k_stage_accum, dim3(gpt), dim3(256), 0, st, s);
