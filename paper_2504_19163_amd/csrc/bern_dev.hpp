@@ -109,6 +109,33 @@ __device__ __forceinline__ void elev11(const T* __restrict__ iv, const T* __rest
   }
 }
 
+// Degree elevation by (R1, R2): (D1, D2) -> (D1+R1, D2+R2), scaled form (the
+// product with the constant 1 written at degree (R1, R2), whose scaled
+// coefficients are C(R1,i) C(R2,j)).
+template <int D1, int D2, int R1, int R2, class T>
+__device__ __forceinline__ void elev_by(const T* __restrict__ iv, const T* __restrict__ im, T* __restrict__ ov,
+                                        T* __restrict__ om, int lane) {
+  constexpr int E2 = D2 + R2, N = (D1 + R1 + 1) * (E2 + 1);
+  for (int o = lane; o < N; o += BBC_WAVE) {
+    const int k = o / (E2 + 1), l = o - k * (E2 + 1);
+    T s = 0, sm = 0;
+#pragma unroll
+    for (int i = 0; i <= R1; ++i) {
+#pragma unroll
+      for (int j = 0; j <= R2; ++j) {
+        const int a = k - i, b = l - j;
+        if (a >= 0 && a <= D1 && b >= 0 && b <= D2) {
+          const T w = T(binom_i(R1, i) * binom_i(R2, j));
+          s = fma(w, iv[a * (D2 + 1) + b], s);
+          sm = fma(w, im[a * (D2 + 1) + b], sm);
+        }
+      }
+    }
+    ov[o] = s;
+    om[o] = sm;
+  }
+}
+
 // Result of the rational range bound (Sec. 4.1, Eq. eq_bbound and its
 // sign-failure rules).
 enum : int { kDirect = 0, kSplit = 1, kUnbounded = 2 };
@@ -136,17 +163,18 @@ __device__ __forceinline__ void iv_div(T pl, T ph, T ql, T qh, T* lo, T* hi) {
   *hi = up(max(max(a, b), max(c, d)));
 }
 
-// Bound of p/q from N scaled coefficients of equal degree.  With final =
-// true a sign that cannot be decided counts as a sign failure; otherwise it
-// is reported through `uncertain` so the caller can redo the box at higher
-// precision.
-template <int N, class T>
-__device__ RB<T> ratio_bound(const T* pv, const T* pm, T tp, const T* qv, const T* qm, T tq, bool final, int lane) {
+// Bound of p/q over N coefficient pairs of equal degree, produced on the fly
+// by get(o, p, ep, q, eq) (value and absolute error bound of the o-th scaled
+// coefficient of each).  With final = true a sign that cannot be decided
+// counts as a sign failure; otherwise it is reported through `uncertain` so
+// the caller can redo the box at higher precision.
+template <class T, class Get>
+__device__ RB<T> ratio_bound_fn(int N, Get get, bool final, int lane) {
   bool q_pos = true, q_neg = true, q_anyp = false, q_anyn = false;
   bool p_pos = true, p_neg = true, p_anyp = false, p_anyn = false;
   for (int o = lane; o < N; o += BBC_WAVE) {
-    const T q = qv[o], eq = safe_err(tq, qm[o]);
-    const T p = pv[o], ep = safe_err(tp, pm[o]);
+    T p, ep, q, eq;
+    get(o, p, ep, q, eq);
     const bool qp = q - eq > T(0), qn = q + eq < T(0);
     const bool pp = p - ep > T(0), pn = p + ep < T(0);
     q_pos &= qp; q_neg &= qn; q_anyp |= qp; q_anyn |= qn;
@@ -164,8 +192,8 @@ __device__ RB<T> ratio_bound(const T* pv, const T* pm, T tp, const T* qv, const 
   if (q_pos || q_neg) {
     T lo = inf, hi = -inf;
     for (int o = lane; o < N; o += BBC_WAVE) {
-      const T q = qv[o], eq = safe_err(tq, qm[o]);
-      const T p = pv[o], ep = safe_err(tp, pm[o]);
+      T p, ep, q, eq;
+      get(o, p, ep, q, eq);
       T a, b;
       iv_div(p - ep, p + ep, q - eq, q + eq, &a, &b);
       lo = min(lo, a);
@@ -186,8 +214,8 @@ __device__ RB<T> ratio_bound(const T* pv, const T* pm, T tp, const T* qv, const 
     // reciprocal rule: bound q/p in [a, b], then invert
     T lo = inf, hi = -inf;
     for (int o = lane; o < N; o += BBC_WAVE) {
-      const T q = qv[o], eq = safe_err(tq, qm[o]);
-      const T p = pv[o], ep = safe_err(tp, pm[o]);
+      T p, ep, q, eq;
+      get(o, p, ep, q, eq);
       T a, b;
       iv_div(q - eq, q + eq, p - ep, p + ep, &a, &b);
       lo = min(lo, a);
@@ -220,6 +248,20 @@ __device__ RB<T> ratio_bound(const T* pv, const T* pm, T tp, const T* qv, const 
   r.lo = r.hi = 0;
   r.uncertain = !p_mixed && !final;
   return r;
+}
+
+// Bound of p/q from N stored scaled coefficients of equal degree.
+template <int N, class T>
+__device__ RB<T> ratio_bound(const T* pv, const T* pm, T tp, const T* qv, const T* qm, T tq, bool final, int lane) {
+  return ratio_bound_fn<T>(
+      N,
+      [&](int o, T& p, T& ep, T& q, T& eq) {
+        q = qv[o];
+        eq = safe_err(tq, qm[o]);
+        p = pv[o];
+        ep = safe_err(tp, pm[o]);
+      },
+      final, lane);
 }
 
 // Range [lo, hi] of a single polynomial from its scaled coefficients.

@@ -1,0 +1,616 @@
+// Position and irradiance bound of one box of a single-refraction tuple,
+// evaluated by one wave in FP64 with its polynomials in LDS (Sec. 4.2-4.4).
+//
+// Refraction (Eq. eq_refr_rational) writes the outgoing direction as
+//   d~ = eta ((n.n) d0 - (d0.n) n) - sqrt(beta) n,
+//   beta = (1 - eta^2)(n.n)(d0.d0) + eta^2 (d0.n)^2,
+// which is rational only after sqrt(beta) is replaced by a linear function of
+// beta plus a remainder (Sec. 4.3).  On a box with beta in [blo, bhi], blo > 0,
+// the secant r(beta) = a beta + b through (blo, sqrt(blo)) and (bhi, sqrt(bhi))
+// satisfies sqrt(beta) - r(beta) in [0, dhi], dhi = (sqrt(bhi) - sqrt(blo))^2 /
+// (4 (sqrt(blo) + sqrt(bhi))), so sqrt(beta) = a beta + b + (1 - xi1) dlo +
+// xi1 dhi for some remainder variable xi1 in [0, 1].  The derivative of
+// sqrt(beta) along u is beta_u w with w = 1 / (2 sqrt(beta)) in
+// [1 / (2 sqrt(bhi)), 1 / (2 sqrt(blo))]; a second remainder variable xi2
+// carries w.  Every polynomial is therefore a tensor in (u, v, xi1, xi2),
+// held here as slices over (xi1, xi2) of scaled (u, v) tensors; a product is a
+// convolution over the slice indices of 2-D convolutions (scaled form in all
+// four axes).
+//
+// det M uses the receiver-origin-free form of the reflection evaluator,
+//   det M = -(Q^2 D0 + Q Tn D1 + Tn^2 D2),  D0 = det[e1, e2, d~],
+//   D1 = det[d~_u, e2, d~] + det[e1, d~_v, d~],  D2 = det[d~_u, d~_v, d~],
+// with d~_u = A_u - w beta_u n, A_u = (eta((n.n) d0 - (d0.n) n))_u - r n_u.
+// Because det[n, n, .] = 0 the w^2 terms of D2 vanish identically, so det M
+// has degree one in xi2 (three in xi1, fifteen in u and v).  It and Q^3 are
+// raised to degree (16, 16, 3, 2) -- the degree of the cofactor expansion of M
+// with the total derivatives written out -- on the fly inside the ratio bound.
+#pragma once
+#include "../../include/bbc.h"
+#include "bern_dev.hpp"
+#include "box_r.hpp"
+#include "geom_dev.hpp"
+
+namespace bbc {
+
+// LDS layout (offsets in elements; a tensor of n coefficients takes 2n: its
+// values, then their magnitudes).
+struct TLay {
+  // position part
+  static constexpr int N = 0, D0v = 24, S = 48, SF1 = 72;               // (1,1) x 3 components
+  static constexpr int NN = 96, DN = 114, DD = 132, BETA = 150;         // (2,2) x 3, (4,4)
+  static constexpr int DT0 = 200;                                        // (3,3) x 3
+  static constexpr int RT = 296;                                         // (4,4) x 2 xi1-slices
+  static constexpr int DT = 396;                                         // (5,5,1) x 3
+  static constexpr int Q = 828, TN = 972;                                // (5,5,1), (1,1)
+  static constexpr int POS_END = 980;
+  // irradiance part
+  static constexpr int NNU = 980, NNV = 988, DDU = 996, DDV = 1004, DNU = 1012, DNV = 1020, G = 1028;
+  static constexpr int BU = 1036, BV = 1068;                             // (3,3)
+  static constexpr int DT0U = 1100, DT0V = 1154;                         // (2,2) x 3
+  static constexpr int AU = 1208, AV = 1508;                             // (4,4,1) x 3
+  static constexpr int DZ = 1808;                                        // D0 (5,5,1)
+  static constexpr int Q2 = 1952, QT = 2678, T2 = 2874;                  // (10,10,2), (6,6,1), (2,2)
+  static constexpr int D1 = 2892, D2 = 4092, Q3 = 2892;                  // (9,9,2,1), (13,13,3,1); Q3 reuses D1
+  static constexpr int IRR_TMP = 7228;
+  // scratch (offsets relative to the scratch base)
+  static constexpr int CC = 0, PU = 432, PV = 628, QE = 824, TNE = 1020;  // position phase: 1164
+  static constexpr int ND = 0, YP = 588, BNU = 2388;                      // irradiance: (6,6,1)x3, (9,9,2)x3, (4,4)x3
+  static constexpr int X = 2538, E1ND = 2970, Z1 = 3166;                   // D1 phase
+  static constexpr int BVAU = 2538, Z = 3306;                              // D2 phase: (7,7,1)x3, (13,13,2)
+  static constexpr int DETM = 0;                                           // (15,15,3,1): 4096
+  static constexpr int TMP_IRR = 4482, TMP_POS = 1164;
+};
+
+template <class T, bool IRR>
+struct LdsT {
+  T buf[IRR ? TLay::IRR_TMP + TLay::TMP_IRR : TLay::POS_END + TLay::TMP_POS];
+};
+
+// A tensor of n coefficients (all slices) at offset off.
+template <class T>
+struct TP {
+  T* v;
+  T* m;
+};
+template <class T>
+__device__ __forceinline__ TP<T> tpat(T* base, int off, int n) {
+  return TP<T>{base + off, base + off + n};
+}
+template <class T>
+__device__ __forceinline__ TP<T> slice(TP<T> t, int s, int n) {
+  return TP<T>{t.v + s * n, t.m + s * n};
+}
+template <class T>
+__device__ __forceinline__ void zero(TP<T> t, int n, int lane) {
+  for (int o = lane; o < n; o += BBC_WAVE) {
+    t.v[o] = T(0);
+    t.m[o] = T(0);
+  }
+}
+// c (=|+=) sgn a*b over 2-D slices of degrees (A1,A2), (B1,B2)
+template <int A1, int A2, int B1, int B2, bool ACC, class T>
+__device__ __forceinline__ void cv(TP<T> a, TP<T> b, TP<T> c, T sgn, int lane) {
+  conv<A1, A2, B1, B2, ACC>(a.v, a.m, b.v, b.m, c.v, c.m, sgn, lane);
+}
+// error factor of a sum of `pairs` slice products
+template <int A1, int A2, int B1, int B2, class T>
+__device__ __forceinline__ T th_conv(T ta, T tb, int pairs) {
+  constexpr int n = ((A1 < B1 ? A1 : B1) + 1) * ((A2 < B2 ? A2 : B2) + 1);
+  return ta + tb + ta * tb + T(n * pairs + 2) * Eps<T>::u;
+}
+
+template <class T, bool IRR>
+__device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool final, int flags, LdsT<T, IRR>& L,
+                             int lane) {
+  const T eps = Eps<T>::u;
+  T* B = L.buf;
+  T* Tm = B + (IRR ? TLay::IRR_TMP : TLay::POS_END);  // scratch
+  BoxOut out;
+  out.status = 0;
+  out.settled = false;
+  out.uk[0] = 0.f;
+  out.uk[1] = 1.f;
+  out.uk[2] = 0.f;
+  out.uk[3] = 1.f;
+  out.E[0] = 0.f;
+  out.E[1] = INFINITY;
+  if (!G.front || u0 + v0 >= T(1)) return out;
+  const T eta = G.eta, e2 = eta * eta, om = T(1) - e2;
+
+  // ---- linear forms n, d0, s at the box corners (scaled = plain at degree 1)
+  const V3<T> pmx = G.p0 - G.x0, pmq = G.p0 - G.q0;
+  for (int task = lane; task < 36; task += BBC_WAVE) {
+    const int which = task / 12, c = (task / 4) % 3, k = task % 4;
+    const T u = (k & 2) ? u1 : u0, v = (k & 1) ? v1 : v0;
+    T a, b, d;
+    if (which == 0) {
+      a = comp(G.n0, c); b = comp(G.dn1, c); d = comp(G.dn2, c);
+    } else if (which == 1) {
+      a = comp(pmx, c); b = comp(G.e1, c); d = comp(G.e2, c);
+    } else {
+      a = comp(pmq, c); b = comp(G.e1, c); d = comp(G.e2, c);
+    }
+    const int base = which == 0 ? TLay::N : (which == 1 ? TLay::D0v : TLay::S);
+    TP<T> dst = tpat(B, base + 8 * c, 4);
+    dst.v[k] = fma(d, v, fma(b, u, a));
+    dst.m[k] = fabs(a) + fabs(b) * fabs(u) + fabs(d) * fabs(v);
+  }
+  const T th_lin = T(4) * eps;
+  auto nC = [&](int c) { return tpat(B, TLay::N + 8 * c, 4); };
+  auto dC = [&](int c) { return tpat(B, TLay::D0v + 8 * c, 4); };
+  auto sC = [&](int c) { return tpat(B, TLay::S + 8 * c, 4); };
+  auto sfC = [&](int c) { return tpat(B, TLay::SF1 + 8 * c, 4); };
+  auto dtC = [&](int c) { return tpat(B, TLay::DT + 144 * c, 72); };  // both xi1-slices of one component
+  wave_sync();
+
+  // ---- s x f1 and the degree-(2,2) products n.n, d0.n, d0.d0
+  {
+    const T* sv[3] = {sC(0).v, sC(1).v, sC(2).v};
+    const T* sm[3] = {sC(0).m, sC(1).m, sC(2).m};
+    const V3<T> f1 = G.f1;
+    const T ax[3] = {T(0), f1.z, -f1.y}, ay[3] = {-f1.z, T(0), f1.x}, az[3] = {f1.y, -f1.x, T(0)};
+    combo<4, 3, false>(sv, sm, ax, sfC(0).v, sfC(0).m, lane);
+    combo<4, 3, false>(sv, sm, ay, sfC(1).v, sfC(1).m, lane);
+    combo<4, 3, false>(sv, sm, az, sfC(2).v, sfC(2).m, lane);
+    const TP<T> nn = tpat(B, TLay::NN, 9), dn = tpat(B, TLay::DN, 9), dd = tpat(B, TLay::DD, 9);
+    cv<1, 1, 1, 1, false>(nC(0), nC(0), nn, T(1), lane);
+    cv<1, 1, 1, 1, false>(dC(0), nC(0), dn, T(1), lane);
+    cv<1, 1, 1, 1, false>(dC(0), dC(0), dd, T(1), lane);
+    for (int c = 1; c < 3; ++c) {
+      cv<1, 1, 1, 1, true>(nC(c), nC(c), nn, T(1), lane);
+      cv<1, 1, 1, 1, true>(dC(c), nC(c), dn, T(1), lane);
+      cv<1, 1, 1, 1, true>(dC(c), dC(c), dd, T(1), lane);
+    }
+  }
+  const T th_sf1 = th_lin + T(4) * eps;
+  const T th_nn = th_conv<1, 1, 1, 1>(th_lin, th_lin, 3) + T(3) * eps;
+  wave_sync();
+  const TP<T> nn = tpat(B, TLay::NN, 9), dn = tpat(B, TLay::DN, 9), dd = tpat(B, TLay::DD, 9);
+  {
+    T lo, hi;
+    poly_range<2, 2>(dn.v, dn.m, th_nn, &lo, &hi, lane);
+    if (lo >= T(0)) return out;  // the light reaches the back of the shading normal everywhere
+  }
+  // ---- beta and the secant of its square root
+  const TP<T> beta = tpat(B, TLay::BETA, 25);
+  cv<2, 2, 2, 2, false>(nn, dd, beta, om, lane);
+  cv<2, 2, 2, 2, true>(dn, dn, beta, e2, lane);
+  const T th_beta = th_conv<2, 2, 2, 2>(th_nn, th_nn, 2) + T(4) * eps;
+  wave_sync();
+  T blo, bhi;
+  poly_range<4, 4>(beta.v, beta.m, th_beta, &blo, &bhi, lane);
+  if (bhi <= T(0)) return out;  // total internal reflection everywhere
+  if (blo <= T(0)) {            // the square root cannot be bounded here: universal bound
+    out.status = 1;
+    return out;
+  }
+  const bool remainder = !(flags & BBC_FLAG_NO_REMAINDER);
+  const T sa = sqrt(blo), sb = sqrt(bhi);
+  const T ra = T(1) / (sa + sb), rb = sa * sb / (sa + sb);
+  // remainder interval of the computed secant, widened by its rounding
+  const T slack = T(16) * eps * sb;
+  const T dlo = remainder ? -slack : T(0);
+  const T dhi = remainder ? up((sb - sa) * (sb - sa) / (T(4) * (sa + sb))) + slack : T(0);
+  const T wlo = remainder ? down(T(0.5) / up(sb)) : ra, whi = remainder ? up(T(0.5) / down(sa)) : ra;
+  // rt_k = a beta + b + d_k (xi1-slices k = 0, 1)
+  const TP<T> rt = tpat(B, TLay::RT, 50);
+  for (int o = lane; o < 50; o += BBC_WAVE) {
+    const int k = o / 25, r = o - 25 * k, i = r / 5, j = r - 5 * i;
+    const T w = T(binom_i(4, i) * binom_i(4, j));
+    const T c = rb + (k ? dhi : dlo);
+    rt.v[o] = fma(ra, beta.v[r], c * w);
+    rt.m[o] = fma(fabs(ra), beta.m[r], fabs(c) * w);
+  }
+  const T th_rt = th_beta + T(4) * eps;
+  // ---- dt0 = eta ((n.n) d0 - (d0.n) n)
+  for (int c = 0; c < 3; ++c) {
+    const TP<T> d = tpat(B, TLay::DT0 + 32 * c, 16);
+    cv<2, 2, 1, 1, false>(nn, dC(c), d, eta, lane);
+    cv<2, 2, 1, 1, true>(dn, nC(c), d, -eta, lane);
+  }
+  const T th_dt0 = th_conv<2, 2, 1, 1>(th_nn, th_lin, 2) + T(3) * eps;
+  wave_sync();
+  // ---- d~_k = dt0 (raised to (5,5)) - rt_k n
+  for (int c = 0; c < 3; ++c) {
+    const TP<T> d = tpat(B, TLay::DT0 + 32 * c, 16);
+    for (int k = 0; k < 2; ++k) {
+      const TP<T> o = slice(dtC(c), k, 36);
+      elev_by<3, 3, 2, 2>(d.v, d.m, o.v, o.m, lane);
+      cv<4, 4, 1, 1, true>(slice(rt, k, 25), nC(c), o, T(-1), lane);
+    }
+  }
+  const T th_dt = max(th_dt0 + T(10) * eps, th_conv<4, 4, 1, 1>(th_rt, th_lin, 1)) + T(2) * eps;
+  wave_sync();
+
+  // ---- cc = d~ x f2, Tn = (s x f1).f2
+  const TP<T> Tn = tpat(B, TLay::TN, 4);
+  {
+    const V3<T> f2 = G.f2;
+    const T ax[3] = {T(0), f2.z, -f2.y}, ay[3] = {-f2.z, T(0), f2.x}, az[3] = {f2.y, -f2.x, T(0)};
+    const T* al[3] = {ax, ay, az};
+    const T* dv[3] = {dtC(0).v, dtC(1).v, dtC(2).v};
+    const T* dm[3] = {dtC(0).m, dtC(1).m, dtC(2).m};
+    for (int c = 0; c < 3; ++c) {
+      const TP<T> cc = tpat(Tm, TLay::CC + 144 * c, 72);
+      combo<72, 3, false>(dv, dm, al[c], cc.v, cc.m, lane);
+    }
+    const T* sv[3] = {sfC(0).v, sfC(1).v, sfC(2).v};
+    const T* sm[3] = {sfC(0).m, sfC(1).m, sfC(2).m};
+    const T af2[3] = {f2.x, f2.y, f2.z};
+    combo<4, 3, false>(sv, sm, af2, Tn.v, Tn.m, lane);
+  }
+  const T th_cc = th_dt + T(3) * eps;
+  const T th_Tn = th_sf1 + T(3) * eps;
+  wave_sync();
+  // ---- Pu = cc.s, Pv = (s x f1).d~, Q = cc.f1 (per xi1-slice)
+  const TP<T> Pu = tpat(Tm, TLay::PU, 98), Pv = tpat(Tm, TLay::PV, 98), Q = tpat(B, TLay::Q, 72);
+  const TP<T> Qe = tpat(Tm, TLay::QE, 98), Tne = tpat(Tm, TLay::TNE, 72);
+  for (int k = 0; k < 2; ++k) {
+    for (int c = 0; c < 3; ++c) {
+      const TP<T> cc = slice(tpat(Tm, TLay::CC + 144 * c, 72), k, 36);
+      if (c == 0) {
+        cv<5, 5, 1, 1, false>(cc, sC(c), slice(Pu, k, 49), T(1), lane);
+        cv<5, 5, 1, 1, false>(slice(dtC(c), k, 36), sfC(c), slice(Pv, k, 49), T(1), lane);
+      } else {
+        cv<5, 5, 1, 1, true>(cc, sC(c), slice(Pu, k, 49), T(1), lane);
+        cv<5, 5, 1, 1, true>(slice(dtC(c), k, 36), sfC(c), slice(Pv, k, 49), T(1), lane);
+      }
+    }
+  }
+  {
+    const T* cvp[3], *cmp[3];
+    for (int c = 0; c < 3; ++c) {
+      const TP<T> cc = tpat(Tm, TLay::CC + 144 * c, 72);
+      cvp[c] = cc.v;
+      cmp[c] = cc.m;
+    }
+    const T af1[3] = {G.f1.x, G.f1.y, G.f1.z};
+    combo<72, 3, false>(cvp, cmp, af1, Q.v, Q.m, lane);
+    for (int k = 0; k < 2; ++k) {
+      const TP<T> o = slice(Tne, k, 36);
+      elev_by<1, 1, 4, 4>(Tn.v, Tn.m, o.v, o.m, lane);
+    }
+  }
+  const T th_P = th_conv<5, 5, 1, 1>(th_cc, th_lin, 3) + T(3) * eps;
+  const T th_Q = th_cc + T(3) * eps;
+  const T th_Tne = th_Tn + T(26) * eps;
+  wave_sync();
+  for (int k = 0; k < 2; ++k) {
+    const TP<T> qi = slice(Q, k, 36), qo = slice(Qe, k, 49);
+    elev11<5, 5>(qi.v, qi.m, qo.v, qo.m, lane);
+  }
+  const T th_Qe = th_Q + T(4) * eps;
+  wave_sync();
+
+  // ---- position bound (Sec. 4.2) and the sign of the ray parameter
+  const RB<T> tb = ratio_bound<72>(Tne.v, Tne.m, th_Tne, Q.v, Q.m, th_Q, final, lane);
+  const RB<T> ub = ratio_bound<98>(Pu.v, Pu.m, th_P, Qe.v, Qe.m, th_Qe, final, lane);
+  const RB<T> vb = ratio_bound<98>(Pv.v, Pv.m, th_P, Qe.v, Qe.m, th_Qe, final, lane);
+  if (tb.uncertain || ub.uncertain || vb.uncertain) {
+    out.status = 2;
+    return out;
+  }
+  if (tb.kind == kDirect && tb.hi <= T(0)) return out;  // every ray points away from the receiver
+  T ulo, uhi, vlo, vhi;
+  if (!clip01(ub, &ulo, &uhi) || !clip01(vb, &vlo, &vhi)) return out;
+  out.uk[0] = out_lo(ulo);
+  out.uk[1] = out_hi(uhi);
+  out.uk[2] = out_lo(vlo);
+  out.uk[3] = out_hi(vhi);
+  out.settled = ub.kind == kDirect && vb.kind == kDirect && ub.lo >= T(0) && ub.hi <= T(1) && vb.lo >= T(0) &&
+                vb.hi <= T(1) && tb.kind == kDirect && tb.lo > T(0);
+  out.status = 1;
+  if constexpr (!IRR) {
+    return out;
+  } else {
+    // ---- derivative linear forms, n_g.d0, and beta_u, beta_v
+    const TP<T> nnu = tpat(B, TLay::NNU, 4), nnv = tpat(B, TLay::NNV, 4), ddu = tpat(B, TLay::DDU, 4),
+                ddv = tpat(B, TLay::DDV, 4), dnu = tpat(B, TLay::DNU, 4), dnv = tpat(B, TLay::DNV, 4),
+                g = tpat(B, TLay::G, 4);
+    {
+      const T* nv[3] = {nC(0).v, nC(1).v, nC(2).v};
+      const T* nm[3] = {nC(0).m, nC(1).m, nC(2).m};
+      const T* dv[3] = {dC(0).v, dC(1).v, dC(2).v};
+      const T* dm[3] = {dC(0).m, dC(1).m, dC(2).m};
+      const T a_nnu[3] = {T(2) * G.dn1.x, T(2) * G.dn1.y, T(2) * G.dn1.z};
+      const T a_nnv[3] = {T(2) * G.dn2.x, T(2) * G.dn2.y, T(2) * G.dn2.z};
+      const T a_ddu[3] = {T(2) * G.e1.x, T(2) * G.e1.y, T(2) * G.e1.z};
+      const T a_ddv[3] = {T(2) * G.e2.x, T(2) * G.e2.y, T(2) * G.e2.z};
+      const T ag[3] = {G.ng.x, G.ng.y, G.ng.z};
+      combo<4, 3, false>(nv, nm, a_nnu, nnu.v, nnu.m, lane);
+      combo<4, 3, false>(nv, nm, a_nnv, nnv.v, nnv.m, lane);
+      combo<4, 3, false>(dv, dm, a_ddu, ddu.v, ddu.m, lane);
+      combo<4, 3, false>(dv, dm, a_ddv, ddv.v, ddv.m, lane);
+      combo<4, 3, false>(dv, dm, ag, g.v, g.m, lane);
+      const T* xv[6] = {nv[0], nv[1], nv[2], dv[0], dv[1], dv[2]};
+      const T* xm[6] = {nm[0], nm[1], nm[2], dm[0], dm[1], dm[2]};
+      const T a_dnu[6] = {G.e1.x, G.e1.y, G.e1.z, G.dn1.x, G.dn1.y, G.dn1.z};
+      const T a_dnv[6] = {G.e2.x, G.e2.y, G.e2.z, G.dn2.x, G.dn2.y, G.dn2.z};
+      combo<4, 6, false>(xv, xm, a_dnu, dnu.v, dnu.m, lane);
+      combo<4, 6, false>(xv, xm, a_dnv, dnv.v, dnv.m, lane);
+    }
+    const T th_l2 = th_lin + T(8) * eps;
+    const T th_g = th_lin + T(8) * eps;
+    wave_sync();
+    const TP<T> bu = tpat(B, TLay::BU, 16), bv = tpat(B, TLay::BV, 16);
+    cv<1, 1, 2, 2, false>(nnu, dd, bu, om, lane);
+    cv<2, 2, 1, 1, true>(nn, ddu, bu, om, lane);
+    cv<2, 2, 1, 1, true>(dn, dnu, bu, T(2) * e2, lane);
+    cv<1, 1, 2, 2, false>(nnv, dd, bv, om, lane);
+    cv<2, 2, 1, 1, true>(nn, ddv, bv, om, lane);
+    cv<2, 2, 1, 1, true>(dn, dnv, bv, T(2) * e2, lane);
+    const T th_bu = th_conv<2, 2, 1, 1>(th_nn, th_l2, 3) + T(4) * eps;
+    // dt0_u = eta (nnu d0 + nn e1 - dnu n - dn dn1), and the same in v
+    for (int c = 0; c < 3; ++c) {
+      const TP<T> du = tpat(B, TLay::DT0U + 18 * c, 9), dv = tpat(B, TLay::DT0V + 18 * c, 9);
+      cv<1, 1, 1, 1, false>(nnu, dC(c), du, eta, lane);
+      cv<1, 1, 1, 1, true>(dnu, nC(c), du, -eta, lane);
+      cv<1, 1, 1, 1, false>(nnv, dC(c), dv, eta, lane);
+      cv<1, 1, 1, 1, true>(dnv, nC(c), dv, -eta, lane);
+      const T* xv[2] = {nn.v, dn.v};
+      const T* xm[2] = {nn.m, dn.m};
+      const T au[2] = {eta * comp(G.e1, c), -eta * comp(G.dn1, c)};
+      const T av[2] = {eta * comp(G.e2, c), -eta * comp(G.dn2, c)};
+      combo<9, 2, true>(xv, xm, au, du.v, du.m, lane);
+      combo<9, 2, true>(xv, xm, av, dv.v, dv.m, lane);
+    }
+    const T th_dt0u = max(th_conv<1, 1, 1, 1>(th_l2, th_lin, 2), th_nn + T(2) * eps) + T(8) * eps;
+    wave_sync();
+    // A_u = dt0_u (raised to (4,4)) - rt dn1, A_v likewise; D0 = (e1 x e2).d~; X = e2 x d~;
+    // nd = n x d~; bnu = beta_u n
+    auto auC = [&](int c) { return tpat(B, TLay::AU + 100 * c, 50); };
+    auto avC = [&](int c) { return tpat(B, TLay::AV + 100 * c, 50); };
+    auto ndC = [&](int c) { return tpat(Tm, TLay::ND + 196 * c, 98); };
+    auto ypC = [&](int c) { return tpat(Tm, TLay::YP + 600 * c, 300); };
+    auto bnuC = [&](int c) { return tpat(Tm, TLay::BNU + 50 * c, 25); };
+    auto xC = [&](int c) { return tpat(Tm, TLay::X + 144 * c, 72); };
+    const TP<T> D0 = tpat(B, TLay::DZ, 72);
+    for (int c = 0; c < 3; ++c) {
+      const TP<T> du = tpat(B, TLay::DT0U + 18 * c, 9), dv = tpat(B, TLay::DT0V + 18 * c, 9);
+      const T* rv[1] = {nullptr};
+      const T* rm[1] = {nullptr};
+      for (int k = 0; k < 2; ++k) {
+        const TP<T> a = slice(auC(c), k, 25), b = slice(avC(c), k, 25), r = slice(rt, k, 25);
+        elev_by<2, 2, 2, 2>(du.v, du.m, a.v, a.m, lane);
+        elev_by<2, 2, 2, 2>(dv.v, dv.m, b.v, b.m, lane);
+        rv[0] = r.v;
+        rm[0] = r.m;
+        const T cu[1] = {-comp(G.dn1, c)}, cvv[1] = {-comp(G.dn2, c)};
+        combo<25, 1, true>(rv, rm, cu, a.v, a.m, lane);
+        combo<25, 1, true>(rv, rm, cvv, b.v, b.m, lane);
+      }
+      cv<3, 3, 1, 1, false>(bu, nC(c), bnuC(c), T(1), lane);
+    }
+    {
+      const V3<T> n12 = cross(G.e1, G.e2), ee2 = G.e2;
+      const T* dv[3] = {dtC(0).v, dtC(1).v, dtC(2).v};
+      const T* dm[3] = {dtC(0).m, dtC(1).m, dtC(2).m};
+      const T a12[3] = {n12.x, n12.y, n12.z};
+      combo<72, 3, false>(dv, dm, a12, D0.v, D0.m, lane);
+      const T xx[3] = {T(0), -ee2.z, ee2.y}, xy[3] = {ee2.z, T(0), -ee2.x}, xz[3] = {-ee2.y, ee2.x, T(0)};
+      combo<72, 3, false>(dv, dm, xx, xC(0).v, xC(0).m, lane);
+      combo<72, 3, false>(dv, dm, xy, xC(1).v, xC(1).m, lane);
+      combo<72, 3, false>(dv, dm, xz, xC(2).v, xC(2).m, lane);
+      for (int c = 0; c < 3; ++c) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        for (int k = 0; k < 2; ++k) {
+          cv<1, 1, 5, 5, false>(nC(a), slice(dtC(b), k, 36), slice(ndC(c), k, 49), T(1), lane);
+          cv<1, 1, 5, 5, true>(nC(b), slice(dtC(a), k, 36), slice(ndC(c), k, 49), T(-1), lane);
+        }
+      }
+    }
+    const T th_A = max(th_dt0u + T(10) * eps, th_rt + T(2) * eps) + T(2) * eps;
+    const T th_D0 = th_dt + T(4) * eps;
+    const T th_X = th_dt + T(3) * eps;
+    const T th_nd = th_conv<1, 1, 5, 5>(th_lin, th_dt, 2);
+    const T th_bnu = th_conv<3, 3, 1, 1>(th_bu, th_lin, 1);
+    wave_sync();
+    // ---- Yp = A_v x d~ (xi1 degree 2), e1.nd
+    for (int c = 0; c < 3; ++c) zero(ypC(c), 300, lane);
+    wave_sync();
+    for (int c = 0; c < 3; ++c) {
+      const int a = (c + 1) % 3, b = (c + 2) % 3;
+      for (int k1 = 0; k1 < 2; ++k1)
+        for (int k2 = 0; k2 < 2; ++k2) {
+          const TP<T> o = slice(ypC(c), k1 + k2, 100);
+          cv<4, 4, 5, 5, true>(slice(avC(a), k1, 25), slice(dtC(b), k2, 36), o, T(1), lane);
+          cv<4, 4, 5, 5, true>(slice(avC(b), k1, 25), slice(dtC(a), k2, 36), o, T(-1), lane);
+        }
+    }
+    const TP<T> e1nd = tpat(Tm, TLay::E1ND, 98);
+    {
+      const T* xv[3] = {ndC(0).v, ndC(1).v, ndC(2).v};
+      const T* xm[3] = {ndC(0).m, ndC(1).m, ndC(2).m};
+      const T ae1[3] = {G.e1.x, G.e1.y, G.e1.z};
+      combo<98, 3, false>(xv, xm, ae1, e1nd.v, e1nd.m, lane);
+    }
+    const T th_Yp = th_conv<4, 4, 5, 5>(th_A, th_dt, 4) + T(2) * eps;
+    const T th_e1nd = th_nd + T(3) * eps;
+    wave_sync();
+    // ---- D1 = A_u.X + e1.Yp - w (beta_u n.X + beta_v e1.nd)
+    const TP<T> D1 = tpat(B, TLay::D1, 600), Z1 = tpat(Tm, TLay::Z1, 200);
+    zero(D1, 600, lane);
+    zero(Z1, 200, lane);
+    wave_sync();
+    for (int c = 0; c < 3; ++c) {
+      for (int k1 = 0; k1 < 2; ++k1)
+        for (int k2 = 0; k2 < 2; ++k2)
+          cv<4, 4, 5, 5, true>(slice(auC(c), k1, 25), slice(xC(c), k2, 36), slice(D1, 2 * (k1 + k2), 100), T(1),
+                               lane);
+      for (int j = 0; j < 2; ++j)
+        cv<4, 4, 5, 5, true>(bnuC(c), slice(xC(c), j, 36), slice(Z1, j, 100), T(1), lane);
+    }
+    for (int j = 0; j < 2; ++j) cv<3, 3, 6, 6, true>(bv, slice(e1nd, j, 49), slice(Z1, j, 100), T(1), lane);
+    {
+      const T ae1[3] = {G.e1.x, G.e1.y, G.e1.z};
+      for (int m = 0; m < 3; ++m) {
+        const TP<T> o = slice(D1, 2 * m, 100);
+        for (int idx = lane; idx < 100; idx += BBC_WAVE) {
+          T s = o.v[idx], sm = o.m[idx];
+          for (int c = 0; c < 3; ++c) {
+            const TP<T> y = slice(ypC(c), m, 100);
+            s = fma(ae1[c], y.v[idx], s);
+            sm = fma(fabs(ae1[c]), y.m[idx], sm);
+          }
+          o.v[idx] = s;
+          o.m[idx] = sm;
+        }
+      }
+    }
+    const T th_Z1 = max(th_conv<4, 4, 5, 5>(th_bnu, th_X, 3), th_conv<3, 3, 6, 6>(th_bu, th_e1nd, 1)) + T(2) * eps;
+    const T th_D10 = max(th_conv<4, 4, 5, 5>(th_A, th_X, 12), th_Yp + T(4) * eps) + T(4) * eps;
+    wave_sync();
+    // D1(m, l) = D1_0(m) - w_l (Z1(m-1) + Z1(m))
+    for (int o = lane; o < 300; o += BBC_WAVE) {
+      const int m = o / 100, idx = o - 100 * m;
+      T z = T(0), zm = T(0);
+      if (m >= 1) { z += Z1.v[(m - 1) * 100 + idx]; zm += Z1.m[(m - 1) * 100 + idx]; }
+      if (m <= 1) { z += Z1.v[m * 100 + idx]; zm += Z1.m[m * 100 + idx]; }
+      const T b0 = D1.v[2 * m * 100 + idx], bm = D1.m[2 * m * 100 + idx];
+      D1.v[2 * m * 100 + idx] = fma(-wlo, z, b0);
+      D1.m[2 * m * 100 + idx] = fma(wlo, zm, bm);
+      D1.v[(2 * m + 1) * 100 + idx] = fma(-whi, z, b0);
+      D1.m[(2 * m + 1) * 100 + idx] = fma(whi, zm, bm);
+    }
+    const T th_D1 = max(th_D10, th_Z1 + T(2) * eps) + T(3) * eps;
+    wave_sync();
+    // ---- D2 = A_u.Yp - w (beta_u n.Yp + beta_v A_u.nd)
+    auto bvauC = [&](int c) { return tpat(Tm, TLay::BVAU + 256 * c, 128); };
+    const TP<T> D2 = tpat(B, TLay::D2, 1568), Z = tpat(Tm, TLay::Z, 588);
+    for (int c = 0; c < 3; ++c)
+      for (int k = 0; k < 2; ++k) cv<3, 3, 4, 4, false>(bv, slice(auC(c), k, 25), slice(bvauC(c), k, 64), T(1), lane);
+    zero(D2, 1568, lane);
+    zero(Z, 588, lane);
+    wave_sync();
+    for (int c = 0; c < 3; ++c) {
+      for (int k1 = 0; k1 < 2; ++k1)
+        for (int k2 = 0; k2 < 3; ++k2)
+          cv<4, 4, 9, 9, true>(slice(auC(c), k1, 25), slice(ypC(c), k2, 100), slice(D2, 2 * (k1 + k2), 196), T(1),
+                               lane);
+      for (int j = 0; j < 3; ++j)
+        cv<4, 4, 9, 9, true>(bnuC(c), slice(ypC(c), j, 100), slice(Z, j, 196), T(1), lane);
+      for (int k1 = 0; k1 < 2; ++k1)
+        for (int k2 = 0; k2 < 2; ++k2)
+          cv<7, 7, 6, 6, true>(slice(bvauC(c), k1, 64), slice(ndC(c), k2, 49), slice(Z, k1 + k2, 196), T(1), lane);
+    }
+    const T th_bvau = th_conv<3, 3, 4, 4>(th_bu, th_A, 1);
+    const T th_Z = max(th_conv<4, 4, 9, 9>(th_bnu, th_Yp, 3), th_conv<7, 7, 6, 6>(th_bvau, th_nd, 6)) + T(2) * eps;
+    const T th_D20 = th_conv<4, 4, 9, 9>(th_A, th_Yp, 6) + T(2) * eps;
+    wave_sync();
+    for (int o = lane; o < 4 * 196; o += BBC_WAVE) {
+      const int m = o / 196, idx = o - 196 * m;
+      T z = T(0), zm = T(0);
+      if (m >= 1) { z += Z.v[(m - 1) * 196 + idx]; zm += Z.m[(m - 1) * 196 + idx]; }
+      if (m <= 2) { z += Z.v[m * 196 + idx]; zm += Z.m[m * 196 + idx]; }
+      const T b0 = D2.v[2 * m * 196 + idx], bm = D2.m[2 * m * 196 + idx];
+      D2.v[2 * m * 196 + idx] = fma(-wlo, z, b0);
+      D2.m[2 * m * 196 + idx] = fma(wlo, zm, bm);
+      D2.v[(2 * m + 1) * 196 + idx] = fma(-whi, z, b0);
+      D2.m[(2 * m + 1) * 196 + idx] = fma(whi, zm, bm);
+    }
+    const T th_D2 = max(th_D20, th_Z + T(2) * eps) + T(3) * eps;
+    // ---- Q^2, Q Tn, Tn^2
+    const TP<T> Q2 = tpat(B, TLay::Q2, 363), QT = tpat(B, TLay::QT, 98), T2 = tpat(B, TLay::T2, 9);
+    zero(Q2, 363, lane);
+    wave_sync();
+    for (int k1 = 0; k1 < 2; ++k1)
+      for (int k2 = 0; k2 < 2; ++k2)
+        cv<5, 5, 5, 5, true>(slice(Q, k1, 36), slice(Q, k2, 36), slice(Q2, k1 + k2, 121), T(1), lane);
+    for (int k = 0; k < 2; ++k) cv<5, 5, 1, 1, false>(slice(Q, k, 36), Tn, slice(QT, k, 49), T(1), lane);
+    cv<1, 1, 1, 1, false>(Tn, Tn, T2, T(1), lane);
+    const T th_Q2 = th_conv<5, 5, 5, 5>(th_Q, th_Q, 2);
+    const T th_QT = th_conv<5, 5, 1, 1>(th_Q, th_Tn, 1);
+    const T th_T2 = th_conv<1, 1, 1, 1>(th_Tn, th_Tn, 1);
+    wave_sync();
+    // ---- det M = -(Q^2 D0 + Q Tn D1 + Tn^2 D2), slices (m, l) with m <= 3, l <= 1
+    const TP<T> detM = tpat(Tm, TLay::DETM, 2048);
+    zero(detM, 2048, lane);
+    wave_sync();
+    for (int k1 = 0; k1 < 3; ++k1)
+      for (int k2 = 0; k2 < 2; ++k2)
+        cv<10, 10, 5, 5, true>(slice(Q2, k1, 121), slice(D0, k2, 36), slice(detM, 2 * (k1 + k2), 256), T(-1), lane);
+    wave_sync();
+    for (int o = lane; o < 4 * 256; o += BBC_WAVE) {
+      const int m = o / 256, idx = o - 256 * m;
+      detM.v[(2 * m + 1) * 256 + idx] = detM.v[2 * m * 256 + idx];
+      detM.m[(2 * m + 1) * 256 + idx] = detM.m[2 * m * 256 + idx];
+    }
+    wave_sync();
+    for (int l = 0; l < 2; ++l) {
+      for (int k1 = 0; k1 < 2; ++k1)
+        for (int k2 = 0; k2 < 3; ++k2)
+          cv<6, 6, 9, 9, true>(slice(QT, k1, 49), slice(D1, 2 * k2 + l, 100), slice(detM, 2 * (k1 + k2) + l, 256),
+                               T(-1), lane);
+      for (int m = 0; m < 4; ++m)
+        cv<2, 2, 13, 13, true>(T2, slice(D2, 2 * m + l, 196), slice(detM, 2 * m + l, 256), T(-1), lane);
+    }
+    const T th_detM = max(max(th_conv<10, 10, 5, 5>(th_Q2, th_D0, 6), th_conv<6, 6, 9, 9>(th_QT, th_D1, 6)),
+                          th_conv<2, 2, 13, 13>(th_T2, th_D2, 1)) +
+                      T(6) * eps;
+    wave_sync();
+    // ---- Q^3 (xi1 degree 3) in the space of D1, D2
+    const TP<T> Q3 = tpat(B, TLay::Q3, 1024);
+    zero(Q3, 1024, lane);
+    wave_sync();
+    for (int k1 = 0; k1 < 3; ++k1)
+      for (int k2 = 0; k2 < 2; ++k2)
+        cv<10, 10, 5, 5, true>(slice(Q2, k1, 121), slice(Q, k2, 36), slice(Q3, k1 + k2, 256), T(1), lane);
+    const T th_Q3 = th_conv<10, 10, 5, 5>(th_Q2, th_Q, 6) + T(2) * eps;
+    wave_sync();
+    // ---- |Q^3 / det M| from the coefficients at degree (16, 16, 3, 2), raised on the fly
+    const T tq3 = th_Q3 + T(8) * eps, tdm = th_detM + T(8) * eps;
+    const RB<T> rbm = ratio_bound_fn<T>(
+        4 * 3 * 289,
+        [&](int o, T& p, T& ep, T& q, T& eq) {
+          const int m = o / 867, r1 = o - 867 * m, l = r1 / 289, r = r1 - 289 * l, i = r / 17, j = r - 17 * i;
+          T pv = T(0), pm = T(0), qv = T(0), qm = T(0);
+          for (int a = i - 1; a <= i; ++a) {
+            if (a < 0 || a > 15) continue;
+            for (int b = j - 1; b <= j; ++b) {
+              if (b < 0 || b > 15) continue;
+              const int id = a * 16 + b;
+              pv += Q3.v[m * 256 + id];
+              pm += Q3.m[m * 256 + id];
+              if (l <= 1) {
+                qv += detM.v[(2 * m) * 256 + id];
+                qm += detM.m[(2 * m) * 256 + id];
+              }
+              if (l >= 1) {
+                qv += detM.v[(2 * m + 1) * 256 + id];
+                qm += detM.m[(2 * m + 1) * 256 + id];
+              }
+            }
+          }
+          const T cl = l == 1 ? T(2) : T(1);
+          p = cl * pv;
+          ep = safe_err(tq3, cl * pm);
+          q = qv;
+          eq = safe_err(tdm, qm);
+        },
+        final, lane);
+    if (rbm.uncertain) {
+      out.status = 2;
+      return out;
+    }
+    T rlo, rhi;
+    abs_bound(rbm, &rlo, &rhi);
+    // dOmega0/dA1 = |g| / h^(3/2) with g = n_g . d0 and h = d0 . d0, bounded factor-wise
+    T glo, ghi, hlo, hhi;
+    poly_range<1, 1>(g.v, g.m, th_g, &glo, &ghi, lane);
+    poly_range<2, 2>(dd.v, dd.m, th_nn, &hlo, &hhi, lane);
+    const T aglo = (glo <= T(0) && ghi >= T(0)) ? T(0) : min(fabs(glo), fabs(ghi));
+    const T aghi = max(fabs(glo), fabs(ghi));
+    const T Glo = down(aglo / (hhi * sqrt(hhi)));
+    const T Ghi = hlo > T(0) ? up(aghi / (hlo * sqrt(hlo))) : T(INFINITY);
+    const T k = G.I0 * G.a1 / G.ak;
+    const T klo = k * (T(1) - T(16) * eps), khi = k * (T(1) + T(16) * eps);
+    const T Elo = (Glo <= T(0) || rlo <= T(0)) ? T(0) : down(klo * down(Glo * rlo));
+    const T Ehi = (isinf(Ghi) || isinf(rhi)) ? T(INFINITY) : up(khi * up(Ghi * rhi));
+    out.E[0] = out_lo(Elo);
+    out.E[1] = out_hi(Ehi);
+    return out;
+  }
+}
+
+}  // namespace bbc

@@ -11,9 +11,11 @@
 //                  children to the next depth's queue
 //   *_fp64         the same decisions for boxes whose denominators could not
 //                  be given a sign in FP32
+//   k_*_t          the refraction chain: every box in FP64 (box_t.hpp)
 // No host synchronisation happens between launches; every count lives in
 // device memory and every buffer has a capacity checked on the device.
 #include "box_r.hpp"
+#include "box_t.hpp"
 #include "internal.hpp"
 
 namespace bbc {
@@ -48,11 +50,12 @@ __device__ __forceinline__ void push_root(const BuildArgs& a, uint32_t t, float4
 }
 
 // Level 0: the whole parameter square of every tuple, position bound only.
-template <class T>
-__device__ void level0_one(const BuildArgs& a, uint32_t t, bool final, LdsRPos<T>& L, int lane) {
+// ev(G, u0, u1, v0, v1) bounds one box.
+template <class T, class Ev>
+__device__ void level0_one(const BuildArgs& a, uint32_t t, Ev ev, int lane) {
   const TupleGeom<T> G = tuple_geom<T>(a.sc, t);
   if (!G.front) return;
-  const BoxOut o = eval_box_r<T, false>(G, T(0), T(1), T(0), T(1), final, L, lane);
+  const BoxOut o = ev(G, T(0), T(1), T(0), T(1));
   if (lane != 0) return;
   if (o.status == 2) {
     const uint32_t i = atomicAdd(&a.C->n_l0_fp64, 1u);
@@ -71,8 +74,11 @@ __device__ void level0_one(const BuildArgs& a, uint32_t t, bool final, LdsRPos<T
 __global__ void __launch_bounds__(64) k_level0(BuildArgs a) {
   __shared__ LdsRPos<float> L;
   const int lane = threadIdx.x;
+  auto ev = [&](const TupleGeom<float>& G, float u0, float u1, float v0, float v1) {
+    return eval_box_r<float, false>(G, u0, u1, v0, v1, false, L, lane);
+  };
   for (int64_t t = blockIdx.x; t < a.n_tuples; t += gridDim.x) {
-    level0_one<float>(a, uint32_t(t), false, L, lane);
+    level0_one<float>(a, uint32_t(t), ev, lane);
     wave_sync();
   }
 }
@@ -80,9 +86,24 @@ __global__ void __launch_bounds__(64) k_level0(BuildArgs a) {
 __global__ void __launch_bounds__(64) k_level0_fp64(BuildArgs a) {
   __shared__ LdsRPos<double> L;
   const int lane = threadIdx.x;
+  auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
+    return eval_box_r<double, false>(G, u0, u1, v0, v1, true, L, lane);
+  };
   const uint32_t n = a.C->n_l0_fp64;
   for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-    level0_one<double>(a, a.l0f_q[i], true, L, lane);
+    level0_one<double>(a, a.l0f_q[i], ev, lane);
+    wave_sync();
+  }
+}
+
+__global__ void __launch_bounds__(64) k_level0_t(BuildArgs a) {
+  __shared__ LdsT<double, false> L;
+  const int lane = threadIdx.x;
+  auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
+    return eval_box_t<double, false>(G, u0, u1, v0, v1, true, a.flags, L, lane);
+  };
+  for (int64_t t = blockIdx.x; t < a.n_tuples; t += gridDim.x) {
+    level0_one<double>(a, uint32_t(t), ev, lane);
     wave_sync();
   }
 }
@@ -98,6 +119,68 @@ struct InitBox {
   uint32_t settled;
 };
 
+// One tuple's breadth-first initialisation; ev(cl, cu, cv) bounds the box
+// (cu, cv) of level cl.
+template <class Ev>
+__device__ void init_one(const BuildArgs& a, uint32_t t, Ev ev, InitBox* cur, InitBox* nxt, int lane) {
+  int ncur = 1;
+  if (lane == 0) cur[0] = InitBox{0u, 0u};
+  wave_sync();
+  bool dead = false;
+  for (int level = 1; level <= a.init_levels; ++level) {
+    bool all_settled = true;
+    for (int j = 0; j < ncur; ++j) all_settled = all_settled && cur[j].settled;
+    if (all_settled) break;
+    int nn = 0;
+    bool over = false;
+    for (int j = 0; j < ncur && !over; ++j) {
+      const InitBox b = cur[j];
+      if (b.settled) {
+        if (lane == 0) nxt[nn] = b;
+        ++nn;
+        over = nn > a.init_pieces;
+        continue;
+      }
+      const int bl = int(b.code >> 28);
+      const uint32_t iu = (b.code >> 14) & 0x3fffu, iv = b.code & 0x3fffu;
+      for (int ch = 0; ch < 4 && !over; ++ch) {
+        const uint32_t cu = 2 * iu + (ch >> 1), cv = 2 * iv + (ch & 1);
+        const int cl = bl + 1;
+        wave_sync();
+        const BoxOut o = ev(cl, cu, cv);
+        if (o.status == 1) {
+          if (lane == 0) nxt[nn] = InitBox{uint32_t(cl) << 28 | cu << 14 | cv, o.settled ? 1u : 0u};
+          ++nn;
+          over = nn > a.init_pieces;
+        }
+      }
+    }
+    wave_sync();
+    if (over) break;
+    if (nn == 0) {
+      dead = true;
+      break;
+    }
+    for (int j = lane; j < nn; j += BBC_WAVE) cur[j] = nxt[j];
+    ncur = nn;
+    wave_sync();
+  }
+  if (!dead && lane == 0) {
+    float u0 = 1.f, u1 = 0.f, v0 = 1.f, v1 = 0.f;
+    for (int j = 0; j < ncur; ++j) {
+      const int bl = int(cur[j].code >> 28);
+      const float w = ldexpf(1.f, -bl);
+      const uint32_t iu = (cur[j].code >> 14) & 0x3fffu, iv = cur[j].code & 0x3fffu;
+      u0 = fminf(u0, iu * w);
+      u1 = fmaxf(u1, (iu + 1) * w);
+      v0 = fminf(v0, iv * w);
+      v1 = fmaxf(v1, (iv + 1) * w);
+    }
+    push_root(a, t, make_float4(u0, u1, v0, v1));
+  }
+  wave_sync();
+}
+
 __global__ void __launch_bounds__(64) k_init(BuildArgs a) {
   __shared__ LdsRPos<float> Lf;
   __shared__ LdsRPos<double> Ld;
@@ -108,84 +191,48 @@ __global__ void __launch_bounds__(64) k_init(BuildArgs a) {
     const uint32_t t = a.init_q[it];
     const TupleGeom<float> Gf = tuple_geom<float>(a.sc, t);
     const TupleGeom<double> Gd = tuple_geom<double>(a.sc, t);
-    int ncur = 1;
-    if (lane == 0) cur[0] = InitBox{0u, 0u};
-    wave_sync();
-    bool dead = false;
-    for (int level = 1; level <= a.init_levels; ++level) {
-      bool all_settled = true;
-      for (int j = 0; j < ncur; ++j) all_settled = all_settled && cur[j].settled;
-      if (all_settled) break;
-      int nn = 0;
-      bool over = false;
-      for (int j = 0; j < ncur && !over; ++j) {
-        const InitBox b = cur[j];
-        if (b.settled) {
-          if (lane == 0) nxt[nn] = b;
-          ++nn;
-          over = nn > a.init_pieces;
-          continue;
-        }
-        const int bl = int(b.code >> 28);
-        const uint32_t iu = (b.code >> 14) & 0x3fffu, iv = b.code & 0x3fffu;
-        for (int ch = 0; ch < 4 && !over; ++ch) {
-          const uint32_t cu = 2 * iu + (ch >> 1), cv = 2 * iv + (ch & 1);
-          const int cl = bl + 1;
-          const float w = ldexpf(1.f, -cl);
-          wave_sync();
-          BoxOut o = eval_box_r<float, false>(Gf, cu * w, (cu + 1) * w, cv * w, (cv + 1) * w, false, Lf, lane);
-          if (o.status == 2) {
-            wave_sync();
-            const double wd = ldexp(1.0, -cl);
-            o = eval_box_r<double, false>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, true, Ld, lane);
-          }
-          if (o.status == 1) {
-            if (lane == 0) nxt[nn] = InitBox{uint32_t(cl) << 28 | cu << 14 | cv, o.settled ? 1u : 0u};
-            ++nn;
-            over = nn > a.init_pieces;
-          }
-        }
+    auto ev = [&](int cl, uint32_t cu, uint32_t cv) {
+      const float w = ldexpf(1.f, -cl);
+      BoxOut o = eval_box_r<float, false>(Gf, cu * w, (cu + 1) * w, cv * w, (cv + 1) * w, false, Lf, lane);
+      if (o.status == 2) {
+        wave_sync();
+        const double wd = ldexp(1.0, -cl);
+        o = eval_box_r<double, false>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, true, Ld, lane);
       }
-      wave_sync();
-      if (over) break;
-      if (nn == 0) {
-        dead = true;
-        break;
-      }
-      for (int j = lane; j < nn; j += BBC_WAVE) cur[j] = nxt[j];
-      ncur = nn;
-      wave_sync();
-    }
-    if (!dead && lane == 0) {
-      float u0 = 1.f, u1 = 0.f, v0 = 1.f, v1 = 0.f;
-      for (int j = 0; j < ncur; ++j) {
-        const int bl = int(cur[j].code >> 28);
-        const float w = ldexpf(1.f, -bl);
-        const uint32_t iu = (cur[j].code >> 14) & 0x3fffu, iv = cur[j].code & 0x3fffu;
-        u0 = fminf(u0, iu * w);
-        u1 = fmaxf(u1, (iu + 1) * w);
-        v0 = fminf(v0, iv * w);
-        v1 = fmaxf(v1, (iv + 1) * w);
-      }
-      push_root(a, t, make_float4(u0, u1, v0, v1));
-    }
-    wave_sync();
+      return o;
+    };
+    init_one(a, t, ev, cur, nxt, lane);
+  }
+}
+
+__global__ void __launch_bounds__(64) k_init_t(BuildArgs a) {
+  __shared__ LdsT<double, false> L;
+  __shared__ InitBox cur[kInitCap], nxt[kInitCap];
+  const int lane = threadIdx.x;
+  const uint32_t n = a.C->n_init;
+  for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const uint32_t t = a.init_q[it];
+    const TupleGeom<double> Gd = tuple_geom<double>(a.sc, t);
+    auto ev = [&](int cl, uint32_t cu, uint32_t cv) {
+      const double wd = ldexp(1.0, -cl);
+      return eval_box_t<double, false>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, true, a.flags, L, lane);
+    };
+    init_one(a, t, ev, cur, nxt, lane);
   }
 }
 
 // One box of the adaptive subdivision (Sec. 6.1): stop when the clipped
 // position bound's area is below sigma, when E_hi / E_lo < alpha, or at the
 // depth cap; otherwise split at the midpoint into four.
-template <class T>
-__device__ void subdiv_one(const BuildArgs& a, QItem it, int depth, bool final, LdsR<T>& L, int lane,
-                           uint32_t* n_boxes) {
+template <class T, class Ev>
+__device__ void subdiv_one(const BuildArgs& a, QItem it, int depth, Ev ev, int lane, uint32_t* n_boxes) {
   const TupleGeom<T> G = tuple_geom<T>(a.sc, it.tuple);
   const float4 r = a.root[it.tuple];
   const uint32_t iu = it.code >> kCodeBits, iv = it.code & ((1u << kCodeBits) - 1);
   const T fu = (T(r.y) - T(r.x)) * T(ldexpf(1.f, -depth)), fv = (T(r.w) - T(r.z)) * T(ldexpf(1.f, -depth));
   const T u0 = T(r.x) + T(iu) * fu, u1 = T(r.x) + T(iu + 1) * fu;
   const T v0 = T(r.z) + T(iv) * fv, v1 = T(r.z) + T(iv + 1) * fv;
-  const BoxOut o = eval_box_r<T, true>(G, u0, u1, v0, v1, final, L, lane);
+  const BoxOut o = ev(G, u0, u1, v0, v1);
   ++*n_boxes;
   if (lane != 0) return;
   if (o.status == 2) {
@@ -232,10 +279,28 @@ __device__ void subdiv_one(const BuildArgs& a, QItem it, int depth, bool final, 
 __global__ void __launch_bounds__(64) k_subdiv(BuildArgs a, int depth) {
   __shared__ LdsR<double> L;
   const int lane = threadIdx.x;
+  auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
+    return eval_box_r<double, true>(G, u0, u1, v0, v1, true, L, lane);
+  };
   const uint32_t n = min(a.C->qcount[depth], a.q_cap);
   uint32_t boxes = 0;
   for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-    subdiv_one<double>(a, a.qin[i], depth, true, L, lane, &boxes);
+    subdiv_one<double>(a, a.qin[i], depth, ev, lane, &boxes);
+    wave_sync();
+  }
+  if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
+}
+
+__global__ void __launch_bounds__(64) k_subdiv_t(BuildArgs a, int depth) {
+  __shared__ LdsT<double, true> L;
+  const int lane = threadIdx.x;
+  auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
+    return eval_box_t<double, true>(G, u0, u1, v0, v1, true, a.flags, L, lane);
+  };
+  const uint32_t n = min(a.C->qcount[depth], a.q_cap);
+  uint32_t boxes = 0;
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    subdiv_one<double>(a, a.qin[i], depth, ev, lane, &boxes);
     wave_sync();
   }
   if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
@@ -287,18 +352,29 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   a.qin = nullptr;
   a.qout = static_cast<QItem*>(b->q[0].p);
   const unsigned g0 = unsigned(std::min<int64_t>(b->n_tuples, int64_t(n_cu) * 64));
-  hipLaunchKernelGGL(k_level0, dim3(g0), dim3(64), 0, s, a);
-  BBC_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_level0_fp64, dim3(persistent), dim3(64), 0, s, a);
+  const bool refr = b->scene.chain == BBC_CHAIN_T;
+  if (refr) {
+    hipLaunchKernelGGL(k_level0_t, dim3(g0), dim3(64), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_level0, dim3(g0), dim3(64), 0, s, a);
+    BBC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_level0_fp64, dim3(persistent), dim3(64), 0, s, a);
+  }
   BBC_HIP(hipGetLastError());
   if (a.init_levels > 0) {
-    hipLaunchKernelGGL(k_init, dim3(persistent), dim3(64), 0, s, a);
+    if (refr)
+      hipLaunchKernelGGL(k_init_t, dim3(persistent), dim3(64), 0, s, a);
+    else
+      hipLaunchKernelGGL(k_init, dim3(persistent), dim3(64), 0, s, a);
     BBC_HIP(hipGetLastError());
   }
   for (int d = 0; d <= a.max_depth; ++d) {
     a.qin = static_cast<QItem*>(b->q[d & 1].p);
     a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
-    hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, s, a, d);
+    if (refr)
+      hipLaunchKernelGGL(k_subdiv_t, dim3(persistent), dim3(64), 0, s, a, d);
+    else
+      hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, s, a, d);
     BBC_HIP(hipGetLastError());
   }
   return BBC_OK;

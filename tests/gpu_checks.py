@@ -1,0 +1,28 @@
+"""Comparisons of GPU bound hierarchies with the FP64 oracle, shared by the
+GPU parity tests."""
+import numpy as np
+
+BOUND_TOL = 1e-5
+
+
+def keyset(L):
+    return set(zip(np.asarray(L["tuple"]).tolist(), map(tuple, np.asarray(L["code"]).tolist())))
+
+
+def check_leaf_bounds(orc, osc, L, idx, tol=BOUND_TOL):
+    """GPU leaves against the oracle's bound of the very same box: the GPU
+    bound contains the oracle's and exceeds it by at most `tol`."""
+    for k in idx:
+        ob = orc.box_bound(osc, int(L["tuple"][k]), L["box"][k].astype(np.float64))
+        assert ob["live"], k
+        gu = L["uk"][k].astype(np.float64)
+        ou = ob["uk"]
+        assert gu[0] <= ou[0] + 1e-12 and gu[2] <= ou[2] + 1e-12, (k, gu, ou)
+        assert gu[1] >= ou[1] - 1e-12 and gu[3] >= ou[3] - 1e-12, (k, gu, ou)
+        assert np.max(np.abs(gu - ou)) <= tol, (k, gu, ou)
+        gE = L["E"][k].astype(np.float64)
+        oE = ob["E"]
+        assert np.isinf(gE[1]) == np.isinf(oE[1]), (k, gE, oE)
+        if np.isfinite(oE[1]):
+            assert gE[1] >= oE[1] * (1 - 1e-12) and gE[1] <= oE[1] * (1 + tol), (k, gE, oE)
+        assert gE[0] <= oE[0] * (1 + 1e-12) and gE[0] >= oE[0] * (1 - tol), (k, gE, oE)

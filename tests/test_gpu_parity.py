@@ -8,6 +8,7 @@ shading point agree to 1e-5 relative (identical Philox draws on both sides, FP64
 polish of every root); tree shapes agree except where a stop decision falls
 within rounding of its threshold.
 """
+import gpu_checks
 import numpy as np
 import pytest
 
@@ -29,27 +30,11 @@ def bbc():
     return B
 
 
-def _keyset(L):
-    return set(zip(np.asarray(L["tuple"]).tolist(), map(tuple, np.asarray(L["code"]).tolist())))
+_keyset = gpu_checks.keyset
 
 
 def _check_leaf_bounds(orc, osc, L, idx):
-    """GPU leaves against the oracle's bound of the very same box."""
-    for k in idx:
-        ob = orc.box_bound(osc, int(L["tuple"][k]), L["box"][k].astype(np.float64))
-        assert ob["live"], k
-        gu = L["uk"][k].astype(np.float64)
-        ou = ob["uk"]
-        # outward: the GPU box contains the oracle's, within the unit-range tolerance
-        assert gu[0] <= ou[0] + 1e-12 and gu[2] <= ou[2] + 1e-12, (k, gu, ou)
-        assert gu[1] >= ou[1] - 1e-12 and gu[3] >= ou[3] - 1e-12, (k, gu, ou)
-        assert np.max(np.abs(gu - ou)) <= BOUND_TOL, (k, gu, ou)
-        gE = L["E"][k].astype(np.float64)
-        oE = ob["E"]
-        assert np.isinf(gE[1]) == np.isinf(oE[1]), (k, gE, oE)
-        if np.isfinite(oE[1]):
-            assert gE[1] >= oE[1] * (1 - 1e-12) and gE[1] <= oE[1] * (1 + BOUND_TOL), (k, gE, oE)
-        assert gE[0] <= oE[0] * (1 + 1e-12) and gE[0] >= oE[0] * (1 - BOUND_TOL), (k, gE, oE)
+    gpu_checks.check_leaf_bounds(orc, osc, L, idx, BOUND_TOL)
 
 
 @pytest.fixture(scope="module")
