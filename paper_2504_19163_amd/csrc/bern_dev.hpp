@@ -35,16 +35,16 @@ __device__ __forceinline__ T safe_err(T theta, T m) {
 
 // C (=|+=) sgn * conv(A, B).  Degrees (A1,A2) x (B1,B2) -> (A1+B1, A2+B2).
 // Each lane owns output coefficients and loops over the smaller operand.
-template <int A1, int A2, int B1, int B2, bool ACC, class T>
+template <int A1, int A2, int B1, int B2, bool ACC, class T, int NT = BBC_WAVE>
 __device__ __forceinline__ void conv(const T* __restrict__ av, const T* __restrict__ am, const T* __restrict__ bv,
                                      const T* __restrict__ bm, T* __restrict__ cv, T* __restrict__ cm, T sgn,
                                      int lane) {
   if constexpr ((A1 + 1) * (A2 + 1) > (B1 + 1) * (B2 + 1)) {
-    conv<B1, B2, A1, A2, ACC, T>(bv, bm, av, am, cv, cm, sgn, lane);
+    conv<B1, B2, A1, A2, ACC, T, NT>(bv, bm, av, am, cv, cm, sgn, lane);
   } else {
     constexpr int C2 = A2 + B2;
     constexpr int N = (A1 + B1 + 1) * (C2 + 1);
-    for (int o = lane; o < N; o += BBC_WAVE) {
+    for (int o = lane; o < N; o += NT) {
       const int k = o / (C2 + 1), l = o - k * (C2 + 1);
       T s = 0, sm = 0;
 #pragma unroll
@@ -77,10 +77,10 @@ __device__ __forceinline__ T conv_theta(T ta, T tb) {
 }
 
 // out (=|+=) sum_k alpha_k A_k over K tensors of N coefficients.
-template <int N, int K, bool ACC, class T>
+template <int N, int K, bool ACC, class T, int NT = BBC_WAVE>
 __device__ __forceinline__ void combo(const T* const* av, const T* const* am, const T* alpha, T* __restrict__ ov,
                                       T* __restrict__ om, int lane) {
-  for (int o = lane; o < N; o += BBC_WAVE) {
+  for (int o = lane; o < N; o += NT) {
     T s = ACC ? ov[o] : T(0), sm = ACC ? om[o] : T(0);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -93,11 +93,11 @@ __device__ __forceinline__ void combo(const T* const* av, const T* const* am, co
 }
 
 // Degree elevation by one along both axes: (D1, D2) -> (D1+1, D2+1), scaled form.
-template <int D1, int D2, class T>
+template <int D1, int D2, class T, int NT = BBC_WAVE>
 __device__ __forceinline__ void elev11(const T* __restrict__ iv, const T* __restrict__ im, T* __restrict__ ov,
                                        T* __restrict__ om, int lane) {
   constexpr int E2 = D2 + 1, N = (D1 + 2) * (D2 + 2);
-  for (int o = lane; o < N; o += BBC_WAVE) {
+  for (int o = lane; o < N; o += NT) {
     const int i = o / (E2 + 1), j = o - i * (E2 + 1);
     T a = 0, b = 0, c = 0, d = 0, ma = 0, mb = 0, mc = 0, md = 0;
     if (i <= D1 && j <= D2) { a = iv[i * (D2 + 1) + j]; ma = im[i * (D2 + 1) + j]; }
@@ -112,11 +112,11 @@ __device__ __forceinline__ void elev11(const T* __restrict__ iv, const T* __rest
 // Degree elevation by (R1, R2): (D1, D2) -> (D1+R1, D2+R2), scaled form (the
 // product with the constant 1 written at degree (R1, R2), whose scaled
 // coefficients are C(R1,i) C(R2,j)).
-template <int D1, int D2, int R1, int R2, class T>
+template <int D1, int D2, int R1, int R2, class T, int NT = BBC_WAVE>
 __device__ __forceinline__ void elev_by(const T* __restrict__ iv, const T* __restrict__ im, T* __restrict__ ov,
                                         T* __restrict__ om, int lane) {
   constexpr int E2 = D2 + R2, N = (D1 + R1 + 1) * (E2 + 1);
-  for (int o = lane; o < N; o += BBC_WAVE) {
+  for (int o = lane; o < N; o += NT) {
     const int k = o / (E2 + 1), l = o - k * (E2 + 1);
     T s = 0, sm = 0;
 #pragma unroll
@@ -168,11 +168,11 @@ __device__ __forceinline__ void iv_div(T pl, T ph, T ql, T qh, T* lo, T* hi) {
 // coefficient of each).  With final = true a sign that cannot be decided
 // counts as a sign failure; otherwise it is reported through `uncertain` so
 // the caller can redo the box at higher precision.
-template <class T, class Get>
+template <class T, int NT = BBC_WAVE, class Get>
 __device__ RB<T> ratio_bound_fn(int N, Get get, bool final, int lane) {
   bool q_pos = true, q_neg = true, q_anyp = false, q_anyn = false;
   bool p_pos = true, p_neg = true, p_anyp = false, p_anyn = false;
-  for (int o = lane; o < N; o += BBC_WAVE) {
+  for (int o = lane; o < N; o += NT) {
     T p, ep, q, eq;
     get(o, p, ep, q, eq);
     const bool qp = q - eq > T(0), qn = q + eq < T(0);
@@ -180,18 +180,18 @@ __device__ RB<T> ratio_bound_fn(int N, Get get, bool final, int lane) {
     q_pos &= qp; q_neg &= qn; q_anyp |= qp; q_anyn |= qn;
     p_pos &= pp; p_neg &= pn; p_anyp |= pp; p_anyn |= pn;
   }
-  q_pos = wave_all(q_pos);
-  q_neg = wave_all(q_neg);
-  const bool q_mixed = wave_any(q_anyp) && wave_any(q_anyn);
-  p_pos = wave_all(p_pos);
-  p_neg = wave_all(p_neg);
-  const bool p_mixed = wave_any(p_anyp) && wave_any(p_anyn);
+  q_pos = blk_all<NT>(q_pos);
+  q_neg = blk_all<NT>(q_neg);
+  const bool q_mixed = blk_any<NT>(q_anyp) && blk_any<NT>(q_anyn);
+  p_pos = blk_all<NT>(p_pos);
+  p_neg = blk_all<NT>(p_neg);
+  const bool p_mixed = blk_any<NT>(p_anyp) && blk_any<NT>(p_anyn);
   RB<T> r;
   r.uncertain = false;
   const T inf = T(INFINITY);
   if (q_pos || q_neg) {
     T lo = inf, hi = -inf;
-    for (int o = lane; o < N; o += BBC_WAVE) {
+    for (int o = lane; o < N; o += NT) {
       T p, ep, q, eq;
       get(o, p, ep, q, eq);
       T a, b;
@@ -200,8 +200,8 @@ __device__ RB<T> ratio_bound_fn(int N, Get get, bool final, int lane) {
       hi = max(hi, b);
     }
     r.kind = kDirect;
-    r.lo = wave_min(lo);
-    r.hi = wave_max(hi);
+    r.lo = blk_min<NT>(lo);
+    r.hi = blk_max<NT>(hi);
     return r;
   }
   if (!q_mixed && !final) {
@@ -213,7 +213,7 @@ __device__ RB<T> ratio_bound_fn(int N, Get get, bool final, int lane) {
   if (p_pos || p_neg) {
     // reciprocal rule: bound q/p in [a, b], then invert
     T lo = inf, hi = -inf;
-    for (int o = lane; o < N; o += BBC_WAVE) {
+    for (int o = lane; o < N; o += NT) {
       T p, ep, q, eq;
       get(o, p, ep, q, eq);
       T a, b;
@@ -221,7 +221,7 @@ __device__ RB<T> ratio_bound_fn(int N, Get get, bool final, int lane) {
       lo = min(lo, a);
       hi = max(hi, b);
     }
-    const T a = wave_min(lo), b = wave_max(hi);
+    const T a = blk_min<NT>(lo), b = blk_max<NT>(hi);
     if (a > T(0) || b < T(0)) {
       r.kind = kDirect;
       r.lo = down(T(1) / b);
@@ -251,9 +251,9 @@ __device__ RB<T> ratio_bound_fn(int N, Get get, bool final, int lane) {
 }
 
 // Bound of p/q from N stored scaled coefficients of equal degree.
-template <int N, class T>
+template <int N, class T, int NT = BBC_WAVE>
 __device__ RB<T> ratio_bound(const T* pv, const T* pm, T tp, const T* qv, const T* qm, T tq, bool final, int lane) {
-  return ratio_bound_fn<T>(
+  return ratio_bound_fn<T, NT>(
       N,
       [&](int o, T& p, T& ep, T& q, T& eq) {
         q = qv[o];
@@ -265,19 +265,19 @@ __device__ RB<T> ratio_bound(const T* pv, const T* pm, T tp, const T* qv, const 
 }
 
 // Range [lo, hi] of a single polynomial from its scaled coefficients.
-template <int D1, int D2, class T>
+template <int D1, int D2, class T, int NT = BBC_WAVE>
 __device__ void poly_range(const T* v, const T* m, T th, T* lo, T* hi, int lane) {
   constexpr int N = (D1 + 1) * (D2 + 1);
   T l = T(INFINITY), h = -T(INFINITY);
-  for (int o = lane; o < N; o += BBC_WAVE) {
+  for (int o = lane; o < N; o += NT) {
     const int i = o / (D2 + 1), j = o - i * (D2 + 1);
     const T w = T(binom_i(D1, i) * binom_i(D2, j));
     const T e = safe_err(th, m[o]);
     l = min(l, down((v[o] - e) / w));
     h = max(h, up((v[o] + e) / w));
   }
-  *lo = wave_min(l);
-  *hi = wave_max(h);
+  *lo = blk_min<NT>(l);
+  *hi = blk_max<NT>(h);
 }
 
 // Clip a ratio bound to [0, 1]; false when the intersection is empty.

@@ -1,5 +1,5 @@
 // Position and irradiance bound of one box of a single-refraction tuple,
-// evaluated by one wave in FP64 with its polynomials in LDS (Sec. 4.2-4.4).
+// evaluated by NT lanes (one or several waves) in FP64 with its polynomials in LDS (Sec. 4.2-4.4).
 //
 // Refraction (Eq. eq_refr_rational) writes the outgoing direction as
 //   d~ = eta ((n.n) d0 - (d0.n) n) - sqrt(beta) n,
@@ -81,17 +81,17 @@ template <class T>
 __device__ __forceinline__ TP<T> slice(TP<T> t, int s, int n) {
   return TP<T>{t.v + s * n, t.m + s * n};
 }
-template <class T>
+template <int NT, class T>
 __device__ __forceinline__ void zero(TP<T> t, int n, int lane) {
-  for (int o = lane; o < n; o += BBC_WAVE) {
+  for (int o = lane; o < n; o += NT) {
     t.v[o] = T(0);
     t.m[o] = T(0);
   }
 }
 // c (=|+=) sgn a*b over 2-D slices of degrees (A1,A2), (B1,B2)
-template <int A1, int A2, int B1, int B2, bool ACC, class T>
+template <int A1, int A2, int B1, int B2, bool ACC, int NT, class T>
 __device__ __forceinline__ void cv(TP<T> a, TP<T> b, TP<T> c, T sgn, int lane) {
-  conv<A1, A2, B1, B2, ACC>(a.v, a.m, b.v, b.m, c.v, c.m, sgn, lane);
+  conv<A1, A2, B1, B2, ACC, T, NT>(a.v, a.m, b.v, b.m, c.v, c.m, sgn, lane);
 }
 // error factor of a sum of `pairs` slice products
 template <int A1, int A2, int B1, int B2, class T>
@@ -100,7 +100,7 @@ __device__ __forceinline__ T th_conv(T ta, T tb, int pairs) {
   return ta + tb + ta * tb + T(n * pairs + 2) * Eps<T>::u;
 }
 
-template <class T, bool IRR>
+template <class T, bool IRR, int NT>
 __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool final, int flags, LdsT<T, IRR>& L,
                              int lane) {
   const T eps = Eps<T>::u;
@@ -120,7 +120,7 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
 
   // ---- linear forms n, d0, s at the box corners (scaled = plain at degree 1)
   const V3<T> pmx = G.p0 - G.x0, pmq = G.p0 - G.q0;
-  for (int task = lane; task < 36; task += BBC_WAVE) {
+  for (int task = lane; task < 36; task += NT) {
     const int which = task / 12, c = (task / 4) % 3, k = task % 4;
     const T u = (k & 2) ? u1 : u0, v = (k & 1) ? v1 : v0;
     T a, b, d;
@@ -150,17 +150,17 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     const T* sm[3] = {sC(0).m, sC(1).m, sC(2).m};
     const V3<T> f1 = G.f1;
     const T ax[3] = {T(0), f1.z, -f1.y}, ay[3] = {-f1.z, T(0), f1.x}, az[3] = {f1.y, -f1.x, T(0)};
-    combo<4, 3, false>(sv, sm, ax, sfC(0).v, sfC(0).m, lane);
-    combo<4, 3, false>(sv, sm, ay, sfC(1).v, sfC(1).m, lane);
-    combo<4, 3, false>(sv, sm, az, sfC(2).v, sfC(2).m, lane);
+    combo<4, 3, false, T, NT>(sv, sm, ax, sfC(0).v, sfC(0).m, lane);
+    combo<4, 3, false, T, NT>(sv, sm, ay, sfC(1).v, sfC(1).m, lane);
+    combo<4, 3, false, T, NT>(sv, sm, az, sfC(2).v, sfC(2).m, lane);
     const TP<T> nn = tpat(B, TLay::NN, 9), dn = tpat(B, TLay::DN, 9), dd = tpat(B, TLay::DD, 9);
-    cv<1, 1, 1, 1, false>(nC(0), nC(0), nn, T(1), lane);
-    cv<1, 1, 1, 1, false>(dC(0), nC(0), dn, T(1), lane);
-    cv<1, 1, 1, 1, false>(dC(0), dC(0), dd, T(1), lane);
+    cv<1, 1, 1, 1, false, NT>(nC(0), nC(0), nn, T(1), lane);
+    cv<1, 1, 1, 1, false, NT>(dC(0), nC(0), dn, T(1), lane);
+    cv<1, 1, 1, 1, false, NT>(dC(0), dC(0), dd, T(1), lane);
     for (int c = 1; c < 3; ++c) {
-      cv<1, 1, 1, 1, true>(nC(c), nC(c), nn, T(1), lane);
-      cv<1, 1, 1, 1, true>(dC(c), nC(c), dn, T(1), lane);
-      cv<1, 1, 1, 1, true>(dC(c), dC(c), dd, T(1), lane);
+      cv<1, 1, 1, 1, true, NT>(nC(c), nC(c), nn, T(1), lane);
+      cv<1, 1, 1, 1, true, NT>(dC(c), nC(c), dn, T(1), lane);
+      cv<1, 1, 1, 1, true, NT>(dC(c), dC(c), dd, T(1), lane);
     }
   }
   const T th_sf1 = th_lin + T(4) * eps;
@@ -169,17 +169,17 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
   const TP<T> nn = tpat(B, TLay::NN, 9), dn = tpat(B, TLay::DN, 9), dd = tpat(B, TLay::DD, 9);
   {
     T lo, hi;
-    poly_range<2, 2>(dn.v, dn.m, th_nn, &lo, &hi, lane);
+    poly_range<2, 2, T, NT>(dn.v, dn.m, th_nn, &lo, &hi, lane);
     if (lo >= T(0)) return out;  // the light reaches the back of the shading normal everywhere
   }
   // ---- beta and the secant of its square root
   const TP<T> beta = tpat(B, TLay::BETA, 25);
-  cv<2, 2, 2, 2, false>(nn, dd, beta, om, lane);
-  cv<2, 2, 2, 2, true>(dn, dn, beta, e2, lane);
+  cv<2, 2, 2, 2, false, NT>(nn, dd, beta, om, lane);
+  cv<2, 2, 2, 2, true, NT>(dn, dn, beta, e2, lane);
   const T th_beta = th_conv<2, 2, 2, 2>(th_nn, th_nn, 2) + T(4) * eps;
   wave_sync();
   T blo, bhi;
-  poly_range<4, 4>(beta.v, beta.m, th_beta, &blo, &bhi, lane);
+  poly_range<4, 4, T, NT>(beta.v, beta.m, th_beta, &blo, &bhi, lane);
   if (bhi <= T(0)) return out;  // total internal reflection everywhere
   if (blo <= T(0)) {            // the square root cannot be bounded here: universal bound
     out.status = 1;
@@ -195,7 +195,7 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
   const T wlo = remainder ? down(T(0.5) / up(sb)) : ra, whi = remainder ? up(T(0.5) / down(sa)) : ra;
   // rt_k = a beta + b + d_k (xi1-slices k = 0, 1)
   const TP<T> rt = tpat(B, TLay::RT, 50);
-  for (int o = lane; o < 50; o += BBC_WAVE) {
+  for (int o = lane; o < 50; o += NT) {
     const int k = o / 25, r = o - 25 * k, i = r / 5, j = r - 5 * i;
     const T w = T(binom_i(4, i) * binom_i(4, j));
     const T c = rb + (k ? dhi : dlo);
@@ -206,8 +206,8 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
   // ---- dt0 = eta ((n.n) d0 - (d0.n) n)
   for (int c = 0; c < 3; ++c) {
     const TP<T> d = tpat(B, TLay::DT0 + 32 * c, 16);
-    cv<2, 2, 1, 1, false>(nn, dC(c), d, eta, lane);
-    cv<2, 2, 1, 1, true>(dn, nC(c), d, -eta, lane);
+    cv<2, 2, 1, 1, false, NT>(nn, dC(c), d, eta, lane);
+    cv<2, 2, 1, 1, true, NT>(dn, nC(c), d, -eta, lane);
   }
   const T th_dt0 = th_conv<2, 2, 1, 1>(th_nn, th_lin, 2) + T(3) * eps;
   wave_sync();
@@ -216,8 +216,8 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     const TP<T> d = tpat(B, TLay::DT0 + 32 * c, 16);
     for (int k = 0; k < 2; ++k) {
       const TP<T> o = slice(dtC(c), k, 36);
-      elev_by<3, 3, 2, 2>(d.v, d.m, o.v, o.m, lane);
-      cv<4, 4, 1, 1, true>(slice(rt, k, 25), nC(c), o, T(-1), lane);
+      elev_by<3, 3, 2, 2, T, NT>(d.v, d.m, o.v, o.m, lane);
+      cv<4, 4, 1, 1, true, NT>(slice(rt, k, 25), nC(c), o, T(-1), lane);
     }
   }
   const T th_dt = max(th_dt0 + T(10) * eps, th_conv<4, 4, 1, 1>(th_rt, th_lin, 1)) + T(2) * eps;
@@ -233,12 +233,12 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     const T* dm[3] = {dtC(0).m, dtC(1).m, dtC(2).m};
     for (int c = 0; c < 3; ++c) {
       const TP<T> cc = tpat(Tm, TLay::CC + 144 * c, 72);
-      combo<72, 3, false>(dv, dm, al[c], cc.v, cc.m, lane);
+      combo<72, 3, false, T, NT>(dv, dm, al[c], cc.v, cc.m, lane);
     }
     const T* sv[3] = {sfC(0).v, sfC(1).v, sfC(2).v};
     const T* sm[3] = {sfC(0).m, sfC(1).m, sfC(2).m};
     const T af2[3] = {f2.x, f2.y, f2.z};
-    combo<4, 3, false>(sv, sm, af2, Tn.v, Tn.m, lane);
+    combo<4, 3, false, T, NT>(sv, sm, af2, Tn.v, Tn.m, lane);
   }
   const T th_cc = th_dt + T(3) * eps;
   const T th_Tn = th_sf1 + T(3) * eps;
@@ -250,11 +250,11 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     for (int c = 0; c < 3; ++c) {
       const TP<T> cc = slice(tpat(Tm, TLay::CC + 144 * c, 72), k, 36);
       if (c == 0) {
-        cv<5, 5, 1, 1, false>(cc, sC(c), slice(Pu, k, 49), T(1), lane);
-        cv<5, 5, 1, 1, false>(slice(dtC(c), k, 36), sfC(c), slice(Pv, k, 49), T(1), lane);
+        cv<5, 5, 1, 1, false, NT>(cc, sC(c), slice(Pu, k, 49), T(1), lane);
+        cv<5, 5, 1, 1, false, NT>(slice(dtC(c), k, 36), sfC(c), slice(Pv, k, 49), T(1), lane);
       } else {
-        cv<5, 5, 1, 1, true>(cc, sC(c), slice(Pu, k, 49), T(1), lane);
-        cv<5, 5, 1, 1, true>(slice(dtC(c), k, 36), sfC(c), slice(Pv, k, 49), T(1), lane);
+        cv<5, 5, 1, 1, true, NT>(cc, sC(c), slice(Pu, k, 49), T(1), lane);
+        cv<5, 5, 1, 1, true, NT>(slice(dtC(c), k, 36), sfC(c), slice(Pv, k, 49), T(1), lane);
       }
     }
   }
@@ -266,10 +266,10 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
       cmp[c] = cc.m;
     }
     const T af1[3] = {G.f1.x, G.f1.y, G.f1.z};
-    combo<72, 3, false>(cvp, cmp, af1, Q.v, Q.m, lane);
+    combo<72, 3, false, T, NT>(cvp, cmp, af1, Q.v, Q.m, lane);
     for (int k = 0; k < 2; ++k) {
       const TP<T> o = slice(Tne, k, 36);
-      elev_by<1, 1, 4, 4>(Tn.v, Tn.m, o.v, o.m, lane);
+      elev_by<1, 1, 4, 4, T, NT>(Tn.v, Tn.m, o.v, o.m, lane);
     }
   }
   const T th_P = th_conv<5, 5, 1, 1>(th_cc, th_lin, 3) + T(3) * eps;
@@ -278,15 +278,15 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
   wave_sync();
   for (int k = 0; k < 2; ++k) {
     const TP<T> qi = slice(Q, k, 36), qo = slice(Qe, k, 49);
-    elev11<5, 5>(qi.v, qi.m, qo.v, qo.m, lane);
+    elev11<5, 5, T, NT>(qi.v, qi.m, qo.v, qo.m, lane);
   }
   const T th_Qe = th_Q + T(4) * eps;
   wave_sync();
 
   // ---- position bound (Sec. 4.2) and the sign of the ray parameter
-  const RB<T> tb = ratio_bound<72>(Tne.v, Tne.m, th_Tne, Q.v, Q.m, th_Q, final, lane);
-  const RB<T> ub = ratio_bound<98>(Pu.v, Pu.m, th_P, Qe.v, Qe.m, th_Qe, final, lane);
-  const RB<T> vb = ratio_bound<98>(Pv.v, Pv.m, th_P, Qe.v, Qe.m, th_Qe, final, lane);
+  const RB<T> tb = ratio_bound<72, T, NT>(Tne.v, Tne.m, th_Tne, Q.v, Q.m, th_Q, final, lane);
+  const RB<T> ub = ratio_bound<98, T, NT>(Pu.v, Pu.m, th_P, Qe.v, Qe.m, th_Qe, final, lane);
+  const RB<T> vb = ratio_bound<98, T, NT>(Pv.v, Pv.m, th_P, Qe.v, Qe.m, th_Qe, final, lane);
   if (tb.uncertain || ub.uncertain || vb.uncertain) {
     out.status = 2;
     return out;
@@ -318,42 +318,42 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
       const T a_ddu[3] = {T(2) * G.e1.x, T(2) * G.e1.y, T(2) * G.e1.z};
       const T a_ddv[3] = {T(2) * G.e2.x, T(2) * G.e2.y, T(2) * G.e2.z};
       const T ag[3] = {G.ng.x, G.ng.y, G.ng.z};
-      combo<4, 3, false>(nv, nm, a_nnu, nnu.v, nnu.m, lane);
-      combo<4, 3, false>(nv, nm, a_nnv, nnv.v, nnv.m, lane);
-      combo<4, 3, false>(dv, dm, a_ddu, ddu.v, ddu.m, lane);
-      combo<4, 3, false>(dv, dm, a_ddv, ddv.v, ddv.m, lane);
-      combo<4, 3, false>(dv, dm, ag, g.v, g.m, lane);
+      combo<4, 3, false, T, NT>(nv, nm, a_nnu, nnu.v, nnu.m, lane);
+      combo<4, 3, false, T, NT>(nv, nm, a_nnv, nnv.v, nnv.m, lane);
+      combo<4, 3, false, T, NT>(dv, dm, a_ddu, ddu.v, ddu.m, lane);
+      combo<4, 3, false, T, NT>(dv, dm, a_ddv, ddv.v, ddv.m, lane);
+      combo<4, 3, false, T, NT>(dv, dm, ag, g.v, g.m, lane);
       const T* xv[6] = {nv[0], nv[1], nv[2], dv[0], dv[1], dv[2]};
       const T* xm[6] = {nm[0], nm[1], nm[2], dm[0], dm[1], dm[2]};
       const T a_dnu[6] = {G.e1.x, G.e1.y, G.e1.z, G.dn1.x, G.dn1.y, G.dn1.z};
       const T a_dnv[6] = {G.e2.x, G.e2.y, G.e2.z, G.dn2.x, G.dn2.y, G.dn2.z};
-      combo<4, 6, false>(xv, xm, a_dnu, dnu.v, dnu.m, lane);
-      combo<4, 6, false>(xv, xm, a_dnv, dnv.v, dnv.m, lane);
+      combo<4, 6, false, T, NT>(xv, xm, a_dnu, dnu.v, dnu.m, lane);
+      combo<4, 6, false, T, NT>(xv, xm, a_dnv, dnv.v, dnv.m, lane);
     }
     const T th_l2 = th_lin + T(8) * eps;
     const T th_g = th_lin + T(8) * eps;
     wave_sync();
     const TP<T> bu = tpat(B, TLay::BU, 16), bv = tpat(B, TLay::BV, 16);
-    cv<1, 1, 2, 2, false>(nnu, dd, bu, om, lane);
-    cv<2, 2, 1, 1, true>(nn, ddu, bu, om, lane);
-    cv<2, 2, 1, 1, true>(dn, dnu, bu, T(2) * e2, lane);
-    cv<1, 1, 2, 2, false>(nnv, dd, bv, om, lane);
-    cv<2, 2, 1, 1, true>(nn, ddv, bv, om, lane);
-    cv<2, 2, 1, 1, true>(dn, dnv, bv, T(2) * e2, lane);
+    cv<1, 1, 2, 2, false, NT>(nnu, dd, bu, om, lane);
+    cv<2, 2, 1, 1, true, NT>(nn, ddu, bu, om, lane);
+    cv<2, 2, 1, 1, true, NT>(dn, dnu, bu, T(2) * e2, lane);
+    cv<1, 1, 2, 2, false, NT>(nnv, dd, bv, om, lane);
+    cv<2, 2, 1, 1, true, NT>(nn, ddv, bv, om, lane);
+    cv<2, 2, 1, 1, true, NT>(dn, dnv, bv, T(2) * e2, lane);
     const T th_bu = th_conv<2, 2, 1, 1>(th_nn, th_l2, 3) + T(4) * eps;
     // dt0_u = eta (nnu d0 + nn e1 - dnu n - dn dn1), and the same in v
     for (int c = 0; c < 3; ++c) {
       const TP<T> du = tpat(B, TLay::DT0U + 18 * c, 9), dv = tpat(B, TLay::DT0V + 18 * c, 9);
-      cv<1, 1, 1, 1, false>(nnu, dC(c), du, eta, lane);
-      cv<1, 1, 1, 1, true>(dnu, nC(c), du, -eta, lane);
-      cv<1, 1, 1, 1, false>(nnv, dC(c), dv, eta, lane);
-      cv<1, 1, 1, 1, true>(dnv, nC(c), dv, -eta, lane);
+      cv<1, 1, 1, 1, false, NT>(nnu, dC(c), du, eta, lane);
+      cv<1, 1, 1, 1, true, NT>(dnu, nC(c), du, -eta, lane);
+      cv<1, 1, 1, 1, false, NT>(nnv, dC(c), dv, eta, lane);
+      cv<1, 1, 1, 1, true, NT>(dnv, nC(c), dv, -eta, lane);
       const T* xv[2] = {nn.v, dn.v};
       const T* xm[2] = {nn.m, dn.m};
       const T au[2] = {eta * comp(G.e1, c), -eta * comp(G.dn1, c)};
       const T av[2] = {eta * comp(G.e2, c), -eta * comp(G.dn2, c)};
-      combo<9, 2, true>(xv, xm, au, du.v, du.m, lane);
-      combo<9, 2, true>(xv, xm, av, dv.v, dv.m, lane);
+      combo<9, 2, true, T, NT>(xv, xm, au, du.v, du.m, lane);
+      combo<9, 2, true, T, NT>(xv, xm, av, dv.v, dv.m, lane);
     }
     const T th_dt0u = max(th_conv<1, 1, 1, 1>(th_l2, th_lin, 2), th_nn + T(2) * eps) + T(8) * eps;
     wave_sync();
@@ -372,31 +372,31 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
       const T* rm[1] = {nullptr};
       for (int k = 0; k < 2; ++k) {
         const TP<T> a = slice(auC(c), k, 25), b = slice(avC(c), k, 25), r = slice(rt, k, 25);
-        elev_by<2, 2, 2, 2>(du.v, du.m, a.v, a.m, lane);
-        elev_by<2, 2, 2, 2>(dv.v, dv.m, b.v, b.m, lane);
+        elev_by<2, 2, 2, 2, T, NT>(du.v, du.m, a.v, a.m, lane);
+        elev_by<2, 2, 2, 2, T, NT>(dv.v, dv.m, b.v, b.m, lane);
         rv[0] = r.v;
         rm[0] = r.m;
         const T cu[1] = {-comp(G.dn1, c)}, cvv[1] = {-comp(G.dn2, c)};
-        combo<25, 1, true>(rv, rm, cu, a.v, a.m, lane);
-        combo<25, 1, true>(rv, rm, cvv, b.v, b.m, lane);
+        combo<25, 1, true, T, NT>(rv, rm, cu, a.v, a.m, lane);
+        combo<25, 1, true, T, NT>(rv, rm, cvv, b.v, b.m, lane);
       }
-      cv<3, 3, 1, 1, false>(bu, nC(c), bnuC(c), T(1), lane);
+      cv<3, 3, 1, 1, false, NT>(bu, nC(c), bnuC(c), T(1), lane);
     }
     {
       const V3<T> n12 = cross(G.e1, G.e2), ee2 = G.e2;
       const T* dv[3] = {dtC(0).v, dtC(1).v, dtC(2).v};
       const T* dm[3] = {dtC(0).m, dtC(1).m, dtC(2).m};
       const T a12[3] = {n12.x, n12.y, n12.z};
-      combo<72, 3, false>(dv, dm, a12, D0.v, D0.m, lane);
+      combo<72, 3, false, T, NT>(dv, dm, a12, D0.v, D0.m, lane);
       const T xx[3] = {T(0), -ee2.z, ee2.y}, xy[3] = {ee2.z, T(0), -ee2.x}, xz[3] = {-ee2.y, ee2.x, T(0)};
-      combo<72, 3, false>(dv, dm, xx, xC(0).v, xC(0).m, lane);
-      combo<72, 3, false>(dv, dm, xy, xC(1).v, xC(1).m, lane);
-      combo<72, 3, false>(dv, dm, xz, xC(2).v, xC(2).m, lane);
+      combo<72, 3, false, T, NT>(dv, dm, xx, xC(0).v, xC(0).m, lane);
+      combo<72, 3, false, T, NT>(dv, dm, xy, xC(1).v, xC(1).m, lane);
+      combo<72, 3, false, T, NT>(dv, dm, xz, xC(2).v, xC(2).m, lane);
       for (int c = 0; c < 3; ++c) {
         const int a = (c + 1) % 3, b = (c + 2) % 3;
         for (int k = 0; k < 2; ++k) {
-          cv<1, 1, 5, 5, false>(nC(a), slice(dtC(b), k, 36), slice(ndC(c), k, 49), T(1), lane);
-          cv<1, 1, 5, 5, true>(nC(b), slice(dtC(a), k, 36), slice(ndC(c), k, 49), T(-1), lane);
+          cv<1, 1, 5, 5, false, NT>(nC(a), slice(dtC(b), k, 36), slice(ndC(c), k, 49), T(1), lane);
+          cv<1, 1, 5, 5, true, NT>(nC(b), slice(dtC(a), k, 36), slice(ndC(c), k, 49), T(-1), lane);
         }
       }
     }
@@ -407,15 +407,15 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     const T th_bnu = th_conv<3, 3, 1, 1>(th_bu, th_lin, 1);
     wave_sync();
     // ---- Yp = A_v x d~ (xi1 degree 2), e1.nd
-    for (int c = 0; c < 3; ++c) zero(ypC(c), 300, lane);
+    for (int c = 0; c < 3; ++c) zero<NT>(ypC(c), 300, lane);
     wave_sync();
     for (int c = 0; c < 3; ++c) {
       const int a = (c + 1) % 3, b = (c + 2) % 3;
       for (int k1 = 0; k1 < 2; ++k1)
         for (int k2 = 0; k2 < 2; ++k2) {
           const TP<T> o = slice(ypC(c), k1 + k2, 100);
-          cv<4, 4, 5, 5, true>(slice(avC(a), k1, 25), slice(dtC(b), k2, 36), o, T(1), lane);
-          cv<4, 4, 5, 5, true>(slice(avC(b), k1, 25), slice(dtC(a), k2, 36), o, T(-1), lane);
+          cv<4, 4, 5, 5, true, NT>(slice(avC(a), k1, 25), slice(dtC(b), k2, 36), o, T(1), lane);
+          cv<4, 4, 5, 5, true, NT>(slice(avC(b), k1, 25), slice(dtC(a), k2, 36), o, T(-1), lane);
         }
     }
     const TP<T> e1nd = tpat(Tm, TLay::E1ND, 98);
@@ -423,30 +423,30 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
       const T* xv[3] = {ndC(0).v, ndC(1).v, ndC(2).v};
       const T* xm[3] = {ndC(0).m, ndC(1).m, ndC(2).m};
       const T ae1[3] = {G.e1.x, G.e1.y, G.e1.z};
-      combo<98, 3, false>(xv, xm, ae1, e1nd.v, e1nd.m, lane);
+      combo<98, 3, false, T, NT>(xv, xm, ae1, e1nd.v, e1nd.m, lane);
     }
     const T th_Yp = th_conv<4, 4, 5, 5>(th_A, th_dt, 4) + T(2) * eps;
     const T th_e1nd = th_nd + T(3) * eps;
     wave_sync();
     // ---- D1 = A_u.X + e1.Yp - w (beta_u n.X + beta_v e1.nd)
     const TP<T> D1 = tpat(B, TLay::D1, 600), Z1 = tpat(Tm, TLay::Z1, 200);
-    zero(D1, 600, lane);
-    zero(Z1, 200, lane);
+    zero<NT>(D1, 600, lane);
+    zero<NT>(Z1, 200, lane);
     wave_sync();
     for (int c = 0; c < 3; ++c) {
       for (int k1 = 0; k1 < 2; ++k1)
         for (int k2 = 0; k2 < 2; ++k2)
-          cv<4, 4, 5, 5, true>(slice(auC(c), k1, 25), slice(xC(c), k2, 36), slice(D1, 2 * (k1 + k2), 100), T(1),
+          cv<4, 4, 5, 5, true, NT>(slice(auC(c), k1, 25), slice(xC(c), k2, 36), slice(D1, 2 * (k1 + k2), 100), T(1),
                                lane);
       for (int j = 0; j < 2; ++j)
-        cv<4, 4, 5, 5, true>(bnuC(c), slice(xC(c), j, 36), slice(Z1, j, 100), T(1), lane);
+        cv<4, 4, 5, 5, true, NT>(bnuC(c), slice(xC(c), j, 36), slice(Z1, j, 100), T(1), lane);
     }
-    for (int j = 0; j < 2; ++j) cv<3, 3, 6, 6, true>(bv, slice(e1nd, j, 49), slice(Z1, j, 100), T(1), lane);
+    for (int j = 0; j < 2; ++j) cv<3, 3, 6, 6, true, NT>(bv, slice(e1nd, j, 49), slice(Z1, j, 100), T(1), lane);
     {
       const T ae1[3] = {G.e1.x, G.e1.y, G.e1.z};
       for (int m = 0; m < 3; ++m) {
         const TP<T> o = slice(D1, 2 * m, 100);
-        for (int idx = lane; idx < 100; idx += BBC_WAVE) {
+        for (int idx = lane; idx < 100; idx += NT) {
           T s = o.v[idx], sm = o.m[idx];
           for (int c = 0; c < 3; ++c) {
             const TP<T> y = slice(ypC(c), m, 100);
@@ -462,7 +462,7 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     const T th_D10 = max(th_conv<4, 4, 5, 5>(th_A, th_X, 12), th_Yp + T(4) * eps) + T(4) * eps;
     wave_sync();
     // D1(m, l) = D1_0(m) - w_l (Z1(m-1) + Z1(m))
-    for (int o = lane; o < 300; o += BBC_WAVE) {
+    for (int o = lane; o < 300; o += NT) {
       const int m = o / 100, idx = o - 100 * m;
       T z = T(0), zm = T(0);
       if (m >= 1) { z += Z1.v[(m - 1) * 100 + idx]; zm += Z1.m[(m - 1) * 100 + idx]; }
@@ -479,26 +479,26 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     auto bvauC = [&](int c) { return tpat(Tm, TLay::BVAU + 256 * c, 128); };
     const TP<T> D2 = tpat(B, TLay::D2, 1568), Z = tpat(Tm, TLay::Z, 588);
     for (int c = 0; c < 3; ++c)
-      for (int k = 0; k < 2; ++k) cv<3, 3, 4, 4, false>(bv, slice(auC(c), k, 25), slice(bvauC(c), k, 64), T(1), lane);
-    zero(D2, 1568, lane);
-    zero(Z, 588, lane);
+      for (int k = 0; k < 2; ++k) cv<3, 3, 4, 4, false, NT>(bv, slice(auC(c), k, 25), slice(bvauC(c), k, 64), T(1), lane);
+    zero<NT>(D2, 1568, lane);
+    zero<NT>(Z, 588, lane);
     wave_sync();
     for (int c = 0; c < 3; ++c) {
       for (int k1 = 0; k1 < 2; ++k1)
         for (int k2 = 0; k2 < 3; ++k2)
-          cv<4, 4, 9, 9, true>(slice(auC(c), k1, 25), slice(ypC(c), k2, 100), slice(D2, 2 * (k1 + k2), 196), T(1),
+          cv<4, 4, 9, 9, true, NT>(slice(auC(c), k1, 25), slice(ypC(c), k2, 100), slice(D2, 2 * (k1 + k2), 196), T(1),
                                lane);
       for (int j = 0; j < 3; ++j)
-        cv<4, 4, 9, 9, true>(bnuC(c), slice(ypC(c), j, 100), slice(Z, j, 196), T(1), lane);
+        cv<4, 4, 9, 9, true, NT>(bnuC(c), slice(ypC(c), j, 100), slice(Z, j, 196), T(1), lane);
       for (int k1 = 0; k1 < 2; ++k1)
         for (int k2 = 0; k2 < 2; ++k2)
-          cv<7, 7, 6, 6, true>(slice(bvauC(c), k1, 64), slice(ndC(c), k2, 49), slice(Z, k1 + k2, 196), T(1), lane);
+          cv<7, 7, 6, 6, true, NT>(slice(bvauC(c), k1, 64), slice(ndC(c), k2, 49), slice(Z, k1 + k2, 196), T(1), lane);
     }
     const T th_bvau = th_conv<3, 3, 4, 4>(th_bu, th_A, 1);
     const T th_Z = max(th_conv<4, 4, 9, 9>(th_bnu, th_Yp, 3), th_conv<7, 7, 6, 6>(th_bvau, th_nd, 6)) + T(2) * eps;
     const T th_D20 = th_conv<4, 4, 9, 9>(th_A, th_Yp, 6) + T(2) * eps;
     wave_sync();
-    for (int o = lane; o < 4 * 196; o += BBC_WAVE) {
+    for (int o = lane; o < 4 * 196; o += NT) {
       const int m = o / 196, idx = o - 196 * m;
       T z = T(0), zm = T(0);
       if (m >= 1) { z += Z.v[(m - 1) * 196 + idx]; zm += Z.m[(m - 1) * 196 + idx]; }
@@ -512,26 +512,26 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     const T th_D2 = max(th_D20, th_Z + T(2) * eps) + T(3) * eps;
     // ---- Q^2, Q Tn, Tn^2
     const TP<T> Q2 = tpat(B, TLay::Q2, 363), QT = tpat(B, TLay::QT, 98), T2 = tpat(B, TLay::T2, 9);
-    zero(Q2, 363, lane);
+    zero<NT>(Q2, 363, lane);
     wave_sync();
     for (int k1 = 0; k1 < 2; ++k1)
       for (int k2 = 0; k2 < 2; ++k2)
-        cv<5, 5, 5, 5, true>(slice(Q, k1, 36), slice(Q, k2, 36), slice(Q2, k1 + k2, 121), T(1), lane);
-    for (int k = 0; k < 2; ++k) cv<5, 5, 1, 1, false>(slice(Q, k, 36), Tn, slice(QT, k, 49), T(1), lane);
-    cv<1, 1, 1, 1, false>(Tn, Tn, T2, T(1), lane);
+        cv<5, 5, 5, 5, true, NT>(slice(Q, k1, 36), slice(Q, k2, 36), slice(Q2, k1 + k2, 121), T(1), lane);
+    for (int k = 0; k < 2; ++k) cv<5, 5, 1, 1, false, NT>(slice(Q, k, 36), Tn, slice(QT, k, 49), T(1), lane);
+    cv<1, 1, 1, 1, false, NT>(Tn, Tn, T2, T(1), lane);
     const T th_Q2 = th_conv<5, 5, 5, 5>(th_Q, th_Q, 2);
     const T th_QT = th_conv<5, 5, 1, 1>(th_Q, th_Tn, 1);
     const T th_T2 = th_conv<1, 1, 1, 1>(th_Tn, th_Tn, 1);
     wave_sync();
     // ---- det M = -(Q^2 D0 + Q Tn D1 + Tn^2 D2), slices (m, l) with m <= 3, l <= 1
     const TP<T> detM = tpat(Tm, TLay::DETM, 2048);
-    zero(detM, 2048, lane);
+    zero<NT>(detM, 2048, lane);
     wave_sync();
     for (int k1 = 0; k1 < 3; ++k1)
       for (int k2 = 0; k2 < 2; ++k2)
-        cv<10, 10, 5, 5, true>(slice(Q2, k1, 121), slice(D0, k2, 36), slice(detM, 2 * (k1 + k2), 256), T(-1), lane);
+        cv<10, 10, 5, 5, true, NT>(slice(Q2, k1, 121), slice(D0, k2, 36), slice(detM, 2 * (k1 + k2), 256), T(-1), lane);
     wave_sync();
-    for (int o = lane; o < 4 * 256; o += BBC_WAVE) {
+    for (int o = lane; o < 4 * 256; o += NT) {
       const int m = o / 256, idx = o - 256 * m;
       detM.v[(2 * m + 1) * 256 + idx] = detM.v[2 * m * 256 + idx];
       detM.m[(2 * m + 1) * 256 + idx] = detM.m[2 * m * 256 + idx];
@@ -540,10 +540,10 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     for (int l = 0; l < 2; ++l) {
       for (int k1 = 0; k1 < 2; ++k1)
         for (int k2 = 0; k2 < 3; ++k2)
-          cv<6, 6, 9, 9, true>(slice(QT, k1, 49), slice(D1, 2 * k2 + l, 100), slice(detM, 2 * (k1 + k2) + l, 256),
+          cv<6, 6, 9, 9, true, NT>(slice(QT, k1, 49), slice(D1, 2 * k2 + l, 100), slice(detM, 2 * (k1 + k2) + l, 256),
                                T(-1), lane);
       for (int m = 0; m < 4; ++m)
-        cv<2, 2, 13, 13, true>(T2, slice(D2, 2 * m + l, 196), slice(detM, 2 * m + l, 256), T(-1), lane);
+        cv<2, 2, 13, 13, true, NT>(T2, slice(D2, 2 * m + l, 196), slice(detM, 2 * m + l, 256), T(-1), lane);
     }
     const T th_detM = max(max(th_conv<10, 10, 5, 5>(th_Q2, th_D0, 6), th_conv<6, 6, 9, 9>(th_QT, th_D1, 6)),
                           th_conv<2, 2, 13, 13>(th_T2, th_D2, 1)) +
@@ -551,16 +551,16 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     wave_sync();
     // ---- Q^3 (xi1 degree 3) in the space of D1, D2
     const TP<T> Q3 = tpat(B, TLay::Q3, 1024);
-    zero(Q3, 1024, lane);
+    zero<NT>(Q3, 1024, lane);
     wave_sync();
     for (int k1 = 0; k1 < 3; ++k1)
       for (int k2 = 0; k2 < 2; ++k2)
-        cv<10, 10, 5, 5, true>(slice(Q2, k1, 121), slice(Q, k2, 36), slice(Q3, k1 + k2, 256), T(1), lane);
+        cv<10, 10, 5, 5, true, NT>(slice(Q2, k1, 121), slice(Q, k2, 36), slice(Q3, k1 + k2, 256), T(1), lane);
     const T th_Q3 = th_conv<10, 10, 5, 5>(th_Q2, th_Q, 6) + T(2) * eps;
     wave_sync();
     // ---- |Q^3 / det M| from the coefficients at degree (16, 16, 3, 2), raised on the fly
     const T tq3 = th_Q3 + T(8) * eps, tdm = th_detM + T(8) * eps;
-    const RB<T> rbm = ratio_bound_fn<T>(
+    const RB<T> rbm = ratio_bound_fn<T, NT>(
         4 * 3 * 289,
         [&](int o, T& p, T& ep, T& q, T& eq) {
           const int m = o / 867, r1 = o - 867 * m, l = r1 / 289, r = r1 - 289 * l, i = r / 17, j = r - 17 * i;
@@ -597,8 +597,8 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     abs_bound(rbm, &rlo, &rhi);
     // dOmega0/dA1 = |g| / h^(3/2) with g = n_g . d0 and h = d0 . d0, bounded factor-wise
     T glo, ghi, hlo, hhi;
-    poly_range<1, 1>(g.v, g.m, th_g, &glo, &ghi, lane);
-    poly_range<2, 2>(dd.v, dd.m, th_nn, &hlo, &hhi, lane);
+    poly_range<1, 1, T, NT>(g.v, g.m, th_g, &glo, &ghi, lane);
+    poly_range<2, 2, T, NT>(dd.v, dd.m, th_nn, &hlo, &hhi, lane);
     const T aglo = (glo <= T(0) && ghi >= T(0)) ? T(0) : min(fabs(glo), fabs(ghi));
     const T aghi = max(fabs(glo), fabs(ghi));
     const T Glo = down(aglo / (hhi * sqrt(hhi)));

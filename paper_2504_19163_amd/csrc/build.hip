@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(64) k_level0_t(BuildArgs a) {
   __shared__ LdsT<double, false> L;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
-    return eval_box_t<double, false>(G, u0, u1, v0, v1, true, a.flags, L, lane);
+    return eval_box_t<double, false, BBC_WAVE>(G, u0, u1, v0, v1, true, a.flags, L, lane);
   };
   for (int64_t t = blockIdx.x; t < a.n_tuples; t += gridDim.x) {
     level0_one<double>(a, uint32_t(t), ev, lane);
@@ -215,7 +215,8 @@ __global__ void __launch_bounds__(64) k_init_t(BuildArgs a) {
     const TupleGeom<double> Gd = tuple_geom<double>(a.sc, t);
     auto ev = [&](int cl, uint32_t cu, uint32_t cv) {
       const double wd = ldexp(1.0, -cl);
-      return eval_box_t<double, false>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, true, a.flags, L, lane);
+      return eval_box_t<double, false, BBC_WAVE>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, true, a.flags, L,
+                                                 lane);
     };
     init_one(a, t, ev, cur, nxt, lane);
   }
@@ -291,11 +292,14 @@ __global__ void __launch_bounds__(64) k_subdiv(BuildArgs a, int depth) {
   if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
 }
 
-__global__ void __launch_bounds__(64) k_subdiv_t(BuildArgs a, int depth) {
+// A refraction box takes ~1.5 Mflop of FP64 over ~90 KB of LDS: four waves
+// share one box so that all four SIMDs of the compute unit work on it.
+constexpr int kSubdivTThreads = 256;
+__global__ void __launch_bounds__(kSubdivTThreads) k_subdiv_t(BuildArgs a, int depth) {
   __shared__ LdsT<double, true> L;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
-    return eval_box_t<double, true>(G, u0, u1, v0, v1, true, a.flags, L, lane);
+    return eval_box_t<double, true, kSubdivTThreads>(G, u0, u1, v0, v1, true, a.flags, L, lane);
   };
   const uint32_t n = min(a.C->qcount[depth], a.q_cap);
   uint32_t boxes = 0;
@@ -372,7 +376,7 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
     a.qin = static_cast<QItem*>(b->q[d & 1].p);
     a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
     if (refr)
-      hipLaunchKernelGGL(k_subdiv_t, dim3(persistent), dim3(64), 0, s, a, d);
+      hipLaunchKernelGGL(k_subdiv_t, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTThreads), 0, s, a, d);
     else
       hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, s, a, d);
     BBC_HIP(hipGetLastError());

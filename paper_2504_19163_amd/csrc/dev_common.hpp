@@ -48,9 +48,52 @@ __device__ __forceinline__ T wave_sum(T v) {
 __device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0ull; }
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
-// One workgroup is one wave in the box kernels, so a workgroup barrier is the
-// LDS fence between the dependent steps of a box evaluation.
+// A workgroup barrier is the LDS fence between the dependent steps of a box
+// evaluation (one wave, or NT lanes of several waves, per box).
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
+
+// Reductions over the NT threads of a workgroup (NT a multiple of 64; one
+// wave needs no LDS).  Every thread must call them.
+template <int NT>
+__device__ __forceinline__ bool blk_all(bool p) {
+  if constexpr (NT == BBC_WAVE) {
+    return wave_all(p);
+  } else {
+    __shared__ int red[NT / BBC_WAVE];
+    const bool w = wave_all(p);
+    __syncthreads();
+    if ((threadIdx.x % BBC_WAVE) == 0) red[threadIdx.x / BBC_WAVE] = w ? 1 : 0;
+    __syncthreads();
+    bool r = true;
+#pragma unroll
+    for (int k = 0; k < NT / BBC_WAVE; ++k) r = r && red[k] != 0;
+    return r;
+  }
+}
+template <int NT>
+__device__ __forceinline__ bool blk_any(bool p) {
+  return !blk_all<NT>(!p);
+}
+template <int NT, class T>
+__device__ __forceinline__ T blk_min(T v) {
+  if constexpr (NT == BBC_WAVE) {
+    return wave_min(v);
+  } else {
+    __shared__ T red[NT / BBC_WAVE];
+    const T w = wave_min(v);
+    __syncthreads();
+    if ((threadIdx.x % BBC_WAVE) == 0) red[threadIdx.x / BBC_WAVE] = w;
+    __syncthreads();
+    T r = red[0];
+#pragma unroll
+    for (int k = 1; k < NT / BBC_WAVE; ++k) r = min(r, red[k]);
+    return r;
+  }
+}
+template <int NT, class T>
+__device__ __forceinline__ T blk_max(T v) {
+  return -blk_min<NT>(-v);
+}
 
 __device__ __forceinline__ float fmin_nan_safe(float a, float b) { return a < b ? a : b; }
 
