@@ -41,6 +41,29 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Algorithmic flops of one path evaluation with its Jacobian (eval_path, reflection),
 # counted from the formulas: FMA = 2 flops.
 FLOPS_PER_PATH_EVAL = 290
+# HBM traffic of one Newton launch of this workload, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the counter
+# reads for a 256 MiB device copy (FETCH_SIZE reads half the copied bytes on
+# this GPU, WRITE_SIZE all of them); see
+# profiles/query_newton_sphere131072_hbm_counters.md.  Valid only for the
+# kernel sources with this digest: reported as null once they change.
+NEWTON_COUNTERS = dict(
+    sources=["paper_2504_19163_amd/csrc/query.hip", "paper_2504_19163_amd/csrc/path_dev.hpp",
+             "paper_2504_19163_amd/csrc/geom_dev.hpp", "paper_2504_19163_amd/csrc/dev_common.hpp"],
+    sha256="957cd90688ad66cc1a21eb35d21f7e9f798676d849830130cc4bdabaf248bf60",
+    fetch_kib=43934.625, write_kib=33075.6875, fetch_scale=262144.0 / 131088.625, write_scale=1.0)
+
+
+def newton_traffic_bytes():
+    import hashlib
+    h = hashlib.sha256()
+    for f in NEWTON_COUNTERS["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != NEWTON_COUNTERS["sha256"]:
+        return None
+    c = NEWTON_COUNTERS
+    return int(round((c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024))
 
 
 def cpu_cores():
@@ -271,7 +294,8 @@ def main():
                        "p99": round(float(np.percentile(step_ms, 99)), 4)},
         "roofline": {"bound": "alu", "kernel": "query (fused kernel)" if form == "fused" else "query Newton kernel",
                      "achieved": round(achieved, 4), "peak": round(PEAK_VALU_TFLOPS, 1), "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_VALU_TFLOPS, 5), "traffic": None,
+                     "frac": round(achieved / PEAK_VALU_TFLOPS, 5),
+                     "traffic": newton_traffic_bytes() if form == "staged" else None, "traffic_unit": "HBM bytes per launch",
                      "kernel_ms": round(kms, 4), "path_evals": int(evals)},
         "work": {"leaves": info["n_leaves"], "grid_entries": info["n_grid_entries"], "pairs": qs["n_pairs"],
                  "newton_starts": qs["n_newton"], "roots": qs["n_roots"]},
