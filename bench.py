@@ -141,6 +141,46 @@ def run_served(bbc, srv, reqs, trace, arrivals=None):
     return t1 - t0, [x[1] for x in res], [x[0] for x in res]
 
 
+def refraction_section(bbc, S, torch, n_side=1024, steps=3):
+    """Single refraction through a 513 x 513-vertex water surface (524288
+    triangles, 4 lights, amplitudes scaled by 0.04), depth cap 6, 1024 x 1024
+    shading points on the pool floor, 64 samples per point: build and query
+    timed separately (inputs resident in device memory)."""
+    dev = torch.device("cuda:0")
+    sc = S.water_surface(m=512, amp_scale=0.04)
+    params = dict(max_depth=6, sigma=1e-4, alpha=2.0, grid_res=512)
+    t0 = time.perf_counter()
+    B = bbc.Bounds(bbc.DeviceScene(sc), params)
+    torch.cuda.synchronize()
+    first_build = time.perf_counter() - t0
+    pts = torch.as_tensor(S.receiver_points(sc, n_side), device=dev)
+    B.query(pts, 64, 0, mode=bbc.QUERY_STAGED)
+    torch.cuda.synchronize()
+    tb, tq = [], []
+    for k in range(steps):
+        t = time.perf_counter()
+        B.rebuild()
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        B.query(pts, 64, 1 + k, mode=bbc.QUERY_STAGED)
+        torch.cuda.synchronize()
+        tq.append(time.perf_counter() - t)
+    _, _, qs = B.query(pts, 64, 1, mode=bbc.QUERY_STAGED, host_stats=True)
+    info = B.info()
+    B.free()
+    n = pts.shape[1]
+    b, q = float(np.median(tb)), float(np.median(tq))
+    return {"workload": "single refraction, water surface 524288 triangles x 4 lights (amplitudes x 0.04), "
+                        "depth cap 6, 1024x1024 floor points, 64 samples/point",
+            "queries_s_whole_step": round(n / (b + q), 1), "build_ms": round(1e3 * b, 2),
+            "query_ms": round(1e3 * q, 2), "query_only_queries_s": round(n / q, 1),
+            "first_build_ms": round(1e3 * first_build, 1),
+            "tuples": info["n_tuples"], "live_tuples": info["n_live_tuples"], "boxes": info["n_boxes"],
+            "leaves": info["n_leaves"], "grid_entries": info["n_grid_entries"], "inf_leaves": info["n_inf_leaves"],
+            "device_bytes": info["device_bytes"], "pairs": qs["n_pairs"], "roots": qs["n_roots"]}
+
+
 def serving_section(bbc, S, torch, sphere_scene, sphere_bounds, n_req=1500, seed=5):
     """Continuous batching vs the plain per-request path on one request
     stream over device-resident bounds: the displaced sphere and a rippled
@@ -205,6 +245,7 @@ def main():
     ap.add_argument("--form", choices=["auto", "fused", "staged"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-refraction", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device tensor copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -303,6 +344,8 @@ def main():
 
     if not args.no_serving:
         out["serving"] = serving_section(bbc, S, torch, scene, B)
+    if not args.no_refraction:
+        out["refraction"] = refraction_section(bbc, S, torch)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O
