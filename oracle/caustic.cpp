@@ -53,16 +53,42 @@ struct Tuple {
   V3 q0, f1, f2;   // receiver
   double ak = 0;   // |f1 x f2| = 1 / |du_k/dx_k|
   bool front = false;  // light strictly on the front side of the triangle plane
+  // two reflections: the second triangle, x2 = p0b + u2 e1b + v2 e2b
+  V3 p0b, e1b, e2b, n0b, dn1b, dn2b, ngb;
 };
 
 static V3 col(const double* a, int64_t n, int64_t i, int row) {
   return v3(a[(row + 0) * n + i], a[(row + 1) * n + i], a[(row + 2) * n + i]);
 }
 
+// Number of tuples: emitters x triangles, and x second-surface triangles for
+// two reflections (tuple = (emitter * n_tri + t1) * n_tri2 + t2).
+static int64_t n_tuples_of(const orc_scene* s) {
+  return s->chain == 2 ? s->n_emit * s->n_tri * s->n_tri2 : s->n_emit * s->n_tri;
+}
+
+static V3 orient(V3 g, V3 nsum) { return dot(g, nsum) < 0 ? -1.0 * g : g; }
+
 static Tuple make_tuple(const orc_scene* s, int64_t tuple) {
   Tuple c;
   const int64_t n = s->n_tri;
-  const int64_t e = tuple / n, t = tuple % n;
+  int64_t first = tuple;
+  if (s->chain == 2) {
+    const int64_t t2 = tuple % s->n_tri2;
+    first = tuple / s->n_tri2;
+    const int64_t m = s->n_tri2;
+    const V3 q0 = col(s->pos2, m, t2, 0), q1 = col(s->pos2, m, t2, 3), q2 = col(s->pos2, m, t2, 6);
+    const V3 m0 = col(s->nrm2, m, t2, 0), m1 = col(s->nrm2, m, t2, 3), m2 = col(s->nrm2, m, t2, 6);
+    c.p0b = q0;
+    c.e1b = q1 - q0;
+    c.e2b = q2 - q0;
+    c.n0b = m0;
+    c.dn1b = m1 - m0;
+    c.dn2b = m2 - m0;
+    const V3 gb = cross(c.e1b, c.e2b);
+    c.ngb = orient((1.0 / norm(gb)) * gb, m0 + m1 + m2);
+  }
+  const int64_t e = first / n, t = first % n;
   c.chain = s->chain;
   c.eta = s->eta;
   const V3 p0 = col(s->pos, n, t, 0), p1 = col(s->pos, n, t, 3), p2 = col(s->pos, n, t, 6);
@@ -136,7 +162,53 @@ struct PathEval {
 // irradiance of the path E_k = I0 dOmega0/dA1 |dx1/du1| |du1/du_k| |du_k/dx_k|
 // (Sec. 4.4, Eq. eq_dwda) with dOmega0/dA1 = |n_g . d0| / |d0|^3, visibility and
 // Fresnel factors dropped (each is at most one).
+static DV operator+(DV a, DV b) { return DV{a.x + b.x, a.y + b.y, a.z + b.z}; }
+
+// Two reflections (Sec. 4.3, Eq. eq_rct applied twice): the reflected ray of
+// x1 meets the second triangle's plane at barycentric u2(u1); there it is
+// reflected again with the interpolated normal and meets the receiver.
+static PathEval eval_path_rr(const Tuple& c, double u, double v) {
+  PathEval r;
+  const DV x1 = dv_lin(c.p0, c.e1, c.e2, u, v);
+  const DV n1 = dv_lin(c.n0, c.dn1, c.dn2, u, v);
+  const DV d0 = x1 - dvc(c.x0);
+  const DV dt1 = ddot(n1, n1) * d0 - (dc(2.0) * ddot(d0, n1)) * n1;
+  const DV sb = x1 - dvc(c.p0b);
+  const DV c1 = dcross(dt1, dvc(c.e2b));
+  const D Q2 = ddot(c1, dvc(c.e1b));
+  const D u2 = ddot(c1, sb) / Q2;
+  const D v2 = ddot(dcross(sb, dvc(c.e1b)), dt1) / Q2;
+  const D s2 = ddot(dcross(sb, dvc(c.e1b)), dvc(c.e2b)) / Q2;  // x2 = x1 + s2 d~1
+  const DV x2 = dvc(c.p0b) + u2 * dvc(c.e1b) + v2 * dvc(c.e2b);
+  const DV n2 = dvc(c.n0b) + u2 * dvc(c.dn1b) + v2 * dvc(c.dn2b);
+  const DV d1 = x2 - x1;
+  const DV dt2 = ddot(n2, n2) * d1 - (dc(2.0) * ddot(d1, n2)) * n2;
+  const DV s3 = x2 - dvc(c.q0);
+  const DV c3 = dcross(dt2, dvc(c.f2));
+  const D Q3 = ddot(c3, dvc(c.f1));
+  const D uk = ddot(c3, s3) / Q3, vk = ddot(dcross(s3, dvc(c.f1)), dt2) / Q3;
+  const D t3 = ddot(dcross(s3, dvc(c.f1)), dvc(c.f2)) / Q3;
+  r.uk = uk.v;
+  r.vk = vk.v;
+  r.t = t3.v;
+  r.J[0][0] = uk.a;
+  r.J[0][1] = uk.b;
+  r.J[1][0] = vk.a;
+  r.J[1][1] = vk.b;
+  r.detJ = uk.a * vk.b - uk.b * vk.a;
+  r.x1 = v3(x1.x.v, x1.y.v, x1.z.v);
+  const V3 d = r.x1 - c.x0;
+  const double dl = norm(d);
+  r.Ek = c.I0 * std::fabs(dot(c.ng, d)) / (dl * dl * dl) * c.a1 / (std::fabs(r.detJ) * c.ak);
+  const V3 dt1v = v3(dt1.x.v, dt1.y.v, dt1.z.v);
+  bool ok = c.front && u >= 0.0 && v >= 0.0 && u + v <= 1.0 && s2.v > 0.0 && u2.v >= 0.0 && v2.v >= 0.0 &&
+            u2.v + v2.v <= 1.0 && dot(dt1v, c.ngb) < 0.0 && r.t > 0.0;
+  r.admissible = ok && std::isfinite(r.uk) && std::isfinite(r.vk);
+  return r;
+}
+
 static PathEval eval_path(const Tuple& c, double u, double v) {
+  if (c.chain == 2) return eval_path_rr(c, u, v);
   PathEval r;
   const DV x1 = dv_lin(c.p0, c.e1, c.e2, u, v);
   const DV n = dv_lin(c.n0, c.dn1, c.dn2, u, v);
@@ -256,9 +328,116 @@ static void abs_bound(const RatioBound& rb, double* lo, double* hi) {
   }
 }
 
+static BV addV(const BV& a, const BV& b) { return BV{add(a.x, b.x), add(a.y, b.y), add(a.z, b.z)}; }
+static BV vecB(const Bern& s, V3 k) { return BV{scale(s, k.x), scale(s, k.y), scale(s, k.z)}; }
+
+// Tuple construction for two reflections (Sec. 6.1 implementation): the second
+// triangle is a candidate when the bound of (x2 - x1) x d~1 covers zero, with
+// x1 over the first triangle's bounding box, x2 over the second's, and d~1 the
+// reflected direction bounded by its Bernstein coefficients over [0,1]^2; the
+// second triangle must also lie ahead along d~1 somewhere.  Plain interval
+// arithmetic on these boxes.
+static bool pair_candidate(const Tuple& c) {
+  const BV n = lin3(c.n0, c.dn1, c.dn2, 0, 1, 0, 1);
+  const BV d0 = lin3(c.p0 - c.x0, c.e1, c.e2, 0, 1, 0, 1);
+  const BV dt = subV(mulSV(dotB(n, n), d0), mulSV(scale(dotB(d0, n), 2.0), n));
+  double dl[3], dh[3];
+  coef_range(dt.x, &dl[0], &dh[0]);
+  coef_range(dt.y, &dl[1], &dh[1]);
+  coef_range(dt.z, &dl[2], &dh[2]);
+  const V3 a0 = c.p0, a1 = c.p0 + c.e1, a2 = c.p0 + c.e2;
+  const V3 b0 = c.p0b, b1 = c.p0b + c.e1b, b2 = c.p0b + c.e2b;
+  double xl[3], xh[3];  // x2 - x1 over the two bounding boxes
+  for (int k = 0; k < 3; ++k) {
+    auto cmp = [k](V3 p) { return k == 0 ? p.x : (k == 1 ? p.y : p.z); };
+    const double alo = std::min({cmp(a0), cmp(a1), cmp(a2)}), ahi = std::max({cmp(a0), cmp(a1), cmp(a2)});
+    const double blo = std::min({cmp(b0), cmp(b1), cmp(b2)}), bhi = std::max({cmp(b0), cmp(b1), cmp(b2)});
+    xl[k] = blo - ahi;
+    xh[k] = bhi - alo;
+  }
+  auto imul = [](double a, double b, double c2, double d, double* lo, double* hi) {
+    const double p[4] = {a * c2, a * d, b * c2, b * d};
+    *lo = std::min({p[0], p[1], p[2], p[3]});
+    *hi = std::max({p[0], p[1], p[2], p[3]});
+  };
+  for (int k = 0; k < 3; ++k) {
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    double pl, ph, ql, qh;
+    imul(xl[i], xh[i], dl[j], dh[j], &pl, &ph);
+    imul(xl[j], xh[j], dl[i], dh[i], &ql, &qh);
+    if (pl - qh > 0.0 || ph - ql < 0.0) return false;  // component k of the cross product cannot vanish
+  }
+  double fh = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double pl, ph;
+    imul(xl[k], xh[k], dl[k], dh[k], &pl, &ph);
+    fh += ph;
+  }
+  return fh > 0.0;
+}
+
+// Position bound of one box for two reflections: the second vertex's
+// barycentric coordinates u2 = Pu2/Q2, v2 = Pv2/Q2 (Eq. eq_rct) must meet the
+// second triangle with the ray going forward and arriving on its front side;
+// with x2 = X2/Q2 and n2 = N2/Q2, the second reflection
+// d~2 = (N2.N2) D1 - 2 (D1.N2) N2 (D1 = X2 - Q2 x1, the common factors of the
+// reflection law dropped) and the receiver coordinates u_k = Pu3/(Q3 Q2) of
+// degree (16, 16) over (15, 15).  No irradiance bound is formed for this chain:
+// E = [0, inf).
+static BoxBound bound_box_rr(const Tuple& c, double u0, double u1, double v0, double v1) {
+  BoxBound bb;
+  if (!c.front) return bb;
+  if (u0 + v0 >= 1.0) return bb;
+  const BV n = lin3(c.n0, c.dn1, c.dn2, u0, u1, v0, v1);
+  const BV d0 = lin3(c.p0 - c.x0, c.e1, c.e2, u0, u1, v0, v1);
+  const BV x1 = lin3(c.p0, c.e1, c.e2, u0, u1, v0, v1);
+  const BV sb = lin3(c.p0 - c.p0b, c.e1, c.e2, u0, u1, v0, v1);
+  const BV dt1 = subV(mulSV(dotB(n, n), d0), mulSV(scale(dotB(d0, n), 2.0), n));
+  const BV c1 = crossC(dt1, c.e2b);
+  const Bern Q2 = dotC(c1, c.e1b);
+  const Bern Pu2 = dotB(c1, sb);
+  const BV sbe1 = crossC(sb, c.e1b);
+  const Bern Pv2 = dotB(sbe1, dt1);
+  const Bern Tn2 = dotC(sbe1, c.e2b);
+  // the ray from x1 must go forward to the second triangle's plane
+  const RatioBound sr = ratio_bound(Tn2, Q2);
+  if (sr.kind == kDirect && sr.hi <= 0.0) return bb;
+  // and arrive on its front side
+  double fl, fh;
+  coef_range(dotC(dt1, c.ngb), &fl, &fh);
+  if (fl >= 0.0) return bb;
+  // u2 must meet the second triangle
+  const RatioBound ub2 = ratio_bound(Pu2, Q2), vb2 = ratio_bound(Pv2, Q2), wb2 = ratio_bound(add(Pu2, Pv2), Q2);
+  if (ub2.kind == kDirect && ub2.hi < 0.0) return bb;
+  if (vb2.kind == kDirect && vb2.hi < 0.0) return bb;
+  if (wb2.kind == kDirect && wb2.lo > 1.0) return bb;
+  const BV X2 = addV(addV(vecB(Q2, c.p0b), vecB(Pu2, c.e1b)), vecB(Pv2, c.e2b));
+  const BV N2 = addV(addV(vecB(Q2, c.n0b), vecB(Pu2, c.dn1b)), vecB(Pv2, c.dn2b));
+  const BV D1 = subV(X2, mulSV(Q2, x1));
+  const BV dt2 = subV(mulSV(dotB(N2, N2), D1), mulSV(scale(dotB(D1, N2), 2.0), N2));
+  const BV S3 = subV(X2, vecB(Q2, c.q0));
+  const BV c3 = crossC(dt2, c.f2);
+  const BV s3f1 = crossC(S3, c.f1);
+  const Bern Den = mul(dotC(c3, c.f1), Q2);
+  const Bern Pu3 = dotB(c3, S3), Pv3 = dotB(s3f1, dt2), Tn3 = dotC(s3f1, c.f2);
+  const RatioBound tb = ratio_bound(Tn3, Den);
+  if (tb.kind == kDirect && tb.hi <= 0.0) return bb;
+  const RatioBound ub = ratio_bound(Pu3, Den), vb = ratio_bound(Pv3, Den);
+  if (!clip01(ub, &bb.uk[0], &bb.uk[1])) return bb;
+  if (!clip01(vb, &bb.uk[2], &bb.uk[3])) return bb;
+  bb.universal = (ub.kind == kUnbounded) || (vb.kind == kUnbounded);
+  const bool inside2 = ub2.kind == kDirect && vb2.kind == kDirect && wb2.kind == kDirect && ub2.lo >= 0.0 &&
+                       vb2.lo >= 0.0 && wb2.hi <= 1.0 && sr.kind == kDirect && sr.lo > 0.0 && fh < 0.0;
+  bb.settled = inside2 && ub.kind == kDirect && vb.kind == kDirect && ub.lo >= 0.0 && ub.hi <= 1.0 &&
+               vb.lo >= 0.0 && vb.hi <= 1.0 && tb.kind == kDirect && tb.lo > 0.0;
+  bb.live = true;
+  return bb;
+}
+
 // Position and irradiance bound of one box of the barycentric domain of u1
 // (Sec. 4.2: U_k and [E_lo, E_hi] from coefficient ratios).
 static BoxBound bound_box(const Tuple& c, double u0, double u1, double v0, double v1, bool want_irr, int flags) {
+  if (c.chain == 2) return bound_box_rr(c, u0, u1, v0, v1);
   BoxBound bb;
   if (!c.front) return bb;
   if (u0 + v0 >= 1.0) return bb;  // box lies outside the triangle u + v <= 1
@@ -398,7 +577,7 @@ struct Build {
   int64_t boxes = 0;
   const orc_scene* scene = nullptr;  // borrowed
   // deep copies so the build owns its geometry
-  std::vector<double> pos, nrm, epos, eI;
+  std::vector<double> pos, nrm, epos, eI, pos2, nrm2;
   orc_scene sc{};
 };
 
@@ -514,8 +693,14 @@ static Build* build_all(const orc_scene* s, const orc_params* p, int n_threads) 
   B->sc.epos = B->epos.data();
   B->sc.eI = B->eI.data();
   B->scene = &B->sc;
+  if (s->chain == 2) {
+    B->pos2.assign(s->pos2, s->pos2 + 9 * s->n_tri2);
+    B->nrm2.assign(s->nrm2, s->nrm2 + 9 * s->n_tri2);
+    B->sc.pos2 = B->pos2.data();
+    B->sc.nrm2 = B->nrm2.data();
+  }
   B->n_tri = n;
-  B->n_tuples = n * s->n_emit;
+  B->n_tuples = n_tuples_of(s);
   const int64_t T = B->n_tuples;
   std::vector<std::vector<Leaf>> per(T);
   std::vector<int> has_root(T, 0);
@@ -524,6 +709,7 @@ static Build* build_all(const orc_scene* s, const orc_params* p, int n_threads) 
   parallel_for(T, n_threads, [&](int64_t t, int worker) {
     const Tuple c = make_tuple(&B->sc, t);
     if (!c.front) return;
+    if (c.chain == 2 && !pair_candidate(c)) return;
     double root[4];
     if (!init_domain(c, *p, root, &boxes[worker])) return;
     has_root[t] = 1;
@@ -743,7 +929,7 @@ using namespace orc;
 extern "C" {
 
 int orc_eval_path(const orc_scene* s, int64_t tuple, double u, double v, double* out) {
-  if (!s || !out || tuple < 0 || tuple >= s->n_tri * s->n_emit) return -1;
+  if (!s || !out || tuple < 0 || tuple >= n_tuples_of(s)) return -1;
   const Tuple c = make_tuple(s, tuple);
   const PathEval e = eval_path(c, u, v);
   out[0] = e.uk;
@@ -760,7 +946,7 @@ int orc_eval_path(const orc_scene* s, int64_t tuple, double u, double v, double*
 }
 
 int orc_box_bound(const orc_scene* s, int64_t tuple, const double* box, int want_irr, double* out) {
-  if (!s || !box || !out || tuple < 0 || tuple >= s->n_tri * s->n_emit) return -1;
+  if (!s || !box || !out || tuple < 0 || tuple >= n_tuples_of(s)) return -1;
   const Tuple c = make_tuple(s, tuple);
   const BoxBound bb = bound_box(c, box[0], box[1], box[2], box[3], want_irr != 0, 0);
   out[0] = bb.live ? 1.0 : 0.0;
@@ -772,7 +958,8 @@ int orc_box_bound(const orc_scene* s, int64_t tuple, const double* box, int want
 }
 
 void* orc_build(const orc_scene* s, const orc_params* p, int n_threads) {
-  if (!s || !p || s->chain < 0 || s->chain > 1 || p->grid_res < 1) return nullptr;
+  if (!s || !p || s->chain < 0 || s->chain > 2 || p->grid_res < 1) return nullptr;
+  if (s->chain == 2 && (!s->pos2 || !s->nrm2 || s->n_tri2 < 1)) return nullptr;
   return build_all(s, p, n_threads);
 }
 
@@ -900,7 +1087,7 @@ int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t se
 int orc_true_irradiance(const orc_scene* s, const double* pts, int64_t n, int lattice, double* E_out,
                         int n_threads) {
   if (!s || !pts || !E_out || n < 0 || lattice < 1) return -1;
-  const int64_t T = s->n_tri * s->n_emit;
+  const int64_t T = n_tuples_of(s);
   const Tuple ref = make_tuple(s, 0);
   parallel_for(n, n_threads, [&](int64_t i, int) {
     const V3 x = v3(pts[i], pts[n + i], pts[2 * n + i]);
@@ -919,7 +1106,7 @@ int orc_true_irradiance(const orc_scene* s, const double* pts, int64_t n, int la
 
 int64_t orc_tuple_roots(const orc_scene* s, int64_t tuple, const double* x, int lattice, double* roots,
                         int64_t cap) {
-  if (!s || !x || tuple < 0 || tuple >= s->n_tri * s->n_emit) return -1;
+  if (!s || !x || tuple < 0 || tuple >= n_tuples_of(s)) return -1;
   const Tuple c = make_tuple(s, tuple);
   double us, vs;
   if (!receiver_coords(c, v3(x[0], x[1], x[2]), &us, &vs)) return 0;

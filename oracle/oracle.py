@@ -130,7 +130,7 @@ class OracleScene:
         s.epos = _ptr(self.epos)
         s.eI = _ptr(self.eI)
         self.c = s
-        self.n_tuples = s.n_tri * s.n_emit
+        self.n_tuples = s.n_tri * s.n_emit * (s.n_tri2 if s.chain == 2 else 1)
 
     @property
     def ref(self):

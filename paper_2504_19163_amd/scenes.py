@@ -284,6 +284,21 @@ def facing_walls(m=64, amp=0.03, seed_offset=4):
 
 # --- tiny scenes for unit tests -------------------------------------------------
 
+def double_mirror(light=(0.1, 0.2, 1.0), upper_z=2.0, receiver_z=1.5, half=1.5):
+    """Two reflections between two parallel flat mirrors: mirror A (one large
+    triangle in z = 0, facing up) and mirror B (one large triangle in
+    z = upper_z, facing down); receiver z = receiver_z over [-half, half]^2.
+    The light's image in A and then in B is a point source at
+    (lx, ly, 2 upper_z + lz): the irradiance has a closed form."""
+    b = 6.0  # each mirror is one triangle covering x, y >= -b, x + y <= 2b
+    na = np.tile(np.array([0.0, 0.0, 1.0]), 3).reshape(9, 1)
+    nb = np.tile(np.array([0.0, 0.0, -1.0]), 3).reshape(9, 1)
+    pa = np.array([[-b, -b, 0.0], [3 * b, -b, 0.0], [-b, 3 * b, 0.0]]).reshape(9, 1)
+    pb = np.array([[-b, -b, upper_z], [-b, 3 * b, upper_z], [3 * b, -b, upper_z]]).reshape(9, 1)
+    return _scene("RR", pa, na, list(light), [1.0], [-half, -half, receiver_z], [2 * half, 0.0, 0.0],
+                  [0.0, 2 * half, 0.0], pos2=pb, nrm2=nb, name="double_mirror")
+
+
 def flat_mirror(light=(0.1, 0.2, 2.0), receiver_z=1.0, half=3.0):
     """One flat mirror triangle in z = 0 (constant normals), light above it and a
     receiver plane above the mirror.  The image-source construction gives the
