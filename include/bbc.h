@@ -55,7 +55,7 @@ typedef int32_t bbc_status;
 #define BBC_ENOMEM (-2)       /* device or host allocation failed */
 #define BBC_EBUDGET (-3)      /* serving: a request can never fit the memory budget */
 #define BBC_EDEVICE (-4)      /* HIP runtime error; text in bbc_last_error() */
-#define BBC_EUNSUPPORTED (-5) /* chain type not available */
+#define BBC_EUNSUPPORTED (-5) /* reserved: a chain type this library does not handle */
 #define BBC_EQUEUE (-6)       /* a device work queue or buffer overflowed its capacity */
 
 #define BBC_CHAIN_R 0  /* one specular reflection */
@@ -113,8 +113,16 @@ typedef struct bbc_bounds bbc_bounds;
  * The scene and emitter arrays are copied into library-owned device memory.
  * *out receives an opaque handle owned by the library until bbc_free_bounds.
  * Returns BBC_EQUEUE if a capacity in `params` order of magnitude is exceeded
- * even after the library's automatic regrowth, BBC_EUNSUPPORTED for a chain
- * this build does not handle. */
+ * even after the library's automatic regrowth.
+ *
+ * Two reflections (BBC_CHAIN_RR): tuples are (emitter, t1, t2) with t1 on
+ * the first surface and t2 on the second, numbered (emitter * n_tri + t1) *
+ * n_tri2 + t2 (below 2^32).  Tuple construction (Sec. 6.1) keeps the pairs
+ * whose interval bound of (x2 - x1) x d~1 covers zero; this costs one host
+ * synchronisation, since the pair count sizes the per-tuple buffers.  Only
+ * position bounds are formed for this chain (the irradiance denominator
+ * reaches degree 46 per axis): every leaf has E = [0, inf), so every candidate
+ * is sampled with P = 1 and the estimate is the exhaustive sum. */
 bbc_status bbc_build_bounds(const bbc_scene* scene, const bbc_emitters* emitters, const bbc_subdiv_params* params,
                             void* stream, bbc_bounds** out);
 

@@ -177,6 +177,12 @@ class DeviceScene:
         s.pos = self.pos.data_ptr()
         s.nrm = self.nrm.data_ptr()
         s.n_tri2 = 0
+        if "pos2" in scene:
+            self.pos2 = t(scene["pos2"])
+            self.nrm2 = t(scene["nrm2"])
+            s.n_tri2 = self.pos2.shape[1]
+            s.pos2 = self.pos2.data_ptr()
+            s.nrm2 = self.nrm2.data_ptr()
         s.eta = float(scene["eta"])
         for k in ("q0", "f1", "f2"):
             getattr(s, k)[:] = [float(x) for x in scene[k]]
@@ -187,7 +193,7 @@ class DeviceScene:
         e.I0 = self.eI.data_ptr()
         self.c_scene = s
         self.c_emit = e
-        self.n_tuples = s.n_tri * e.n
+        self.n_tuples = s.n_tri * e.n * (s.n_tri2 if s.n_tri2 else 1)
 
 
 class Bounds:

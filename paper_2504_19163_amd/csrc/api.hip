@@ -56,7 +56,7 @@ static void release_all(Bounds* b) {
   DevBuf* all[] = {&b->pos, &b->nrm, &b->epos, &b->eI, &b->counters, &b->root, &b->init_q, &b->l0f_q, &b->q[0],
                    &b->q[1], &b->fq, &b->lt, &b->lc, &b->lu, &b->le, &b->gl_t, &b->gl_c, &b->gl_u, &b->gl_e, &b->st, &b->sc, &b->su, &b->se, &b->tcount,
                    &b->toff, &b->tcur, &b->trip, &b->ccount, &b->coff, &b->ccur, &b->ut, &b->ue, &b->ucell, &b->gt, &b->ge,
-                   &b->scan_tmp, &b->trec,
+                   &b->scan_tmp, &b->trec, &b->pos2, &b->nrm2, &b->box2, &b->rowcount, &b->rowoff, &b->tid,
                    &b->qw_buf, &b->max_cell_dev, &b->qcounters};
   for (DevBuf* d : all) release(*d);
   b->device_bytes = 0;
@@ -72,12 +72,12 @@ static bbc_status copy_in(DevBuf& dst, const void* src, size_t bytes, int memory
 
 static bbc_status validate(const bbc_scene* sc, const bbc_emitters* em, const bbc_subdiv_params* p) {
   if (!sc || !em || !p) return invalid("null scene, emitters or params");
-  if (sc->chain != BBC_CHAIN_R && sc->chain != BBC_CHAIN_T) {
-    if (sc->chain == BBC_CHAIN_RR) {
-      set_error("two-vertex chains are not available in this build");
-      return BBC_EUNSUPPORTED;
-    }
+  if (sc->chain != BBC_CHAIN_R && sc->chain != BBC_CHAIN_T && sc->chain != BBC_CHAIN_RR)
     return invalid("unknown chain type");
+  if (sc->chain == BBC_CHAIN_RR) {
+    if (sc->n_tri2 < 1 || !sc->pos2 || !sc->nrm2) return invalid("two reflections need n_tri2 >= 1 and pos2/nrm2");
+    if (double(sc->n_tri) * double(sc->n_tri2) * double(em->n) > 4294967000.0)
+      return invalid("more than 2^32 triangle pairs");
   }
   if (sc->memory != BBC_MEM_HOST && sc->memory != BBC_MEM_DEVICE) return invalid("scene memory flag");
   if (em->memory != BBC_MEM_HOST && em->memory != BBC_MEM_DEVICE) return invalid("emitter memory flag");
@@ -100,10 +100,13 @@ static bbc_status validate(const bbc_scene* sc, const bbc_emitters* em, const bb
   return BBC_OK;
 }
 
+static bbc_status construct_pairs(Bounds* b, hipStream_t s);
+
 static bbc_status run_build(Bounds* b, hipStream_t s) {
   const int64_t G = b->params.grid_res;
   const int64_t ncell = G * G;
   bbc_status e;
+  if (b->scene.chain == BBC_CHAIN_RR && (e = construct_pairs(b, s))) return e;
   if (b->q_cap == 0) {
     b->q_cap = size_t(std::max<int64_t>(4 * b->n_tuples, 1 << 20));
     b->fq_cap = b->q_cap;
@@ -128,7 +131,7 @@ static bbc_status run_build(Bounds* b, hipStream_t s) {
         (e = ensure(b->ucell, b->trip_cap * 4, b)) || (e = ensure(b->gt, b->trip_cap * 4, b)) ||
         (e = ensure(b->ge, b->trip_cap * 4, b)) ||
         (e = ensure(b->scan_tmp, scan_tmp_bytes(std::max(ncell, b->n_tuples)) + 64, b)) ||
-        (e = ensure(b->trec, size_t(b->n_tuples) * kRecFloats * 4, b)) ||
+        (e = ensure(b->trec, size_t(std::max<int64_t>(b->n_tuples, 1)) * b->rec_floats * 4, b)) ||
         (e = ensure(b->max_cell_dev, 64, b)))
       return e;
     if ((e = launch_build(b, s))) return e;
@@ -171,6 +174,11 @@ static bbc_status load_scene(Bounds* b, const bbc_scene* sc, const bbc_emitters*
   if ((e = copy_in(b->nrm, sc->nrm, nt * 9 * 4, sc->memory, b, s))) return e;
   if ((e = copy_in(b->epos, em->pos, size_t(em->n) * 3 * 4, em->memory, b, s))) return e;
   if ((e = copy_in(b->eI, em->I0, size_t(em->n) * 4, em->memory, b, s))) return e;
+  if (sc->chain == BBC_CHAIN_RR) {
+    const size_t n2 = size_t(sc->n_tri2);
+    if ((e = copy_in(b->pos2, sc->pos2, n2 * 9 * 4, sc->memory, b, s))) return e;
+    if ((e = copy_in(b->nrm2, sc->nrm2, n2 * 9 * 4, sc->memory, b, s))) return e;
+  }
   b->params = *p;
   DevScene& d = b->scene;
   d.chain = sc->chain;
@@ -186,7 +194,42 @@ static bbc_status load_scene(Bounds* b, const bbc_scene* sc, const bbc_emitters*
     d.f1[k] = sc->f1[k];
     d.f2[k] = sc->f2[k];
   }
+  d.n_tri2 = sc->chain == BBC_CHAIN_RR ? sc->n_tri2 : 0;
+  d.pos2 = sc->chain == BBC_CHAIN_RR ? static_cast<const float*>(b->pos2.p) : nullptr;
+  d.nrm2 = sc->chain == BBC_CHAIN_RR ? static_cast<const float*>(b->nrm2.p) : nullptr;
+  d.tid = nullptr;
+  b->n_dense = sc->n_tri * em->n * (sc->chain == BBC_CHAIN_RR ? sc->n_tri2 : 1);
   b->n_tuples = sc->n_tri * em->n;
+  b->rec_floats = sc->chain == BBC_CHAIN_RR ? kRecFloatsRR : kRecFloats;
+  return BBC_OK;
+}
+
+// Tuple construction for two reflections: count the candidate pairs of every
+// (emitter, first triangle) row, scan, read the total (one host
+// synchronisation: it sizes every per-tuple buffer), and write the pairs.
+static bbc_status construct_pairs(Bounds* b, hipStream_t s) {
+  DevScene& d = b->scene;
+  const int64_t rows = d.n_emit * d.n_tri;
+  bbc_status e;
+  if ((e = ensure(b->box2, size_t(d.n_tri2) * 6 * 8, b)) || (e = ensure(b->rowcount, size_t(rows) * 4, b)) ||
+      (e = ensure(b->rowoff, size_t(rows + 1) * 4 + 8, b)) || (e = ensure(b->scan_tmp, scan_tmp_bytes(rows) + 64, b)))
+    return e;
+  double* box2 = static_cast<double*>(b->box2.p);
+  uint32_t* rc = static_cast<uint32_t*>(b->rowcount.p);
+  uint32_t* ro = static_cast<uint32_t*>(b->rowoff.p);
+  if ((e = launch_pairs(d, box2, rc, ro, nullptr, false, s))) return e;
+  if ((e = launch_scan_u32(rc, ro, rows, b->scan_tmp.p, s))) return e;
+  uint32_t total = 0;
+  BBC_HIP(hipMemcpyAsync(&total, ro + rows, 4, hipMemcpyDeviceToHost, s));
+  BBC_HIP(hipStreamSynchronize(s));
+  if ((e = ensure(b->tid, size_t(std::max<uint32_t>(total, 1)) * 4, b))) return e;
+  d.tid = static_cast<const uint32_t*>(b->tid.p);
+  if (total && (e = launch_pairs(d, box2, rc, ro, static_cast<uint32_t*>(b->tid.p), true, s))) return e;
+  b->n_tuples = total;
+  if (b->tuples_cap < total) {  // per-tuple buffers are sized by the tuple count
+    b->q_cap = 0;
+    b->tuples_cap = total;
+  }
   return BBC_OK;
 }
 
@@ -251,7 +294,7 @@ bbc_status bbc_free_bounds(bbc_bounds* h) {
 bbc_status bbc_bounds_info(const bbc_bounds* h, bbc_bounds_info_t* out) {
   if (!h || !out) return invalid("null argument");
   const Bounds* b = reinterpret_cast<const Bounds*>(h);
-  out->n_tuples = b->n_tuples;
+  out->n_tuples = b->n_dense;
   out->n_live_tuples = b->host.n_live;
   out->n_boxes = int64_t(b->host.n_boxes) + int64_t(b->host.n_fp64);
   out->n_leaves = b->n_leaves;
@@ -276,7 +319,14 @@ bbc_status bbc_export_leaves(const bbc_bounds* h, uint32_t* tuple, uint32_t* cod
     BBC_HIP(hipMemcpy(u.data(), b->su.p, n * 16, hipMemcpyDeviceToHost));
     BBC_HIP(hipMemcpy(e.data(), b->se.p, n * 8, hipMemcpyDeviceToHost));
   }
-  if (tuple) std::memcpy(tuple, t.data(), n * 4);
+  if (tuple) {
+    std::memcpy(tuple, t.data(), n * 4);
+    if (b->scene.chain == BBC_CHAIN_RR && n) {
+      std::vector<uint32_t> tid(size_t(b->n_tuples));
+      BBC_HIP(hipMemcpy(tid.data(), b->tid.p, tid.size() * 4, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < n; ++i) tuple[i] = tid[t[i]];
+    }
+  }
   if (code) std::memcpy(code, c.data(), n * 4);
   if (ukbox) std::memcpy(ukbox, u.data(), n * 16);
   if (E) std::memcpy(E, e.data(), n * 8);
@@ -303,7 +353,14 @@ bbc_status bbc_export_grid(const bbc_bounds* h, uint32_t* offsets, uint32_t* tup
   const Bounds* b = reinterpret_cast<const Bounds*>(h);
   const int64_t nc = int64_t(b->params.grid_res) * b->params.grid_res;
   if (offsets) BBC_HIP(hipMemcpy(offsets, b->coff.p, size_t(nc + 1) * 4, hipMemcpyDeviceToHost));
-  if (tuple && b->n_entries) BBC_HIP(hipMemcpy(tuple, b->gt.p, size_t(b->n_entries) * 4, hipMemcpyDeviceToHost));
+  if (tuple && b->n_entries) {
+    BBC_HIP(hipMemcpy(tuple, b->gt.p, size_t(b->n_entries) * 4, hipMemcpyDeviceToHost));
+    if (b->scene.chain == BBC_CHAIN_RR) {  // report pair numbers, ascending like the indices
+      std::vector<uint32_t> tid(size_t(b->n_tuples));
+      BBC_HIP(hipMemcpy(tid.data(), b->tid.p, tid.size() * 4, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < b->n_entries; ++i) tuple[i] = tid[tuple[i]];
+    }
+  }
   if (Et && b->n_entries) BBC_HIP(hipMemcpy(Et, b->ge.p, size_t(b->n_entries) * 4, hipMemcpyDeviceToHost));
   return BBC_OK;
 }

@@ -12,9 +12,12 @@
 //   *_fp64         the same decisions for boxes whose denominators could not
 //                  be given a sign in FP32
 //   k_*_t          the refraction chain: every box in FP64 (box_t.hpp)
+//   k_pairs_*      two reflections: tuple construction over all triangle pairs
+//   k_*_rr         two reflections: position bounds in FP64 (box_rr.hpp)
 // No host synchronisation happens between launches; every count lives in
 // device memory and every buffer has a capacity checked on the device.
 #include "box_r.hpp"
+#include "box_rr.hpp"
 #include "box_t.hpp"
 #include "internal.hpp"
 
@@ -106,6 +109,178 @@ __global__ void __launch_bounds__(64) k_level0_t(BuildArgs a) {
     level0_one<double>(a, uint32_t(t), ev, lane);
     wave_sync();
   }
+}
+
+__global__ void __launch_bounds__(64) k_level0_rr(BuildArgs a) {
+  __shared__ LdsRR<double> L;
+  const int lane = threadIdx.x;
+  auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
+    return eval_box_rr<double>(G, u0, u1, v0, v1, L, lane);
+  };
+  for (int64_t t = blockIdx.x; t < a.n_tuples; t += gridDim.x) {
+    level0_one<double>(a, uint32_t(t), ev, lane);
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------- tuple construction, two reflections
+// A second-surface triangle joins a first-surface triangle's tuple when the
+// interval bound of (x2 - x1) x d~1 covers zero in every component and
+// (x2 - x1) . d~1 can be positive, with x1 and x2 over the triangles' bounding
+// boxes and d~1 the reflected direction bounded by its Bernstein coefficients
+// over [0,1]^2 (Sec. 6.1, tuple construction).  The light must be in front of
+// the first triangle.  Plain FP64 interval arithmetic.
+struct PairArgs {
+  DevScene sc;
+  const double* box2;  // [6][n_tri2]: lo xyz, hi xyz of every second-surface triangle
+  uint32_t* rowcount;  // [n_emit * n_tri]
+  const uint32_t* rowoff;
+  uint32_t* tid;
+};
+
+__global__ void k_pair_boxes(DevScene sc, double* box2) {
+  const int64_t n = sc.n_tri2;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
+    for (int k = 0; k < 3; ++k) {
+      const double a = sc.pos2[k * n + t], b = sc.pos2[(3 + k) * n + t], c = sc.pos2[(6 + k) * n + t];
+      box2[k * n + t] = fmin(a, fmin(b, c));
+      box2[(3 + k) * n + t] = fmax(a, fmax(b, c));
+    }
+  }
+}
+
+struct PairRow {
+  bool front;
+  double alo[3], ahi[3], dlo[3], dhi[3];
+};
+
+// Bounding box of the first triangle and coefficient ranges of d~1 over
+// [0,1]^2, in scaled Bernstein form (one thread).
+__device__ PairRow pair_row(const DevScene& sc, int64_t row) {
+  PairRow r;
+  const int64_t n = sc.n_tri, t = row % n, e = row / n;
+  const TupleGeom<double> G = tuple_geom_first<double>(sc, t, e);
+  r.front = G.front;
+  const V3<double> a0 = G.p0, a1 = G.p0 + G.e1, a2 = G.p0 + G.e2;
+  for (int k = 0; k < 3; ++k) {
+    r.alo[k] = fmin(comp(a0, k), fmin(comp(a1, k), comp(a2, k)));
+    r.ahi[k] = fmax(comp(a0, k), fmax(comp(a1, k), comp(a2, k)));
+  }
+  // corner values (index 2 iu + iv) of n and d0; degree (1,1) scaled = plain
+  double nc[3][4], dc[3][4];
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < 4; ++k) {
+      const double u = (k & 2) ? 1.0 : 0.0, v = (k & 1) ? 1.0 : 0.0;
+      nc[c][k] = comp(G.n0, c) + u * comp(G.dn1, c) + v * comp(G.dn2, c);
+      dc[c][k] = comp(G.p0 - G.x0, c) + u * comp(G.e1, c) + v * comp(G.e2, c);
+    }
+  double nn[9] = {0}, dn[9] = {0};
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        const int i = (a >> 1) + (b >> 1), j = (a & 1) + (b & 1);
+        nn[3 * i + j] += nc[c][a] * nc[c][b];
+        dn[3 * i + j] += dc[c][a] * nc[c][b];
+      }
+  for (int c = 0; c < 3; ++c) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i <= 3; ++i)
+      for (int j = 0; j <= 3; ++j) {
+        double sv = 0.0;
+        for (int a = 0; a <= 2; ++a)
+          for (int b = 0; b <= 2; ++b) {
+            const int di = i - a, dj = j - b;
+            if (di < 0 || di > 1 || dj < 0 || dj > 1) continue;
+            sv += nn[3 * a + b] * dc[c][2 * di + dj] - 2.0 * dn[3 * a + b] * nc[c][2 * di + dj];
+          }
+        const double bc = sv / double(binom_i(3, i) * binom_i(3, j));
+        lo = fmin(lo, bc);
+        hi = fmax(hi, bc);
+      }
+    r.dlo[c] = lo;
+    r.dhi[c] = hi;
+  }
+  return r;
+}
+
+__device__ __forceinline__ void imul(double a, double b, double c, double d, double* lo, double* hi) {
+  const double p0 = a * c, p1 = a * d, p2 = b * c, p3 = b * d;
+  *lo = fmin(fmin(p0, p1), fmin(p2, p3));
+  *hi = fmax(fmax(p0, p1), fmax(p2, p3));
+}
+
+__device__ __forceinline__ bool pair_test(const PairRow& r, const double* box2, int64_t n2, int64_t t2) {
+  double xl[3], xh[3];
+  for (int k = 0; k < 3; ++k) {
+    xl[k] = box2[k * n2 + t2] - r.ahi[k];
+    xh[k] = box2[(3 + k) * n2 + t2] - r.alo[k];
+  }
+  for (int k = 0; k < 3; ++k) {
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    double pl, ph, ql, qh;
+    imul(xl[i], xh[i], r.dlo[j], r.dhi[j], &pl, &ph);
+    imul(xl[j], xh[j], r.dlo[i], r.dhi[i], &ql, &qh);
+    if (pl - qh > 0.0 || ph - ql < 0.0) return false;
+  }
+  double fh = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double pl, ph;
+    imul(xl[k], xh[k], r.dlo[k], r.dhi[k], &pl, &ph);
+    fh += ph;
+  }
+  return fh > 0.0;
+}
+
+constexpr int kPairThreads = 256;
+
+// fill = false: count the candidates of every row; fill = true: write their
+// tuple numbers in ascending order at the row's offset.
+__global__ void __launch_bounds__(kPairThreads) k_pairs(PairArgs a, int fill) {
+  __shared__ PairRow R;
+  __shared__ uint32_t wsum[kPairThreads / BBC_WAVE];
+  const int64_t rows = a.sc.n_emit * a.sc.n_tri, n2 = a.sc.n_tri2;
+  const int lane = threadIdx.x % BBC_WAVE, w = threadIdx.x / BBC_WAVE;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    if (threadIdx.x == 0) R = pair_row(a.sc, row);
+    __syncthreads();
+    const PairRow r = R;
+    uint32_t base = fill ? a.rowoff[row] : 0u, count = 0;
+    for (int64_t c0 = 0; c0 < n2; c0 += kPairThreads) {
+      const int64_t t2 = c0 + threadIdx.x;
+      const bool pass = r.front && t2 < n2 && pair_test(r, a.box2, n2, t2);
+      const uint64_t m = __ballot(pass);
+      if (lane == 0) wsum[w] = uint32_t(__popcll(m));
+      __syncthreads();
+      uint32_t before = 0, total = 0;
+      for (int k = 0; k < kPairThreads / BBC_WAVE; ++k) {
+        if (k < w) before += wsum[k];
+        total += wsum[k];
+      }
+      if (fill && pass) {
+        const uint32_t rank = before + uint32_t(__popcll(m & ((1ull << lane) - 1ull)));
+        a.tid[base + count + rank] = uint32_t(row * n2 + t2);
+      }
+      count += total;
+      __syncthreads();
+    }
+    if (!fill && threadIdx.x == 0) a.rowcount[row] = count;
+    __syncthreads();
+  }
+}
+
+bbc_status launch_pairs(const DevScene& sc, double* box2, uint32_t* rowcount, const uint32_t* rowoff, uint32_t* tid,
+                        bool fill, hipStream_t s) {
+  const int64_t rows = sc.n_emit * sc.n_tri;
+  if (!fill) {
+    hipLaunchKernelGGL(k_pair_boxes, dim3(unsigned(std::min<int64_t>((sc.n_tri2 + 255) / 256, 1024))), dim3(256),
+                       0, s, sc, box2);
+    BBC_HIP(hipGetLastError());
+  }
+  PairArgs a{sc, box2, rowcount, rowoff, tid};
+  hipLaunchKernelGGL(k_pairs, dim3(unsigned(std::min<int64_t>(rows, 8192))), dim3(kPairThreads), 0, s, a,
+                     fill ? 1 : 0);
+  BBC_HIP(hipGetLastError());
+  return BBC_OK;
 }
 
 // Domain initialisation (Sec. 6.1): breadth-first refinement of [0,1]^2 that
@@ -205,6 +380,22 @@ __global__ void __launch_bounds__(64) k_init(BuildArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(64) k_init_rr(BuildArgs a) {
+  __shared__ LdsRR<double> L;
+  __shared__ InitBox cur[kInitCap], nxt[kInitCap];
+  const int lane = threadIdx.x;
+  const uint32_t n = a.C->n_init;
+  for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const uint32_t t = a.init_q[it];
+    const TupleGeom<double> Gd = tuple_geom<double>(a.sc, t);
+    auto ev = [&](int cl, uint32_t cu, uint32_t cv) {
+      const double wd = ldexp(1.0, -cl);
+      return eval_box_rr<double>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, L, lane);
+    };
+    init_one(a, t, ev, cur, nxt, lane);
+  }
+}
+
 __global__ void __launch_bounds__(64) k_init_t(BuildArgs a) {
   __shared__ LdsT<double, false> L;
   __shared__ InitBox cur[kInitCap], nxt[kInitCap];
@@ -292,6 +483,21 @@ __global__ void __launch_bounds__(64) k_subdiv(BuildArgs a, int depth) {
   if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
 }
 
+__global__ void __launch_bounds__(64) k_subdiv_rr(BuildArgs a, int depth) {
+  __shared__ LdsRR<double> L;
+  const int lane = threadIdx.x;
+  auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
+    return eval_box_rr<double>(G, u0, u1, v0, v1, L, lane);
+  };
+  const uint32_t n = min(a.C->qcount[depth], a.q_cap);
+  uint32_t boxes = 0;
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    subdiv_one<double>(a, a.qin[i], depth, ev, lane, &boxes);
+    wave_sync();
+  }
+  if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
+}
+
 // A refraction box takes ~1.5 Mflop of FP64 over ~90 KB of LDS: four waves
 // share one box so that all four SIMDs of the compute unit work on it.
 constexpr int kSubdivTThreads = 256;
@@ -355,9 +561,11 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   if (st) return st;
   a.qin = nullptr;
   a.qout = static_cast<QItem*>(b->q[0].p);
-  const unsigned g0 = unsigned(std::min<int64_t>(b->n_tuples, int64_t(n_cu) * 64));
-  const bool refr = b->scene.chain == BBC_CHAIN_T;
-  if (refr) {
+  const unsigned g0 = unsigned(std::max<int64_t>(1, std::min<int64_t>(b->n_tuples, int64_t(n_cu) * 64)));
+  const bool refr = b->scene.chain == BBC_CHAIN_T, rr = b->scene.chain == BBC_CHAIN_RR;
+  if (rr) {
+    hipLaunchKernelGGL(k_level0_rr, dim3(g0), dim3(64), 0, s, a);
+  } else if (refr) {
     hipLaunchKernelGGL(k_level0_t, dim3(g0), dim3(64), 0, s, a);
   } else {
     hipLaunchKernelGGL(k_level0, dim3(g0), dim3(64), 0, s, a);
@@ -366,7 +574,9 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   }
   BBC_HIP(hipGetLastError());
   if (a.init_levels > 0) {
-    if (refr)
+    if (rr)
+      hipLaunchKernelGGL(k_init_rr, dim3(persistent), dim3(64), 0, s, a);
+    else if (refr)
       hipLaunchKernelGGL(k_init_t, dim3(persistent), dim3(64), 0, s, a);
     else
       hipLaunchKernelGGL(k_init, dim3(persistent), dim3(64), 0, s, a);
@@ -375,7 +585,9 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   for (int d = 0; d <= a.max_depth; ++d) {
     a.qin = static_cast<QItem*>(b->q[d & 1].p);
     a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
-    if (refr)
+    if (rr)
+      hipLaunchKernelGGL(k_subdiv_rr, dim3(persistent), dim3(64), 0, s, a, d);
+    else if (refr)
       hipLaunchKernelGGL(k_subdiv_t, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTThreads), 0, s, a, d);
     else
       hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, s, a, d);

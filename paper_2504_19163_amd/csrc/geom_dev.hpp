@@ -49,6 +49,12 @@ struct DevScene {
   const float* eI;    // [n_emit]
   float eta;
   float q0[3], f1[3], f2[3];
+  // two reflections: the second surface, and the candidate pairs that survived
+  // tuple construction (tuple k is tid[k] = (emitter * n_tri + t1) * n_tri2 + t2)
+  int64_t n_tri2;
+  const float* pos2;  // [9][n_tri2]
+  const float* nrm2;  // [9][n_tri2]
+  const uint32_t* tid;
 };
 
 // Constants of one (emitter, triangle) tuple.  Barycentric parameterisation of
@@ -59,6 +65,8 @@ struct TupleGeom {
   V3<T> p0, e1, e2, n0, dn1, dn2, x0, q0, f1, f2, ng;
   T I0, a1, ak, eta;
   bool front;  // light strictly in front of the triangle plane (n_g oriented with the vertex normals)
+  // two reflections: x2 = p0b + u2 e1b + v2 e2b, n2 likewise, ngb oriented like ng
+  V3<T> p0b, e1b, e2b, n0b, dn1b, dn2b, ngb;
 };
 
 __device__ __forceinline__ V3<float> load3(const float* a, int64_t n, int64_t i, int row) {
@@ -71,15 +79,29 @@ __device__ __forceinline__ V3<T> cvt3(V3<float> a) {
 }
 
 template <class T>
-__device__ TupleGeom<T> tuple_geom(const DevScene& s, uint32_t tuple) {
-  const int64_t t = int64_t(tuple) % s.n_tri, e = int64_t(tuple) / s.n_tri;
+__device__ __forceinline__ void second_triangle(TupleGeom<T>& g, V3<T> q0, V3<T> q1, V3<T> q2, V3<T> m0, V3<T> m1,
+                                                V3<T> m2) {
+  g.p0b = q0;
+  g.e1b = q1 - q0;
+  g.e2b = q2 - q0;
+  g.n0b = m0;
+  g.dn1b = m1 - m0;
+  g.dn2b = m2 - m0;
+  const V3<T> c = cross(g.e1b, g.e2b);
+  g.ngb = (T(1) / sqrt(dot(c, c))) * c;
+  if (dot(g.ngb, m0 + m1 + m2) < T(0)) g.ngb = T(-1) * g.ngb;
+}
+
+// The first-surface part of a tuple: triangle t lit by emitter e.
+template <class T>
+__device__ TupleGeom<T> tuple_geom_first(const DevScene& s, int64_t t, int64_t e) {
+  TupleGeom<T> g;
   const V3<T> p0 = cvt3<T>(load3(s.pos, s.n_tri, t, 0));
   const V3<T> p1 = cvt3<T>(load3(s.pos, s.n_tri, t, 3));
   const V3<T> p2 = cvt3<T>(load3(s.pos, s.n_tri, t, 6));
   const V3<T> n0 = cvt3<T>(load3(s.nrm, s.n_tri, t, 0));
   const V3<T> n1 = cvt3<T>(load3(s.nrm, s.n_tri, t, 3));
   const V3<T> n2 = cvt3<T>(load3(s.nrm, s.n_tri, t, 6));
-  TupleGeom<T> g;
   g.p0 = p0;
   g.e1 = p1 - p0;
   g.e2 = p2 - p0;
@@ -102,13 +124,31 @@ __device__ TupleGeom<T> tuple_geom(const DevScene& s, uint32_t tuple) {
   return g;
 }
 
-// Packed per-tuple record read by the query stage (one 128-byte line pair per
+// Tuple `tuple` of the scene: emitter * n_tri + triangle for one vertex; for
+// two reflections the index of a constructed pair, whose number tid[tuple] is
+// (emitter * n_tri + t1) * n_tri2 + t2.
+template <class T>
+__device__ TupleGeom<T> tuple_geom(const DevScene& s, uint32_t tuple) {
+  if (s.chain != 2) return tuple_geom_first<T>(s, int64_t(tuple) % s.n_tri, int64_t(tuple) / s.n_tri);
+  const uint32_t dense = s.tid[tuple];
+  const int64_t t2 = int64_t(dense) % s.n_tri2, m = s.n_tri2, first = int64_t(dense) / s.n_tri2;
+  TupleGeom<T> g = tuple_geom_first<T>(s, first % s.n_tri, first / s.n_tri);
+  second_triangle<T>(g, cvt3<T>(load3(s.pos2, m, t2, 0)), cvt3<T>(load3(s.pos2, m, t2, 3)),
+                     cvt3<T>(load3(s.pos2, m, t2, 6)), cvt3<T>(load3(s.nrm2, m, t2, 0)),
+                     cvt3<T>(load3(s.nrm2, m, t2, 3)), cvt3<T>(load3(s.nrm2, m, t2, 6)));
+  return g;
+}
+
+// Packed per-tuple record read by the query stage (one 128-byte line per
 // tuple instead of eighteen scattered structure-of-arrays loads):
 //   [0..8] p0 p1 p2, [9..17] n0 n1 n2, [18..20] x0, [21] I0,
-//   [22] first leaf, [23] end leaf (as uint bits), [24..27] root box, [28..31] 0.
+//   [22] first leaf, [23] end leaf (as uint bits), [24..27] root box, [28..31] 0;
+// two reflections append the second triangle: [28..36] p0 p1 p2, [37..45] n0 n1
+// n2, [46..47] 0 (192 bytes).
 constexpr int kRecFloats = 32;
+constexpr int kRecFloatsRR = 48;
 
-template <class T>
+template <class T, bool RR = false>
 __device__ __forceinline__ TupleGeom<T> tuple_geom_rec(const float* rec, const DevScene& s) {
   const V3<T> p0 = mk(T(rec[0]), T(rec[1]), T(rec[2]));
   const V3<T> p1 = mk(T(rec[3]), T(rec[4]), T(rec[5]));
@@ -136,6 +176,10 @@ __device__ __forceinline__ TupleGeom<T> tuple_geom_rec(const float* rec, const D
   g.ak = sqrt(dot(fk, fk));
   g.eta = T(s.eta);
   g.front = dot(g.x0 - p0, g.ng) > T(0);
+  if constexpr (RR)
+    second_triangle<T>(g, mk(T(rec[28]), T(rec[29]), T(rec[30])), mk(T(rec[31]), T(rec[32]), T(rec[33])),
+                       mk(T(rec[34]), T(rec[35]), T(rec[36])), mk(T(rec[37]), T(rec[38]), T(rec[39])),
+                       mk(T(rec[40]), T(rec[41]), T(rec[42])), mk(T(rec[43]), T(rec[44]), T(rec[45])));
   return g;
 }
 

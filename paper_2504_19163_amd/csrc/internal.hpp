@@ -82,9 +82,15 @@ struct Bounds {
   Tuning tune;
   bbc_subdiv_params params{};
   DevScene scene{};       // device pointers into the buffers below
-  int64_t n_tuples = 0;
+  int64_t n_tuples = 0;   // tuples the build works on (constructed pairs for two reflections)
+  int64_t n_dense = 0;    // emitters x triangles (x second-surface triangles)
+  int64_t tuples_cap = 0;
+  int rec_floats = kRecFloats;
   // scene copies
-  DevBuf pos, nrm, epos, eI;
+  DevBuf pos, nrm, epos, eI, pos2, nrm2;
+  // tuple construction (two reflections): second-surface boxes, per-row counts
+  // and offsets, pair numbers
+  DevBuf box2, rowcount, rowoff, tid;
   // build work space
   DevBuf counters;        // BuildCounters
   DevBuf root;            // float4 [n_tuples]
@@ -138,6 +144,8 @@ bbc_status launch_record(Bounds* b, hipStream_t s);
 bbc_status launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
 bbc_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+bbc_status launch_pairs(const DevScene& sc, double* box2, uint32_t* rowcount, const uint32_t* rowoff, uint32_t* tid,
+                        bool fill, hipStream_t s);
 bbc_status launch_query(const Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
                         int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t s);
 bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,

@@ -12,7 +12,101 @@ struct PathT {
   T J00, J01, J10, J11, det;  // d(u_k, v_k) / d(u, v)
   T dn, beta;
   V3<T> x1;
+  T s2, u2, v2, f2;  // two reflections: ray parameter and barycentrics of x2, d~1 . n_g2
 };
+
+// Value and partial derivatives in (u, v) (forward differentiation).
+template <class T>
+struct Dl {
+  T v, a, b;
+};
+template <class T>
+__device__ __forceinline__ Dl<T> operator+(Dl<T> x, Dl<T> y) { return Dl<T>{x.v + y.v, x.a + y.a, x.b + y.b}; }
+template <class T>
+__device__ __forceinline__ Dl<T> operator-(Dl<T> x, Dl<T> y) { return Dl<T>{x.v - y.v, x.a - y.a, x.b - y.b}; }
+template <class T>
+__device__ __forceinline__ Dl<T> operator*(Dl<T> x, Dl<T> y) {
+  return Dl<T>{x.v * y.v, x.a * y.v + x.v * y.a, x.b * y.v + x.v * y.b};
+}
+template <class T>
+__device__ __forceinline__ Dl<T> operator*(T s, Dl<T> x) { return Dl<T>{s * x.v, s * x.a, s * x.b}; }
+template <class T>
+__device__ __forceinline__ Dl<T> operator/(Dl<T> x, Dl<T> y) {
+  const T q = x.v / y.v, iy = T(1) / y.v;
+  return Dl<T>{q, (x.a - q * y.a) * iy, (x.b - q * y.b) * iy};
+}
+template <class T>
+struct DV {
+  Dl<T> x, y, z;
+};
+template <class T>
+__device__ __forceinline__ DV<T> dlin(V3<T> base, V3<T> du, V3<T> dv, T u, T v) {
+  return DV<T>{Dl<T>{base.x + u * du.x + v * dv.x, du.x, dv.x}, Dl<T>{base.y + u * du.y + v * dv.y, du.y, dv.y},
+               Dl<T>{base.z + u * du.z + v * dv.z, du.z, dv.z}};
+}
+template <class T>
+__device__ __forceinline__ DV<T> dconst(V3<T> a) {
+  return DV<T>{Dl<T>{a.x, T(0), T(0)}, Dl<T>{a.y, T(0), T(0)}, Dl<T>{a.z, T(0), T(0)}};
+}
+template <class T>
+__device__ __forceinline__ DV<T> operator+(DV<T> a, DV<T> b) { return DV<T>{a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class T>
+__device__ __forceinline__ DV<T> operator-(DV<T> a, DV<T> b) { return DV<T>{a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class T>
+__device__ __forceinline__ DV<T> operator*(Dl<T> s, DV<T> a) { return DV<T>{s * a.x, s * a.y, s * a.z}; }
+template <class T>
+__device__ __forceinline__ Dl<T> ddot(DV<T> a, DV<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T>
+__device__ __forceinline__ Dl<T> ddotc(DV<T> a, V3<T> k) { return k.x * a.x + k.y * a.y + k.z * a.z; }
+template <class T>
+__device__ __forceinline__ DV<T> dcrossc(DV<T> a, V3<T> k) {  // a x k, k constant
+  return DV<T>{k.z * a.y - k.y * a.z, k.x * a.z - k.z * a.x, k.y * a.x - k.x * a.y};
+}
+template <class T>
+__device__ __forceinline__ DV<T> dscale(DV<T> a, Dl<T> s) { return s * a; }
+
+// Two reflections: Eq. eq_rct maps x1 and the reflected direction d~1 to the
+// barycentrics u2 of the second vertex, whose interpolated normal reflects
+// d1 = x2 - x1 into d~2, and Eq. eq_rct again maps (x2, d~2) to the receiver.
+template <class T>
+__device__ PathT<T> eval_path_rr(const TupleGeom<T>& G, T u, T v) {
+  PathT<T> r;
+  const DV<T> x1 = dlin(G.p0, G.e1, G.e2, u, v);
+  const DV<T> n1 = dlin(G.n0, G.dn1, G.dn2, u, v);
+  const DV<T> d0 = x1 - dconst(G.x0);
+  const Dl<T> two{T(2), T(0), T(0)};
+  const DV<T> dt1 = ddot(n1, n1) * d0 - (two * ddot(d0, n1)) * n1;
+  const DV<T> sb = x1 - dconst(G.p0b);
+  const DV<T> c1 = dcrossc(dt1, G.e2b);
+  const DV<T> sbe1 = dcrossc(sb, G.e1b);
+  const Dl<T> Q2 = ddotc(c1, G.e1b);
+  const Dl<T> u2 = ddot(c1, sb) / Q2, v2 = ddot(sbe1, dt1) / Q2, s2 = ddotc(sbe1, G.e2b) / Q2;
+  const DV<T> x2 = dconst(G.p0b) + u2 * dconst(G.e1b) + v2 * dconst(G.e2b);
+  const DV<T> n2 = dconst(G.n0b) + u2 * dconst(G.dn1b) + v2 * dconst(G.dn2b);
+  const DV<T> d1 = x2 - x1;
+  const DV<T> dt2 = ddot(n2, n2) * d1 - (two * ddot(d1, n2)) * n2;
+  const DV<T> s3 = x2 - dconst(G.q0);
+  const DV<T> c3 = dcrossc(dt2, G.f2);
+  const DV<T> s3f1 = dcrossc(s3, G.f1);
+  const Dl<T> Q3 = ddotc(c3, G.f1);
+  const Dl<T> uk = ddot(c3, s3) / Q3, vk = ddot(s3f1, dt2) / Q3, t3 = ddotc(s3f1, G.f2) / Q3;
+  r.uk = uk.v;
+  r.vk = vk.v;
+  r.t = t3.v;
+  r.J00 = uk.a;
+  r.J01 = uk.b;
+  r.J10 = vk.a;
+  r.J11 = vk.b;
+  r.det = r.J00 * r.J11 - r.J01 * r.J10;
+  r.dn = T(0);
+  r.beta = T(1);
+  r.x1 = mk(x1.x.v, x1.y.v, x1.z.v);
+  r.s2 = s2.v;
+  r.u2 = u2.v;
+  r.v2 = v2.v;
+  r.f2 = dt1.x.v * G.ngb.x + dt1.y.v * G.ngb.y + dt1.z.v * G.ngb.z;
+  return r;
+}
 
 // Receiver coordinates of the path through barycentric (u, v) and their
 // Jacobian, by forward differentiation of the rational map of Eq. eq_rct with
@@ -20,6 +114,7 @@ struct PathT {
 // chain 1: refraction).
 template <class T>
 __device__ __forceinline__ PathT<T> eval_path(const TupleGeom<T>& G, int chain, T u, T v) {
+  if (chain == 2) return eval_path_rr<T>(G, u, v);
   PathT<T> r;
   const V3<T> x1 = G.p0 + u * G.e1 + v * G.e2;
   const V3<T> n = G.n0 + u * G.dn1 + v * G.dn2;
@@ -66,12 +161,16 @@ __device__ __forceinline__ PathT<T> eval_path(const TupleGeom<T>& G, int chain, 
 }
 
 // Admissible specular path: inside the closed triangle, the receiver ahead of
-// the specular vertex, and for refraction no total internal reflection with
-// light arriving on the front of the shading normal.
+// the specular vertex, for refraction no total internal reflection with light
+// arriving on the front of the shading normal, and for two reflections the
+// second vertex inside its closed triangle, ahead of the first and reached on
+// its front side.
 template <class T>
 __device__ __forceinline__ bool admissible(const TupleGeom<T>& G, int chain, const PathT<T>& p, T u, T v) {
   bool ok = G.front && u >= T(0) && v >= T(0) && u + v <= T(1) && p.t > T(0) && isfinite(p.uk) && isfinite(p.vk);
   if (chain == 1) ok = ok && p.beta > T(0) && p.dn < T(0);
+  if (chain == 2)
+    ok = ok && p.s2 > T(0) && p.u2 >= T(0) && p.v2 >= T(0) && p.u2 + p.v2 <= T(1) && p.f2 < T(0);
   return ok;
 }
 

@@ -41,7 +41,13 @@ struct QueryArgs {
   // preq[i]; nullable, then every point uses W, seed and base above
   const uint16_t* preq;
   const ReqDesc* reqs;
+  // two reflections: the grid holds indices of constructed pairs; the random
+  // stream is keyed by the pair number tid[T]
+  const uint32_t* tid;
+  int rec_floats;
 };
+
+__device__ __forceinline__ uint32_t tuple_key(const QueryArgs& a, uint32_t T) { return a.tid ? a.tid[T] : T; }
 
 struct PointReq {
   float W;
@@ -153,11 +159,14 @@ __device__ __forceinline__ float select_prob(float e, float gamma, bool exhausti
 // (deterministic initialisation, Sec. 6.1): FP32 iterations that abandon a
 // start leaving its box by more than one width, then two FP64 steps; a root is
 // accepted when its FP64 residual on the receiver is below 1e-6 scene units.
+template <int CH>
 __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target& tg, WorkCount& wc) {
-  float rec[kRecFloats];
-  const float4* r4 = reinterpret_cast<const float4*>(a.rec + size_t(T) * kRecFloats);
+  constexpr bool RR = CH == BBC_CHAIN_RR;
+  constexpr int NF = RR ? kRecFloatsRR : kRecFloats, NL = RR ? 12 : 7;
+  float rec[NF];
+  const float4* r4 = reinterpret_cast<const float4*>(a.rec + size_t(T) * NF);
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
+  for (int k = 0; k < NL; ++k) {
     const float4 q = r4[k];
     rec[4 * k] = q.x;
     rec[4 * k + 1] = q.y;
@@ -166,8 +175,8 @@ __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target&
   }
   const uint32_t lb = __float_as_uint(rec[22]), le = __float_as_uint(rec[23]);
   if (lb == le) return 0.0;
-  const int chain = a.sc.chain;
-  const TupleGeom<float> Gf = tuple_geom_rec<float>(rec, a.sc);
+  constexpr int chain = CH;
+  const TupleGeom<float> Gf = tuple_geom_rec<float, RR>(rec, a.sc);
   const float rx = rec[24], ry = rec[25], rz = rec[26], rw = rec[27];
   double ru0 = 0, rv0 = 0, ru1 = 0, rv1 = 0, ru2 = 0, rv2 = 0, ru3 = 0, rv3 = 0;
   int nr = 0;
@@ -217,7 +226,7 @@ __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target&
     // receiver cannot become admissible in the polish (margin 1e-3 >> FP32 error)
     if (!(u >= -1e-3f && v >= -1e-3f && u + v <= 1.f + 1e-3f) || !(t_last > 0.f)) continue;
     // FP64 polish
-    const TupleGeom<double> Gd = tuple_geom_rec<double>(rec, a.sc);
+    const TupleGeom<double> Gd = tuple_geom_rec<double, RR>(rec, a.sc);
     double ud = u, vd = v;
     ++wc.it64;  // FP64 path evaluations
     PathT<double> p = eval_path<double>(Gd, chain, ud, vd);
@@ -267,7 +276,7 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, int lane) {
 // order, so the estimate is bit-identical to the staged form.
 constexpr int kPairCap = 512;
 
-template <int kWaves, int kTile>
+template <int kWaves, int kTile, int CH>
 __global__ void __launch_bounds__(64, kWaves) k_query_fused(QueryArgs a) {
   __shared__ uint32_t s_t[kPairCap];
   __shared__ float s_p[kPairCap];
@@ -305,7 +314,7 @@ __global__ void __launch_bounds__(64, kWaves) k_query_fused(QueryArgs a) {
       const float e = Et[j];
       const float P = select_prob(e, gamma, exhaustive);
       if (P > 0.f && isfinite(e)) mu2 += double(e) * double(e) / double(P);
-      cnt += selection_uniform(pr.seed, key, Tt[j]) < P ? 1u : 0u;
+      cnt += selection_uniform(pr.seed, key, tuple_key(a, Tt[j])) < P ? 1u : 0u;
     }
     const uint32_t off = wave_excl_scan(cnt, lane);
     const uint32_t total = __shfl(off + cnt, BBC_WAVE - 1, BBC_WAVE);
@@ -318,7 +327,7 @@ __global__ void __launch_bounds__(64, kWaves) k_query_fused(QueryArgs a) {
         const float e = Et[cur];
         const uint32_t T = Tt[cur];
         const float P = select_prob(e, gamma, exhaustive);
-        if (selection_uniform(pr.seed, key, T) < P) {
+        if (selection_uniform(pr.seed, key, tuple_key(a, T)) < P) {
           const uint32_t slot = off + emitted - w0;
           s_t[slot] = T;
           s_p[slot] = P;
@@ -339,7 +348,7 @@ __global__ void __launch_bounds__(64, kWaves) k_query_fused(QueryArgs a) {
         t2.v = float(t2.vd);
         const uint32_t r0 = wc.roots;
         ++wc.pairs;
-        s_c[k] = tuple_irradiance(a, s_t[k], t2, wc) / double(s_p[k]);
+        s_c[k] = tuple_irradiance<CH>(a, s_t[k], t2, wc) / double(s_p[k]);
         s_nr[k] = uint8_t(min(wc.roots - r0, 255u));
       }
       __syncthreads();
@@ -377,6 +386,8 @@ static QueryArgs make_args(const Bounds* b, const float* pts, int64_t n, int32_t
   a.coff = static_cast<const uint32_t*>(b->coff.p);
   a.gt = static_cast<const uint32_t*>(b->gt.p);
   a.ge = static_cast<const float*>(b->ge.p);
+  a.tid = b->scene.chain == BBC_CHAIN_RR ? b->scene.tid : nullptr;
+  a.rec_floats = b->rec_floats;
   a.pts = pts;
   a.n = n;
   a.W = float(spp);
@@ -398,7 +409,15 @@ bbc_status launch_query(const Bounds* b, const float* pts, int64_t n, int32_t sp
   const bool w4 = b->tune.query_waves >= 4;
   Bounds* mb = const_cast<Bounds*>(b);
   if (b->tune.timing) BBC_HIP(hipEventRecord(mb->ev[0], s));
-#define BBC_FUSED(W, TP) hipLaunchKernelGGL((k_query_fused<W, TP>), dim3(grid), dim3(64), 0, s, a)
+#define BBC_FUSED(W, TP)                                                                           \
+  do {                                                                                             \
+    if (a.sc.chain == BBC_CHAIN_RR)                                                                \
+      hipLaunchKernelGGL((k_query_fused<W, TP, BBC_CHAIN_RR>), dim3(grid), dim3(64), 0, s, a);      \
+    else if (a.sc.chain == BBC_CHAIN_T)                                                            \
+      hipLaunchKernelGGL((k_query_fused<W, TP, BBC_CHAIN_T>), dim3(grid), dim3(64), 0, s, a);       \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_query_fused<W, TP, BBC_CHAIN_R>), dim3(grid), dim3(64), 0, s, a);       \
+  } while (0)
   if (tp == 16) {
     if (w4) BBC_FUSED(4, 16); else BBC_FUSED(2, 16);
   } else if (tp == 32) {
@@ -459,7 +478,7 @@ __global__ void __launch_bounds__(64) k_stage_count(StagedArgs s, uint32_t* sel)
     const PointReq pr = point_req(a, i);
     for (uint32_t j = lane; j < nU; j += BBC_WAVE) {
       const float P = select_prob(a.ge[b + j], gamma, exhaustive);
-      c += selection_uniform(pr.seed, pr.key, a.gt[b + j]) < P ? 1u : 0u;
+      c += selection_uniform(pr.seed, pr.key, tuple_key(a, a.gt[b + j])) < P ? 1u : 0u;
     }
     c = wave_sum(c);
     if (lane == 0) sel[i] = c;
@@ -483,7 +502,7 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
       if (j < nU) {
         T = a.gt[b + j];
         P = select_prob(a.ge[b + j], gamma, exhaustive);
-        take = selection_uniform(pr.seed, pr.key, T) < P;
+        take = selection_uniform(pr.seed, pr.key, tuple_key(a, T)) < P;
       }
       const uint64_t m = __ballot(take);
       const uint32_t rank = __popcll(m & ((1ull << lane) - 1ull));
@@ -499,6 +518,7 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
 
 // Newton over the selected pairs, one lane per pair for the whole of its
 // starts.
+template <int CH>
 __global__ void __launch_bounds__(64) k_stage_newton(StagedArgs s, const uint32_t* total) {
   const QueryArgs& a = s.q;
   const uint32_t np = min(*total, s.pair_cap);
@@ -508,7 +528,7 @@ __global__ void __launch_bounds__(64) k_stage_newton(StagedArgs s, const uint32_
     const Target tg = receiver_target(a, i);
     ++wc.pairs;
     const uint32_t r0 = wc.roots;
-    s.pair_c[k] = tuple_irradiance(a, s.pair_t[k], tg, wc) / double(s.pair_p[k]);
+    s.pair_c[k] = tuple_irradiance<CH>(a, s.pair_t[k], tg, wc) / double(s.pair_p[k]);
     if (a.stats) s.pair_nr[k] = uint8_t(min(wc.roots - r0, 255u));
   }
   flush_counts(a, wc);
@@ -604,7 +624,12 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   hipLaunchKernelGGL(k_stage_fill, dim3(grid), dim3(64), 0, st, s);
   if (ev0) BBC_HIP(hipEventRecord(ev0, st));
   const unsigned gp = unsigned(std::min<size_t>((pairs + 63) / 64, 32768));
-  hipLaunchKernelGGL(k_stage_newton, dim3(gp), dim3(64), 0, st, s, s.off + n);
+  if (q.sc.chain == BBC_CHAIN_RR)
+    hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_RR>, dim3(gp), dim3(64), 0, st, s, s.off + n);
+  else if (q.sc.chain == BBC_CHAIN_T)
+    hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_T>, dim3(gp), dim3(64), 0, st, s, s.off + n);
+  else
+    hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_R>, dim3(gp), dim3(64), 0, st, s, s.off + n);
   if (ev1) BBC_HIP(hipEventRecord(ev1, st));
   hipLaunchKernelGGL(k_stage_accum, dim3(gpt), dim3(256), 0, st, s);
   BBC_HIP(hipGetLastError());

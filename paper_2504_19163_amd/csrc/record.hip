@@ -284,13 +284,27 @@ __global__ void k_grid_rank(RecArgs a) {
 }
 
 // One packed record per tuple with leaves (see geom_dev.hpp).
-__global__ void k_tuple_records(RecArgs a, DevScene sc, const float4* root, float* rec) {
+__global__ void k_tuple_records(RecArgs a, DevScene sc, const float4* root, float* rec, int rec_floats) {
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < a.n_tuples;
        t += int64_t(gridDim.x) * blockDim.x) {
     const uint32_t lb = a.toff[t], le = a.toff[t + 1];
     if (lb == le) continue;
-    const int64_t tri = t % sc.n_tri, e = t / sc.n_tri;
-    float4* r = reinterpret_cast<float4*>(rec + t * kRecFloats);
+    int64_t first = t;
+    float4* r = reinterpret_cast<float4*>(rec + t * rec_floats);
+    if (sc.chain == 2) {
+      const int64_t dense = sc.tid[t], n2 = sc.n_tri2, t2 = dense % n2;
+      first = dense / n2;
+      const float* P2 = sc.pos2;
+      const float* N2 = sc.nrm2;
+      r[7] = make_float4(P2[0 * n2 + t2], P2[1 * n2 + t2], P2[2 * n2 + t2], P2[3 * n2 + t2]);
+      r[8] = make_float4(P2[4 * n2 + t2], P2[5 * n2 + t2], P2[6 * n2 + t2], P2[7 * n2 + t2]);
+      r[9] = make_float4(P2[8 * n2 + t2], N2[0 * n2 + t2], N2[1 * n2 + t2], N2[2 * n2 + t2]);
+      r[10] = make_float4(N2[3 * n2 + t2], N2[4 * n2 + t2], N2[5 * n2 + t2], N2[6 * n2 + t2]);
+      r[11] = make_float4(N2[7 * n2 + t2], N2[8 * n2 + t2], 0.f, 0.f);
+    } else {
+      r[7] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    const int64_t tri = first % sc.n_tri, e = first / sc.n_tri;
     const float* P = sc.pos;
     const float* N = sc.nrm;
     const int64_t n = sc.n_tri;
@@ -301,7 +315,6 @@ __global__ void k_tuple_records(RecArgs a, DevScene sc, const float4* root, floa
     r[4] = make_float4(N[7 * n + tri], N[8 * n + tri], sc.epos[e], sc.epos[sc.n_emit + e]);
     r[5] = make_float4(sc.epos[2 * sc.n_emit + e], sc.eI[e], __uint_as_float(lb), __uint_as_float(le));
     r[6] = root[t];
-    r[7] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
 }
 
@@ -353,8 +366,10 @@ bbc_status launch_record(Bounds* b, hipStream_t s) {
   if ((st = launch_scan_u32(a.ccount, a.coff, ncell, b->scan_tmp.p, s))) return st;
   hipLaunchKernelGGL(k_grid_scatter, dim3(gl), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_grid_rank, dim3(gl), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_tuple_records, dim3(unsigned(std::min<int64_t>((b->n_tuples + 255) / 256, 4096))), dim3(256),
-                     0, s, a, b->scene, static_cast<const float4*>(b->root.p), static_cast<float*>(b->trec.p));
+  hipLaunchKernelGGL(k_tuple_records,
+                     dim3(unsigned(std::max<int64_t>(1, std::min<int64_t>((b->n_tuples + 255) / 256, 4096)))),
+                     dim3(256), 0, s, a, b->scene, static_cast<const float4*>(b->root.p), static_cast<float*>(b->trec.p),
+                     b->rec_floats);
   BBC_HIP(hipGetLastError());
   return BBC_OK;
 }

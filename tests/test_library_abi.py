@@ -75,5 +75,7 @@ def test_bad_parameters_are_rejected(L):
     s.f2[:] = list(s.f1)  # degenerate receiver
     assert L.bbc_build_bounds(C.byref(s), C.byref(e), C.byref(p), None, C.byref(h)) == bbc.EINVAL
     s.f2[:] = [float(x) for x in sc["f2"]]
-    s.chain = 2
-    assert L.bbc_build_bounds(C.byref(s), C.byref(e), C.byref(p), None, C.byref(h)) == bbc.EUNSUPPORTED
+    s.chain = 2  # two reflections without a second surface
+    assert L.bbc_build_bounds(C.byref(s), C.byref(e), C.byref(p), None, C.byref(h)) == bbc.EINVAL
+    s.chain = 7  # no such chain
+    assert L.bbc_build_bounds(C.byref(s), C.byref(e), C.byref(p), None, C.byref(h)) == bbc.EINVAL
