@@ -181,6 +181,42 @@ def refraction_section(bbc, S, torch, n_side=1024, steps=3):
             "device_bytes": info["device_bytes"], "pairs": qs["n_pairs"], "roots": qs["n_roots"]}
 
 
+def two_reflection_section(bbc, S, torch, steps=2):
+    """Two reflections between two facing rippled walls (8192 triangles each,
+    67,108,864 candidate pairs), depth cap 2, alpha 10, 256 x 256 floor points,
+    256 samples per point: tuple construction + build and query timed."""
+    dev = torch.device("cuda:0")
+    sc = S.facing_walls(64)
+    params = dict(max_depth=2, sigma=1e-4, alpha=10.0, grid_res=512)
+    t0 = time.perf_counter()
+    B = bbc.Bounds(bbc.DeviceScene(sc), params)
+    torch.cuda.synchronize()
+    first_build = time.perf_counter() - t0
+    pts = torch.as_tensor(S.receiver_points(sc, 256), device=dev)
+    tb, tq = [], []
+    for k in range(steps):
+        t = time.perf_counter()
+        B.rebuild()
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        B.query(pts, 256, 1 + k, mode=bbc.QUERY_STAGED)
+        torch.cuda.synchronize()
+        tq.append(time.perf_counter() - t)
+    _, _, qs = B.query(pts, 256, 1, mode=bbc.QUERY_STAGED, host_stats=True)
+    info = B.info()
+    B.free()
+    n = pts.shape[1]
+    b, q = float(np.median(tb)), float(np.median(tq))
+    return {"workload": "two reflections, facing walls 8192 + 8192 triangles (67.1M candidate pairs), depth cap 2, "
+                        "256x256 floor points, 256 samples/point; position bounds only (E = [0, inf), P = 1)",
+            "queries_s_whole_step": round(n / (b + q), 1), "build_ms": round(1e3 * b, 2),
+            "query_ms": round(1e3 * q, 2), "first_build_ms": round(1e3 * first_build, 1),
+            "candidate_pairs": info["n_tuples"], "live_tuples": info["n_live_tuples"], "boxes": info["n_boxes"],
+            "leaves": info["n_leaves"], "grid_entries": info["n_grid_entries"], "device_bytes": info["device_bytes"],
+            "mean_candidates_per_point": round(qs["sum_U"] / n, 1), "roots": qs["n_roots"]}
+
+
 def serving_section(bbc, S, torch, sphere_scene, sphere_bounds, n_req=1500, seed=5):
     """Continuous batching vs the plain per-request path on one request
     stream over device-resident bounds: the displaced sphere and a rippled
@@ -246,6 +282,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-refraction", action="store_true")
+    ap.add_argument("--no-two-reflections", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device tensor copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -346,6 +383,8 @@ def main():
         out["serving"] = serving_section(bbc, S, torch, scene, B)
     if not args.no_refraction:
         out["refraction"] = refraction_section(bbc, S, torch)
+    if not args.no_two_reflections:
+        out["two_reflections"] = two_reflection_section(bbc, S, torch)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O
