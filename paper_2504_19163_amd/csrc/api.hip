@@ -143,7 +143,7 @@ static bbc_status run_build(Bounds* b, hipStream_t s) {
     const uint32_t ov = b->host.overflow;
     if (!ov) {
       b->n_leaves = b->host.n_leaves;
-      b->n_entries = b->host.n_triples;
+      b->n_entries = b->host.n_entries;
       b->max_cell = mc;
       return BBC_OK;
     }

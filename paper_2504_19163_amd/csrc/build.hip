@@ -42,20 +42,73 @@ struct BuildArgs {
   float2* le;
 };
 
-__device__ __forceinline__ void push_root(const BuildArgs& a, uint32_t t, float4 box) {
+// Outputs of a workgroup's boxes (queue items for the next depth, leaves,
+// tuples for domain initialisation), staged in LDS by thread 0 and written
+// with one atomic per counter per flush: boxes finish every few microseconds
+// on every compute unit, and one global atomic per box on the same counter
+// serialises the whole grid.
+constexpr int kStageItems = 64, kStageLeaves = 32;
+struct Stage {
+  QItem item[kStageItems];
+  uint32_t initq[kStageItems];
+  uint32_t lt[kStageLeaves], lc[kStageLeaves];
+  float4 lu[kStageLeaves];
+  float2 le[kStageLeaves];
+  uint32_t n_item, n_init, n_leaf, n_inf, max_depth, n_live, base_item, base_init, base_leaf;
+};
+
+__device__ __forceinline__ void stage_reset(Stage& S, int lane) {
+  if (lane == 0) S.n_item = S.n_init = S.n_leaf = S.n_inf = S.max_depth = S.n_live = 0u;
+}
+
+// Room for one more box's outputs (four items, one leaf, one tuple).
+__device__ __forceinline__ bool stage_full(const Stage& S) {
+  return S.n_item > kStageItems - 4 || S.n_leaf >= kStageLeaves || S.n_init >= kStageItems;
+}
+
+// Called by every thread of the workgroup; `items` go to queue qcount[depth].
+template <int NT>
+__device__ void stage_flush(const BuildArgs& a, int depth, Stage& S, int lane) {
+  wave_sync();
+  if (lane == 0) {
+    S.base_item = S.n_item ? atomicAdd(&a.C->qcount[depth], S.n_item) : 0u;
+    S.base_leaf = S.n_leaf ? atomicAdd(&a.C->n_leaves, S.n_leaf) : 0u;
+    S.base_init = S.n_init ? atomicAdd(&a.C->n_init, S.n_init) : 0u;
+    if (S.n_live) atomicAdd(&a.C->n_live, S.n_live);
+    if (S.n_inf) atomicAdd(&a.C->n_inf, S.n_inf);
+    if (S.n_leaf) atomicMax(&a.C->max_depth, S.max_depth);
+    if (S.n_item && S.base_item + S.n_item > a.q_cap) atomicOr(&a.C->overflow, 1u);
+    if (S.n_leaf && S.base_leaf + S.n_leaf > a.leaf_cap) atomicOr(&a.C->overflow, 2u);
+  }
+  wave_sync();
+  const uint32_t ni = S.n_item, nl = S.n_leaf, nt = S.n_init;
+  const uint32_t bi = S.base_item, bl = S.base_leaf, bt = S.base_init;
+  for (uint32_t k = lane; k < ni; k += NT)
+    if (bi + k < a.q_cap) a.qout[bi + k] = S.item[k];
+  for (uint32_t k = lane; k < nt; k += NT) a.init_q[bt + k] = S.initq[k];  // capacity n_tuples: cannot overflow
+  for (uint32_t k = lane; k < nl; k += NT)
+    if (bl + k < a.leaf_cap) {
+      a.lt[bl + k] = S.lt[k];
+      a.lc[bl + k] = S.lc[k];
+      a.lu[bl + k] = S.lu[k];
+      a.le[bl + k] = S.le[k];
+    }
+  wave_sync();
+  stage_reset(S, lane);
+  wave_sync();
+}
+
+// A live tuple's root box: store it and stage the tuple's depth-0 queue item.
+__device__ __forceinline__ void push_root(const BuildArgs& a, uint32_t t, float4 box, Stage& S) {
   a.root[t] = box;
-  const uint32_t i = atomicAdd(&a.C->qcount[0], 1u);
-  if (i < a.q_cap)
-    a.qout[i] = QItem{t, 0u};
-  else
-    atomicOr(&a.C->overflow, 1u);
-  atomicAdd(&a.C->n_live, 1u);
+  S.item[S.n_item++] = QItem{t, 0u};
+  ++S.n_live;
 }
 
 // Level 0: the whole parameter square of every tuple, position bound only.
 // ev(G, u0, u1, v0, v1) bounds one box.
 template <class T, class Ev>
-__device__ void level0_one(const BuildArgs& a, uint32_t t, Ev ev, int lane) {
+__device__ void level0_one(const BuildArgs& a, uint32_t t, Ev ev, int lane, Stage& S) {
   const TupleGeom<T> G = tuple_geom<T>(a.sc, t);
   if (!G.front) return;
   const BoxOut o = ev(G, T(0), T(1), T(0), T(1));
@@ -66,61 +119,63 @@ __device__ void level0_one(const BuildArgs& a, uint32_t t, Ev ev, int lane) {
     return;
   }
   if (o.status == 0) return;
-  if (o.settled || a.init_levels == 0) {
-    push_root(a, t, make_float4(0.f, 1.f, 0.f, 1.f));
-  } else {
-    const uint32_t i = atomicAdd(&a.C->n_init, 1u);
-    a.init_q[i] = t;
+  if (o.settled || a.init_levels == 0)
+    push_root(a, t, make_float4(0.f, 1.f, 0.f, 1.f), S);
+  else
+    S.initq[S.n_init++] = t;
+}
+
+// The per-tuple loop of the level-0 kernels with staged outputs.
+template <class T, class Ev, class Tuples>
+__device__ void level0_loop(const BuildArgs& a, Ev ev, int lane, Stage& S, uint32_t n, Tuples tuple_at) {
+  stage_reset(S, lane);
+  wave_sync();
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    level0_one<T>(a, tuple_at(i), ev, lane, S);
+    wave_sync();
+    if (stage_full(S)) stage_flush<BBC_WAVE>(a, 0, S, lane);
   }
+  stage_flush<BBC_WAVE>(a, 0, S, lane);
 }
 
 __global__ void __launch_bounds__(64) k_level0(BuildArgs a) {
   __shared__ LdsRPos<float> L;
+  __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<float>& G, float u0, float u1, float v0, float v1) {
     return eval_box_r<float, false>(G, u0, u1, v0, v1, false, L, lane);
   };
-  for (int64_t t = blockIdx.x; t < a.n_tuples; t += gridDim.x) {
-    level0_one<float>(a, uint32_t(t), ev, lane);
-    wave_sync();
-  }
+  level0_loop<float>(a, ev, lane, S, uint32_t(a.n_tuples), [](uint32_t i) { return i; });
 }
 
 __global__ void __launch_bounds__(64) k_level0_fp64(BuildArgs a) {
   __shared__ LdsRPos<double> L;
+  __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
     return eval_box_r<double, false>(G, u0, u1, v0, v1, true, L, lane);
   };
-  const uint32_t n = a.C->n_l0_fp64;
-  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-    level0_one<double>(a, a.l0f_q[i], ev, lane);
-    wave_sync();
-  }
+  level0_loop<double>(a, ev, lane, S, a.C->n_l0_fp64, [&](uint32_t i) { return a.l0f_q[i]; });
 }
 
 __global__ void __launch_bounds__(64) k_level0_t(BuildArgs a) {
   __shared__ LdsT<double, false> L;
+  __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
     return eval_box_t<double, false, BBC_WAVE>(G, u0, u1, v0, v1, true, a.flags, L, lane);
   };
-  for (int64_t t = blockIdx.x; t < a.n_tuples; t += gridDim.x) {
-    level0_one<double>(a, uint32_t(t), ev, lane);
-    wave_sync();
-  }
+  level0_loop<double>(a, ev, lane, S, uint32_t(a.n_tuples), [](uint32_t i) { return i; });
 }
 
 __global__ void __launch_bounds__(64) k_level0_rr(BuildArgs a) {
   __shared__ LdsRR<double> L;
+  __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
     return eval_box_rr<double>(G, u0, u1, v0, v1, L, lane);
   };
-  for (int64_t t = blockIdx.x; t < a.n_tuples; t += gridDim.x) {
-    level0_one<double>(a, uint32_t(t), ev, lane);
-    wave_sync();
-  }
+  level0_loop<double>(a, ev, lane, S, uint32_t(a.n_tuples), [](uint32_t i) { return i; });
 }
 
 // ---------------------------------------------------------------- tuple construction, two reflections
@@ -297,7 +352,7 @@ struct InitBox {
 // One tuple's breadth-first initialisation; ev(cl, cu, cv) bounds the box
 // (cu, cv) of level cl.
 template <class Ev>
-__device__ void init_one(const BuildArgs& a, uint32_t t, Ev ev, InitBox* cur, InitBox* nxt, int lane) {
+__device__ void init_one(const BuildArgs& a, uint32_t t, Ev ev, InitBox* cur, InitBox* nxt, int lane, Stage& S) {
   int ncur = 1;
   if (lane == 0) cur[0] = InitBox{0u, 0u};
   wave_sync();
@@ -351,17 +406,21 @@ __device__ void init_one(const BuildArgs& a, uint32_t t, Ev ev, InitBox* cur, In
       v0 = fminf(v0, iv * w);
       v1 = fmaxf(v1, (iv + 1) * w);
     }
-    push_root(a, t, make_float4(u0, u1, v0, v1));
+    push_root(a, t, make_float4(u0, u1, v0, v1), S);
   }
   wave_sync();
+  if (stage_full(S)) stage_flush<BBC_WAVE>(a, 0, S, lane);
 }
 
 __global__ void __launch_bounds__(64) k_init(BuildArgs a) {
   __shared__ LdsRPos<float> Lf;
   __shared__ LdsRPos<double> Ld;
   __shared__ InitBox cur[kInitCap], nxt[kInitCap];
+  __shared__ Stage S;
   const int lane = threadIdx.x;
   const uint32_t n = a.C->n_init;
+  stage_reset(S, lane);
+  wave_sync();
   for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
     const uint32_t t = a.init_q[it];
     const TupleGeom<float> Gf = tuple_geom<float>(a.sc, t);
@@ -376,15 +435,19 @@ __global__ void __launch_bounds__(64) k_init(BuildArgs a) {
       }
       return o;
     };
-    init_one(a, t, ev, cur, nxt, lane);
+    init_one(a, t, ev, cur, nxt, lane, S);
   }
+  stage_flush<BBC_WAVE>(a, 0, S, lane);
 }
 
 __global__ void __launch_bounds__(64) k_init_rr(BuildArgs a) {
   __shared__ LdsRR<double> L;
   __shared__ InitBox cur[kInitCap], nxt[kInitCap];
+  __shared__ Stage S;
   const int lane = threadIdx.x;
   const uint32_t n = a.C->n_init;
+  stage_reset(S, lane);
+  wave_sync();
   for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
     const uint32_t t = a.init_q[it];
     const TupleGeom<double> Gd = tuple_geom<double>(a.sc, t);
@@ -392,15 +455,19 @@ __global__ void __launch_bounds__(64) k_init_rr(BuildArgs a) {
       const double wd = ldexp(1.0, -cl);
       return eval_box_rr<double>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, L, lane);
     };
-    init_one(a, t, ev, cur, nxt, lane);
+    init_one(a, t, ev, cur, nxt, lane, S);
   }
+  stage_flush<BBC_WAVE>(a, 0, S, lane);
 }
 
 __global__ void __launch_bounds__(64) k_init_t(BuildArgs a) {
   __shared__ LdsT<double, false> L;
   __shared__ InitBox cur[kInitCap], nxt[kInitCap];
+  __shared__ Stage S;
   const int lane = threadIdx.x;
   const uint32_t n = a.C->n_init;
+  stage_reset(S, lane);
+  wave_sync();
   for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
     const uint32_t t = a.init_q[it];
     const TupleGeom<double> Gd = tuple_geom<double>(a.sc, t);
@@ -409,15 +476,16 @@ __global__ void __launch_bounds__(64) k_init_t(BuildArgs a) {
       return eval_box_t<double, false, BBC_WAVE>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, true, a.flags, L,
                                                  lane);
     };
-    init_one(a, t, ev, cur, nxt, lane);
+    init_one(a, t, ev, cur, nxt, lane, S);
   }
+  stage_flush<BBC_WAVE>(a, 0, S, lane);
 }
 
 // One box of the adaptive subdivision (Sec. 6.1): stop when the clipped
 // position bound's area is below sigma, when E_hi / E_lo < alpha, or at the
 // depth cap; otherwise split at the midpoint into four.
 template <class T, class Ev>
-__device__ void subdiv_one(const BuildArgs& a, QItem it, int depth, Ev ev, int lane, uint32_t* n_boxes) {
+__device__ void subdiv_one(const BuildArgs& a, QItem it, int depth, Ev ev, int lane, uint32_t* n_boxes, Stage& S) {
   const TupleGeom<T> G = tuple_geom<T>(a.sc, it.tuple);
   const float4 r = a.root[it.tuple];
   const uint32_t iu = it.code >> kCodeBits, iv = it.code & ((1u << kCodeBits) - 1);
@@ -443,26 +511,33 @@ __device__ void subdiv_one(const BuildArgs& a, QItem it, int depth, Ev ev, int l
     stop = stop || (o.E[0] > 0.f && isfinite(o.E[1]) && o.E[1] < a.alpha * o.E[0]);
   }
   if (stop) {
-    const uint32_t i = atomicAdd(&a.C->n_leaves, 1u);
-    if (i < a.leaf_cap) {
-      a.lt[i] = it.tuple;
-      a.lc[i] = uint32_t(depth) << 28 | it.code;
-      a.lu[i] = make_float4(o.uk[0], o.uk[1], o.uk[2], o.uk[3]);
-      a.le[i] = make_float2(o.E[0], o.E[1]);
-    } else {
-      atomicOr(&a.C->overflow, 2u);
-    }
-    if (isinf(o.E[1])) atomicAdd(&a.C->n_inf, 1u);
-    atomicMax(&a.C->max_depth, uint32_t(depth));
+    const uint32_t k = S.n_leaf++;
+    S.lt[k] = it.tuple;
+    S.lc[k] = uint32_t(depth) << 28 | it.code;
+    S.lu[k] = make_float4(o.uk[0], o.uk[1], o.uk[2], o.uk[3]);
+    S.le[k] = make_float2(o.E[0], o.E[1]);
+    if (isinf(o.E[1])) ++S.n_inf;
+    S.max_depth = max(S.max_depth, uint32_t(depth));
     return;
   }
-  const uint32_t i = atomicAdd(&a.C->qcount[depth + 1], 4u);
-  if (i + 4 <= a.q_cap) {
-    for (uint32_t ch = 0; ch < 4; ++ch)
-      a.qout[i + ch] = QItem{it.tuple, (2 * iu + (ch >> 1)) << kCodeBits | (2 * iv + (ch & 1))};
-  } else {
-    atomicOr(&a.C->overflow, 1u);
+  for (uint32_t ch = 0; ch < 4; ++ch)
+    S.item[S.n_item++] = QItem{it.tuple, (2 * iu + (ch >> 1)) << kCodeBits | (2 * iv + (ch & 1))};
+}
+
+// The per-box loop of the subdivision kernels: children go to depth + 1.
+template <int NT, class Ev>
+__device__ void subdiv_loop(const BuildArgs& a, int depth, Ev ev, int lane, Stage& S) {
+  stage_reset(S, lane);
+  wave_sync();
+  const uint32_t n = min(a.C->qcount[depth], a.q_cap);
+  uint32_t boxes = 0;
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    subdiv_one<double>(a, a.qin[i], depth, ev, lane, &boxes, S);
+    wave_sync();
+    if (stage_full(S)) stage_flush<NT>(a, depth + 1, S, lane);
   }
+  stage_flush<NT>(a, depth + 1, S, lane);
+  if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
 }
 
 // Subdivision boxes carry the irradiance bound, whose denominator det M has
@@ -470,32 +545,22 @@ __device__ void subdiv_one(const BuildArgs& a, QItem it, int depth, Ev ev, int l
 // evaluated in FP64, which on this GPU issues at the rate of unpacked FP32.
 __global__ void __launch_bounds__(64) k_subdiv(BuildArgs a, int depth) {
   __shared__ LdsR<double> L;
+  __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
     return eval_box_r<double, true>(G, u0, u1, v0, v1, true, L, lane);
   };
-  const uint32_t n = min(a.C->qcount[depth], a.q_cap);
-  uint32_t boxes = 0;
-  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-    subdiv_one<double>(a, a.qin[i], depth, ev, lane, &boxes);
-    wave_sync();
-  }
-  if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
+  subdiv_loop<BBC_WAVE>(a, depth, ev, lane, S);
 }
 
 __global__ void __launch_bounds__(64) k_subdiv_rr(BuildArgs a, int depth) {
   __shared__ LdsRR<double> L;
+  __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
     return eval_box_rr<double>(G, u0, u1, v0, v1, L, lane);
   };
-  const uint32_t n = min(a.C->qcount[depth], a.q_cap);
-  uint32_t boxes = 0;
-  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-    subdiv_one<double>(a, a.qin[i], depth, ev, lane, &boxes);
-    wave_sync();
-  }
-  if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
+  subdiv_loop<BBC_WAVE>(a, depth, ev, lane, S);
 }
 
 // A refraction box takes ~1.5 Mflop of FP64 over ~90 KB of LDS: four waves
@@ -503,17 +568,12 @@ __global__ void __launch_bounds__(64) k_subdiv_rr(BuildArgs a, int depth) {
 constexpr int kSubdivTThreads = 256;
 __global__ void __launch_bounds__(kSubdivTThreads) k_subdiv_t(BuildArgs a, int depth) {
   __shared__ LdsT<double, true> L;
+  __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
     return eval_box_t<double, true, kSubdivTThreads>(G, u0, u1, v0, v1, true, a.flags, L, lane);
   };
-  const uint32_t n = min(a.C->qcount[depth], a.q_cap);
-  uint32_t boxes = 0;
-  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-    subdiv_one<double>(a, a.qin[i], depth, ev, lane, &boxes);
-    wave_sync();
-  }
-  if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
+  subdiv_loop<kSubdivTThreads>(a, depth, ev, lane, S);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {

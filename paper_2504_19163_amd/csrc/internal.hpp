@@ -41,7 +41,8 @@ struct BuildCounters {
   uint32_t n_live;                 // tuples with a root box
   uint32_t overflow;               // bit flags: 1 queue, 2 leaves, 4 grid entries, 8 fp64 queue, 16 init
   uint32_t max_depth;
-  uint32_t n_triples;
+  uint32_t n_triples;              // reserved triple slots (chunks; some unused)
+  uint32_t n_entries;              // (cell, tuple) entries of the grid
   uint32_t n_inf;
   uint32_t qcount[kMaxDepth + 2];  // items at each depth
   uint32_t fcount[kMaxDepth + 2];  // FP64 items at each depth

@@ -178,11 +178,22 @@ __device__ __forceinline__ int cell_of(float x, int G) {
 constexpr int kGridThreads = 256;
 constexpr int kTile = 16384;  // cells rasterised per LDS band
 
+// Triple slots are reserved in chunks of kTripChunk per workgroup (one global
+// atomic per chunk, not per tuple); unused slots of a chunk are marked with
+// kNoCell and skipped by the scatter.
+constexpr uint32_t kTripChunk = 1024, kNoCell = 0xffffffffu;
+
+__device__ void mark_unused(const RecArgs& a, uint32_t b, uint32_t e) {
+  for (uint32_t i = b + threadIdx.x; i < e && i < a.trip_cap; i += kGridThreads) a.trip[i] = kNoCell;
+}
+
 __global__ void __launch_bounds__(kGridThreads) k_grid_tuple(RecArgs a) {
   __shared__ uint32_t tile[kTile];
   __shared__ int rect[4];
-  __shared__ uint32_t base_slot;
+  __shared__ uint32_t base_slot, chunk_b, chunk_e, drop_b, drop_e, n_real;
   const int G = a.G;
+  if (threadIdx.x == 0) chunk_b = chunk_e = n_real = 0u;
+  __syncthreads();
   for (int64_t t = blockIdx.x; t < a.n_tuples; t += gridDim.x) {
     const uint32_t lb = a.toff[t], le = a.toff[t + 1];
     if (lb == le) continue;
@@ -230,8 +241,21 @@ __global__ void __launch_bounds__(kGridThreads) k_grid_tuple(RecArgs a) {
       for (int i = threadIdx.x; i < ncell; i += kGridThreads) mine += tile[i] != 0u;
       uint32_t tot;
       uint32_t off = block_exclusive_scan(mine, &tot);
-      if (threadIdx.x == 0) base_slot = tot ? atomicAdd(&a.C->n_triples, tot) : 0u;
+      if (threadIdx.x == 0) {
+        drop_b = drop_e = 0u;
+        if (tot > chunk_e - chunk_b) {  // a fresh chunk; the rest of the old one is marked unused
+          drop_b = chunk_b;
+          drop_e = chunk_e;
+          const uint32_t want = max(tot, kTripChunk);
+          chunk_b = atomicAdd(&a.C->n_triples, want);
+          chunk_e = chunk_b + want;
+        }
+        base_slot = chunk_b;
+        chunk_b += tot;
+        n_real += tot;
+      }
       __syncthreads();
+      mark_unused(a, drop_b, drop_e);
       const uint32_t bs = base_slot;
       if (bs + tot > a.trip_cap) {
         if (threadIdx.x == 0 && tot) atomicOr(&a.C->overflow, 4u);
@@ -250,6 +274,8 @@ __global__ void __launch_bounds__(kGridThreads) k_grid_tuple(RecArgs a) {
       __syncthreads();
     }
   }
+  mark_unused(a, chunk_b, chunk_e);
+  if (threadIdx.x == 0 && n_real) atomicAdd(&a.C->n_entries, n_real);
 }
 
 // Triples -> cells: first grouped by cell in arbitrary order, then each entry
@@ -259,6 +285,7 @@ __global__ void k_grid_scatter(RecArgs a) {
   const uint32_t n = min(a.C->n_triples, a.trip_cap);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t cell = a.trip[i];
+    if (cell == kNoCell) continue;
     const uint32_t p = a.coff[cell] + atomicAdd(&a.ccur[cell], 1u);
     a.ut[p] = a.trip[a.trip_cap + i];
     a.ue[p] = __uint_as_float(a.trip[2 * size_t(a.trip_cap) + i]);
@@ -267,7 +294,7 @@ __global__ void k_grid_scatter(RecArgs a) {
 }
 
 __global__ void k_grid_rank(RecArgs a) {
-  const uint32_t n = min(a.C->n_triples, a.trip_cap);
+  const uint32_t n = a.coff[uint32_t(a.G) * uint32_t(a.G)];  // entries scattered into the cells
   uint32_t mx = 0;
   for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
     const uint32_t cell = a.ucell[p];
