@@ -61,9 +61,10 @@ __device__ __forceinline__ void stage_reset(Stage& S, int lane) {
   if (lane == 0) S.n_item = S.n_init = S.n_leaf = S.n_inf = S.max_depth = S.n_live = 0u;
 }
 
-// Room for one more box's outputs (four items, one leaf, one tuple).
+// Room for four more items, leaves and tuples (one box's children, or one
+// result from each of four lane groups).
 __device__ __forceinline__ bool stage_full(const Stage& S) {
-  return S.n_item > kStageItems - 4 || S.n_leaf >= kStageLeaves || S.n_init >= kStageItems;
+  return S.n_item > kStageItems - 4 || S.n_leaf > kStageLeaves - 4 || S.n_init > kStageItems - 4;
 }
 
 // Called by every thread of the workgroup; `items` go to queue qcount[depth].
@@ -101,8 +102,23 @@ __device__ void stage_flush(const BuildArgs& a, int depth, Stage& S, int lane) {
 // A live tuple's root box: store it and stage the tuple's depth-0 queue item.
 __device__ __forceinline__ void push_root(const BuildArgs& a, uint32_t t, float4 box, Stage& S) {
   a.root[t] = box;
-  S.item[S.n_item++] = QItem{t, 0u};
-  ++S.n_live;
+  S.item[atomicAdd(&S.n_item, 1u)] = QItem{t, 0u};
+  atomicAdd(&S.n_live, 1u);
+}
+
+// What a tuple's level-0 bound decides: culled, a root box [0,1]^2, or domain
+// initialisation.  One thread per tuple.
+__device__ __forceinline__ void level0_decide(const BuildArgs& a, uint32_t t, const BoxOut& o, Stage& S) {
+  if (o.status == 2) {
+    const uint32_t i = atomicAdd(&a.C->n_l0_fp64, 1u);
+    a.l0f_q[i] = t;  // capacity n_tuples: cannot overflow
+    return;
+  }
+  if (o.status == 0) return;
+  if (o.settled || a.init_levels == 0)
+    push_root(a, t, make_float4(0.f, 1.f, 0.f, 1.f), S);
+  else
+    S.initq[atomicAdd(&S.n_init, 1u)] = t;
 }
 
 // Level 0: the whole parameter square of every tuple, position bound only.
@@ -113,16 +129,7 @@ __device__ void level0_one(const BuildArgs& a, uint32_t t, Ev ev, int lane, Stag
   if (!G.front) return;
   const BoxOut o = ev(G, T(0), T(1), T(0), T(1));
   if (lane != 0) return;
-  if (o.status == 2) {
-    const uint32_t i = atomicAdd(&a.C->n_l0_fp64, 1u);
-    a.l0f_q[i] = t;  // capacity n_tuples: cannot overflow
-    return;
-  }
-  if (o.status == 0) return;
-  if (o.settled || a.init_levels == 0)
-    push_root(a, t, make_float4(0.f, 1.f, 0.f, 1.f), S);
-  else
-    S.initq[S.n_init++] = t;
+  level0_decide(a, t, o, S);
 }
 
 // The per-tuple loop of the level-0 kernels with staged outputs.
@@ -138,14 +145,27 @@ __device__ void level0_loop(const BuildArgs& a, Ev ev, int lane, Stage& S, uint3
   stage_flush<BBC_WAVE>(a, 0, S, lane);
 }
 
+// Position-only boxes of reflection tuples have at most 25 coefficients per
+// polynomial: a wave bounds four of them at once, 16 lanes each.
+constexpr int kGroup = 16, kGroups = BBC_WAVE / kGroup;
+
 __global__ void __launch_bounds__(64) k_level0(BuildArgs a) {
-  __shared__ LdsRPos<float> L;
+  __shared__ LdsRPos<float> L[kGroups];
   __shared__ Stage S;
-  const int lane = threadIdx.x;
-  auto ev = [&](const TupleGeom<float>& G, float u0, float u1, float v0, float v1) {
-    return eval_box_r<float, false>(G, u0, u1, v0, v1, false, L, lane);
-  };
-  level0_loop<float>(a, ev, lane, S, uint32_t(a.n_tuples), [](uint32_t i) { return i; });
+  const int g = threadIdx.x / kGroup, lane = threadIdx.x % kGroup;
+  const uint32_t n = uint32_t(a.n_tuples);
+  stage_reset(S, threadIdx.x);
+  wave_sync();
+  for (uint32_t i0 = blockIdx.x * kGroups; i0 < n; i0 += gridDim.x * kGroups) {
+    const uint32_t t = i0 + g;
+    const bool have = t < n;
+    const TupleGeom<float> G = tuple_geom<float>(a.sc, have ? t : i0);
+    const BoxOut o = eval_box_r<float, false, LdsRPos<float>, kGroup>(G, 0.f, 1.f, 0.f, 1.f, false, L[g], lane);
+    if (have && lane == 0) level0_decide(a, t, o, S);
+    wave_sync();
+    if (stage_full(S)) stage_flush<BBC_WAVE>(a, 0, S, threadIdx.x);
+  }
+  stage_flush<BBC_WAVE>(a, 0, S, threadIdx.x);
 }
 
 __global__ void __launch_bounds__(64) k_level0_fp64(BuildArgs a) {
@@ -412,32 +432,103 @@ __device__ void init_one(const BuildArgs& a, uint32_t t, Ev ev, InitBox* cur, In
   if (stage_full(S)) stage_flush<BBC_WAVE>(a, 0, S, lane);
 }
 
+// Domain initialisation of reflection tuples: the four children of a box are
+// bounded at once (16 lanes each, FP32); a child whose denominator sign is
+// undecided is redone by the whole wave in FP64.  Children are kept in child
+// order, so the result is that of the one-child-at-a-time loop.
 __global__ void __launch_bounds__(64) k_init(BuildArgs a) {
-  __shared__ LdsRPos<float> Lf;
+  __shared__ LdsRPos<float> Lf[kGroups];
   __shared__ LdsRPos<double> Ld;
   __shared__ InitBox cur[kInitCap], nxt[kInitCap];
   __shared__ Stage S;
-  const int lane = threadIdx.x;
+  __shared__ int res_status[kGroups], res_settled[kGroups];
+  const int tid = threadIdx.x, g = tid / kGroup, lane = tid % kGroup;
   const uint32_t n = a.C->n_init;
-  stage_reset(S, lane);
+  stage_reset(S, tid);
   wave_sync();
   for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
     const uint32_t t = a.init_q[it];
     const TupleGeom<float> Gf = tuple_geom<float>(a.sc, t);
     const TupleGeom<double> Gd = tuple_geom<double>(a.sc, t);
-    auto ev = [&](int cl, uint32_t cu, uint32_t cv) {
-      const float w = ldexpf(1.f, -cl);
-      BoxOut o = eval_box_r<float, false>(Gf, cu * w, (cu + 1) * w, cv * w, (cv + 1) * w, false, Lf, lane);
-      if (o.status == 2) {
+    int ncur = 1;
+    if (tid == 0) cur[0] = InitBox{0u, 0u};
+    wave_sync();
+    bool dead = false;
+    for (int level = 1; level <= a.init_levels; ++level) {
+      bool all_settled = true;
+      for (int j = 0; j < ncur; ++j) all_settled = all_settled && cur[j].settled;
+      if (all_settled) break;
+      int nn = 0;
+      bool over = false;
+      for (int j = 0; j < ncur && !over; ++j) {
+        const InitBox b = cur[j];
+        if (b.settled) {
+          if (tid == 0) nxt[nn] = b;
+          ++nn;
+          over = nn > a.init_pieces;
+          continue;
+        }
+        const int cl = int(b.code >> 28) + 1;
+        const uint32_t iu = (b.code >> 14) & 0x3fffu, iv = b.code & 0x3fffu;
+        const float w = ldexpf(1.f, -cl);
+        const uint32_t cu = 2 * iu + (g >> 1), cv = 2 * iv + (g & 1);
         wave_sync();
-        const double wd = ldexp(1.0, -cl);
-        o = eval_box_r<double, false>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, true, Ld, lane);
+        const BoxOut o = eval_box_r<float, false, LdsRPos<float>, kGroup>(Gf, cu * w, (cu + 1) * w, cv * w,
+                                                                          (cv + 1) * w, false, Lf[g], lane);
+        if (lane == 0) {
+          res_status[g] = o.status;
+          res_settled[g] = o.settled ? 1 : 0;
+        }
+        wave_sync();
+        for (int ch = 0; ch < kGroups; ++ch) {
+          if (res_status[ch] != 2) continue;
+          const double wd = ldexp(1.0, -cl);
+          const uint32_t du = 2 * iu + (ch >> 1), dv = 2 * iv + (ch & 1);
+          wave_sync();
+          const BoxOut od = eval_box_r<double, false>(Gd, du * wd, (du + 1) * wd, dv * wd, (dv + 1) * wd, true, Ld, tid);
+          wave_sync();
+          if (tid == 0) {
+            res_status[ch] = od.status;
+            res_settled[ch] = od.settled ? 1 : 0;
+          }
+          wave_sync();
+        }
+        for (int ch = 0; ch < kGroups && !over; ++ch) {
+          if (res_status[ch] != 1) continue;
+          if (tid == 0)
+            nxt[nn] = InitBox{uint32_t(cl) << 28 | (2 * iu + (ch >> 1)) << 14 | (2 * iv + (ch & 1)),
+                              uint32_t(res_settled[ch])};
+          ++nn;
+          over = nn > a.init_pieces;
+        }
       }
-      return o;
-    };
-    init_one(a, t, ev, cur, nxt, lane, S);
+      wave_sync();
+      if (over) break;
+      if (nn == 0) {
+        dead = true;
+        break;
+      }
+      for (int j = tid; j < nn; j += BBC_WAVE) cur[j] = nxt[j];
+      ncur = nn;
+      wave_sync();
+    }
+    if (!dead && tid == 0) {
+      float u0 = 1.f, u1 = 0.f, v0 = 1.f, v1 = 0.f;
+      for (int j = 0; j < ncur; ++j) {
+        const int bl = int(cur[j].code >> 28);
+        const float ww = ldexpf(1.f, -bl);
+        const uint32_t iu = (cur[j].code >> 14) & 0x3fffu, iv = cur[j].code & 0x3fffu;
+        u0 = fminf(u0, iu * ww);
+        u1 = fmaxf(u1, (iu + 1) * ww);
+        v0 = fminf(v0, iv * ww);
+        v1 = fmaxf(v1, (iv + 1) * ww);
+      }
+      push_root(a, t, make_float4(u0, u1, v0, v1), S);
+    }
+    wave_sync();
+    if (stage_full(S)) stage_flush<BBC_WAVE>(a, 0, S, tid);
   }
-  stage_flush<BBC_WAVE>(a, 0, S, lane);
+  stage_flush<BBC_WAVE>(a, 0, S, tid);
 }
 
 __global__ void __launch_bounds__(64) k_init_rr(BuildArgs a) {

@@ -52,12 +52,17 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 // evaluation (one wave, or NT lanes of several waves, per box).
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
-// Reductions over the NT threads of a workgroup (NT a multiple of 64; one
-// wave needs no LDS).  Every thread must call them.
+// Reductions over NT threads: a group of NT < 64 lanes of one wave (aligned to
+// NT), the wave, or NT a multiple of 64 across the workgroup's waves (through
+// LDS).  Every thread of the group must call them.
 template <int NT>
 __device__ __forceinline__ bool blk_all(bool p) {
   if constexpr (NT == BBC_WAVE) {
     return wave_all(p);
+  } else if constexpr (NT < BBC_WAVE) {  // the NT-lane group of this lane
+    const uint64_t b = __ballot(!p);
+    const int g = int(threadIdx.x % BBC_WAVE) / NT;
+    return ((b >> (g * NT)) & ((1ull << NT) - 1ull)) == 0ull;
   } else {
     __shared__ int red[NT / BBC_WAVE];
     const bool w = wave_all(p);
@@ -78,6 +83,10 @@ template <int NT, class T>
 __device__ __forceinline__ T blk_min(T v) {
   if constexpr (NT == BBC_WAVE) {
     return wave_min(v);
+  } else if constexpr (NT < BBC_WAVE) {
+#pragma unroll
+    for (int m = NT / 2; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, BBC_WAVE));
+    return v;
   } else {
     __shared__ T red[NT / BBC_WAVE];
     const T w = wave_min(v);

@@ -181,7 +181,7 @@ constexpr int kTile = 16384;  // cells rasterised per LDS band
 // Triple slots are reserved in chunks of kTripChunk per workgroup (one global
 // atomic per chunk, not per tuple); unused slots of a chunk are marked with
 // kNoCell and skipped by the scatter.
-constexpr uint32_t kTripChunk = 1024, kNoCell = 0xffffffffu;
+constexpr uint32_t kTripChunk = 256, kNoCell = 0xffffffffu;
 
 __device__ void mark_unused(const RecArgs& a, uint32_t b, uint32_t e) {
   for (uint32_t i = b + threadIdx.x; i < e && i < a.trip_cap; i += kGridThreads) a.trip[i] = kNoCell;
