@@ -203,12 +203,16 @@ bbc_status bbc_query_irradiance_ex(const bbc_bounds* b, const float* points_dev,
  *  BBC_TUNE_QUERY_TILE         fused query shading points per wave: 16, 32 or 64
  *  BBC_TUNE_TIMING             1: record HIP events on the query stream around the
  *                              query's dominant kernel (see bbc_query_kernel_ms)
+ *  BBC_TUNE_NEWTON_STEPS       staged query: FP32 Newton iterations per pass of the
+ *                              pooled Newton kernel (1..20, default 4); 0 gives each
+ *                              lane one selected pair for all of its starts
  * Applies to later calls on the handle; EINVAL for an unknown knob or value. */
 #define BBC_TUNE_QUERY_WAVES 1
 #define BBC_TUNE_QUERY_GRID 2
 #define BBC_TUNE_BUILD_GRID_PER_CU 3
 #define BBC_TUNE_QUERY_TILE 4
 #define BBC_TUNE_TIMING 5
+#define BBC_TUNE_NEWTON_STEPS 6
 bbc_status bbc_set_tuning(bbc_bounds* b, int32_t knob, int64_t value);
 bbc_status bbc_get_tuning(const bbc_bounds* b, int32_t knob, int64_t* value);
 

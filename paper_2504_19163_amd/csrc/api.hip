@@ -453,6 +453,10 @@ bbc_status bbc_set_tuning(bbc_bounds* h, int32_t knob, int64_t value) {
       }
       b->tune.timing = int(value);
       return BBC_OK;
+    case BBC_TUNE_NEWTON_STEPS:
+      if (value < 0 || value > 20) return invalid("Newton steps per pass must be in [0, 20]");
+      b->tune.newton_steps = int(value);
+      return BBC_OK;
     default:
       return invalid("unknown tuning knob");
   }
@@ -467,6 +471,7 @@ bbc_status bbc_get_tuning(const bbc_bounds* h, int32_t knob, int64_t* value) {
     case BBC_TUNE_BUILD_GRID_PER_CU: *value = b->tune.build_grid_per_cu; return BBC_OK;
     case BBC_TUNE_QUERY_TILE: *value = b->tune.query_tile; return BBC_OK;
     case BBC_TUNE_TIMING: *value = b->tune.timing; return BBC_OK;
+    case BBC_TUNE_NEWTON_STEPS: *value = b->tune.newton_steps; return BBC_OK;
     default: return invalid("unknown tuning knob");
   }
 }

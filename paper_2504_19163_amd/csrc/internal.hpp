@@ -76,6 +76,7 @@ struct Tuning {
   int query_tile = 16;        // fused query: shading points per wave (16, 32 or 64)
   int timing = 0;             // record events around the query's dominant kernel
   int build_grid_per_cu = 16; // subdivision: persistent workgroups per CU
+  int newton_steps = 4;       // staged query: FP32 iterations per pooled Newton pass (0: lane per pair)
 };
 
 struct Bounds {

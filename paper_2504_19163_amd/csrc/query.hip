@@ -12,6 +12,8 @@
 // Staged form: the same stages as separate launches with their intermediate
 // results in HBM: gamma per point, selection count + scan + compaction into
 // (point, tuple, P) pairs, Newton per pair, accumulation per point.
+#include <atomic>
+
 #include "internal.hpp"
 #include "path_dev.hpp"
 
@@ -154,11 +156,125 @@ __device__ __forceinline__ float select_prob(float e, float gamma, bool exhausti
   return fminf(gamma * e, 1.f);
 }
 
+// One Newton start: the centre of a leaf of T whose position bound holds the
+// target, and the box it may not leave (the leaf widened by one width on each
+// side).  FP32 state carried between passes of the pooled form.
+struct Start32 {
+  float u, v, lu0, lu1, lv0, lv1, prev, t_last;
+  int it;
+};
+
+__device__ __forceinline__ Start32 start_of(uint32_t code, float rx, float ry, float rz, float rw) {
+  const int depth = int(code >> 28);
+  const uint32_t iu = (code >> kCodeBits) & ((1u << kCodeBits) - 1), iv = code & ((1u << kCodeBits) - 1);
+  const float sc = ldexpf(1.f, -depth);
+  const float fu = (ry - rx) * sc, fv = (rw - rz) * sc;
+  const float u0 = rx + float(iu) * fu, v0 = rz + float(iv) * fv;
+  Start32 st;
+  st.u = u0 + 0.5f * fu;
+  st.v = v0 + 0.5f * fv;
+  st.lu0 = u0 - fu;
+  st.lu1 = u0 + 2.f * fu;
+  st.lv0 = v0 - fv;
+  st.lv1 = v0 + 2.f * fv;
+  st.prev = INFINITY;
+  st.t_last = -1.f;
+  st.it = 0;
+  return st;
+}
+
+// At most `steps` more FP32 Newton iterations of a start (20 in all).  The
+// iteration stops when the step falls below 1e-5 or stagnates at FP32 noise
+// level (below 1e-3 and no longer halving): for small triangles the FP32
+// residual cannot resolve the root further, and the FP64 polish that follows
+// runs to a receiver residual below 1e-9.  Returns 0 while the start is still
+// running, 1 when it failed (singular Jacobian or the iterate left its box),
+// 2 when it ended (converged or out of iterations).
+template <int CH>
+__device__ __forceinline__ int newton32(const TupleGeom<float>& Gf, float tu, float tv, Start32& st, int steps,
+                                        WorkCount& wc) {
+  for (int r = 0; r < steps; ++r) {
+    if (st.it >= 20) return 2;
+    ++st.it;
+    ++wc.it32;  // FP32 path evaluations
+    const PathT<float> p = eval_path<float>(Gf, CH, st.u, st.v);
+    const float ru_ = p.uk - tu, rv_ = p.vk - tv;
+    if (!(isfinite(p.det)) || p.det == 0.f) return 1;
+    const float du = (p.J11 * ru_ - p.J01 * rv_) / p.det;
+    const float dv = (-p.J10 * ru_ + p.J00 * rv_) / p.det;
+    st.u -= du;
+    st.v -= dv;
+    st.t_last = p.t;
+    if (!(st.u >= st.lu0 && st.u <= st.lu1 && st.v >= st.lv0 && st.v <= st.lv1)) return 1;
+    const float step = fabsf(du) + fabsf(dv);
+    if (step < 1e-5f || (step < 1e-3f && step > 0.5f * st.prev)) return 2;
+    st.prev = step;
+  }
+  return st.it >= 20 ? 2 : 0;
+}
+
+// A start whose FP32 root lies clearly outside the triangle or behind the
+// receiver cannot become admissible in the polish (margin 1e-3 >> FP32 error).
+__device__ __forceinline__ bool worth_polish(const Start32& st) {
+  return st.u >= -1e-3f && st.v >= -1e-3f && st.u + st.v <= 1.f + 1e-3f && st.t_last > 0.f;
+}
+
+// FP64 polish of an FP32 root (up to ten steps next to a fold, where
+// convergence is only linear); the root is accepted when its FP64 residual on
+// the receiver is below 1e-6 scene units and the path is admissible.  On
+// acceptance writes the root and its irradiance.
+template <int CH>
+__device__ __forceinline__ bool polish64(const TupleGeom<double>& Gd, double tud, double tvd, float u, float v,
+                                         double& ud, double& vd, double& E, WorkCount& wc) {
+  ud = u;
+  vd = v;
+  ++wc.it64;  // FP64 path evaluations
+  PathT<double> p = eval_path<double>(Gd, CH, ud, vd);
+  double res = INFINITY;
+  for (int it = 0; it < 10; ++it) {
+    ++wc.it64;
+    const double ru_ = p.uk - tud, rv_ = p.vk - tvd;
+    if (!(p.det != 0.0) || !isfinite(p.det)) break;
+    ud -= (p.J11 * ru_ - p.J01 * rv_) / p.det;
+    vd -= (-p.J10 * ru_ + p.J00 * rv_) / p.det;
+    p = eval_path<double>(Gd, CH, ud, vd);
+    res = residual<double>(Gd, p, tud, tvd);
+    if (res < 1e-9) break;
+  }
+  if (!(res < 1e-6) || !admissible<double>(Gd, CH, p, ud, vd)) return false;
+  E = path_irradiance<double>(Gd, p);
+  return true;
+}
+
+// Roots of one tuple taken in start order: a root within 1e-7 (in u1) of one
+// of the first four accepted roots is the same root found again.
+struct RootSum {
+  double ru0 = 0, rv0 = 0, ru1 = 0, rv1 = 0, ru2 = 0, rv2 = 0, ru3 = 0, rv3 = 0;
+  int nr = 0;
+  double ET = 0.0;
+
+  __device__ __forceinline__ void add(double ud, double vd, double E, WorkCount& wc) {
+    bool dup = false;
+    if (nr > 0) dup = dup || (fabs(ru0 - ud) <= 1e-7 && fabs(rv0 - vd) <= 1e-7);
+    if (nr > 1) dup = dup || (fabs(ru1 - ud) <= 1e-7 && fabs(rv1 - vd) <= 1e-7);
+    if (nr > 2) dup = dup || (fabs(ru2 - ud) <= 1e-7 && fabs(rv2 - vd) <= 1e-7);
+    if (nr > 3) dup = dup || (fabs(ru3 - ud) <= 1e-7 && fabs(rv3 - vd) <= 1e-7);
+    if (dup) return;
+    if (nr == 0) { ru0 = ud; rv0 = vd; }
+    else if (nr == 1) { ru1 = ud; rv1 = vd; }
+    else if (nr == 2) { ru2 = ud; rv2 = vd; }
+    else if (nr == 3) { ru3 = ud; rv3 = vd; }
+    ++nr;
+    ET += E;
+    ++wc.roots;
+  }
+};
+
 // Sum of the irradiance of every admissible path of tuple T that Newton finds
 // from the centres of T's leaves whose position bound contains the target
 // (deterministic initialisation, Sec. 6.1): FP32 iterations that abandon a
-// start leaving its box by more than one width, then two FP64 steps; a root is
-// accepted when its FP64 residual on the receiver is below 1e-6 scene units.
+// start leaving its box by more than one width, then the FP64 polish.  One
+// thread does all of T's starts.
 template <int CH>
 __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target& tg, WorkCount& wc) {
   constexpr bool RR = CH == BBC_CHAIN_RR;
@@ -175,88 +291,19 @@ __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target&
   }
   const uint32_t lb = __float_as_uint(rec[22]), le = __float_as_uint(rec[23]);
   if (lb == le) return 0.0;
-  constexpr int chain = CH;
   const TupleGeom<float> Gf = tuple_geom_rec<float, RR>(rec, a.sc);
-  const float rx = rec[24], ry = rec[25], rz = rec[26], rw = rec[27];
-  double ru0 = 0, rv0 = 0, ru1 = 0, rv1 = 0, ru2 = 0, rv2 = 0, ru3 = 0, rv3 = 0;
-  int nr = 0;
-  double ET = 0.0;
+  RootSum rs;
   for (uint32_t k = lb; k < le; ++k) {
     const float4 uk = a.luk[k];
     if (!(tg.ud >= uk.x && tg.ud <= uk.y && tg.vd >= uk.z && tg.vd <= uk.w)) continue;
-    const uint32_t code = a.lcode[k];
-    const int depth = int(code >> 28);
-    const uint32_t iu = (code >> kCodeBits) & ((1u << kCodeBits) - 1), iv = code & ((1u << kCodeBits) - 1);
-    const float sc = ldexpf(1.f, -depth);
-    const float fu = (ry - rx) * sc, fv = (rw - rz) * sc;
-    const float u0 = rx + float(iu) * fu, v0 = rz + float(iv) * fv;
-    float u = u0 + 0.5f * fu, v = v0 + 0.5f * fv;
-    const float lu0 = u0 - fu, lu1 = u0 + 2.f * fu, lv0 = v0 - fv, lv1 = v0 + 2.f * fv;
+    Start32 st = start_of(a.lcode[k], rec[24], rec[25], rec[26], rec[27]);
     ++wc.starts;
-    // FP32 Newton until the step falls below 1e-5 or stagnates at FP32 noise
-    // level (below 1e-3 and no longer halving): for small triangles the FP32
-    // residual cannot resolve the root further, and the FP64 polish that
-    // follows runs to a receiver residual below 1e-9 (up to ten steps next to a
-    // fold, where convergence is only linear)
-    bool ok = true;
-    float t_last = -1.f, prev = INFINITY;
-    for (int it = 0; it < 20; ++it) {
-      ++wc.it32;  // FP32 path evaluations
-      const PathT<float> p = eval_path<float>(Gf, chain, u, v);
-      const float ru_ = p.uk - tg.u, rv_ = p.vk - tg.v;
-      if (!(isfinite(p.det)) || p.det == 0.f) {
-        ok = false;
-        break;
-      }
-      const float du = (p.J11 * ru_ - p.J01 * rv_) / p.det;
-      const float dv = (-p.J10 * ru_ + p.J00 * rv_) / p.det;
-      u -= du;
-      v -= dv;
-      t_last = p.t;
-      if (!(u >= lu0 && u <= lu1 && v >= lv0 && v <= lv1)) {
-        ok = false;
-        break;
-      }
-      const float step = fabsf(du) + fabsf(dv);
-      if (step < 1e-5f || (step < 1e-3f && step > 0.5f * prev)) break;
-      prev = step;
-    }
-    if (!ok) continue;
-    // a start whose FP32 root lies clearly outside the triangle or behind the
-    // receiver cannot become admissible in the polish (margin 1e-3 >> FP32 error)
-    if (!(u >= -1e-3f && v >= -1e-3f && u + v <= 1.f + 1e-3f) || !(t_last > 0.f)) continue;
-    // FP64 polish
+    if (newton32<CH>(Gf, tg.u, tg.v, st, 20, wc) != 2 || !worth_polish(st)) continue;
     const TupleGeom<double> Gd = tuple_geom_rec<double, RR>(rec, a.sc);
-    double ud = u, vd = v;
-    ++wc.it64;  // FP64 path evaluations
-    PathT<double> p = eval_path<double>(Gd, chain, ud, vd);
-    double res = INFINITY;
-    for (int it = 0; it < 10; ++it) {
-      ++wc.it64;
-      const double ru_ = p.uk - tg.ud, rv_ = p.vk - tg.vd;
-      if (!(p.det != 0.0) || !isfinite(p.det)) break;
-      ud -= (p.J11 * ru_ - p.J01 * rv_) / p.det;
-      vd -= (-p.J10 * ru_ + p.J00 * rv_) / p.det;
-      p = eval_path<double>(Gd, chain, ud, vd);
-      res = residual<double>(Gd, p, tg.ud, tg.vd);
-      if (res < 1e-9) break;
-    }
-    if (!(res < 1e-6) || !admissible<double>(Gd, chain, p, ud, vd)) continue;
-    bool dup = false;
-    if (nr > 0) dup = dup || (fabs(ru0 - ud) <= 1e-7 && fabs(rv0 - vd) <= 1e-7);
-    if (nr > 1) dup = dup || (fabs(ru1 - ud) <= 1e-7 && fabs(rv1 - vd) <= 1e-7);
-    if (nr > 2) dup = dup || (fabs(ru2 - ud) <= 1e-7 && fabs(rv2 - vd) <= 1e-7);
-    if (nr > 3) dup = dup || (fabs(ru3 - ud) <= 1e-7 && fabs(rv3 - vd) <= 1e-7);
-    if (dup) continue;
-    if (nr == 0) { ru0 = ud; rv0 = vd; }
-    else if (nr == 1) { ru1 = ud; rv1 = vd; }
-    else if (nr == 2) { ru2 = ud; rv2 = vd; }
-    else if (nr == 3) { ru3 = ud; rv3 = vd; }
-    ++nr;
-    ET += path_irradiance<double>(Gd, p);
-    ++wc.roots;
+    double ud, vd, E;
+    if (polish64<CH>(Gd, tg.ud, tg.vd, st.u, st.v, ud, vd, E, wc)) rs.add(ud, vd, E, wc);
   }
-  return ET;
+  return rs.ET;
 }
 
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, int lane) {
@@ -452,6 +499,7 @@ struct StagedArgs {
 __global__ void k_stage_gamma(StagedArgs s) {
   const QueryArgs& a = s.q;
   const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) s.off[a.n + 1] = 0u;  // work counter of the pooled Newton kernel
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x) {
     const Target tg = receiver_target(a, i);
     uint32_t b = 0, nU = 0;
@@ -534,6 +582,279 @@ __global__ void __launch_bounds__(64) k_stage_newton(StagedArgs s, const uint32_
   flush_counts(a, wc);
 }
 
+// Pooled form of the same per-pair computation.  A wave takes 64 selected
+// pairs at a time and spreads their Newton starts over its lanes instead of
+// giving each lane one pair for all of its starts, which leaves most lanes
+// idle while one lane iterates.  The starts (leaves of the pair's tuple whose
+// position bound holds the target) are gathered into a pool in LDS; in each
+// pass a lane advances one start by at most `steps` FP32 iterations and puts
+// it back if it is still running; converged starts queue for the FP64 polish,
+// which runs 64 at a time; accepted roots are summed per pair in leaf order
+// with the same deduplication, so every pair's result is that of
+// tuple_irradiance.  A pair whose roots do not fit the result buffer is redone
+// by tuple_irradiance.
+constexpr int kPool = 128;  // FP32 starts (ring); at most 127 are held
+constexpr int kCand = 128;  // FP32 roots waiting for the polish; at most 127
+constexpr int kRes = 96;    // accepted roots of the 64 pairs (about 7 on average)
+
+template <int CH>
+struct NewtonPool {
+  static constexpr int NF = CH == BBC_CHAIN_RR ? 48 : 28;  // record floats Newton reads
+  static constexpr int RS = NF + 1;                         // odd row stride: rows of different pairs do not share banks
+  float rec[BBC_WAVE * RS];
+  float tu[BBC_WAVE], tv[BBC_WAVE];
+  double tud[BBC_WAVE], tvd[BBC_WAVE];
+  uint32_t lb[BBC_WAVE], lscan[BBC_WAVE + 1];
+  uint32_t redo[BBC_WAVE];
+  float pu[kPool], pv[kPool], plu0[kPool], plu1[kPool], plv0[kPool], plv1[kPool], pprev[kPool], ptl[kPool];
+  uint32_t pk[kPool], pmeta[kPool];  // leaf index; pair | iterations done << 8
+  float cu[kCand], cv[kCand];
+  uint32_t ck[kCand], cp[kCand];
+  double rud[kRes], rvd[kRes], rE[kRes];
+  uint32_t rk[kRes], rp[kRes];
+};
+
+template <int CH>
+__global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* ticket,
+                                                          int steps) {
+  constexpr bool RR = CH == BBC_CHAIN_RR;
+  using Pool = NewtonPool<CH>;
+  constexpr int NF = Pool::NF, RS = Pool::RS, NREC = RR ? kRecFloatsRR : kRecFloats;
+  __shared__ Pool L;
+  const QueryArgs& a = s.q;
+  const int lane = int(threadIdx.x);
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint32_t np = min(*total, s.pair_cap);
+  WorkCount wc;
+  while (true) {
+    // the next 64 pairs, taken from a shared counter so that workgroups that
+    // drew cheap pairs take more of them
+    uint32_t batch = 0;
+    if (lane == 0) batch = atomicAdd(ticket, 1u);
+    batch = __shfl(batch, 0, BBC_WAVE);
+    if (uint64_t(batch) * BBC_WAVE >= np) break;
+    const uint32_t k = batch * uint32_t(BBC_WAVE) + uint32_t(lane);
+    const bool valid = k < np;
+    Target tg{};
+    uint32_t T = 0, cnt = 0;
+    L.redo[lane] = 0u;
+    if (valid) {
+      T = s.pair_t[k];
+      tg = receiver_target(a, s.pair_pt[k]);
+      const float4* r4 = reinterpret_cast<const float4*>(a.rec + size_t(T) * NREC);
+      float* R = &L.rec[lane * RS];
+#pragma unroll
+      for (int q = 0; q < NF / 4; ++q) {
+        const float4 v = r4[q];
+        R[4 * q] = v.x;
+        R[4 * q + 1] = v.y;
+        R[4 * q + 2] = v.z;
+        R[4 * q + 3] = v.w;
+        if (q == 5) {
+          L.lb[lane] = __float_as_uint(v.z);
+          cnt = __float_as_uint(v.w) - __float_as_uint(v.z);
+        }
+      }
+      L.tu[lane] = tg.u;
+      L.tv[lane] = tg.v;
+      L.tud[lane] = tg.ud;
+      L.tvd[lane] = tg.vd;
+    }
+    const uint32_t ex = wave_excl_scan(cnt, lane);
+    const uint32_t tot = __shfl(ex + cnt, BBC_WAVE - 1, BBC_WAVE);
+    L.lscan[lane] = ex;
+    if (lane == BBC_WAVE - 1) L.lscan[BBC_WAVE] = tot;
+    __syncthreads();
+
+    // wave-uniform counters: leaf slots scanned, pool ring head and size,
+    // queued candidates, stored roots
+    uint32_t scan = 0, head = 0, pn = 0, cn = 0, rn = 0;
+    auto polish = [&](uint32_t n) {
+      bool ok = false, keep = false;
+      double ud = 0, vd = 0, E = 0;
+      uint32_t p = 0, kk = 0;
+      if (uint32_t(lane) < n) {
+        p = L.cp[lane];
+        kk = L.ck[lane];
+        const TupleGeom<double> Gd = tuple_geom_rec<double, RR>(&L.rec[p * RS], a.sc);
+        ok = polish64<CH>(Gd, L.tud[p], L.tvd[p], L.cu[lane], L.cv[lane], ud, vd, E, wc);
+      }
+      const uint64_t m = __ballot(ok);
+      if (ok) {
+        const uint32_t r = rn + uint32_t(__popcll(m & below));
+        if (r < uint32_t(kRes)) {
+          L.rud[r] = ud;
+          L.rvd[r] = vd;
+          L.rE[r] = E;
+          L.rk[r] = kk;
+          L.rp[r] = p;
+        } else {
+          L.redo[p] = 1u;
+        }
+      }
+      rn = min(rn + uint32_t(__popcll(m)), uint32_t(kRes));
+      // move the candidates not polished yet (fewer than 64) to the front
+      float mu = 0.f, mv = 0.f;
+      uint32_t mk = 0, mp = 0;
+      const uint32_t rest = cn - n;
+      keep = uint32_t(lane) < rest;
+      if (keep) {
+        mu = L.cu[n + lane];
+        mv = L.cv[n + lane];
+        mk = L.ck[n + lane];
+        mp = L.cp[n + lane];
+      }
+      __syncthreads();
+      if (keep) {
+        L.cu[lane] = mu;
+        L.cv[lane] = mv;
+        L.ck[lane] = mk;
+        L.cp[lane] = mp;
+      }
+      cn = rest;
+      __syncthreads();
+    };
+
+    while (true) {
+      // refill the pool from the next 64 leaf slots until it holds a pass
+      while (pn < uint32_t(BBC_WAVE) && scan < tot) {
+        const uint32_t j = scan + uint32_t(lane);
+        bool take = false;
+        Start32 st{};
+        uint32_t p = 0, kk = 0;
+        if (j < tot) {
+          int lo = 0, hi = BBC_WAVE - 1;  // the pair whose slots hold j: the last with lscan[p] <= j
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.lscan[mid] <= j) lo = mid; else hi = mid - 1;
+          }
+          p = uint32_t(lo);
+          kk = L.lb[p] + (j - L.lscan[p]);
+          const float4 uk = a.luk[kk];
+          const double ud = L.tud[p], vd = L.tvd[p];
+          if (ud >= uk.x && ud <= uk.y && vd >= uk.z && vd <= uk.w) {
+            take = true;
+            const float* R = &L.rec[p * RS];
+            st = start_of(a.lcode[kk], R[24], R[25], R[26], R[27]);
+            ++wc.starts;
+          }
+        }
+        const uint64_t m = __ballot(take);
+        if (take) {
+          const uint32_t q = (head + pn + uint32_t(__popcll(m & below))) % uint32_t(kPool);
+          L.pu[q] = st.u;
+          L.pv[q] = st.v;
+          L.plu0[q] = st.lu0;
+          L.plu1[q] = st.lu1;
+          L.plv0[q] = st.lv0;
+          L.plv1[q] = st.lv1;
+          L.pprev[q] = st.prev;
+          L.ptl[q] = st.t_last;
+          L.pk[q] = kk;
+          L.pmeta[q] = p;
+        }
+        pn += uint32_t(__popcll(m));
+        scan += uint32_t(BBC_WAVE);
+      }
+      if (pn == 0u) break;
+      __syncthreads();
+      // one pass of FP32 iterations over (up to) 64 starts
+      const uint32_t tk = min(pn, uint32_t(BBC_WAVE));
+      const bool act = uint32_t(lane) < tk;
+      int status = 1;
+      Start32 st{};
+      uint32_t p = 0, kk = 0;
+      if (act) {
+        const uint32_t q = (head + uint32_t(lane)) % uint32_t(kPool);
+        st.u = L.pu[q];
+        st.v = L.pv[q];
+        st.lu0 = L.plu0[q];
+        st.lu1 = L.plu1[q];
+        st.lv0 = L.plv0[q];
+        st.lv1 = L.plv1[q];
+        st.prev = L.pprev[q];
+        st.t_last = L.ptl[q];
+        kk = L.pk[q];
+        const uint32_t meta = L.pmeta[q];
+        p = meta & 0xffu;
+        st.it = int(meta >> 8);
+        const TupleGeom<float> Gf = tuple_geom_rec<float, RR>(&L.rec[p * RS], a.sc);
+        status = newton32<CH>(Gf, L.tu[p], L.tv[p], st, steps, wc);
+      }
+      head = (head + tk) % uint32_t(kPool);
+      pn -= tk;
+      __syncthreads();
+      const bool again = act && status == 0;
+      const uint64_t mr = __ballot(again);
+      if (again) {
+        const uint32_t q = (head + pn + uint32_t(__popcll(mr & below))) % uint32_t(kPool);
+        L.pu[q] = st.u;
+        L.pv[q] = st.v;
+        L.plu0[q] = st.lu0;
+        L.plu1[q] = st.lu1;
+        L.plv0[q] = st.lv0;
+        L.plv1[q] = st.lv1;
+        L.pprev[q] = st.prev;
+        L.ptl[q] = st.t_last;
+        L.pk[q] = kk;
+        L.pmeta[q] = p | (uint32_t(st.it) << 8);
+      }
+      pn += uint32_t(__popcll(mr));
+      const bool cand = act && status == 2 && worth_polish(st);
+      const uint64_t mc = __ballot(cand);
+      if (cand) {
+        const uint32_t c = cn + uint32_t(__popcll(mc & below));
+        L.cu[c] = st.u;
+        L.cv[c] = st.v;
+        L.ck[c] = kk;
+        L.cp[c] = p;
+      }
+      cn += uint32_t(__popcll(mc));
+      __syncthreads();
+      if (cn >= uint32_t(BBC_WAVE)) polish(uint32_t(BBC_WAVE));
+    }
+    while (cn > 0u) polish(min(cn, uint32_t(BBC_WAVE)));
+    __syncthreads();
+
+    // each pair's roots in leaf order (the order of its starts)
+    if (valid) {
+      const uint32_t r0 = wc.roots;
+      double ET;
+      if (L.redo[lane]) {
+        WorkCount again;
+        ET = tuple_irradiance<CH>(a, T, tg, again);
+        wc.roots += again.roots;
+      } else {
+        RootSum rs;
+        uint32_t last = 0;
+        bool first = true;
+        while (true) {
+          uint32_t best = 0xffffffffu;
+          int bi = -1;
+          for (uint32_t r = 0; r < rn; ++r) {
+            if (L.rp[r] != uint32_t(lane)) continue;
+            const uint32_t kr = L.rk[r];
+            if ((first || kr > last) && kr < best) {
+              best = kr;
+              bi = int(r);
+            }
+          }
+          if (bi < 0) break;
+          rs.add(L.rud[bi], L.rvd[bi], L.rE[bi], wc);
+          last = best;
+          first = false;
+        }
+        ET = rs.ET;
+      }
+      ++wc.pairs;
+      s.pair_c[k] = ET / double(s.pair_p[k]);
+      if (a.stats) s.pair_nr[k] = uint8_t(min(wc.roots - r0, 255u));
+    }
+    __syncthreads();
+  }
+  flush_counts(a, wc);
+}
+
 // Sum of each point's contributions in pair order (entry order of its cell),
 // and the optional per-point statistics: |U|, |S|, roots, sum of E~^2 / P.
 __global__ void k_stage_accum(StagedArgs s) {
@@ -595,10 +916,29 @@ void staged_carve(void* base, int64_t n, size_t pairs, StagedWork& w) {
   w.pairs = up;
 }
 
+// Workgroups of a pooled Newton kernel that fit on the device at once (its
+// LDS and registers allow a few per compute unit), cached per device and chain.
+template <typename K>
+static bbc_status pool_grid(K kernel, int chain, int* out) {
+  static std::atomic<int> cache[64][3];
+  int dev = 0;
+  BBC_HIP(hipGetDevice(&dev));
+  if (dev < 64 && chain >= 0 && chain < 3 && cache[dev][chain].load() > 0) {
+    *out = cache[dev][chain].load();
+    return BBC_OK;
+  }
+  int per_cu = 0, n_cu = 0;
+  BBC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), 64, 0));
+  BBC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  *out = std::max(1, per_cu) * std::max(1, n_cu);
+  if (dev < 64 && chain >= 0 && chain < 3) cache[dev][chain].store(*out);
+  return BBC_OK;
+}
+
 // The five stage launches of one staged query; events (nullable) bracket the
 // Newton kernel.
-static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pairs, hipEvent_t ev0, hipEvent_t ev1,
-                             hipStream_t st) {
+static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pairs, int newton_steps,
+                             hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
   const int64_t n = q.n;
   StagedArgs s{};
   s.q = q;
@@ -623,13 +963,35 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   if (e) return e;
   hipLaunchKernelGGL(k_stage_fill, dim3(grid), dim3(64), 0, st, s);
   if (ev0) BBC_HIP(hipEventRecord(ev0, st));
-  const unsigned gp = unsigned(std::min<size_t>((pairs + 63) / 64, 32768));
-  if (q.sc.chain == BBC_CHAIN_RR)
-    hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_RR>, dim3(gp), dim3(64), 0, st, s, s.off + n);
-  else if (q.sc.chain == BBC_CHAIN_T)
-    hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_T>, dim3(gp), dim3(64), 0, st, s, s.off + n);
-  else
-    hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_R>, dim3(gp), dim3(64), 0, st, s, s.off + n);
+  if (newton_steps > 0) {
+    // as many workgroups as stay resident together; they take batches of 64
+    // pairs from the counter at off[n + 1] (cleared by k_stage_gamma)
+    int nres = 0;
+    if (q.sc.chain == BBC_CHAIN_RR) {
+      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_RR>, BBC_CHAIN_RR, &nres))) return e;
+      const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
+      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_RR>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
+                         newton_steps);
+    } else if (q.sc.chain == BBC_CHAIN_T) {
+      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_T>, BBC_CHAIN_T, &nres))) return e;
+      const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
+      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_T>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
+                         newton_steps);
+    } else {
+      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_R>, BBC_CHAIN_R, &nres))) return e;
+      const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
+      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_R>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
+                         newton_steps);
+    }
+  } else {
+    const unsigned gp = unsigned(std::min<size_t>((pairs + 63) / 64, 32768));
+    if (q.sc.chain == BBC_CHAIN_RR)
+      hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_RR>, dim3(gp), dim3(64), 0, st, s, s.off + n);
+    else if (q.sc.chain == BBC_CHAIN_T)
+      hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_T>, dim3(gp), dim3(64), 0, st, s, s.off + n);
+    else
+      hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_R>, dim3(gp), dim3(64), 0, st, s, s.off + n);
+  }
   if (ev1) BBC_HIP(hipEventRecord(ev1, st));
   hipLaunchKernelGGL(k_stage_accum, dim3(gpt), dim3(256), 0, st, s);
   BBC_HIP(hipGetLastError());
@@ -649,7 +1011,8 @@ bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t s
   }
   const QueryArgs q = make_args(b, pts, n, spp, seed, base, mode, out, stats, counters);
   const bool timed = b->tune.timing != 0;
-  bbc_status e = run_staged(q, b->qw, b->qw.pairs, timed ? b->ev[0] : nullptr, timed ? b->ev[1] : nullptr, st);
+  bbc_status e = run_staged(q, b->qw, b->qw.pairs, b->tune.newton_steps, timed ? b->ev[0] : nullptr,
+                            timed ? b->ev[1] : nullptr, st);
   if (e) return e;
   if (timed) b->ev_recorded = true;
   return BBC_OK;
@@ -666,7 +1029,7 @@ bbc_status launch_query_batch(const Bounds* b, const float* pts, int64_t n, cons
   QueryArgs q = make_args(b, pts, n, 1, 0, 0, mode, out, nullptr, nullptr);
   q.preq = preq;
   q.reqs = reqs;
-  return run_staged(q, w, w.pairs, ev0, ev1, st);
+  return run_staged(q, w, w.pairs, b->tune.newton_steps, ev0, ev1, st);
 }
 
 }  // namespace bbc
