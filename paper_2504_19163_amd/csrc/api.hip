@@ -55,7 +55,7 @@ void release(DevBuf& b) {
 static void release_all(Bounds* b) {
   DevBuf* all[] = {&b->pos, &b->nrm, &b->epos, &b->eI, &b->counters, &b->root, &b->init_q, &b->l0f_q, &b->q[0],
                    &b->q[1], &b->fq, &b->lt, &b->lc, &b->lu, &b->le, &b->gl_t, &b->gl_c, &b->gl_u, &b->gl_e, &b->st, &b->sc, &b->su, &b->se, &b->tcount,
-                   &b->toff, &b->tcur, &b->trip, &b->ccount, &b->coff, &b->ccur, &b->ut, &b->ue, &b->ucell, &b->gt, &b->ge,
+                   &b->toff, &b->tcur, &b->lrect, &b->lcoarse, &b->ccount, &b->coff, &b->gt, &b->ge,
                    &b->scan_tmp, &b->trec, &b->pos2, &b->nrm2, &b->box2, &b->rowcount, &b->rowoff, &b->tid,
                    &b->qw_buf, &b->max_cell_dev, &b->qcounters};
   for (DevBuf* d : all) release(*d);
@@ -111,7 +111,7 @@ static bbc_status run_build(Bounds* b, hipStream_t s) {
     b->q_cap = size_t(std::max<int64_t>(4 * b->n_tuples, 1 << 20));
     b->fq_cap = b->q_cap;
     b->leaf_cap = b->q_cap;
-    b->trip_cap = size_t(32) << 20;
+    b->grid_cap = size_t(32) << 20;
   }
   for (int attempt = 0; attempt < 5; ++attempt) {
     if ((e = ensure(b->counters, sizeof(BuildCounters), b)) || (e = ensure(b->root, b->n_tuples * 16, b)) ||
@@ -125,11 +125,9 @@ static bbc_status run_build(Bounds* b, hipStream_t s) {
         (e = ensure(b->sc, b->leaf_cap * 4, b)) || (e = ensure(b->su, b->leaf_cap * 16, b)) ||
         (e = ensure(b->se, b->leaf_cap * 8, b)) || (e = ensure(b->tcount, b->n_tuples * 4, b)) ||
         (e = ensure(b->toff, (b->n_tuples + 1) * 4, b)) || (e = ensure(b->tcur, b->n_tuples * 4, b)) ||
-        (e = ensure(b->trip, b->trip_cap * 12, b)) || (e = ensure(b->ccount, ncell * 4, b)) ||
-        (e = ensure(b->coff, (ncell + 1) * 4, b)) || (e = ensure(b->ccur, ncell * 4, b)) ||
-        (e = ensure(b->ut, b->trip_cap * 4, b)) || (e = ensure(b->ue, b->trip_cap * 4, b)) ||
-        (e = ensure(b->ucell, b->trip_cap * 4, b)) || (e = ensure(b->gt, b->trip_cap * 4, b)) ||
-        (e = ensure(b->ge, b->trip_cap * 4, b)) ||
+        (e = ensure(b->lrect, b->leaf_cap * 16, b)) || (e = ensure(b->lcoarse, (b->leaf_cap + 3 * 2048) * 4, b)) || (e = ensure(b->ccount, ncell * 4, b)) ||
+        (e = ensure(b->coff, (ncell + 1) * 4, b)) || (e = ensure(b->gt, b->grid_cap * 4, b)) ||
+        (e = ensure(b->ge, b->grid_cap * 4, b)) ||
         (e = ensure(b->scan_tmp, scan_tmp_bytes(std::max(ncell, b->n_tuples)) + 64, b)) ||
         (e = ensure(b->trec, size_t(std::max<int64_t>(b->n_tuples, 1)) * b->rec_floats * 4, b)) ||
         (e = ensure(b->max_cell_dev, 64, b)))
@@ -152,8 +150,8 @@ static bbc_status run_build(Bounds* b, hipStream_t s) {
       b->fq_cap *= 4;
       b->leaf_cap *= 4;
     }
-    if (ov & 4u) b->trip_cap = std::max<size_t>(b->trip_cap * 2, size_t(b->host.n_triples) + 1024);
-    if (b->q_cap > (size_t(1) << 31) || b->trip_cap > (size_t(1) << 31)) break;
+    if (ov & 4u) b->grid_cap = std::max<size_t>(b->grid_cap * 2, size_t(b->host.n_triples) + 1024);
+    if (b->q_cap > (size_t(1) << 31) || b->grid_cap > (size_t(1) << 31)) break;
   }
   const uint32_t ov = b->host.overflow;
   std::string what;

@@ -41,7 +41,7 @@ struct BuildCounters {
   uint32_t n_live;                 // tuples with a root box
   uint32_t overflow;               // bit flags: 1 queue, 2 leaves, 4 grid entries, 8 fp64 queue, 16 init
   uint32_t max_depth;
-  uint32_t n_triples;              // reserved triple slots (chunks; some unused)
+  uint32_t n_triples;              // grid entries wanted when they overflowed the capacity
   uint32_t n_entries;              // (cell, tuple) entries of the grid
   uint32_t n_inf;
   uint32_t qcount[kMaxDepth + 2];  // items at each depth
@@ -108,10 +108,10 @@ struct Bounds {
   size_t leaf_cap = 0;
   DevBuf tcount, toff, tcur;  // per-tuple counts / offsets [n_tuples + 1] / cursors
   // receiver grid
-  DevBuf trip;                // triples: cell u32, tuple u32, E float
-  size_t trip_cap = 0;
-  DevBuf ccount, coff, ccur;  // per-cell counts / offsets [G*G + 1] / cursors
-  DevBuf ut, ue, ucell;       // entries grouped by cell (unsorted)
+  DevBuf lrect;               // cell rectangle, tuple and E_hi of each sorted leaf
+  DevBuf lcoarse;             // the rectangle in tiles of 16 cells (padded by two scan steps)
+  size_t grid_cap = 0;        // capacity of the grid entry arrays gt / ge
+  DevBuf ccount, coff;        // per-cell counts / offsets [G*G + 1]
   DevBuf gt, ge;              // entries: tuple u32, E~ float, sorted by tuple per cell
   DevBuf scan_tmp;
   DevBuf trec;                // packed per-tuple records for the query [n_tuples][32] float

@@ -5,10 +5,9 @@
 //
 // Kernels (all counts read from device memory, no host synchronisation):
 //   k_leaf_count / scan / k_leaf_scatter / k_leaf_rank   leaves grouped by tuple
-//   k_grid_tuple   one 256-thread workgroup per tuple: the union of its leaves'
-//                  cell rectangles is rasterised in LDS bands with an atomic
-//                  max, then the occupied cells are emitted as triples
-//   scan / k_grid_scatter / k_grid_rank                   triples -> CSR by cell
+//   k_leaf_rects   cell rectangle of every leaf
+//   k_grid_cells<false> / scan / k_grid_cells<true>      entries per cell, then
+//                  the CSR, one workgroup per 16 x 16 tile of cells
 //   k_tuple_records  one packed 128-byte record per tuple for the query stage
 #include "internal.hpp"
 
@@ -105,7 +104,7 @@ bbc_status launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* t
 struct RecArgs {
   BuildCounters* C;
   int64_t n_tuples;
-  uint32_t leaf_cap, trip_cap;
+  uint32_t leaf_cap, grid_cap;
   int G;
   const uint32_t* lt;
   const uint32_t* lc;
@@ -122,14 +121,11 @@ struct RecArgs {
   uint32_t* sc;
   float4* su;
   float2* se;
-  uint32_t* trip;  // [3][trip_cap]: cell, tuple, E bits
+  uint4* lrect;     // cell rectangle, tuple and E_hi bits of each sorted leaf
+  uint32_t* lcoarse;  // rectangle in tiles of each sorted leaf (padded with empty ones)
   uint32_t* ccount;
   uint32_t* coff;
-  uint32_t* ccur;
-  uint32_t* ut;     // entries grouped by cell, arbitrary order inside a cell
-  float* ue;
-  uint32_t* ucell;
-  uint32_t* gt;     // final entries, sorted by tuple inside each cell
+  uint32_t* gt;     // entries, sorted by tuple inside each cell
   float* ge;
   uint32_t* max_cell;
 };
@@ -175,139 +171,183 @@ __device__ __forceinline__ int cell_of(float x, int G) {
   return min(G - 1, max(0, int(c)));
 }
 
-constexpr int kGridThreads = 256;
-constexpr int kTile = 16384;  // cells rasterised per LDS band
+// What the grid needs of every leaf (in the tuple order of the sorted
+// leaves), in one 16-byte record: its closed cell rectangle packed as
+// (cu0 | cu1 << 16, cv0 | cv1 << 16), its tuple, and the bits of its E_hi
+// (E_hi >= 0, so the bit order is the value order); and, for the scan of the
+// grid kernel, the rectangle in units of 16-cell tiles in one word
+// (tu0 | tu1 << 8 | tv0 << 16 | tv1 << 24; grid_res <= 4096 keeps tile
+// indices below 256).  Coarse words from the last leaf up to two scan steps
+// beyond it hold an empty rectangle (tu0 = 255 > tu1 = 0).
+constexpr int kCellTile = 16, kCellThreads = kCellTile * kCellTile;
+constexpr int kPerThread = 8, kChunk = kCellThreads * kPerThread;  // leaves tested per scan step
+constexpr uint32_t kEmptyCoarse = 0x000000ffu;
 
-// Triple slots are reserved in chunks of kTripChunk per workgroup (one global
-// atomic per chunk, not per tuple); unused slots of a chunk are marked with
-// kNoCell and skipped by the scatter.
-constexpr uint32_t kTripChunk = 256, kNoCell = 0xffffffffu;
-
-__device__ void mark_unused(const RecArgs& a, uint32_t b, uint32_t e) {
-  for (uint32_t i = b + threadIdx.x; i < e && i < a.trip_cap; i += kGridThreads) a.trip[i] = kNoCell;
-}
-
-__global__ void __launch_bounds__(kGridThreads) k_grid_tuple(RecArgs a) {
-  __shared__ uint32_t tile[kTile];
-  __shared__ int rect[4];
-  __shared__ uint32_t base_slot, chunk_b, chunk_e, drop_b, drop_e, n_real;
-  const int G = a.G;
-  if (threadIdx.x == 0) chunk_b = chunk_e = n_real = 0u;
-  __syncthreads();
-  for (int64_t t = blockIdx.x; t < a.n_tuples; t += gridDim.x) {
-    const uint32_t lb = a.toff[t], le = a.toff[t + 1];
-    if (lb == le) continue;
-    // union of the leaves' cell rectangles
-    int cu0 = G, cu1 = -1, cv0 = G, cv1 = -1;
-    for (uint32_t k = lb + threadIdx.x; k < le; k += kGridThreads) {
-      const float4 u = a.su[k];
-      cu0 = min(cu0, cell_of(u.x, G));
-      cu1 = max(cu1, cell_of(u.y, G));
-      cv0 = min(cv0, cell_of(u.z, G));
-      cv1 = max(cv1, cell_of(u.w, G));
+__global__ void k_leaf_rects(RecArgs a) {
+  const uint32_t n = min(a.C->n_leaves, a.leaf_cap);
+  const uint32_t n_pad = (n + uint32_t(kChunk) - 1) / uint32_t(kChunk) * uint32_t(kChunk) + uint32_t(kChunk);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += gridDim.x * blockDim.x) {
+    if (i >= n) {
+      a.lcoarse[i] = kEmptyCoarse;
+      continue;
     }
-    cu0 = wave_min(cu0); cu1 = wave_max(cu1); cv0 = wave_min(cv0); cv1 = wave_max(cv1);
-    if (threadIdx.x == 0) { rect[0] = G; rect[1] = -1; rect[2] = G; rect[3] = -1; }
-    __syncthreads();
-    if (threadIdx.x % BBC_WAVE == 0) {
-      atomicMin(&rect[0], cu0); atomicMax(&rect[1], cu1); atomicMin(&rect[2], cv0); atomicMax(&rect[3], cv1);
-    }
-    __syncthreads();
-    cu0 = rect[0]; cu1 = rect[1]; cv0 = rect[2]; cv1 = rect[3];
-    const int W = cv1 - cv0 + 1;
-    const int rows = max(1, kTile / W);
-    __syncthreads();
-    for (int r0 = cu0; r0 <= cu1; r0 += rows) {
-      const int r1 = min(cu1, r0 + rows - 1);
-      const int ncell = (r1 - r0 + 1) * W;
-      for (int i = threadIdx.x; i < ncell; i += kGridThreads) tile[i] = 0u;
-      __syncthreads();
-      for (uint32_t k = lb; k < le; ++k) {
-        const float4 u = a.su[k];
-        const int a0 = max(r0, cell_of(u.x, G)), a1 = min(r1, cell_of(u.y, G));
-        if (a0 > a1) continue;
-        const int b0 = cell_of(u.z, G), b1 = cell_of(u.w, G);
-        const int bw = b1 - b0 + 1;
-        const uint32_t key = __float_as_uint(a.se[k].y) + 1u;  // E_hi >= 0: bit order is value order
-        const int cnt = (a1 - a0 + 1) * bw;
-        for (int i = threadIdx.x; i < cnt; i += kGridThreads) {
-          const int ru = a0 + i / bw, cv = b0 + i % bw;
-          atomicMax(&tile[(ru - r0) * W + (cv - cv0)], key);
-        }
-      }
-      __syncthreads();
-      // emit the occupied cells of the band
-      uint32_t mine = 0;
-      for (int i = threadIdx.x; i < ncell; i += kGridThreads) mine += tile[i] != 0u;
-      uint32_t tot;
-      uint32_t off = block_exclusive_scan(mine, &tot);
-      if (threadIdx.x == 0) {
-        drop_b = drop_e = 0u;
-        if (tot > chunk_e - chunk_b) {  // a fresh chunk; the rest of the old one is marked unused
-          drop_b = chunk_b;
-          drop_e = chunk_e;
-          const uint32_t want = max(tot, kTripChunk);
-          chunk_b = atomicAdd(&a.C->n_triples, want);
-          chunk_e = chunk_b + want;
-        }
-        base_slot = chunk_b;
-        chunk_b += tot;
-        n_real += tot;
-      }
-      __syncthreads();
-      mark_unused(a, drop_b, drop_e);
-      const uint32_t bs = base_slot;
-      if (bs + tot > a.trip_cap) {
-        if (threadIdx.x == 0 && tot) atomicOr(&a.C->overflow, 4u);
-      } else {
-        for (int i = threadIdx.x; i < ncell; i += kGridThreads) {
-          const uint32_t key = tile[i];
-          if (!key) continue;
-          const uint32_t cell = uint32_t(r0 + i / W) * uint32_t(G) + uint32_t(cv0 + i % W);
-          const uint32_t slot = bs + off++;
-          a.trip[slot] = cell;
-          a.trip[a.trip_cap + slot] = uint32_t(t);
-          a.trip[2 * size_t(a.trip_cap) + slot] = key - 1u;
-          atomicAdd(&a.ccount[cell], 1u);
-        }
-      }
-      __syncthreads();
-    }
-  }
-  mark_unused(a, chunk_b, chunk_e);
-  if (threadIdx.x == 0 && n_real) atomicAdd(&a.C->n_entries, n_real);
-}
-
-// Triples -> cells: first grouped by cell in arbitrary order, then each entry
-// ranks its tuple id among its cell's entries (tuple ids are unique within a
-// cell) and moves to its final slot, so every cell list is sorted by tuple.
-__global__ void k_grid_scatter(RecArgs a) {
-  const uint32_t n = min(a.C->n_triples, a.trip_cap);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t cell = a.trip[i];
-    if (cell == kNoCell) continue;
-    const uint32_t p = a.coff[cell] + atomicAdd(&a.ccur[cell], 1u);
-    a.ut[p] = a.trip[a.trip_cap + i];
-    a.ue[p] = __uint_as_float(a.trip[2 * size_t(a.trip_cap) + i]);
-    a.ucell[p] = cell;
+    const float4 u = a.su[i];
+    const uint32_t cu0 = uint32_t(cell_of(u.x, a.G)), cu1 = uint32_t(cell_of(u.y, a.G));
+    const uint32_t cv0 = uint32_t(cell_of(u.z, a.G)), cv1 = uint32_t(cell_of(u.w, a.G));
+    a.lrect[i] = make_uint4(cu0 | cu1 << 16, cv0 | cv1 << 16, a.st[i], __float_as_uint(a.se[i].y));
+    a.lcoarse[i] = (cu0 / kCellTile) | (cu1 / kCellTile) << 8 | (cv0 / kCellTile) << 16 | (cv1 / kCellTile) << 24;
   }
 }
 
-__global__ void k_grid_rank(RecArgs a) {
-  const uint32_t n = a.coff[uint32_t(a.G) * uint32_t(a.G)];  // entries scattered into the cells
+// Cell-major rasterisation.  One workgroup per tile of 16 x 16 cells, one
+// thread per cell.  The workgroup scans all leaves in their tuple order,
+// keeps those whose rectangle meets the tile (in order, in LDS), and each
+// thread walks that list: consecutive leaves of one tuple that touch its cell
+// merge into one entry with the maximum E_hi, and a new tuple closes the
+// previous entry.  Each cell's list therefore comes out sorted by tuple, with
+// no atomics on cells and no sort.  WRITE = false counts the entries per cell
+// (and the largest cell); WRITE = true writes them at the scanned offsets.
+constexpr int kLeafBuf = kChunk + 1024;  // leaves meeting the tile, staged per flush
+constexpr uint32_t kNoRect = 0u;
+
+// Bits lo..hi of a 16-bit mask (empty when lo > hi).
+__device__ __forceinline__ uint32_t span_mask(int lo, int hi) {
+  return lo > hi ? 0u : ((0xffffu >> (15 - hi)) & (0xffffu << lo));
+}
+constexpr uint32_t kNoTuple = 0xffffffffu;
+
+template <bool WRITE>
+__global__ void __launch_bounds__(kCellThreads) k_grid_cells(RecArgs a) {
+  __shared__ __align__(16) uint32_t s_t[kLeafBuf + 4], s_key[kLeafBuf + 4], s_rect[kLeafBuf + 4];
+  // s_t holds the leaf index until the staged leaves are resolved before a walk
+  const int G = a.G, tid = int(threadIdx.x), lane = tid % BBC_WAVE;
+  const uint32_t n = min(a.C->n_leaves, a.leaf_cap);
+  const int nt = (G + kCellTile - 1) / kCellTile;
+  const uint32_t total = WRITE ? a.coff[uint32_t(G) * uint32_t(G)] : 0u;
+  if (WRITE && total > a.grid_cap) {
+    if (blockIdx.x == 0 && tid == 0) {
+      atomicOr(&a.C->overflow, 4u);
+      a.C->n_triples = total;
+    }
+    return;
+  }
+  if (WRITE && blockIdx.x == 0 && tid == 0) a.C->n_entries = total;
   uint32_t mx = 0;
-  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-    const uint32_t cell = a.ucell[p];
-    const uint32_t b = a.coff[cell], e = a.coff[cell + 1];
-    const uint32_t t = a.ut[p];
-    uint32_t r = 0;
-    for (uint32_t j = b; j < e; ++j) r += a.ut[j] < t ? 1u : 0u;
-    a.gt[b + r] = t;
-    a.ge[b + r] = a.ue[p];
-    mx = max(mx, e - b);
+  for (int tile = blockIdx.x; tile < nt * nt; tile += gridDim.x) {
+    const int tu0 = (tile / nt) * kCellTile, tv0 = (tile % nt) * kCellTile;
+    const int lu = tid / kCellTile, lv = tid % kCellTile;
+    const int cu = tu0 + lu, cv = tv0 + lv;
+    const bool inside = cu < G && cv < G;
+    const uint32_t cell = uint32_t(cu) * uint32_t(G) + uint32_t(cv);
+    uint32_t p = (WRITE && inside) ? a.coff[cell] : 0u;
+    uint32_t cnt = 0, last_t = kNoTuple, last_key = 0u;
+    uint32_t nb = 0;  // leaves staged in LDS (the same in every thread)
+    // the leaf's cell rectangle inside the tile as two 16-bit masks (rows in
+    // the low half, columns in the high half); this cell's bits:
+    const uint32_t bu = 1u << lu, bv = 1u << (16 + lv);
+    auto visit = [&](uint32_t t, uint32_t key) {
+      if (t == last_t) {
+        last_key = max(last_key, key);
+        return;
+      }
+      if (last_t != kNoTuple) {
+        if (WRITE) {
+          a.gt[p] = last_t;
+          a.ge[p] = __uint_as_float(last_key);
+          ++p;
+        }
+        ++cnt;
+      }
+      last_t = t;
+      last_key = key;
+    };
+    // four staged leaves per step (the list is padded with empty masks); the
+    // staged leaf indices are first replaced by the leaves' tuples, E_hi bits
+    // and rectangle masks (one load per staged leaf, spread over the block)
+    auto walk = [&]() {
+      for (uint32_t i = uint32_t(tid); i < nb; i += kCellThreads) {
+        const uint4 r = a.lrect[s_t[i]];
+        const int u0 = int(r.x & 0xffffu), u1 = int(r.x >> 16), v0 = int(r.y & 0xffffu), v1 = int(r.y >> 16);
+        s_rect[i] = span_mask(max(u0 - tu0, 0), min(u1 - tu0, kCellTile - 1)) |
+                    span_mask(max(v0 - tv0, 0), min(v1 - tv0, kCellTile - 1)) << 16;
+        s_t[i] = r.z;
+        s_key[i] = r.w;
+      }
+      if (tid < 4) s_rect[nb + tid] = kNoRect;  // pad to a multiple of four
+      __syncthreads();
+      if (!inside) return;
+      for (uint32_t i = 0; i < nb; i += 4) {
+        const uint4 m = *reinterpret_cast<const uint4*>(&s_rect[i]);
+        const bool h0 = (m.x & bu) && (m.x & bv), h1 = (m.y & bu) && (m.y & bv);
+        const bool h2 = (m.z & bu) && (m.z & bv), h3 = (m.w & bu) && (m.w & bv);
+        if (!(h0 || h1 || h2 || h3)) continue;
+        const uint4 t = *reinterpret_cast<const uint4*>(&s_t[i]);
+        const uint4 k = *reinterpret_cast<const uint4*>(&s_key[i]);
+        if (h0) visit(t.x, k.x);
+        if (h1) visit(t.y, k.y);
+        if (h2) visit(t.z, k.z);
+        if (h3) visit(t.w, k.w);
+      }
+    };
+    // Leaves are tested kChunk at a time on their coarse words, kPerThread
+    // consecutive ones per thread, so that one block scan orders the hits;
+    // the next step's words are loaded while the current ones are tested (two
+    // register buffers in turn).  Only the indices of hits are staged.
+    const uint32_t ti = uint32_t(tu0 / kCellTile), tj = uint32_t(tv0 / kCellTile);
+    const uint4* coarse4 = reinterpret_cast<const uint4*>(a.lcoarse);
+    uint4 ra[kPerThread / 4], rb[kPerThread / 4];
+    auto load = [&](uint4* r, uint32_t base) {
+#pragma unroll
+      for (int c = 0; c < kPerThread / 4; ++c) r[c] = coarse4[(base + uint32_t(tid * kPerThread)) / 4 + c];
+    };
+    auto test = [&](const uint4* r, uint32_t base) {
+      if (base >= n) return;
+      uint32_t hitmask = 0;
+#pragma unroll
+      for (int c = 0; c < kPerThread; ++c) {
+        const uint32_t w = c % 4 == 0 ? r[c / 4].x : c % 4 == 1 ? r[c / 4].y : c % 4 == 2 ? r[c / 4].z : r[c / 4].w;
+        const bool hit = (w & 0xffu) <= ti && ((w >> 8) & 0xffu) >= ti && ((w >> 16) & 0xffu) <= tj && (w >> 24) >= tj;
+        hitmask |= hit ? 1u << c : 0u;
+      }
+      if (!__syncthreads_or(int(hitmask))) return;
+      uint32_t tot;
+      uint32_t q = nb + block_exclusive_scan(uint32_t(__popc(hitmask)), &tot);
+#pragma unroll
+      for (int c = 0; c < kPerThread; ++c)
+        if (hitmask & (1u << c)) s_t[q++] = base + uint32_t(tid * kPerThread + c);
+      nb += tot;
+      __syncthreads();
+      if (nb > uint32_t(kLeafBuf - kChunk)) {
+        walk();
+        nb = 0;
+        __syncthreads();
+      }
+    };
+    load(ra, 0u);
+    for (uint32_t k0 = 0; k0 < n; k0 += 2 * kChunk) {
+      load(rb, k0 + kChunk);
+      test(ra, k0);
+      load(ra, k0 + 2 * kChunk);
+      test(rb, k0 + kChunk);
+    }
+    walk();
+    if (inside) {
+      if (last_t != kNoTuple) {
+        if (WRITE) {
+          a.gt[p] = last_t;
+          a.ge[p] = __uint_as_float(last_key);
+        }
+        ++cnt;
+      }
+      if (!WRITE) a.ccount[cell] = cnt;
+    }
+    mx = max(mx, cnt);
+    __syncthreads();
   }
-  mx = wave_max(mx);
-  if (threadIdx.x % BBC_WAVE == 0 && mx) atomicMax(a.max_cell, mx);
+  if (!WRITE) {
+    mx = wave_max(mx);
+    if (lane == 0 && mx) atomicMax(a.max_cell, mx);
+  }
 }
 
 // One packed record per tuple with leaves (see geom_dev.hpp).
@@ -350,7 +390,7 @@ bbc_status launch_record(Bounds* b, hipStream_t s) {
   a.C = static_cast<BuildCounters*>(b->counters.p);
   a.n_tuples = b->n_tuples;
   a.leaf_cap = uint32_t(b->leaf_cap);
-  a.trip_cap = uint32_t(b->trip_cap);
+  a.grid_cap = uint32_t(b->grid_cap);
   a.G = b->params.grid_res;
   a.lt = static_cast<uint32_t*>(b->lt.p);
   a.lc = static_cast<uint32_t*>(b->lc.p);
@@ -367,13 +407,10 @@ bbc_status launch_record(Bounds* b, hipStream_t s) {
   a.sc = static_cast<uint32_t*>(b->sc.p);
   a.su = static_cast<float4*>(b->su.p);
   a.se = static_cast<float2*>(b->se.p);
-  a.trip = static_cast<uint32_t*>(b->trip.p);
+  a.lrect = static_cast<uint4*>(b->lrect.p);
+  a.lcoarse = static_cast<uint32_t*>(b->lcoarse.p);
   a.ccount = static_cast<uint32_t*>(b->ccount.p);
   a.coff = static_cast<uint32_t*>(b->coff.p);
-  a.ccur = static_cast<uint32_t*>(b->ccur.p);
-  a.ut = static_cast<uint32_t*>(b->ut.p);
-  a.ue = static_cast<float*>(b->ue.p);
-  a.ucell = static_cast<uint32_t*>(b->ucell.p);
   a.gt = static_cast<uint32_t*>(b->gt.p);
   a.ge = static_cast<float*>(b->ge.p);
   a.max_cell = static_cast<uint32_t*>(b->max_cell_dev.p);
@@ -381,18 +418,18 @@ bbc_status launch_record(Bounds* b, hipStream_t s) {
   bbc_status st;
   if ((st = launch_fill_u32(a.tcount, 0, b->n_tuples, s))) return st;
   if ((st = launch_fill_u32(a.tcur, 0, b->n_tuples, s))) return st;
-  if ((st = launch_fill_u32(a.ccount, 0, ncell, s))) return st;
-  if ((st = launch_fill_u32(a.ccur, 0, ncell, s))) return st;
   if ((st = launch_fill_u32(a.max_cell, 0, 1, s))) return st;
   const unsigned gl = 2048;
   hipLaunchKernelGGL(k_leaf_count, dim3(gl), dim3(256), 0, s, a);
   if ((st = launch_scan_u32(a.tcount, a.toff, b->n_tuples, b->scan_tmp.p, s))) return st;
   hipLaunchKernelGGL(k_leaf_scatter, dim3(gl), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_leaf_rank, dim3(gl), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_grid_tuple, dim3(4096), dim3(kGridThreads), 0, s, a);
+  hipLaunchKernelGGL(k_leaf_rects, dim3(gl), dim3(256), 0, s, a);
+  const int nt = (a.G + kCellTile - 1) / kCellTile;
+  const unsigned gc = unsigned(nt) * unsigned(nt);
+  hipLaunchKernelGGL(k_grid_cells<false>, dim3(gc), dim3(kCellThreads), 0, s, a);
   if ((st = launch_scan_u32(a.ccount, a.coff, ncell, b->scan_tmp.p, s))) return st;
-  hipLaunchKernelGGL(k_grid_scatter, dim3(gl), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_grid_rank, dim3(gl), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_grid_cells<true>, dim3(gc), dim3(kCellThreads), 0, s, a);
   hipLaunchKernelGGL(k_tuple_records,
                      dim3(unsigned(std::max<int64_t>(1, std::min<int64_t>((b->n_tuples + 255) / 256, 4096)))),
                      dim3(256), 0, s, a, b->scene, static_cast<const float4*>(b->root.p), static_cast<float*>(b->trec.p),
