@@ -60,6 +60,7 @@ struct StagedWork {
   float* gamma = nullptr;
   uint32_t* cnt = nullptr;
   uint32_t* off = nullptr;
+  double2* tgt = nullptr;  // receiver coordinates (u, v) of each point
   void* scan = nullptr;
   uint32_t* pair_pt = nullptr;
   uint32_t* pair_t = nullptr;

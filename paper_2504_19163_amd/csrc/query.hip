@@ -488,6 +488,7 @@ struct StagedArgs {
   uint32_t* cnt;      // [n] |U|
   float* gamma;       // [n]
   uint32_t* off;      // [n + 1] exclusive scan of the selection counts
+  double2* tgt;       // [n] receiver coordinates of the point
   uint32_t* pair_pt;  // [pairs]
   uint32_t* pair_t;
   float* pair_p;
@@ -499,7 +500,6 @@ struct StagedArgs {
 __global__ void k_stage_gamma(StagedArgs s) {
   const QueryArgs& a = s.q;
   const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) s.off[a.n + 1] = 0u;  // work counter of the pooled Newton kernel
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x) {
     const Target tg = receiver_target(a, i);
     uint32_t b = 0, nU = 0;
@@ -512,6 +512,7 @@ __global__ void k_stage_gamma(StagedArgs s) {
     s.cell_b[i] = b;
     s.gamma[i] = gamma;
     s.cnt[i] = nU;
+    s.tgt[i] = make_double2(tg.ud, tg.vd);
   }
 }
 
@@ -615,8 +616,7 @@ struct NewtonPool {
 };
 
 template <int CH>
-__global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* ticket,
-                                                          int steps) {
+__global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const uint32_t* total, int steps) {
   constexpr bool RR = CH == BBC_CHAIN_RR;
   using Pool = NewtonPool<CH>;
   constexpr int NF = Pool::NF, RS = Pool::RS, NREC = RR ? kRecFloatsRR : kRecFloats;
@@ -626,45 +626,87 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
   const uint64_t below = (1ull << lane) - 1ull;
   const uint32_t np = min(*total, s.pair_cap);
   WorkCount wc;
-  while (true) {
-    // the next 64 pairs, taken from a shared counter so that workgroups that
-    // drew cheap pairs take more of them
-    uint32_t batch = 0;
-    if (lane == 0) batch = atomicAdd(ticket, 1u);
-    batch = __shfl(batch, 0, BBC_WAVE);
+  // Batches of 64 pairs, strided over a grid that is resident as a whole (a
+  // shared work counter measured slower: every batch paid a contended
+  // atomic).  A batch's pair data is loaded ahead: its tuple and point while
+  // the previous batch starts, the point's receiver coordinates and the
+  // tuple's leaf range and root box once that batch's refill is done, so a
+  // batch starts with only its tuple records and leaf bounds in flight.
+  const uint32_t stride = gridDim.x;
+  uint32_t nT = 0, nPt = 0, nLb = 0, nCnt = 0;
+  double2 nTgt = make_double2(0.0, 0.0);
+  float4 nRoot = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto fetch_pair = [&](uint32_t b) {
+    const uint64_t kn = uint64_t(b) * BBC_WAVE + uint64_t(lane);
+    if (kn < np) {
+      nT = s.pair_t[kn];
+      nPt = s.pair_pt[kn];
+    }
+  };
+  auto fetch_rest = [&](uint32_t b) {
+    const uint64_t kn = uint64_t(b) * BBC_WAVE + uint64_t(lane);
+    if (kn < np) {
+      nTgt = s.tgt[nPt];  // as receiver_target computed it for the gamma stage
+      nLb = a.toff[nT];
+      nCnt = a.toff[nT + 1] - nLb;
+      nRoot = reinterpret_cast<const float4*>(a.rec + size_t(nT) * NREC)[6];
+    }
+  };
+  fetch_pair(blockIdx.x);
+  fetch_rest(blockIdx.x);
+  for (uint32_t batch = blockIdx.x;; batch += stride) {
     if (uint64_t(batch) * BBC_WAVE >= np) break;
     const uint32_t k = batch * uint32_t(BBC_WAVE) + uint32_t(lane);
     const bool valid = k < np;
+    const uint32_t T = nT, cnt = valid ? nCnt : 0u;
     Target tg{};
-    uint32_t T = 0, cnt = 0;
+    tg.ud = nTgt.x;
+    tg.vd = nTgt.y;
+    tg.u = float(nTgt.x);
+    tg.v = float(nTgt.y);
+    tg.on = true;
     L.redo[lane] = 0u;
+    // the rest of the record (the root box is already here) stays in
+    // registers until the first refill is under way
+    float4 rq[NF / 4];
     if (valid) {
-      T = s.pair_t[k];
-      tg = receiver_target(a, s.pair_pt[k]);
       const float4* r4 = reinterpret_cast<const float4*>(a.rec + size_t(T) * NREC);
-      float* R = &L.rec[lane * RS];
 #pragma unroll
-      for (int q = 0; q < NF / 4; ++q) {
-        const float4 v = r4[q];
-        R[4 * q] = v.x;
-        R[4 * q + 1] = v.y;
-        R[4 * q + 2] = v.z;
-        R[4 * q + 3] = v.w;
-        if (q == 5) {
-          L.lb[lane] = __float_as_uint(v.z);
-          cnt = __float_as_uint(v.w) - __float_as_uint(v.z);
-        }
-      }
+      for (int q = 0; q < NF / 4; ++q)
+        if (q != 6) rq[q] = r4[q];
+      float* R = &L.rec[lane * RS];
+      R[24] = nRoot.x;
+      R[25] = nRoot.y;
+      R[26] = nRoot.z;
+      R[27] = nRoot.w;
+      L.lb[lane] = nLb;
       L.tu[lane] = tg.u;
       L.tv[lane] = tg.v;
       L.tud[lane] = tg.ud;
       L.tvd[lane] = tg.vd;
     }
+    fetch_pair(batch + stride);
     const uint32_t ex = wave_excl_scan(cnt, lane);
     const uint32_t tot = __shfl(ex + cnt, BBC_WAVE - 1, BBC_WAVE);
     L.lscan[lane] = ex;
     if (lane == BBC_WAVE - 1) L.lscan[BBC_WAVE] = tot;
     __syncthreads();
+    bool stored = false;
+    auto store_rec = [&]() {
+      if (valid) {
+        float* R = &L.rec[lane * RS];
+#pragma unroll
+        for (int q = 0; q < NF / 4; ++q) {
+          if (q == 6) continue;
+          R[4 * q] = rq[q].x;
+          R[4 * q + 1] = rq[q].y;
+          R[4 * q + 2] = rq[q].z;
+          R[4 * q + 3] = rq[q].w;
+        }
+      }
+      fetch_rest(batch + stride);
+      stored = true;
+    };
 
     // wave-uniform counters: leaf slots scanned, pool ring head and size,
     // queued candidates, stored roots
@@ -731,11 +773,12 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
           p = uint32_t(lo);
           kk = L.lb[p] + (j - L.lscan[p]);
           const float4 uk = a.luk[kk];
+          const uint32_t code = a.lcode[kk];  // loaded with the bound (one round trip)
           const double ud = L.tud[p], vd = L.tvd[p];
           if (ud >= uk.x && ud <= uk.y && vd >= uk.z && vd <= uk.w) {
             take = true;
             const float* R = &L.rec[p * RS];
-            st = start_of(a.lcode[kk], R[24], R[25], R[26], R[27]);
+            st = start_of(code, R[24], R[25], R[26], R[27]);
             ++wc.starts;
           }
         }
@@ -756,6 +799,7 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
         pn += uint32_t(__popcll(m));
         scan += uint32_t(BBC_WAVE);
       }
+      if (!stored) store_rec();
       if (pn == 0u) break;
       __syncthreads();
       // one pass of FP32 iterations over (up to) 64 starts
@@ -821,9 +865,7 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
       const uint32_t r0 = wc.roots;
       double ET;
       if (L.redo[lane]) {
-        WorkCount again;
-        ET = tuple_irradiance<CH>(a, T, tg, again);
-        wc.roots += again.roots;
+        ET = NAN;  // redone by k_stage_redo
       } else {
         RootSum rs;
         uint32_t last = 0;
@@ -851,6 +893,30 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
       if (a.stats) s.pair_nr[k] = uint8_t(min(wc.roots - r0, 255u));
     }
     __syncthreads();
+  }
+  flush_counts(a, wc);
+}
+
+// Pairs whose accepted roots did not fit the pooled kernel's result buffer
+// (marked with a NaN contribution) are redone one lane per pair.
+template <int CH>
+__global__ void k_stage_redo(StagedArgs s, const uint32_t* total) {
+  const QueryArgs& a = s.q;
+  const uint32_t np = min(*total, s.pair_cap);
+  WorkCount wc;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x) {
+    if (!isnan(s.pair_c[k])) continue;
+    const double2 t2 = s.tgt[s.pair_pt[k]];
+    Target tg{};
+    tg.ud = t2.x;
+    tg.vd = t2.y;
+    tg.u = float(t2.x);
+    tg.v = float(t2.y);
+    tg.on = true;
+    WorkCount w2;
+    s.pair_c[k] = tuple_irradiance<CH>(a, s.pair_t[k], tg, w2) / double(s.pair_p[k]);
+    if (a.stats) s.pair_nr[k] = uint8_t(min(w2.roots, 255u));
+    wc.roots += w2.roots;  // its starts and iterations were counted by the pooled pass
   }
   flush_counts(a, wc);
 }
@@ -890,7 +956,7 @@ size_t staged_pairs(const Bounds* b, int64_t n) { return size_t(n) * size_t(std:
 
 size_t staged_bytes(int64_t n, size_t pairs) {
   const size_t un = size_t(std::max<int64_t>(n, 1)), up = std::max<size_t>(pairs, 1);
-  return 3 * align256(un * 4) + align256((un + 1) * 4 + 8) + align256(scan_tmp_bytes(int64_t(un)) + 64) +
+  return 3 * align256(un * 4) + align256((un + 1) * 4 + 8) + align256(un * 16) + align256(scan_tmp_bytes(int64_t(un)) + 64) +
          3 * align256(up * 4) + align256(up * 8) + align256(up);
 }
 
@@ -906,6 +972,7 @@ void staged_carve(void* base, int64_t n, size_t pairs, StagedWork& w) {
   w.gamma = static_cast<float*>(take(un * 4));
   w.cnt = static_cast<uint32_t*>(take(un * 4));
   w.off = static_cast<uint32_t*>(take((un + 1) * 4 + 8));
+  w.tgt = static_cast<double2*>(take(un * 16));
   w.scan = take(scan_tmp_bytes(int64_t(un)) + 64);
   w.pair_pt = static_cast<uint32_t*>(take(up * 4));
   w.pair_t = static_cast<uint32_t*>(take(up * 4));
@@ -946,6 +1013,7 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   s.gamma = w.gamma;
   s.cnt = w.cnt;
   s.off = w.off;
+  s.tgt = w.tgt;
   s.pair_pt = w.pair_pt;
   s.pair_t = w.pair_t;
   s.pair_p = w.pair_p;
@@ -964,24 +1032,28 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   hipLaunchKernelGGL(k_stage_fill, dim3(grid), dim3(64), 0, st, s);
   if (ev0) BBC_HIP(hipEventRecord(ev0, st));
   if (newton_steps > 0) {
-    // as many workgroups as stay resident together; they take batches of 64
-    // pairs from the counter at off[n + 1] (cleared by k_stage_gamma)
+    // as many workgroups as stay resident together, striding over the
+    // batches of 64 pairs; then the rare pairs to redo
     int nres = 0;
+    const unsigned gr = unsigned(std::min<size_t>((pairs + 255) / 256, 2048));
     if (q.sc.chain == BBC_CHAIN_RR) {
       if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_RR>, BBC_CHAIN_RR, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
-      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_RR>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
-                         newton_steps);
+      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_RR>, dim3(gq), dim3(64), 0, st, s, s.off + n, newton_steps);
+      if (ev1) BBC_HIP(hipEventRecord(ev1, st));
+      hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_RR>, dim3(gr), dim3(256), 0, st, s, s.off + n);
     } else if (q.sc.chain == BBC_CHAIN_T) {
       if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_T>, BBC_CHAIN_T, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
-      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_T>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
-                         newton_steps);
+      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_T>, dim3(gq), dim3(64), 0, st, s, s.off + n, newton_steps);
+      if (ev1) BBC_HIP(hipEventRecord(ev1, st));
+      hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_T>, dim3(gr), dim3(256), 0, st, s, s.off + n);
     } else {
       if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_R>, BBC_CHAIN_R, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
-      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_R>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
-                         newton_steps);
+      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_R>, dim3(gq), dim3(64), 0, st, s, s.off + n, newton_steps);
+      if (ev1) BBC_HIP(hipEventRecord(ev1, st));
+      hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_R>, dim3(gr), dim3(256), 0, st, s, s.off + n);
     }
   } else {
     const unsigned gp = unsigned(std::min<size_t>((pairs + 63) / 64, 32768));
@@ -991,8 +1063,8 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
       hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_T>, dim3(gp), dim3(64), 0, st, s, s.off + n);
     else
       hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_R>, dim3(gp), dim3(64), 0, st, s, s.off + n);
+    if (ev1) BBC_HIP(hipEventRecord(ev1, st));
   }
-  if (ev1) BBC_HIP(hipEventRecord(ev1, st));
   hipLaunchKernelGGL(k_stage_accum, dim3(gpt), dim3(256), 0, st, s);
   BBC_HIP(hipGetLastError());
   return BBC_OK;
