@@ -206,6 +206,10 @@ bbc_status bbc_query_irradiance_ex(const bbc_bounds* b, const float* points_dev,
  *  BBC_TUNE_NEWTON_STEPS       staged query: FP32 Newton iterations per pass of the
  *                              pooled Newton kernel (1..20, default 4); 0 gives each
  *                              lane one selected pair for all of its starts
+ *  BBC_TUNE_NEWTON_RESULTS     pooled Newton kernel: accepted roots it keeps per batch
+ *                              of 64 pairs (1..96, default 96); the pairs whose roots
+ *                              do not fit are redone one lane per pair (smaller values
+ *                              exercise that path)
  * Applies to later calls on the handle; EINVAL for an unknown knob or value. */
 #define BBC_TUNE_QUERY_WAVES 1
 #define BBC_TUNE_QUERY_GRID 2
@@ -213,6 +217,7 @@ bbc_status bbc_query_irradiance_ex(const bbc_bounds* b, const float* points_dev,
 #define BBC_TUNE_QUERY_TILE 4
 #define BBC_TUNE_TIMING 5
 #define BBC_TUNE_NEWTON_STEPS 6
+#define BBC_TUNE_NEWTON_RESULTS 7
 bbc_status bbc_set_tuning(bbc_bounds* b, int32_t knob, int64_t value);
 bbc_status bbc_get_tuning(const bbc_bounds* b, int32_t knob, int64_t* value);
 

@@ -28,7 +28,7 @@ EXPORTS = [
 ]
 SERVER_PAUSED = 1
 TUNE_QUERY_WAVES, TUNE_QUERY_GRID, TUNE_BUILD_GRID_PER_CU, TUNE_QUERY_TILE, TUNE_TIMING = 1, 2, 3, 4, 5
-TUNE_NEWTON_STEPS = 6
+TUNE_NEWTON_STEPS, TUNE_NEWTON_RESULTS = 6, 7
 
 
 class BBCError(RuntimeError):

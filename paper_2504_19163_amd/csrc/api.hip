@@ -455,6 +455,10 @@ bbc_status bbc_set_tuning(bbc_bounds* h, int32_t knob, int64_t value) {
       if (value < 0 || value > 20) return invalid("Newton steps per pass must be in [0, 20]");
       b->tune.newton_steps = int(value);
       return BBC_OK;
+    case BBC_TUNE_NEWTON_RESULTS:
+      if (value < 1 || value > 96) return invalid("Newton result buffer must be in [1, 96]");
+      b->tune.newton_results = int(value);
+      return BBC_OK;
     default:
       return invalid("unknown tuning knob");
   }
@@ -470,6 +474,7 @@ bbc_status bbc_get_tuning(const bbc_bounds* h, int32_t knob, int64_t* value) {
     case BBC_TUNE_QUERY_TILE: *value = b->tune.query_tile; return BBC_OK;
     case BBC_TUNE_TIMING: *value = b->tune.timing; return BBC_OK;
     case BBC_TUNE_NEWTON_STEPS: *value = b->tune.newton_steps; return BBC_OK;
+    case BBC_TUNE_NEWTON_RESULTS: *value = b->tune.newton_results; return BBC_OK;
     default: return invalid("unknown tuning knob");
   }
 }

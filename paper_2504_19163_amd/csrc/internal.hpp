@@ -61,6 +61,7 @@ struct StagedWork {
   uint32_t* cnt = nullptr;
   uint32_t* off = nullptr;
   double2* tgt = nullptr;  // receiver coordinates (u, v) of each point
+  uint32_t* redo = nullptr;  // pairs left to the redo kernel
   void* scan = nullptr;
   uint32_t* pair_pt = nullptr;
   uint32_t* pair_t = nullptr;
@@ -78,6 +79,7 @@ struct Tuning {
   int timing = 0;             // record events around the query's dominant kernel
   int build_grid_per_cu = 16; // subdivision: persistent workgroups per CU
   int newton_steps = 4;       // staged query: FP32 iterations per pooled Newton pass (0: lane per pair)
+  int newton_results = 96;    // pooled Newton: accepted roots kept per 64 pairs before pairs are redone
 };
 
 struct Bounds {

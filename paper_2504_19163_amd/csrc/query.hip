@@ -489,6 +489,7 @@ struct StagedArgs {
   float* gamma;       // [n]
   uint32_t* off;      // [n + 1] exclusive scan of the selection counts
   double2* tgt;       // [n] receiver coordinates of the point
+  uint32_t* redo;     // [kRedoCap] pairs the pooled Newton kernel could not finish
   uint32_t* pair_pt;  // [pairs]
   uint32_t* pair_t;
   float* pair_p;
@@ -500,6 +501,7 @@ struct StagedArgs {
 __global__ void k_stage_gamma(StagedArgs s) {
   const QueryArgs& a = s.q;
   const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) s.off[a.n + 1] = 0u;  // redo count of the pooled Newton kernel
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x) {
     const Target tg = receiver_target(a, i);
     uint32_t b = 0, nU = 0;
@@ -597,6 +599,7 @@ __global__ void __launch_bounds__(64) k_stage_newton(StagedArgs s, const uint32_
 constexpr int kPool = 128;  // FP32 starts (ring); at most 127 are held
 constexpr int kCand = 128;  // FP32 roots waiting for the polish; at most 127
 constexpr int kRes = 96;    // accepted roots of the 64 pairs (about 7 on average)
+constexpr uint32_t kRedoCap = 16384;  // listed pairs to redo per query
 
 template <int CH>
 struct NewtonPool {
@@ -616,7 +619,8 @@ struct NewtonPool {
 };
 
 template <int CH>
-__global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const uint32_t* total, int steps) {
+__global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
+                                                          int steps, uint32_t res_cap) {
   constexpr bool RR = CH == BBC_CHAIN_RR;
   using Pool = NewtonPool<CH>;
   constexpr int NF = Pool::NF, RS = Pool::RS, NREC = RR ? kRecFloatsRR : kRecFloats;
@@ -724,17 +728,18 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
       const uint64_t m = __ballot(ok);
       if (ok) {
         const uint32_t r = rn + uint32_t(__popcll(m & below));
-        if (r < uint32_t(kRes)) {
+        if (r < res_cap) {
           L.rud[r] = ud;
           L.rvd[r] = vd;
           L.rE[r] = E;
           L.rk[r] = kk;
           L.rp[r] = p;
-        } else {
-          L.redo[p] = 1u;
+        } else if (atomicExch(&L.redo[p], 1u) == 0u) {  // first overflow of this pair: list it once
+          const uint32_t slot = atomicAdd(redo_n, 1u);
+          if (slot < kRedoCap) s.redo[slot] = batch * uint32_t(BBC_WAVE) + p;
         }
       }
-      rn = min(rn + uint32_t(__popcll(m)), uint32_t(kRes));
+      rn = min(rn + uint32_t(__popcll(m)), res_cap);
       // move the candidates not polished yet (fewer than 64) to the front
       float mu = 0.f, mv = 0.f;
       uint32_t mk = 0, mp = 0;
@@ -898,13 +903,19 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
 }
 
 // Pairs whose accepted roots did not fit the pooled kernel's result buffer
-// (marked with a NaN contribution) are redone one lane per pair.
+// (marked with a NaN contribution and listed) are redone one lane per pair;
+// when the list itself overflowed, every pair is checked for the mark.
 template <int CH>
-__global__ void k_stage_redo(StagedArgs s, const uint32_t* total) {
+__global__ void k_stage_redo(StagedArgs s, const uint32_t* total, const uint32_t* redo_n) {
+  const uint32_t nr = *redo_n;
+  if (nr == 0u) return;
+  const bool listed = nr <= kRedoCap;
   const QueryArgs& a = s.q;
   const uint32_t np = min(*total, s.pair_cap);
+  const uint32_t m = listed ? nr : np;
   WorkCount wc;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x) {
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+    const uint32_t k = listed ? s.redo[j] : j;
     if (!isnan(s.pair_c[k])) continue;
     const double2 t2 = s.tgt[s.pair_pt[k]];
     Target tg{};
@@ -956,7 +967,8 @@ size_t staged_pairs(const Bounds* b, int64_t n) { return size_t(n) * size_t(std:
 
 size_t staged_bytes(int64_t n, size_t pairs) {
   const size_t un = size_t(std::max<int64_t>(n, 1)), up = std::max<size_t>(pairs, 1);
-  return 3 * align256(un * 4) + align256((un + 1) * 4 + 8) + align256(un * 16) + align256(scan_tmp_bytes(int64_t(un)) + 64) +
+  return 3 * align256(un * 4) + align256((un + 1) * 4 + 8) + align256(un * 16) + align256(size_t(kRedoCap) * 4) +
+         align256(scan_tmp_bytes(int64_t(un)) + 64) +
          3 * align256(up * 4) + align256(up * 8) + align256(up);
 }
 
@@ -973,6 +985,7 @@ void staged_carve(void* base, int64_t n, size_t pairs, StagedWork& w) {
   w.cnt = static_cast<uint32_t*>(take(un * 4));
   w.off = static_cast<uint32_t*>(take((un + 1) * 4 + 8));
   w.tgt = static_cast<double2*>(take(un * 16));
+  w.redo = static_cast<uint32_t*>(take(size_t(kRedoCap) * 4));
   w.scan = take(scan_tmp_bytes(int64_t(un)) + 64);
   w.pair_pt = static_cast<uint32_t*>(take(up * 4));
   w.pair_t = static_cast<uint32_t*>(take(up * 4));
@@ -1005,7 +1018,8 @@ static bbc_status pool_grid(K kernel, int chain, int* out) {
 // The five stage launches of one staged query; events (nullable) bracket the
 // Newton kernel.
 static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pairs, int newton_steps,
-                             hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
+                             int newton_results, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
+  const uint32_t res_cap = uint32_t(std::min(std::max(newton_results, 1), kRes));
   const int64_t n = q.n;
   StagedArgs s{};
   s.q = q;
@@ -1014,6 +1028,7 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   s.cnt = w.cnt;
   s.off = w.off;
   s.tgt = w.tgt;
+  s.redo = w.redo;
   s.pair_pt = w.pair_pt;
   s.pair_t = w.pair_t;
   s.pair_p = w.pair_p;
@@ -1039,21 +1054,24 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
     if (q.sc.chain == BBC_CHAIN_RR) {
       if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_RR>, BBC_CHAIN_RR, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
-      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_RR>, dim3(gq), dim3(64), 0, st, s, s.off + n, newton_steps);
+      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_RR>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
+                         newton_steps, res_cap);
       if (ev1) BBC_HIP(hipEventRecord(ev1, st));
-      hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_RR>, dim3(gr), dim3(256), 0, st, s, s.off + n);
+      hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_RR>, dim3(gr), dim3(256), 0, st, s, s.off + n, s.off + n + 1);
     } else if (q.sc.chain == BBC_CHAIN_T) {
       if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_T>, BBC_CHAIN_T, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
-      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_T>, dim3(gq), dim3(64), 0, st, s, s.off + n, newton_steps);
+      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_T>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
+                         newton_steps, res_cap);
       if (ev1) BBC_HIP(hipEventRecord(ev1, st));
-      hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_T>, dim3(gr), dim3(256), 0, st, s, s.off + n);
+      hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_T>, dim3(gr), dim3(256), 0, st, s, s.off + n, s.off + n + 1);
     } else {
       if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_R>, BBC_CHAIN_R, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
-      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_R>, dim3(gq), dim3(64), 0, st, s, s.off + n, newton_steps);
+      hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_R>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
+                         newton_steps, res_cap);
       if (ev1) BBC_HIP(hipEventRecord(ev1, st));
-      hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_R>, dim3(gr), dim3(256), 0, st, s, s.off + n);
+      hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_R>, dim3(gr), dim3(256), 0, st, s, s.off + n, s.off + n + 1);
     }
   } else {
     const unsigned gp = unsigned(std::min<size_t>((pairs + 63) / 64, 32768));
@@ -1083,7 +1101,8 @@ bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t s
   }
   const QueryArgs q = make_args(b, pts, n, spp, seed, base, mode, out, stats, counters);
   const bool timed = b->tune.timing != 0;
-  bbc_status e = run_staged(q, b->qw, b->qw.pairs, b->tune.newton_steps, timed ? b->ev[0] : nullptr,
+  bbc_status e = run_staged(q, b->qw, b->qw.pairs, b->tune.newton_steps, b->tune.newton_results,
+                            timed ? b->ev[0] : nullptr,
                             timed ? b->ev[1] : nullptr, st);
   if (e) return e;
   if (timed) b->ev_recorded = true;
@@ -1101,7 +1120,7 @@ bbc_status launch_query_batch(const Bounds* b, const float* pts, int64_t n, cons
   QueryArgs q = make_args(b, pts, n, 1, 0, 0, mode, out, nullptr, nullptr);
   q.preq = preq;
   q.reqs = reqs;
-  return run_staged(q, w, w.pairs, b->tune.newton_steps, ev0, ev1, st);
+  return run_staged(q, w, w.pairs, b->tune.newton_steps, b->tune.newton_results, ev0, ev1, st);
 }
 
 }  // namespace bbc

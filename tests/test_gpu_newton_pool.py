@@ -50,21 +50,27 @@ def test_pooled_newton_matches_lane_per_pair(bbc, name, exhaustive):
     print(name, "exhaustive" if exhaustive else "sampled", "points", pts.shape[1], flush=True)
     E0, st0, h0 = _run(bbc, B, pts, spp, 0, mode)
     assert h0["n_roots"] > 0
-    for steps in (1, 3, 4, 20):
+    for steps, results in ((1, 96), (3, 96), (4, 96), (20, 96), (4, 1), (2, 5)):
+        # a small result buffer sends most pairs with roots through the redo
+        # kernel, whose work counters cover only the roots it adds
+        B.set_tuning(bbc.TUNE_NEWTON_RESULTS, results)
         E1, st1, h1 = _run(bbc, B, pts, spp, steps, mode)
-        assert np.array_equal(E0.view(np.uint32), E1.view(np.uint32)), (name, steps)
-        assert np.array_equal(st0.view(np.uint32), st1.view(np.uint32)), (name, steps)
+        assert np.array_equal(E0.view(np.uint32), E1.view(np.uint32)), (name, steps, results)
+        assert np.array_equal(st0.view(np.uint32), st1.view(np.uint32)), (name, steps, results)
         for f in ("n_pairs", "n_newton", "n_roots", "n_iter_fp32", "n_iter_fp64"):
-            assert h0[f] == h1[f], (name, steps, f)
+            assert h0[f] == h1[f], (name, steps, results, f)
     B.set_tuning(bbc.TUNE_NEWTON_STEPS, 4)
+    B.set_tuning(bbc.TUNE_NEWTON_RESULTS, 96)
 
 
-def test_newton_steps_knob_validation(bbc):
+def test_newton_knob_validation(bbc):
     sc = S.heightfield_mirror(4)
     B = bbc.Bounds(bbc.DeviceScene(sc), dict(max_depth=2))
     assert B.get_tuning(bbc.TUNE_NEWTON_STEPS) == 4
-    for bad in (-1, 21):
+    assert B.get_tuning(bbc.TUNE_NEWTON_RESULTS) == 96
+    for knob, bad in ((bbc.TUNE_NEWTON_STEPS, -1), (bbc.TUNE_NEWTON_STEPS, 21), (bbc.TUNE_NEWTON_RESULTS, 0),
+                      (bbc.TUNE_NEWTON_RESULTS, 97)):
         with pytest.raises(RuntimeError):
-            B.set_tuning(bbc.TUNE_NEWTON_STEPS, bad)
+            B.set_tuning(knob, bad)
     B.set_tuning(bbc.TUNE_NEWTON_STEPS, 0)
     assert B.get_tuning(bbc.TUNE_NEWTON_STEPS) == 0
