@@ -831,13 +831,110 @@ static void philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]
 }
 
 // The rng() of Alg. 1, keyed by (seed, index of the point in its request,
-// tuple), so a result never depends on how requests are batched.
-static double uniform(uint64_t seed, uint64_t point, uint32_t tuple) {
-  const uint32_t ctr[4] = {uint32_t(point), uint32_t(point >> 32), tuple, 0u};
+// tuple), so a result never depends on how requests are batched.  The other
+// samplers draw from their own streams (last counter word): draw j of the
+// one-sample estimator from stream 1, bin b of the bin-packed sampler from
+// stream 2.  Values are multiples of 2^-24 in [0, 1), exact in FP32.
+static double uniform_stream(uint64_t seed, uint64_t point, uint32_t index, uint32_t stream) {
+  const uint32_t ctr[4] = {uint32_t(point), uint32_t(point >> 32), index, stream};
   const uint32_t key[2] = {uint32_t(seed), uint32_t(seed >> 32)};
   uint32_t o[4];
   philox(ctr, key, o);
   return double(o[0] >> 8) * (1.0 / 16777216.0);
+}
+static double uniform(uint64_t seed, uint64_t point, uint32_t tuple) { return uniform_stream(seed, point, tuple, 0u); }
+
+// ---------------------------------------------------------------- other samplers
+// The sampling schemes the paper compares with its multi-sample estimator
+// (Sec. 5.2-5.3 and the sampling-scheme comparison figure), each as a list of
+// selected candidates with the probability weight 1/P of its contribution.
+// Where a floating-point comparison decides which candidate is selected, it
+// is made in FP32, in list order, as the GPU makes it (the paper fixes no
+// precision); weights are FP32 too.
+struct Pick {
+  size_t k;  // index into U
+  float P;   // contribution weight is 1 / P
+};
+
+// Uniform: every candidate of U with the same P = W' / |U|, W' = min(W, |U|)
+// (position bound only; the irradiance bound is not consulted).
+static std::vector<Pick> pick_uniform(size_t n, double W, uint64_t seed, uint64_t point, const int64_t* U) {
+  std::vector<Pick> out;
+  if (n == 0) return out;
+  const float P = float(std::min(W, double(n))) / float(n);
+  for (size_t k = 0; k < n; ++k)
+    if (float(uniform(seed, point, uint32_t(U[k]))) < P) out.push_back({k, P});
+  return out;
+}
+
+// One-sample estimator repeated W times (Sec. 5.2): W independent draws with
+// P1(T) = E~_T / sum E~ over the finite bounds (FP32 prefix sums in list
+// order; draw j selects the first candidate whose running sum exceeds
+// r_j * sum), and ⟨E⟩ = (1/W) sum_j E(T_j) / P1(T_j).  A candidate drawn c
+// times enters once with weight c / (W P1).  Reading: candidates with an
+// infinite bound have no finite P1; each is evaluated once with P = 1.
+// Candidates with E~ = 0 are never drawn (their E(T) is 0).
+static std::vector<Pick> pick_one_sample(const std::vector<double>& Et, int W, uint64_t seed, uint64_t point) {
+  const size_t n = Et.size();
+  std::vector<Pick> out;
+  std::vector<float> Ef(n, 0.f), C(n, 0.f);
+  float S = 0.f;
+  for (size_t k = 0; k < n; ++k) {
+    if (std::isinf(Et[k])) {
+      out.push_back({k, 1.f});
+    } else if (Et[k] > 0.0) {
+      Ef[k] = float(Et[k]);
+      S = S + Ef[k];
+    }
+    C[k] = S;
+  }
+  if (!(S > 0.f)) return out;
+  std::vector<int> cnt(n, 0);
+  size_t last = 0;
+  for (size_t k = 0; k < n; ++k)
+    if (Ef[k] > 0.f) last = k;
+  for (int j = 0; j < W; ++j) {
+    const float t = float(uniform_stream(seed, point, uint32_t(j), 1u)) * S;
+    size_t sel = last;  // t can round up to the total
+    for (size_t k = 0; k < n; ++k)
+      if (Ef[k] > 0.f && t < C[k]) {
+        sel = k;
+        break;
+      }
+    ++cnt[sel];
+  }
+  for (size_t k = 0; k < n; ++k)
+    if (cnt[k]) out.push_back({k, float(W) * (Ef[k] / S) / float(cnt[k])});
+  std::sort(out.begin(), out.end(), [](const Pick& a, const Pick& b) { return a.k < b.k; });
+  return out;
+}
+
+// Bin-packed multi-sample estimator (Sec. 5.3): the bound-optimal P_T packed
+// in list order into bins of total probability at most 1, one importance
+// sample per bin.  Reading: next-fit packing (a candidate that does not fit
+// the open bin closes it and opens the next), which is the greedy rule with
+// O(|U|) time and approximation ratio 2 that the text states.  Candidate k
+// of bin b owns [o_k, o_k + P_k) of that bin (FP32 running sum) and is
+// selected when the bin's draw r_b falls there, so its selection probability
+// is P_k and at most one candidate per bin is selected.
+static std::vector<Pick> pick_bins(const std::vector<double>& P, uint64_t seed, uint64_t point) {
+  std::vector<Pick> out;
+  uint32_t b = 0;
+  float fill = 0.f;
+  float r = float(uniform_stream(seed, point, 0u, 2u));
+  for (size_t k = 0; k < P.size(); ++k) {
+    const float p = float(P[k]);
+    if (!(p > 0.f)) continue;
+    if (fill + p > 1.f) {
+      ++b;
+      fill = 0.f;
+      r = float(uniform_stream(seed, point, b, 2u));
+    }
+    const float lo = fill;
+    fill = fill + p;
+    if (r >= lo && r < fill) out.push_back({k, p});
+  }
+  return out;
 }
 
 // ---------------------------------------------------------------- roots
@@ -1039,9 +1136,11 @@ int64_t orc_cell_list(const void* h, int32_t cu, int32_t cv, int64_t* tuples, do
 int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t seed, int mode, double* E_out,
               double* stats, int n_threads) {
   const Build* B = static_cast<const Build*>(h);
-  if (!B || !pts || !E_out || n < 0 || !(W >= 1.0) || mode < 0 || mode > 3) return -1;
+  if (!B || !pts || !E_out || n < 0 || !(W >= 1.0) || mode < 0 || mode > 15) return -1;
   const int G = B->p.grid_res;
   const bool exhaustive = (mode & 1) != 0, brute = (mode & 2) != 0;
+  const int sampler = (mode >> 2) & 3;  // 0 Alg. 1 with the bound-optimal P, 1 uniform, 2 one-sample, 3 bins
+  if (exhaustive && sampler != 0) return -1;
   const Tuple ref = make_tuple(B->scene, 0);
   parallel_for(n, n_threads, [&](int64_t i, int) {
     const V3 x = v3(pts[i], pts[n + i], pts[2 * n + i]);
@@ -1059,24 +1158,38 @@ int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t se
     }
     std::vector<double> P(U.size(), 1.0);
     if (!exhaustive) probabilities(Et.data(), int64_t(U.size()), W, P.data());
-    double E = 0.0, mu2 = 0.0;
-    int64_t nS = 0, nroots = 0;
-    for (size_t k = 0; k < U.size(); ++k) {
-      if (P[k] > 0.0) mu2 += Et[k] * Et[k] / P[k];
-      const double r = uniform(seed, uint64_t(i), uint32_t(U[k]));
-      if (!(r < P[k])) continue;
-      ++nS;
+    std::vector<Pick> S;
+    double mu2 = 0.0;
+    if (sampler == 1) {
+      S = pick_uniform(U.size(), W, seed, uint64_t(i), U.data());
+    } else if (sampler == 2) {
+      S = pick_one_sample(Et, int(W), seed, uint64_t(i));
+    } else if (sampler == 3) {
+      S = pick_bins(P, seed, uint64_t(i));
+      for (size_t k = 0; k < U.size(); ++k)
+        if (P[k] > 0.0) mu2 += Et[k] * Et[k] / P[k];
+    } else {
+      for (size_t k = 0; k < U.size(); ++k) {
+        if (P[k] > 0.0) mu2 += Et[k] * Et[k] / P[k];
+        const double r = uniform(seed, uint64_t(i), uint32_t(U[k]));
+        if (r < P[k]) S.push_back({k, float(0)});
+      }
+    }
+    double E = 0.0;
+    int64_t nroots = 0;
+    for (const Pick& pk : S) {
+      const size_t k = pk.k;
       const Tuple c = make_tuple(B->scene, U[k]);
       const std::vector<RootHit> roots = brute ? brute_roots(c, us, vs, 64) : leaf_roots(*B, c, U[k], us, vs);
       double ET = 0.0;
       for (const RootHit& rh : roots) ET += rh.Ek;
       nroots += int64_t(roots.size());
-      E += ET / P[k];
+      E += sampler == 0 ? ET / P[k] : ET / double(pk.P);
     }
     E_out[i] = E;
     if (st) {
       st[0] = double(U.size());
-      st[1] = double(nS);
+      st[1] = double(S.size());
       st[2] = double(nroots);
       st[3] = mu2;
     }
@@ -1140,6 +1253,29 @@ int orc_probabilities(const double* Et, int64_t n, double W, double* P) {
   if ((!Et && n) || (!P && n) || n < 0 || !(W >= 1.0)) return -1;
   probabilities(Et, n, W, P);
   return 0;
+}
+
+int64_t orc_sample(const double* Et, const int64_t* U, int64_t n, double W, uint64_t seed, uint64_t point,
+                   int sampler, int64_t* k_out, double* P_out, int64_t cap) {
+  if ((!Et && n) || (!U && n) || n < 0 || !(W >= 1.0) || sampler < 0 || sampler > 3) return -1;
+  std::vector<double> E(Et, Et + n), P(size_t(n), 1.0);
+  probabilities(E.data(), n, W, P.data());
+  std::vector<Pick> S;
+  if (sampler == 1) {
+    S = pick_uniform(size_t(n), W, seed, point, U);
+  } else if (sampler == 2) {
+    S = pick_one_sample(E, int(W), seed, point);
+  } else if (sampler == 3) {
+    S = pick_bins(P, seed, point);
+  } else {
+    for (int64_t k = 0; k < n; ++k)
+      if (uniform(seed, point, uint32_t(U[k])) < P[size_t(k)]) S.push_back({size_t(k), float(P[size_t(k)])});
+  }
+  for (size_t j = 0; j < S.size() && int64_t(j) < cap; ++j) {
+    k_out[j] = int64_t(S[j].k);
+    P_out[j] = sampler == 0 ? P[S[j].k] : double(S[j].P);
+  }
+  return int64_t(S.size());
 }
 
 void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox(ctr, key, out); }

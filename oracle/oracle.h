@@ -80,6 +80,10 @@ int64_t orc_cell_list(const void* h, int32_t cu, int32_t cv, int64_t* tuples, do
  * mode 0: sample with the bound-optimal probabilities, roots by Newton from the
  *         covering leaves;  mode 1: exhaustive (every tuple of U with P = 1),
  *         same roots;  mode 2/3: as 0/1 with brute-force roots.
+ * mode | 4:  uniform P = W'/|U| instead of the bound-optimal P;
+ * mode | 8:  one-sample estimator with P1 = E~ / sum E~, W draws;
+ * mode | 12: bound-optimal P, one sample per next-fit bin of total P <= 1
+ *         (these three exclude mode 1; -1 for that combination).
  * stats (nullable) [n][4] = |U|, |S|, roots found, sum over U of E~^2 / P. */
 int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t seed, int mode,
               double* E_out, double* stats, int n_threads);
@@ -94,6 +98,13 @@ int64_t orc_tuple_roots(const orc_scene* s, int64_t tuple, const double* x, int 
                         int64_t cap);
 /* Roots of one tuple found from the covering leaves of a build. */
 int64_t orc_tuple_roots_leaves(const void* h, int64_t tuple, const double* x, double* roots, int64_t cap);
+
+/* The candidates one shading point selects from a list U[n] with bounds Et[n]
+ * (sampler 0 Alg. 1 with the bound-optimal P, 1 uniform, 2 one-sample, 3 bins;
+ * as orc_query modes 0, 4, 8, 12): indices into the list and the weight P of
+ * each (contribution E(T) / P).  Returns the count (writes at most cap). */
+int64_t orc_sample(const double* Et, const int64_t* U, int64_t n, double W, uint64_t seed, uint64_t point,
+                   int sampler, int64_t* k_out, double* P_out, int64_t cap);
 
 /* Bound-optimal selection probabilities for a candidate list with bounds Et[n]
  * and expected sample count W (Sec. 5.4 with the water-filling solve of gamma). */

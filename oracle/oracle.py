@@ -78,6 +78,7 @@ def _declare(L):
         "orc_tuple_roots": (i64, [vp, i64, vp, C.c_int, vp, i64]),
         "orc_tuple_roots_leaves": (i64, [vp, i64, vp, vp, i64]),
         "orc_probabilities": (C.c_int, [vp, i64, d, vp]),
+        "orc_sample": (i64, [vp, vp, i64, d, u64, u64, C.c_int, vp, vp, i64]),
         "orc_philox4x32_10": (None, [vp, vp, vp]),
         "orc_uniform": (d, [u64, u64, C.c_uint32]),
         "orc_bern_mul": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -251,6 +252,22 @@ def probabilities(Et, W):
     P = np.zeros_like(e)
     assert lib().orc_probabilities(_ptr(e), e.size, float(W), _ptr(P)) == 0
     return P
+
+
+SAMPLER_BOUND, SAMPLER_UNIFORM, SAMPLER_ONE, SAMPLER_BINS = 0, 1, 2, 3
+
+
+def sample(Et, W, seed, point, sampler, tuples=None):
+    """Candidates selected from one list (indices, weights P) by a sampler."""
+    e = _f64(Et)
+    n = e.size
+    U = np.ascontiguousarray(np.arange(n, dtype=np.int64) if tuples is None else np.asarray(tuples, np.int64))
+    cap = max(n, 1)
+    k = np.zeros(cap, np.int64)
+    P = np.zeros(cap)
+    m = lib().orc_sample(_ptr(e), _ptr(U), n, float(W), int(seed), int(point), int(sampler), _ptr(k), _ptr(P), cap)
+    assert m >= 0
+    return k[:m].copy(), P[:m].copy()
 
 
 def philox4x32_10(ctr, key):
