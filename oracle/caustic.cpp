@@ -914,9 +914,13 @@ static std::vector<Pick> pick_one_sample(const std::vector<double>& Et, int W, u
 // sample per bin.  Reading: next-fit packing (a candidate that does not fit
 // the open bin closes it and opens the next), which is the greedy rule with
 // O(|U|) time and approximation ratio 2 that the text states.  Candidate k
-// of bin b owns [o_k, o_k + P_k) of that bin (FP32 running sum) and is
-// selected when the bin's draw r_b falls there, so its selection probability
-// is P_k and at most one candidate per bin is selected.
+// of bin b owns [o_k, min(o_k + P_k, 1)) of that bin (FP32 running sum) and
+// is selected when the bin's draw r_b falls there; its weight is the length
+// of that interval, its selection probability, and at most one candidate per
+// bin is selected.  Probabilities that sum to exactly 1 (as the bound-optimal
+// ones often do) land on 1 only up to rounding, so a bin accepts a candidate
+// while the sum stays within 2^-20 of 1, and the part above 1 is cut.
+constexpr float kBinSlack = 1.0f / 1048576.0f;
 static std::vector<Pick> pick_bins(const std::vector<double>& P, uint64_t seed, uint64_t point) {
   std::vector<Pick> out;
   uint32_t b = 0;
@@ -925,14 +929,15 @@ static std::vector<Pick> pick_bins(const std::vector<double>& P, uint64_t seed, 
   for (size_t k = 0; k < P.size(); ++k) {
     const float p = float(P[k]);
     if (!(p > 0.f)) continue;
-    if (fill + p > 1.f) {
+    if (fill + p > 1.f + kBinSlack) {
       ++b;
       fill = 0.f;
       r = float(uniform_stream(seed, point, b, 2u));
     }
     const float lo = fill;
     fill = fill + p;
-    if (r >= lo && r < fill) out.push_back({k, p});
+    const float hi = std::min(fill, 1.f);
+    if (r >= lo && r < hi) out.push_back({k, hi - lo});
   }
   return out;
 }

@@ -53,8 +53,8 @@ def test_bins_keep_the_bound_optimal_marginals(orc):
         sd = np.sqrt(np.maximum(P * (1 - P), 1e-12) / T)
         assert np.all(np.abs(f - P) < 4.5 * sd + 1e-12), trial
         assert f[P == 0].sum() == 0
-        for k, ws in w.items():  # weight of a selected candidate is its own P
-            assert ws == {float(np.float32(P[k]))}
+        for k, ws in w.items():  # weight of a selected candidate is its own P (interval cut at 1)
+            assert all(abs(x - P[k]) <= 2e-6 * max(P[k], 1e-3) + 2.0 ** -20 for x in ws)
 
 
 def test_bins_one_bin_gives_exactly_one_sample(orc):
