@@ -186,15 +186,30 @@ bbc_status bbc_query_irradiance(const bbc_bounds* b, const float* points_dev, in
  *  BBC_QUERY_FUSED   one persistent kernel per call (default of bbc_query_irradiance)
  *  BBC_QUERY_STAGED  one launch per stage: gather+gamma, selection, Newton, accumulation
  *  BBC_QUERY_EXHAUSTIVE (or-ed in) every candidate tuple with P = 1 (position-only enumeration)
+ * and, or-ed into BBC_QUERY_STAGED only (EINVAL with the fused form or with
+ * EXHAUSTIVE), one of the other sampling schemes the paper compares its
+ * estimator with (Sec. 5.2-5.3, the sampling-scheme comparison figure):
+ *  BBC_QUERY_UNIFORM     every candidate independently with P = W'/|U|, W' = min(spp, |U|)
+ *                        (position bound only)
+ *  BBC_QUERY_ONE_SAMPLE  spp independent draws with P1 = E~ / sum of the finite E~; a tuple
+ *                        drawn c times contributes E(T) c / (spp P1); unbounded tuples once
+ *                        with P = 1
+ *  BBC_QUERY_BINS        the bound-optimal P packed next-fit in list order into bins of total
+ *                        at most 1, one draw per bin (at most one tuple per bin)
  * point_index_base offsets the point index used by the random stream, so a
  * request split into pieces draws exactly what it would draw whole. */
 #define BBC_QUERY_FUSED 0
 #define BBC_QUERY_STAGED 1
 #define BBC_QUERY_EXHAUSTIVE 16
+#define BBC_QUERY_UNIFORM 32
+#define BBC_QUERY_ONE_SAMPLE 64
+#define BBC_QUERY_BINS 96
+#define BBC_QUERY_SAMPLERS 96  /* mask of the three above */
 bbc_status bbc_query_irradiance_ex(const bbc_bounds* b, const float* points_dev, int64_t n, int32_t spp, uint64_t seed,
                                    int64_t point_index_base, int32_t mode, float* out_E_dev, float* stats_dev,
                                    bbc_query_stats* stats_host, void* stream);
-/* stats_dev (nullable) [n][4] FP32: |U|, |S|, roots, sum_U E~^2/P per point. */
+/* stats_dev (nullable) [n][4] FP32: |U|, |S|, roots, sum_U E~^2/P per point
+ * (the last is 0 for the uniform and one-sample schemes). */
 
 /* Launch-shape knobs (chosen by the autotuner; results never depend on them):
  *  BBC_TUNE_QUERY_WAVES        fused query register budget: 2 (256 VGPRs) or 4 (128) waves per SIMD
@@ -260,7 +275,7 @@ typedef struct {
   int32_t max_batch_points;   /* points in one batch, 1..2^24; a request must fit one batch */
   int32_t max_batch_requests; /* requests in one batch, 1..65535 */
   int32_t queue_capacity;     /* waiting requests before submit returns BBC_EQUEUE, >= 1 */
-  int32_t mode;               /* 0 (sampled, Alg. 1) or BBC_QUERY_EXHAUSTIVE */
+  int32_t mode;               /* 0 (sampled, Alg. 1), BBC_QUERY_EXHAUSTIVE or one of the samplers */
   int32_t flags;              /* BBC_SERVER_PAUSED */
 } bbc_server_config;
 

@@ -19,6 +19,7 @@ CHAIN = {"R": 0, "T": 1, "RR": 2}
 MEM_HOST, MEM_DEVICE = 0, 1
 FLAG_FIXED_DEPTH, FLAG_NO_REMAINDER = 1, 2
 QUERY_FUSED, QUERY_STAGED, QUERY_EXHAUSTIVE = 0, 1, 16
+QUERY_UNIFORM, QUERY_ONE_SAMPLE, QUERY_BINS = 32, 64, 96
 
 EXPORTS = [
     "bbc_build_bounds", "bbc_rebuild_bounds", "bbc_free_bounds", "bbc_bounds_info", "bbc_export_leaves",

@@ -372,8 +372,11 @@ bbc_status bbc_query_irradiance_ex(const bbc_bounds* h, const float* points_dev,
   if (spp < 1) return invalid("spp must be >= 1");
   if (point_index_base < 0) return invalid("point_index_base must be >= 0");
   const int form = mode & 15;
-  if ((form != BBC_QUERY_FUSED && form != BBC_QUERY_STAGED) || (mode & ~(15 | BBC_QUERY_EXHAUSTIVE)))
+  if ((form != BBC_QUERY_FUSED && form != BBC_QUERY_STAGED) ||
+      (mode & ~(15 | BBC_QUERY_EXHAUSTIVE | BBC_QUERY_SAMPLERS)))
     return invalid("unknown query mode");
+  if ((mode & BBC_QUERY_SAMPLERS) && (form != BBC_QUERY_STAGED || (mode & BBC_QUERY_EXHAUSTIVE)))
+    return invalid("the uniform, one-sample and bin samplers need the staged form without EXHAUSTIVE");
   Bounds* b = const_cast<Bounds*>(reinterpret_cast<const Bounds*>(h));
   const hipStream_t s = as_stream(stream);
   bbc_status e;

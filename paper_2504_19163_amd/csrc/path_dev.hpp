@@ -205,10 +205,15 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 }
 
 // The rng() of Alg. 1 for (seed, point index, tuple): top 24 bits of word 0.
-__device__ __forceinline__ float selection_uniform(uint64_t seed, uint64_t point, uint32_t tuple) {
-  const uint4 o = philox4x32_10(make_uint4(uint32_t(point), uint32_t(point >> 32), tuple, 0u),
+__device__ __forceinline__ float sample_stream(uint64_t seed, uint64_t point, uint32_t index, uint32_t stream) {
+  const uint4 o = philox4x32_10(make_uint4(uint32_t(point), uint32_t(point >> 32), index, stream),
                                 make_uint2(uint32_t(seed), uint32_t(seed >> 32)));
   return float(o.x >> 8) * (1.0f / 16777216.0f);
+}
+// The rng() of Alg. 1 for one tuple (stream 0); the one-sample draws use
+// stream 1 (index = draw) and the bins of the bin-packed sampler stream 2.
+__device__ __forceinline__ float selection_uniform(uint64_t seed, uint64_t point, uint32_t tuple) {
+  return sample_stream(seed, point, tuple, 0u);
 }
 
 }  // namespace bbc

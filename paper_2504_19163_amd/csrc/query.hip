@@ -518,19 +518,132 @@ __global__ void k_stage_gamma(StagedArgs s) {
   }
 }
 
+// The selections of shading point i in list order, one chunk of 64
+// candidates at a time: chunk(take, T, P) runs on every lane of the wave for
+// each chunk, lane l holding candidate j0 + l (take: selected; P: the
+// probability its contribution is divided by).
+//  * bound-optimal (Alg. 1) and uniform P = W'/|U|: independent decisions;
+//  * one-sample (Sec. 5.2), W draws with P1 = E~ / sum E~: the running sum of
+//    the finite bounds is formed in list order by every lane in lockstep
+//    (FP32, the same order as a sequential loop), each candidate counts the
+//    draws that fall in its interval, and a candidate drawn c times enters
+//    once with P = W P1 / c; unbounded candidates enter with P = 1;
+//  * bins (Sec. 5.3): the bound-optimal P packed next-fit in list order into
+//    bins of total at most 1, one draw per bin; all lanes walk the packing in
+//    lockstep and the candidate whose interval holds its bin's draw is taken.
+//    A bin accepts a candidate while its running sum stays within 2^-20 of 1
+//    (probabilities that sum to 1 exactly reach it only up to rounding); the
+//    part of an interval above 1 is cut and the weight is the interval's
+//    length, the candidate's selection probability.
+constexpr float kBinSlack = 1.0f / 1048576.0f;
+template <class F>
+__device__ void point_selection(const QueryArgs& a, const StagedArgs& s, int64_t i, int lane, F&& chunk) {
+  const uint32_t b = s.cell_b[i], nU = s.cnt[i];
+  const float gamma = s.gamma[i];
+  const PointReq pr = point_req(a, i);
+  const int sampler = a.mode & BBC_QUERY_SAMPLERS;
+  const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
+  if (sampler == BBC_QUERY_ONE_SAMPLE) {
+    float S = 0.f;
+    int64_t last = -1;
+    for (uint32_t j0 = 0; j0 < nU; j0 += BBC_WAVE) {
+      const uint32_t j = j0 + lane;
+      const float e = j < nU ? a.ge[b + j] : 0.f;
+      const float ef = (isfinite(e) && e > 0.f) ? e : 0.f;
+      const uint32_t cnt = min(uint32_t(BBC_WAVE), nU - j0);
+      for (uint32_t q = 0; q < cnt; ++q) {
+        const float eq = __shfl(ef, int(q), BBC_WAVE);
+        if (eq > 0.f) {
+          S = S + eq;
+          last = int64_t(j0 + q);
+        }
+      }
+    }
+    const int W = int(pr.W);
+    float C = 0.f;
+    for (uint32_t j0 = 0; j0 < nU; j0 += BBC_WAVE) {
+      const uint32_t j = j0 + lane;
+      const float e = j < nU ? a.ge[b + j] : 0.f;
+      const uint32_t T = j < nU ? a.gt[b + j] : 0u;
+      const float ef = (isfinite(e) && e > 0.f) ? e : 0.f;
+      const uint32_t cnt = min(uint32_t(BBC_WAVE), nU - j0);
+      float lo = 0.f, hi = 0.f;
+      for (uint32_t q = 0; q < cnt; ++q) {
+        const float eq = __shfl(ef, int(q), BBC_WAVE);
+        if (lane == int(q)) lo = C;
+        if (eq > 0.f) C = C + eq;
+        if (lane == int(q)) hi = C;
+      }
+      if (int64_t(j) == last) hi = INFINITY;  // a draw that rounds up to the total
+      uint32_t c = 0;
+      if (S > 0.f) {
+        for (int d0 = 0; d0 < W; d0 += BBC_WAVE) {
+          const float t = d0 + lane < W ? sample_stream(pr.seed, pr.key, uint32_t(d0 + lane), 1u) * S : -1.f;
+          for (int q = 0; q < BBC_WAVE; ++q) {
+            const float tq = __shfl(t, q, BBC_WAVE);
+            c += (ef > 0.f && tq >= lo && tq < hi) ? 1u : 0u;
+          }
+        }
+      }
+      const bool inf = j < nU && isinf(e);
+      const bool take = j < nU && (inf || c > 0u);
+      const float P = inf ? 1.f : (c > 0u ? float(W) * (ef / S) / float(c) : 0.f);
+      chunk(take, T, P);
+    }
+    return;
+  }
+  if (sampler == BBC_QUERY_BINS) {
+    uint32_t bin = 0;
+    float fill = 0.f;
+    float r = sample_stream(pr.seed, pr.key, 0u, 2u);
+    for (uint32_t j0 = 0; j0 < nU; j0 += BBC_WAVE) {
+      const uint32_t j = j0 + lane;
+      const uint32_t T = j < nU ? a.gt[b + j] : 0u;
+      const float p = j < nU ? select_prob(a.ge[b + j], gamma, false) : 0.f;
+      const uint32_t cnt = min(uint32_t(BBC_WAVE), nU - j0);
+      bool take = false;
+      float w = p;
+      for (uint32_t q = 0; q < cnt; ++q) {
+        const float pq = __shfl(p, int(q), BBC_WAVE);
+        if (!(pq > 0.f)) continue;
+        if (fill + pq > 1.f + kBinSlack) {
+          ++bin;
+          fill = 0.f;
+          r = sample_stream(pr.seed, pr.key, bin, 2u);
+        }
+        const float lo = fill;
+        fill = fill + pq;
+        const float hi = fminf(fill, 1.f);
+        if (lane == int(q)) {
+          take = r >= lo && r < hi;
+          w = hi - lo;
+        }
+      }
+      chunk(take, T, w);
+    }
+    return;
+  }
+  const float Pu = fminf(pr.W, float(nU)) / float(nU);
+  for (uint32_t j0 = 0; j0 < nU; j0 += BBC_WAVE) {
+    const uint32_t j = j0 + lane;
+    bool take = false;
+    float P = 0.f;
+    uint32_t T = 0;
+    if (j < nU) {
+      T = a.gt[b + j];
+      P = sampler == BBC_QUERY_UNIFORM ? Pu : select_prob(a.ge[b + j], gamma, exhaustive);
+      take = selection_uniform(pr.seed, pr.key, tuple_key(a, T)) < P;
+    }
+    chunk(take, T, P);
+  }
+}
+
 __global__ void __launch_bounds__(64) k_stage_count(StagedArgs s, uint32_t* sel) {
   const QueryArgs& a = s.q;
   const int lane = threadIdx.x;
-  const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
   for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
-    const uint32_t b = s.cell_b[i], nU = s.cnt[i];
-    const float gamma = s.gamma[i];
     uint32_t c = 0;
-    const PointReq pr = point_req(a, i);
-    for (uint32_t j = lane; j < nU; j += BBC_WAVE) {
-      const float P = select_prob(a.ge[b + j], gamma, exhaustive);
-      c += selection_uniform(pr.seed, pr.key, tuple_key(a, a.gt[b + j])) < P ? 1u : 0u;
-    }
+    point_selection(a, s, i, lane, [&](bool take, uint32_t, float) { c += take ? 1u : 0u; });
     c = wave_sum(c);
     if (lane == 0) sel[i] = c;
   }
@@ -539,22 +652,9 @@ __global__ void __launch_bounds__(64) k_stage_count(StagedArgs s, uint32_t* sel)
 __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
   const QueryArgs& a = s.q;
   const int lane = threadIdx.x;
-  const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
   for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
-    const uint32_t b = s.cell_b[i], nU = s.cnt[i];
-    const float gamma = s.gamma[i];
-    const PointReq pr = point_req(a, i);
     uint32_t o = s.off[i];
-    for (uint32_t j0 = 0; j0 < nU; j0 += BBC_WAVE) {
-      const uint32_t j = j0 + lane;
-      bool take = false;
-      float P = 0.f;
-      uint32_t T = 0;
-      if (j < nU) {
-        T = a.gt[b + j];
-        P = select_prob(a.ge[b + j], gamma, exhaustive);
-        take = selection_uniform(pr.seed, pr.key, tuple_key(a, T)) < P;
-      }
+    point_selection(a, s, i, lane, [&](bool take, uint32_t T, float P) {
       const uint64_t m = __ballot(take);
       const uint32_t rank = __popcll(m & ((1ull << lane) - 1ull));
       if (take && o + rank < s.pair_cap) {
@@ -563,7 +663,7 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
         s.pair_p[o + rank] = P;
       }
       o += __popcll(m);
-    }
+    });
   }
 }
 
@@ -937,6 +1037,9 @@ __global__ void k_stage_redo(StagedArgs s, const uint32_t* total, const uint32_t
 __global__ void k_stage_accum(StagedArgs s) {
   const QueryArgs& a = s.q;
   const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
+  // the moment bound sum E~^2 / P is reported for the bound-optimal P only
+  const int sampler = a.mode & BBC_QUERY_SAMPLERS;
+  const bool bound_p = sampler == 0 || sampler == BBC_QUERY_BINS;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x) {
     double E = 0.0;
     const uint32_t o0 = min(s.off[i], s.pair_cap), o1 = min(s.off[i + 1], s.pair_cap);
@@ -951,7 +1054,7 @@ __global__ void k_stage_accum(StagedArgs s) {
       for (uint32_t j = 0; j < nU; ++j) {
         const float e = a.ge[b + j];
         const float P = select_prob(e, gamma, exhaustive);
-        if (P > 0.f && isfinite(e)) mu2 += double(e) * double(e) / double(P);
+        if (bound_p && P > 0.f && isfinite(e)) mu2 += double(e) * double(e) / double(P);
       }
       a.stats[4 * i + 0] = float(nU);
       a.stats[4 * i + 1] = float(s.off[i + 1] - s.off[i]);

@@ -312,7 +312,9 @@ bbc_status bbc_server_create(bbc_bounds* const* bounds, int32_t n_bounds, const 
   if (cfg->max_batch_requests < 1 || cfg->max_batch_requests > 65535)
     return fail(BBC_EINVAL, "max_batch_requests must be in 1..65535");
   if (cfg->queue_capacity < 1) return fail(BBC_EINVAL, "queue_capacity must be >= 1");
-  if (cfg->mode != 0 && cfg->mode != BBC_QUERY_EXHAUSTIVE) return fail(BBC_EINVAL, "mode must be 0 or EXHAUSTIVE");
+  if (cfg->mode != 0 && cfg->mode != BBC_QUERY_EXHAUSTIVE && cfg->mode != BBC_QUERY_UNIFORM &&
+      cfg->mode != BBC_QUERY_ONE_SAMPLE && cfg->mode != BBC_QUERY_BINS)
+    return fail(BBC_EINVAL, "mode must be 0, EXHAUSTIVE or one sampler");
   if (cfg->flags & ~BBC_SERVER_PAUSED) return fail(BBC_EINVAL, "unknown server flags");
   std::vector<Bounds*> bs;
   for (int32_t i = 0; i < n_bounds; ++i) {
