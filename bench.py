@@ -217,6 +217,49 @@ def two_reflection_section(bbc, S, torch, steps=2):
             "mean_candidates_per_point": round(qs["sum_U"] / n, 1), "roots": qs["n_roots"]}
 
 
+def samplers_section(bbc, torch, B, pts, spps=(4, 16), seeds=4, reps=5):
+    """The sampling schemes side by side on the benchmark bounds (the paper's
+    sampling-scheme comparison): RelMSE against the exhaustive sum over U at
+    equal expected samples per point W (below the typical |U| of ~16, where
+    the schemes differ), the staged query time, and samples and roots per
+    point."""
+    ex, _ = B.query(pts, 1, 0, mode=bbc.QUERY_STAGED | bbc.QUERY_EXHAUSTIVE)
+    ref = ex.double().cpu().numpy()
+    modes = {"bound_optimal": 0, "bins": bbc.QUERY_BINS, "one_sample": bbc.QUERY_ONE_SAMPLE,
+             "uniform": bbc.QUERY_UNIFORM}
+    n = pts.shape[1]
+    out = {"reference": "exhaustive sum over the cell list (enumerate)", "seeds": seeds}
+    for spp in spps:
+        row = {}
+        for name, m in modes.items():
+            mode = bbc.QUERY_STAGED | m
+            times, errs = [], []
+            for k in range(max(seeds, reps)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                E, _ = B.query(pts, spp, 500 + k, mode=mode)
+                torch.cuda.synchronize()
+                times.append(1e3 * (time.perf_counter() - t0))
+                if k < seeds:
+                    errs.append(relmse(E.double().cpu().numpy(), ref))
+            _, _, qs = B.query(pts, spp, 500, mode=mode, host_stats=True)
+            row[name] = {"relmse": float(np.mean(errs)), "query_ms": round(float(np.median(times)), 3),
+                         "samples_per_point": round(qs["sum_S"] / n, 3),
+                         "roots_per_point": round(qs["n_roots"] / n, 4)}
+        out[f"spp{spp}"] = row
+    times = []
+    for k in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.query(pts, 1, 0, mode=bbc.QUERY_STAGED | bbc.QUERY_EXHAUSTIVE)
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t0))
+    _, _, qs = B.query(pts, 1, 0, mode=bbc.QUERY_STAGED | bbc.QUERY_EXHAUSTIVE, host_stats=True)
+    out["enumerate"] = {"relmse": 0.0, "query_ms": round(float(np.median(times)), 3),
+                        "samples_per_point": round(qs["sum_S"] / n, 3), "roots_per_point": round(qs["n_roots"] / n, 4)}
+    return out
+
+
 def serving_section(bbc, S, torch, sphere_scene, sphere_bounds, n_req=1500, seed=5):
     """Continuous batching vs the plain per-request path on one request
     stream over device-resident bounds: the displaced sphere and a rippled
@@ -283,6 +326,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-refraction", action="store_true")
     ap.add_argument("--no-two-reflections", action="store_true")
+    ap.add_argument("--no-samplers", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device tensor copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -379,6 +423,8 @@ def main():
                  "newton_starts": qs["n_newton"], "roots": qs["n_roots"]},
     }
 
+    if not args.no_samplers:
+        out["samplers"] = samplers_section(bbc, torch, B, pts)
     if not args.no_serving:
         out["serving"] = serving_section(bbc, S, torch, scene, B)
     if not args.no_refraction:
