@@ -5,6 +5,7 @@
 #include <cmath>
 #include <limits>
 #include <stdexcept>
+#include <vector>
 
 namespace orc {
 
@@ -69,15 +70,25 @@ Bern mul(const Bern& A, const Bern& B) {
   Deg d;
   for (int a = 0; a < kAxes; ++a) d[a] = A.deg[a] + B.deg[a];
   Bern C(d);
+  // the binomials and multi-indices the sum below uses, tabulated once per
+  // call (the same values binom() returns, in the same order of operations)
+  std::array<std::vector<double>, kAxes> bA, bB, bC;
+  for (int a = 0; a < kAxes; ++a) {
+    for (int i = 0; i <= A.deg[a]; ++i) bA[a].push_back(binom(A.deg[a], i));
+    for (int i = 0; i <= B.deg[a]; ++i) bB[a].push_back(binom(B.deg[a], i));
+    for (int i = 0; i <= d[a]; ++i) bC[a].push_back(binom(d[a], i));
+  }
+  std::vector<std::array<int, kAxes>> MB(B.size());
+  for (size_t ib = 0; ib < B.size(); ++ib) MB[ib] = B.multi(ib);
   for (size_t ia = 0; ia < A.size(); ++ia) {
     const auto mi = A.multi(ia);
     for (size_t ib = 0; ib < B.size(); ++ib) {
-      const auto mj = B.multi(ib);
+      const auto& mj = MB[ib];
       std::array<int, kAxes> mk;
       double w = 1.0;
       for (int a = 0; a < kAxes; ++a) {
         mk[a] = mi[a] + mj[a];
-        w *= binom(A.deg[a], mi[a]) * binom(B.deg[a], mj[a]) / binom(d[a], mk[a]);
+        w *= bA[a][size_t(mi[a])] * bB[a][size_t(mj[a])] / bC[a][size_t(mk[a])];
       }
       C.at(mk) += w * A.c[ia] * B.c[ib];
     }

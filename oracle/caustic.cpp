@@ -384,7 +384,11 @@ static bool pair_candidate(const Tuple& c) {
 // reflection law dropped) and the receiver coordinates u_k = Pu3/(Q3 Q2) of
 // degree (16, 16) over (15, 15).  No irradiance bound is formed for this chain:
 // E = [0, inf).
-static BoxBound bound_box_rr(const Tuple& c, double u0, double u1, double v0, double v1) {
+static void irradiance_from(const Tuple& c, const BV& d0, const Bern& Q, const Bern& Pu, const Bern& Pv,
+                            const Bern& Qu, const Bern& Qv, const Bern& Puu, const Bern& Puv, const Bern& Pvu,
+                            const Bern& Pvv, BoxBound* bb);
+
+static BoxBound bound_box_rr(const Tuple& c, double u0, double u1, double v0, double v1, bool want_irr) {
   BoxBound bb;
   if (!c.front) return bb;
   if (u0 + v0 >= 1.0) return bb;
@@ -431,13 +435,22 @@ static BoxBound bound_box_rr(const Tuple& c, double u0, double u1, double v0, do
   bb.settled = inside2 && ub.kind == kDirect && vb.kind == kDirect && ub.lo >= 0.0 && ub.hi <= 1.0 &&
                vb.lo >= 0.0 && vb.hi <= 1.0 && tb.kind == kDirect && tb.lo > 0.0;
   bb.live = true;
+  if (!want_irr) return bb;
+  // Irradiance bound of the chain parametrised by the first vertex (the
+  // generalised geometric term of Sec. 4.4 holds for any chain whose receiver
+  // point is a function of u1): det(du_k/du1) = det M / Den^3 with M built from
+  // (Den, Pu3, Pv3) and their u-, v-derivatives; det M has degree (46, 46).
+  const double wu = u1 - u0, wv = v1 - v0;
+  irradiance_from(c, d0, Den, Pu3, Pv3, scale(deriv(Den, 0), 1.0 / wu), scale(deriv(Den, 1), 1.0 / wv),
+                  scale(deriv(Pu3, 0), 1.0 / wu), scale(deriv(Pu3, 1), 1.0 / wv), scale(deriv(Pv3, 0), 1.0 / wu),
+                  scale(deriv(Pv3, 1), 1.0 / wv), &bb);
   return bb;
 }
 
 // Position and irradiance bound of one box of the barycentric domain of u1
 // (Sec. 4.2: U_k and [E_lo, E_hi] from coefficient ratios).
 static BoxBound bound_box(const Tuple& c, double u0, double u1, double v0, double v1, bool want_irr, int flags) {
-  if (c.chain == 2) return bound_box_rr(c, u0, u1, v0, v1);
+  if (c.chain == 2) return bound_box_rr(c, u0, u1, v0, v1, want_irr);
   BoxBound bb;
   if (!c.front) return bb;
   if (u0 + v0 >= 1.0) return bb;  // box lies outside the triangle u + v <= 1
@@ -530,14 +543,24 @@ static BoxBound bound_box(const Tuple& c, double u0, double u1, double v0, doubl
                vb.hi <= 1.0 && tb.kind == kDirect && tb.lo > 0.0;
   bb.live = true;
   if (!want_irr) return bb;
-  // irradiance bound: det(du_k/du1) = det M / Q^3 with
-  // M = [[Q, Pu, Pv], [Q_u, Pu_u, Pv_u], [Q_v, Pu_v, Pv_v]] (Sec. 4.4, Eq. eq_irr_term3a)
+  irradiance_from(c, d0, Q, Pu, Pv, Qu, Qv, Puu, Puv, Pvu, Pvv, &bb);
+  return bb;
+}
+
+// Irradiance bound [E_lo, E_hi] of a box from the receiver map u_k = (Pu/Q,
+// Pv/Q) and its total derivatives: det(du_k/du1) = det M / Q^3 with
+// M = [[Q, Pu, Pv], [Q_u, Pu_u, Pv_u], [Q_v, Pu_v, Pv_v]] (Sec. 4.4, Eq.
+// eq_irr_term3a), |du1/du_k| bounded by the ratio of Q^3 to det M, and
+// dOmega0/dA1 = |g| / h^(3/2) with g = n_g . d0 and h = d0 . d0 bounded
+// factor-wise; E = I0 (A1 / A_k) G1 |Q^3 / det M|.
+static void irradiance_from(const Tuple& c, const BV& d0, const Bern& Q, const Bern& Pu, const Bern& Pv,
+                            const Bern& Qu, const Bern& Qv, const Bern& Puu, const Bern& Puv, const Bern& Pvu,
+                            const Bern& Pvv, BoxBound* bb) {
   const Bern detM = add(sub(mul(Q, sub(mul(Puu, Pvv), mul(Pvu, Puv))), mul(Pu, sub(mul(Qu, Pvv), mul(Pvu, Qv)))),
                         mul(Pv, sub(mul(Qu, Puv), mul(Puu, Qv))));
   const Bern Q3 = mul(mul(Q, Q), Q);
   double rlo, rhi;
   abs_bound(ratio_bound(Q3, detM), &rlo, &rhi);
-  // dOmega0/dA1 = |g| / h^(3/2) with g = n_g . d0 and h = d0 . d0, bounded factor-wise
   double glo, ghi, hlo, hhi;
   coef_range(dotC(d0, c.ng), &glo, &ghi);
   coef_range(dotB(d0, d0), &hlo, &hhi);
@@ -546,9 +569,8 @@ static BoxBound bound_box(const Tuple& c, double u0, double u1, double v0, doubl
   const double Glo = aglo / std::pow(hhi, 1.5);
   const double Ghi = hlo > 0.0 ? aghi / std::pow(hlo, 1.5) : kInf;
   const double k = c.I0 * c.a1 / c.ak;
-  bb.E[0] = (Glo == 0.0 || rlo == 0.0) ? 0.0 : k * Glo * rlo;
-  bb.E[1] = (std::isinf(Ghi) || std::isinf(rhi)) ? kInf : k * Ghi * rhi;
-  return bb;
+  bb->E[0] = (Glo == 0.0 || rlo == 0.0) ? 0.0 : k * Glo * rlo;
+  bb->E[1] = (std::isinf(Ghi) || std::isinf(rhi)) ? kInf : k * Ghi * rhi;
 }
 
 // ---------------------------------------------------------------- build

@@ -2,7 +2,8 @@
 applied twice against an ordinary ray tracer, its Jacobian against finite
 differences, its irradiance against the solid angle of a ray triangle over
 the receiver area it lands on, the double-mirror image source, containment of
-every leaf's position bound (Sec. 4.2), and test (c) over all tuples: every
+every leaf's position and irradiance bound (Sec. 4.2, 4.4) and the
+irradiance bound's tightness on small boxes, and test (c) over all tuples: every
 admissible path lies in a tuple of its cell list (so pair culling and the
 bounds lose nothing) and the leaf-seeded search finds almost all of them."""
 import numpy as np
@@ -137,16 +138,21 @@ def test_rr_jacobian_and_irradiance_first_principles(orc, walls):
         assert abs(om / area - e["Ek"]) <= 2e-3 * e["Ek"], (t, u, v, om / area, e["Ek"])
 
 
-def test_rr_position_bounds_contain_paths(orc, walls):
+def test_rr_bounds_contain_paths(orc, walls):
+    """Every leaf's position bound and irradiance bound contain u_k and E_k
+    (E_k pinned from first principles above) of the admissible paths through
+    a grid of its box."""
     sc, osc, b = walls
     L = b.leaves()
-    assert np.all(np.isinf(L["E"][:, 1]))  # no irradiance bound for this chain
+    fin = np.isfinite(L["E"][:, 1])
+    assert fin.mean() > 0.8  # the chain's irradiance bound is finite on most leaves
     n_paths = 0
     rng = np.random.default_rng(4)
     for k in rng.choice(len(L["tuple"]), 200, replace=False):
         t = L["tuple"][k]
         u0, u1, v0, v1 = L["box"][k]
         ulo, uhi, vlo, vhi = L["uk"][k]
+        Elo, Ehi = L["E"][k]
         for u in np.linspace(u0, u1, 9):
             for v in np.linspace(v0, v1, 9):
                 e = orc.eval_path(osc, t, u, v)
@@ -154,7 +160,35 @@ def test_rr_position_bounds_contain_paths(orc, walls):
                     continue
                 n_paths += 1
                 assert ulo - 1e-9 <= e["uk"] <= uhi + 1e-9 and vlo - 1e-9 <= e["vk"] <= vhi + 1e-9, (t, u, v)
+                assert Elo * (1 - 1e-9) <= e["Ek"] <= Ehi * (1 + 1e-9), (t, u, v, e["Ek"], Elo, Ehi)
     assert n_paths > 500
+
+
+def test_rr_irradiance_bound_is_tight_on_small_boxes(orc, walls):
+    """On small boxes around admissible paths the bound is no wider than 1.5
+    times the range of E_k sampled over the box (a dropped or wrong term in
+    det M or Den^3 would leave it far looser or cut into the range)."""
+    sc, osc, b = walls
+    L = b.leaves()
+    n_checked = 0
+    for k in np.nonzero(np.isfinite(L["E"][:, 1]))[0][:80]:
+        t = L["tuple"][k]
+        u0, u1, v0, v1 = L["box"][k]
+        uc, vc = 0.5 * (u0 + u1), 0.5 * (v0 + v1)
+        if not orc.eval_path(osc, t, uc, vc)["admissible"]:
+            continue
+        h = (u1 - u0) / 32
+        bb = orc.box_bound(osc, t, [uc - h, uc + h, vc - h, vc + h])
+        if not (bb["live"] and np.isfinite(bb["E"][1])):
+            continue
+        E = [orc.eval_path(osc, t, u, v) for u in np.linspace(uc - h, uc + h, 7) for v in np.linspace(vc - h, vc + h, 7)]
+        if not all(e["admissible"] for e in E):
+            continue
+        E = np.array([e["Ek"] for e in E])
+        assert bb["E"][0] <= E.min() * (1 + 1e-9) and bb["E"][1] >= E.max() * (1 - 1e-9)
+        assert bb["E"][1] - bb["E"][0] <= 1.5 * (E.max() - E.min()) + 1e-9 * E.max(), (k, bb["E"], E.min(), E.max())
+        n_checked += 1
+    assert n_checked >= 10
 
 
 def test_rr_c_every_path_is_in_its_cell_list(orc, walls):
