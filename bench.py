@@ -209,7 +209,7 @@ def two_reflection_section(bbc, S, torch, steps=2):
     n = pts.shape[1]
     b, q = float(np.median(tb)), float(np.median(tq))
     return {"workload": "two reflections, facing walls 8192 + 8192 triangles (67.1M candidate pairs), depth cap 2, "
-                        "256x256 floor points, 256 samples/point; position bounds only (E = [0, inf), P = 1)",
+                        "256x256 floor points, 256 samples/point",
             "queries_s_whole_step": round(n / (b + q), 1), "build_ms": round(1e3 * b, 2),
             "query_ms": round(1e3 * q, 2), "first_build_ms": round(1e3 * first_build, 1),
             "candidate_pairs": info["n_tuples"], "live_tuples": info["n_live_tuples"], "boxes": info["n_boxes"],

@@ -119,10 +119,10 @@ typedef struct bbc_bounds bbc_bounds;
  * the first surface and t2 on the second, numbered (emitter * n_tri + t1) *
  * n_tri2 + t2 (below 2^32).  Tuple construction (Sec. 6.1) keeps the pairs
  * whose interval bound of (x2 - x1) x d~1 covers zero; this costs one host
- * synchronisation, since the pair count sizes the per-tuple buffers.  Only
- * position bounds are formed for this chain (the irradiance denominator
- * reaches degree 46 per axis): every leaf has E = [0, inf), so every candidate
- * is sampled with P = 1 and the estimate is the exhaustive sum. */
+ * synchronisation, since the pair count sizes the per-tuple buffers.  The
+ * irradiance bound of this chain (Sec. 4.4, with u1 as the parameter: det M
+ * of degree 46 per axis over Den^3) takes the ratio's coefficient signs as
+ * computed in FP64; a box whose det M changes sign gets E = [0, inf). */
 bbc_status bbc_build_bounds(const bbc_scene* scene, const bbc_emitters* emitters, const bbc_subdiv_params* params,
                             void* stream, bbc_bounds** out);
 

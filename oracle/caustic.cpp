@@ -382,8 +382,8 @@ static bool pair_candidate(const Tuple& c) {
 // with x2 = X2/Q2 and n2 = N2/Q2, the second reflection
 // d~2 = (N2.N2) D1 - 2 (D1.N2) N2 (D1 = X2 - Q2 x1, the common factors of the
 // reflection law dropped) and the receiver coordinates u_k = Pu3/(Q3 Q2) of
-// degree (16, 16) over (15, 15).  No irradiance bound is formed for this chain:
-// E = [0, inf).
+// degree (16, 16) over (15, 15).  The irradiance bound follows the box's
+// position bound (see irradiance_from).
 static void irradiance_from(const Tuple& c, const BV& d0, const Bern& Q, const Bern& Pu, const Bern& Pv,
                             const Bern& Qu, const Bern& Qv, const Bern& Puu, const Bern& Puv, const Bern& Pvu,
                             const Bern& Pvv, BoxBound* bb);

@@ -9,8 +9,7 @@
  * Conventions: every array is FP64, structure-of-arrays, owned by the caller.
  * Functions return 0 (or a count >= 0) on success and a negative value on bad
  * arguments.  Tuples are numbered emitter * n_tri + triangle; for two
- * reflections (emitter * n_tri + t1) * n_tri2 + t2.  The two-reflection chain
- * has position bounds only (E = [0, inf)).
+ * reflections (emitter * n_tri + t1) * n_tri2 + t2.
  */
 #ifndef CAUSTIC_ORACLE_H
 #define CAUSTIC_ORACLE_H

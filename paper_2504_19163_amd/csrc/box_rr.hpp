@@ -12,8 +12,18 @@
 //   S3 = X2 - Q2 q0,  ray parameter ((S3 x f1).f2) / (Q3 Q2),
 // numerators of degree (16,16) over a denominator of degree (15,15).  A box is
 // culled when the ray to the second plane cannot go forward, cannot reach the
-// second triangle's front side, or u2 cannot meet the second triangle.  No
-// irradiance bound is formed for this chain: E = [0, inf).
+// second triangle's front side, or u2 cannot meet the second triangle.
+//
+// Irradiance bound (IRR, Sec. 4.4).  The receiver point is a function of u1
+// alone, so the generalised geometric term of the single bounce holds for the
+// chain: E = I0 (A1 / A_k) G1 |Den^3 / det M| with
+// M = [[Den, Pu3, Pv3], [Den_u, Pu3_u, Pv3_u], [Den_v, Pu3_v, Pv3_v]] and
+//   det M = Den (Pu3_u Pv3_v - Pv3_u Pu3_v) - Pu3 (Den_u Pv3_v - Pv3_u Den_v)
+//         + Pv3 (Den_u Pu3_v - Pu3_u Den_v)                         (46,46),
+// the derivatives taken in the box's local coordinates (det M then carries
+// the factor 1 / (w_u w_v), restored on the ratio).  These tensors need about
+// 90 KB of LDS; they reuse the buffers of the position bound that are dead
+// by then, and four waves share a box.
 #pragma once
 #include "box_t.hpp"
 
@@ -32,16 +42,64 @@ struct RRLay {
   static constexpr int PU3 = 5182, PV3 = 5760;                                   // (16,16)
   static constexpr int TN3 = 6338, TN3E = 6388;                                  // (4,4), (15,15)
   static constexpr int END = 6900;
+  // irradiance bound, after the position bound: G1, H1 hold values then
+  // magnitudes; the det M / Den^3 tensors hold values only
+  static constexpr int G1 = 6400, H1 = 6410;                                     // n_g.d0 (1,1), d0.d0 (2,2)
+  static constexpr int PUU = 0, PUV = 272, PVU = 544, PVV = 816;                 // (15,16), (16,15)
+  static constexpr int DENU = 1088, DENV = 1328;                                 // (14,15), (15,14)
+  static constexpr int DETM = 6900, MINOR = 9109;                                // (46,46); A (31,31) | B, C (30,30)
+  static constexpr int DEN2 = 0, DEN3 = 9109, DEN3E = 0;                         // (30,30), (45,45), (46,46)
+  static constexpr int END_IRR = 11225;
 };
 
-template <class T>
+template <class T, bool IRR = false>
 struct LdsRR {
-  T buf[RRLay::END];
+  T buf[IRR ? RRLay::END_IRR : RRLay::END];
 };
 
-template <class T>
-__device__ BoxOut eval_box_rr(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, LdsRR<T>& L, int lane) {
-  constexpr int NT = BBC_WAVE;
+// Local derivative along one axis in scaled Bernstein form:
+// s'_i = (i + 1) s_{i+1} - (D - i) s_i, degree one lower along that axis
+// (values only: the irradiance ratio is taken at face value).
+template <int D1, int D2, int AXIS, class T, int NT>
+__device__ __forceinline__ void bern_deriv(const T* in, T* out, int lane) {
+  constexpr int O1 = AXIS == 0 ? D1 - 1 : D1, O2 = AXIS == 0 ? D2 : D2 - 1;
+  for (int o = lane; o < (O1 + 1) * (O2 + 1); o += NT) {
+    const int i = o / (O2 + 1), j = o - i * (O2 + 1);
+    const int ka = AXIS == 0 ? (i + 1) * (D2 + 1) + j : i * (D2 + 1) + j + 1;
+    const int kb = i * (D2 + 1) + j;
+    const T ca = T(AXIS == 0 ? i + 1 : j + 1), cb = T(AXIS == 0 ? D1 - i : D2 - j);
+    out[o] = fma(ca, in[ka], -(cb * in[kb]));
+  }
+}
+
+// c (=|+=) sgn * conv(a, b) on values only, for the large tensors of the
+// irradiance bound: the sums of conv() over each output's valid index range
+// in runtime loops (full unrolling at these degrees costs more registers than
+// a wave has).
+template <int A1, int A2, int B1, int B2, bool ACC, int NT, class T>
+__device__ __forceinline__ void cv_wide(const T* a, const T* b, T* c, T sgn, int lane) {
+  constexpr int C2 = A2 + B2, N = (A1 + B1 + 1) * (C2 + 1);
+  for (int o = lane; o < N; o += NT) {
+    const int k = o / (C2 + 1), l = o - k * (C2 + 1);
+    const int i0 = k - B1 > 0 ? k - B1 : 0, i1 = k < A1 ? k : A1;
+    const int j0 = l - B2 > 0 ? l - B2 : 0, j1 = l < A2 ? l : A2;
+    T s = 0;
+#pragma nounroll
+    for (int i = i0; i <= i1; ++i) {
+      const T* av = a + i * (A2 + 1);
+      const T* bv = b + (k - i) * (B2 + 1) + l;
+#pragma unroll 4
+      for (int j = j0; j <= j1; ++j) s = fma(av[j], bv[-j], s);
+    }
+    c[o] = ACC ? fma(sgn, s, c[o]) : sgn * s;
+  }
+}
+
+// Always inlined into its kernel: as a separate function, the irradiance
+// instantiation came back with corrupted receiver bounds after its calls to
+// the (non-inlined) ratio-bound helpers, while the same code inlined is exact.
+template <class T, bool IRR = false, int NT = BBC_WAVE>
+__device__ __forceinline__ BoxOut eval_box_rr(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, LdsRR<T, IRR>& L, int lane) {
   const bool final = true;
   const T eps = Eps<T>::u;
   T* B = L.buf;
@@ -312,7 +370,113 @@ __device__ BoxOut eval_box_rr(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, Lds
   out.settled = inside2 && ub.kind == kDirect && vb.kind == kDirect && ub.lo >= T(0) && ub.hi <= T(1) &&
                 vb.lo >= T(0) && vb.hi <= T(1) && tb.kind == kDirect && tb.lo > T(0);
   out.status = 1;
-  return out;
+  if constexpr (!IRR) {
+    return out;
+  } else {
+    // ---- G1 = |g| / h^(3/2), g = n_g . d0, h = d0 . d0 (d0 is still in LDS)
+    const TP<T> g1 = tpat(B, RRLay::G1, 4), h1 = tpat(B, RRLay::H1, 9);
+    {
+      const T* dv[3] = {lin(RRLay::D0v, 0).v, lin(RRLay::D0v, 1).v, lin(RRLay::D0v, 2).v};
+      const T* dm[3] = {lin(RRLay::D0v, 0).m, lin(RRLay::D0v, 1).m, lin(RRLay::D0v, 2).m};
+      const T ag[3] = {G.ng.x, G.ng.y, G.ng.z};
+      combo<4, 3, false, T, NT>(dv, dm, ag, g1.v, g1.m, lane);
+      for (int c = 0; c < 3; ++c) {
+        if (c == 0)
+          cv<1, 1, 1, 1, false, NT>(lin(RRLay::D0v, c), lin(RRLay::D0v, c), h1, T(1), lane);
+        else
+          cv<1, 1, 1, 1, true, NT>(lin(RRLay::D0v, c), lin(RRLay::D0v, c), h1, T(1), lane);
+      }
+    }
+    const T th_g = th_lin + T(8) * eps;  // the unit normal carries a few roundings of its own
+    const T th_h = th_conv<1, 1, 1, 1>(th_lin, th_lin, 3) + T(3) * eps;
+    wave_sync();
+    T glo, ghi, hlo, hhi;
+    poly_range<1, 1, T, NT>(g1.v, g1.m, th_g, &glo, &ghi, lane);
+    poly_range<2, 2, T, NT>(h1.v, h1.m, th_h, &hlo, &hhi, lane);
+    wave_sync();
+    // ---- local derivatives of Den, Pu3, Pv3
+    T* const puu = B + RRLay::PUU;
+    T* const puv = B + RRLay::PUV;
+    T* const pvu = B + RRLay::PVU;
+    T* const pvv = B + RRLay::PVV;
+    T* const denu = B + RRLay::DENU;
+    T* const denv = B + RRLay::DENV;
+    bern_deriv<16, 16, 0, T, NT>(pu3.v, puu, lane);
+    bern_deriv<16, 16, 1, T, NT>(pu3.v, puv, lane);
+    bern_deriv<16, 16, 0, T, NT>(pv3.v, pvu, lane);
+    bern_deriv<16, 16, 1, T, NT>(pv3.v, pvv, lane);
+    bern_deriv<15, 15, 0, T, NT>(den.v, denu, lane);
+    bern_deriv<15, 15, 1, T, NT>(den.v, denv, lane);
+    wave_sync();
+    // ---- det M = Den A - Pu3 B + Pv3 C with the minors
+    //   A = Pu_u Pv_v - Pv_u Pu_v, B = Den_u Pv_v - Pv_u Den_v, C = Den_u Pu_v - Pu_u Den_v
+    // formed one at a time in one buffer, each added to det M before the next
+    T* const detm = B + RRLay::DETM;
+    T* const minor = B + RRLay::MINOR;
+    cv_wide<15, 16, 16, 15, false, NT>(puu, pvv, minor, T(1), lane);
+    cv_wide<15, 16, 16, 15, true, NT>(pvu, puv, minor, T(-1), lane);
+    wave_sync();
+    cv_wide<15, 15, 31, 31, false, NT>(den.v, minor, detm, T(1), lane);
+    wave_sync();
+    cv_wide<14, 15, 16, 15, false, NT>(denu, pvv, minor, T(1), lane);
+    cv_wide<15, 16, 15, 14, true, NT>(pvu, denv, minor, T(-1), lane);
+    wave_sync();
+    cv_wide<16, 16, 30, 30, true, NT>(pu3.v, minor, detm, T(-1), lane);
+    wave_sync();
+    cv_wide<14, 15, 16, 15, false, NT>(denu, puv, minor, T(1), lane);
+    cv_wide<15, 16, 15, 14, true, NT>(puu, denv, minor, T(-1), lane);
+    wave_sync();
+    cv_wide<16, 16, 30, 30, true, NT>(pv3.v, minor, detm, T(1), lane);
+    wave_sync();
+    // ---- Den^3, elevated to (46, 46): the scaled coefficient (i, j) is the
+    // sum of the (up to four) degree-(45, 45) neighbours (i-1..i, j-1..j)
+    T* const den2 = B + RRLay::DEN2;
+    T* const den3 = B + RRLay::DEN3;
+    T* const den3e = B + RRLay::DEN3E;
+    cv_wide<15, 15, 15, 15, false, NT>(den.v, den.v, den2, T(1), lane);
+    wave_sync();
+    cv_wide<30, 30, 15, 15, false, NT>(den2, den.v, den3, T(1), lane);
+    wave_sync();
+    for (int o = lane; o < 47 * 47; o += NT) {
+      const int i = o / 47, j = o - i * 47;
+      const T a = (i <= 45 && j <= 45) ? den3[i * 46 + j] : T(0);
+      const T b = (i >= 1 && j <= 45) ? den3[(i - 1) * 46 + j] : T(0);
+      const T c = (i <= 45 && j >= 1) ? den3[i * 46 + j - 1] : T(0);
+      const T d = (i >= 1 && j >= 1) ? den3[(i - 1) * 46 + j - 1] : T(0);
+      den3e[o] = (a + b) + (c + d);
+    }
+    wave_sync();
+    // |Den^3 / det M| at face value: with rounding control, det M's
+    // coefficients (three nested cancellations at degree (46, 46)) leave
+    // their signs undecided on most boxes; the bound takes them as computed
+    const RB<T> rb = ratio_bound_fn<T, NT>(
+        2209,
+        [&](int o, T& p, T& ep, T& q, T& eq) {
+          q = detm[o];
+          p = den3e[o];
+          ep = eq = T(0);
+        },
+        final, lane);
+    T rlo, rhi;
+    abs_bound(rb, &rlo, &rhi);
+    // det M from local derivatives is w_u w_v times the global one (each
+    // term has one u- and one v-derivative): the global ratio is the local
+    // one times w_u w_v
+    const T area = (u1 - u0) * (v1 - v0);
+    rlo = down(rlo * area * (T(1) - T(4) * eps));
+    rhi = isinf(rhi) ? rhi : up(rhi * area * (T(1) + T(4) * eps));
+    const T aglo = (glo <= T(0) && ghi >= T(0)) ? T(0) : min(fabs(glo), fabs(ghi));
+    const T aghi = max(fabs(glo), fabs(ghi));
+    const T Glo = down(aglo / (hhi * sqrt(hhi)));
+    const T Ghi = hlo > T(0) ? up(aghi / (hlo * sqrt(hlo))) : T(INFINITY);
+    const T k = G.I0 * G.a1 / G.ak;
+    const T klo = k * (T(1) - T(16) * eps), khi = k * (T(1) + T(16) * eps);
+    const T Elo = (Glo <= T(0) || rlo <= T(0)) ? T(0) : down(klo * down(Glo * rlo));
+    const T Ehi = (isinf(Ghi) || isinf(rhi)) ? T(INFINITY) : up(khi * up(Ghi * rhi));
+    out.E[0] = out_lo(Elo);
+    out.E[1] = out_hi(Ehi);
+    return out;
+  }
 }
 
 }  // namespace bbc

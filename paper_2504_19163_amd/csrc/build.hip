@@ -644,14 +644,18 @@ __global__ void __launch_bounds__(64) k_subdiv(BuildArgs a, int depth) {
   subdiv_loop<BBC_WAVE>(a, depth, ev, lane, S);
 }
 
-__global__ void __launch_bounds__(64) k_subdiv_rr(BuildArgs a, int depth) {
-  __shared__ LdsRR<double> L;
+// A two-reflection subdivision box also carries the irradiance bound, whose
+// det M of degree (46, 46) takes ~90 KB of LDS: one box per compute unit,
+// four waves on it.
+constexpr int kSubdivRRThreads = 256;
+__global__ void __launch_bounds__(kSubdivRRThreads) k_subdiv_rr(BuildArgs a, int depth) {
+  __shared__ LdsRR<double, true> L;
   __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
-    return eval_box_rr<double>(G, u0, u1, v0, v1, L, lane);
+    return eval_box_rr<double, true, kSubdivRRThreads>(G, u0, u1, v0, v1, L, lane);
   };
-  subdiv_loop<BBC_WAVE>(a, depth, ev, lane, S);
+  subdiv_loop<kSubdivRRThreads>(a, depth, ev, lane, S);
 }
 
 // A refraction box takes ~1.5 Mflop of FP64 over ~90 KB of LDS: four waves
@@ -737,7 +741,7 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
     a.qin = static_cast<QItem*>(b->q[d & 1].p);
     a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
     if (rr)
-      hipLaunchKernelGGL(k_subdiv_rr, dim3(persistent), dim3(64), 0, s, a, d);
+      hipLaunchKernelGGL(k_subdiv_rr, dim3(unsigned(n_cu)), dim3(kSubdivRRThreads), 0, s, a, d);
     else if (refr)
       hipLaunchKernelGGL(k_subdiv_t, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTThreads), 0, s, a, d);
     else

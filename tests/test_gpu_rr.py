@@ -47,7 +47,7 @@ def test_rr_tree_and_bounds(bbc, orc, walls):
     L, OL = B.leaves(), Ob.leaves()
     print("leaves", len(L["tuple"]), "oracle", len(OL["tuple"]), flush=True)
     assert gpu_checks.keyset(L) == gpu_checks.keyset(OL)
-    gpu_checks.check_leaf_bounds(orc, osc, L, range(len(L["tuple"])))
+    gpu_checks.check_leaf_bounds(orc, osc, L, range(len(L["tuple"])), e_face_value=True)
     info, st = B.info(), Ob.stats()
     assert info["n_tuples"] == st["tuples"]
     assert info["n_live_tuples"] == st["live_tuples"]
@@ -64,7 +64,12 @@ def test_rr_grid_matches_oracle(bbc, orc, walls):
         ot, oe = Ob.cell_list(cu, cv)
         a, b = off[c], off[c + 1]
         assert np.array_equal(gt[a:b].astype(np.int64), ot), c
-        assert np.all(np.isinf(ge[a:b])) and np.all(np.isinf(oe))
+        # E~ from a ratio taken at face value on both sides: equal up to the
+        # order of the FP64 sums and the outward FP32 rounding
+        e = ge[a:b].astype(np.float64)
+        fin = np.isfinite(oe)
+        assert np.array_equal(np.isfinite(e), fin), c
+        assert np.all(np.abs(e[fin] - oe[fin]) <= gpu_checks.BOUND_TOL * np.abs(oe[fin])), c
 
 
 @pytest.mark.parametrize("form", ["staged", "fused"])
