@@ -50,8 +50,8 @@ FLOPS_PER_PATH_EVAL = 290
 NEWTON_COUNTERS = dict(
     sources=["paper_2504_19163_amd/csrc/query.hip", "paper_2504_19163_amd/csrc/path_dev.hpp",
              "paper_2504_19163_amd/csrc/geom_dev.hpp", "paper_2504_19163_amd/csrc/dev_common.hpp"],
-    sha256="67a8d3bb216a308b2c8569e47d2e64884e6e22801f63d84ea275e5f0594f7d5a",
-    fetch_kib=40843.25, write_kib=47796.875, fetch_scale=262144.0 / 131087.875, write_scale=1.0)
+    sha256="6727f06a35b63eccb3e61e81f9a134817530374151e0f3dbd2326f8deec5ad1d",
+    fetch_kib=40824.125, write_kib=46767.125, fetch_scale=262144.0 / 131087.875, write_scale=1.0)
 
 
 def newton_traffic_bytes():

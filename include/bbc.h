@@ -214,7 +214,8 @@ bbc_status bbc_query_irradiance_ex(const bbc_bounds* b, const float* points_dev,
 /* Launch-shape knobs (chosen by the autotuner; results never depend on them):
  *  BBC_TUNE_QUERY_WAVES        fused query register budget: 2 (256 VGPRs) or 4 (128) waves per SIMD
  *  BBC_TUNE_QUERY_GRID         fused query persistent workgroups (1..2^20)
- *  BBC_TUNE_BUILD_GRID_PER_CU  subdivision persistent workgroups per compute unit (1..64)
+ *  BBC_TUNE_BUILD_GRID_PER_CU  persistent build kernels: workgroups per compute unit (1..64),
+ *                              or 0 (default) for one resident round of each kernel
  *  BBC_TUNE_QUERY_TILE         fused query shading points per wave: 16, 32 or 64
  *  BBC_TUNE_TIMING             1: record HIP events on the query stream around the
  *                              query's dominant kernel (see bbc_query_kernel_ms)

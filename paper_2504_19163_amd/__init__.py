@@ -1,6 +1,6 @@
 """Bernstein-bound caustics on AMD Instinct MI355X.
 
 The method runs in the HIP library libbbc.so (C ABI in include/bbc.h); this
-package holds its Python binding (bbc), its build step (build_lib), the
-seeded input generators (scenes) and the launch-shape autotuner (autotune).
+package holds its Python binding (bbc), its build step (build_lib) and the
+seeded input generators (scenes).
 """

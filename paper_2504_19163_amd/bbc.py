@@ -383,9 +383,10 @@ TUNING_FILE = os.path.join(HERE, "tuning.json")
 
 
 def apply_tuning(bounds, workload_key, path=TUNING_FILE):
-    """Apply the autotuner's launch-shape choices for this device and workload
-    (written by paper_2504_19163_amd.autotune); returns the chosen entry, or {}
-    when none was recorded.  Results never depend on these knobs."""
+    """Apply launch-shape choices recorded for this device and workload in a
+    JSON table ({arch: {workload: {knob: value}}}, tuning.json beside this
+    module); returns the chosen entry, or {} when none was recorded.  Results
+    never depend on these knobs."""
     import json
     if not os.path.exists(path):
         return {}

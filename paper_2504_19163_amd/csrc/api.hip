@@ -439,7 +439,7 @@ bbc_status bbc_set_tuning(bbc_bounds* h, int32_t knob, int64_t value) {
       b->tune.query_grid = int(value);
       return BBC_OK;
     case BBC_TUNE_BUILD_GRID_PER_CU:
-      if (value < 1 || value > 64) return invalid("build grid per CU must be in [1, 64]");
+      if (value < 0 || value > 64) return invalid("build grid per CU must be in [0, 64]");
       b->tune.build_grid_per_cu = int(value);
       return BBC_OK;
     case BBC_TUNE_QUERY_TILE:

@@ -13,9 +13,11 @@
 //                  be given a sign in FP32
 //   k_*_t          the refraction chain: every box in FP64 (box_t.hpp)
 //   k_pairs_*      two reflections: tuple construction over all triangle pairs
-//   k_*_rr         two reflections: position bounds in FP64 (box_rr.hpp)
+//   k_*_rr         two reflections: position and irradiance bounds in FP64 (box_rr.hpp)
 // No host synchronisation happens between launches; every count lives in
 // device memory and every buffer has a capacity checked on the device.
+#include <atomic>
+
 #include "box_r.hpp"
 #include "box_rr.hpp"
 #include "box_t.hpp"
@@ -435,10 +437,17 @@ __device__ void init_one(const BuildArgs& a, uint32_t t, Ev ev, InitBox* cur, In
 // Domain initialisation of reflection tuples: the four children of a box are
 // bounded at once (16 lanes each, FP32); a child whose denominator sign is
 // undecided is redone by the whole wave in FP64.  Children are kept in child
-// order, so the result is that of the one-child-at-a-time loop.
+// order, so the result is that of the one-child-at-a-time loop.  The FP64
+// redo starts after the FP32 results are read, so its tensors share the FP32
+// tensors' LDS (15 KB per wave).
+union InitLds {
+  LdsRPos<float> f[kGroups];
+  LdsRPos<double> d;
+};
 __global__ void __launch_bounds__(64) k_init(BuildArgs a) {
-  __shared__ LdsRPos<float> Lf[kGroups];
-  __shared__ LdsRPos<double> Ld;
+  __shared__ InitLds U;
+  LdsRPos<float>* const Lf = U.f;
+  LdsRPos<double>& Ld = U.d;
   __shared__ InitBox cur[kInitCap], nxt[kInitCap];
   __shared__ Stage S;
   __shared__ int res_status[kGroups], res_settled[kGroups];
@@ -684,6 +693,23 @@ bbc_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   return BBC_OK;
 }
 
+// Workgroups of `kernel` (64 threads) that stay resident together on the
+// device: the persistent kernels stride statically over their items, so a
+// grid of exactly one round has no tail of late-starting workgroups.
+template <class K>
+static bbc_status resident_grid(K kernel, int slot, int dev, int n_cu, unsigned* out) {
+  static std::atomic<unsigned> cache[64][4];
+  if (dev < 64 && cache[dev][slot].load() > 0u) {
+    *out = cache[dev][slot].load();
+    return BBC_OK;
+  }
+  int per_cu = 0;
+  BBC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), 64, 0));
+  *out = unsigned(std::max(1, per_cu)) * unsigned(std::max(1, n_cu));
+  if (dev < 64) cache[dev][slot].store(*out);
+  return BBC_OK;
+}
+
 bbc_status launch_build(Bounds* b, hipStream_t s) {
   BuildArgs a{};
   a.sc = b->scene;
@@ -710,7 +736,19 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   BBC_HIP(hipGetDevice(&dev));
   int n_cu = 256;
   BBC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  const unsigned persistent = unsigned(n_cu) * unsigned(std::max(1, b->tune.build_grid_per_cu));
+  // persistent grids: a fixed number per compute unit when tuned, else one
+  // resident round of each kernel
+  const int per_cu = b->tune.build_grid_per_cu;
+  unsigned g_fp64 = unsigned(n_cu) * 16u, g_init = g_fp64, g_sub = g_fp64;
+  if (per_cu > 0) {
+    g_fp64 = g_init = g_sub = unsigned(n_cu) * unsigned(per_cu);
+  } else if (b->scene.chain == BBC_CHAIN_R) {
+    bbc_status e = resident_grid(k_init, 0, dev, n_cu, &g_init);
+    if (!e) e = resident_grid(k_subdiv, 1, dev, n_cu, &g_sub);
+    if (!e) e = resident_grid(k_level0_fp64, 2, dev, n_cu, &g_fp64);
+    if (e) return e;
+  }
+  const unsigned persistent = g_sub;
 
   bbc_status st = launch_fill_u32(static_cast<uint32_t*>(b->counters.p), 0u, sizeof(BuildCounters) / 4, s);
   if (st) return st;
@@ -725,7 +763,7 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   } else {
     hipLaunchKernelGGL(k_level0, dim3(g0), dim3(64), 0, s, a);
     BBC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_level0_fp64, dim3(persistent), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_level0_fp64, dim3(g_fp64), dim3(64), 0, s, a);
   }
   BBC_HIP(hipGetLastError());
   if (a.init_levels > 0) {
@@ -734,7 +772,7 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
     else if (refr)
       hipLaunchKernelGGL(k_init_t, dim3(persistent), dim3(64), 0, s, a);
     else
-      hipLaunchKernelGGL(k_init, dim3(persistent), dim3(64), 0, s, a);
+      hipLaunchKernelGGL(k_init, dim3(g_init), dim3(64), 0, s, a);
     BBC_HIP(hipGetLastError());
   }
   for (int d = 0; d <= a.max_depth; ++d) {

@@ -77,7 +77,7 @@ struct Tuning {
   int query_grid = 256 * 64;  // fused query: persistent workgroups
   int query_tile = 16;        // fused query: shading points per wave (16, 32 or 64)
   int timing = 0;             // record events around the query's dominant kernel
-  int build_grid_per_cu = 16; // subdivision: persistent workgroups per CU
+  int build_grid_per_cu = 0;  // persistent build kernels: workgroups per CU (0: one resident round)
   int newton_steps = 4;       // staged query: FP32 iterations per pooled Newton pass (0: lane per pair)
   int newton_results = 96;    // pooled Newton: accepted roots kept per 64 pairs before pairs are redone
 };

@@ -1151,9 +1151,11 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   if (ev0) BBC_HIP(hipEventRecord(ev0, st));
   if (newton_steps > 0) {
     // as many workgroups as stay resident together, striding over the
-    // batches of 64 pairs; then the rare pairs to redo
+    // batches of 64 pairs; then the rare pairs to redo (a list of at most
+    // kRedoCap, or in its overflow a strided scan of every pair): a small
+    // grid, since the launch mostly finds the list empty
     int nres = 0;
-    const unsigned gr = unsigned(std::min<size_t>((pairs + 255) / 256, 2048));
+    const unsigned gr = unsigned(std::min<size_t>((pairs + 255) / 256, 128));
     if (q.sc.chain == BBC_CHAIN_RR) {
       if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_RR>, BBC_CHAIN_RR, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));

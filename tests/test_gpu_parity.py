@@ -121,6 +121,36 @@ def test_fused_equals_staged_and_tuning_is_invisible(bbc, cfg1):
     B.set_tuning(bbc.TUNE_QUERY_TILE, 16)
 
 
+def _leaf_table(L):
+    c = np.asarray(L["code"])  # (depth, iu, iv) per leaf
+    order = np.lexsort((c[:, 2], c[:, 1], c[:, 0], np.asarray(L["tuple"])))
+    return {k: np.asarray(L[k])[order] for k in ("tuple", "code", "uk", "E")}
+
+
+def test_build_grid_knob_is_invisible(bbc, cfg1):
+    """The persistent build kernels' grid (one resident round, or a fixed
+    count per compute unit) changes neither the leaves nor the grid."""
+    sc, osc, ds, B, Ob = cfg1
+    pts = torch.as_tensor(S.random_points(sc, 1500, seed=6), device="cuda")
+    ref_L, ref_G, ref_E = None, None, None
+    for per_cu in (0, 1, 16, 0):
+        B.set_tuning(bbc.TUNE_BUILD_GRID_PER_CU, per_cu)
+        assert B.get_tuning(bbc.TUNE_BUILD_GRID_PER_CU) == per_cu
+        B.rebuild()
+        L, G = _leaf_table(B.leaves()), B.grid()
+        E, _ = B.query(pts, 8, 5)
+        if ref_L is None:
+            ref_L, ref_G, ref_E = L, G, E
+            continue
+        for k in ref_L:
+            assert np.array_equal(L[k], ref_L[k]), (per_cu, k)
+        for a, b in zip(G, ref_G):
+            assert np.array_equal(a, b), per_cu
+        assert torch.equal(E, ref_E), per_cu
+    with pytest.raises(Exception):
+        B.set_tuning(bbc.TUNE_BUILD_GRID_PER_CU, 65)
+
+
 def test_split_request_draws_what_the_whole_draws(bbc, cfg1):
     sc, osc, ds, B, Ob = cfg1
     pts = torch.as_tensor(S.random_points(sc, 2000, seed=4), device="cuda")
