@@ -388,6 +388,9 @@ static void irradiance_from(const Tuple& c, const BV& d0, const Bern& Q, const B
                             const Bern& Qu, const Bern& Qv, const Bern& Puu, const Bern& Puv, const Bern& Pvu,
                             const Bern& Pvv, BoxBound* bb);
 
+static void implicit_irradiance(const Tuple& c, const BV& d0, const BV& x1, const BV& n, double wu, double wv,
+                                BoxBound* bb);
+
 static BoxBound bound_box_rr(const Tuple& c, double u0, double u1, double v0, double v1, bool want_irr) {
   BoxBound bb;
   if (!c.front) return bb;
@@ -460,7 +463,6 @@ static BoxBound bound_box(const Tuple& c, double u0, double u1, double v0, doubl
   const BV d0 = lin3(c.p0 - c.x0, c.e1, c.e2, u0, u1, v0, v1);
   const BV s = lin3(c.p0 - c.q0, c.e1, c.e2, u0, u1, v0, v1);
   const Bern nn = dotB(n, n), dn = dotB(d0, n);
-  (void)x1;
 
   Bern Pu, Pv, Q;
   // rows of M for the irradiance bound: (Q, Pu, Pv) and their total u-, v-derivatives
@@ -543,8 +545,26 @@ static BoxBound bound_box(const Tuple& c, double u0, double u1, double v0, doubl
                vb.hi <= 1.0 && tb.kind == kDirect && tb.lo > 0.0;
   bb.live = true;
   if (!want_irr) return bb;
-  irradiance_from(c, d0, Q, Pu, Pv, Qu, Qv, Puu, Puv, Pvu, Pvv, &bb);
+  if (c.chain == 1 && (flags & 4))
+    implicit_irradiance(c, d0, x1, n, wu, wv, &bb);
+  else
+    irradiance_from(c, d0, Q, Pu, Pv, Qu, Qv, Puu, Puv, Pvu, Pvv, &bb);
   return bb;
+}
+
+// G1 = |n_g . d0| / |d0|^3 bounded factor-wise, times I0 A1 / A_k, applied to
+// a bound [rlo, rhi] of |du1/du_k|.
+static void irradiance_factor(const Tuple& c, const BV& d0, double rlo, double rhi, double* Elo, double* Ehi) {
+  double glo, ghi, hlo, hhi;
+  coef_range(dotC(d0, c.ng), &glo, &ghi);
+  coef_range(dotB(d0, d0), &hlo, &hhi);
+  const double aglo = (glo <= 0.0 && ghi >= 0.0) ? 0.0 : std::min(std::fabs(glo), std::fabs(ghi));
+  const double aghi = std::max(std::fabs(glo), std::fabs(ghi));
+  const double Glo = aglo / std::pow(hhi, 1.5);
+  const double Ghi = hlo > 0.0 ? aghi / std::pow(hlo, 1.5) : kInf;
+  const double k = c.I0 * c.a1 / c.ak;
+  *Elo = (Glo == 0.0 || rlo == 0.0) ? 0.0 : k * Glo * rlo;
+  *Ehi = (std::isinf(Ghi) || std::isinf(rhi)) ? kInf : k * Ghi * rhi;
 }
 
 // Irradiance bound [E_lo, E_hi] of a box from the receiver map u_k = (Pu/Q,
@@ -561,16 +581,59 @@ static void irradiance_from(const Tuple& c, const BV& d0, const Bern& Q, const B
   const Bern Q3 = mul(mul(Q, Q), Q);
   double rlo, rhi;
   abs_bound(ratio_bound(Q3, detM), &rlo, &rhi);
-  double glo, ghi, hlo, hhi;
-  coef_range(dotC(d0, c.ng), &glo, &ghi);
-  coef_range(dotB(d0, d0), &hlo, &hhi);
-  const double aglo = (glo <= 0.0 && ghi >= 0.0) ? 0.0 : std::min(std::fabs(glo), std::fabs(ghi));
-  const double aghi = std::max(std::fabs(glo), std::fabs(ghi));
-  const double Glo = aglo / std::pow(hhi, 1.5);
-  const double Ghi = hlo > 0.0 ? aghi / std::pow(hlo, 1.5) : kInf;
-  const double k = c.I0 * c.a1 / c.ak;
-  bb->E[0] = (Glo == 0.0 || rlo == 0.0) ? 0.0 : k * Glo * rlo;
-  bb->E[1] = (std::isinf(Ghi) || std::isinf(rhi)) ? kInf : k * Ghi * rhi;
+  irradiance_factor(c, d0, rlo, rhi, &bb->E[0], &bb->E[1]);
+}
+
+static BV crossB(const BV& a, const BV& b) {
+  return BV{sub(mul(a.y, b.z), mul(a.z, b.y)), sub(mul(a.z, b.x), mul(a.x, b.z)), sub(mul(a.x, b.y), mul(a.y, b.x))};
+}
+
+// Irradiance bound of a refraction box by implicit differentiation (Sec. 4.4,
+// "Implicit differentiation").  The refraction at x1 is written as two
+// polynomials in u1 and the receiver coordinates u_k (the multivariate
+// specular polynomials of the footnote there):
+//   F = |d0|^2 ((d1 x n).b)^2 - eta^2 |d1|^2 ((d0 x n).b)^2   (Snell's law along b),
+//   G = (d0 x n).d1                                            (coplanarity),
+// with d0 = x1 - x0, d1 = x_k - x1, n the interpolated normal and eta the
+// ratio n_incident / n_transmitted of the refraction evaluator (reading R30).
+// u1 and u_k are independent variables over the box times its position bound
+// U_k (a 4-D superset of the path manifold, axes u, v, u_k, v_k); from
+// F = G = 0, du1/du_k = -J_1^{-1} J_k with J_1 = d(F,G)/d(u1,v1) and
+// J_k = d(F,G)/d(u_k,v_k), so |det du1/du_k| = |det J_k / det J_1| and
+// E = I0 (A1/A_k) G1 |det J_k / det J_1|.  The bound is formed with b = (1,0,0)
+// and b = (0,1,0) and the two intervals intersected.
+static void implicit_irradiance(const Tuple& c, const BV& d0, const BV& x1, const BV& n, double wu, double wv,
+                                BoxBound* bb) {
+  bb->E[0] = 0.0;
+  bb->E[1] = kInf;
+  const double wk = bb->uk[1] - bb->uk[0], wl = bb->uk[3] - bb->uk[2];
+  if (!(wk > 0.0 && wl > 0.0)) return;
+  const Bern ukB = affine_axis(2, bb->uk[0], bb->uk[1]), vkB = affine_axis(3, bb->uk[2], bb->uk[3]);
+  const BV q0{Bern::constant(c.q0.x), Bern::constant(c.q0.y), Bern::constant(c.q0.z)};
+  const BV xk = addV(addV(q0, vecB(ukB, c.f1)), vecB(vkB, c.f2));
+  const BV d1 = subV(xk, x1);
+  const BV c0 = crossB(d0, n), c1 = crossB(d1, n);
+  const Bern d0d0 = dotB(d0, d0), d1d1 = dotB(d1, d1);
+  const Bern G = dotB(c0, d1);
+  const Bern Gu = scale(deriv(G, 0), 1.0 / wu), Gv = scale(deriv(G, 1), 1.0 / wv);
+  const Bern Gk = scale(deriv(G, 2), 1.0 / wk), Gl = scale(deriv(G, 3), 1.0 / wl);
+  double Elo = 0.0, Ehi = kInf;
+  for (int axis = 0; axis < 2; ++axis) {  // b = (1,0,0), then (0,1,0)
+    const Bern& a0 = axis == 0 ? c0.x : c0.y;
+    const Bern& a1 = axis == 0 ? c1.x : c1.y;
+    const Bern F = sub(mul(d0d0, mul(a1, a1)), scale(mul(d1d1, mul(a0, a0)), c.eta * c.eta));
+    const Bern Fu = scale(deriv(F, 0), 1.0 / wu), Fv = scale(deriv(F, 1), 1.0 / wv);
+    const Bern Fk = scale(deriv(F, 2), 1.0 / wk), Fl = scale(deriv(F, 3), 1.0 / wl);
+    const Bern detJ1 = sub(mul(Fu, Gv), mul(Fv, Gu));
+    const Bern detJk = sub(mul(Fk, Gl), mul(Fl, Gk));
+    double rlo, rhi, elo, ehi;
+    abs_bound(ratio_bound(detJk, detJ1), &rlo, &rhi);
+    irradiance_factor(c, d0, rlo, rhi, &elo, &ehi);
+    Elo = std::max(Elo, elo);
+    Ehi = std::min(Ehi, ehi);
+  }
+  bb->E[0] = Elo;
+  bb->E[1] = Ehi;
 }
 
 // ---------------------------------------------------------------- build
@@ -1070,9 +1133,14 @@ int orc_eval_path(const orc_scene* s, int64_t tuple, double u, double v, double*
 }
 
 int orc_box_bound(const orc_scene* s, int64_t tuple, const double* box, int want_irr, double* out) {
+  return orc_box_bound_flags(s, tuple, box, want_irr, 0, out);
+}
+
+int orc_box_bound_flags(const orc_scene* s, int64_t tuple, const double* box, int want_irr, int flags,
+                        double* out) {
   if (!s || !box || !out || tuple < 0 || tuple >= n_tuples_of(s)) return -1;
   const Tuple c = make_tuple(s, tuple);
-  const BoxBound bb = bound_box(c, box[0], box[1], box[2], box[3], want_irr != 0, 0);
+  const BoxBound bb = bound_box(c, box[0], box[1], box[2], box[3], want_irr != 0, flags);
   out[0] = bb.live ? 1.0 : 0.0;
   for (int i = 0; i < 4; ++i) out[1 + i] = bb.uk[i];
   out[5] = bb.E[0];

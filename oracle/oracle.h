@@ -42,7 +42,9 @@ typedef struct {
   int32_t init_pieces; /* domain initialisation keeps at most this many boxes */
   int32_t init_levels; /* and descends at most this many levels */
   int32_t flags;       /* bit 0: fixed depth (only the depth cap stops);
-                          bit 1: no remainder variable (ablation, T only) */
+                          bit 1: no remainder variable (ablation, T only);
+                          bit 2: refraction irradiance bound by implicit
+                          differentiation (T only) */
 } orc_params;
 
 /* Path evaluation at barycentric (u, v) of a tuple.  out[0..9] =
@@ -55,6 +57,10 @@ int orc_eval_path(const orc_scene* s, int64_t tuple, double u, double v, double*
  * out[5..6] = E_lo, E_hi (E_hi may be +inf); out[7] = 1 if the position bound
  * was universal.  want_irr = 0 skips the irradiance bound (E = [0, inf)). */
 int orc_box_bound(const orc_scene* s, int64_t tuple, const double* box, int want_irr, double* out);
+/* The same with build flags (4: the refraction irradiance bound by implicit
+ * differentiation). */
+int orc_box_bound_flags(const orc_scene* s, int64_t tuple, const double* box, int want_irr, int flags,
+                        double* out);
 
 /* Full precomputation: tuples, domain initialisation, adaptive subdivision,
  * leaves and the receiver grid. */

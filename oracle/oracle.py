@@ -65,6 +65,7 @@ def _declare(L):
     sig = {
         "orc_eval_path": (C.c_int, [vp, i64, d, d, vp]),
         "orc_box_bound": (C.c_int, [vp, i64, vp, C.c_int, vp]),
+        "orc_box_bound_flags": (C.c_int, [vp, i64, vp, C.c_int, C.c_int, vp]),
         "orc_build": (vp, [vp, vp, C.c_int]),
         "orc_free": (None, [vp]),
         "orc_n_leaves": (i64, [vp]),
@@ -157,10 +158,10 @@ def eval_path(osc, tuple_id, u, v):
                 beta=out[6], x1=out[7:10].copy())
 
 
-def box_bound(osc, tuple_id, box, want_irr=True):
+def box_bound(osc, tuple_id, box, want_irr=True, flags=0):
     b = _f64(box)
     out = np.zeros(8)
-    assert lib().orc_box_bound(osc.ref, int(tuple_id), _ptr(b), int(want_irr), _ptr(out)) == 0
+    assert lib().orc_box_bound_flags(osc.ref, int(tuple_id), _ptr(b), int(want_irr), int(flags), _ptr(out)) == 0
     return dict(live=bool(out[0]), uk=out[1:5].copy(), E=out[5:7].copy(), universal=bool(out[7]))
 
 
