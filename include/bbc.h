@@ -106,6 +106,11 @@ typedef struct {
 } bbc_subdiv_params;
 #define BBC_FLAG_FIXED_DEPTH 1  /* only the depth cap stops subdivision (parity mode) */
 #define BBC_FLAG_NO_REMAINDER 2 /* refraction without remainder variables (ablation; bounds may be invalid) */
+/* refraction: irradiance bound by implicit differentiation of the specular
+ * polynomials F (Snell's law) and G (coplanarity) over the box times its
+ * position bound (Sec. 4.4, "Implicit differentiation"), coefficients taken
+ * at face value; the other chains ignore it */
+#define BBC_FLAG_IMPLICIT_IRR 4
 
 typedef struct bbc_bounds bbc_bounds;
 

@@ -96,7 +96,7 @@ static bbc_status validate(const bbc_scene* sc, const bbc_emitters* em, const bb
   if (p->grid_res < 1 || p->grid_res > 4096) return invalid("grid_res must be in [1, 4096]");
   if (p->init_pieces < 1 || p->init_pieces > 256) return invalid("init_pieces must be in [1, 256]");
   if (p->init_levels < 0 || p->init_levels > 12) return invalid("init_levels must be in [0, 12]");
-  if (p->flags & ~(BBC_FLAG_FIXED_DEPTH | BBC_FLAG_NO_REMAINDER)) return invalid("unknown flags");
+  if (p->flags & ~(BBC_FLAG_FIXED_DEPTH | BBC_FLAG_NO_REMAINDER | BBC_FLAG_IMPLICIT_IRR)) return invalid("unknown flags");
   return BBC_OK;
 }
 

@@ -100,6 +100,95 @@ __device__ __forceinline__ T th_conv(T ta, T tb, int pairs) {
   return ta + tb + ta * tb + T(n * pairs + 2) * Eps<T>::u;
 }
 
+// ---- 4-D tensors of the implicit-differentiation bound: axes (u, v, u_k,
+// v_k), values only in scaled Bernstein form, row-major with u slowest.
+template <int D1, int D2, int D3, int D4>
+struct N4 {
+  static constexpr int n = (D1 + 1) * (D2 + 1) * (D3 + 1) * (D4 + 1);
+};
+
+// c (=|+=) sgn * a * b: a 4-D convolution, each output's valid index ranges in
+// runtime loops.
+template <int A1, int A2, int A3, int A4, int B1, int B2, int B3, int B4, bool ACC, int NT, class T>
+__device__ __forceinline__ void cv4(const T* a, const T* b, T* c, T sgn, int lane) {
+  constexpr int C2 = A2 + B2, C3 = A3 + B3, C4 = A4 + B4;
+  constexpr int N = (A1 + B1 + 1) * (C2 + 1) * (C3 + 1) * (C4 + 1);
+  for (int o = lane; o < N; o += NT) {
+    int r = o;
+    const int l = r % (C4 + 1);
+    r /= C4 + 1;
+    const int k = r % (C3 + 1);
+    r /= C3 + 1;
+    const int j = r % (C2 + 1), i = r / (C2 + 1);
+    T s = T(0);
+#pragma nounroll
+    for (int i1 = max(0, i - B1); i1 <= min(i, A1); ++i1)
+#pragma nounroll
+      for (int j1 = max(0, j - B2); j1 <= min(j, A2); ++j1)
+        for (int k1 = max(0, k - B3); k1 <= min(k, A3); ++k1)
+          for (int l1 = max(0, l - B4); l1 <= min(l, A4); ++l1)
+            s = fma(a[((i1 * (A2 + 1) + j1) * (A3 + 1) + k1) * (A4 + 1) + l1],
+                    b[(((i - i1) * (B2 + 1) + (j - j1)) * (B3 + 1) + (k - k1)) * (B4 + 1) + (l - l1)], s);
+    c[o] = ACC ? fma(sgn, s, c[o]) : sgn * s;
+  }
+}
+
+// Local derivative along axis AX: s'_t = (t + 1) s_{t+1} - (D - t) s_t.
+template <int D1, int D2, int D3, int D4, int AX, int NT, class T>
+__device__ __forceinline__ void deriv4(const T* in, T* out, int lane) {
+  constexpr int O1 = D1 - (AX == 0), O2 = D2 - (AX == 1), O3 = D3 - (AX == 2), O4 = D4 - (AX == 3);
+  constexpr int DA = AX == 0 ? D1 : (AX == 1 ? D2 : (AX == 2 ? D3 : D4));
+  for (int o = lane; o < (O1 + 1) * (O2 + 1) * (O3 + 1) * (O4 + 1); o += NT) {
+    int r = o;
+    const int l = r % (O4 + 1);
+    r /= O4 + 1;
+    const int k = r % (O3 + 1);
+    r /= O3 + 1;
+    const int j = r % (O2 + 1), i = r / (O2 + 1);
+    const int t = AX == 0 ? i : (AX == 1 ? j : (AX == 2 ? k : l));
+    auto at = [&](int ii, int jj, int kk, int ll) { return in[((ii * (D2 + 1) + jj) * (D3 + 1) + kk) * (D4 + 1) + ll]; };
+    const T hi = at(i + (AX == 0), j + (AX == 1), k + (AX == 2), l + (AX == 3));
+    out[o] = fma(T(t + 1), hi, -(T(DA - t) * at(i, j, k, l)));
+  }
+}
+
+// Elevation by R_a in {0, 1} per axis: the scaled coefficient is the sum of
+// its (up to 2^4) lower neighbours.
+template <int D1, int D2, int D3, int D4, int R1, int R2, int R3, int R4, int NT, class T>
+__device__ __forceinline__ void elev4(const T* in, T* out, int lane) {
+  constexpr int E1 = D1 + R1, E2 = D2 + R2, E3 = D3 + R3, E4 = D4 + R4;
+  for (int o = lane; o < (E1 + 1) * (E2 + 1) * (E3 + 1) * (E4 + 1); o += NT) {
+    int r = o;
+    const int l = r % (E4 + 1);
+    r /= E4 + 1;
+    const int k = r % (E3 + 1);
+    r /= E3 + 1;
+    const int j = r % (E2 + 1), i = r / (E2 + 1);
+    T s = T(0);
+    for (int a = 0; a <= R1; ++a)
+      for (int b = 0; b <= R2; ++b)
+        for (int c = 0; c <= R3; ++c)
+          for (int d = 0; d <= R4; ++d) {
+            const int ii = i - a, jj = j - b, kk = k - c, ll = l - d;
+            if (ii >= 0 && ii <= D1 && jj >= 0 && jj <= D2 && kk >= 0 && kk <= D3 && ll >= 0 && ll <= D4)
+              s += in[((ii * (D2 + 1) + jj) * (D3 + 1) + kk) * (D4 + 1) + ll];
+          }
+    out[o] = s;
+  }
+}
+
+// LDS offsets of the implicit-differentiation tensors (values only), after
+// the position part's live linear forms, d0.d0 and n_g.d0 (TLay::G).
+struct ILay {
+  static constexpr int D1 = TLay::G + 8, C0 = D1 + 48, C1 = C0 + 27, D1D1 = C1 + 108;   // (1,1,1,1)x3, (2,2,0,0)x3, (2,2,1,1)x3
+  static constexpr int GG = D1D1 + 81, GU = GG + 64, GV = GU + 48, GK = GV + 48;  // (2,2,2,2), G (3,3,1,1)
+  static constexpr int GL = GK + 32, A0SQ = GL + 32, A1SQ = A0SQ + 25, F = A1SQ + 225;
+  static constexpr int FU = F + 441, FV = FU + 378, FK = FV + 378, FL = FK + 294;  // F (6,6,2,2)
+  static constexpr int J1 = FL + 294, JK = J1 + 1296, J1E = JK + 900, JKE = J1E + 1600;
+  static constexpr int END = JKE + 1600;
+};
+static_assert(ILay::END <= TLay::IRR_TMP + TLay::TMP_IRR, "implicit tensors exceed the refraction LDS");
+
 template <class T, bool IRR, int NT>
 __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool final, int flags, LdsT<T, IRR>& L,
                              int lane) {
@@ -304,6 +393,128 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
   if constexpr (!IRR) {
     return out;
   } else {
+    if (flags & BBC_FLAG_IMPLICIT_IRR) {
+      // ---- irradiance by implicit differentiation (Sec. 4.4): F (Snell's law
+      // along b) and G (coplanarity) over the box times U_k, |du1/du_k| =
+      // |det J_k / det J_1|; coefficients taken at face value (degree
+      // (9, 9, 3, 3)); b = (1,0,0), (0,1,0), intervals intersected
+      const T wk = uhi - ulo, wl = vhi - vlo;
+      if (!(wk > T(0) && wl > T(0))) return out;
+      T* const d1 = B + ILay::D1;
+      T* const c0 = B + ILay::C0;
+      T* const c1 = B + ILay::C1;
+      T* const d1d1 = B + ILay::D1D1;
+      T* const gg = B + ILay::GG;
+      const TP<T> g = tpat(B, TLay::G, 4);
+      {
+        const T* dv[3] = {dC(0).v, dC(1).v, dC(2).v};
+        const T* dm[3] = {dC(0).m, dC(1).m, dC(2).m};
+        const T ag[3] = {G.ng.x, G.ng.y, G.ng.z};
+        combo<4, 3, false, T, NT>(dv, dm, ag, g.v, g.m, lane);
+        // d1 = x_k - x1 = -(x1 - q0) + u_k f1 + v_k f2 at the 16 corners
+        for (int o = lane; o < 48; o += NT) {
+          const int c = o / 16, r = o - 16 * c, ij = r / 4, k = (r / 2) & 1, l = r & 1;
+          const T uk = k ? uhi : ulo, vk = l ? vhi : vlo;
+          d1[o] = fma(vk, comp(G.f2, c), fma(uk, comp(G.f1, c), -sC(c).v[ij]));
+        }
+      }
+      wave_sync();
+      for (int c = 0; c < 3; ++c) {  // c0 = d0 x n, c1 = d1 x n
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        cv4<1, 1, 0, 0, 1, 1, 0, 0, false, NT>(dC(a).v, nC(b).v, c0 + 9 * c, T(1), lane);
+        cv4<1, 1, 0, 0, 1, 1, 0, 0, true, NT>(dC(b).v, nC(a).v, c0 + 9 * c, T(-1), lane);
+        cv4<1, 1, 1, 1, 1, 1, 0, 0, false, NT>(d1 + 16 * a, nC(b).v, c1 + 36 * c, T(1), lane);
+        cv4<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(d1 + 16 * b, nC(a).v, c1 + 36 * c, T(-1), lane);
+        if (c == 0)
+          cv4<1, 1, 1, 1, 1, 1, 1, 1, false, NT>(d1, d1, d1d1, T(1), lane);
+        else
+          cv4<1, 1, 1, 1, 1, 1, 1, 1, true, NT>(d1 + 16 * c, d1 + 16 * c, d1d1, T(1), lane);
+      }
+      const T th_g = th_lin + T(8) * eps;
+      wave_sync();
+      for (int c = 0; c < 3; ++c)  // G = c0 . d1
+        if (c == 0)
+          cv4<2, 2, 0, 0, 1, 1, 1, 1, false, NT>(c0, d1, gg, T(1), lane);
+        else
+          cv4<2, 2, 0, 0, 1, 1, 1, 1, true, NT>(c0 + 9 * c, d1 + 16 * c, gg, T(1), lane);
+      wave_sync();
+      T* const gu = B + ILay::GU;
+      T* const gv = B + ILay::GV;
+      T* const gk = B + ILay::GK;
+      T* const gl = B + ILay::GL;
+      deriv4<3, 3, 1, 1, 0, NT>(gg, gu, lane);
+      deriv4<3, 3, 1, 1, 1, NT>(gg, gv, lane);
+      deriv4<3, 3, 1, 1, 2, NT>(gg, gk, lane);
+      deriv4<3, 3, 1, 1, 3, NT>(gg, gl, lane);
+      T glo, ghi, hlo, hhi;
+      poly_range<1, 1, T, NT>(g.v, g.m, th_g, &glo, &ghi, lane);
+      poly_range<2, 2, T, NT>(dd.v, dd.m, th_nn, &hlo, &hhi, lane);
+      const T aglo = (glo <= T(0) && ghi >= T(0)) ? T(0) : min(fabs(glo), fabs(ghi));
+      const T aghi = max(fabs(glo), fabs(ghi));
+      const T Glo = down(aglo / (hhi * sqrt(hhi)));
+      const T Ghi = hlo > T(0) ? up(aghi / (hlo * sqrt(hlo))) : T(INFINITY);
+      const T k = G.I0 * G.a1 / G.ak;
+      const T klo = k * (T(1) - T(16) * eps), khi = k * (T(1) + T(16) * eps);
+      // local derivatives: the ratio carries (w_u w_v) / (w_uk w_vk)
+      const T wscale = (u1 - u0) * (v1 - v0) / (wk * wl);
+      T* const a0sq = B + ILay::A0SQ;
+      T* const a1sq = B + ILay::A1SQ;
+      T* const F = B + ILay::F;
+      T* const fu = B + ILay::FU;
+      T* const fv = B + ILay::FV;
+      T* const fk = B + ILay::FK;
+      T* const fl = B + ILay::FL;
+      T* const j1 = B + ILay::J1;
+      T* const jk = B + ILay::JK;
+      T* const j1e = B + ILay::J1E;
+      T* const jke = B + ILay::JKE;
+      T Elo = T(0), Ehi = T(INFINITY);
+      for (int bax = 0; bax < 2; ++bax) {  // b = (1,0,0), then (0,1,0)
+        wave_sync();
+        const T* a0 = c0 + 9 * bax;
+        const T* a1 = c1 + 36 * bax;
+        cv4<2, 2, 0, 0, 2, 2, 0, 0, false, NT>(a0, a0, a0sq, T(1), lane);
+        cv4<2, 2, 1, 1, 2, 2, 1, 1, false, NT>(a1, a1, a1sq, T(1), lane);
+        wave_sync();
+        // F = |d0|^2 a1^2 - eta^2 |d1|^2 a0^2
+        cv4<2, 2, 0, 0, 4, 4, 2, 2, false, NT>(dd.v, a1sq, F, T(1), lane);
+        cv4<2, 2, 2, 2, 4, 4, 0, 0, true, NT>(d1d1, a0sq, F, -(eta * eta), lane);
+        wave_sync();
+        deriv4<6, 6, 2, 2, 0, NT>(F, fu, lane);
+        deriv4<6, 6, 2, 2, 1, NT>(F, fv, lane);
+        deriv4<6, 6, 2, 2, 2, NT>(F, fk, lane);
+        deriv4<6, 6, 2, 2, 3, NT>(F, fl, lane);
+        wave_sync();
+        // det J_1 = F_u G_v - F_v G_u (8,8,3,3), det J_k = F_uk G_vk - F_vk G_uk (9,9,2,2)
+        cv4<5, 6, 2, 2, 3, 2, 1, 1, false, NT>(fu, gv, j1, T(1), lane);
+        cv4<6, 5, 2, 2, 2, 3, 1, 1, true, NT>(fv, gu, j1, T(-1), lane);
+        cv4<6, 6, 1, 2, 3, 3, 1, 0, false, NT>(fk, gl, jk, T(1), lane);
+        cv4<6, 6, 2, 1, 3, 3, 0, 1, true, NT>(fl, gk, jk, T(-1), lane);
+        wave_sync();
+        elev4<8, 8, 3, 3, 1, 1, 0, 0, NT>(j1, j1e, lane);
+        elev4<9, 9, 2, 2, 0, 0, 1, 1, NT>(jk, jke, lane);
+        wave_sync();
+        const RB<T> rb = ratio_bound_fn<T, NT>(
+            N4<9, 9, 3, 3>::n,
+            [&](int o, T& p, T& ep, T& q, T& eq) {
+              p = jke[o];
+              q = j1e[o];
+              ep = eq = T(0);
+            },
+            final, lane);
+        T rlo, rhi;
+        abs_bound(rb, &rlo, &rhi);
+        rlo = down(rlo * wscale);
+        rhi = isinf(rhi) ? rhi : up(rhi * wscale);
+        const T elo = (Glo <= T(0) || rlo <= T(0)) ? T(0) : down(klo * down(Glo * rlo));
+        const T ehi = (isinf(Ghi) || isinf(rhi)) ? T(INFINITY) : up(khi * up(Ghi * rhi));
+        Elo = max(Elo, elo);
+        Ehi = min(Ehi, ehi);
+      }
+      out.E[0] = out_lo(Elo);
+      out.E[1] = out_hi(Ehi);
+      return out;
+    }
     // ---- derivative linear forms, n_g.d0, and beta_u, beta_v
     const TP<T> nnu = tpat(B, TLay::NNU, 4), nnv = tpat(B, TLay::NNV, 4), ddu = tpat(B, TLay::DDU, 4),
                 ddv = tpat(B, TLay::DDV, 4), dnu = tpat(B, TLay::DNU, 4), dnv = tpat(B, TLay::DNV, 4),

@@ -9,13 +9,13 @@ def keyset(L):
     return set(zip(np.asarray(L["tuple"]).tolist(), map(tuple, np.asarray(L["code"]).tolist())))
 
 
-def check_leaf_bounds(orc, osc, L, idx, tol=BOUND_TOL, e_face_value=False):
+def check_leaf_bounds(orc, osc, L, idx, tol=BOUND_TOL, e_face_value=False, flags=0):
     """GPU leaves against the oracle's bound of the very same box: the GPU
     bound contains the oracle's and exceeds it by at most `tol`.  With
     e_face_value the irradiance bound is one taken at face value on both
     sides (no rounding control), so it only agrees to within `tol`."""
     for k in idx:
-        ob = orc.box_bound(osc, int(L["tuple"][k]), L["box"][k].astype(np.float64))
+        ob = orc.box_bound(osc, int(L["tuple"][k]), L["box"][k].astype(np.float64), flags=flags)
         assert ob["live"], k
         gu = L["uk"][k].astype(np.float64)
         ou = ob["uk"]

@@ -1,0 +1,84 @@
+"""GPU parity of the refraction chain's irradiance bound by implicit
+differentiation (Sec. 4.4; build flag BBC_FLAG_IMPLICIT_IRR) against the FP64
+oracle with the same flag: tree shape, every leaf's bound against the oracle's
+bound of the same box (the irradiance ratio is taken at face value on both
+sides, so E agrees to the bound tolerance rather than by containment), the
+grid and the estimates.  Cases as for the explicit bound: a curved refractor
+entering a denser medium, one leaving it (total internal reflection inside
+the domain), and a water surface with four lights."""
+import gpu_checks
+import numpy as np
+import pytest
+
+from paper_2504_19163_amd import scenes as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+IMPLICIT = 4
+CASES = {
+    "curved": (lambda: S.curved_triangles(8, seed=3, chain="T", eta=1 / 1.5), dict(max_depth=4, alpha=1.1)),
+    "steep": (lambda: S.curved_triangles(6, seed=5, chain="T", eta=2.0), dict(max_depth=4, alpha=1.1)),
+    "water": (lambda: S.water_surface(m=4, amp_scale=0.04), dict(max_depth=3)),
+}
+
+
+@pytest.fixture(scope="module")
+def bbc():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2504_19163_amd import bbc as B
+    B.lib()
+    return B
+
+
+@pytest.fixture(scope="module")
+def built(bbc, orc):
+    out = {}
+    for name, (make, params) in CASES.items():
+        sc = make()
+        osc = orc.OracleScene(sc)
+        p = dict(params, flags=IMPLICIT)
+        out[name] = (sc, osc, bbc.Bounds(bbc.DeviceScene(sc), p), orc.OracleBuild(osc, p))
+    return out
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_implicit_tree_and_bounds(bbc, orc, built, case):
+    sc, osc, B, Ob = built[case]
+    L, OL = B.leaves(), Ob.leaves()
+    print(case, "leaves", len(L["tuple"]), "oracle", len(OL["tuple"]), "inf", B.info()["n_inf_leaves"], flush=True)
+    assert gpu_checks.keyset(L) == gpu_checks.keyset(OL)
+    gpu_checks.check_leaf_bounds(orc, osc, L, range(len(L["tuple"])), e_face_value=True, flags=IMPLICIT)
+    info, st = B.info(), Ob.stats()
+    assert info["n_live_tuples"] == st["live_tuples"]
+    assert info["n_inf_leaves"] == st["inf_leaves"]
+
+
+def test_implicit_grid_matches_oracle(bbc, orc, built):
+    sc, osc, B, Ob = built["water"]
+    off, gt, ge = B.grid()
+    G = 512
+    rng = np.random.default_rng(4)
+    for c in rng.choice(G * G, 3000, replace=False):
+        cu, cv = divmod(int(c), G)
+        ot, oe = Ob.cell_list(cu, cv)
+        a, b = off[c], off[c + 1]
+        assert np.array_equal(gt[a:b].astype(np.int64), ot), c
+        e = ge[a:b].astype(np.float64)
+        fin = np.isfinite(oe)
+        assert np.array_equal(np.isfinite(e), fin), c
+        assert np.all(np.abs(e[fin] - oe[fin]) <= gpu_checks.BOUND_TOL * np.abs(oe[fin])), c
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_implicit_query_matches_oracle(bbc, orc, built, case):
+    sc, osc, B, Ob = built[case]
+    pts = S.receiver_points(sc, 48)
+    E, st = B.query(torch.as_tensor(pts, device="cuda"), 8, 21, mode=bbc.QUERY_STAGED, stats=True)
+    E = E.cpu().numpy().astype(np.float64)
+    st = st.cpu().numpy()
+    OE, ost = Ob.query(pts, 8, 21, mode=0)
+    assert np.array_equal(st[:, 0], ost[:, 0])
+    assert np.array_equal(st[:, 1], ost[:, 1])
+    np.testing.assert_allclose(E, OE, rtol=1e-5, atol=1e-12)
