@@ -48,8 +48,10 @@ struct Tuple {
   V3 p0, e1, e2, n0, dn1, dn2;
   V3 ng;           // unit geometric normal, oriented to agree with the vertex normals
   double a1 = 0;   // |e1 x e2| = |dx1/du1|
-  V3 x0;           // point light
+  V3 x0;           // point light, or the corner of an area light
   double I0 = 1;
+  bool area = false;  // area light x0 + z1 ea + z2 eb, (z1, z2) in [0,1]^2
+  V3 ea, eb;
   V3 q0, f1, f2;   // receiver
   double ak = 0;   // |f1 x f2| = 1 / |du_k/dx_k|
   bool front = false;  // light strictly on the front side of the triangle plane
@@ -110,6 +112,27 @@ static Tuple make_tuple(const orc_scene* s, int64_t tuple) {
   c.f2 = v3(s->f2[0], s->f2[1], s->f2[2]);
   c.ak = norm(cross(c.f1, c.f2));
   c.front = dot(c.x0 - p0, c.ng) > 0.0;
+  if (s->eedge) {
+    // an area light faces the triangle when any point of it lies strictly in
+    // front of the triangle's plane: the front side of its four corners
+    c.area = true;
+    c.ea = col(s->eedge, s->n_emit, e, 0);
+    c.eb = col(s->eedge, s->n_emit, e, 3);
+    for (int k = 1; k < 4; ++k) {
+      const V3 xc = c.x0 + double(k & 1) * c.ea + double(k >> 1) * c.eb;
+      c.front = c.front || dot(xc - p0, c.ng) > 0.0;
+    }
+  }
+  return c;
+}
+
+// The tuple as lit from the point (z1, z2) of its area light.
+static Tuple at_light_point(Tuple c, double z1, double z2) {
+  if (c.area) {
+    c.x0 = c.x0 + z1 * c.ea + z2 * c.eb;
+    c.front = dot(c.x0 - c.p0, c.ng) > 0.0;
+    c.area = false;
+  }
   return c;
 }
 
@@ -460,7 +483,14 @@ static BoxBound bound_box(const Tuple& c, double u0, double u1, double v0, doubl
   const double wu = u1 - u0, wv = v1 - v0;
   const BV x1 = lin3(c.p0, c.e1, c.e2, u0, u1, v0, v1);
   const BV n = lin3(c.n0, c.dn1, c.dn2, u0, u1, v0, v1);
-  const BV d0 = lin3(c.p0 - c.x0, c.e1, c.e2, u0, u1, v0, v1);
+  BV d0 = lin3(c.p0 - c.x0, c.e1, c.e2, u0, u1, v0, v1);
+  if (c.area) {
+    // area light: d0 = x1 - (x0 + z1 ea + z2 eb) over axes (u, v, z1, z2);
+    // the bounds below then hold for every point of the light
+    d0 = BV{add(d0.x, add(affine_axis(2, 0.0, -c.ea.x), affine_axis(3, 0.0, -c.eb.x))),
+            add(d0.y, add(affine_axis(2, 0.0, -c.ea.y), affine_axis(3, 0.0, -c.eb.y))),
+            add(d0.z, add(affine_axis(2, 0.0, -c.ea.z), affine_axis(3, 0.0, -c.eb.z)))};
+  }
   const BV s = lin3(c.p0 - c.q0, c.e1, c.e2, u0, u1, v0, v1);
   const Bern nn = dotB(n, n), dn = dotB(d0, n);
 
@@ -662,7 +692,7 @@ struct Build {
   int64_t boxes = 0;
   const orc_scene* scene = nullptr;  // borrowed
   // deep copies so the build owns its geometry
-  std::vector<double> pos, nrm, epos, eI, pos2, nrm2;
+  std::vector<double> pos, nrm, epos, eI, pos2, nrm2, eedge;
   orc_scene sc{};
 };
 
@@ -777,6 +807,10 @@ static Build* build_all(const orc_scene* s, const orc_params* p, int n_threads) 
   B->sc.nrm = B->nrm.data();
   B->sc.epos = B->epos.data();
   B->sc.eI = B->eI.data();
+  if (s->eedge) {
+    B->eedge.assign(s->eedge, s->eedge + 6 * s->n_emit);
+    B->sc.eedge = B->eedge.data();
+  }
   B->scene = &B->sc;
   if (s->chain == 2) {
     B->pos2.assign(s->pos2, s->pos2 + 9 * s->n_tri2);
@@ -1132,6 +1166,23 @@ int orc_eval_path(const orc_scene* s, int64_t tuple, double u, double v, double*
   return 0;
 }
 
+int orc_eval_path_at(const orc_scene* s, int64_t tuple, double u, double v, double z1, double z2, double* out) {
+  if (!s || !out || tuple < 0 || tuple >= n_tuples_of(s)) return -1;
+  const Tuple c = at_light_point(make_tuple(s, tuple), z1, z2);
+  const PathEval e = eval_path(c, u, v);
+  out[0] = e.uk;
+  out[1] = e.vk;
+  out[2] = e.t;
+  out[3] = e.Ek;
+  out[4] = e.detJ;
+  out[5] = e.admissible ? 1.0 : 0.0;
+  out[6] = e.beta;
+  out[7] = e.x1.x;
+  out[8] = e.x1.y;
+  out[9] = e.x1.z;
+  return 0;
+}
+
 int orc_box_bound(const orc_scene* s, int64_t tuple, const double* box, int want_irr, double* out) {
   return orc_box_bound_flags(s, tuple, box, want_irr, 0, out);
 }
@@ -1152,6 +1203,7 @@ int orc_box_bound_flags(const orc_scene* s, int64_t tuple, const double* box, in
 void* orc_build(const orc_scene* s, const orc_params* p, int n_threads) {
   if (!s || !p || s->chain < 0 || s->chain > 2 || p->grid_res < 1) return nullptr;
   if (s->chain == 2 && (!s->pos2 || !s->nrm2 || s->n_tri2 < 1)) return nullptr;
+  if (s->eedge && s->chain != 0) return nullptr;  // area lights: one reflection only
   return build_all(s, p, n_threads);
 }
 
@@ -1274,7 +1326,10 @@ int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t se
     int64_t nroots = 0;
     for (const Pick& pk : S) {
       const size_t k = pk.k;
-      const Tuple c = make_tuple(B->scene, U[k]);
+      Tuple c = make_tuple(B->scene, U[k]);
+      if (c.area)  // one light point per selected pair, from streams 3 and 4
+        c = at_light_point(c, uniform_stream(seed, uint64_t(i), uint32_t(U[k]), 3u),
+                           uniform_stream(seed, uint64_t(i), uint32_t(U[k]), 4u));
       const std::vector<RootHit> roots = brute ? brute_roots(c, us, vs, 64) : leaf_roots(*B, c, U[k], us, vs);
       double ET = 0.0;
       for (const RootHit& rh : roots) ET += rh.Ek;
@@ -1294,7 +1349,7 @@ int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t se
 
 int orc_true_irradiance(const orc_scene* s, const double* pts, int64_t n, int lattice, double* E_out,
                         int n_threads) {
-  if (!s || !pts || !E_out || n < 0 || lattice < 1) return -1;
+  if (!s || !pts || !E_out || n < 0 || lattice < 1 || s->eedge) return -1;
   const int64_t T = n_tuples_of(s);
   const Tuple ref = make_tuple(s, 0);
   parallel_for(n, n_threads, [&](int64_t i, int) {

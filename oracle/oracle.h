@@ -32,6 +32,11 @@ typedef struct {
   int64_t n_emit;
   const double* epos; /* [3][n_emit] */
   const double* eI;   /* [n_emit] intensities */
+  /* area lights (one reflection only): NULL for point lights, else [6][n_emit]
+   * edges a, b of parallelogram emitters x0 = epos + z1 a + z2 b, (z1, z2) in
+   * [0,1]^2, every point of which emits with intensity eI; the irradiance is
+   * the mean over (z1, z2) */
+  const double* eedge;
 } orc_scene;
 
 typedef struct {
@@ -50,6 +55,8 @@ typedef struct {
 /* Path evaluation at barycentric (u, v) of a tuple.  out[0..9] =
  * u_k, v_k, t, E_k, detJ, admissible (0/1), beta (T), x1.x, x1.y, x1.z */
 int orc_eval_path(const orc_scene* s, int64_t tuple, double u, double v, double* out);
+/* The same from the point (z1, z2) of an area emitter. */
+int orc_eval_path_at(const orc_scene* s, int64_t tuple, double u, double v, double z1, double z2, double* out);
 
 /* Bound of one box [u0,u1]x[v0,v1] of a tuple's barycentric domain.
  * out[0] = 1 if the box is live, 0 if it is culled;

@@ -49,7 +49,7 @@ class Scene(C.Structure):
         ("chain", C.c_int32), ("n_tri", C.c_int64), ("pos", C.c_void_p), ("nrm", C.c_void_p),
         ("n_tri2", C.c_int64), ("pos2", C.c_void_p), ("nrm2", C.c_void_p),
         ("eta", C.c_double), ("q0", C.c_double * 3), ("f1", C.c_double * 3), ("f2", C.c_double * 3),
-        ("n_emit", C.c_int64), ("epos", C.c_void_p), ("eI", C.c_void_p),
+        ("n_emit", C.c_int64), ("epos", C.c_void_p), ("eI", C.c_void_p), ("eedge", C.c_void_p),
     ]
 
 
@@ -64,6 +64,7 @@ def _declare(L):
     vp, i64, i32, d, u64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_uint64
     sig = {
         "orc_eval_path": (C.c_int, [vp, i64, d, d, vp]),
+        "orc_eval_path_at": (C.c_int, [vp, i64, d, d, d, d, vp]),
         "orc_box_bound": (C.c_int, [vp, i64, vp, C.c_int, vp]),
         "orc_box_bound_flags": (C.c_int, [vp, i64, vp, C.c_int, C.c_int, vp]),
         "orc_build": (vp, [vp, vp, C.c_int]),
@@ -115,6 +116,7 @@ class OracleScene:
         self.nrm = _f64(scene["nrm"])
         self.epos = _f64(scene["epos"])
         self.eI = _f64(scene["eI"])
+        self.eedge = _f64(scene["eedge"]) if scene.get("eedge") is not None else None
         self.pos2 = _f64(scene["pos2"]) if "pos2" in scene else None
         self.nrm2 = _f64(scene["nrm2"]) if "nrm2" in scene else None
         s = Scene()
@@ -131,6 +133,7 @@ class OracleScene:
         s.n_emit = self.eI.shape[0]
         s.epos = _ptr(self.epos)
         s.eI = _ptr(self.eI)
+        s.eedge = _ptr(self.eedge)
         self.c = s
         self.n_tuples = s.n_tri * s.n_emit * (s.n_tri2 if s.chain == 2 else 1)
 
@@ -151,9 +154,15 @@ def _params(p):
     return q
 
 
-def eval_path(osc, tuple_id, u, v):
+def eval_path(osc, tuple_id, u, v, z=None):
+    """Path through barycentric (u, v) of a tuple; for an area light, from its
+    point z = (z1, z2)."""
     out = np.zeros(10)
-    assert lib().orc_eval_path(osc.ref, int(tuple_id), float(u), float(v), _ptr(out)) == 0
+    if z is None:
+        assert lib().orc_eval_path(osc.ref, int(tuple_id), float(u), float(v), _ptr(out)) == 0
+    else:
+        assert lib().orc_eval_path_at(osc.ref, int(tuple_id), float(u), float(v), float(z[0]), float(z[1]),
+                                      _ptr(out)) == 0
     return dict(uk=out[0], vk=out[1], t=out[2], Ek=out[3], detJ=out[4], admissible=bool(out[5]),
                 beta=out[6], x1=out[7:10].copy())
 

@@ -309,6 +309,20 @@ def flat_mirror(light=(0.1, 0.2, 2.0), receiver_z=1.0, half=3.0):
                   [-half, -half, receiver_z], [2 * half, 0, 0], [0, 2 * half, 0], name="flat_mirror")
 
 
+def area_light(scene, a, b):
+    """The scene with each point light replaced by a parallelogram light
+    centred on it: corner epos - a/2 - b/2, edges a and b (the same for every
+    emitter), stored as eedge [6][n_emit]."""
+    s = dict(scene)
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    n = scene["epos"].shape[1]
+    s["epos"] = _f32(scene["epos"].astype(np.float64) - 0.5 * (a + b)[:, None])
+    s["eedge"] = _f32(np.concatenate([np.repeat(a[:, None], n, 1), np.repeat(b[:, None], n, 1)]))
+    s["name"] = scene.get("name", "") + "_area"
+    return s
+
+
 def curved_triangles(n=4, seed=7, chain="R", eta=1.0, receiver_z=None):
     """n triangles in a row with seeded tilted vertex normals (a curved
     reflector or refractor).  Light above; receiver above (R) or below (T)."""
