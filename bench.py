@@ -192,6 +192,48 @@ def refraction_section(bbc, S, torch, n_side=1024, steps=3, flags=0):
             "device_bytes": info["device_bytes"], "pairs": qs["n_pairs"], "roots": qs["n_roots"]}
 
 
+def area_light_section(bbc, S, torch, steps=3):
+    """Single reflection off a 65 x 65-vertex heightfield (8192 triangles) lit
+    by a 0.4 x 0.4 area light centred where the point light sits, depth cap 3
+    (a box's receiver footprint cannot shrink below the light's image, so
+    subdivision runs to the cap), 512 x 512 receiver points, 64 samples per
+    point (one light point per selected pair): build and query timed
+    separately (inputs resident in device memory)."""
+    dev = torch.device("cuda:0")
+    sc = S.area_light(S.heightfield_mirror(64), [0.4, 0.0, 0.0], [0.0, 0.4, 0.0])
+    params = dict(max_depth=3, sigma=1e-4, alpha=2.0, grid_res=512)
+    t0 = time.perf_counter()
+    B = bbc.Bounds(bbc.DeviceScene(sc), params)
+    torch.cuda.synchronize()
+    first_build = time.perf_counter() - t0
+    pts = torch.as_tensor(S.receiver_points(sc, 512), device=dev)
+    B.query(pts, 64, 0, mode=bbc.QUERY_STAGED)
+    torch.cuda.synchronize()
+    tb, tq = [], []
+    for k in range(steps):
+        t = time.perf_counter()
+        B.rebuild()
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        B.query(pts, 64, 1 + k, mode=bbc.QUERY_STAGED)
+        torch.cuda.synchronize()
+        tq.append(time.perf_counter() - t)
+    _, _, qs = B.query(pts, 64, 1, mode=bbc.QUERY_STAGED, host_stats=True)
+    info = B.info()
+    B.free()
+    n = pts.shape[1]
+    b, q = float(np.median(tb)), float(np.median(tq))
+    return {"workload": "single reflection, heightfield 8192 triangles, 0.4 x 0.4 area light, depth cap 3, "
+                        "512x512 receiver points, 64 samples/point",
+            "queries_s_whole_step": round(n / (b + q), 1), "build_ms": round(1e3 * b, 2),
+            "query_ms": round(1e3 * q, 2), "query_only_queries_s": round(n / q, 1),
+            "first_build_ms": round(1e3 * first_build, 1),
+            "live_tuples": info["n_live_tuples"], "boxes": info["n_boxes"], "leaves": info["n_leaves"],
+            "inf_leaves": info["n_inf_leaves"], "grid_entries": info["n_grid_entries"],
+            "pairs": qs["n_pairs"], "roots": qs["n_roots"]}
+
+
 def two_reflection_section(bbc, S, torch, steps=2):
     """Two reflections between two facing rippled walls (8192 triangles each,
     67,108,864 candidate pairs), depth cap 2, alpha 10, 256 x 256 floor points,
@@ -338,6 +380,7 @@ def main():
     ap.add_argument("--no-refraction", action="store_true")
     ap.add_argument("--no-two-reflections", action="store_true")
     ap.add_argument("--no-samplers", action="store_true")
+    ap.add_argument("--no-area-light", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device tensor copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -443,6 +486,8 @@ def main():
         out["refraction_implicit"] = refraction_section(bbc, S, torch, steps=2, flags=bbc.FLAG_IMPLICIT_IRR)
     if not args.no_two_reflections:
         out["two_reflections"] = two_reflection_section(bbc, S, torch)
+    if not args.no_area_light:
+        out["area_light"] = area_light_section(bbc, S, torch)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

@@ -85,12 +85,19 @@ typedef struct {
   float q0[3], f1[3], f2[3];
 } bbc_scene;
 
-/* Point emitters: pos [3][n], intensity I0 [n] (Sec. 4.4). */
+/* Emitters: pos [3][n], intensity I0 [n] (Sec. 4.4).  Point lights when edges
+ * is NULL.  Otherwise area lights (the emitter variable of the implementation
+ * section's area-light remark; single reflection only, EINVAL for the other
+ * chains): edges [6][n] holds a and b of the parallelogram
+ * pos + z1 a + z2 b, (z1, z2) in [0,1]^2, every point of which emits with
+ * intensity I0; the irradiance is the mean over (z1, z2).  Bounds hold for
+ * the whole light; a query draws one light point per selected pair. */
 typedef struct {
-  int32_t memory; /* BBC_MEM_* for pos and I0 */
+  int32_t memory; /* BBC_MEM_* for pos, I0 and edges */
   int64_t n;
   const float* pos;
   const float* I0;
+  const float* edges; /* nullable */
 } bbc_emitters;
 
 /* Subdivision controls (Sec. 6.1).  Defaults: max_depth 8, sigma 1e-4,

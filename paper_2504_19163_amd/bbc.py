@@ -47,7 +47,8 @@ class Scene(C.Structure):
 
 
 class Emitters(C.Structure):
-    _fields_ = [("memory", C.c_int32), ("n", C.c_int64), ("pos", C.c_void_p), ("I0", C.c_void_p)]
+    _fields_ = [("memory", C.c_int32), ("n", C.c_int64), ("pos", C.c_void_p), ("I0", C.c_void_p),
+                ("edges", C.c_void_p)]
 
 
 class SubdivParams(C.Structure):
@@ -193,6 +194,9 @@ class DeviceScene:
         e.n = self.eI.shape[0]
         e.pos = self.epos.data_ptr()
         e.I0 = self.eI.data_ptr()
+        if scene.get("eedge") is not None:  # area lights
+            self.eedge = t(scene["eedge"])
+            e.edges = self.eedge.data_ptr()
         self.c_scene = s
         self.c_emit = e
         self.n_tuples = s.n_tri * e.n * (s.n_tri2 if s.n_tri2 else 1)

@@ -53,7 +53,7 @@ void release(DevBuf& b) {
 }
 
 static void release_all(Bounds* b) {
-  DevBuf* all[] = {&b->pos, &b->nrm, &b->epos, &b->eI, &b->counters, &b->root, &b->init_q, &b->l0f_q, &b->q[0],
+  DevBuf* all[] = {&b->pos, &b->nrm, &b->epos, &b->eI, &b->eedge, &b->counters, &b->root, &b->init_q, &b->l0f_q, &b->q[0],
                    &b->q[1], &b->fq, &b->lt, &b->lc, &b->lu, &b->le, &b->gl_t, &b->gl_c, &b->gl_u, &b->gl_e, &b->st, &b->sc, &b->su, &b->se, &b->tcount,
                    &b->toff, &b->tcur, &b->lrect, &b->lcoarse, &b->ccount, &b->coff, &b->gt, &b->ge,
                    &b->scan_tmp, &b->trec, &b->pos2, &b->nrm2, &b->box2, &b->rowcount, &b->rowoff, &b->tid,
@@ -84,6 +84,7 @@ static bbc_status validate(const bbc_scene* sc, const bbc_emitters* em, const bb
   if (sc->n_tri < 1 || !sc->pos || !sc->nrm) return invalid("scene needs n_tri >= 1 and pos/nrm arrays");
   if (em->n < 1 || !em->pos || !em->I0) return invalid("emitters need n >= 1 and pos/I0 arrays");
   if (double(sc->n_tri) * double(em->n) > 4294967000.0) return invalid("more than 2^32 tuples");
+  if (em->edges && sc->chain != BBC_CHAIN_R) return invalid("area lights (edges) need the single-reflection chain");
   const double f1[3] = {sc->f1[0], sc->f1[1], sc->f1[2]}, f2[3] = {sc->f2[0], sc->f2[1], sc->f2[2]};
   const double c[3] = {f1[1] * f2[2] - f1[2] * f2[1], f1[2] * f2[0] - f1[0] * f2[2], f1[0] * f2[1] - f1[1] * f2[0]};
   const double ak = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
@@ -172,6 +173,7 @@ static bbc_status load_scene(Bounds* b, const bbc_scene* sc, const bbc_emitters*
   if ((e = copy_in(b->nrm, sc->nrm, nt * 9 * 4, sc->memory, b, s))) return e;
   if ((e = copy_in(b->epos, em->pos, size_t(em->n) * 3 * 4, em->memory, b, s))) return e;
   if ((e = copy_in(b->eI, em->I0, size_t(em->n) * 4, em->memory, b, s))) return e;
+  if (em->edges && (e = copy_in(b->eedge, em->edges, size_t(em->n) * 6 * 4, em->memory, b, s))) return e;
   if (sc->chain == BBC_CHAIN_RR) {
     const size_t n2 = size_t(sc->n_tri2);
     if ((e = copy_in(b->pos2, sc->pos2, n2 * 9 * 4, sc->memory, b, s))) return e;
@@ -186,6 +188,7 @@ static bbc_status load_scene(Bounds* b, const bbc_scene* sc, const bbc_emitters*
   d.n_emit = em->n;
   d.epos = static_cast<const float*>(b->epos.p);
   d.eI = static_cast<const float*>(b->eI.p);
+  d.eedge = em->edges ? static_cast<const float*>(b->eedge.p) : nullptr;
   d.eta = sc->chain == BBC_CHAIN_T ? sc->eta : 1.f;
   for (int k = 0; k < 3; ++k) {
     d.q0[k] = sc->q0[k];

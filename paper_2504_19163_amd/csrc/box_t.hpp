@@ -152,8 +152,8 @@ __device__ __forceinline__ void deriv4(const T* in, T* out, int lane) {
   }
 }
 
-// Elevation by R_a in {0, 1} per axis: the scaled coefficient is the sum of
-// its (up to 2^4) lower neighbours.
+// Elevation by (R1, R2, R3, R4): the product with the constant 1 at that
+// degree, whose scaled coefficients are C(R1,a) C(R2,b) C(R3,c) C(R4,d).
 template <int D1, int D2, int D3, int D4, int R1, int R2, int R3, int R4, int NT, class T>
 __device__ __forceinline__ void elev4(const T* in, T* out, int lane) {
   constexpr int E1 = D1 + R1, E2 = D2 + R2, E3 = D3 + R3, E4 = D4 + R4;
@@ -171,7 +171,8 @@ __device__ __forceinline__ void elev4(const T* in, T* out, int lane) {
           for (int d = 0; d <= R4; ++d) {
             const int ii = i - a, jj = j - b, kk = k - c, ll = l - d;
             if (ii >= 0 && ii <= D1 && jj >= 0 && jj <= D2 && kk >= 0 && kk <= D3 && ll >= 0 && ll <= D4)
-              s += in[((ii * (D2 + 1) + jj) * (D3 + 1) + kk) * (D4 + 1) + ll];
+              s = fma(T(binom_i(R1, a) * binom_i(R2, b) * binom_i(R3, c) * binom_i(R4, d)),
+                      in[((ii * (D2 + 1) + jj) * (D3 + 1) + kk) * (D4 + 1) + ll], s);
           }
     out[o] = s;
   }

@@ -19,6 +19,7 @@
 #include <atomic>
 
 #include "box_r.hpp"
+#include "box_ra.hpp"
 #include "box_rr.hpp"
 #include "box_t.hpp"
 #include "internal.hpp"
@@ -186,6 +187,17 @@ __global__ void __launch_bounds__(64) k_level0_t(BuildArgs a) {
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
     return eval_box_t<double, false, BBC_WAVE>(G, u0, u1, v0, v1, true, a.flags, L, lane);
+  };
+  level0_loop<double>(a, ev, lane, S, uint32_t(a.n_tuples), [](uint32_t i) { return i; });
+}
+
+// Area lights (single reflection): every box over the whole light, in FP64.
+__global__ void __launch_bounds__(64) k_level0_ra(BuildArgs a) {
+  __shared__ LdsRA<double, false> L;
+  __shared__ Stage S;
+  const int lane = threadIdx.x;
+  auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
+    return eval_box_ra<double, false, BBC_WAVE>(G, u0, u1, v0, v1, L, lane);
   };
   level0_loop<double>(a, ev, lane, S, uint32_t(a.n_tuples), [](uint32_t i) { return i; });
 }
@@ -560,6 +572,26 @@ __global__ void __launch_bounds__(64) k_init_rr(BuildArgs a) {
   stage_flush<BBC_WAVE>(a, 0, S, lane);
 }
 
+__global__ void __launch_bounds__(64) k_init_ra(BuildArgs a) {
+  __shared__ LdsRA<double, false> L;
+  __shared__ InitBox cur[kInitCap], nxt[kInitCap];
+  __shared__ Stage S;
+  const int lane = threadIdx.x;
+  const uint32_t n = a.C->n_init;
+  stage_reset(S, lane);
+  wave_sync();
+  for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const uint32_t t = a.init_q[it];
+    const TupleGeom<double> Gd = tuple_geom<double>(a.sc, t);
+    auto ev = [&](int cl, uint32_t cu, uint32_t cv) {
+      const double wd = ldexp(1.0, -cl);
+      return eval_box_ra<double, false, BBC_WAVE>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, L, lane);
+    };
+    init_one(a, t, ev, cur, nxt, lane, S);
+  }
+  stage_flush<BBC_WAVE>(a, 0, S, lane);
+}
+
 __global__ void __launch_bounds__(64) k_init_t(BuildArgs a) {
   __shared__ LdsT<double, false> L;
   __shared__ InitBox cur[kInitCap], nxt[kInitCap];
@@ -667,6 +699,19 @@ __global__ void __launch_bounds__(kSubdivRRThreads) k_subdiv_rr(BuildArgs a, int
   subdiv_loop<kSubdivRRThreads>(a, depth, ev, lane, S);
 }
 
+// An area-light reflection box (four axes, det M of degree (10,10,3,3)) takes
+// ~70 KB of LDS: four waves share it.
+constexpr int kSubdivRAThreads = 256;
+__global__ void __launch_bounds__(kSubdivRAThreads) k_subdiv_ra(BuildArgs a, int depth) {
+  __shared__ LdsRA<double, true> L;
+  __shared__ Stage S;
+  const int lane = threadIdx.x;
+  auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
+    return eval_box_ra<double, true, kSubdivRAThreads>(G, u0, u1, v0, v1, L, lane);
+  };
+  subdiv_loop<kSubdivRAThreads>(a, depth, ev, lane, S);
+}
+
 // A refraction box takes ~1.5 Mflop of FP64 over ~90 KB of LDS: four waves
 // share one box so that all four SIMDs of the compute unit work on it.
 constexpr int kSubdivTThreads = 256;
@@ -742,7 +787,7 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   unsigned g_fp64 = unsigned(n_cu) * 16u, g_init = g_fp64, g_sub = g_fp64;
   if (per_cu > 0) {
     g_fp64 = g_init = g_sub = unsigned(n_cu) * unsigned(per_cu);
-  } else if (b->scene.chain == BBC_CHAIN_R) {
+  } else if (b->scene.chain == BBC_CHAIN_R && !b->scene.eedge) {
     bbc_status e = resident_grid(k_init, 0, dev, n_cu, &g_init);
     if (!e) e = resident_grid(k_subdiv, 1, dev, n_cu, &g_sub);
     if (!e) e = resident_grid(k_level0_fp64, 2, dev, n_cu, &g_fp64);
@@ -756,7 +801,10 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   a.qout = static_cast<QItem*>(b->q[0].p);
   const unsigned g0 = unsigned(std::max<int64_t>(1, std::min<int64_t>(b->n_tuples, int64_t(n_cu) * 64)));
   const bool refr = b->scene.chain == BBC_CHAIN_T, rr = b->scene.chain == BBC_CHAIN_RR;
-  if (rr) {
+  const bool area = b->scene.eedge != nullptr;
+  if (area) {
+    hipLaunchKernelGGL(k_level0_ra, dim3(g0), dim3(64), 0, s, a);
+  } else if (rr) {
     hipLaunchKernelGGL(k_level0_rr, dim3(g0), dim3(64), 0, s, a);
   } else if (refr) {
     hipLaunchKernelGGL(k_level0_t, dim3(g0), dim3(64), 0, s, a);
@@ -767,7 +815,9 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   }
   BBC_HIP(hipGetLastError());
   if (a.init_levels > 0) {
-    if (rr)
+    if (area)
+      hipLaunchKernelGGL(k_init_ra, dim3(persistent), dim3(64), 0, s, a);
+    else if (rr)
       hipLaunchKernelGGL(k_init_rr, dim3(persistent), dim3(64), 0, s, a);
     else if (refr)
       hipLaunchKernelGGL(k_init_t, dim3(persistent), dim3(64), 0, s, a);
@@ -778,7 +828,9 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   for (int d = 0; d <= a.max_depth; ++d) {
     a.qin = static_cast<QItem*>(b->q[d & 1].p);
     a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
-    if (rr)
+    if (area)
+      hipLaunchKernelGGL(k_subdiv_ra, dim3(unsigned(n_cu) * 2u), dim3(kSubdivRAThreads), 0, s, a, d);
+    else if (rr)
       hipLaunchKernelGGL(k_subdiv_rr, dim3(unsigned(n_cu)), dim3(kSubdivRRThreads), 0, s, a, d);
     else if (refr)
       hipLaunchKernelGGL(k_subdiv_t, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTThreads), 0, s, a, d);

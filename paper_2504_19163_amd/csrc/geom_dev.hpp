@@ -47,6 +47,7 @@ struct DevScene {
   int64_t n_emit;
   const float* epos;  // [3][n_emit]
   const float* eI;    // [n_emit]
+  const float* eedge; // [6][n_emit] edges a, b of area lights, or null (point lights)
   float eta;
   float q0[3], f1[3], f2[3];
   // two reflections: the second surface, and the candidate pairs that survived
@@ -65,6 +66,9 @@ struct TupleGeom {
   V3<T> p0, e1, e2, n0, dn1, dn2, x0, q0, f1, f2, ng;
   T I0, a1, ak, eta;
   bool front;  // light strictly in front of the triangle plane (n_g oriented with the vertex normals)
+  // area light x0 + z1 ea + z2 eb, (z1, z2) in [0,1]^2 (front: any point of it)
+  bool area;
+  V3<T> ea, eb;
   // two reflections: x2 = p0b + u2 e1b + v2 e2b, n2 likewise, ngb oriented like ng
   V3<T> p0b, e1b, e2b, n0b, dn1b, dn2b, ngb;
 };
@@ -121,6 +125,14 @@ __device__ TupleGeom<T> tuple_geom_first(const DevScene& s, int64_t t, int64_t e
   g.ak = sqrt(dot(fk, fk));
   g.eta = T(s.eta);
   g.front = dot(g.x0 - p0, g.ng) > T(0);
+  g.area = s.eedge != nullptr;
+  if (g.area) {
+    const int64_t ne = s.n_emit;
+    g.ea = mk(T(s.eedge[e]), T(s.eedge[ne + e]), T(s.eedge[2 * ne + e]));
+    g.eb = mk(T(s.eedge[3 * ne + e]), T(s.eedge[4 * ne + e]), T(s.eedge[5 * ne + e]));
+    for (int k = 1; k < 4; ++k)
+      g.front = g.front || dot(g.x0 + T(k & 1) * g.ea + T(k >> 1) * g.eb - p0, g.ng) > T(0);
+  }
   return g;
 }
 
@@ -176,6 +188,7 @@ __device__ __forceinline__ TupleGeom<T> tuple_geom_rec(const float* rec, const D
   g.ak = sqrt(dot(fk, fk));
   g.eta = T(s.eta);
   g.front = dot(g.x0 - p0, g.ng) > T(0);
+  g.area = false;  // a query record carries the pair's light point in x0
   if constexpr (RR)
     second_triangle<T>(g, mk(T(rec[28]), T(rec[29]), T(rec[30])), mk(T(rec[31]), T(rec[32]), T(rec[33])),
                        mk(T(rec[34]), T(rec[35]), T(rec[36])), mk(T(rec[37]), T(rec[38]), T(rec[39])),

@@ -92,7 +92,7 @@ struct Bounds {
   int64_t tuples_cap = 0;
   int rec_floats = kRecFloats;
   // scene copies
-  DevBuf pos, nrm, epos, eI, pos2, nrm2;
+  DevBuf pos, nrm, epos, eI, pos2, nrm2, eedge;
   // tuple construction (two reflections): second-surface boxes, per-row counts
   // and offsets, pair numbers
   DevBuf box2, rowcount, rowoff, tid;

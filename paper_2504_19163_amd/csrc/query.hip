@@ -84,6 +84,7 @@ struct Target {
   float u, v;
   double ud, vd;
   uint32_t cell;
+  int64_t pt;  // shading point index (its sampling parameters and light points)
 };
 
 // Receiver texture coordinates of a shading point (least squares on the
@@ -106,6 +107,7 @@ __device__ __forceinline__ Target receiver_target(const QueryArgs& a, int64_t i)
   const int cu = min(a.G - 1, max(0, int(floor(t.ud * a.G))));
   const int cv = min(a.G - 1, max(0, int(floor(t.vd * a.G))));
   t.cell = uint32_t(cu) * uint32_t(a.G) + uint32_t(cv);
+  t.pt = i;
   return t;
 }
 
@@ -275,6 +277,22 @@ struct RootSum {
 // (deterministic initialisation, Sec. 6.1): FP32 iterations that abandon a
 // start leaving its box by more than one width, then the FP64 polish.  One
 // thread does all of T's starts.
+// The light point of a selected pair: for an area light x0 + z1 a + z2 b
+// with (z1, z2) from Philox streams 3 and 4 of (seed, point, tuple), written
+// over x0 in the pair's copy of the tuple record.  Area lights come with the
+// single reflection only, whose tuple is emitter * n_tri + triangle.
+__device__ __forceinline__ void pair_light_point(const QueryArgs& a, float* rec, int64_t i, uint32_t T) {
+  if (!a.sc.eedge) return;
+  const PointReq pr = point_req(a, i);
+  const uint32_t tk = tuple_key(a, T);
+  const double z1 = sample_stream(pr.seed, pr.key, tk, 3u), z2 = sample_stream(pr.seed, pr.key, tk, 4u);
+  const int64_t e = int64_t(T) / a.sc.n_tri, ne = a.sc.n_emit;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    rec[18 + c] = float(double(rec[18 + c]) + z1 * double(a.sc.eedge[c * ne + e]) +
+                        z2 * double(a.sc.eedge[(3 + c) * ne + e]));
+}
+
 template <int CH>
 __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target& tg, WorkCount& wc) {
   constexpr bool RR = CH == BBC_CHAIN_RR;
@@ -291,6 +309,7 @@ __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target&
   }
   const uint32_t lb = __float_as_uint(rec[22]), le = __float_as_uint(rec[23]);
   if (lb == le) return 0.0;
+  if constexpr (!RR) pair_light_point(a, rec, tg.pt, T);
   const TupleGeom<float> Gf = tuple_geom_rec<float, RR>(rec, a.sc);
   RootSum rs;
   for (uint32_t k = lb; k < le; ++k) {
@@ -393,6 +412,7 @@ __global__ void __launch_bounds__(64, kWaves) k_query_fused(QueryArgs a) {
         t2.vd = s_vd[pt];
         t2.u = float(t2.ud);
         t2.v = float(t2.vd);
+        t2.pt = tile * kTile + pt;
         const uint32_t r0 = wc.roots;
         ++wc.pairs;
         s_c[k] = tuple_irradiance<CH>(a, s_t[k], t2, wc) / double(s_p[k]);
@@ -762,13 +782,14 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
     if (uint64_t(batch) * BBC_WAVE >= np) break;
     const uint32_t k = batch * uint32_t(BBC_WAVE) + uint32_t(lane);
     const bool valid = k < np;
-    const uint32_t T = nT, cnt = valid ? nCnt : 0u;
+    const uint32_t T = nT, Pt = nPt, cnt = valid ? nCnt : 0u;
     Target tg{};
     tg.ud = nTgt.x;
     tg.vd = nTgt.y;
     tg.u = float(nTgt.x);
     tg.v = float(nTgt.y);
     tg.on = true;
+    tg.pt = Pt;
     L.redo[lane] = 0u;
     // the rest of the record (the root box is already here) stays in
     // registers until the first refill is under way
@@ -807,6 +828,7 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
           R[4 * q + 2] = rq[q].z;
           R[4 * q + 3] = rq[q].w;
         }
+        if constexpr (!RR) pair_light_point(a, R, Pt, T);
       }
       fetch_rest(batch + stride);
       stored = true;
@@ -1024,6 +1046,7 @@ __global__ void k_stage_redo(StagedArgs s, const uint32_t* total, const uint32_t
     tg.u = float(t2.x);
     tg.v = float(t2.y);
     tg.on = true;
+    tg.pt = s.pair_pt[k];
     WorkCount w2;
     s.pair_c[k] = tuple_irradiance<CH>(a, s.pair_t[k], tg, w2) / double(s.pair_p[k]);
     if (a.stats) s.pair_nr[k] = uint8_t(min(w2.roots, 255u));
