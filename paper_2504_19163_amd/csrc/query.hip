@@ -738,7 +738,10 @@ struct NewtonPool {
   uint32_t rk[kRes], rp[kRes];
 };
 
-template <int CH>
+// AREA: the scene's emitters are area lights, and each pair's record copy
+// takes its own light point (a separate instantiation, so that the point-light
+// kernel carries none of that code).
+template <int CH, bool AREA = false>
 __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
                                                           int steps, uint32_t res_cap) {
   constexpr bool RR = CH == BBC_CHAIN_RR;
@@ -828,7 +831,7 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
           R[4 * q + 2] = rq[q].z;
           R[4 * q + 3] = rq[q].w;
         }
-        if constexpr (!RR) pair_light_point(a, R, Pt, T);
+        if constexpr (AREA) pair_light_point(a, R, Pt, T);
       }
       fetch_rest(batch + stride);
       stored = true;
@@ -1126,10 +1129,10 @@ void staged_carve(void* base, int64_t n, size_t pairs, StagedWork& w) {
 // LDS and registers allow a few per compute unit), cached per device and chain.
 template <typename K>
 static bbc_status pool_grid(K kernel, int chain, int* out) {
-  static std::atomic<int> cache[64][3];
+  static std::atomic<int> cache[64][4];  // the three chains, then the area-light reflection
   int dev = 0;
   BBC_HIP(hipGetDevice(&dev));
-  if (dev < 64 && chain >= 0 && chain < 3 && cache[dev][chain].load() > 0) {
+  if (dev < 64 && chain >= 0 && chain < 4 && cache[dev][chain].load() > 0) {
     *out = cache[dev][chain].load();
     return BBC_OK;
   }
@@ -1137,7 +1140,7 @@ static bbc_status pool_grid(K kernel, int chain, int* out) {
   BBC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), 64, 0));
   BBC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   *out = std::max(1, per_cu) * std::max(1, n_cu);
-  if (dev < 64 && chain >= 0 && chain < 3) cache[dev][chain].store(*out);
+  if (dev < 64 && chain >= 0 && chain < 4) cache[dev][chain].store(*out);
   return BBC_OK;
 }
 
@@ -1193,6 +1196,13 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
                          newton_steps, res_cap);
       if (ev1) BBC_HIP(hipEventRecord(ev1, st));
       hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_T>, dim3(gr), dim3(256), 0, st, s, s.off + n, s.off + n + 1);
+    } else if (q.sc.eedge) {
+      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_R, true>, 3, &nres))) return e;
+      const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
+      hipLaunchKernelGGL((k_stage_newton_pool<BBC_CHAIN_R, true>), dim3(gq), dim3(64), 0, st, s, s.off + n,
+                         s.off + n + 1, newton_steps, res_cap);
+      if (ev1) BBC_HIP(hipEventRecord(ev1, st));
+      hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_R>, dim3(gr), dim3(256), 0, st, s, s.off + n, s.off + n + 1);
     } else {
       if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_R>, BBC_CHAIN_R, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
