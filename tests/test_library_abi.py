@@ -79,3 +79,38 @@ def test_bad_parameters_are_rejected(L):
     assert L.bbc_build_bounds(C.byref(s), C.byref(e), C.byref(p), None, C.byref(h)) == bbc.EINVAL
     s.chain = 7  # no such chain
     assert L.bbc_build_bounds(C.byref(s), C.byref(e), C.byref(p), None, C.byref(h)) == bbc.EINVAL
+    s.chain = 1  # area lights are for the single reflection only
+    edges = np.zeros((6, 1), np.float32)
+    e.edges = edges.ctypes.data
+    assert L.bbc_build_bounds(C.byref(s), C.byref(e), C.byref(p), None, C.byref(h)) == bbc.EINVAL
+    assert "area lights" in bbc.last_error()
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """The binding's ctypes structures have the header's sizes and field
+    offsets (compiled with the system C compiler against include/bbc.h)."""
+    import shutil
+    import subprocess
+    from paper_2504_19163_amd import bbc
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"bbc_scene": bbc.Scene, "bbc_emitters": bbc.Emitters, "bbc_subdiv_params": bbc.SubdivParams}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-o", str(exe), str(src)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
