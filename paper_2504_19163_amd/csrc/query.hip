@@ -687,6 +687,58 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
   }
 }
 
+// Count and fill for the samplers whose decisions are independent per
+// candidate (bound-optimal, exhaustive, uniform): a group of GL = 16 lanes per
+// point, four points per wave (a cell list holds ~16 candidates), the
+// candidates of a point in list order in chunks of GL, so the pairs come out
+// in the same order as from the one-wave-per-point kernels above.
+constexpr int kSelLanes = 16;
+template <bool FILL>
+__global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* sel) {
+  constexpr int GL = kSelLanes, NG = BBC_WAVE / GL;
+  const QueryArgs& a = s.q;
+  const int lane = threadIdx.x, g = lane / GL, gl = lane % GL;
+  const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
+  const bool uniform = (a.mode & BBC_QUERY_SAMPLERS) == BBC_QUERY_UNIFORM;
+  for (int64_t i0 = int64_t(blockIdx.x) * NG; i0 < a.n; i0 += int64_t(gridDim.x) * NG) {
+    const int64_t i = i0 + g;
+    const bool valid = i < a.n;
+    const uint32_t b = valid ? s.cell_b[i] : 0u, nU = valid ? s.cnt[i] : 0u;
+    const float gamma = valid ? s.gamma[i] : 0.f;
+    const PointReq pr = point_req(a, valid ? i : i0);
+    const float Pu = fminf(pr.W, float(nU)) / float(nU);
+    uint32_t o = FILL && valid ? s.off[i] : 0u, c = 0;
+    for (uint32_t j0 = 0; j0 < nU; j0 += GL) {  // the group's lanes run the same trip count
+      const uint32_t j = j0 + gl;
+      bool take = false;
+      float P = 0.f;
+      uint32_t T = 0;
+      if (j < nU) {
+        T = a.gt[b + j];
+        P = uniform ? Pu : select_prob(a.ge[b + j], gamma, exhaustive);
+        take = selection_uniform(pr.seed, pr.key, tuple_key(a, T)) < P;
+      }
+      if constexpr (FILL) {
+        const uint32_t m = uint32_t(__ballot(take) >> (GL * g)) & ((1u << GL) - 1u);
+        const uint32_t rank = __popc(m & ((1u << gl) - 1u));
+        if (take && o + rank < s.pair_cap) {
+          s.pair_pt[o + rank] = uint32_t(i);
+          s.pair_t[o + rank] = T;
+          s.pair_p[o + rank] = P;
+        }
+        o += __popc(m);
+      } else {
+        c += take ? 1u : 0u;
+      }
+    }
+    if constexpr (!FILL) {
+#pragma unroll
+      for (int m = GL / 2; m >= 1; m >>= 1) c += __shfl_xor(c, m, BBC_WAVE);
+      if (valid && gl == 0) sel[i] = c;
+    }
+  }
+}
+
 // Newton over the selected pairs, one lane per pair for the whole of its
 // starts.
 template <int CH>
@@ -1170,10 +1222,19 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   // selection counts go to the head of the pair_pt buffer, are scanned into
   // off, and are overwritten by the fill kernel afterwards
   uint32_t* sel = w.pair_pt;
-  hipLaunchKernelGGL(k_stage_count, dim3(grid), dim3(64), 0, st, s, sel);
+  const int sampler = q.mode & BBC_QUERY_SAMPLERS;
+  const bool independent = sampler == 0 || sampler == BBC_QUERY_UNIFORM;
+  const unsigned g16 = unsigned(std::min<int64_t>((n + 3) / 4, 256 * 64));
+  if (independent)
+    hipLaunchKernelGGL(k_stage_select16<false>, dim3(g16), dim3(64), 0, st, s, sel);
+  else
+    hipLaunchKernelGGL(k_stage_count, dim3(grid), dim3(64), 0, st, s, sel);
   bbc_status e = launch_scan_u32(sel, s.off, n, w.scan, st);
   if (e) return e;
-  hipLaunchKernelGGL(k_stage_fill, dim3(grid), dim3(64), 0, st, s);
+  if (independent)
+    hipLaunchKernelGGL(k_stage_select16<true>, dim3(g16), dim3(64), 0, st, s, sel);
+  else
+    hipLaunchKernelGGL(k_stage_fill, dim3(grid), dim3(64), 0, st, s);
   if (ev0) BBC_HIP(hipEventRecord(ev0, st));
   if (newton_steps > 0) {
     // as many workgroups as stay resident together, striding over the
