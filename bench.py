@@ -50,8 +50,8 @@ FLOPS_PER_PATH_EVAL = 290
 NEWTON_COUNTERS = dict(
     sources=["paper_2504_19163_amd/csrc/query.hip", "paper_2504_19163_amd/csrc/path_dev.hpp",
              "paper_2504_19163_amd/csrc/geom_dev.hpp", "paper_2504_19163_amd/csrc/dev_common.hpp"],
-    sha256="b71020d729d95dea77681ebc2eca85561966c792399956c50fc2ba8a67efa520",
-    fetch_kib=40845.8125, write_kib=47555.0, fetch_scale=262144.0 / 131087.9375, write_scale=1.0)
+    sha256="603355a3c565364cffa7f6e91227239917d38a61b76a12481e28c41850b40606",
+    fetch_kib=40841.4375, write_kib=47877.5, fetch_scale=262144.0 / 131087.75, write_scale=1.0)
 
 
 def newton_traffic_bytes():
