@@ -253,7 +253,7 @@ def test_cfg2_full_size_sampled_parity(bbc, orc, cfg2):
     _check_leaf_bounds(orc, osc, L, rng.choice(len(L["tuple"]), 1500, replace=False))
     pts = S.random_points(sc, 3000, seed=5)
     ptd = torch.as_tensor(pts, device="cuda")
-    for mode, omode in ((bbc.QUERY_EXHAUSTIVE, 1), (bbc.QUERY_FUSED, 0)):
+    for mode, omode in ((bbc.QUERY_EXHAUSTIVE, 1), (bbc.QUERY_FUSED, 0), (bbc.QUERY_STAGED, 0)):
         E, st = B.query(ptd, 64, 3, mode=mode, stats=True)
         OE, ost = Ob.query(pts, 64, 3, mode=omode)
         E = E.cpu().numpy()
