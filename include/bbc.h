@@ -160,6 +160,33 @@ typedef struct {
 } bbc_bounds_info_t;
 bbc_status bbc_bounds_info(const bbc_bounds* b, bbc_bounds_info_t* out);
 
+/* Persist a built hierarchy so that a later process can query it without
+ * rebuilding (the bounds depend only on the scene, Sec. 6.1, so one build
+ * serves every query of that scene).
+ *
+ * bbc_bounds_save writes the scene and emitter copies, the subdivision
+ * parameters, the build counters and every array the queries and exports
+ * read (tuple records, root boxes, leaves grouped by tuple, receiver grid,
+ * and for two reflections the second surface and the pair numbers) to the
+ * file at `path` (created or truncated).  The file is little-endian in the
+ * layout of this library version: magic "BBCBOUND", version 1, a header,
+ * one length-prefixed section per array, and a trailing FNV-1a-64 hash of
+ * all preceding bytes.  The handle must hold a completed build (the last
+ * build or rebuild returned BBC_OK).  EINVAL for a null argument or when the
+ * file cannot be written; EDEVICE if a device copy fails.
+ *
+ * bbc_bounds_load reads such a file into a new handle on the current device
+ * (copies ordered on `stream`, which is synchronised before return) and
+ * stores it in *out (NULL on failure).  The file is checked before any
+ * device memory is written: magic, version, header counts, every section's
+ * size, the hash, and that every offset, tuple number, pair number and box
+ * code stays inside its array; any failure gives EINVAL with the reason in
+ * bbc_last_error().  ENOMEM if device memory runs out.  A loaded handle
+ * answers queries, exports and bbc_bounds_info like the saved one, and
+ * bbc_rebuild_bounds works on it as on any other handle. */
+bbc_status bbc_bounds_save(const bbc_bounds* b, const char* path);
+bbc_status bbc_bounds_load(const char* path, void* stream, bbc_bounds** out);
+
 /* Copy the leaves to host memory (arrays of length n_leaves, any may be NULL):
  * tuple[n], code[n] (depth << 28 | iu << 14 | iv, the box index inside the
  * tuple's root box), box[n][4] (u0,u1,v0,v1 of u1), ukbox[n][4] (u_lo,u_hi,

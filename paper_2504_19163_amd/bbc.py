@@ -22,7 +22,8 @@ QUERY_FUSED, QUERY_STAGED, QUERY_EXHAUSTIVE = 0, 1, 16
 QUERY_UNIFORM, QUERY_ONE_SAMPLE, QUERY_BINS = 32, 64, 96
 
 EXPORTS = [
-    "bbc_build_bounds", "bbc_rebuild_bounds", "bbc_free_bounds", "bbc_bounds_info", "bbc_export_leaves",
+    "bbc_build_bounds", "bbc_rebuild_bounds", "bbc_free_bounds", "bbc_bounds_info", "bbc_bounds_save",
+    "bbc_bounds_load", "bbc_export_leaves",
     "bbc_export_grid", "bbc_query_irradiance", "bbc_query_irradiance_ex", "bbc_set_tuning", "bbc_get_tuning",
     "bbc_query_kernel_ms", "bbc_last_error", "bbc_server_create", "bbc_server_submit", "bbc_server_poll",
     "bbc_server_wait", "bbc_server_resume", "bbc_server_stats", "bbc_server_destroy",
@@ -114,6 +115,8 @@ def lib():
             "bbc_rebuild_bounds": [vp, vp, vp, vp, vp],
             "bbc_free_bounds": [vp],
             "bbc_bounds_info": [vp, vp],
+            "bbc_bounds_save": [vp, C.c_char_p],
+            "bbc_bounds_load": [C.c_char_p, vp, vp],
             "bbc_export_leaves": [vp, vp, vp, vp, vp, vp],
             "bbc_export_grid": [vp, vp, vp, vp],
             "bbc_query_irradiance": [vp, vp, i64, i32, u64, vp, vp, vp],
@@ -213,6 +216,24 @@ class Bounds:
         _check(lib().bbc_build_bounds(C.byref(dscene.c_scene), C.byref(dscene.c_emit), C.byref(self._p),
                                       _stream_handle(stream), C.byref(h)), "bbc_build_bounds")
         self.h = h
+
+    def save(self, path):
+        """Write the hierarchy to a file (bbc_bounds_save)."""
+        _check(lib().bbc_bounds_save(self.h, os.fsencode(path)), "bbc_bounds_save")
+
+    @classmethod
+    def load(cls, path, dscene=None, params=None, stream=None):
+        """Read a file written by save() into a new handle on the current
+        device (bbc_bounds_load).  `dscene` and `params` (optional) are what
+        rebuild() will use; the loaded hierarchy itself carries its own."""
+        self = cls.__new__(cls)
+        self.dscene = dscene
+        self.params = dict(default_params(), **(params or {}))
+        self._p = SubdivParams(**self.params)
+        h = C.c_void_p()
+        _check(lib().bbc_bounds_load(os.fsencode(path), _stream_handle(stream), C.byref(h)), "bbc_bounds_load")
+        self.h = h
+        return self
 
     def rebuild(self, stream=None):
         _check(lib().bbc_rebuild_bounds(self.h, C.byref(self.dscene.c_scene), C.byref(self.dscene.c_emit),

@@ -1,8 +1,10 @@
 // Host side of the C ABI (include/bbc.h): argument validation, library-owned
 // device buffers, capacity regrowth, and the stage launch sequences.
 #include <cmath>
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <iterator>
 #include <string>
 #include <vector>
 
@@ -236,6 +238,183 @@ static bbc_status construct_pairs(Bounds* b, hipStream_t s) {
 
 static hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+// ---- bound file (bbc_bounds_save / bbc_bounds_load) ----
+// Layout: FileHeader, then one section per array (u64 byte count, bytes) in
+// the order of bound_sections(), then a u64 FNV-1a hash of every byte before it.
+constexpr char kFileMagic[8] = {'B', 'B', 'C', 'B', 'O', 'U', 'N', 'D'};
+constexpr uint32_t kFileVersion = 1;
+
+struct FileHeader {
+  char magic[8];
+  uint32_t version;
+  uint32_t header_bytes;
+  int32_t chain, has_edges, rec_floats;
+  float eta;
+  int64_t n_tri, n_tri2, n_emit, n_tuples, n_dense, n_leaves, n_entries, max_cell;
+  float q0[3], f1[3], f2[3];
+  uint32_t pad;
+  bbc_subdiv_params params;
+  BuildCounters host;
+};
+
+struct Section {
+  DevBuf* buf;
+  size_t bytes;
+};
+
+// Every array a loaded handle needs for queries, exports and statistics.
+static std::vector<Section> bound_sections(Bounds* b, int64_t n_tri, int64_t n_tri2, int64_t n_emit, bool edges) {
+  const size_t nt = size_t(b->n_tuples), nl = size_t(b->n_leaves), ne = size_t(b->n_entries);
+  const size_t G = size_t(b->params.grid_res);
+  std::vector<Section> v = {{&b->pos, size_t(n_tri) * 36}, {&b->nrm, size_t(n_tri) * 36},
+                            {&b->epos, size_t(n_emit) * 12}, {&b->eI, size_t(n_emit) * 4}};
+  if (edges) v.push_back({&b->eedge, size_t(n_emit) * 24});
+  if (b->scene.chain == BBC_CHAIN_RR) {
+    v.push_back({&b->pos2, size_t(n_tri2) * 36});
+    v.push_back({&b->nrm2, size_t(n_tri2) * 36});
+    v.push_back({&b->tid, nt * 4});
+  }
+  const Section rest[] = {{&b->trec, nt * size_t(b->rec_floats) * 4},
+                          {&b->root, nt * 16},
+                          {&b->toff, (nt + 1) * 4},
+                          {&b->st, nl * 4},
+                          {&b->sc, nl * 4},
+                          {&b->su, nl * 16},
+                          {&b->se, nl * 8},
+                          {&b->coff, (G * G + 1) * 4},
+                          {&b->gt, ne * 4},
+                          {&b->ge, ne * 4}};
+  v.insert(v.end(), std::begin(rest), std::end(rest));
+  return v;
+}
+
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  }
+};
+
+// Host-side consistency of a loaded file: every index the query kernels
+// follow (tuple offsets, grid offsets, tuple numbers, pair numbers, box codes)
+// stays inside its array, so a damaged file cannot send a kernel out of bounds.
+static bbc_status check_loaded(const FileHeader& fh, const std::vector<std::vector<char>>& data,
+                               const std::vector<Section>& secs, const Bounds* b) {
+  auto find = [&](const DevBuf* d) -> const std::vector<char>& {
+    for (size_t i = 0; i < secs.size(); ++i)
+      if (secs[i].buf == d) return data[i];
+    return data[0];
+  };
+  const uint32_t* toff = reinterpret_cast<const uint32_t*>(find(&b->toff).data());
+  const uint32_t* coff = reinterpret_cast<const uint32_t*>(find(&b->coff).data());
+  const uint32_t* st = reinterpret_cast<const uint32_t*>(find(&b->st).data());
+  const uint32_t* sc = reinterpret_cast<const uint32_t*>(find(&b->sc).data());
+  const uint32_t* gt = reinterpret_cast<const uint32_t*>(find(&b->gt).data());
+  const int64_t nt = fh.n_tuples, nl = fh.n_leaves, ne = fh.n_entries;
+  const int64_t nc = int64_t(fh.params.grid_res) * fh.params.grid_res;
+  if (toff[0] != 0 || int64_t(toff[nt]) != nl) return invalid("bound file: tuple offsets do not span the leaves");
+  for (int64_t t = 0; t < nt; ++t)
+    if (toff[t + 1] < toff[t]) return invalid("bound file: tuple offsets decrease");
+  for (int64_t i = 0; i < nl; ++i) {
+    if (int64_t(st[i]) >= nt || i < int64_t(toff[st[i]]) || i >= int64_t(toff[st[i] + 1]))
+      return invalid("bound file: leaf tuple outside its offsets");
+    const uint32_t depth = sc[i] >> 28, iu = (sc[i] >> kCodeBits) & ((1u << kCodeBits) - 1),
+                   iv = sc[i] & ((1u << kCodeBits) - 1);
+    if (depth > uint32_t(kMaxDepth) || iu >> depth || iv >> depth) return invalid("bound file: leaf code out of range");
+  }
+  int64_t mc = 0;
+  if (coff[0] != 0 || int64_t(coff[nc]) != ne) return invalid("bound file: cell offsets do not span the entries");
+  for (int64_t c = 0; c < nc; ++c) {
+    if (coff[c + 1] < coff[c]) return invalid("bound file: cell offsets decrease");
+    mc = std::max<int64_t>(mc, coff[c + 1] - coff[c]);
+  }
+  if (mc != fh.max_cell) return invalid("bound file: fullest cell differs from the header");
+  for (int64_t i = 0; i < ne; ++i)
+    if (int64_t(gt[i]) >= nt) return invalid("bound file: grid entry names a tuple out of range");
+  if (fh.chain == BBC_CHAIN_RR) {
+    const uint32_t* tid = reinterpret_cast<const uint32_t*>(find(&b->tid).data());
+    for (int64_t t = 0; t < nt; ++t)
+      if (int64_t(tid[t]) >= fh.n_dense) return invalid("bound file: pair number out of range");
+  }
+  return BBC_OK;
+}
+
+static bbc_status read_exact(FILE* f, void* p, size_t n, Fnv& h) {
+  if (n && std::fread(p, 1, n, f) != n) return invalid("bound file truncated");
+  h.add(p, n);
+  return BBC_OK;
+}
+
+static bbc_status load_file(FILE* f, Bounds* b, hipStream_t s) {
+  Fnv h;
+  FileHeader fh{};
+  bbc_status e;
+  if ((e = read_exact(f, &fh, sizeof fh, h))) return e;
+  if (std::memcmp(fh.magic, kFileMagic, 8) != 0) return invalid("not a bound file (magic)");
+  if (fh.version != kFileVersion || fh.header_bytes != sizeof(FileHeader))
+    return invalid("bound file version or header size not supported");
+  const bool rr = fh.chain == BBC_CHAIN_RR;
+  if (fh.chain != BBC_CHAIN_R && fh.chain != BBC_CHAIN_T && !rr) return invalid("bound file: unknown chain");
+  if (fh.params.grid_res < 1 || fh.params.grid_res > 4096 || fh.n_tri < 1 || fh.n_emit < 1 || fh.n_tuples < 0 ||
+      fh.n_leaves < 0 || fh.n_entries < 0 || fh.n_leaves > (int64_t(1) << 32) || fh.n_entries > (int64_t(1) << 32) ||
+      fh.max_cell < 0 || (rr && fh.n_tri2 < 1) || (!rr && fh.n_tri2 != 0) || (fh.has_edges && fh.chain != BBC_CHAIN_R))
+    return invalid("bound file: counts out of range");
+  const int64_t dense = fh.n_tri * fh.n_emit * (rr ? fh.n_tri2 : 1);
+  if (double(fh.n_tri) * double(fh.n_emit) * double(rr ? fh.n_tri2 : 1) > 4294967000.0 || fh.n_dense != dense ||
+      fh.n_tuples > dense || (!rr && fh.n_tuples != dense) || fh.rec_floats != (rr ? kRecFloatsRR : kRecFloats))
+    return invalid("bound file: tuple counts inconsistent");
+  b->params = fh.params;
+  b->scene.chain = fh.chain;
+  b->n_tuples = fh.n_tuples;
+  b->n_dense = fh.n_dense;
+  b->tuples_cap = rr ? fh.n_tuples : 0;
+  b->rec_floats = fh.rec_floats;
+  b->n_leaves = fh.n_leaves;
+  b->n_entries = fh.n_entries;
+  const std::vector<Section> secs = bound_sections(b, fh.n_tri, fh.n_tri2, fh.n_emit, fh.has_edges != 0);
+  std::vector<std::vector<char>> data(secs.size());
+  for (size_t i = 0; i < secs.size(); ++i) {
+    uint64_t n = 0;
+    if ((e = read_exact(f, &n, 8, h))) return e;
+    if (n != secs[i].bytes) return invalid("bound file: section size differs from the header's counts");
+    data[i].resize(std::max<size_t>(n, 4));
+    if ((e = read_exact(f, data[i].data(), n, h))) return e;
+  }
+  uint64_t hash = 0;
+  Fnv dummy;
+  if ((e = read_exact(f, &hash, 8, dummy))) return e;
+  if (hash != h.h) return invalid("bound file checksum mismatch");
+  if ((e = check_loaded(fh, data, secs, b))) return e;
+  // The file is sound: only now touch the device.
+  BBC_HIP(hipGetDevice(&b->device));
+  for (size_t i = 0; i < secs.size(); ++i)
+    if ((e = copy_in(*secs[i].buf, data[i].data(), secs[i].bytes, BBC_MEM_HOST, b, s))) return e;
+  BBC_HIP(hipStreamSynchronize(s));  // the host staging vectors go out of scope below
+  DevScene& d = b->scene;
+  d.n_tri = fh.n_tri;
+  d.pos = static_cast<const float*>(b->pos.p);
+  d.nrm = static_cast<const float*>(b->nrm.p);
+  d.n_emit = fh.n_emit;
+  d.epos = static_cast<const float*>(b->epos.p);
+  d.eI = static_cast<const float*>(b->eI.p);
+  d.eedge = fh.has_edges ? static_cast<const float*>(b->eedge.p) : nullptr;
+  d.eta = fh.eta;
+  for (int k = 0; k < 3; ++k) {
+    d.q0[k] = fh.q0[k];
+    d.f1[k] = fh.f1[k];
+    d.f2[k] = fh.f2[k];
+  }
+  d.n_tri2 = fh.n_tri2;
+  d.pos2 = rr ? static_cast<const float*>(b->pos2.p) : nullptr;
+  d.nrm2 = rr ? static_cast<const float*>(b->nrm2.p) : nullptr;
+  d.tid = rr ? static_cast<const uint32_t*>(b->tid.p) : nullptr;
+  b->host = fh.host;
+  b->max_cell = fh.max_cell;
+  return BBC_OK;
+}
+
+
 }  // namespace bbc
 
 using namespace bbc;
@@ -289,6 +468,87 @@ bbc_status bbc_free_bounds(bbc_bounds* h) {
   if (b->ev[0]) (void)hipEventDestroy(b->ev[0]);
   if (b->ev[1]) (void)hipEventDestroy(b->ev[1]);
   delete b;
+  return BBC_OK;
+}
+
+bbc_status bbc_bounds_save(const bbc_bounds* h, const char* path) {
+  if (!h || !path) return invalid("null bounds handle or path");
+  Bounds* b = const_cast<Bounds*>(reinterpret_cast<const Bounds*>(h));
+  FileHeader fh{};
+  std::memcpy(fh.magic, kFileMagic, 8);
+  fh.version = kFileVersion;
+  fh.header_bytes = sizeof(FileHeader);
+  const DevScene& d = b->scene;
+  fh.chain = d.chain;
+  fh.has_edges = d.eedge != nullptr;
+  fh.rec_floats = b->rec_floats;
+  fh.eta = d.eta;
+  fh.n_tri = d.n_tri;
+  fh.n_tri2 = d.n_tri2;
+  fh.n_emit = d.n_emit;
+  fh.n_tuples = b->n_tuples;
+  fh.n_dense = b->n_dense;
+  fh.n_leaves = b->n_leaves;
+  fh.n_entries = b->n_entries;
+  fh.max_cell = b->max_cell;
+  for (int k = 0; k < 3; ++k) {
+    fh.q0[k] = d.q0[k];
+    fh.f1[k] = d.f1[k];
+    fh.f2[k] = d.f2[k];
+  }
+  fh.params = b->params;
+  fh.host = b->host;
+  const std::vector<Section> secs = bound_sections(b, d.n_tri, d.n_tri2, d.n_emit, d.eedge != nullptr);
+  std::vector<char> buf;
+  for (const Section& sec : secs) {
+    if (sec.bytes > sec.buf->bytes) return invalid("bounds handle holds no completed build");
+  }
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return invalid("cannot open the bound file for writing");
+  Fnv hsh;
+  bool ok = std::fwrite(&fh, sizeof fh, 1, f) == 1;
+  hsh.add(&fh, sizeof fh);
+  for (size_t i = 0; ok && i < secs.size(); ++i) {
+    const uint64_t n = secs[i].bytes;
+    buf.resize(std::max<size_t>(n, 1));
+    if (n) {
+      const hipError_t he = hipMemcpy(buf.data(), secs[i].buf->p, n, hipMemcpyDeviceToHost);
+      if (he != hipSuccess) {
+        std::fclose(f);
+        return hip_fail(he, "hipMemcpy (bound file)");
+      }
+    }
+    ok = std::fwrite(&n, 8, 1, f) == 1 && (n == 0 || std::fwrite(buf.data(), 1, n, f) == n);
+    hsh.add(&n, 8);
+    hsh.add(buf.data(), n);
+  }
+  ok = ok && std::fwrite(&hsh.h, 8, 1, f) == 1;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return invalid("writing the bound file failed");
+  return BBC_OK;
+}
+
+bbc_status bbc_bounds_load(const char* path, void* stream, bbc_bounds** out) {
+  if (!out) return invalid("null output handle pointer");
+  *out = nullptr;
+  if (!path) return invalid("null path");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return invalid("cannot open the bound file");
+  Bounds* b = new (std::nothrow) Bounds();
+  if (!b) {
+    std::fclose(f);
+    set_error("host allocation failed");
+    return BBC_ENOMEM;
+  }
+  const bbc_status e = load_file(f, b, as_stream(stream));
+  std::fclose(f);
+  if (e) {
+    if (b->device_bytes) (void)hipStreamSynchronize(as_stream(stream));
+    release_all(b);
+    delete b;
+    return e;
+  }
+  *out = reinterpret_cast<bbc_bounds*>(b);
   return BBC_OK;
 }
 
