@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <iterator>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -373,12 +374,26 @@ static bbc_status load_file(FILE* f, Bounds* b, hipStream_t s) {
   b->n_leaves = fh.n_leaves;
   b->n_entries = fh.n_entries;
   const std::vector<Section> secs = bound_sections(b, fh.n_tri, fh.n_tri2, fh.n_emit, fh.has_edges != 0);
+  // The whole file's size follows from the header: check it before any
+  // allocation, so that a damaged count cannot ask for a huge buffer.
+  uint64_t want = sizeof(FileHeader) + 8;
+  for (const Section& sec : secs) want += 8 + sec.bytes;
+  const long here = std::ftell(f);
+  if (here < 0 || std::fseek(f, 0, SEEK_END) != 0) return invalid("bound file is not seekable");
+  const long end = std::ftell(f);
+  if (end < 0 || std::fseek(f, here, SEEK_SET) != 0) return invalid("bound file is not seekable");
+  if (uint64_t(end) != want) return invalid("bound file size differs from what its header describes");
   std::vector<std::vector<char>> data(secs.size());
   for (size_t i = 0; i < secs.size(); ++i) {
     uint64_t n = 0;
     if ((e = read_exact(f, &n, 8, h))) return e;
     if (n != secs[i].bytes) return invalid("bound file: section size differs from the header's counts");
-    data[i].resize(std::max<size_t>(n, 4));
+    try {
+      data[i].resize(std::max<size_t>(n, 4));
+    } catch (const std::bad_alloc&) {
+      set_error("host allocation for the bound file failed");
+      return BBC_ENOMEM;
+    }
     if ((e = read_exact(f, data[i].data(), n, h))) return e;
   }
   uint64_t hash = 0;
@@ -510,7 +525,13 @@ bbc_status bbc_bounds_save(const bbc_bounds* h, const char* path) {
   hsh.add(&fh, sizeof fh);
   for (size_t i = 0; ok && i < secs.size(); ++i) {
     const uint64_t n = secs[i].bytes;
-    buf.resize(std::max<size_t>(n, 1));
+    try {
+      buf.resize(std::max<size_t>(n, 1));
+    } catch (const std::bad_alloc&) {
+      std::fclose(f);
+      set_error("host allocation for the bound file failed");
+      return BBC_ENOMEM;
+    }
     if (n) {
       const hipError_t he = hipMemcpy(buf.data(), secs[i].buf->p, n, hipMemcpyDeviceToHost);
       if (he != hipSuccess) {

@@ -89,9 +89,9 @@ def test_wellformed_file_passes_host_validation(L, tmp_path):
 
 
 @pytest.mark.parametrize("case,needle", [
-    ("magic", "magic"), ("version", "version"), ("truncated", "truncated"), ("flip", "checksum"),
-    ("toff", "tuple offsets"), ("coff", "cell offsets"), ("max_cell", "fullest cell"), ("grid_res", "section size"),
-    ("trailing", "checksum"), ("empty", "truncated"), ("leaf_tuple", "leaf tuple"), ("leaf_code", "leaf code"),
+    ("magic", "magic"), ("version", "version"), ("truncated", "file size"), ("flip", "checksum"),
+    ("toff", "tuple offsets"), ("coff", "cell offsets"), ("max_cell", "fullest cell"), ("grid_res", "file size"),
+    ("trailing", "file size"), ("empty", "truncated"), ("leaves_claimed", "file size"), ("leaf_tuple", "leaf tuple"), ("leaf_code", "leaf code"),
     ("entry", "grid entry"),
 ])
 def test_damaged_files_are_rejected(L, tmp_path, case, needle):
@@ -107,6 +107,7 @@ def test_damaged_files_are_rejected(L, tmp_path, case, needle):
         "grid_res": lambda: _file(grid_res=2),
         "trailing": lambda: _file(extra_section=True),
         "empty": lambda: b"",
+        "leaves_claimed": lambda: (lambda d: d[:72] + struct.pack("<q", 1 << 31) + d[80:])(_file()),
         "leaf_tuple": lambda: _file(leaf=(1, 0)),
         "leaf_code": lambda: _file(leaf=(0, 1 << 28 | 2 << 14)),
         "entry": lambda: _file(entry=1),
