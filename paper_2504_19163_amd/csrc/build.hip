@@ -136,16 +136,16 @@ __device__ void level0_one(const BuildArgs& a, uint32_t t, Ev ev, int lane, Stag
 }
 
 // The per-tuple loop of the level-0 kernels with staged outputs.
-template <class T, class Ev, class Tuples>
+template <class T, int NT = BBC_WAVE, class Ev, class Tuples>
 __device__ void level0_loop(const BuildArgs& a, Ev ev, int lane, Stage& S, uint32_t n, Tuples tuple_at) {
   stage_reset(S, lane);
   wave_sync();
   for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
     level0_one<T>(a, tuple_at(i), ev, lane, S);
     wave_sync();
-    if (stage_full(S)) stage_flush<BBC_WAVE>(a, 0, S, lane);
+    if (stage_full(S)) stage_flush<NT>(a, 0, S, lane);
   }
-  stage_flush<BBC_WAVE>(a, 0, S, lane);
+  stage_flush<NT>(a, 0, S, lane);
 }
 
 // Position-only boxes of reflection tuples have at most 25 coefficients per
@@ -202,14 +202,18 @@ __global__ void __launch_bounds__(64) k_level0_ra(BuildArgs a) {
   level0_loop<double>(a, ev, lane, S, uint32_t(a.n_tuples), [](uint32_t i) { return i; });
 }
 
-__global__ void __launch_bounds__(64) k_level0_rr(BuildArgs a) {
+// Two-reflection position bounds (degree 16 per axis, FP64) take ~57 KB of
+// LDS, so two workgroups fit a compute unit: four waves share each box, as in
+// the subdivision, rather than one wave alone.
+constexpr int kInitRRThreads = 256;
+__global__ void __launch_bounds__(kInitRRThreads) k_level0_rr(BuildArgs a) {
   __shared__ LdsRR<double> L;
   __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
-    return eval_box_rr<double>(G, u0, u1, v0, v1, L, lane);
+    return eval_box_rr<double, false, kInitRRThreads>(G, u0, u1, v0, v1, L, lane);
   };
-  level0_loop<double>(a, ev, lane, S, uint32_t(a.n_tuples), [](uint32_t i) { return i; });
+  level0_loop<double, kInitRRThreads>(a, ev, lane, S, uint32_t(a.n_tuples), [](uint32_t i) { return i; });
 }
 
 // ---------------------------------------------------------------- tuple construction, two reflections
@@ -385,7 +389,7 @@ struct InitBox {
 
 // One tuple's breadth-first initialisation; ev(cl, cu, cv) bounds the box
 // (cu, cv) of level cl.
-template <class Ev>
+template <int NT = BBC_WAVE, class Ev>
 __device__ void init_one(const BuildArgs& a, uint32_t t, Ev ev, InitBox* cur, InitBox* nxt, int lane, Stage& S) {
   int ncur = 1;
   if (lane == 0) cur[0] = InitBox{0u, 0u};
@@ -425,7 +429,7 @@ __device__ void init_one(const BuildArgs& a, uint32_t t, Ev ev, InitBox* cur, In
       dead = true;
       break;
     }
-    for (int j = lane; j < nn; j += BBC_WAVE) cur[j] = nxt[j];
+    for (int j = lane; j < nn; j += NT) cur[j] = nxt[j];
     ncur = nn;
     wave_sync();
   }
@@ -443,7 +447,7 @@ __device__ void init_one(const BuildArgs& a, uint32_t t, Ev ev, InitBox* cur, In
     push_root(a, t, make_float4(u0, u1, v0, v1), S);
   }
   wave_sync();
-  if (stage_full(S)) stage_flush<BBC_WAVE>(a, 0, S, lane);
+  if (stage_full(S)) stage_flush<NT>(a, 0, S, lane);
 }
 
 // Domain initialisation of reflection tuples: the four children of a box are
@@ -552,7 +556,7 @@ __global__ void __launch_bounds__(64) k_init(BuildArgs a) {
   stage_flush<BBC_WAVE>(a, 0, S, tid);
 }
 
-__global__ void __launch_bounds__(64) k_init_rr(BuildArgs a) {
+__global__ void __launch_bounds__(kInitRRThreads) k_init_rr(BuildArgs a) {
   __shared__ LdsRR<double> L;
   __shared__ InitBox cur[kInitCap], nxt[kInitCap];
   __shared__ Stage S;
@@ -565,11 +569,11 @@ __global__ void __launch_bounds__(64) k_init_rr(BuildArgs a) {
     const TupleGeom<double> Gd = tuple_geom<double>(a.sc, t);
     auto ev = [&](int cl, uint32_t cu, uint32_t cv) {
       const double wd = ldexp(1.0, -cl);
-      return eval_box_rr<double>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, L, lane);
+      return eval_box_rr<double, false, kInitRRThreads>(Gd, cu * wd, (cu + 1) * wd, cv * wd, (cv + 1) * wd, L, lane);
     };
-    init_one(a, t, ev, cur, nxt, lane, S);
+    init_one<kInitRRThreads>(a, t, ev, cur, nxt, lane, S);
   }
-  stage_flush<BBC_WAVE>(a, 0, S, lane);
+  stage_flush<kInitRRThreads>(a, 0, S, lane);
 }
 
 __global__ void __launch_bounds__(64) k_init_ra(BuildArgs a) {
@@ -805,7 +809,7 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   if (area) {
     hipLaunchKernelGGL(k_level0_ra, dim3(g0), dim3(64), 0, s, a);
   } else if (rr) {
-    hipLaunchKernelGGL(k_level0_rr, dim3(g0), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_level0_rr, dim3(g0), dim3(kInitRRThreads), 0, s, a);
   } else if (refr) {
     hipLaunchKernelGGL(k_level0_t, dim3(g0), dim3(64), 0, s, a);
   } else {
@@ -818,7 +822,7 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
     if (area)
       hipLaunchKernelGGL(k_init_ra, dim3(persistent), dim3(64), 0, s, a);
     else if (rr)
-      hipLaunchKernelGGL(k_init_rr, dim3(persistent), dim3(64), 0, s, a);
+      hipLaunchKernelGGL(k_init_rr, dim3(persistent), dim3(kInitRRThreads), 0, s, a);
     else if (refr)
       hipLaunchKernelGGL(k_init_t, dim3(persistent), dim3(64), 0, s, a);
     else
