@@ -716,17 +716,21 @@ __global__ void __launch_bounds__(kSubdivRAThreads) k_subdiv_ra(BuildArgs a, int
   subdiv_loop<kSubdivRAThreads>(a, depth, ev, lane, S);
 }
 
-// A refraction box takes ~1.5 Mflop of FP64 over ~90 KB of LDS: four waves
-// share one box so that all four SIMDs of the compute unit work on it.
-constexpr int kSubdivTThreads = 256;
-__global__ void __launch_bounds__(kSubdivTThreads) k_subdiv_t(BuildArgs a, int depth) {
+// A refraction box takes ~1.5 Mflop of FP64 over ~90 KB of LDS, so one box
+// fills a compute unit: four waves share it with the explicit irradiance
+// bound, eight with the implicit one (its many small steps hide more latency
+// with two waves per SIMD: 1.26 -> 0.97 s per water build, while the explicit
+// bound's large convolutions gain nothing from the extra waves).
+constexpr int kSubdivTThreads = 256, kSubdivTImplicitThreads = 512;
+template <int NT>
+__global__ void __launch_bounds__(NT) k_subdiv_t(BuildArgs a, int depth) {
   __shared__ LdsT<double, true> L;
   __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
-    return eval_box_t<double, true, kSubdivTThreads>(G, u0, u1, v0, v1, true, a.flags, L, lane);
+    return eval_box_t<double, true, NT>(G, u0, u1, v0, v1, true, a.flags, L, lane);
   };
-  subdiv_loop<kSubdivTThreads>(a, depth, ev, lane, S);
+  subdiv_loop<NT>(a, depth, ev, lane, S);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
@@ -836,8 +840,11 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
       hipLaunchKernelGGL(k_subdiv_ra, dim3(unsigned(n_cu) * 2u), dim3(kSubdivRAThreads), 0, s, a, d);
     else if (rr)
       hipLaunchKernelGGL(k_subdiv_rr, dim3(unsigned(n_cu)), dim3(kSubdivRRThreads), 0, s, a, d);
+    else if (refr && (a.flags & BBC_FLAG_IMPLICIT_IRR))
+      hipLaunchKernelGGL(k_subdiv_t<kSubdivTImplicitThreads>, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTImplicitThreads),
+                         0, s, a, d);
     else if (refr)
-      hipLaunchKernelGGL(k_subdiv_t, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTThreads), 0, s, a, d);
+      hipLaunchKernelGGL(k_subdiv_t<kSubdivTThreads>, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTThreads), 0, s, a, d);
     else
       hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, s, a, d);
     BBC_HIP(hipGetLastError());
