@@ -87,3 +87,21 @@ def test_rebuilt_handle_saves_its_new_hierarchy(bbc, tmp_path):
     _same_export(A, B)
     C = bbc.Bounds(ds, dict(max_depth=2, grid_res=64))
     _same_export(C, B)
+
+
+def test_loaded_bounds_serve_like_the_original(bbc, tmp_path):
+    """A server over a loaded handle returns what the staged query of the
+    handle that wrote the file returns, bit for bit."""
+    sc = S.heightfield_mirror(8)
+    A = bbc.Bounds(bbc.DeviceScene(sc), dict(max_depth=5))
+    A.save(tmp_path / "serve.bbc")
+    B = bbc.Bounds.load(tmp_path / "serve.bbc")
+    pts = S.random_points(sc, 2000, seed=9)
+    Ea, _ = A.query(torch.as_tensor(pts, device="cuda"), 16, 7, mode=bbc.QUERY_STAGED, point_index_base=100)
+    torch.cuda.synchronize()
+    srv = bbc.Server([B], hbm_budget_bytes=1 << 28, max_inflight=2)
+    try:
+        out, _ = srv.wait(srv.submit(0, pts, 16, 7, point_index_base=100))
+    finally:
+        srv.close()
+    assert np.array_equal(out, Ea.cpu().numpy())
