@@ -155,10 +155,20 @@ bbc_status launch_query(const Bounds* b, const float* pts, int64_t n, int32_t sp
                         int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t s);
 bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
                                int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t s);
+// The staged query over caller-provided work space of `bytes` bytes at `work`
+// (device memory, 256-byte aligned): the points run in consecutive slices of
+// as many points as the space holds at the worst case.  EBUDGET when one
+// point's worst case does not fit.  Allocates nothing.
+bbc_status launch_query_staged_in(const Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed,
+                                  int64_t base, int32_t mode, float* out, float* stats, void* work, size_t bytes,
+                                  hipStream_t s);
 
 // Staged work space: worst-case pair count of n points (every entry of the
 // fullest cell selected), bytes for n points and that many pairs, and the
-// carving of one allocation of that size.
+// carving of one allocation of that size.  Pair offsets and pair indices are
+// 32-bit, so one staged launch is sized for at most kMaxStagedPairs pairs;
+// a larger query runs as consecutive launches over slices of its points.
+constexpr size_t kMaxStagedPairs = size_t(1) << 28;
 size_t staged_pairs(const Bounds* b, int64_t n);
 size_t staged_bytes(int64_t n, size_t pairs);
 void staged_carve(void* base, int64_t n, size_t pairs, StagedWork& w);

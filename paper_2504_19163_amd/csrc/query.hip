@@ -30,8 +30,9 @@ struct QueryArgs {
   const uint32_t* coff;
   const uint32_t* gt;
   const float* ge;
-  const float* pts;
+  const float* pts;  // [3][pstride]: row r of point i at pts[r * pstride + i]
   int64_t n;
+  int64_t pstride;
   float W;
   uint64_t seed;
   int64_t base;
@@ -91,7 +92,7 @@ struct Target {
 // receiver parallelogram) and its grid cell (Sec. 6.1 bound storage).
 __device__ __forceinline__ Target receiver_target(const QueryArgs& a, int64_t i) {
   Target t;
-  const double x = a.pts[i], y = a.pts[a.n + i], z = a.pts[2 * a.n + i];
+  const double x = a.pts[i], y = a.pts[a.pstride + i], z = a.pts[2 * a.pstride + i];
   const double rx = x - a.sc.q0[0], ry = y - a.sc.q0[1], rz = z - a.sc.q0[2];
   const double f1x = a.sc.f1[0], f1y = a.sc.f1[1], f1z = a.sc.f1[2];
   const double f2x = a.sc.f2[0], f2y = a.sc.f2[1], f2z = a.sc.f2[2];
@@ -457,6 +458,7 @@ static QueryArgs make_args(const Bounds* b, const float* pts, int64_t n, int32_t
   a.rec_floats = b->rec_floats;
   a.pts = pts;
   a.n = n;
+  a.pstride = n;
   a.W = float(spp);
   a.seed = seed;
   a.base = base;
@@ -1287,24 +1289,77 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   return BBC_OK;
 }
 
+// Points per staged launch: the worst case of every launch (every candidate
+// of the fullest cell selected) stays within kMaxStagedPairs pairs.
+static int64_t staged_slice(const Bounds* b, int64_t n) {
+  const int64_t per = int64_t(kMaxStagedPairs / size_t(std::max<int64_t>(1, b->max_cell)));
+  return std::max<int64_t>(1, std::min(n, per));
+}
+
+// One staged launch over points [i0, i0 + m) of a query of n points, in the
+// carved work space w (sized for at least m points).
+static bbc_status staged_slice_run(const Bounds* b, const float* pts, int64_t n, int64_t i0, int64_t m, int32_t spp,
+                                   uint64_t seed, int64_t base, int32_t mode, float* out, float* stats,
+                                   unsigned long long* counters, const StagedWork& w, hipEvent_t ev0, hipEvent_t ev1,
+                                   hipStream_t st) {
+  QueryArgs q = make_args(b, pts + i0, m, spp, seed, base + i0, mode, out + i0, stats ? stats + 4 * i0 : nullptr,
+                          counters);
+  q.pstride = n;
+  return run_staged(q, w, w.pairs, b->tune.newton_steps, b->tune.newton_results, ev0, ev1, st);
+}
+
 bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
                                int32_t mode, float* out, float* stats, unsigned long long* counters, hipStream_t st) {
   if (n == 0) return BBC_OK;
-  const size_t pairs = staged_pairs(b, n);
-  if (size_t(n) > b->qw.pts || pairs > b->qw.pairs) {
-    const int64_t np = std::max<int64_t>(n, int64_t(b->qw.pts));
+  const int64_t slice = staged_slice(b, n);
+  const size_t pairs = staged_pairs(b, slice);
+  if (size_t(slice) > b->qw.pts || pairs > b->qw.pairs) {
+    const int64_t np = std::max<int64_t>(slice, int64_t(b->qw.pts));
     const size_t pp = std::max(pairs, b->qw.pairs);
     bbc_status e = ensure(b->qw_buf, staged_bytes(np, pp), b);
     if (e) return e;
     staged_carve(b->qw_buf.p, np, pp, b->qw);
   }
-  const QueryArgs q = make_args(b, pts, n, spp, seed, base, mode, out, stats, counters);
   const bool timed = b->tune.timing != 0;
-  bbc_status e = run_staged(q, b->qw, b->qw.pairs, b->tune.newton_steps, b->tune.newton_results,
-                            timed ? b->ev[0] : nullptr,
-                            timed ? b->ev[1] : nullptr, st);
-  if (e) return e;
+  for (int64_t i0 = 0; i0 < n; i0 += slice) {
+    const int64_t m = std::min(slice, n - i0);
+    // events bracket the Newton kernel of the first slice
+    const bool ev = timed && i0 == 0;
+    bbc_status e = staged_slice_run(b, pts, n, i0, m, spp, seed, base, mode, out, stats, counters, b->qw,
+                                    ev ? b->ev[0] : nullptr, ev ? b->ev[1] : nullptr, st);
+    if (e) return e;
+  }
   if (timed) b->ev_recorded = true;
+  return BBC_OK;
+}
+
+bbc_status launch_query_staged_in(const Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed,
+                                  int64_t base, int32_t mode, float* out, float* stats, void* work, size_t bytes,
+                                  hipStream_t st) {
+  if (n == 0) return BBC_OK;
+  // the largest slice whose worst-case work space fits `bytes`
+  int64_t lo = 0, hi = staged_slice(b, n);
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (staged_bytes(mid, staged_pairs(b, mid)) <= bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  if (lo == 0) {
+    set_error("work space of " + std::to_string(bytes) + " bytes cannot hold one shading point's worst case (" +
+              std::to_string(staged_bytes(1, staged_pairs(b, 1))) + " bytes for a cell of " +
+              std::to_string(b->max_cell) + " candidates)");
+    return BBC_EBUDGET;
+  }
+  StagedWork w;
+  staged_carve(work, lo, staged_pairs(b, lo), w);
+  for (int64_t i0 = 0; i0 < n; i0 += lo) {
+    const int64_t m = std::min(lo, n - i0);
+    bbc_status e = staged_slice_run(b, pts, n, i0, m, spp, seed, base, mode, out, stats, nullptr, w, nullptr, nullptr,
+                                    st);
+    if (e) return e;
+  }
   return BBC_OK;
 }
 

@@ -166,8 +166,11 @@ __global__ void k_leaf_rank(RecArgs a) {
 }
 
 // ---------------------------------------------------------------- receiver grid
+// Cell of a receiver coordinate: the product x G is exact in FP64 (24-bit
+// significand times G <= 4096), so a bound's edge is never rounded into the
+// next cell.
 __device__ __forceinline__ int cell_of(float x, int G) {
-  const float c = floorf(fminf(fmaxf(x, 0.f), 1.f) * float(G));  // NaN maps to 0
+  const double c = floor(double(fminf(fmaxf(x, 0.f), 1.f)) * double(G));  // NaN maps to 0
   return min(G - 1, max(0, int(c)));
 }
 

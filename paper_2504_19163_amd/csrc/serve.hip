@@ -47,6 +47,9 @@ static BatchLayout batch_layout(const Bounds* b, int64_t n, int32_t nreq) {
   L.work = o;
   o += staged_bytes(n, staged_pairs(b, n));
   L.total = o;
+  // a batch is one staged launch, whose 32-bit pair indices limit its
+  // worst-case pair count: a larger batch never fits
+  if (staged_pairs(b, n) > std::max(kMaxStagedPairs, staged_pairs(b, 1))) L.total = SIZE_MAX;
   return L;
 }
 
@@ -377,6 +380,9 @@ bbc_status bbc_server_submit(bbc_server* s, const bbc_request* r, uint64_t* tick
   if (r->n > s->cfg.max_batch_points)
     return reject(BBC_EBUDGET, "request has more points than max_batch_points");
   const size_t need = batch_layout(s->bounds[r->scene], r->n, 1).total;
+  if (need == SIZE_MAX)
+    return reject(BBC_EBUDGET, "request's worst-case pair count exceeds one staged launch (" +
+                                   std::to_string(kMaxStagedPairs) + " pairs): split it into smaller requests");
   if (!s->arena.ever_fits(need))
     return reject(BBC_EBUDGET, "request needs " + std::to_string(need) + " bytes of work space, more than the budget");
   {
