@@ -967,12 +967,11 @@ static double uniform(uint64_t seed, uint64_t point, uint32_t tuple) { return un
 // The sampling schemes the paper compares with its multi-sample estimator
 // (Sec. 5.2-5.3 and the sampling-scheme comparison figure), each as a list of
 // selected candidates with the probability weight 1/P of its contribution.
-// Where a floating-point comparison decides which candidate is selected, it
-// is made in FP32, in list order, as the GPU makes it (the paper fixes no
-// precision); weights are FP32 too.
+// Every quantity is FP64, the sums run in list order, and each weight is the
+// candidate's selection probability.
 struct Pick {
   size_t k;  // index into U
-  float P;   // contribution weight is 1 / P
+  double P;  // contribution weight is 1 / P
 };
 
 // Uniform: every candidate of U with the same P = W' / |U|, W' = min(W, |U|)
@@ -980,50 +979,48 @@ struct Pick {
 static std::vector<Pick> pick_uniform(size_t n, double W, uint64_t seed, uint64_t point, const int64_t* U) {
   std::vector<Pick> out;
   if (n == 0) return out;
-  const float P = float(std::min(W, double(n))) / float(n);
+  const double P = std::min(W, double(n)) / double(n);
   for (size_t k = 0; k < n; ++k)
-    if (float(uniform(seed, point, uint32_t(U[k]))) < P) out.push_back({k, P});
+    if (uniform(seed, point, uint32_t(U[k])) < P) out.push_back({k, P});
   return out;
 }
 
 // One-sample estimator repeated W times (Sec. 5.2): W independent draws with
-// P1(T) = E~_T / sum E~ over the finite bounds (FP32 prefix sums in list
-// order; draw j selects the first candidate whose running sum exceeds
-// r_j * sum), and ⟨E⟩ = (1/W) sum_j E(T_j) / P1(T_j).  A candidate drawn c
-// times enters once with weight c / (W P1).  Reading: candidates with an
-// infinite bound have no finite P1; each is evaluated once with P = 1.
-// Candidates with E~ = 0 are never drawn (their E(T) is 0).
+// P1(T) = E~_T / sum E~ over the finite bounds, by inversion of the running
+// sums in list order (draw j selects the first candidate whose running sum
+// exceeds r_j times the total), and <E> = (1/W) sum_j E(T_j) / P1(T_j).  A
+// candidate drawn c times enters once with weight c / (W P1).  Reading:
+// candidates with an infinite bound have no finite P1; each is evaluated once
+// with P = 1.  Candidates with E~ = 0 are never drawn (their E(T) is 0).
 static std::vector<Pick> pick_one_sample(const std::vector<double>& Et, int W, uint64_t seed, uint64_t point) {
   const size_t n = Et.size();
   std::vector<Pick> out;
-  std::vector<float> Ef(n, 0.f), C(n, 0.f);
-  float S = 0.f;
+  std::vector<double> C(n, 0.0);
+  double S = 0.0;
+  size_t last = 0;
   for (size_t k = 0; k < n; ++k) {
     if (std::isinf(Et[k])) {
-      out.push_back({k, 1.f});
+      out.push_back({k, 1.0});
     } else if (Et[k] > 0.0) {
-      Ef[k] = float(Et[k]);
-      S = S + Ef[k];
+      S += Et[k];
+      last = k;
     }
     C[k] = S;
   }
-  if (!(S > 0.f)) return out;
+  if (!(S > 0.0)) return out;
   std::vector<int> cnt(n, 0);
-  size_t last = 0;
-  for (size_t k = 0; k < n; ++k)
-    if (Ef[k] > 0.f) last = k;
   for (int j = 0; j < W; ++j) {
-    const float t = float(uniform_stream(seed, point, uint32_t(j), 1u)) * S;
-    size_t sel = last;  // t can round up to the total
+    const double t = uniform_stream(seed, point, uint32_t(j), 1u) * S;
+    size_t sel = last;
     for (size_t k = 0; k < n; ++k)
-      if (Ef[k] > 0.f && t < C[k]) {
+      if (std::isfinite(Et[k]) && Et[k] > 0.0 && t < C[k]) {
         sel = k;
         break;
       }
     ++cnt[sel];
   }
   for (size_t k = 0; k < n; ++k)
-    if (cnt[k]) out.push_back({k, float(W) * (Ef[k] / S) / float(cnt[k])});
+    if (cnt[k]) out.push_back({k, double(W) * (Et[k] / S) / double(cnt[k])});
   std::sort(out.begin(), out.end(), [](const Pick& a, const Pick& b) { return a.k < b.k; });
   return out;
 }
@@ -1033,32 +1030,85 @@ static std::vector<Pick> pick_one_sample(const std::vector<double>& Et, int W, u
 // sample per bin.  Reading: next-fit packing (a candidate that does not fit
 // the open bin closes it and opens the next), which is the greedy rule with
 // O(|U|) time and approximation ratio 2 that the text states.  Candidate k
-// of bin b owns [o_k, min(o_k + P_k, 1)) of that bin (FP32 running sum) and
-// is selected when the bin's draw r_b falls there; its weight is the length
-// of that interval, its selection probability, and at most one candidate per
-// bin is selected.  Probabilities that sum to exactly 1 (as the bound-optimal
-// ones often do) land on 1 only up to rounding, so a bin accepts a candidate
-// while the sum stays within 2^-20 of 1, and the part above 1 is cut.
-constexpr float kBinSlack = 1.0f / 1048576.0f;
+// of bin b owns [o_k, min(o_k + P_k, 1)) of that bin and is selected when the
+// bin's draw r_b falls there; its weight is the length of that interval, its
+// selection probability, and at most one candidate per bin is selected.
+// The bound-optimal P sum to whole numbers in exact arithmetic, which their
+// FP64 values reach only up to rounding, so "fits" means a running sum of at
+// most 1 + 2^-40 (the part above 1 is cut), and a candidate whose interval
+// would be empty (a full bin, or a P below the rounding of the sum) opens a
+// new bin instead, so every candidate with P > 0 can be selected.
+constexpr double kBinSlack = 1.0 / 1099511627776.0;  // 2^-40
+static bool bin_fits(double fill, double p) { return fill + p <= 1.0 + kBinSlack && std::min(fill + p, 1.0) > fill; }
 static std::vector<Pick> pick_bins(const std::vector<double>& P, uint64_t seed, uint64_t point) {
   std::vector<Pick> out;
   uint32_t b = 0;
-  float fill = 0.f;
-  float r = float(uniform_stream(seed, point, 0u, 2u));
+  double fill = 0.0;
+  double r = uniform_stream(seed, point, 0u, 2u);
   for (size_t k = 0; k < P.size(); ++k) {
-    const float p = float(P[k]);
-    if (!(p > 0.f)) continue;
-    if (fill + p > 1.f + kBinSlack) {
+    const double p = P[k];
+    if (!(p > 0.0)) continue;
+    if (!bin_fits(fill, p)) {
       ++b;
-      fill = 0.f;
-      r = float(uniform_stream(seed, point, b, 2u));
+      fill = 0.0;
+      r = uniform_stream(seed, point, b, 2u);
     }
-    const float lo = fill;
-    fill = fill + p;
-    const float hi = std::min(fill, 1.f);
+    const double lo = fill;
+    fill += p;
+    const double hi = std::min(fill, 1.0);
     if (r >= lo && r < hi) out.push_back({k, hi - lo});
   }
   return out;
+}
+
+// Smallest distance between a quantity that decides a selection and its
+// threshold, over the decisions one point's sampler takes (Alg. 1 and
+// uniform: |r - P|; one-sample: |r S - C_k| / S over the running sums C_k;
+// bins: |fill + P - 1| of every packing test and |r - o|, |r - o - P| of
+// every interval).  Selections taken in another precision can differ only
+// where this margin is below that precision's rounding.
+static double sample_margin(const std::vector<double>& Et, const int64_t* U, double W, uint64_t seed,
+                            uint64_t point, int sampler) {
+  const size_t n = Et.size();
+  double m = INFINITY;
+  std::vector<double> P(n, 1.0);
+  probabilities(Et.data(), int64_t(n), W, P.data());
+  if (sampler == 0 || sampler == 1) {
+    const double Pu = n ? std::min(W, double(n)) / double(n) : 0.0;
+    for (size_t k = 0; k < n; ++k) {
+      const double p = sampler == 1 ? Pu : P[k];
+      if (p > 0.0 && p < 1.0) m = std::min(m, std::fabs(uniform(seed, point, uint32_t(U[k])) - p));
+    }
+  } else if (sampler == 2) {
+    double S = 0.0;
+    std::vector<double> C;
+    for (size_t k = 0; k < n; ++k)
+      if (std::isfinite(Et[k]) && Et[k] > 0.0) {
+        S += Et[k];
+        C.push_back(S);
+      }
+    if (S > 0.0)
+      for (int j = 0; j < int(W); ++j) {
+        const double t = uniform_stream(seed, point, uint32_t(j), 1u) * S;
+        for (double c : C) m = std::min(m, std::fabs(t - c) / S);
+      }
+  } else {
+    uint32_t b = 0;
+    double fill = 0.0, r = uniform_stream(seed, point, 0u, 2u);
+    for (size_t k = 0; k < n; ++k) {
+      const double p = P[k];
+      if (!(p > 0.0)) continue;
+      m = std::min(m, std::fabs(fill + p - 1.0));
+      if (!bin_fits(fill, p)) {
+        ++b;
+        fill = 0.0;
+        r = uniform_stream(seed, point, b, 2u);
+      }
+      m = std::min(m, std::min(std::fabs(r - fill), std::fabs(r - std::min(fill + p, 1.0))));
+      fill += p;
+    }
+  }
+  return m;
 }
 
 // ---------------------------------------------------------------- roots
@@ -1319,7 +1369,7 @@ int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t se
       for (size_t k = 0; k < U.size(); ++k) {
         if (P[k] > 0.0) mu2 += Et[k] * Et[k] / P[k];
         const double r = uniform(seed, uint64_t(i), uint32_t(U[k]));
-        if (r < P[k]) S.push_back({k, float(0)});
+        if (r < P[k]) S.push_back({k, P[k]});
       }
     }
     double E = 0.0;
@@ -1334,7 +1384,7 @@ int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t se
       double ET = 0.0;
       for (const RootHit& rh : roots) ET += rh.Ek;
       nroots += int64_t(roots.size());
-      E += sampler == 0 ? ET / P[k] : ET / double(pk.P);
+      E += sampler == 0 ? ET / P[k] : ET / pk.P;
     }
     E_out[i] = E;
     if (st) {
@@ -1419,13 +1469,19 @@ int64_t orc_sample(const double* Et, const int64_t* U, int64_t n, double W, uint
     S = pick_bins(P, seed, point);
   } else {
     for (int64_t k = 0; k < n; ++k)
-      if (uniform(seed, point, uint32_t(U[k])) < P[size_t(k)]) S.push_back({size_t(k), float(P[size_t(k)])});
+      if (uniform(seed, point, uint32_t(U[k])) < P[size_t(k)]) S.push_back({size_t(k), P[size_t(k)]});
   }
   for (size_t j = 0; j < S.size() && int64_t(j) < cap; ++j) {
     k_out[j] = int64_t(S[j].k);
-    P_out[j] = sampler == 0 ? P[S[j].k] : double(S[j].P);
+    P_out[j] = S[j].P;
   }
   return int64_t(S.size());
+}
+
+double orc_sample_margin(const double* Et, const int64_t* U, int64_t n, double W, uint64_t seed, uint64_t point,
+                         int sampler) {
+  if ((!Et && n) || (!U && n) || n < 0 || !(W >= 1.0) || sampler < 0 || sampler > 3) return -1.0;
+  return sample_margin(std::vector<double>(Et, Et + n), U, W, seed, point, sampler);
 }
 
 void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox(ctr, key, out); }

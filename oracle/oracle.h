@@ -118,6 +118,12 @@ int64_t orc_tuple_roots_leaves(const void* h, int64_t tuple, const double* x, do
 int64_t orc_sample(const double* Et, const int64_t* U, int64_t n, double W, uint64_t seed, uint64_t point,
                    int sampler, int64_t* k_out, double* P_out, int64_t cap);
 
+/* Smallest distance between a decision quantity of that selection and its
+ * threshold (|r - P|; |r S - C_k| / S for the one-sample running sums; |fill +
+ * P - 1| and the interval ends for the bins).  Negative on bad arguments. */
+double orc_sample_margin(const double* Et, const int64_t* U, int64_t n, double W, uint64_t seed, uint64_t point,
+                         int sampler);
+
 /* Bound-optimal selection probabilities for a candidate list with bounds Et[n]
  * and expected sample count W (Sec. 5.4 with the water-filling solve of gamma). */
 int orc_probabilities(const double* Et, int64_t n, double W, double* P);

@@ -81,6 +81,7 @@ def _declare(L):
         "orc_tuple_roots_leaves": (i64, [vp, i64, vp, vp, i64]),
         "orc_probabilities": (C.c_int, [vp, i64, d, vp]),
         "orc_sample": (i64, [vp, vp, i64, d, u64, u64, C.c_int, vp, vp, i64]),
+        "orc_sample_margin": (d, [vp, vp, i64, d, u64, u64, C.c_int]),
         "orc_philox4x32_10": (None, [vp, vp, vp]),
         "orc_uniform": (d, [u64, u64, C.c_uint32]),
         "orc_bern_mul": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -278,6 +279,17 @@ def sample(Et, W, seed, point, sampler, tuples=None):
     m = lib().orc_sample(_ptr(e), _ptr(U), n, float(W), int(seed), int(point), int(sampler), _ptr(k), _ptr(P), cap)
     assert m >= 0
     return k[:m].copy(), P[:m].copy()
+
+
+def sample_margin(Et, W, seed, point, sampler, tuples=None):
+    """Smallest distance between a decision quantity of one list's selection
+    and its threshold (FP64)."""
+    e = _f64(Et)
+    n = e.size
+    U = np.ascontiguousarray(np.arange(n, dtype=np.int64) if tuples is None else np.asarray(tuples, np.int64))
+    m = lib().orc_sample_margin(_ptr(e), _ptr(U), n, float(W), int(seed), int(point), int(sampler))
+    assert m >= 0
+    return m
 
 
 def philox4x32_10(ctr, key):

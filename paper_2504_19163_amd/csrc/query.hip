@@ -628,7 +628,10 @@ __device__ void point_selection(const QueryArgs& a, const StagedArgs& s, int64_t
       for (uint32_t q = 0; q < cnt; ++q) {
         const float pq = __shfl(p, int(q), BBC_WAVE);
         if (!(pq > 0.f)) continue;
-        if (fill + pq > 1.f + kBinSlack) {
+        // a candidate that would overflow the bin, or whose interval would
+        // be empty (a full bin, or pq below the rounding of the sum), opens
+        // the next bin, so every candidate with pq > 0 can be selected
+        if (!(fill + pq <= 1.f + kBinSlack && fminf(fill + pq, 1.f) > fill)) {
           ++bin;
           fill = 0.f;
           r = sample_stream(pr.seed, pr.key, bin, 2u);

@@ -2,7 +2,14 @@
 estimator, the bin-packed multi-sample estimator; staged form) against the
 FP64 oracle on the same seeded inputs: candidate counts, selected counts,
 roots and estimates per shading point, and the variance-bound statistic for
-the bins.  Selection decisions are made in FP32 in list order on both sides."""
+the bins.
+
+The kernel takes its selection decisions in FP32 (probabilities, running
+sums, bin fills), the oracle in FP64.  A point's selections may therefore
+differ only where one of its decision quantities lies within 1e-6 of its
+threshold in the oracle's FP64 arithmetic (orc_sample_margin); such points
+are counted and bounded, and every other point must agree exactly in its
+selections and to 1e-5 in its estimate."""
 import numpy as np
 import pytest
 
@@ -42,22 +49,41 @@ def built(bbc, orc):
 SAMPLERS = {"uniform": (32, 4), "one_sample": (64, 8), "bins": (96, 12)}
 
 
+MARGIN = 1e-6
+
+
+def _point_list(orc, sc, Ob, x):
+    """The oracle's candidate list of the cell holding receiver point x."""
+    q0, f1, f2 = (np.asarray(sc[k], np.float64) for k in ("q0", "f1", "f2"))
+    A = np.stack([f1, f2], axis=1)
+    uv = np.linalg.lstsq(A, x - q0, rcond=None)[0]
+    G = Ob.params["grid_res"]
+    cu, cv = (min(G - 1, max(0, int(np.floor(c * G)))) for c in uv)
+    return Ob.cell_list(cu, cv)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("sampler", list(SAMPLERS))
 @pytest.mark.parametrize("W", [4, 16])
-def test_sampler_matches_oracle(bbc, built, name, sampler, W):
+def test_sampler_matches_oracle(bbc, orc, built, name, sampler, W):
     sc, B, Ob, pts = built[name]
     gmode, omode = SAMPLERS[sampler]
     E, st = B.query(torch.as_tensor(pts, device="cuda"), W, 5, mode=bbc.QUERY_STAGED | gmode, stats=True)
     E = E.cpu().numpy().astype(np.float64)
     st = st.cpu().numpy()
     OE, ost = Ob.query(pts, W, 5, mode=omode)
-    print(name, sampler, W, "selected", int(st[:, 1].sum()), "roots", int(st[:, 2].sum()), flush=True)
     assert st[:, 1].sum() > 0
     assert np.array_equal(st[:, 0], ost[:, 0])  # |U|
-    assert np.array_equal(st[:, 1], ost[:, 1])  # |S|: the same selections
-    assert np.array_equal(st[:, 2], ost[:, 2])  # roots
-    np.testing.assert_allclose(E, OE, rtol=EST_TOL, atol=1e-12)
+    same = (st[:, 1] == ost[:, 1]) & (st[:, 2] == ost[:, 2]) & np.isclose(E, OE, rtol=EST_TOL, atol=1e-12)
+    flips = np.flatnonzero(~same)
+    for i in flips:  # selections taken in FP32 may differ only at a near-threshold FP64 decision
+        U, Et = _point_list(orc, sc, Ob, pts[:, i].astype(np.float64))
+        m = orc.sample_margin(Et, W, 5, int(i), omode // 4, tuples=U)
+        assert m < MARGIN, (i, m, st[i], ost[i], E[i], OE[i])
+    print(name, sampler, W, "selected", int(st[:, 1].sum()), "roots", int(st[:, 2].sum()), "near-threshold flips",
+          len(flips), "of", pts.shape[1], flush=True)
+    assert len(flips) <= max(2, pts.shape[1] // 200)
+    np.testing.assert_allclose(E[same], OE[same], rtol=EST_TOL, atol=1e-12)
     if sampler == "bins":
         fin = np.isfinite(ost[:, 3])
         np.testing.assert_allclose(st[fin, 3], ost[fin, 3], rtol=1e-5)

@@ -83,3 +83,61 @@ def test_containment_refraction(orc, eta):
     b = orc.OracleBuild(osc, dict(max_depth=3))
     n_paths, _ = _check_containment(orc, osc, b, n=15)
     assert n_paths > 500
+
+
+def _small_box_ratios(orc, osc, build, divs=(32, 64), n_max=40):
+    """For leaves with a finite bound around an admissible centre: on boxes of
+    half-width w/d around that centre, E_lo / min E_k, E_hi / max E_k and
+    (E_hi - E_lo) / (max - min) over a 9 x 9 sample of the box."""
+    L = build.leaves()
+    rows = []
+    for k in np.nonzero(np.isfinite(L["E"][:, 1]))[0]:
+        t = L["tuple"][k]
+        u0, u1, v0, v1 = L["box"][k]
+        uc, vc = 0.5 * (u0 + u1), 0.5 * (v0 + v1)
+        if not orc.eval_path(osc, t, uc, vc)["admissible"]:
+            continue
+        res = []
+        for d in divs:
+            h = (u1 - u0) / d
+            bb = orc.box_bound(osc, t, [uc - h, uc + h, vc - h, vc + h])
+            if not (bb["live"] and np.isfinite(bb["E"][1])):
+                break
+            E = [orc.eval_path(osc, t, u, v) for u in np.linspace(uc - h, uc + h, 9)
+                 for v in np.linspace(vc - h, vc + h, 9)]
+            if not all(e["admissible"] for e in E):
+                break
+            E = np.array([e["Ek"] for e in E])
+            res.append((bb["E"][0] / E.min(), bb["E"][1] / E.max(), (bb["E"][1] - bb["E"][0]) / (E.max() - E.min())))
+        if len(res) == len(divs):
+            rows.append(res)
+        if len(rows) >= n_max:
+            break
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("case", ["reflection", "refraction"])
+def test_irradiance_bound_is_tight_on_small_boxes(orc, case):
+    """The explicit irradiance bound (Sec. 4.4, Eq. eq_irr_term3a with the
+    factor-wise bound of |n_g.d0| / |d0|^3) on small boxes around admissible
+    paths: it contains the sampled E_k, its ends sit within 1 % of the
+    sampled extremes at half-width w/32, its width is within a small factor
+    of the sampled range, and its excess over the sampled extremes halves
+    (at least) when the box halves -- the product of the factors' ranges
+    converges linearly, each factor's Bernstein range quadratically (Sec.
+    4.1).  A lower end collapsing to 0, an extra factor on the upper end or a
+    wrong term in det M or Q^3 fails one of these."""
+    if case == "reflection":
+        sc, params, wmax = S.heightfield_mirror(16), dict(max_depth=4), 1.5
+    else:
+        sc, params, wmax = S.water_surface(m=8, amp_scale=0.04), dict(max_depth=4), 2.5
+    osc = orc.OracleScene(sc)
+    rows = _small_box_ratios(orc, osc, orc.OracleBuild(osc, params))
+    assert len(rows) >= 20
+    lo, hi, width = rows[:, :, 0], rows[:, :, 1], rows[:, :, 2]
+    assert np.all(lo <= 1 + 1e-9) and np.all(hi >= 1 - 1e-9)  # containment
+    assert lo[:, 0].min() >= 0.99 and hi[:, 0].max() <= 1.01
+    assert np.all(width <= wmax)
+    shrink_hi = (hi[:, 0] - 1) / np.maximum(hi[:, 1] - 1, 1e-300)
+    shrink_lo = (1 - lo[:, 0]) / np.maximum(1 - lo[:, 1], 1e-300)
+    assert np.median(shrink_hi) >= 1.7 and np.median(shrink_lo) >= 1.7
