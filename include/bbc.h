@@ -250,6 +250,24 @@ bbc_status bbc_query_irradiance_ex(const bbc_bounds* b, const float* points_dev,
 /* stats_dev (nullable) [n][4] FP32: |U|, |S|, roots, sum_U E~^2/P per point
  * (the last is 0 for the uniform and one-sample schemes). */
 
+/* The staged query for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and results as bbc_query_irradiance_ex with
+ * stats_host = NULL; `mode` must be BBC_QUERY_STAGED, optionally or-ed with
+ * BBC_QUERY_EXHAUSTIVE or one sampler.  Results are bit-identical to that
+ * call's.  The work space is a 64 MiB device array inside the library (one
+ * per GPU, held until the process ends); the points run in consecutive
+ * slices of as many points as it holds at the worst case (every candidate of
+ * the fullest grid cell selected).  The call allocates nothing and calls no
+ * allocating routine.  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, other host threads) race, so the
+ * caller orders them.  EBUDGET when one point's worst case exceeds the array
+ * (a cell of more than about 3 million candidates); EINVAL as
+ * bbc_query_irradiance_ex, or when the current device is not the handle's. */
+bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points_dev, int64_t n, int32_t spp,
+                                        uint64_t seed, int64_t point_index_base, int32_t mode, float* out_E_dev,
+                                        float* stats_dev, void* stream);
+
 /* Launch-shape knobs (chosen by the autotuner; results never depend on them):
  *  BBC_TUNE_QUERY_WAVES        fused query register budget: 2 (256 VGPRs) or 4 (128) waves per SIMD
  *  BBC_TUNE_QUERY_GRID         fused query persistent workgroups (1..2^20)

@@ -27,6 +27,7 @@ EXPORTS = [
     "bbc_export_grid", "bbc_query_irradiance", "bbc_query_irradiance_ex", "bbc_set_tuning", "bbc_get_tuning",
     "bbc_query_kernel_ms", "bbc_last_error", "bbc_server_create", "bbc_server_submit", "bbc_server_poll",
     "bbc_server_wait", "bbc_server_resume", "bbc_server_stats", "bbc_server_destroy",
+    "bbc_query_irradiance_noalloc",
 ]
 SERVER_PAUSED = 1
 TUNE_QUERY_WAVES, TUNE_QUERY_GRID, TUNE_BUILD_GRID_PER_CU, TUNE_QUERY_TILE, TUNE_TIMING = 1, 2, 3, 4, 5
@@ -121,6 +122,7 @@ def lib():
             "bbc_export_grid": [vp, vp, vp, vp],
             "bbc_query_irradiance": [vp, vp, i64, i32, u64, vp, vp, vp],
             "bbc_query_irradiance_ex": [vp, vp, i64, i32, u64, i64, i32, vp, vp, vp, vp],
+            "bbc_query_irradiance_noalloc": [vp, vp, i64, i32, u64, i64, i32, vp, vp, vp],
             "bbc_set_tuning": [vp, i32, i64],
             "bbc_get_tuning": [vp, i32, vp],
             "bbc_query_kernel_ms": [vp, vp],
@@ -310,6 +312,25 @@ class Bounds:
                "bbc_query_irradiance_ex")
         if host_stats:
             return out, st, {k: getattr(hs, k) for k, _ in QueryStats._fields_}
+        return out, st
+
+
+    def query_noalloc(self, points, spp, seed, mode=QUERY_STAGED, out=None, stats=False, point_index_base=0,
+                      stream=None):
+        """The staged query over the library's own device work space
+        (bbc_query_irradiance_noalloc); `out` and the stats array are
+        allocated here when not given."""
+        import torch
+        assert points.is_cuda and points.dtype == torch.float32 and points.dim() == 2 and points.shape[0] == 3
+        points = points.contiguous()
+        n = points.shape[1]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=points.device)
+        st = torch.zeros((n, 4), dtype=torch.float32, device=points.device) if stats else None
+        _check(lib().bbc_query_irradiance_noalloc(self.h, points.data_ptr(), n, int(spp), int(seed),
+                                                  int(point_index_base), int(mode), out.data_ptr(),
+                                                  st.data_ptr() if st is not None else None, _stream_handle(stream)),
+               "bbc_query_irradiance_noalloc")
         return out, st
 
 

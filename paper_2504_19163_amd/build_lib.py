@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbbc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "build.hip", "record.hip", "query.hip", "serve.hip"]
+SOURCES = ["api.hip", "build.hip", "record.hip", "query.hip", "serve.hip", "noalloc.hip"]
 ARCH = os.environ.get("BBC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -32,7 +32,7 @@ def _compile(src):
 def build(verbose=False):
     """Compile every HIP source for gfx950 and link libbbc.so (always rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
