@@ -689,6 +689,7 @@ struct Build {
   std::vector<Leaf> leaves;
   std::vector<int64_t> leaf_begin;  // per tuple, into leaves (size n_tuples + 1)
   std::vector<std::map<int64_t, double>> cells;  // per grid cell: tuple -> E~
+  std::map<int64_t, double> cover;               // cover-all list: tuple -> largest E_hi of its leaves
   int64_t boxes = 0;
   const orc_scene* scene = nullptr;  // borrowed
   // deep copies so the build owns its geometry
@@ -845,10 +846,33 @@ static Build* build_all(const orc_scene* s, const orc_params* p, int n_threads) 
   B->leaf_begin[T] = int64_t(B->leaves.size());
   // Bound storage (Sec. 6.1): splat each leaf's irradiance bound into every grid
   // cell its closed position bound touches; per (cell, tuple) keep the maximum
-  // (Eq. eq_pertuple_b with m = 1).
+  // (Eq. eq_pertuple_b with m = 1).  A tuple whose leaves would write at least
+  // cover_frac * G^2 (leaf, cell) records (universal and very wide position
+  // bounds) is stored once instead, in the cover-all list that every shading
+  // point reads beside its cell, with the largest E_hi of all its leaves: a
+  // larger per-tuple bound than its cells would hold, so still conservative.
   const int G = p->grid_res;
   B->cells.assign(size_t(G) * G, {});
+  std::vector<char> in_cover(size_t(T), 0);
+  if (p->cover_frac > 0.0) {
+    const double thr = p->cover_frac * double(G) * double(G);
+    for (int64_t t = 0; t < T; ++t) {
+      int64_t cells = 0;
+      double emax = 0.0;
+      for (int64_t k = B->leaf_begin[t]; k < B->leaf_begin[t + 1]; ++k) {
+        const Leaf& l = B->leaves[size_t(k)];
+        cells += int64_t(cell_of(l.uk[1], G) - cell_of(l.uk[0], G) + 1) *
+                 int64_t(cell_of(l.uk[3], G) - cell_of(l.uk[2], G) + 1);
+        emax = std::max(emax, l.E[1]);
+      }
+      if (cells > 0 && double(cells) >= thr) {
+        in_cover[size_t(t)] = 1;
+        B->cover.emplace(t, emax);
+      }
+    }
+  }
   for (const Leaf& l : B->leaves) {
+    if (in_cover[size_t(l.tuple)]) continue;
     const int cu0 = cell_of(l.uk[0], G), cu1 = cell_of(l.uk[1], G);
     const int cv0 = cell_of(l.uk[2], G), cv1 = cell_of(l.uk[3], G);
     for (int cu = cu0; cu <= cu1; ++cu)
@@ -1251,7 +1275,7 @@ int orc_box_bound_flags(const orc_scene* s, int64_t tuple, const double* box, in
 }
 
 void* orc_build(const orc_scene* s, const orc_params* p, int n_threads) {
-  if (!s || !p || s->chain < 0 || s->chain > 2 || p->grid_res < 1) return nullptr;
+  if (!s || !p || s->chain < 0 || s->chain > 2 || p->grid_res < 1 || !(p->cover_frac >= 0.0)) return nullptr;
   if (s->chain == 2 && (!s->pos2 || !s->nrm2 || s->n_tri2 < 1)) return nullptr;
   if (s->eedge && s->chain != 0) return nullptr;  // area lights: one reflection only
   return build_all(s, p, n_threads);
@@ -1298,6 +1322,7 @@ int orc_build_stats(const void* h, double* st) {
   const Build* B = static_cast<const Build*>(h);
   int64_t entries = 0, inf = 0, uni = 0, maxl = 0;
   for (const auto& m : B->cells) entries += int64_t(m.size());
+  entries += int64_t(B->cover.size());
   for (const Leaf& l : B->leaves) {
     inf += std::isinf(l.E[1]) ? 1 : 0;
     uni += l.universal ? 1 : 0;
@@ -1311,7 +1336,22 @@ int orc_build_stats(const void* h, double* st) {
   st[5] = double(inf);
   st[6] = double(uni);
   st[7] = double(maxl);
+  st[8] = double(B->cover.size());
   return 0;
+}
+
+int64_t orc_cover_list(const void* h, int64_t* tuples, double* Et, int64_t cap) {
+  const Build* B = static_cast<const Build*>(h);
+  if (!B) return -1;
+  int64_t k = 0;
+  for (const auto& kv : B->cover) {
+    if (k < cap) {
+      tuples[k] = kv.first;
+      Et[k] = kv.second;
+    }
+    ++k;
+  }
+  return k;
 }
 
 int64_t orc_cell_list(const void* h, int32_t cu, int32_t cv, int64_t* tuples, double* Et, int64_t cap) {
@@ -1346,10 +1386,15 @@ int orc_query(const void* h, const double* pts, int64_t n, double W, uint64_t se
     if (st) st[0] = st[1] = st[2] = st[3] = 0.0;
     E_out[i] = 0.0;
     if (!receiver_coords(ref, x, &us, &vs)) return;
+    // U: the cell's list, then the cover-all list (each ascending by tuple)
     const auto& m = B->cells[size_t(cell_of(us, G)) * G + cell_of(vs, G)];
     std::vector<int64_t> U;
     std::vector<double> Et;
     for (const auto& kv : m) {
+      U.push_back(kv.first);
+      Et.push_back(kv.second);
+    }
+    for (const auto& kv : B->cover) {
       U.push_back(kv.first);
       Et.push_back(kv.second);
     }

@@ -50,6 +50,10 @@ typedef struct {
                           bit 1: no remainder variable (ablation, T only);
                           bit 2: refraction irradiance bound by implicit
                           differentiation (T only) */
+  double cover_frac;   /* a tuple whose leaves' cell rectangles add up to at
+                          least cover_frac * G^2 cells is stored once, in the
+                          cover-all list, with the largest E_hi of its leaves,
+                          instead of in the cells; 0 disables the list */
 } orc_params;
 
 /* Path evaluation at barycentric (u, v) of a tuple.  out[0..9] =
@@ -81,12 +85,16 @@ int orc_get_leaves(const void* h, int64_t* tuple, int32_t* code, double* box, do
 int64_t orc_n_roots(const void* h);
 /* root boxes after domain initialisation: tuple[n], box[n][4] */
 int orc_get_roots(const void* h, int64_t* tuple, double* box);
-/* stats[0..7] = tuples, live tuples, boxes bounded, leaves, grid entries,
- * infinite-bound leaves, universal-position leaves, max leaves of one tuple */
+/* stats[0..8] = tuples, live tuples, boxes bounded, leaves, grid entries
+ * (the cells' entries plus the cover-all list), infinite-bound leaves,
+ * universal-position leaves, max leaves of one tuple, cover-all tuples */
 int orc_build_stats(const void* h, double* stats);
-/* The candidate list U of grid cell (cu, cv): tuples ascending with their
+/* The list stored in grid cell (cu, cv): tuples ascending with their
  * per-tuple bound E~.  Returns the list length (writes at most cap entries). */
 int64_t orc_cell_list(const void* h, int32_t cu, int32_t cv, int64_t* tuples, double* Et, int64_t cap);
+/* The cover-all list: tuples ascending with the largest E_hi of their leaves.
+ * A shading point's candidate list U is its cell's list followed by this one. */
+int64_t orc_cover_list(const void* h, int64_t* tuples, double* Et, int64_t cap);
 
 /* Estimator of Alg. 1 at each shading point (points [3][n]).
  * mode 0: sample with the bound-optimal probabilities, roots by Newton from the

@@ -56,7 +56,7 @@ class Scene(C.Structure):
 class Params(C.Structure):
     _fields_ = [
         ("max_depth", C.c_int32), ("sigma", C.c_double), ("alpha", C.c_double), ("grid_res", C.c_int32),
-        ("init_pieces", C.c_int32), ("init_levels", C.c_int32), ("flags", C.c_int32),
+        ("init_pieces", C.c_int32), ("init_levels", C.c_int32), ("flags", C.c_int32), ("cover_frac", C.c_double),
     ]
 
 
@@ -75,6 +75,7 @@ def _declare(L):
         "orc_get_roots": (C.c_int, [vp, vp, vp]),
         "orc_build_stats": (C.c_int, [vp, vp]),
         "orc_cell_list": (i64, [vp, i32, i32, vp, vp, i64]),
+        "orc_cover_list": (i64, [vp, vp, vp, i64]),
         "orc_query": (C.c_int, [vp, vp, i64, d, u64, C.c_int, vp, vp, C.c_int]),
         "orc_true_irradiance": (C.c_int, [vp, vp, i64, C.c_int, vp, C.c_int]),
         "orc_tuple_roots": (i64, [vp, i64, vp, C.c_int, vp, i64]),
@@ -143,9 +144,10 @@ class OracleScene:
         return C.byref(self.c)
 
 
-def default_params(max_depth=4, sigma=1e-4, alpha=2.0, grid_res=512, init_pieces=100, init_levels=4, flags=0):
+def default_params(max_depth=4, sigma=1e-4, alpha=2.0, grid_res=512, init_pieces=100, init_levels=4, flags=0,
+                   cover_frac=0.5):
     return dict(max_depth=max_depth, sigma=sigma, alpha=alpha, grid_res=grid_res,
-                init_pieces=init_pieces, init_levels=init_levels, flags=flags)
+                init_pieces=init_pieces, init_levels=init_levels, flags=flags, cover_frac=cover_frac)
 
 
 def _params(p):
@@ -210,11 +212,25 @@ class OracleBuild:
         return dict(tuple=tup, box=box)
 
     def stats(self):
-        st = np.zeros(8)
+        st = np.zeros(9)
         lib().orc_build_stats(self.h, _ptr(st))
         keys = ["tuples", "live_tuples", "boxes", "leaves", "grid_entries", "inf_leaves", "universal_leaves",
-                "max_leaves_per_tuple"]
+                "max_leaves_per_tuple", "cover_tuples"]
         return {k: int(v) for k, v in zip(keys, st)}
+
+    def cover_list(self):
+        n = lib().orc_cover_list(self.h, None, None, 0)
+        t = np.zeros(max(n, 1), np.int64)
+        e = np.zeros(max(n, 1))
+        lib().orc_cover_list(self.h, _ptr(t), _ptr(e), n)
+        return t[:n], e[:n]
+
+    def candidates(self, cu, cv):
+        """A shading point's candidate list U in cell (cu, cv): the cell's list,
+        then the cover-all list."""
+        t0, e0 = self.cell_list(cu, cv)
+        t1, e1 = self.cover_list()
+        return np.concatenate([t0, t1]), np.concatenate([e0, e1])
 
     def cell_list(self, cu, cv):
         n = lib().orc_cell_list(self.h, int(cu), int(cv), None, None, 0)

@@ -105,7 +105,7 @@ def test_c_brute_force_roots_are_enumerated(orc, small):
         x = pts[:, i].astype(float)
         u = (x[0] - sc["q0"][0]) / sc["f1"][0]
         v = (x[1] - sc["q0"][1]) / sc["f2"][1]
-        U, Et = b.cell_list(min(G - 1, int(u * G)), min(G - 1, int(v * G)))
+        U, Et = b.candidates(min(G - 1, int(u * G)), min(G - 1, int(v * G)))
         inU = dict(zip(U.tolist(), Et.tolist()))
         for t in range(osc.n_tuples):
             roots = orc.tuple_roots(osc, t, x, lattice=24)
@@ -151,7 +151,7 @@ def test_d_estimator_unbiased_within_3se(orc, small):
         x = pts[:, i].astype(float)
         u = (x[0] - sc["q0"][0]) / sc["f1"][0]
         v = (x[1] - sc["q0"][1]) / sc["f2"][1]
-        U, Et = b.cell_list(min(G - 1, int(u * G)), min(G - 1, int(v * G)))
+        U, Et = b.candidates(min(G - 1, int(u * G)), min(G - 1, int(v * G)))
         if len(U) == 0:
             continue
         P = orc.probabilities(Et, W)

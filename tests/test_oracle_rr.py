@@ -200,7 +200,7 @@ def test_rr_c_every_path_is_in_its_cell_list(orc, walls):
         x = pts[:, i].astype(float)
         u = (x[0] - sc["q0"][0]) / sc["f1"][0]
         v = (x[1] - sc["q0"][1]) / sc["f2"][1]
-        U, _ = b.cell_list(min(G - 1, int(u * G)), min(G - 1, int(v * G)))
+        U, _ = b.candidates(min(G - 1, int(u * G)), min(G - 1, int(v * G)))
         inU = set(U.tolist())
         for t in range(osc.n_tuples):
             roots = orc.tuple_roots(osc, t, x, lattice=12)

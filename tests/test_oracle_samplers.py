@@ -117,7 +117,7 @@ def _per_point_lists(orc, sc, b, pts):
         x = pts[:, i].astype(float)
         u = (x[0] - sc["q0"][0]) / sc["f1"][0]
         v = (x[1] - sc["q0"][1]) / sc["f2"][1]
-        U, Et = b.cell_list(min(G - 1, int(u * G)), min(G - 1, int(v * G)))
+        U, Et = b.candidates(min(G - 1, int(u * G)), min(G - 1, int(v * G)))
         ET = np.array([b.tuple_roots_leaves(t, x)[:, 2].sum() for t in U]) if len(U) else np.zeros(0)
         out.append((U, Et, ET))
     return out
