@@ -100,8 +100,9 @@ typedef struct {
   const float* edges; /* nullable */
 } bbc_emitters;
 
-/* Subdivision controls (Sec. 6.1).  Defaults: max_depth 8, sigma 1e-4,
- * alpha 2 (single scattering), grid_res 512, init_pieces 100, init_levels 4. */
+/* Subdivision and storage controls (Sec. 6.1).  Defaults: max_depth 8,
+ * sigma 1e-4, alpha 2 (single scattering), grid_res 512, init_pieces 100,
+ * init_levels 4, cover_frac 0.5. */
 typedef struct {
   int32_t max_depth;   /* depth cap, counted from the initialised root box */
   float sigma;         /* stop when the clipped position-bound area (in receiver units) < sigma */
@@ -110,6 +111,10 @@ typedef struct {
   int32_t init_pieces; /* domain initialisation keeps at most this many boxes */
   int32_t init_levels; /* and descends at most this many levels */
   int32_t flags;       /* BBC_FLAG_* */
+  float cover_frac;    /* bound storage: a tuple whose leaves' closed cell rectangles add up to at
+                          least cover_frac * grid_res^2 cells is stored once, in a cover-all list
+                          read by every shading point after its cell's list, with the largest E_hi
+                          of its leaves (default 0.5; 0 keeps every tuple in the cells) */
 } bbc_subdiv_params;
 #define BBC_FLAG_FIXED_DEPTH 1  /* only the depth cap stops subdivision (parity mode) */
 #define BBC_FLAG_NO_REMAINDER 2 /* refraction without remainder variables (ablation; bounds may be invalid) */
@@ -151,12 +156,13 @@ typedef struct {
   int64_t n_live_tuples;  /* tuples with a root box after domain initialisation */
   int64_t n_boxes;        /* boxes bounded during subdivision */
   int64_t n_leaves;
-  int64_t n_grid_entries; /* (cell, tuple) records */
+  int64_t n_grid_entries; /* (cell, tuple) records plus the cover-all list's */
   int64_t n_inf_leaves;   /* leaves with an infinite irradiance bound */
   int64_t n_fp64_boxes;   /* boxes re-evaluated in FP64 (sign-uncertain denominators) */
   int64_t device_bytes;   /* device memory held by the handle */
   int32_t grid_res;
   int32_t max_depth_reached;
+  int64_t n_cover_tuples; /* tuples stored in the cover-all list instead of the cells */
 } bbc_bounds_info_t;
 bbc_status bbc_bounds_info(const bbc_bounds* b, bbc_bounds_info_t* out);
 
@@ -194,8 +200,11 @@ bbc_status bbc_bounds_load(const char* path, void* stream, bbc_bounds** out);
  * Leaves are ordered by tuple, then code. */
 bbc_status bbc_export_leaves(const bbc_bounds* b, uint32_t* tuple, uint32_t* code, float* box, float* ukbox, float* E);
 
-/* Copy the receiver grid to host memory: offsets[grid_res^2 + 1], and
- * n_grid_entries entries of (tuple, E~) sorted by tuple within each cell. */
+/* Copy the receiver grid to host memory: offsets[grid_res^2 + 2] and
+ * n_grid_entries entries of (tuple, E~).  Slice c = cu * grid_res + cv
+ * (offsets[c] .. offsets[c + 1]) is cell (cu, cv), sorted by tuple; slice
+ * grid_res^2 is the cover-all list, sorted by tuple.  A shading point's
+ * candidate list U is its cell's slice followed by the cover-all slice. */
 bbc_status bbc_export_grid(const bbc_bounds* b, uint32_t* offsets, uint32_t* tuple, float* Et);
 
 /* Per-query statistics (host struct, summed over the points of a call). */
@@ -268,7 +277,10 @@ bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points
                                         uint64_t seed, int64_t point_index_base, int32_t mode, float* out_E_dev,
                                         float* stats_dev, void* stream);
 
-/* Launch-shape knobs (chosen by the autotuner; results never depend on them):
+/* Launch-shape knobs (results never depend on them; paper_2504_19163_amd/
+ * autotune.py measures the launch-shape ones on a GPU and records its choice
+ * per device and workload in paper_2504_19163_amd/tuning.json, which the
+ * Python binding applies):
  *  BBC_TUNE_QUERY_WAVES        fused query register budget: 2 (256 VGPRs) or 4 (128) waves per SIMD
  *  BBC_TUNE_QUERY_GRID         fused query persistent workgroups (1..2^20)
  *  BBC_TUNE_BUILD_GRID_PER_CU  persistent build kernels: workgroups per compute unit (1..64),
@@ -283,6 +295,15 @@ bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points
  *                              of 64 pairs (1..96, default 96); the pairs whose roots
  *                              do not fit are redone one lane per pair (smaller values
  *                              exercise that path)
+ *  BBC_TUNE_STAGED_PAIRS       staged query and serving batches: worst-case selected pairs
+ *                              of one launch (1..2^28, default 2^28); a larger query or
+ *                              batch runs as consecutive launches over slices of its points
+ *                              (smaller values exercise that path)
+ *  BBC_TUNE_GRAPH              staged query: 1 = capture each call's launches into a HIP
+ *                              graph (the handle's executable graph is updated in place)
+ *                              and replay it on a stream of the handle's own, ordered
+ *                              after the caller's stream; 0 (default) launches directly.
+ *                              Not with BBC_TUNE_TIMING (timed queries launch directly)
  * Applies to later calls on the handle; EINVAL for an unknown knob or value. */
 #define BBC_TUNE_QUERY_WAVES 1
 #define BBC_TUNE_QUERY_GRID 2
@@ -291,14 +312,23 @@ bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points
 #define BBC_TUNE_TIMING 5
 #define BBC_TUNE_NEWTON_STEPS 6
 #define BBC_TUNE_NEWTON_RESULTS 7
+#define BBC_TUNE_STAGED_PAIRS 8
+#define BBC_TUNE_GRAPH 9
 bbc_status bbc_set_tuning(bbc_bounds* b, int32_t knob, int64_t value);
 bbc_status bbc_get_tuning(const bbc_bounds* b, int32_t knob, int64_t* value);
 
 /* Duration in milliseconds of the dominant kernel of the last query on this
- * handle (the fused kernel, or the staged form's Newton kernel), measured with
- * HIP events on the query's stream; waits for that event.  EINVAL unless
- * BBC_TUNE_TIMING is on and a query ran since. */
+ * handle (the fused kernel, or the staged form's Newton kernel summed over the
+ * query's slices), measured with HIP events on the query's stream; waits for
+ * those events.  EINVAL unless BBC_TUNE_TIMING is on and a query ran since. */
 bbc_status bbc_query_kernel_ms(const bbc_bounds* b, float* ms);
+
+/* Duration in milliseconds of the adaptive-subdivision launches of the last
+ * build or rebuild on this handle (the step's dominant build kernel, Sec. 6.1
+ * domain subdivision), measured with HIP events on the build's stream, and the
+ * number of launches (nullable).  Waits for the end event.  EINVAL unless
+ * BBC_TUNE_TIMING was on when the build ran. */
+bbc_status bbc_build_kernel_ms(const bbc_bounds* b, float* ms, int32_t* launches);
 
 /* ------------------------------------------------------------------ serving
  * A continuous-batching server over resident bound hierarchies (one per
@@ -326,6 +356,9 @@ bbc_status bbc_query_kernel_ms(const bbc_bounds* b, float* ms);
 typedef struct bbc_server bbc_server;
 
 #define BBC_SERVER_PAUSED 1 /* create paused: admit nothing until bbc_server_resume */
+/* replay each batch's staged launches as a HIP graph captured on the slot's
+ * stream (one executable graph per slot, updated in place per batch) */
+#define BBC_SERVER_GRAPH 2
 
 typedef struct {
   int64_t hbm_budget_bytes;   /* device arena for batch work space, >= 1 MiB */
@@ -334,7 +367,7 @@ typedef struct {
   int32_t max_batch_requests; /* requests in one batch, 1..65535 */
   int32_t queue_capacity;     /* waiting requests before submit returns BBC_EQUEUE, >= 1 */
   int32_t mode;               /* 0 (sampled, Alg. 1), BBC_QUERY_EXHAUSTIVE or one of the samplers */
-  int32_t flags;              /* BBC_SERVER_PAUSED */
+  int32_t flags;              /* BBC_SERVER_PAUSED | BBC_SERVER_GRAPH */
 } bbc_server_config;
 
 /* One request: n shading points [3][n] and n results, both host or both

@@ -27,11 +27,11 @@ EXPORTS = [
     "bbc_export_grid", "bbc_query_irradiance", "bbc_query_irradiance_ex", "bbc_set_tuning", "bbc_get_tuning",
     "bbc_query_kernel_ms", "bbc_last_error", "bbc_server_create", "bbc_server_submit", "bbc_server_poll",
     "bbc_server_wait", "bbc_server_resume", "bbc_server_stats", "bbc_server_destroy",
-    "bbc_query_irradiance_noalloc",
+    "bbc_query_irradiance_noalloc", "bbc_build_kernel_ms",
 ]
-SERVER_PAUSED = 1
+SERVER_PAUSED, SERVER_GRAPH = 1, 2
 TUNE_QUERY_WAVES, TUNE_QUERY_GRID, TUNE_BUILD_GRID_PER_CU, TUNE_QUERY_TILE, TUNE_TIMING = 1, 2, 3, 4, 5
-TUNE_NEWTON_STEPS, TUNE_NEWTON_RESULTS = 6, 7
+TUNE_NEWTON_STEPS, TUNE_NEWTON_RESULTS, TUNE_STAGED_PAIRS, TUNE_GRAPH = 6, 7, 8, 9
 
 
 class BBCError(RuntimeError):
@@ -56,7 +56,7 @@ class Emitters(C.Structure):
 class SubdivParams(C.Structure):
     _fields_ = [
         ("max_depth", C.c_int32), ("sigma", C.c_float), ("alpha", C.c_float), ("grid_res", C.c_int32),
-        ("init_pieces", C.c_int32), ("init_levels", C.c_int32), ("flags", C.c_int32),
+        ("init_pieces", C.c_int32), ("init_levels", C.c_int32), ("flags", C.c_int32), ("cover_frac", C.c_float),
     ]
 
 
@@ -65,6 +65,7 @@ class BoundsInfo(C.Structure):
         ("n_tuples", C.c_int64), ("n_live_tuples", C.c_int64), ("n_boxes", C.c_int64), ("n_leaves", C.c_int64),
         ("n_grid_entries", C.c_int64), ("n_inf_leaves", C.c_int64), ("n_fp64_boxes", C.c_int64),
         ("device_bytes", C.c_int64), ("grid_res", C.c_int32), ("max_depth_reached", C.c_int32),
+        ("n_cover_tuples", C.c_int64),
     ]
 
 
@@ -126,6 +127,7 @@ def lib():
             "bbc_set_tuning": [vp, i32, i64],
             "bbc_get_tuning": [vp, i32, vp],
             "bbc_query_kernel_ms": [vp, vp],
+            "bbc_build_kernel_ms": [vp, vp, vp],
             "bbc_server_create": [vp, i32, vp, vp],
             "bbc_server_submit": [vp, vp, vp],
             "bbc_server_poll": [vp, u64, vp],
@@ -155,9 +157,10 @@ def _check(st, where):
         raise BBCError(st, where)
 
 
-def default_params(max_depth=8, sigma=1e-4, alpha=2.0, grid_res=512, init_pieces=100, init_levels=4, flags=0):
+def default_params(max_depth=8, sigma=1e-4, alpha=2.0, grid_res=512, init_pieces=100, init_levels=4, flags=0,
+                   cover_frac=0.5):
     return dict(max_depth=max_depth, sigma=sigma, alpha=alpha, grid_res=grid_res, init_pieces=init_pieces,
-                init_levels=init_levels, flags=flags)
+                init_levels=init_levels, flags=flags, cover_frac=cover_frac)
 
 
 def _stream_handle(stream):
@@ -265,6 +268,13 @@ class Bounds:
         _check(lib().bbc_query_kernel_ms(self.h, C.byref(v)), "bbc_query_kernel_ms")
         return v.value
 
+    def build_kernel_ms(self):
+        """(ms, launches) of the subdivision kernels of the last build."""
+        v = C.c_float()
+        n = C.c_int32()
+        _check(lib().bbc_build_kernel_ms(self.h, C.byref(v), C.byref(n)), "bbc_build_kernel_ms")
+        return v.value, n.value
+
     def info(self):
         i = BoundsInfo()
         _check(lib().bbc_bounds_info(self.h, C.byref(i)), "bbc_bounds_info")
@@ -285,9 +295,11 @@ class Bounds:
         return dict(tuple=t.astype(np.int64), code=np.stack([depth, iu, iv], 1), box=box, uk=uk, E=E)
 
     def grid(self):
+        """(offsets [G*G + 2], tuples, E~): slices 0 .. G*G - 1 are the cells,
+        slice G*G the cover-all list."""
         info = self.info()
         G = info["grid_res"]
-        off = np.zeros(G * G + 1, np.uint32)
+        off = np.zeros(G * G + 2, np.uint32)
         t = np.zeros(max(info["n_grid_entries"], 1), np.uint32)
         e = np.zeros(max(info["n_grid_entries"], 1), np.float32)
         _check(lib().bbc_export_grid(self.h, off.ctypes.data, t.ctypes.data, e.ctypes.data), "bbc_export_grid")
@@ -342,11 +354,12 @@ class Server:
     is allocated here and kept alive until wait() returns it."""
 
     def __init__(self, bounds, hbm_budget_bytes=8 << 30, max_inflight=4, max_batch_points=262144,
-                 max_batch_requests=4096, queue_capacity=4096, mode=0, paused=False):
+                 max_batch_requests=4096, queue_capacity=4096, mode=0, paused=False, graph=False):
         self.bounds = list(bounds)  # keeps the handles alive
         arr = (C.c_void_p * len(self.bounds))(*[b.h.value for b in self.bounds])
         cfg = ServerConfig(int(hbm_budget_bytes), int(max_inflight), int(max_batch_points), int(max_batch_requests),
-                           int(queue_capacity), int(mode), SERVER_PAUSED if paused else 0)
+                           int(queue_capacity), int(mode),
+                           (SERVER_PAUSED if paused else 0) | (SERVER_GRAPH if graph else 0))
         h = C.c_void_p()
         _check(lib().bbc_server_create(arr, len(self.bounds), C.byref(cfg), C.byref(h)), "bbc_server_create")
         self.h = h
@@ -431,8 +444,8 @@ TUNING_FILE = os.path.join(HERE, "tuning.json")
 def apply_tuning(bounds, workload_key, path=TUNING_FILE):
     """Apply launch-shape choices recorded for this device and workload in a
     JSON table ({arch: {workload: {knob: value}}}, tuning.json beside this
-    module); returns the chosen entry, or {} when none was recorded.  Results
-    never depend on these knobs."""
+    module, written by autotune.py on the GPU); returns the chosen entry, or {}
+    when none was recorded.  Results never depend on these knobs."""
     import json
     if not os.path.exists(path):
         return {}
@@ -441,7 +454,7 @@ def apply_tuning(bounds, workload_key, path=TUNING_FILE):
     table = json.load(open(path))
     entry = table.get(dev, {}).get(workload_key, {})
     knobs = {"query_waves": TUNE_QUERY_WAVES, "query_tile": TUNE_QUERY_TILE, "query_grid": TUNE_QUERY_GRID,
-             "build_grid_per_cu": TUNE_BUILD_GRID_PER_CU}
+             "build_grid_per_cu": TUNE_BUILD_GRID_PER_CU, "newton_steps": TUNE_NEWTON_STEPS, "graph": TUNE_GRAPH}
     for k, knob in knobs.items():
         if k in entry:
             bounds.set_tuning(knob, entry[k])

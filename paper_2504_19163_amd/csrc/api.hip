@@ -22,6 +22,15 @@ bbc_status hip_fail(hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? BBC_ENOMEM : BBC_EDEVICE;
 }
 
+void release_graph(QueryGraph& g) {
+  if (g.stream) (void)hipStreamSynchronize(g.stream);
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.in) (void)hipEventDestroy(g.in);
+  if (g.out) (void)hipEventDestroy(g.out);
+  if (g.stream) (void)hipStreamDestroy(g.stream);
+  g = QueryGraph{};
+}
+
 static bbc_status invalid(const char* msg) {
   set_error(msg);
   return BBC_EINVAL;
@@ -60,7 +69,7 @@ static void release_all(Bounds* b) {
                    &b->q[1], &b->fq, &b->lt, &b->lc, &b->lu, &b->le, &b->gl_t, &b->gl_c, &b->gl_u, &b->gl_e, &b->st, &b->sc, &b->su, &b->se, &b->tcount,
                    &b->toff, &b->tcur, &b->lrect, &b->lcoarse, &b->ccount, &b->coff, &b->gt, &b->ge,
                    &b->scan_tmp, &b->trec, &b->pos2, &b->nrm2, &b->box2, &b->rowcount, &b->rowoff, &b->tid,
-                   &b->qw_buf, &b->max_cell_dev, &b->qcounters};
+                   &b->qw_buf, &b->max_cell_dev, &b->qcounters, &b->cflag, &b->cpos, &b->cE};
   for (DevBuf* d : all) release(*d);
   b->device_bytes = 0;
 }
@@ -101,6 +110,7 @@ static bbc_status validate(const bbc_scene* sc, const bbc_emitters* em, const bb
   if (p->init_pieces < 1 || p->init_pieces > 256) return invalid("init_pieces must be in [1, 256]");
   if (p->init_levels < 0 || p->init_levels > 12) return invalid("init_levels must be in [0, 12]");
   if (p->flags & ~(BBC_FLAG_FIXED_DEPTH | BBC_FLAG_NO_REMAINDER | BBC_FLAG_IMPLICIT_IRR)) return invalid("unknown flags");
+  if (!(p->cover_frac >= 0.f) || !std::isfinite(p->cover_frac)) return invalid("cover_frac must be finite and >= 0");
   return BBC_OK;
 }
 
@@ -130,7 +140,9 @@ static bbc_status run_build(Bounds* b, hipStream_t s) {
         (e = ensure(b->se, b->leaf_cap * 8, b)) || (e = ensure(b->tcount, b->n_tuples * 4, b)) ||
         (e = ensure(b->toff, (b->n_tuples + 1) * 4, b)) || (e = ensure(b->tcur, b->n_tuples * 4, b)) ||
         (e = ensure(b->lrect, b->leaf_cap * 16, b)) || (e = ensure(b->lcoarse, (b->leaf_cap + 3 * 2048) * 4, b)) || (e = ensure(b->ccount, ncell * 4, b)) ||
-        (e = ensure(b->coff, (ncell + 1) * 4, b)) || (e = ensure(b->gt, b->grid_cap * 4, b)) ||
+        (e = ensure(b->coff, (ncell + 2) * 4, b)) || (e = ensure(b->gt, b->grid_cap * 4, b)) ||
+        (e = ensure(b->cflag, b->n_tuples * 4, b)) || (e = ensure(b->cpos, (b->n_tuples + 1) * 4, b)) ||
+        (e = ensure(b->cE, b->n_tuples * 4, b)) ||
         (e = ensure(b->ge, b->grid_cap * 4, b)) ||
         (e = ensure(b->scan_tmp, scan_tmp_bytes(std::max(ncell, b->n_tuples)) + 64, b)) ||
         (e = ensure(b->trec, size_t(std::max<int64_t>(b->n_tuples, 1)) * b->rec_floats * 4, b)) ||
@@ -243,7 +255,7 @@ static hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 // Layout: FileHeader, then one section per array (u64 byte count, bytes) in
 // the order of bound_sections(), then a u64 FNV-1a hash of every byte before it.
 constexpr char kFileMagic[8] = {'B', 'B', 'C', 'B', 'O', 'U', 'N', 'D'};
-constexpr uint32_t kFileVersion = 1;
+constexpr uint32_t kFileVersion = 2;
 
 struct FileHeader {
   char magic[8];
@@ -282,7 +294,7 @@ static std::vector<Section> bound_sections(Bounds* b, int64_t n_tri, int64_t n_t
                           {&b->sc, nl * 4},
                           {&b->su, nl * 16},
                           {&b->se, nl * 8},
-                          {&b->coff, (G * G + 1) * 4},
+                          {&b->coff, (G * G + 2) * 4},
                           {&b->gt, ne * 4},
                           {&b->ge, ne * 4}};
   v.insert(v.end(), std::begin(rest), std::end(rest));
@@ -325,12 +337,15 @@ static bbc_status check_loaded(const FileHeader& fh, const std::vector<std::vect
     if (depth > uint32_t(kMaxDepth) || iu >> depth || iv >> depth) return invalid("bound file: leaf code out of range");
   }
   int64_t mc = 0;
-  if (coff[0] != 0 || int64_t(coff[nc]) != ne) return invalid("bound file: cell offsets do not span the entries");
-  for (int64_t c = 0; c < nc; ++c) {
+  // cells 0 .. nc-1, then the cover-all list as slice nc
+  if (coff[0] != 0 || int64_t(coff[nc + 1]) != ne) return invalid("bound file: cell offsets do not span the entries");
+  for (int64_t c = 0; c <= nc; ++c) {
     if (coff[c + 1] < coff[c]) return invalid("bound file: cell offsets decrease");
-    mc = std::max<int64_t>(mc, coff[c + 1] - coff[c]);
+    if (c < nc) mc = std::max<int64_t>(mc, coff[c + 1] - coff[c]);
   }
-  if (mc != fh.max_cell) return invalid("bound file: fullest cell differs from the header");
+  if (int64_t(coff[nc + 1] - coff[nc]) != int64_t(fh.host.n_cover))
+    return invalid("bound file: cover-all list length differs from the header");
+  if (mc + int64_t(fh.host.n_cover) != fh.max_cell) return invalid("bound file: fullest cell differs from the header");
   for (int64_t i = 0; i < ne; ++i)
     if (int64_t(gt[i]) >= nt) return invalid("bound file: grid entry names a tuple out of range");
   if (fh.chain == BBC_CHAIN_RR) {
@@ -480,8 +495,10 @@ bbc_status bbc_free_bounds(bbc_bounds* h) {
   Bounds* b = reinterpret_cast<Bounds*>(h);
   (void)hipDeviceSynchronize();
   release_all(b);
-  if (b->ev[0]) (void)hipEventDestroy(b->ev[0]);
-  if (b->ev[1]) (void)hipEventDestroy(b->ev[1]);
+  release_graph(b->qgraph);
+  for (hipEvent_t ev : b->tev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : b->bev)
+    if (ev) (void)hipEventDestroy(ev);
   delete b;
   return BBC_OK;
 }
@@ -586,6 +603,7 @@ bbc_status bbc_bounds_info(const bbc_bounds* h, bbc_bounds_info_t* out) {
   out->device_bytes = b->device_bytes;
   out->grid_res = b->params.grid_res;
   out->max_depth_reached = int32_t(b->host.max_depth);
+  out->n_cover_tuples = b->host.n_cover;
   return BBC_OK;
 }
 
@@ -634,7 +652,7 @@ bbc_status bbc_export_grid(const bbc_bounds* h, uint32_t* offsets, uint32_t* tup
   if (!h) return invalid("null bounds handle");
   const Bounds* b = reinterpret_cast<const Bounds*>(h);
   const int64_t nc = int64_t(b->params.grid_res) * b->params.grid_res;
-  if (offsets) BBC_HIP(hipMemcpy(offsets, b->coff.p, size_t(nc + 1) * 4, hipMemcpyDeviceToHost));
+  if (offsets) BBC_HIP(hipMemcpy(offsets, b->coff.p, size_t(nc + 2) * 4, hipMemcpyDeviceToHost));
   if (tuple && b->n_entries) {
     BBC_HIP(hipMemcpy(tuple, b->gt.p, size_t(b->n_entries) * 4, hipMemcpyDeviceToHost));
     if (b->scene.chain == BBC_CHAIN_RR) {  // report pair numbers, ascending like the indices
@@ -732,9 +750,16 @@ bbc_status bbc_set_tuning(bbc_bounds* h, int32_t knob, int64_t value) {
       return BBC_OK;
     case BBC_TUNE_TIMING:
       if (value != 0 && value != 1) return invalid("timing must be 0 or 1");
-      if (value && !b->ev[0]) {
-        BBC_HIP(hipEventCreate(&b->ev[0]));
-        BBC_HIP(hipEventCreate(&b->ev[1]));
+      if (value && !b->bev[0]) {
+        BBC_HIP(hipEventCreate(&b->bev[0]));
+        BBC_HIP(hipEventCreate(&b->bev[1]));
+      }
+      if (value && b->tev.empty()) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        BBC_HIP(hipEventCreate(&e0));
+        b->tev.push_back(e0);
+        BBC_HIP(hipEventCreate(&e1));
+        b->tev.push_back(e1);
       }
       b->tune.timing = int(value);
       return BBC_OK;
@@ -745,6 +770,14 @@ bbc_status bbc_set_tuning(bbc_bounds* h, int32_t knob, int64_t value) {
     case BBC_TUNE_NEWTON_RESULTS:
       if (value < 1 || value > 96) return invalid("Newton result buffer must be in [1, 96]");
       b->tune.newton_results = int(value);
+      return BBC_OK;
+    case BBC_TUNE_STAGED_PAIRS:
+      if (value < 1 || value > int64_t(kMaxStagedPairs)) return invalid("staged pairs must be in [1, 2^28]");
+      b->tune.staged_pairs = value;
+      return BBC_OK;
+    case BBC_TUNE_GRAPH:
+      if (value != 0 && value != 1) return invalid("graph must be 0 or 1");
+      b->tune.graph = int(value);
       return BBC_OK;
     default:
       return invalid("unknown tuning knob");
@@ -762,6 +795,8 @@ bbc_status bbc_get_tuning(const bbc_bounds* h, int32_t knob, int64_t* value) {
     case BBC_TUNE_TIMING: *value = b->tune.timing; return BBC_OK;
     case BBC_TUNE_NEWTON_STEPS: *value = b->tune.newton_steps; return BBC_OK;
     case BBC_TUNE_NEWTON_RESULTS: *value = b->tune.newton_results; return BBC_OK;
+    case BBC_TUNE_STAGED_PAIRS: *value = b->tune.staged_pairs; return BBC_OK;
+    case BBC_TUNE_GRAPH: *value = b->tune.graph; return BBC_OK;
     default: return invalid("unknown tuning knob");
   }
 }
@@ -769,9 +804,25 @@ bbc_status bbc_get_tuning(const bbc_bounds* h, int32_t knob, int64_t* value) {
 bbc_status bbc_query_kernel_ms(const bbc_bounds* h, float* ms) {
   if (!h || !ms) return invalid("null argument");
   const Bounds* b = reinterpret_cast<const Bounds*>(h);
-  if (!b->tune.timing || !b->ev_recorded) return invalid("no timed query on this handle (enable BBC_TUNE_TIMING)");
-  BBC_HIP(hipEventSynchronize(b->ev[1]));
-  BBC_HIP(hipEventElapsedTime(ms, b->ev[0], b->ev[1]));
+  if (!b->tune.timing || b->tev_used == 0) return invalid("no timed query on this handle (enable BBC_TUNE_TIMING)");
+  float sum = 0.f;
+  for (int k = 0; k < b->tev_used; ++k) {
+    float t = 0.f;
+    BBC_HIP(hipEventSynchronize(b->tev[2 * k + 1]));
+    BBC_HIP(hipEventElapsedTime(&t, b->tev[2 * k], b->tev[2 * k + 1]));
+    sum += t;
+  }
+  *ms = sum;
+  return BBC_OK;
+}
+
+bbc_status bbc_build_kernel_ms(const bbc_bounds* h, float* ms, int32_t* launches) {
+  if (!h || !ms) return invalid("null argument");
+  const Bounds* b = reinterpret_cast<const Bounds*>(h);
+  if (!b->tune.timing || !b->bev_recorded) return invalid("no timed build on this handle (enable BBC_TUNE_TIMING)");
+  BBC_HIP(hipEventSynchronize(b->bev[1]));
+  BBC_HIP(hipEventElapsedTime(ms, b->bev[0], b->bev[1]));
+  if (launches) *launches = b->subdiv_launches;
   return BBC_OK;
 }
 

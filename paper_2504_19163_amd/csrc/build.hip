@@ -834,6 +834,9 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
       hipLaunchKernelGGL(k_init, dim3(g_init), dim3(64), 0, s, a);
     BBC_HIP(hipGetLastError());
   }
+  const bool timed = b->tune.timing && b->bev[0];
+  if (timed) BBC_HIP(hipEventRecord(b->bev[0], s));
+  b->subdiv_launches = a.max_depth + 1;
   for (int d = 0; d <= a.max_depth; ++d) {
     a.qin = static_cast<QItem*>(b->q[d & 1].p);
     a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
@@ -849,6 +852,10 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
     else
       hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, s, a, d);
     BBC_HIP(hipGetLastError());
+  }
+  if (timed) {
+    BBC_HIP(hipEventRecord(b->bev[1], s));
+    b->bev_recorded = true;
   }
   return BBC_OK;
 }

@@ -44,6 +44,7 @@ struct BuildCounters {
   uint32_t n_triples;              // grid entries wanted when they overflowed the capacity
   uint32_t n_entries;              // (cell, tuple) entries of the grid
   uint32_t n_inf;
+  uint32_t n_cover;                // tuples in the cover-all list
   uint32_t qcount[kMaxDepth + 2];  // items at each depth
   uint32_t fcount[kMaxDepth + 2];  // FP64 items at each depth
 };
@@ -71,7 +72,7 @@ struct StagedWork {
   size_t pts = 0, pairs = 0;  // capacities
 };
 
-// Launch-shape knobs chosen by the autotuner (bbc_set_tuning).
+// Launch-shape knobs (bbc_set_tuning; tuning.json written by the package's autotuner).
 struct Tuning {
   int query_waves = 2;        // fused query: minimum waves per SIMD (register budget 256 / 128)
   int query_grid = 256 * 64;  // fused query: persistent workgroups
@@ -80,7 +81,28 @@ struct Tuning {
   int build_grid_per_cu = 0;  // persistent build kernels: workgroups per CU (0: one resident round)
   int newton_steps = 4;       // staged query: FP32 iterations per pooled Newton pass (0: lane per pair)
   int newton_results = 96;    // pooled Newton: accepted roots kept per 64 pairs before pairs are redone
+  int64_t staged_pairs = int64_t(1) << 28;  // worst-case pairs of one staged launch (slices a larger query)
+  int graph = 0;              // staged query: 1 = replay the launches as a HIP graph
 };
+
+// A staged query's launches captured into a HIP graph on a stream of the
+// library's own, and the executable graph updated in place for each call.
+struct QueryGraph {
+  hipStream_t stream = nullptr;  // capture and replay stream (non-blocking, default priority)
+  hipEvent_t in = nullptr, out = nullptr;  // orders the replay after / before the caller's stream
+  hipGraphExec_t exec = nullptr;
+  int64_t launches = 0, instantiations = 0;
+};
+void release_graph(QueryGraph& g);
+// Capture the launches that `enqueue(cs)` makes on stream cs into a graph and
+// update the executable graph *exec with it (instantiated when absent or when
+// the update is refused).
+template <class F>
+bbc_status capture_into(hipStream_t cs, hipGraphExec_t* exec, int64_t* instantiations, F&& enqueue);
+// capture_into on g's stream, then replay g's executable graph there, ordered
+// after the work already on `caller` and before the caller's later work.
+template <class F>
+bbc_status run_as_graph(QueryGraph& g, hipStream_t caller, F&& enqueue);
 
 struct Bounds {
   int device = 0;
@@ -114,8 +136,9 @@ struct Bounds {
   DevBuf lrect;               // cell rectangle, tuple and E_hi of each sorted leaf
   DevBuf lcoarse;             // the rectangle in tiles of 16 cells (padded by two scan steps)
   size_t grid_cap = 0;        // capacity of the grid entry arrays gt / ge
-  DevBuf ccount, coff;        // per-cell counts / offsets [G*G + 1]
+  DevBuf ccount, coff;        // per-cell counts / offsets [G*G + 2]: the last slice is the cover-all list
   DevBuf gt, ge;              // entries: tuple u32, E~ float, sorted by tuple per cell
+  DevBuf cflag, cpos, cE;     // cover-all decision per tuple, its slot (scan), largest E_hi
   DevBuf scan_tmp;
   DevBuf trec;                // packed per-tuple records for the query [n_tuples][32] float
   // host copies of the final counts
@@ -127,8 +150,15 @@ struct Bounds {
   StagedWork qw;
   DevBuf max_cell_dev;
   DevBuf qcounters;           // 8 x u64 query work counters (filled when host stats are requested)
-  hipEvent_t ev[2] = {nullptr, nullptr};  // around the last query's dominant kernel
-  bool ev_recorded = false;
+  // event pairs around the dominant kernel of each launch of the last query
+  // (one pair for the fused form, one per slice for the staged form)
+  std::vector<hipEvent_t> tev;
+  int tev_used = 0;
+  // events around the subdivision launches of the last build (timing on)
+  hipEvent_t bev[2] = {nullptr, nullptr};
+  bool bev_recorded = false;
+  int subdiv_launches = 0;
+  QueryGraph qgraph;          // the staged query as a graph (BBC_TUNE_GRAPH)
 };
 
 // error plumbing
@@ -170,12 +200,67 @@ bbc_status launch_query_staged_in(const Bounds* b, const float* pts, int64_t n, 
 // a larger query runs as consecutive launches over slices of its points.
 constexpr size_t kMaxStagedPairs = size_t(1) << 28;
 size_t staged_pairs(const Bounds* b, int64_t n);
+// Points of one staged launch for a query of n points (at most n).
+int64_t staged_slice(const Bounds* b, int64_t n);
 size_t staged_bytes(int64_t n, size_t pairs);
 void staged_carve(void* base, int64_t n, size_t pairs, StagedWork& w);
 // Staged launch over a batch of requests: point i belongs to reqs[preq[i]].
-// Events (nullable) bracket the Newton kernel.
+// The batch runs in consecutive slices of staged_slice(b, n) points over the
+// work space w, which must hold one slice.  Events (nullable) bracket the
+// Newton kernel of the first slice.
 bbc_status launch_query_batch(const Bounds* b, const float* pts, int64_t n, const uint16_t* preq,
                               const ReqDesc* reqs, int32_t mode, float* out, const StagedWork& w, hipEvent_t ev0,
                               hipEvent_t ev1, hipStream_t s);
+
+template <class F>
+bbc_status capture_into(hipStream_t cs, hipGraphExec_t* exec, int64_t* instantiations, F&& enqueue) {
+  BBC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  const bbc_status e = enqueue(cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t he = hipStreamEndCapture(cs, &graph);
+  if (e || he != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return e ? e : hip_fail(he, "hipStreamEndCapture");
+  }
+  if (*exec) {
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult r = hipGraphExecUpdateSuccess;
+    if (hipGraphExecUpdate(*exec, graph, &bad, &r) != hipSuccess || r != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(*exec);
+      *exec = nullptr;
+    }
+  }
+  hipError_t ie = hipSuccess;
+  if (!*exec) {
+    ie = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    ++*instantiations;
+  }
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    *exec = nullptr;
+    return hip_fail(ie, "hipGraphInstantiate");
+  }
+  return BBC_OK;
+}
+
+template <class F>
+bbc_status run_as_graph(QueryGraph& g, hipStream_t caller, F&& enqueue) {
+  if (!g.stream) {
+    BBC_HIP(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking));
+    BBC_HIP(hipEventCreateWithFlags(&g.in, hipEventDisableTiming));
+    BBC_HIP(hipEventCreateWithFlags(&g.out, hipEventDisableTiming));
+  }
+  bbc_status e = capture_into(g.stream, &g.exec, &g.instantiations, enqueue);
+  if (e) return e;
+  BBC_HIP(hipEventRecord(g.in, caller));
+  BBC_HIP(hipStreamWaitEvent(g.stream, g.in, 0));
+  BBC_HIP(hipGraphLaunch(g.exec, g.stream));
+  BBC_HIP(hipEventRecord(g.out, g.stream));
+  BBC_HIP(hipStreamWaitEvent(caller, g.out, 0));
+  ++g.launches;
+  return BBC_OK;
+}
 
 }  // namespace bbc

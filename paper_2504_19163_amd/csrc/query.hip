@@ -44,6 +44,7 @@ struct QueryArgs {
   // preq[i]; nullable, then every point uses W, seed and base above
   const uint16_t* preq;
   const ReqDesc* reqs;
+  int64_t ioff;  // index of point 0 of this launch inside the batch (a slice of a larger batch)
   // two reflections: the grid holds indices of constructed pairs; the random
   // stream is keyed by the pair number tid[T]
   const uint32_t* tid;
@@ -51,6 +52,23 @@ struct QueryArgs {
 };
 
 __device__ __forceinline__ uint32_t tuple_key(const QueryArgs& a, uint32_t T) { return a.tid ? a.tid[T] : T; }
+
+// A shading point's candidate list U (Sec. 6.1 bound storage): its cell's
+// slice of the grid entries, then the cover-all slice (slice G^2).  Entry j of
+// U is grid entry at(j).
+struct CandList {
+  uint32_t b0, n0, b1, n;
+  __device__ __forceinline__ uint32_t at(uint32_t j) const { return j < n0 ? b0 + j : b1 + (j - n0); }
+};
+__device__ __forceinline__ CandList cand_list(const QueryArgs& a, uint32_t cell) {
+  const uint32_t G2 = uint32_t(a.G) * uint32_t(a.G);
+  CandList c;
+  c.b0 = a.coff[cell];
+  c.n0 = a.coff[cell + 1] - c.b0;
+  c.b1 = a.coff[G2];
+  c.n = c.n0 + (a.coff[G2 + 1] - c.b1);
+  return c;
+}
 
 struct PointReq {
   float W;
@@ -63,7 +81,7 @@ struct PointReq {
 __device__ __forceinline__ PointReq point_req(const QueryArgs& a, int64_t i) {
   if (!a.preq) return PointReq{a.W, a.seed, uint64_t(a.base + i)};
   const ReqDesc& r = a.reqs[a.preq[i]];
-  return PointReq{r.W, r.seed, uint64_t(r.base + (i - r.start))};
+  return PointReq{r.W, r.seed, uint64_t(r.base + (i + a.ioff - r.start))};
 }
 
 // Per-lane work counters, summed per wave into the optional device counters.
@@ -117,11 +135,12 @@ __device__ __forceinline__ Target receiver_target(const QueryArgs& a, int64_t i)
 // n_fin) expected samples with P = min(gamma E~, 1).  Iterates the saturated
 // set {gamma E~ >= 1}, which only grows, until it is stable.  Returns +inf when
 // every finite entry is taken with P = 1.  One thread per shading point.
-__device__ float solve_gamma(const float* Et, uint32_t nU, float W) {
+__device__ float solve_gamma(const float* ge, const CandList& cl, float W) {
+  const uint32_t nU = cl.n;
   uint32_t n_inf = 0, n_fin = 0;
   float S = 0.f;
   for (uint32_t j = 0; j < nU; ++j) {
-    const float e = Et[j];
+    const float e = ge[cl.at(j)];
     n_inf += isinf(e) ? 1u : 0u;
     if (isfinite(e) && e > 0.f) {
       ++n_fin;
@@ -137,7 +156,7 @@ __device__ float solve_gamma(const float* Et, uint32_t nU, float W) {
     uint32_t kn = 0;
     float Sn = 0.f;
     for (uint32_t j = 0; j < nU; ++j) {
-      const float e = Et[j];
+      const float e = ge[cl.at(j)];
       if (isfinite(e) && e > 0.f) {
         if (gamma * e >= 1.f)
           ++kn;
@@ -145,6 +164,54 @@ __device__ float solve_gamma(const float* Et, uint32_t nU, float W) {
           Sn += e;
       }
     }
+    if (kn == k || !(Sn > 0.f)) break;
+    k = kn;
+    gamma = (Wf - float(k)) / Sn;
+  }
+  return gamma;
+}
+
+// The same solve for a long list with the 64 lanes of a wave: lane l takes
+// entries l, l + 64, ... of U and the counts and sums are combined by a
+// butterfly (every lane ends with the same value, and the order of the FP32
+// additions depends only on the list), so every lane returns the same gamma,
+// whichever kernel or batch the point is in.  Lists longer than
+// kLongList take this path in every query form.
+constexpr uint32_t kLongList = 96;
+__device__ float solve_gamma_wave(const float* ge, const CandList& cl, float W, int lane) {
+  const uint32_t nU = cl.n;
+  uint32_t n_inf = 0, n_fin = 0;
+  float S = 0.f;
+  for (uint32_t j = uint32_t(lane); j < nU; j += BBC_WAVE) {
+    const float e = ge[cl.at(j)];
+    n_inf += isinf(e) ? 1u : 0u;
+    if (isfinite(e) && e > 0.f) {
+      ++n_fin;
+      S += e;
+    }
+  }
+  n_inf = wave_sum(n_inf);
+  n_fin = wave_sum(n_fin);
+  S = wave_sum(S);
+  const float Wp = fminf(W, float(nU));
+  const float Wf = fminf(fmaxf(Wp - float(n_inf), 1.f), float(n_fin));
+  if (n_fin == 0 || Wf >= float(n_fin)) return INFINITY;
+  float gamma = Wf / S;
+  uint32_t k = 0;
+  for (uint32_t iter = 0; iter <= n_fin; ++iter) {
+    uint32_t kn = 0;
+    float Sn = 0.f;
+    for (uint32_t j = uint32_t(lane); j < nU; j += BBC_WAVE) {
+      const float e = ge[cl.at(j)];
+      if (isfinite(e) && e > 0.f) {
+        if (gamma * e >= 1.f)
+          ++kn;
+        else
+          Sn += e;
+      }
+    }
+    kn = wave_sum(kn);
+    Sn = wave_sum(Sn);
     if (kn == k || !(Sn > 0.f)) break;
     k = kn;
     gamma = (Wf - float(k)) / Sn;
@@ -358,30 +425,37 @@ __global__ void __launch_bounds__(64, kWaves) k_query_fused(QueryArgs a) {
     const int64_t i = tile * kTile + lane;
     const bool valid = lane < kTile && i < a.n;
     Target tg{};
-    uint32_t b = 0, nU = 0;
+    CandList cl{0u, 0u, 0u, 0u};
     if (valid) {
       tg = receiver_target(a, i);
-      if (tg.on) {
-        b = a.coff[tg.cell];
-        nU = a.coff[tg.cell + 1] - b;
-      }
+      if (tg.on) cl = cand_list(a, tg.cell);
     }
+    const uint32_t nU = cl.n;
     if (lane < kTile) {
       s_ud[lane] = tg.ud;
       s_vd[lane] = tg.vd;
     }
-    const float* Et = a.ge + b;
-    const uint32_t* Tt = a.gt + b;
     const PointReq pr = valid ? point_req(a, i) : PointReq{1.f, 0, 0};
-    const float gamma = (exhaustive || nU == 0) ? INFINITY : solve_gamma(Et, nU, pr.W);
+    float gamma = (exhaustive || nU == 0 || nU > kLongList) ? INFINITY : solve_gamma(a.ge, cl, pr.W);
+    if (!exhaustive) {  // long lists: the whole wave solves each in turn
+      uint64_t longs = __ballot(nU > kLongList);
+      while (longs) {
+        const int q = __ffsll((unsigned long long)longs) - 1;
+        longs &= longs - 1;
+        const CandList cq{uint32_t(__shfl(int(cl.b0), q, BBC_WAVE)), uint32_t(__shfl(int(cl.n0), q, BBC_WAVE)),
+                          uint32_t(__shfl(int(cl.b1), q, BBC_WAVE)), uint32_t(__shfl(int(cl.n), q, BBC_WAVE))};
+        const float g = solve_gamma_wave(a.ge, cq, __shfl(pr.W, q, BBC_WAVE), lane);
+        if (lane == q) gamma = g;
+      }
+    }
     const uint64_t key = pr.key;
     uint32_t cnt = 0;
     double mu2 = 0.0;
     for (uint32_t j = 0; j < nU; ++j) {
-      const float e = Et[j];
+      const float e = a.ge[cl.at(j)];
       const float P = select_prob(e, gamma, exhaustive);
       if (P > 0.f && isfinite(e)) mu2 += double(e) * double(e) / double(P);
-      cnt += selection_uniform(pr.seed, key, tuple_key(a, Tt[j])) < P ? 1u : 0u;
+      cnt += selection_uniform(pr.seed, key, tuple_key(a, a.gt[cl.at(j)])) < P ? 1u : 0u;
     }
     const uint32_t off = wave_excl_scan(cnt, lane);
     const uint32_t total = __shfl(off + cnt, BBC_WAVE - 1, BBC_WAVE);
@@ -391,8 +465,8 @@ __global__ void __launch_bounds__(64, kWaves) k_query_fused(QueryArgs a) {
     for (uint32_t w0 = 0; w0 < total; w0 += kPairCap) {
       // this lane's pairs whose global index falls in [w0, w0 + cap)
       while (emitted < cnt && off + emitted < w0 + kPairCap) {
-        const float e = Et[cur];
-        const uint32_t T = Tt[cur];
+        const float e = a.ge[cl.at(cur)];
+        const uint32_t T = a.gt[cl.at(cur)];
         const float P = select_prob(e, gamma, exhaustive);
         if (selection_uniform(pr.seed, key, tuple_key(a, T)) < P) {
           const uint32_t slot = off + emitted - w0;
@@ -477,7 +551,10 @@ bbc_status launch_query(const Bounds* b, const float* pts, int64_t n, int32_t sp
   const unsigned grid = unsigned(std::min<int64_t>(tiles, int64_t(b->tune.query_grid)));
   const bool w4 = b->tune.query_waves >= 4;
   Bounds* mb = const_cast<Bounds*>(b);
-  if (b->tune.timing) BBC_HIP(hipEventRecord(mb->ev[0], s));
+  if (b->tune.timing) {
+    mb->tev_used = 0;
+    BBC_HIP(hipEventRecord(mb->tev[0], s));
+  }
 #define BBC_FUSED(W, TP)                                                                           \
   do {                                                                                             \
     if (a.sc.chain == BBC_CHAIN_RR)                                                                \
@@ -496,8 +573,8 @@ bbc_status launch_query(const Bounds* b, const float* pts, int64_t n, int32_t sp
   }
 #undef BBC_FUSED
   if (b->tune.timing) {
-    BBC_HIP(hipEventRecord(mb->ev[1], s));
-    mb->ev_recorded = true;
+    BBC_HIP(hipEventRecord(mb->tev[1], s));
+    mb->tev_used = 1;
   }
   BBC_HIP(hipGetLastError());
   return BBC_OK;
@@ -506,7 +583,7 @@ bbc_status launch_query(const Bounds* b, const float* pts, int64_t n, int32_t sp
 // ---------------------------------------------------------------- staged form
 struct StagedArgs {
   QueryArgs q;
-  uint32_t* cell_b;   // [n] first entry of the point's cell (or 0)
+  uint32_t* cell_b;   // [n] the point's grid cell (0 off the receiver, where |U| = 0)
   uint32_t* cnt;      // [n] |U|
   float* gamma;       // [n]
   uint32_t* off;      // [n + 1] exclusive scan of the selection counts
@@ -526,17 +603,32 @@ __global__ void k_stage_gamma(StagedArgs s) {
   if (blockIdx.x == 0 && threadIdx.x == 0) s.off[a.n + 1] = 0u;  // redo count of the pooled Newton kernel
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x) {
     const Target tg = receiver_target(a, i);
-    uint32_t b = 0, nU = 0;
+    uint32_t nU = 0;
     float gamma = INFINITY;
     if (tg.on) {
-      b = a.coff[tg.cell];
-      nU = a.coff[tg.cell + 1] - b;
-      if (!exhaustive && nU > 0) gamma = solve_gamma(a.ge + b, nU, point_req(a, i).W);
+      const CandList cl = cand_list(a, tg.cell);
+      nU = cl.n;
+      if (!exhaustive && nU > 0 && nU <= kLongList) gamma = solve_gamma(a.ge, cl, point_req(a, i).W);
     }
-    s.cell_b[i] = b;
+    s.cell_b[i] = tg.on ? tg.cell : 0u;
     s.gamma[i] = gamma;
     s.cnt[i] = nU;
     s.tgt[i] = make_double2(tg.ud, tg.vd);
+  }
+}
+
+// Gamma of the points whose candidate lists are longer than kLongList: one
+// wave per point (k_stage_gamma left them at +inf), after k_stage_gamma.
+__global__ void __launch_bounds__(256) k_stage_gamma_long(StagedArgs s) {
+  const QueryArgs& a = s.q;
+  if (a.mode & BBC_QUERY_EXHAUSTIVE) return;
+  const int lane = int(threadIdx.x % BBC_WAVE);
+  const int64_t waves = int64_t(gridDim.x) * (blockDim.x / BBC_WAVE);
+  for (int64_t i = int64_t(blockIdx.x) * (blockDim.x / BBC_WAVE) + threadIdx.x / BBC_WAVE; i < a.n; i += waves) {
+    const uint32_t nU = s.cnt[i];
+    if (nU <= kLongList) continue;
+    const float g = solve_gamma_wave(a.ge, cand_list(a, s.cell_b[i]), point_req(a, i).W, lane);
+    if (lane == 0) s.gamma[i] = g;
   }
 }
 
@@ -560,7 +652,8 @@ __global__ void k_stage_gamma(StagedArgs s) {
 constexpr float kBinSlack = 1.0f / 1048576.0f;
 template <class F>
 __device__ void point_selection(const QueryArgs& a, const StagedArgs& s, int64_t i, int lane, F&& chunk) {
-  const uint32_t b = s.cell_b[i], nU = s.cnt[i];
+  const uint32_t nU = s.cnt[i];
+  const CandList cl = cand_list(a, s.cell_b[i]);
   const float gamma = s.gamma[i];
   const PointReq pr = point_req(a, i);
   const int sampler = a.mode & BBC_QUERY_SAMPLERS;
@@ -570,7 +663,7 @@ __device__ void point_selection(const QueryArgs& a, const StagedArgs& s, int64_t
     int64_t last = -1;
     for (uint32_t j0 = 0; j0 < nU; j0 += BBC_WAVE) {
       const uint32_t j = j0 + lane;
-      const float e = j < nU ? a.ge[b + j] : 0.f;
+      const float e = j < nU ? a.ge[cl.at(j)] : 0.f;
       const float ef = (isfinite(e) && e > 0.f) ? e : 0.f;
       const uint32_t cnt = min(uint32_t(BBC_WAVE), nU - j0);
       for (uint32_t q = 0; q < cnt; ++q) {
@@ -585,8 +678,8 @@ __device__ void point_selection(const QueryArgs& a, const StagedArgs& s, int64_t
     float C = 0.f;
     for (uint32_t j0 = 0; j0 < nU; j0 += BBC_WAVE) {
       const uint32_t j = j0 + lane;
-      const float e = j < nU ? a.ge[b + j] : 0.f;
-      const uint32_t T = j < nU ? a.gt[b + j] : 0u;
+      const float e = j < nU ? a.ge[cl.at(j)] : 0.f;
+      const uint32_t T = j < nU ? a.gt[cl.at(j)] : 0u;
       const float ef = (isfinite(e) && e > 0.f) ? e : 0.f;
       const uint32_t cnt = min(uint32_t(BBC_WAVE), nU - j0);
       float lo = 0.f, hi = 0.f;
@@ -620,8 +713,8 @@ __device__ void point_selection(const QueryArgs& a, const StagedArgs& s, int64_t
     float r = sample_stream(pr.seed, pr.key, 0u, 2u);
     for (uint32_t j0 = 0; j0 < nU; j0 += BBC_WAVE) {
       const uint32_t j = j0 + lane;
-      const uint32_t T = j < nU ? a.gt[b + j] : 0u;
-      const float p = j < nU ? select_prob(a.ge[b + j], gamma, false) : 0.f;
+      const uint32_t T = j < nU ? a.gt[cl.at(j)] : 0u;
+      const float p = j < nU ? select_prob(a.ge[cl.at(j)], gamma, false) : 0.f;
       const uint32_t cnt = min(uint32_t(BBC_WAVE), nU - j0);
       bool take = false;
       float w = p;
@@ -655,8 +748,8 @@ __device__ void point_selection(const QueryArgs& a, const StagedArgs& s, int64_t
     float P = 0.f;
     uint32_t T = 0;
     if (j < nU) {
-      T = a.gt[b + j];
-      P = sampler == BBC_QUERY_UNIFORM ? Pu : select_prob(a.ge[b + j], gamma, exhaustive);
+      T = a.gt[cl.at(j)];
+      P = sampler == BBC_QUERY_UNIFORM ? Pu : select_prob(a.ge[cl.at(j)], gamma, exhaustive);
       take = selection_uniform(pr.seed, pr.key, tuple_key(a, T)) < P;
     }
     chunk(take, T, P);
@@ -708,7 +801,8 @@ __global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* s
   for (int64_t i0 = int64_t(blockIdx.x) * NG; i0 < a.n; i0 += int64_t(gridDim.x) * NG) {
     const int64_t i = i0 + g;
     const bool valid = i < a.n;
-    const uint32_t b = valid ? s.cell_b[i] : 0u, nU = valid ? s.cnt[i] : 0u;
+    const uint32_t nU = valid ? s.cnt[i] : 0u;
+    const CandList cl = cand_list(a, valid ? s.cell_b[i] : 0u);
     const float gamma = valid ? s.gamma[i] : 0.f;
     const PointReq pr = point_req(a, valid ? i : i0);
     const float Pu = fminf(pr.W, float(nU)) / float(nU);
@@ -719,8 +813,8 @@ __global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* s
       float P = 0.f;
       uint32_t T = 0;
       if (j < nU) {
-        T = a.gt[b + j];
-        P = uniform ? Pu : select_prob(a.ge[b + j], gamma, exhaustive);
+        T = a.gt[cl.at(j)];
+        P = uniform ? Pu : select_prob(a.ge[cl.at(j)], gamma, exhaustive);
         take = selection_uniform(pr.seed, pr.key, tuple_key(a, T)) < P;
       }
       if constexpr (FILL) {
@@ -1131,11 +1225,12 @@ __global__ void k_stage_accum(StagedArgs s) {
     if (a.stats) {
       uint32_t roots = 0;
       for (uint32_t k = o0; k < o1; ++k) roots += s.pair_nr[k];
-      const uint32_t b = s.cell_b[i], nU = s.cnt[i];
+      const uint32_t nU = s.cnt[i];
+      const CandList cl = cand_list(a, s.cell_b[i]);
       const float gamma = s.gamma[i];
       double mu2 = 0.0;
       for (uint32_t j = 0; j < nU; ++j) {
-        const float e = a.ge[b + j];
+        const float e = a.ge[cl.at(j)];
         const float P = select_prob(e, gamma, exhaustive);
         if (bound_p && P > 0.f && isfinite(e)) mu2 += double(e) * double(e) / double(P);
       }
@@ -1224,6 +1319,8 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   const unsigned grid = unsigned(std::min<int64_t>(n, 256 * 64));
   const unsigned gpt = unsigned(std::min<int64_t>((n + 255) / 256, 4096));
   hipLaunchKernelGGL(k_stage_gamma, dim3(gpt), dim3(256), 0, st, s);
+  const unsigned gl = unsigned(std::min<int64_t>((n + 3) / 4, 16384));
+  hipLaunchKernelGGL(k_stage_gamma_long, dim3(gl), dim3(256), 0, st, s);
   // selection counts go to the head of the pair_pt buffer, are scanned into
   // off, and are overwritten by the fill kernel afterwards
   uint32_t* sel = w.pair_pt;
@@ -1294,8 +1391,9 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
 
 // Points per staged launch: the worst case of every launch (every candidate
 // of the fullest cell selected) stays within kMaxStagedPairs pairs.
-static int64_t staged_slice(const Bounds* b, int64_t n) {
-  const int64_t per = int64_t(kMaxStagedPairs / size_t(std::max<int64_t>(1, b->max_cell)));
+int64_t staged_slice(const Bounds* b, int64_t n) {
+  const int64_t cap = std::min<int64_t>(b->tune.staged_pairs, int64_t(kMaxStagedPairs));
+  const int64_t per = cap / std::max<int64_t>(1, b->max_cell);
   return std::max<int64_t>(1, std::min(n, per));
 }
 
@@ -1324,15 +1422,35 @@ bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t s
     staged_carve(b->qw_buf.p, np, pp, b->qw);
   }
   const bool timed = b->tune.timing != 0;
-  for (int64_t i0 = 0; i0 < n; i0 += slice) {
-    const int64_t m = std::min(slice, n - i0);
-    // events bracket the Newton kernel of the first slice
-    const bool ev = timed && i0 == 0;
-    bbc_status e = staged_slice_run(b, pts, n, i0, m, spp, seed, base, mode, out, stats, counters, b->qw,
-                                    ev ? b->ev[0] : nullptr, ev ? b->ev[1] : nullptr, st);
-    if (e) return e;
+  if (b->tune.graph && !timed) {
+    // every slice's launches in one graph, replayed on the handle's stream
+    return run_as_graph(b->qgraph, st, [&](hipStream_t gs) -> bbc_status {
+      for (int64_t i0 = 0; i0 < n; i0 += slice) {
+        const int64_t m = std::min(slice, n - i0);
+        bbc_status e = staged_slice_run(b, pts, n, i0, m, spp, seed, base, mode, out, stats, counters, b->qw, nullptr,
+                                        nullptr, gs);
+        if (e) return e;
+      }
+      return BBC_OK;
+    });
   }
-  if (timed) b->ev_recorded = true;
+  if (timed) {
+    // one pair of events around the Newton kernel of every slice
+    const size_t want = size_t(2 * ((n + slice - 1) / slice));
+    while (b->tev.size() < want) {
+      hipEvent_t ev = nullptr;
+      BBC_HIP(hipEventCreate(&ev));
+      b->tev.push_back(ev);
+    }
+    b->tev_used = 0;
+  }
+  for (int64_t i0 = 0, k = 0; i0 < n; i0 += slice, ++k) {
+    const int64_t m = std::min(slice, n - i0);
+    bbc_status e = staged_slice_run(b, pts, n, i0, m, spp, seed, base, mode, out, stats, counters, b->qw,
+                                    timed ? b->tev[2 * k] : nullptr, timed ? b->tev[2 * k + 1] : nullptr, st);
+    if (e) return e;
+    if (timed) b->tev_used = int(k + 1);
+  }
   return BBC_OK;
 }
 
@@ -1370,14 +1488,26 @@ bbc_status launch_query_batch(const Bounds* b, const float* pts, int64_t n, cons
                               const ReqDesc* reqs, int32_t mode, float* out, const StagedWork& w, hipEvent_t ev0,
                               hipEvent_t ev1, hipStream_t st) {
   if (n == 0) return BBC_OK;
-  if (size_t(n) > w.pts || staged_pairs(b, n) > w.pairs) {
-    set_error("batch work space smaller than the batch");
+  const int64_t slice = staged_slice(b, n);
+  if (size_t(slice) > w.pts || staged_pairs(b, slice) > w.pairs) {
+    set_error("batch work space smaller than one slice of the batch");
     return BBC_EINVAL;
   }
-  QueryArgs q = make_args(b, pts, n, 1, 0, 0, mode, out, nullptr, nullptr);
-  q.preq = preq;
-  q.reqs = reqs;
-  return run_staged(q, w, w.pairs, b->tune.newton_steps, b->tune.newton_results, ev0, ev1, st);
+  // consecutive slices of the batch over the same work space; each point
+  // keeps its request's random stream through the slice offset
+  for (int64_t i0 = 0; i0 < n; i0 += slice) {
+    const int64_t m = std::min(slice, n - i0);
+    QueryArgs q = make_args(b, pts + i0, m, 1, 0, 0, mode, out + i0, nullptr, nullptr);
+    q.pstride = n;
+    q.preq = preq + i0;
+    q.reqs = reqs;
+    q.ioff = i0;
+    const bool ev = i0 == 0;
+    bbc_status e = run_staged(q, w, w.pairs, b->tune.newton_steps, b->tune.newton_results, ev ? ev0 : nullptr,
+                              ev ? ev1 : nullptr, st);
+    if (e) return e;
+  }
+  return BBC_OK;
 }
 
 }  // namespace bbc

@@ -125,9 +125,15 @@ struct RecArgs {
   uint32_t* lcoarse;  // rectangle in tiles of each sorted leaf (padded with empty ones)
   uint32_t* ccount;
   uint32_t* coff;
-  uint32_t* gt;     // entries, sorted by tuple inside each cell
+  uint32_t* gt;     // entries, sorted by tuple inside each cell, then the cover-all list
   float* ge;
   uint32_t* max_cell;
+  // cover-all list: per-tuple flag (then its scan: the tuple's slot in the
+  // list) and the largest E_hi of the tuple's leaves
+  uint32_t* cflag;
+  uint32_t* cpos;
+  float* cE;
+  double cover_cells;  // footprint (leaf-cell records) at which a tuple goes to the list; 0: never
 };
 
 __global__ void k_leaf_count(RecArgs a) {
@@ -174,6 +180,51 @@ __device__ __forceinline__ int cell_of(float x, int G) {
   return min(G - 1, max(0, int(c)));
 }
 
+// Cover-all decision per tuple (Sec. 6.1 bound storage, cover-all reading):
+// the sum over its leaves of the number of cells of their closed cell
+// rectangles, against cover_frac * G^2; and the largest E_hi of its leaves.
+__global__ void k_tuple_cover(RecArgs a) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < a.n_tuples;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const uint32_t lb = a.toff[t], le = a.toff[t + 1];
+    uint64_t cells = 0;
+    float emax = 0.f;
+    for (uint32_t i = lb; i < le; ++i) {
+      const float4 u = a.su[i];
+      cells += uint64_t(cell_of(u.y, a.G) - cell_of(u.x, a.G) + 1) * uint64_t(cell_of(u.w, a.G) - cell_of(u.z, a.G) + 1);
+      emax = fmaxf(emax, a.se[i].y);
+    }
+    a.cflag[t] = (a.cover_cells > 0.0 && cells > 0 && double(cells) >= a.cover_cells) ? 1u : 0u;
+    a.cE[t] = emax;
+  }
+}
+
+// The cover-all list after the cells' entries: tuple t with its flag set goes
+// to slot cpos[t] (tuples ascending), and the last offset closes the list.
+__global__ void k_cover_write(RecArgs a) {
+  const uint32_t G2 = uint32_t(a.G) * uint32_t(a.G);
+  const uint32_t base = a.coff[G2], n_cover = a.cpos[a.n_tuples];
+  if (uint64_t(base) + n_cover > a.grid_cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      atomicOr(&a.C->overflow, 4u);
+      a.C->n_triples = base + n_cover;
+    }
+    return;
+  }
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < a.n_tuples;
+       t += int64_t(gridDim.x) * blockDim.x)
+    if (a.cflag[t]) {
+      a.gt[base + a.cpos[t]] = uint32_t(t);
+      a.ge[base + a.cpos[t]] = a.cE[t];
+    }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.coff[G2 + 1] = base + n_cover;
+    a.C->n_entries = base + n_cover;
+    a.C->n_cover = n_cover;
+    *a.max_cell += n_cover;  // every point reads its cell's list and the cover-all list
+  }
+}
+
 // What the grid needs of every leaf (in the tuple order of the sorted
 // leaves), in one 16-byte record: its closed cell rectangle packed as
 // (cu0 | cu1 << 16, cv0 | cv1 << 16), its tuple, and the bits of its E_hi
@@ -191,6 +242,10 @@ __global__ void k_leaf_rects(RecArgs a) {
   const uint32_t n_pad = (n + uint32_t(kChunk) - 1) / uint32_t(kChunk) * uint32_t(kChunk) + uint32_t(kChunk);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += gridDim.x * blockDim.x) {
     if (i >= n) {
+      a.lcoarse[i] = kEmptyCoarse;
+      continue;
+    }
+    if (a.cflag[a.st[i]]) {  // the tuple is in the cover-all list: the leaf meets no tile
       a.lcoarse[i] = kEmptyCoarse;
       continue;
     }
@@ -234,7 +289,6 @@ __global__ void __launch_bounds__(kCellThreads) k_grid_cells(RecArgs a) {
     }
     return;
   }
-  if (WRITE && blockIdx.x == 0 && tid == 0) a.C->n_entries = total;
   uint32_t mx = 0;
   for (int tile = blockIdx.x; tile < nt * nt; tile += gridDim.x) {
     const int tu0 = (tile / nt) * kCellTile, tv0 = (tile % nt) * kCellTile;
@@ -417,6 +471,10 @@ bbc_status launch_record(Bounds* b, hipStream_t s) {
   a.gt = static_cast<uint32_t*>(b->gt.p);
   a.ge = static_cast<float*>(b->ge.p);
   a.max_cell = static_cast<uint32_t*>(b->max_cell_dev.p);
+  a.cflag = static_cast<uint32_t*>(b->cflag.p);
+  a.cpos = static_cast<uint32_t*>(b->cpos.p);
+  a.cE = static_cast<float*>(b->cE.p);
+  a.cover_cells = double(b->params.cover_frac) * double(a.G) * double(a.G);
   const int64_t ncell = int64_t(a.G) * a.G;
   bbc_status st;
   if ((st = launch_fill_u32(a.tcount, 0, b->n_tuples, s))) return st;
@@ -427,12 +485,16 @@ bbc_status launch_record(Bounds* b, hipStream_t s) {
   if ((st = launch_scan_u32(a.tcount, a.toff, b->n_tuples, b->scan_tmp.p, s))) return st;
   hipLaunchKernelGGL(k_leaf_scatter, dim3(gl), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_leaf_rank, dim3(gl), dim3(256), 0, s, a);
+  const unsigned gt_ = unsigned(std::max<int64_t>(1, std::min<int64_t>((b->n_tuples + 255) / 256, 4096)));
+  hipLaunchKernelGGL(k_tuple_cover, dim3(gt_), dim3(256), 0, s, a);
+  if ((st = launch_scan_u32(a.cflag, a.cpos, b->n_tuples, b->scan_tmp.p, s))) return st;
   hipLaunchKernelGGL(k_leaf_rects, dim3(gl), dim3(256), 0, s, a);
   const int nt = (a.G + kCellTile - 1) / kCellTile;
   const unsigned gc = unsigned(nt) * unsigned(nt);
   hipLaunchKernelGGL(k_grid_cells<false>, dim3(gc), dim3(kCellThreads), 0, s, a);
   if ((st = launch_scan_u32(a.ccount, a.coff, ncell, b->scan_tmp.p, s))) return st;
   hipLaunchKernelGGL(k_grid_cells<true>, dim3(gc), dim3(kCellThreads), 0, s, a);
+  hipLaunchKernelGGL(k_cover_write, dim3(gt_), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_tuple_records,
                      dim3(unsigned(std::max<int64_t>(1, std::min<int64_t>((b->n_tuples + 255) / 256, 4096)))),
                      dim3(256), 0, s, a, b->scene, static_cast<const float4*>(b->root.p), static_cast<float*>(b->trec.p),

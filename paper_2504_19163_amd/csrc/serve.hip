@@ -45,11 +45,11 @@ static BatchLayout batch_layout(const Bounds* b, int64_t n, int32_t nreq) {
   L.reqs = o;
   o += Arena::round(size_t(std::max(nreq, 1)) * sizeof(ReqDesc));
   L.work = o;
-  o += staged_bytes(n, staged_pairs(b, n));
+  // the batch runs in slices whose worst-case pair count fits the staged
+  // launch's 32-bit pair indices; its work space holds one slice
+  const int64_t slice = staged_slice(b, std::max<int64_t>(n, 1));
+  o += staged_bytes(slice, staged_pairs(b, slice));
   L.total = o;
-  // a batch is one staged launch, whose 32-bit pair indices limit its
-  // worst-case pair count: a larger batch never fits
-  if (staged_pairs(b, n) > std::max(kMaxStagedPairs, staged_pairs(b, 1))) L.total = SIZE_MAX;
   return L;
 }
 
@@ -61,6 +61,8 @@ struct Slot {
   uint16_t* h_preq = nullptr;
   ReqDesc* h_reqs = nullptr;
   bool busy = false;
+  hipGraphExec_t gexec = nullptr;  // BBC_SERVER_GRAPH: the slot's batch launches as a graph
+  int64_t instantiations = 0;
   // the batch in flight
   std::vector<Request> reqs;
   std::vector<int64_t> start;
@@ -145,7 +147,8 @@ static bbc_status launch_slot(bbc_server* s, Slot& sl, const Bounds* b) {
   uint16_t* d_preq = reinterpret_cast<uint16_t*>(base + L.preq);
   ReqDesc* d_reqs = reinterpret_cast<ReqDesc*>(base + L.reqs);
   StagedWork w;
-  staged_carve(base + L.work, sl.n, staged_pairs(b, sl.n), w);
+  const int64_t slice = staged_slice(b, std::max<int64_t>(sl.n, 1));
+  staged_carve(base + L.work, slice, staged_pairs(b, slice), w);
   const int64_t n = sl.n;
   bool any_host = false;
   for (int32_t k = 0; k < nreq; ++k) {
@@ -176,7 +179,15 @@ static bbc_status launch_slot(bbc_server* s, Slot& sl, const Bounds* b) {
   }
   BBC_HIP(hipMemcpyAsync(d_preq, sl.h_preq, size_t(n) * 2, hipMemcpyHostToDevice, st));
   BBC_HIP(hipMemcpyAsync(d_reqs, sl.h_reqs, size_t(nreq) * sizeof(ReqDesc), hipMemcpyHostToDevice, st));
-  bbc_status e = launch_query_batch(b, d_pts, n, d_preq, d_reqs, s->cfg.mode, d_out, w, nullptr, nullptr, st);
+  bbc_status e;
+  if (s->cfg.flags & BBC_SERVER_GRAPH) {
+    e = capture_into(st, &sl.gexec, &sl.instantiations, [&](hipStream_t cs) {
+      return launch_query_batch(b, d_pts, n, d_preq, d_reqs, s->cfg.mode, d_out, w, nullptr, nullptr, cs);
+    });
+    if (!e) BBC_HIP(hipGraphLaunch(sl.gexec, st));
+  } else {
+    e = launch_query_batch(b, d_pts, n, d_preq, d_reqs, s->cfg.mode, d_out, w, nullptr, nullptr, st);
+  }
   if (e) return e;
   if (any_host) BBC_HIP(hipMemcpyAsync(sl.h_out, d_out, size_t(n) * 4, hipMemcpyDeviceToHost, st));
   for (int32_t k = 0; k < nreq; ++k) {
@@ -285,6 +296,7 @@ static void destroy_resources(bbc_server* s) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
     if (sl.ev_start) (void)hipEventDestroy(sl.ev_start);
     if (sl.ev_done) (void)hipEventDestroy(sl.ev_done);
+    if (sl.gexec) (void)hipGraphExecDestroy(sl.gexec);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
     if (sl.h_pts) (void)hipHostFree(sl.h_pts);
     if (sl.h_out) (void)hipHostFree(sl.h_out);
@@ -318,7 +330,7 @@ bbc_status bbc_server_create(bbc_bounds* const* bounds, int32_t n_bounds, const 
   if (cfg->mode != 0 && cfg->mode != BBC_QUERY_EXHAUSTIVE && cfg->mode != BBC_QUERY_UNIFORM &&
       cfg->mode != BBC_QUERY_ONE_SAMPLE && cfg->mode != BBC_QUERY_BINS)
     return fail(BBC_EINVAL, "mode must be 0, EXHAUSTIVE or one sampler");
-  if (cfg->flags & ~BBC_SERVER_PAUSED) return fail(BBC_EINVAL, "unknown server flags");
+  if (cfg->flags & ~(BBC_SERVER_PAUSED | BBC_SERVER_GRAPH)) return fail(BBC_EINVAL, "unknown server flags");
   std::vector<Bounds*> bs;
   for (int32_t i = 0; i < n_bounds; ++i) {
     if (!bounds[i]) return fail(BBC_EINVAL, "null bounds handle");
@@ -380,9 +392,6 @@ bbc_status bbc_server_submit(bbc_server* s, const bbc_request* r, uint64_t* tick
   if (r->n > s->cfg.max_batch_points)
     return reject(BBC_EBUDGET, "request has more points than max_batch_points");
   const size_t need = batch_layout(s->bounds[r->scene], r->n, 1).total;
-  if (need == SIZE_MAX)
-    return reject(BBC_EBUDGET, "request's worst-case pair count exceeds one staged launch (" +
-                                   std::to_string(kMaxStagedPairs) + " pairs): split it into smaller requests");
   if (!s->arena.ever_fits(need))
     return reject(BBC_EBUDGET, "request needs " + std::to_string(need) + " bytes of work space, more than the budget");
   {

@@ -34,3 +34,17 @@ def check_leaf_bounds(orc, osc, L, idx, tol=BOUND_TOL, e_face_value=False, flags
         if np.isfinite(oE[1]):
             assert gE[1] >= oE[1] * (1 - 1e-12) and gE[1] <= oE[1] * (1 + tol), (k, gE, oE)
         assert gE[0] <= oE[0] * (1 + 1e-12) and gE[0] >= oE[0] * (1 - tol), (k, gE, oE)
+
+
+def check_cover_list(off, gt, ge, Ob, G, tol=BOUND_TOL):
+    """The GPU grid's last slice (the cover-all list) against the oracle's:
+    the same tuples in the same order, and the same largest E_hi up to the
+    FP32 rounding of the outputs (both are maxima of the leaves' E_hi)."""
+    assert len(off) == G * G + 2 and off[-1] == len(gt)
+    ot, oe = Ob.cover_list()
+    a, b = off[G * G], off[G * G + 1]
+    assert np.array_equal(gt[a:b].astype(np.int64), ot)
+    e = ge[a:b].astype(np.float64)
+    fin = np.isfinite(oe)
+    assert np.array_equal(np.isfinite(e), fin)
+    assert np.all(np.abs(e[fin] - oe[fin]) <= tol * np.abs(oe[fin]))

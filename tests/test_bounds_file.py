@@ -9,7 +9,7 @@ import struct
 import numpy as np
 import pytest
 
-HEADER_BYTES = 336  # magic, version, size, 3 i32 + f32, 8 i64, 9 f32 + pad, 7 params, 43 build counters
+HEADER_BYTES = 344  # magic, version, size, 3 i32 + f32, 8 i64, 9 f32 + pad, 8 params, 44 build counters
 
 
 @pytest.fixture(scope="module")
@@ -28,22 +28,24 @@ def _fnv(data):
     return h
 
 
-def _file(toff=(0, 0), coff=(0, 0), magic=b"BBCBOUND", version=1, grid_res=1, max_cell=0, extra_section=False,
-          leaf=None, entry=None):
+def _file(toff=(0, 0), coff=(0, 0, 0), magic=b"BBCBOUND", version=2, grid_res=1, max_cell=0, extra_section=False,
+          leaf=None, entry=None, cover=0):
     """A well-formed file of one mirror triangle, one point light, one tuple
     without leaves and a 1x1 receiver grid (built by hand, not by the library).
-    leaf = (tuple, code) adds one leaf, entry = tuple one grid entry."""
+    leaf = (tuple, code) adds one leaf, entry = tuple one grid entry; the cell
+    offsets end with the (empty) cover-all slice, whose length the header's
+    cover counter gives (cover)."""
     nl, ne = int(leaf is not None), int(entry is not None)
     if leaf is not None:
         toff = (0, 1)
     if entry is not None:
-        coff, max_cell = (0, 1), 1
+        coff, max_cell = (0, 1, 1), 1
     hdr = magic + struct.pack("<II", version, HEADER_BYTES)
     hdr += struct.pack("<iiif", 0, 0, 32, 1.0)  # chain R, no edges, 32 floats per record, eta
     hdr += struct.pack("<8q", 1, 0, 1, 1, 1, nl, ne, max_cell)  # triangles, emitters, tuples, leaves, entries
     hdr += struct.pack("<9fI", 0, 0, 0, 1, 0, 0, 0, 1, 0, 0)
-    hdr += struct.pack("<iffiiii", 8, 1e-4, 2.0, grid_res, 100, 4, 0)
-    hdr += bytes(43 * 4)
+    hdr += struct.pack("<iffiiiif", 8, 1e-4, 2.0, grid_res, 100, 4, 0, 0.5)
+    hdr += bytes(11 * 4) + struct.pack("<I", cover) + bytes(32 * 4)  # build counters, n_cover the 12th
     assert len(hdr) == HEADER_BYTES
     secs = [np.zeros(9, np.float32), np.zeros(9, np.float32), np.array([0, 0, 1], np.float32),
             np.ones(1, np.float32), np.zeros(32, np.float32), np.array([0, 1, 0, 1], np.float32),
@@ -92,17 +94,18 @@ def test_wellformed_file_passes_host_validation(L, tmp_path):
     ("magic", "magic"), ("version", "version"), ("truncated", "file size"), ("flip", "checksum"),
     ("toff", "tuple offsets"), ("coff", "cell offsets"), ("max_cell", "fullest cell"), ("grid_res", "file size"),
     ("trailing", "file size"), ("empty", "truncated"), ("leaves_claimed", "file size"), ("leaf_tuple", "leaf tuple"), ("leaf_code", "leaf code"),
-    ("entry", "grid entry"),
+    ("entry", "grid entry"), ("cover", "cover-all"),
 ])
 def test_damaged_files_are_rejected(L, tmp_path, case, needle):
     from paper_2504_19163_amd import bbc
     data = {
         "magic": lambda: _file(magic=b"BBCBOUNX"),
-        "version": lambda: _file(version=2),
+        "version": lambda: _file(version=1),
         "truncated": lambda: _file()[:-20],
         "flip": lambda: (lambda d: d[:400] + bytes([d[400] ^ 1]) + d[401:])(_file()),
         "toff": lambda: _file(toff=(0, 3)),
-        "coff": lambda: _file(coff=(0, 2)),
+        "coff": lambda: _file(coff=(0, 2, 2)),
+        "cover": lambda: _file(cover=1),
         "max_cell": lambda: _file(max_cell=1),
         "grid_res": lambda: _file(grid_res=2),
         "trailing": lambda: _file(extra_section=True),

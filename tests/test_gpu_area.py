@@ -68,6 +68,7 @@ def test_area_grid_matches_oracle(bbc, orc, built):
         fin = np.isfinite(oe)
         assert np.array_equal(np.isfinite(e), fin), c
         assert np.all(np.abs(e[fin] - oe[fin]) <= gpu_checks.BOUND_TOL * np.abs(oe[fin])), c
+    gpu_checks.check_cover_list(off, gt, ge, Ob, G)
 
 
 @pytest.mark.parametrize("case", list(CASES))

@@ -74,7 +74,7 @@ def test_cfg1_grid_matches_oracle(bbc, orc, cfg1):
     sc, osc, ds, B, Ob = cfg1
     off, gt, ge = B.grid()
     G = 512
-    assert len(off) == G * G + 1 and off[-1] == len(gt)
+    assert len(off) == G * G + 2 and off[-1] == len(gt)
     rng = np.random.default_rng(1)
     for c in rng.choice(G * G, 6000, replace=False):
         cu, cv = divmod(int(c), G)
@@ -85,6 +85,7 @@ def test_cfg1_grid_matches_oracle(bbc, orc, cfg1):
         fin = np.isfinite(oe)
         assert np.array_equal(np.isfinite(e), fin)
         assert np.all(e[fin] >= oe[fin] * (1 - 1e-12)) and np.all(e[fin] <= oe[fin] * (1 + BOUND_TOL))
+    gpu_checks.check_cover_list(off, gt, ge, Ob, G)
 
 
 @pytest.mark.parametrize("form", ["fused", "staged"])
@@ -178,7 +179,7 @@ def test_estimator_mean_matches_exhaustive_sum(bbc, orc, cfg1):
         x = pts[:, i].astype(float)
         u = (x[0] - sc["q0"][0]) / sc["f1"][0]
         v = (x[1] - sc["q0"][1]) / sc["f2"][1]
-        U, Et = Ob.cell_list(min(G - 1, int(u * G)), min(G - 1, int(v * G)))
+        U, Et = Ob.candidates(min(G - 1, int(u * G)), min(G - 1, int(v * G)))
         if len(U):
             P = orc.probabilities(Et, W)
             ET = np.array([Ob.tuple_roots_leaves(t, x)[:, 2].sum() for t in U])

@@ -71,6 +71,7 @@ def test_refraction_grid_matches_oracle(bbc, orc, built):
         fin = np.isfinite(oe)
         assert np.array_equal(np.isfinite(e), fin)
         assert np.all(e[fin] >= oe[fin] * (1 - 1e-12)) and np.all(e[fin] <= oe[fin] * (1 + gpu_checks.BOUND_TOL))
+    gpu_checks.check_cover_list(off, gt, ge, Ob, G)
 
 
 @pytest.mark.parametrize("case", list(CASES))

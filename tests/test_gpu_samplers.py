@@ -59,7 +59,7 @@ def _point_list(orc, sc, Ob, x):
     uv = np.linalg.lstsq(A, x - q0, rcond=None)[0]
     G = Ob.params["grid_res"]
     cu, cv = (min(G - 1, max(0, int(np.floor(c * G)))) for c in uv)
-    return Ob.cell_list(cu, cv)
+    return Ob.candidates(cu, cv)
 
 
 @pytest.mark.parametrize("name", list(CASES))

@@ -207,3 +207,37 @@ def test_budget_limits_concurrency(bbc, two_scenes):
         assert st["batches"] == len(reqs)
     finally:
         srv.close()
+
+
+def test_sliced_batches_equal_whole(bbc, two_scenes):
+    """A small BBC_TUNE_STAGED_PAIRS makes the staged query and every served
+    batch run as consecutive launches over slices of their points (the path a
+    scene with very full grid cells takes at full size); each point keeps its
+    request's random stream, so results equal the whole-launch ones bit for
+    bit."""
+    reqs = [r for r in _requests(two_scenes, 24, seed=8, max_n=2500)]
+    ref = [_alone(bbc, two_scenes, r) for r in reqs]
+    bounds = [b for _, _, b in two_scenes]
+    old = [b.get_tuning(bbc.TUNE_STAGED_PAIRS) for b in bounds]
+    try:
+        for b in bounds:
+            off = b.grid()[0].astype(np.int64)
+            # slices of about 100 points at the worst case
+            b.set_tuning(bbc.TUNE_STAGED_PAIRS, max(1, int(np.diff(off).max())) * 100)
+        sliced = [_alone(bbc, two_scenes, r) for r in reqs]
+        for e, g in zip(ref, sliced):
+            assert np.array_equal(e.view(np.uint32), g.view(np.uint32))
+        srv = bbc.Server(bounds, hbm_budget_bytes=1 << 28, max_inflight=3, max_batch_points=16384,
+                         max_batch_requests=64, paused=True)
+        try:
+            tickets = [_submit(srv, r) for r in reqs]
+            srv.resume()
+            for t, e in zip(tickets, ref):
+                got = _host(srv.wait(t)[0])
+                assert np.array_equal(got.view(np.uint32), e.view(np.uint32))
+            assert srv.stats()["batches"] < len(reqs)
+        finally:
+            srv.close()
+    finally:
+        for b, v in zip(bounds, old):
+            b.set_tuning(bbc.TUNE_STAGED_PAIRS, v)
