@@ -200,6 +200,12 @@ bbc_status bbc_bounds_load(const char* path, void* stream, bbc_bounds** out);
  * Leaves are ordered by tuple, then code. */
 bbc_status bbc_export_leaves(const bbc_bounds* b, uint32_t* tuple, uint32_t* code, float* box, float* ukbox, float* E);
 
+/* The tuples the build works on, in the numbering above, ascending: every
+ * emitter x triangle for one vertex, the constructed pairs for two
+ * reflections (tuple construction, Sec. 6.1).  *n receives their count; up to
+ * cap of them are copied to host memory at `tuples` (nullable). */
+bbc_status bbc_export_tuples(const bbc_bounds* b, uint32_t* tuples, int64_t cap, int64_t* n);
+
 /* Copy the receiver grid to host memory: offsets[grid_res^2 + 2] and
  * n_grid_entries entries of (tuple, E~).  Slice c = cu * grid_res + cv
  * (offsets[c] .. offsets[c + 1]) is cell (cu, cv), sorted by tuple; slice

@@ -195,6 +195,93 @@ void split(const Bern& A, int axis, double t, Bern* left, Bern* right) {
   }
 }
 
+// Elevation matrix of one axis from degree m to degree n >= m:
+// b'_i = sum_j E_ij b_j with E_ij = C(n-m, i-j) C(m, j) / C(n, i).
+static std::vector<double> elevation_matrix(int m, int n) {
+  std::vector<double> E(size_t(n + 1) * size_t(m + 1), 0.0);
+  for (int i = 0; i <= n; ++i)
+    for (int j = 0; j <= m; ++j)
+      if (i - j >= 0 && i - j <= n - m) E[size_t(i) * (m + 1) + j] = binom(n - m, i - j) * binom(m, j) / binom(n, i);
+  return E;
+}
+
+// Pseudo-inverse (m+1) x (n+1) of the (n+1) x (m+1) elevation matrix by its
+// singular-value decomposition E = U S V^T (one-sided Jacobi: plane rotations
+// of the columns until they are mutually orthogonal), E+ = V S^-1 U^T.
+static std::vector<double> elevation_pinv(int m, int n) {
+  const int R = n + 1, C = m + 1;
+  std::vector<double> W = elevation_matrix(m, n), V(size_t(C) * C, 0.0);
+  for (int j = 0; j < C; ++j) V[size_t(j) * C + j] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < C; ++p)
+      for (int q = p + 1; q < C; ++q) {
+        double a = 0, b = 0, g = 0;
+        for (int i = 0; i < R; ++i) {
+          const double wp = W[size_t(i) * C + p], wq = W[size_t(i) * C + q];
+          a += wp * wp;
+          b += wq * wq;
+          g += wp * wq;
+        }
+        if (std::fabs(g) <= 1e-15 * std::sqrt(a * b)) continue;
+        off = std::max(off, std::fabs(g) / std::sqrt(a * b));
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+        for (int i = 0; i < R; ++i) {
+          const double wp = W[size_t(i) * C + p], wq = W[size_t(i) * C + q];
+          W[size_t(i) * C + p] = cs * wp - sn * wq;
+          W[size_t(i) * C + q] = sn * wp + cs * wq;
+        }
+        for (int i = 0; i < C; ++i) {
+          const double vp = V[size_t(i) * C + p], vq = V[size_t(i) * C + q];
+          V[size_t(i) * C + p] = cs * vp - sn * vq;
+          V[size_t(i) * C + q] = sn * vp + cs * vq;
+        }
+      }
+    if (off < 1e-15) break;
+  }
+  // W = U S: column j has norm s_j; E+ = V S^-1 U^T = V S^-2 W^T
+  std::vector<double> P(size_t(C) * R, 0.0);
+  for (int j = 0; j < C; ++j) {
+    double s2 = 0;
+    for (int i = 0; i < R; ++i) s2 += W[size_t(i) * C + j] * W[size_t(i) * C + j];
+    for (int r = 0; r < C; ++r)
+      for (int i = 0; i < R; ++i) P[size_t(r) * R + i] += V[size_t(r) * C + j] * W[size_t(i) * C + j] / s2;
+  }
+  return P;
+}
+
+Bern reduce_degree(const Bern& A, const Deg& to, double* rem) {
+  Bern X = A;
+  for (int ax = 0; ax < kAxes; ++ax) {
+    if (to[ax] > A.deg[ax]) throw std::invalid_argument("reduce_degree: target degree above current");
+    if (to[ax] == A.deg[ax]) continue;
+    const int n = X.deg[ax], m = to[ax];
+    const std::vector<double> P = elevation_pinv(m, n);
+    Deg d = X.deg;
+    d[ax] = m;
+    Bern Y(d);
+    for (size_t f = 0; f < Y.size(); ++f) {
+      auto mi = Y.multi(f);
+      const int r = mi[ax];
+      double v = 0.0;
+      for (int i = 0; i <= n; ++i) {
+        auto mx = mi;
+        mx[ax] = i;
+        v += P[size_t(r) * (n + 1) + i] * X.at(mx);
+      }
+      Y.c[f] = v;
+    }
+    X = Y;
+  }
+  const Bern back = elevate(X, A.deg);
+  double r = 0.0;
+  for (size_t f = 0; f < A.size(); ++f) r = std::max(r, std::fabs(A.c[f] - back.c[f]));
+  *rem = r;
+  return X;
+}
+
 double eval(const Bern& A, const std::array<double, kAxes>& x) {
   double s = 0.0;
   for (size_t f = 0; f < A.size(); ++f) {

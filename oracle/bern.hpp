@@ -51,6 +51,15 @@ void split(const Bern& A, int axis, double t, Bern* left, Bern* right);  // de C
 double eval(const Bern& A, const std::array<double, kAxes>& x);         // sum b_i B_i(x)
 void coef_range(const Bern& A, double* lo, double* hi);                 // min/max coefficient
 
+// Degree reduction (Sec. 6.1, "Degree reduction"): the polynomial of degree
+// `to` whose degree-elevated coefficients are closest to A's in the least-
+// squares sense (a linear regression solved through the singular-value
+// decomposition of the elevation matrix of each reduced axis), and in *rem
+// the largest coefficient of the difference at A's degree, which bounds
+// |A - reduced| everywhere on the box (convex hull of the Bernstein
+// coefficients): A = reduced + xi * rem for some xi in [-1, 1].
+Bern reduce_degree(const Bern& A, const Deg& to, double* rem);
+
 // Range bound of p/q from coefficient ratios (Sec. 4.1, Eq. eq_bbound) with the
 // sign-failure rules of the same section: when q's coefficients are not all of
 // one strict sign, bound q/p instead and invert (possibly two intervals); when

@@ -1462,6 +1462,18 @@ int orc_true_irradiance(const orc_scene* s, const double* pts, int64_t n, int la
   return 0;
 }
 
+int64_t orc_pair_list(const orc_scene* s, int64_t emitter, int64_t t1, int64_t* t2_out, int64_t cap) {
+  if (!s || s->chain != 2 || emitter < 0 || emitter >= s->n_emit || t1 < 0 || t1 >= s->n_tri) return -1;
+  int64_t k = 0;
+  for (int64_t t2 = 0; t2 < s->n_tri2; ++t2) {
+    const Tuple c = make_tuple(s, (emitter * s->n_tri + t1) * s->n_tri2 + t2);
+    if (!c.front || !pair_candidate(c)) continue;
+    if (k < cap) t2_out[k] = t2;
+    ++k;
+  }
+  return k;
+}
+
 int64_t orc_tuple_roots(const orc_scene* s, int64_t tuple, const double* x, int lattice, double* roots,
                         int64_t cap) {
   if (!s || !x || tuple < 0 || tuple >= n_tuples_of(s)) return -1;

@@ -116,6 +116,11 @@ int orc_true_irradiance(const orc_scene* s, const double* pts, int64_t n, int la
 /* Brute-force roots of one tuple at one shading point: roots[k][4] = u, v, E_k, residual. */
 int64_t orc_tuple_roots(const orc_scene* s, int64_t tuple, const double* x, int lattice, double* roots,
                         int64_t cap);
+/* Tuple construction of two reflections (Sec. 6.1): the second-surface
+ * triangles t2 that form a candidate pair with first triangle t1 under
+ * emitter e (light in front of t1, and the interval test of the pair), in
+ * ascending order.  Returns the count (writes at most cap). */
+int64_t orc_pair_list(const orc_scene* s, int64_t emitter, int64_t t1, int64_t* t2_out, int64_t cap);
 /* Roots of one tuple found from the covering leaves of a build. */
 int64_t orc_tuple_roots_leaves(const void* h, int64_t tuple, const double* x, double* roots, int64_t cap);
 

@@ -76,6 +76,7 @@ def _declare(L):
         "orc_build_stats": (C.c_int, [vp, vp]),
         "orc_cell_list": (i64, [vp, i32, i32, vp, vp, i64]),
         "orc_cover_list": (i64, [vp, vp, vp, i64]),
+        "orc_pair_list": (i64, [vp, i64, i64, vp, i64]),
         "orc_query": (C.c_int, [vp, vp, i64, d, u64, C.c_int, vp, vp, C.c_int]),
         "orc_true_irradiance": (C.c_int, [vp, vp, i64, C.c_int, vp, C.c_int]),
         "orc_tuple_roots": (i64, [vp, i64, vp, C.c_int, vp, i64]),
@@ -255,6 +256,14 @@ class OracleBuild:
         out = np.zeros((cap, 4))
         n = lib().orc_tuple_roots_leaves(self.h, int(tuple_id), _ptr(xx), _ptr(out), cap)
         return out[:min(n, cap)].copy()
+
+
+def pair_list(osc, emitter, t1):
+    """Second-surface triangles forming candidate pairs with (emitter, t1)."""
+    n = lib().orc_pair_list(osc.ref, int(emitter), int(t1), None, 0)
+    out = np.zeros(max(n, 1), np.int64)
+    lib().orc_pair_list(osc.ref, int(emitter), int(t1), _ptr(out), n)
+    return out[:n]
 
 
 def true_irradiance(osc, pts, lattice=24, n_threads=None):

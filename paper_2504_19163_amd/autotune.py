@@ -9,7 +9,8 @@ W over {16, ..., 256}) through the staged query, median of three passes; the
 build knob is timed on rebuilds.  Knobs change launch shapes only, never
 results (the library's tests check that), so the choice is free.  The table
 is written as JSON {arch: {workload: {knob: value, "ms": {...}}}}, by default
-to tuning.json beside this module, where bbc.apply_tuning reads it.
+to tuning.json beside this module, where bbc.apply_tuning reads it; the entry
+"serving" holds the server's graph flag, timed on a mixed request stream.
 
     python -m paper_2504_19163_amd.autotune [--out PATH] [--workloads sphere131072,...]
 """
@@ -32,7 +33,7 @@ if ROOT not in sys.path:
 WORKLOADS = {
     "sphere131072": (lambda S: S.displaced_sphere(7), dict(max_depth=8, alpha=2.0)),
     "water512x512": (lambda S: S.water_surface(m=512, amp_scale=0.04), dict(max_depth=6, alpha=2.0)),
-    "walls64x64": (lambda S: S.facing_walls(64), dict(max_depth=2, alpha=10.0)),
+    "walls64x64": (lambda S: S.facing_walls(64), dict(max_depth=5, alpha=10.0)),
 }
 
 # staged-query knobs in tuning order, with their candidate values
@@ -123,11 +124,56 @@ def tune_workload(bbc, torch, S, key, n_req=24, log=print):
     return dict(best, ms=ms, requests=n_req)
 
 
+def tune_serving(bbc, torch, S, table_arch, n_req=96, log=print):
+    """The server's graph flag: one stream of requests over the three
+    workloads' bounds (tuned knobs applied), all submitted at once, served with
+    and without BBC_SERVER_GRAPH; median of three passes."""
+    bounds, pools = [], []
+    for j, key in enumerate(WORKLOADS):
+        make, params = WORKLOADS[key]
+        scene = make(S)
+        B = bbc.Bounds(bbc.DeviceScene(scene), params)
+        for knob, name in (("TUNE_NEWTON_STEPS", "newton_steps"), ("TUNE_GRAPH", "graph")):
+            if name in table_arch.get(key, {}):
+                B.set_tuning(getattr(bbc, knob), table_arch[key][name])
+        bounds.append(B)
+        pools.append(torch.as_tensor(S.random_points(scene, 65536, seed=30 + j), device="cuda:0"))
+    rng = np.random.default_rng(5)
+    reqs = []
+    for k in range(n_req):
+        n = int(np.floor(np.exp(rng.uniform(np.log(256), np.log(65536)))))
+        sc = int(rng.integers(0, len(bounds)))
+        o = int(rng.integers(0, 65536 - n + 1))
+        reqs.append((sc, pools[sc][:, o:o + n].contiguous(), int(rng.choice([16, 32, 64, 128, 256])),
+                     int(rng.integers(0, 2**62))))
+    row = {}
+    for g in (0, 1):
+        srv = bbc.Server(bounds, hbm_budget_bytes=64 << 30, max_inflight=4, max_batch_points=1 << 20,
+                         max_batch_requests=1024, queue_capacity=1 << 16, graph=bool(g))
+        ts = []
+        for rep in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tickets = [srv.submit(sc, p, spp, seed, sync_inputs=False) for sc, p, spp, seed in reqs]
+            for t in tickets:
+                srv.wait(t)
+            if rep:
+                ts.append(1e3 * (time.perf_counter() - t0))
+        srv.close()
+        row[g] = float(np.median(ts))
+        log(f"serving graph={g}: {row[g]:.3f} ms")
+    for B in bounds:
+        B.free()
+    best = min(row, key=row.get)
+    return {"graph": best, "ms": {str(k): round(t, 3) for k, t in row.items()}, "requests": n_req}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", default=os.path.join(HERE, "tuning.json"))
     ap.add_argument("--workloads", default=",".join(WORKLOADS))
     ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--no-serving", action="store_true", help="skip the server's graph flag")
     args = ap.parse_args()
     import torch
     from paper_2504_19163_amd import bbc, scenes as S
@@ -140,6 +186,10 @@ def main():
     for key in args.workloads.split(","):
         table.setdefault(arch, {})[key] = tune_workload(bbc, torch, S, key, n_req=args.requests,
                                                         log=lambda m: print(m, flush=True))
+        with open(args.out, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+    if not args.no_serving:
+        table[arch]["serving"] = tune_serving(bbc, torch, S, table[arch], log=lambda m: print(m, flush=True))
         with open(args.out, "w") as f:
             json.dump(table, f, indent=1, sort_keys=True)
     print(json.dumps(table[arch]), flush=True)

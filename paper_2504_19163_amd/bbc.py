@@ -27,7 +27,7 @@ EXPORTS = [
     "bbc_export_grid", "bbc_query_irradiance", "bbc_query_irradiance_ex", "bbc_set_tuning", "bbc_get_tuning",
     "bbc_query_kernel_ms", "bbc_last_error", "bbc_server_create", "bbc_server_submit", "bbc_server_poll",
     "bbc_server_wait", "bbc_server_resume", "bbc_server_stats", "bbc_server_destroy",
-    "bbc_query_irradiance_noalloc", "bbc_build_kernel_ms",
+    "bbc_query_irradiance_noalloc", "bbc_build_kernel_ms", "bbc_export_tuples",
 ]
 SERVER_PAUSED, SERVER_GRAPH = 1, 2
 TUNE_QUERY_WAVES, TUNE_QUERY_GRID, TUNE_BUILD_GRID_PER_CU, TUNE_QUERY_TILE, TUNE_TIMING = 1, 2, 3, 4, 5
@@ -121,6 +121,7 @@ def lib():
             "bbc_bounds_load": [C.c_char_p, vp, vp],
             "bbc_export_leaves": [vp, vp, vp, vp, vp, vp],
             "bbc_export_grid": [vp, vp, vp, vp],
+            "bbc_export_tuples": [vp, vp, i64, vp],
             "bbc_query_irradiance": [vp, vp, i64, i32, u64, vp, vp, vp],
             "bbc_query_irradiance_ex": [vp, vp, i64, i32, u64, i64, i32, vp, vp, vp, vp],
             "bbc_query_irradiance_noalloc": [vp, vp, i64, i32, u64, i64, i32, vp, vp, vp],
@@ -294,6 +295,15 @@ class Bounds:
         iv = (c & 0x3FFF).astype(np.int32)
         return dict(tuple=t.astype(np.int64), code=np.stack([depth, iu, iv], 1), box=box, uk=uk, E=E)
 
+    def tuples(self):
+        """The tuple numbers the build works on (constructed pairs for two
+        reflections), ascending."""
+        n = C.c_int64()
+        _check(lib().bbc_export_tuples(self.h, None, 0, C.byref(n)), "bbc_export_tuples")
+        out = np.zeros(max(n.value, 1), np.uint32)
+        _check(lib().bbc_export_tuples(self.h, out.ctypes.data, n.value, C.byref(n)), "bbc_export_tuples")
+        return out[:n.value].astype(np.int64)
+
     def grid(self):
         """(offsets [G*G + 2], tuples, E~): slices 0 .. G*G - 1 are the cells,
         slice G*G the cover-all list."""
@@ -439,6 +449,17 @@ class Server:
 
 
 TUNING_FILE = os.path.join(HERE, "tuning.json")
+
+
+def tuned_value(workload_key, knob, default, path=TUNING_FILE):
+    """One recorded choice for this device (see apply_tuning), or default."""
+    import json
+    if not os.path.exists(path):
+        return default
+    import torch
+    dev = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    with open(path) as f:
+        return json.load(f).get(dev, {}).get(workload_key, {}).get(knob, default)
 
 
 def apply_tuning(bounds, workload_key, path=TUNING_FILE):

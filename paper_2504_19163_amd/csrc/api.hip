@@ -648,6 +648,20 @@ bbc_status bbc_export_leaves(const bbc_bounds* h, uint32_t* tuple, uint32_t* cod
   return BBC_OK;
 }
 
+bbc_status bbc_export_tuples(const bbc_bounds* h, uint32_t* tuples, int64_t cap, int64_t* n) {
+  if (!h || !n) return invalid("null bounds handle or count");
+  const Bounds* b = reinterpret_cast<const Bounds*>(h);
+  *n = b->n_tuples;
+  if (!tuples || cap <= 0) return BBC_OK;
+  const int64_t m = std::min<int64_t>(cap, b->n_tuples);
+  if (b->scene.chain == BBC_CHAIN_RR) {
+    if (m) BBC_HIP(hipMemcpy(tuples, b->tid.p, size_t(m) * 4, hipMemcpyDeviceToHost));
+  } else {
+    for (int64_t t = 0; t < m; ++t) tuples[t] = uint32_t(t);
+  }
+  return BBC_OK;
+}
+
 bbc_status bbc_export_grid(const bbc_bounds* h, uint32_t* offsets, uint32_t* tuple, float* Et) {
   if (!h) return invalid("null bounds handle");
   const Bounds* b = reinterpret_cast<const Bounds*>(h);

@@ -62,10 +62,6 @@ struct TLay {
   static constexpr int TMP_IRR = 4482, TMP_POS = 1164;
 };
 
-template <class T, bool IRR>
-struct LdsT {
-  T buf[IRR ? TLay::IRR_TMP + TLay::TMP_IRR : TLay::POS_END + TLay::TMP_POS];
-};
 
 // A tensor of n coefficients (all slices) at offset off.
 template <class T>
@@ -178,17 +174,154 @@ __device__ __forceinline__ void elev4(const T* in, T* out, int lane) {
   }
 }
 
-// LDS offsets of the implicit-differentiation tensors (values only), after
-// the position part's live linear forms, d0.d0 and n_g.d0 (TLay::G).
+// ---- the same 4-D operations with magnitude companions (values at t.v,
+// magnitudes at t.m; |computed - exact| <= theta * m coefficient-wise, as for
+// the 2-D tensors of bern_dev.hpp), so the bounds built from them are rounded
+// outward.
+template <int A1, int A2, int A3, int A4, int B1, int B2, int B3, int B4, bool ACC, int NT, class T>
+__device__ __forceinline__ void cv4m(TP<T> a, TP<T> b, TP<T> c, T sgn, int lane) {
+  constexpr int C2 = A2 + B2, C3 = A3 + B3, C4 = A4 + B4;
+  constexpr int N = (A1 + B1 + 1) * (C2 + 1) * (C3 + 1) * (C4 + 1);
+  for (int o = lane; o < N; o += NT) {
+    int r = o;
+    const int l = r % (C4 + 1);
+    r /= C4 + 1;
+    const int k = r % (C3 + 1);
+    r /= C3 + 1;
+    const int j = r % (C2 + 1), i = r / (C2 + 1);
+    T s = T(0), sm = T(0);
+#pragma nounroll
+    for (int i1 = max(0, i - B1); i1 <= min(i, A1); ++i1)
+#pragma nounroll
+      for (int j1 = max(0, j - B2); j1 <= min(j, A2); ++j1)
+        for (int k1 = max(0, k - B3); k1 <= min(k, A3); ++k1)
+          for (int l1 = max(0, l - B4); l1 <= min(l, A4); ++l1) {
+            const int ia = ((i1 * (A2 + 1) + j1) * (A3 + 1) + k1) * (A4 + 1) + l1;
+            const int ib = (((i - i1) * (B2 + 1) + (j - j1)) * (B3 + 1) + (k - k1)) * (B4 + 1) + (l - l1);
+            s = fma(a.v[ia], b.v[ib], s);
+            sm = fma(a.m[ia], b.m[ib], sm);
+          }
+    if (ACC) {
+      c.v[o] = fma(sgn, s, c.v[o]);
+      c.m[o] = fma(fabs(sgn), sm, c.m[o]);
+    } else {
+      c.v[o] = sgn * s;
+      c.m[o] = fabs(sgn) * sm;
+    }
+  }
+}
+// Error factor of a 4-D product accumulated into a sum of `terms` products.
+template <int A1, int A2, int A3, int A4, int B1, int B2, int B3, int B4, class T>
+__device__ __forceinline__ T th_cv4(T ta, T tb, int terms) {
+  constexpr int n = ((A1 < B1 ? A1 : B1) + 1) * ((A2 < B2 ? A2 : B2) + 1) * ((A3 < B3 ? A3 : B3) + 1) *
+                    ((A4 < B4 ? A4 : B4) + 1);
+  return ta + tb + ta * tb + T(n + terms + 2) * Eps<T>::u;
+}
+
+template <int D1, int D2, int D3, int D4, int AX, int NT, class T>
+__device__ __forceinline__ void deriv4m(TP<T> in, TP<T> out, int lane) {
+  constexpr int O1 = D1 - (AX == 0), O2 = D2 - (AX == 1), O3 = D3 - (AX == 2), O4 = D4 - (AX == 3);
+  constexpr int DA = AX == 0 ? D1 : (AX == 1 ? D2 : (AX == 2 ? D3 : D4));
+  for (int o = lane; o < (O1 + 1) * (O2 + 1) * (O3 + 1) * (O4 + 1); o += NT) {
+    int r = o;
+    const int l = r % (O4 + 1);
+    r /= O4 + 1;
+    const int k = r % (O3 + 1);
+    r /= O3 + 1;
+    const int j = r % (O2 + 1), i = r / (O2 + 1);
+    const int t = AX == 0 ? i : (AX == 1 ? j : (AX == 2 ? k : l));
+    auto at = [&](int ii, int jj, int kk, int ll) { return ((ii * (D2 + 1) + jj) * (D3 + 1) + kk) * (D4 + 1) + ll; };
+    const int ih = at(i + (AX == 0), j + (AX == 1), k + (AX == 2), l + (AX == 3)), il = at(i, j, k, l);
+    out.v[o] = fma(T(t + 1), in.v[ih], -(T(DA - t) * in.v[il]));
+    out.m[o] = fma(T(t + 1), in.m[ih], T(DA - t) * in.m[il]);
+  }
+}
+
+template <int D1, int D2, int D3, int D4, int R1, int R2, int R3, int R4, int NT, class T>
+__device__ __forceinline__ void elev4m(TP<T> in, TP<T> out, int lane) {
+  constexpr int E1 = D1 + R1, E2 = D2 + R2, E3 = D3 + R3, E4 = D4 + R4;
+  for (int o = lane; o < (E1 + 1) * (E2 + 1) * (E3 + 1) * (E4 + 1); o += NT) {
+    int r = o;
+    const int l = r % (E4 + 1);
+    r /= E4 + 1;
+    const int k = r % (E3 + 1);
+    r /= E3 + 1;
+    const int j = r % (E2 + 1), i = r / (E2 + 1);
+    T s = T(0), sm = T(0);
+    for (int a = 0; a <= R1; ++a)
+      for (int b = 0; b <= R2; ++b)
+        for (int c = 0; c <= R3; ++c)
+          for (int d = 0; d <= R4; ++d) {
+            const int ii = i - a, jj = j - b, kk = k - c, ll = l - d;
+            if (ii >= 0 && ii <= D1 && jj >= 0 && jj <= D2 && kk >= 0 && kk <= D3 && ll >= 0 && ll <= D4) {
+              const T w = T(binom_i(R1, a) * binom_i(R2, b) * binom_i(R3, c) * binom_i(R4, d));
+              const int ix = ((ii * (D2 + 1) + jj) * (D3 + 1) + kk) * (D4 + 1) + ll;
+              s = fma(w, in.v[ix], s);
+              sm = fma(w, in.m[ix], sm);
+            }
+          }
+    out.v[o] = s;
+    out.m[o] = sm;
+  }
+}
+template <int R1, int R2, int R3, int R4, class T>
+__device__ __forceinline__ T th_elev4(T t) {
+  return t + T((R1 + 1) * (R2 + 1) * (R3 + 1) * (R4 + 1) + 1) * Eps<T>::u;
+}
+
+// Range of a 4-D polynomial from its scaled coefficients and their error
+// bounds, rounded outward.
+template <int D1, int D2, int D3, int D4, class T, int NT>
+__device__ __forceinline__ void range4m(TP<T> t, T th, T* lo, T* hi, int lane) {
+  T l = T(INFINITY), h = -T(INFINITY);
+  for (int o = lane; o < N4<D1, D2, D3, D4>::n; o += NT) {
+    int r = o;
+    const int d = r % (D4 + 1);
+    r /= D4 + 1;
+    const int c = r % (D3 + 1);
+    r /= D3 + 1;
+    const int b = r % (D2 + 1), a = r / (D2 + 1);
+    const T w = T(binom_i(D1, a) * binom_i(D2, b) * binom_i(D3, c) * binom_i(D4, d));
+    const T e = safe_err(th, t.m[o]);
+    l = min(l, down((t.v[o] - e) / w));
+    h = max(h, up((t.v[o] + e) / w));
+  }
+  *lo = blk_min<NT>(l);
+  *hi = blk_max<NT>(h);
+}
+
+// Ratio bound of p/q over n coefficient pairs of equal degree with their
+// error bounds (Eq. eq_bbound, rounded outward).
+template <class T, int NT>
+__device__ __forceinline__ RB<T> ratio4m(int n, TP<T> p, T tp, TP<T> q, T tq, bool final, int lane) {
+  return ratio_bound_fn<T, NT>(
+      n,
+      [&](int o, T& pv, T& ep, T& qv, T& eq) {
+        pv = p.v[o];
+        ep = safe_err(tp, p.m[o]);
+        qv = q.v[o];
+        eq = safe_err(tq, q.m[o]);
+      },
+      final, lane);
+}
+
+// LDS offsets of the implicit-differentiation tensors, after the position
+// part's live linear forms, d0.d0 and n_g.d0 (TLay::G); a tensor of n
+// coefficients takes 2n (values, then magnitudes).
 struct ILay {
-  static constexpr int D1 = TLay::G + 8, C0 = D1 + 48, C1 = C0 + 27, D1D1 = C1 + 108;   // (1,1,1,1)x3, (2,2,0,0)x3, (2,2,1,1)x3
-  static constexpr int GG = D1D1 + 81, GU = GG + 64, GV = GU + 48, GK = GV + 48;  // (2,2,2,2), G (3,3,1,1)
-  static constexpr int GL = GK + 32, A0SQ = GL + 32, A1SQ = A0SQ + 25, F = A1SQ + 225;
-  static constexpr int FU = F + 441, FV = FU + 378, FK = FV + 378, FL = FK + 294;  // F (6,6,2,2)
-  static constexpr int J1 = FL + 294, JK = J1 + 1296, J1E = JK + 900, JKE = J1E + 1600;
-  static constexpr int END = JKE + 1600;
+  static constexpr int D1 = TLay::G + 8, C0 = D1 + 96, C1 = C0 + 54, D1D1 = C1 + 216;  // (1,1,1,1)x3, (2,2,0,0)x3, (2,2,1,1)x3
+  static constexpr int GG = D1D1 + 162, GU = GG + 128, GV = GU + 96, GK = GV + 96;   // (2,2,2,2), G (3,3,1,1)
+  static constexpr int GL = GK + 64, A0SQ = GL + 64, A1SQ = A0SQ + 50, F = A1SQ + 450;
+  static constexpr int FU = F + 882, FV = FU + 756, FK = FV + 756, FL = FK + 588;    // F (6,6,2,2)
+  static constexpr int J1 = FL + 588, JK = J1 + 2592, J1E = JK + 1800, JKE = J1E + 3200;
+  static constexpr int END = JKE + 3200;
 };
-static_assert(ILay::END <= TLay::IRR_TMP + TLay::TMP_IRR, "implicit tensors exceed the refraction LDS");
+
+template <class T, bool IRR>
+struct LdsT {
+  static constexpr int kIrr = TLay::IRR_TMP + TLay::TMP_IRR > ILay::END ? TLay::IRR_TMP + TLay::TMP_IRR : ILay::END;
+  T buf[IRR ? kIrr : TLay::POS_END + TLay::TMP_POS];
+};
 
 template <class T, bool IRR, int NT>
 __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool final, int flags, LdsT<T, IRR>& L,
@@ -397,15 +530,12 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     if (flags & BBC_FLAG_IMPLICIT_IRR) {
       // ---- irradiance by implicit differentiation (Sec. 4.4): F (Snell's law
       // along b) and G (coplanarity) over the box times U_k, |du1/du_k| =
-      // |det J_k / det J_1|; coefficients taken at face value (degree
-      // (9, 9, 3, 3)); b = (1,0,0), (0,1,0), intervals intersected
+      // |det J_k / det J_1|, degree (9, 9, 3, 3); b = (1,0,0), (0,1,0),
+      // intervals intersected; every tensor with magnitudes, rounded outward
       const T wk = uhi - ulo, wl = vhi - vlo;
       if (!(wk > T(0) && wl > T(0))) return out;
-      T* const d1 = B + ILay::D1;
-      T* const c0 = B + ILay::C0;
-      T* const c1 = B + ILay::C1;
-      T* const d1d1 = B + ILay::D1D1;
-      T* const gg = B + ILay::GG;
+      const TP<T> d1 = tpat(B, ILay::D1, 48), c0 = tpat(B, ILay::C0, 27), c1 = tpat(B, ILay::C1, 108);
+      const TP<T> d1d1 = tpat(B, ILay::D1D1, 81), gg = tpat(B, ILay::GG, 64);
       const TP<T> g = tpat(B, TLay::G, 4);
       {
         const T* dv[3] = {dC(0).v, dC(1).v, dC(2).v};
@@ -416,37 +546,42 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
         for (int o = lane; o < 48; o += NT) {
           const int c = o / 16, r = o - 16 * c, ij = r / 4, k = (r / 2) & 1, l = r & 1;
           const T uk = k ? uhi : ulo, vk = l ? vhi : vlo;
-          d1[o] = fma(vk, comp(G.f2, c), fma(uk, comp(G.f1, c), -sC(c).v[ij]));
+          d1.v[o] = fma(vk, comp(G.f2, c), fma(uk, comp(G.f1, c), -sC(c).v[ij]));
+          d1.m[o] = fabs(vk) * fabs(comp(G.f2, c)) + fabs(uk) * fabs(comp(G.f1, c)) + sC(c).m[ij];
         }
       }
+      const T th_d1 = th_lin + T(3) * eps;
       wave_sync();
       for (int c = 0; c < 3; ++c) {  // c0 = d0 x n, c1 = d1 x n
         const int a = (c + 1) % 3, b = (c + 2) % 3;
-        cv4<1, 1, 0, 0, 1, 1, 0, 0, false, NT>(dC(a).v, nC(b).v, c0 + 9 * c, T(1), lane);
-        cv4<1, 1, 0, 0, 1, 1, 0, 0, true, NT>(dC(b).v, nC(a).v, c0 + 9 * c, T(-1), lane);
-        cv4<1, 1, 1, 1, 1, 1, 0, 0, false, NT>(d1 + 16 * a, nC(b).v, c1 + 36 * c, T(1), lane);
-        cv4<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(d1 + 16 * b, nC(a).v, c1 + 36 * c, T(-1), lane);
+        cv4m<1, 1, 0, 0, 1, 1, 0, 0, false, NT>(dC(a), nC(b), slice(c0, c, 9), T(1), lane);
+        cv4m<1, 1, 0, 0, 1, 1, 0, 0, true, NT>(dC(b), nC(a), slice(c0, c, 9), T(-1), lane);
+        cv4m<1, 1, 1, 1, 1, 1, 0, 0, false, NT>(slice(d1, a, 16), nC(b), slice(c1, c, 36), T(1), lane);
+        cv4m<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(slice(d1, b, 16), nC(a), slice(c1, c, 36), T(-1), lane);
         if (c == 0)
-          cv4<1, 1, 1, 1, 1, 1, 1, 1, false, NT>(d1, d1, d1d1, T(1), lane);
+          cv4m<1, 1, 1, 1, 1, 1, 1, 1, false, NT>(slice(d1, c, 16), slice(d1, c, 16), d1d1, T(1), lane);
         else
-          cv4<1, 1, 1, 1, 1, 1, 1, 1, true, NT>(d1 + 16 * c, d1 + 16 * c, d1d1, T(1), lane);
+          cv4m<1, 1, 1, 1, 1, 1, 1, 1, true, NT>(slice(d1, c, 16), slice(d1, c, 16), d1d1, T(1), lane);
       }
       const T th_g = th_lin + T(8) * eps;
+      const T th_c0 = th_cv4<1, 1, 0, 0, 1, 1, 0, 0>(th_lin, th_lin, 2);
+      const T th_c1 = th_cv4<1, 1, 1, 1, 1, 1, 0, 0>(th_d1, th_lin, 2);
+      const T th_d1d1 = th_cv4<1, 1, 1, 1, 1, 1, 1, 1>(th_d1, th_d1, 3);
       wave_sync();
       for (int c = 0; c < 3; ++c)  // G = c0 . d1
         if (c == 0)
-          cv4<2, 2, 0, 0, 1, 1, 1, 1, false, NT>(c0, d1, gg, T(1), lane);
+          cv4m<2, 2, 0, 0, 1, 1, 1, 1, false, NT>(slice(c0, c, 9), slice(d1, c, 16), gg, T(1), lane);
         else
-          cv4<2, 2, 0, 0, 1, 1, 1, 1, true, NT>(c0 + 9 * c, d1 + 16 * c, gg, T(1), lane);
+          cv4m<2, 2, 0, 0, 1, 1, 1, 1, true, NT>(slice(c0, c, 9), slice(d1, c, 16), gg, T(1), lane);
+      const T th_gg = th_cv4<2, 2, 0, 0, 1, 1, 1, 1>(th_c0, th_d1, 3);
       wave_sync();
-      T* const gu = B + ILay::GU;
-      T* const gv = B + ILay::GV;
-      T* const gk = B + ILay::GK;
-      T* const gl = B + ILay::GL;
-      deriv4<3, 3, 1, 1, 0, NT>(gg, gu, lane);
-      deriv4<3, 3, 1, 1, 1, NT>(gg, gv, lane);
-      deriv4<3, 3, 1, 1, 2, NT>(gg, gk, lane);
-      deriv4<3, 3, 1, 1, 3, NT>(gg, gl, lane);
+      const TP<T> gu = tpat(B, ILay::GU, 48), gv = tpat(B, ILay::GV, 48), gk = tpat(B, ILay::GK, 32),
+                  gl = tpat(B, ILay::GL, 32);
+      deriv4m<3, 3, 1, 1, 0, NT>(gg, gu, lane);
+      deriv4m<3, 3, 1, 1, 1, NT>(gg, gv, lane);
+      deriv4m<3, 3, 1, 1, 2, NT>(gg, gk, lane);
+      deriv4m<3, 3, 1, 1, 3, NT>(gg, gl, lane);
+      const T th_gd = th_gg + T(3) * eps;
       T glo, ghi, hlo, hhi;
       poly_range<1, 1, T, NT>(g.v, g.m, th_g, &glo, &ghi, lane);
       poly_range<2, 2, T, NT>(dd.v, dd.m, th_nn, &hlo, &hhi, lane);
@@ -458,51 +593,44 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
       const T klo = k * (T(1) - T(16) * eps), khi = k * (T(1) + T(16) * eps);
       // local derivatives: the ratio carries (w_u w_v) / (w_uk w_vk)
       const T wscale = (u1 - u0) * (v1 - v0) / (wk * wl);
-      T* const a0sq = B + ILay::A0SQ;
-      T* const a1sq = B + ILay::A1SQ;
-      T* const F = B + ILay::F;
-      T* const fu = B + ILay::FU;
-      T* const fv = B + ILay::FV;
-      T* const fk = B + ILay::FK;
-      T* const fl = B + ILay::FL;
-      T* const j1 = B + ILay::J1;
-      T* const jk = B + ILay::JK;
-      T* const j1e = B + ILay::J1E;
-      T* const jke = B + ILay::JKE;
+      const TP<T> a0sq = tpat(B, ILay::A0SQ, 25), a1sq = tpat(B, ILay::A1SQ, 225), F = tpat(B, ILay::F, 441);
+      const TP<T> fu = tpat(B, ILay::FU, 378), fv = tpat(B, ILay::FV, 378), fk = tpat(B, ILay::FK, 294),
+                  fl = tpat(B, ILay::FL, 294);
+      const TP<T> j1 = tpat(B, ILay::J1, 1296), jk = tpat(B, ILay::JK, 900), j1e = tpat(B, ILay::J1E, 1600),
+                  jke = tpat(B, ILay::JKE, 1600);
+      const T th_a0sq = th_cv4<2, 2, 0, 0, 2, 2, 0, 0>(th_c0, th_c0, 1);
+      const T th_a1sq = th_cv4<2, 2, 1, 1, 2, 2, 1, 1>(th_c1, th_c1, 1);
+      // eta is an FP32 input, so eta^2 is exact in FP64
+      const T th_F = max(th_cv4<2, 2, 0, 0, 4, 4, 2, 2>(th_nn, th_a1sq, 2), th_cv4<2, 2, 2, 2, 4, 4, 0, 0>(th_d1d1, th_a0sq, 2));
+      const T th_fd = th_F + T(3) * eps;
+      const T th_j = max(th_cv4<5, 6, 2, 2, 3, 2, 1, 1>(th_fd, th_gd, 2), th_cv4<6, 6, 1, 2, 3, 3, 1, 0>(th_fd, th_gd, 2));
+      const T th_je = th_elev4<1, 1, 1, 1>(th_j);
       T Elo = T(0), Ehi = T(INFINITY);
       for (int bax = 0; bax < 2; ++bax) {  // b = (1,0,0), then (0,1,0)
         wave_sync();
-        const T* a0 = c0 + 9 * bax;
-        const T* a1 = c1 + 36 * bax;
-        cv4<2, 2, 0, 0, 2, 2, 0, 0, false, NT>(a0, a0, a0sq, T(1), lane);
-        cv4<2, 2, 1, 1, 2, 2, 1, 1, false, NT>(a1, a1, a1sq, T(1), lane);
+        const TP<T> a0 = slice(c0, bax, 9), a1 = slice(c1, bax, 36);
+        cv4m<2, 2, 0, 0, 2, 2, 0, 0, false, NT>(a0, a0, a0sq, T(1), lane);
+        cv4m<2, 2, 1, 1, 2, 2, 1, 1, false, NT>(a1, a1, a1sq, T(1), lane);
         wave_sync();
         // F = |d0|^2 a1^2 - eta^2 |d1|^2 a0^2
-        cv4<2, 2, 0, 0, 4, 4, 2, 2, false, NT>(dd.v, a1sq, F, T(1), lane);
-        cv4<2, 2, 2, 2, 4, 4, 0, 0, true, NT>(d1d1, a0sq, F, -(eta * eta), lane);
+        cv4m<2, 2, 0, 0, 4, 4, 2, 2, false, NT>(dd, a1sq, F, T(1), lane);
+        cv4m<2, 2, 2, 2, 4, 4, 0, 0, true, NT>(d1d1, a0sq, F, -(eta * eta), lane);
         wave_sync();
-        deriv4<6, 6, 2, 2, 0, NT>(F, fu, lane);
-        deriv4<6, 6, 2, 2, 1, NT>(F, fv, lane);
-        deriv4<6, 6, 2, 2, 2, NT>(F, fk, lane);
-        deriv4<6, 6, 2, 2, 3, NT>(F, fl, lane);
+        deriv4m<6, 6, 2, 2, 0, NT>(F, fu, lane);
+        deriv4m<6, 6, 2, 2, 1, NT>(F, fv, lane);
+        deriv4m<6, 6, 2, 2, 2, NT>(F, fk, lane);
+        deriv4m<6, 6, 2, 2, 3, NT>(F, fl, lane);
         wave_sync();
         // det J_1 = F_u G_v - F_v G_u (8,8,3,3), det J_k = F_uk G_vk - F_vk G_uk (9,9,2,2)
-        cv4<5, 6, 2, 2, 3, 2, 1, 1, false, NT>(fu, gv, j1, T(1), lane);
-        cv4<6, 5, 2, 2, 2, 3, 1, 1, true, NT>(fv, gu, j1, T(-1), lane);
-        cv4<6, 6, 1, 2, 3, 3, 1, 0, false, NT>(fk, gl, jk, T(1), lane);
-        cv4<6, 6, 2, 1, 3, 3, 0, 1, true, NT>(fl, gk, jk, T(-1), lane);
+        cv4m<5, 6, 2, 2, 3, 2, 1, 1, false, NT>(fu, gv, j1, T(1), lane);
+        cv4m<6, 5, 2, 2, 2, 3, 1, 1, true, NT>(fv, gu, j1, T(-1), lane);
+        cv4m<6, 6, 1, 2, 3, 3, 1, 0, false, NT>(fk, gl, jk, T(1), lane);
+        cv4m<6, 6, 2, 1, 3, 3, 0, 1, true, NT>(fl, gk, jk, T(-1), lane);
         wave_sync();
-        elev4<8, 8, 3, 3, 1, 1, 0, 0, NT>(j1, j1e, lane);
-        elev4<9, 9, 2, 2, 0, 0, 1, 1, NT>(jk, jke, lane);
+        elev4m<8, 8, 3, 3, 1, 1, 0, 0, NT>(j1, j1e, lane);
+        elev4m<9, 9, 2, 2, 0, 0, 1, 1, NT>(jk, jke, lane);
         wave_sync();
-        const RB<T> rb = ratio_bound_fn<T, NT>(
-            N4<9, 9, 3, 3>::n,
-            [&](int o, T& p, T& ep, T& q, T& eq) {
-              p = jke[o];
-              q = j1e[o];
-              ep = eq = T(0);
-            },
-            final, lane);
+        const RB<T> rb = ratio4m<T, NT>(N4<9, 9, 3, 3>::n, jke, th_je, j1e, th_je, true, lane);
         T rlo, rhi;
         abs_bound(rb, &rlo, &rhi);
         rlo = down(rlo * wscale);

@@ -349,16 +349,22 @@ struct RootSum {
 // with (z1, z2) from Philox streams 3 and 4 of (seed, point, tuple), written
 // over x0 in the pair's copy of the tuple record.  Area lights come with the
 // single reflection only, whose tuple is emitter * n_tri + triangle.
-__device__ __forceinline__ void pair_light_point(const QueryArgs& a, float* rec, int64_t i, uint32_t T) {
-  if (!a.sc.eedge) return;
+// The light point of a selected pair of an area-light scene (Philox streams 3
+// and 4 of (seed, point, tuple)): the FP64 point goes to the polish and the
+// irradiance, its FP32 rounding into the pair's record copy for the FP32
+// iterations.
+__device__ __forceinline__ V3<double> pair_light_point(const QueryArgs& a, float* rec, int64_t i, uint32_t T) {
   const PointReq pr = point_req(a, i);
   const uint32_t tk = tuple_key(a, T);
   const double z1 = sample_stream(pr.seed, pr.key, tk, 3u), z2 = sample_stream(pr.seed, pr.key, tk, 4u);
   const int64_t e = int64_t(T) / a.sc.n_tri, ne = a.sc.n_emit;
+  double x[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-    rec[18 + c] = float(double(rec[18 + c]) + z1 * double(a.sc.eedge[c * ne + e]) +
-                        z2 * double(a.sc.eedge[(3 + c) * ne + e]));
+  for (int c = 0; c < 3; ++c) {
+    x[c] = double(rec[18 + c]) + z1 * double(a.sc.eedge[c * ne + e]) + z2 * double(a.sc.eedge[(3 + c) * ne + e]);
+    rec[18 + c] = float(x[c]);
+  }
+  return mk(x[0], x[1], x[2]);
 }
 
 template <int CH>
@@ -377,7 +383,9 @@ __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target&
   }
   const uint32_t lb = __float_as_uint(rec[22]), le = __float_as_uint(rec[23]);
   if (lb == le) return 0.0;
-  if constexpr (!RR) pair_light_point(a, rec, tg.pt, T);
+  V3<double> xl = mk(0.0, 0.0, 0.0);
+  if constexpr (!RR)
+    if (a.sc.eedge) xl = pair_light_point(a, rec, tg.pt, T);
   const TupleGeom<float> Gf = tuple_geom_rec<float, RR>(rec, a.sc);
   RootSum rs;
   for (uint32_t k = lb; k < le; ++k) {
@@ -386,7 +394,8 @@ __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target&
     Start32 st = start_of(a.lcode[k], rec[24], rec[25], rec[26], rec[27]);
     ++wc.starts;
     if (newton32<CH>(Gf, tg.u, tg.v, st, 20, wc) != 2 || !worth_polish(st)) continue;
-    const TupleGeom<double> Gd = tuple_geom_rec<double, RR>(rec, a.sc);
+    TupleGeom<double> Gd = tuple_geom_rec<double, RR>(rec, a.sc);
+    if (!RR && a.sc.eedge) Gd.x0 = xl;
     double ud, vd, E;
     if (polish64<CH>(Gd, tg.ud, tg.vd, st.u, st.v, ud, vd, E, wc)) rs.add(ud, vd, E, wc);
   }
@@ -872,11 +881,12 @@ constexpr int kCand = 128;  // FP32 roots waiting for the polish; at most 127
 constexpr int kRes = 96;    // accepted roots of the 64 pairs (about 7 on average)
 constexpr uint32_t kRedoCap = 16384;  // listed pairs to redo per query
 
-template <int CH>
+template <int CH, bool AREA = false>
 struct NewtonPool {
   static constexpr int NF = CH == BBC_CHAIN_RR ? 48 : 28;  // record floats Newton reads
   static constexpr int RS = NF + 1;                         // odd row stride: rows of different pairs do not share banks
   float rec[BBC_WAVE * RS];
+  double lx[AREA ? BBC_WAVE : 1], ly[AREA ? BBC_WAVE : 1], lz[AREA ? BBC_WAVE : 1];  // FP64 light points
   float tu[BBC_WAVE], tv[BBC_WAVE];
   double tud[BBC_WAVE], tvd[BBC_WAVE];
   uint32_t lb[BBC_WAVE], lscan[BBC_WAVE + 1];
@@ -896,7 +906,7 @@ template <int CH, bool AREA = false>
 __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
                                                           int steps, uint32_t res_cap) {
   constexpr bool RR = CH == BBC_CHAIN_RR;
-  using Pool = NewtonPool<CH>;
+  using Pool = NewtonPool<CH, AREA>;
   constexpr int NF = Pool::NF, RS = Pool::RS, NREC = RR ? kRecFloatsRR : kRecFloats;
   __shared__ Pool L;
   const QueryArgs& a = s.q;
@@ -982,7 +992,12 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
           R[4 * q + 2] = rq[q].z;
           R[4 * q + 3] = rq[q].w;
         }
-        if constexpr (AREA) pair_light_point(a, R, Pt, T);
+        if constexpr (AREA) {
+          const V3<double> xl = pair_light_point(a, R, Pt, T);
+          L.lx[lane] = xl.x;
+          L.ly[lane] = xl.y;
+          L.lz[lane] = xl.z;
+        }
       }
       fetch_rest(batch + stride);
       stored = true;
@@ -998,7 +1013,8 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
       if (uint32_t(lane) < n) {
         p = L.cp[lane];
         kk = L.ck[lane];
-        const TupleGeom<double> Gd = tuple_geom_rec<double, RR>(&L.rec[p * RS], a.sc);
+        TupleGeom<double> Gd = tuple_geom_rec<double, RR>(&L.rec[p * RS], a.sc);
+        if constexpr (AREA) Gd.x0 = mk(L.lx[p], L.ly[p], L.lz[p]);
         ok = polish64<CH>(Gd, L.tud[p], L.tvd[p], L.cu[lane], L.cv[lane], ud, vd, E, wc);
       }
       const uint64_t m = __ballot(ok);

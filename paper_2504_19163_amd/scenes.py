@@ -198,12 +198,14 @@ def displaced_sphere(levels=7, amp=0.02, seed_offset=2):
 
 
 def water_surface(m=512, n_waves=32, n_lights=4, eta=1.0 / 1.5, seed_offset=3, amp=(0.01, 0.05),
-                  wavelength=(0.05, 0.5), amp_scale=1.0):
+                  wavelength=(0.05, 0.5), amp_scale=1.0, crop=None):
     """Single refraction through a water surface: (m+1)^2 vertices on [-1,1]^2
     (2 m^2 triangles), height = sum of n_waves seeded sine waves (amplitude and
     wavelength uniform in the given ranges, random direction and phase),
     analytic normals facing up (the incident side); n_lights unit point lights at
-    xy ~ U[-1,1]^2, z ~ U[2,4]; receiver (pool floor) z = -1 over [-1,1]^2."""
+    xy ~ U[-1,1]^2, z ~ U[2,4]; receiver (pool floor) z = -1 over [-1,1]^2.
+    crop = (i0, j0, k) keeps only the k x k cells from vertex (i0, j0) on: the
+    same surface, lights and receiver at full resolution, 2 k^2 triangles."""
     rng = np.random.default_rng(SEED_BASE + seed_offset)
     a = rng.uniform(amp[0], amp[1], n_waves) * amp_scale
     lam = rng.uniform(wavelength[0], wavelength[1], n_waves)
@@ -221,13 +223,19 @@ def water_surface(m=512, n_waves=32, n_lights=4, eta=1.0 / 1.5, seed_offset=3, a
         dZx += a[s] * np.cos(arg) * k * math.cos(th[s])
         dZy += a[s] * np.cos(arg) * k * math.sin(th[s])
     N = _normalize(np.stack([-dZx, -dZy, np.ones_like(X)]))
+    name = f"water{m}x{m}"
+    if crop is not None:
+        i0, j0, k = crop
+        sl = (slice(i0, i0 + k + 1), slice(j0, j0 + k + 1))
+        X, Y, Z, N = X[sl], Y[sl], Z[sl], N[(slice(None),) + sl]
+        name += f"_crop{i0}_{j0}_{k}"
     pos, nrm = _grid_triangles(X, Y, Z, N)
     lx = rng.uniform(-1, 1, n_lights)
     ly = rng.uniform(-1, 1, n_lights)
     lz = rng.uniform(2, 4, n_lights)
     return _scene("T", pos, nrm, np.stack([lx, ly, lz]), np.ones(n_lights),
                   [-1.0, -1.0, -1.0], [2.0, 0.0, 0.0], [0.0, 2.0, 0.0], eta=eta,
-                  name=f"water{m}x{m}")
+                  name=name)
 
 
 def facing_walls(m=64, amp=0.03, seed_offset=4):

@@ -2,8 +2,9 @@
 are two more axes of every polynomial, and a query draws one light point per
 selected pair from Philox streams 3 and 4) against the FP64 oracle: tree
 shape, every leaf's position and irradiance bound against the oracle's bound
-of the same box (both taken at face value, so they agree to the bound
-tolerance), the grid and the estimates with the same light-point draws."""
+of the same box (rounded outward: containing the oracle's, within the bound
+tolerance), the grid and the estimates with the same light-point draws (the
+polish takes the FP64 light point, so estimates agree to 1e-5)."""
 import gpu_checks
 import numpy as np
 import pytest
@@ -48,7 +49,9 @@ def test_area_tree_and_bounds(bbc, orc, built, case):
     print(case, "leaves", len(L["tuple"]), "oracle", len(OL["tuple"]), flush=True)
     assert len(L["tuple"]) > 0
     assert gpu_checks.keyset(L) == gpu_checks.keyset(OL)
-    gpu_checks.check_leaf_bounds(orc, osc, L, range(len(L["tuple"])), e_face_value=True, uk_face_value=True)
+    # position and irradiance bounds carry rounding control: they contain the
+    # oracle's and exceed them by at most the tolerance
+    gpu_checks.check_leaf_bounds(orc, osc, L, range(len(L["tuple"])))
     info, st = B.info(), Ob.stats()
     assert info["n_live_tuples"] == st["live_tuples"]
     assert info["n_inf_leaves"] == st["inf_leaves"]
@@ -84,7 +87,7 @@ def test_area_query_matches_oracle(bbc, orc, built, case, mode, omode):
     assert np.array_equal(st[:, 0], ost[:, 0])
     assert np.array_equal(st[:, 1], ost[:, 1])
     assert np.count_nonzero(OE) > 50
-    np.testing.assert_allclose(E, OE, rtol=1e-4, atol=1e-12)
+    np.testing.assert_allclose(E, OE, rtol=1e-5, atol=1e-12)
     Ef, _ = B.query(torch.as_tensor(pts, device="cuda"), 8, 13, mode=m & ~bbc.QUERY_STAGED)
     np.testing.assert_allclose(Ef.cpu().numpy().astype(np.float64), E, rtol=1e-6, atol=1e-12)
 

@@ -1,0 +1,215 @@
+"""Oracle parity of the refraction and two-reflection workloads at full size
+(Sec. 6.1 tuple construction; Sec. 6.3 bounding correctness), where the
+oracle cannot build the whole hierarchy in a test's time:
+
+  * two reflections (8192 + 8192 wall triangles, 67.1 M candidate pairs): the
+    constructed pair list equals the oracle's tuple construction, bit for bit,
+    for 256 seeded first triangles over all 8192 second triangles;
+  * sampled leaves of the full builds (water surface 524288 triangles x 4
+    lights, facing walls at depth 5): each leaf's bound against the oracle's
+    bound of the very same box;
+  * sampled shading points: the GPU's exhaustive estimate (every candidate of
+    the point's list with P = 1) against the sum, over that list, of the
+    oracle's brute-force roots (dense multi-start Newton in FP64): equal to
+    1e-5 on at least 95 % of the lit points, and never a root the brute force
+    does not find;
+  * a full-resolution crop of the water surface (64 x 64 cells of the 512 x 512
+    grid, 8192 triangles x 4 lights) that the oracle builds whole: the same
+    tree, grid and query results (up to leaves decided within rounding of a
+    stop threshold, at most 0.1 % of them, and the points whose lists they
+    change);
+  * the staged query's redo path (a small result buffer sends the pairs with
+    the most roots through k_stage_redo) against the oracle's estimates.
+Each test prints what it checks before its GPU calls."""
+import concurrent.futures as cf
+import os
+
+import gpu_checks
+import numpy as np
+import pytest
+
+from paper_2504_19163_amd import scenes as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+@pytest.fixture(scope="module")
+def bbc():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2504_19163_amd import bbc as B
+    B.lib()
+    return B
+
+
+@pytest.fixture(scope="module")
+def walls(bbc, orc):
+    sc = S.facing_walls(64)
+    print("building the facing walls (depth 5)", flush=True)
+    B = bbc.Bounds(bbc.DeviceScene(sc), dict(max_depth=5, alpha=10.0))
+    yield sc, orc.OracleScene(sc), B
+    B.free()
+
+
+@pytest.fixture(scope="module")
+def water(bbc, orc):
+    sc = S.water_surface(m=512, amp_scale=0.04)
+    print("building the water surface (depth 6)", flush=True)
+    B = bbc.Bounds(bbc.DeviceScene(sc), dict(max_depth=6))
+    yield sc, orc.OracleScene(sc), B
+    B.free()
+
+
+def test_walls_pair_list_matches_oracle(orc, walls):
+    sc, osc, B = walls
+    n1, n2 = sc["pos"].shape[1], sc["pos2"].shape[1]
+    pairs = B.tuples()
+    assert len(pairs) > 10000 and np.all(np.diff(pairs) > 0)
+    t1_of = pairs // n2
+    rng = np.random.default_rng(21)
+    firsts = rng.choice(n1, 256, replace=False)
+    print("pair lists of", len(firsts), "first triangles", flush=True)
+    with cf.ThreadPoolExecutor(THREADS) as ex:
+        lists = list(ex.map(lambda t1: orc.pair_list(osc, 0, int(t1)), firsts))
+    n_pairs = 0
+    for t1, ol in zip(firsts, lists):
+        gl = pairs[t1_of == t1] % n2
+        assert np.array_equal(gl, ol), (int(t1), len(gl), len(ol))
+        n_pairs += len(ol)
+    assert n_pairs > 100
+
+
+def _leaf_sample(L, n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.choice(len(L["tuple"]), min(n, len(L["tuple"])), replace=False)
+
+
+def test_water_fullsize_leaves_match_oracle(orc, water):
+    sc, osc, B = water
+    L = B.leaves()
+    idx = _leaf_sample(L, 1500, 3)
+    print("water leaves", len(L["tuple"]), "sampled", len(idx), flush=True)
+    parts = np.array_split(idx, THREADS)
+    with cf.ThreadPoolExecutor(THREADS) as ex:
+        list(ex.map(lambda p: gpu_checks.check_leaf_bounds(orc, osc, L, p), parts))
+
+
+def test_walls_fullsize_leaves_match_oracle(orc, walls):
+    sc, osc, B = walls
+    L = B.leaves()
+    idx = _leaf_sample(L, 1500, 4)
+    print("walls leaves", len(L["tuple"]), "sampled", len(idx), flush=True)
+    parts = np.array_split(idx, THREADS)
+    # the two-reflection irradiance ratio is taken at face value on both sides
+    with cf.ThreadPoolExecutor(THREADS) as ex:
+        list(ex.map(lambda p: gpu_checks.check_leaf_bounds(orc, osc, L, p, e_face_value=True), parts))
+
+
+def _candidates(B, G, us, vs):
+    """Each point's candidate list in the oracle's tuple numbering (the grid
+    export reports two-reflection pairs by their pair numbers)."""
+    off, gt, ge = B.grid()
+    out = []
+    for u, v in zip(us, vs):
+        c = min(G - 1, int(np.floor(u * G))) * G + min(G - 1, int(np.floor(v * G)))
+        out.append(np.concatenate([gt[off[c]:off[c + 1]], gt[off[G * G]:off[G * G + 1]]]).astype(np.int64))
+    return out
+
+
+def _brute_sum(orc, osc, U, x, lattice):
+    return float(sum(orc.tuple_roots(osc, int(t), x, lattice=lattice)[:, 2].sum() for t in U))
+
+
+def _exhaustive_vs_brute(bbc, orc, sc, osc, B, n_pts, seed, lattice):
+    G = 512
+    pts = S.random_points(sc, n_pts, seed=seed)
+    E, st = B.query(torch.as_tensor(pts, device="cuda"), 1, 0, mode=bbc.QUERY_STAGED | bbc.QUERY_EXHAUSTIVE,
+                    stats=True)
+    E = E.cpu().numpy().astype(np.float64)
+    q0, f1, f2 = (sc[k].astype(np.float64) for k in ("q0", "f1", "f2"))
+    us = (pts[0] - q0[0]) / f1[0]
+    vs = (pts[1] - q0[1]) / f2[1]
+    lists = _candidates(B, G, us, vs)
+    assert all(len(U) == int(n) for U, n in zip(lists, st[:, 0].cpu().numpy()))
+    with cf.ThreadPoolExecutor(THREADS) as ex:
+        ref = np.array(list(ex.map(lambda k: _brute_sum(orc, osc, lists[k], pts[:, k].astype(float), lattice),
+                                   range(n_pts))))
+    lit = ref > 0
+    assert np.all(E <= ref * (1 + 1e-5) + 1e-12), "a root the brute force does not find"
+    close = np.abs(E - ref) <= 1e-5 * np.abs(ref) + 1e-12
+    return lit.sum(), close[lit].mean()
+
+
+def test_water_fullsize_exhaustive_matches_brute_force(bbc, orc, water):
+    sc, osc, B = water
+    print("water: 500 points, brute-force roots over each candidate list", flush=True)
+    n_lit, frac = _exhaustive_vs_brute(bbc, orc, sc, osc, B, 500, 31, lattice=16)
+    assert n_lit >= 400
+    assert frac >= 0.95, frac
+
+
+def test_walls_fullsize_exhaustive_matches_brute_force(bbc, orc, walls):
+    sc, osc, B = walls
+    print("walls: 48 points, brute-force roots over each candidate list", flush=True)
+    n_lit, frac = _exhaustive_vs_brute(bbc, orc, sc, osc, B, 48, 32, lattice=12)
+    assert n_lit >= 30
+    assert frac >= 0.95, frac
+
+
+def test_water_crop_matches_oracle_build(bbc, orc):
+    sc = S.water_surface(m=512, amp_scale=0.04, crop=(192, 192, 64))
+    params = dict(max_depth=6)
+    print("water crop: 8192 triangles x 4 lights, oracle build", flush=True)
+    B = bbc.Bounds(bbc.DeviceScene(sc), params)
+    osc = orc.OracleScene(sc)
+    Ob = orc.OracleBuild(osc, params, n_threads=THREADS)
+    L = B.leaves()
+    gk, ok = gpu_checks.keyset(L), gpu_checks.keyset(Ob.leaves())
+    # a leaf decided within rounding of a stop threshold may differ
+    assert len(gk ^ ok) <= 1e-3 * len(ok)
+    gpu_checks.check_leaf_bounds(orc, osc, L, _leaf_sample(L, 800, 5))
+    off, gt, ge = B.grid()
+    G = 512
+    rng = np.random.default_rng(6)
+    n_same = 0
+    cells = rng.choice(G * G, 3000, replace=False)
+    for c in cells:
+        ot, oe = Ob.cell_list(*divmod(int(c), G))
+        n_same += np.array_equal(gt[off[c]:off[c + 1]].astype(np.int64), ot)
+    assert n_same >= 0.99 * len(cells)
+    gpu_checks.check_cover_list(off, gt, ge, Ob, G)
+    pts = S.receiver_points(sc, 128)
+    for mode, omode, W in ((bbc.QUERY_STAGED | bbc.QUERY_EXHAUSTIVE, 1, 1), (bbc.QUERY_STAGED, 0, 64)):
+        E, st = B.query(torch.as_tensor(pts, device="cuda"), W, 9, mode=mode, stats=True)
+        OE, ost = Ob.query(pts, W, 9, mode=omode, n_threads=THREADS)
+        st = st.cpu().numpy()
+        same = st[:, 0] == ost[:, 0]
+        assert same.mean() >= 0.99
+        assert np.array_equal(st[same, 1], ost[same, 1])
+        assert np.count_nonzero(OE) > 1000
+        np.testing.assert_allclose(E.cpu().numpy().astype(np.float64)[same], OE[same], rtol=1e-5, atol=1e-12)
+    B.free()
+
+
+def test_redo_path_matches_oracle(bbc, orc):
+    """A result buffer of 2 roots per batch of 64 pairs sends most pairs with
+    roots through the redo kernel; its estimates must still be the oracle's."""
+    sc = S.heightfield_mirror(16)
+    params = dict(max_depth=4)
+    B = bbc.Bounds(bbc.DeviceScene(sc), params)
+    Ob = orc.OracleBuild(orc.OracleScene(sc), params)
+    pts = S.receiver_points(sc, 64)
+    OE, ost = Ob.query(pts, 16, 3, mode=0)
+    B.set_tuning(bbc.TUNE_NEWTON_RESULTS, 2)
+    print("redo path: 4096 points, W = 16", flush=True)
+    E, st, hs = B.query(torch.as_tensor(pts, device="cuda"), 16, 3, mode=bbc.QUERY_STAGED, stats=True,
+                        host_stats=True)
+    st = st.cpu().numpy()
+    assert hs["n_roots"] > 200
+    assert np.array_equal(st[:, 1], ost[:, 1])
+    assert np.array_equal(st[:, 2], ost[:, 2])
+    np.testing.assert_allclose(E.cpu().numpy().astype(np.float64), OE, rtol=1e-5, atol=1e-12)
+    B.free()
