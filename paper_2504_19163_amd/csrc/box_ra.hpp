@@ -8,7 +8,7 @@
 //   u_k = Pu/Q, v_k = Pv/Q (Eq. eq_rct)   Pu, Pv (4,4,1,1), Q (3,3,1,1),
 //   E = I0 (A1/A_k) G1 |Q^3 / det M|   (Sec. 4.4), M = [[Q, Pu, Pv],
 //   [Q_u, Pu_u, Pv_u], [Q_v, Pu_v, Pv_v]] with u-, v-derivatives only:
-//   det M (10,10,3,3) over Q^3 raised to the same degree.
+//   det M (9,9,3,3) and Q^3 both raised to (10,10,3,3).
 // FP64 in scaled Bernstein form; every tensor carries magnitudes and an error
 // factor theta (|computed - exact| <= theta * m), so the position and
 // irradiance bounds are rounded outward (Eq. eq_bbound).
@@ -25,10 +25,13 @@ struct RALay {
   static constexpr int DT = 117, CC = 309, SF1 = 501, PU = 513, PV = 613;  // 3x64, 3x64, 3x4, 100, 100
   static constexpr int Q = 713, TN = 777, TNE = 781, QE = 845;             // 64, 4, 64, 100
   static constexpr int POS_END = 945;
-  static constexpr int GG = 945, HH = 961, QU = 1042, QV = 1090;           // 16, 81, 48, 48
-  static constexpr int PUU = 1138, PUV = 1218, PVU = 1298, PVV = 1378;     // 80 each
-  static constexpr int AM = 1458, BM = 2034, CM = 2475, DETM = 2916;       // 576, 441, 441, 1936
-  static constexpr int Q2 = 4852, Q3 = 5293, Q3E = 6893, END = 8829;       // 441, 1600, 1936
+  static constexpr int GG = 945, HH = 961, NNU = 1042, NNV = 1046;        // 16, 81, 4, 4
+  static constexpr int DNU = 1050, DNV = 1066, DTU = 1082, DTV = 1190;     // 16, 16, 3x36, 3x36
+  static constexpr int CCU = 1298, CCV = 1406, QU = 1514, QV = 1550;       // 3x36, 3x36, 36, 36
+  static constexpr int PUU = 1586, PUV = 1650, PVU = 1714, PVV = 1778;     // 64 each
+  static constexpr int AM = 1842, BM = 2283, CM = 2607, Q2 = 2931;         // 441, 324, 324, 441
+  static constexpr int DETM = 3372, Q3 = 4972, Q3E = 6572, END = 8508;     // 1600, 1600, 1936
+  static constexpr int DETME = GG;                                         // 1936, over the dead GG .. CM
   static constexpr int mo(bool irr) { return irr ? END : POS_END; }
 };
 
@@ -166,12 +169,49 @@ __device__ __forceinline__ BoxOut eval_box_ra(const TupleGeom<T>& G, T u0, T u1,
   if constexpr (!IRR) {
     return out;
   } else {
-    // ---- irradiance bound (Sec. 4.4) over the box and the whole light
-    const TP<T> gg = at(RALay::GG), hh = at(RALay::HH), qu = at(RALay::QU), qv = at(RALay::QV);
+    // ---- irradiance bound (Sec. 4.4) over the box and the whole light.  The
+    // u-, v-derivatives of Q, Pu, Pv are formed by the product rule from the
+    // exact derivatives of the linear forms (d0_u = s_u = e1, n_u = dn1), not
+    // by differencing their coefficients (which cancels to O(w) of the terms
+    // and would inflate det M's rounding bound by (degree / w)^2); det M then
+    // has degree (9,9,3,3) and is elevated, with Q^3, to (10,10,3,3), the
+    // degree at which differencing would give it.
+    const TP<T> gg = at(RALay::GG), hh = at(RALay::HH), nnu = at(RALay::NNU), nnv = at(RALay::NNV);
+    const TP<T> dnu = at(RALay::DNU), dnv = at(RALay::DNV), dtu = at(RALay::DTU), dtv = at(RALay::DTV);
+    const TP<T> ccu = at(RALay::CCU), ccv = at(RALay::CCV), qu = at(RALay::QU), qv = at(RALay::QV);
     const TP<T> puu = at(RALay::PUU), puv = at(RALay::PUV), pvu = at(RALay::PVU), pvv = at(RALay::PVV);
+    const V3<T> e1 = G.e1, e2 = G.e2, dn1 = G.dn1, dn2 = G.dn2;
     for (int o = lane; o < 16; o += NT) {
       gg.v[o] = dot(mk(d0.v[o], d0.v[16 + o], d0.v[32 + o]), G.ng);
       gg.m[o] = d0.m[o] * fabs(G.ng.x) + d0.m[16 + o] * fabs(G.ng.y) + d0.m[32 + o] * fabs(G.ng.z);
+      // (d0.n)_u = e1.n + d0.dn1 over (u, v, z1, z2)
+      const int ij = o >> 2;
+      T su = T(0), sum = T(0), sv2 = T(0), svm = T(0);
+      for (int c = 0; c < 3; ++c) {
+        const T nc = nv.v[4 * c + ij], ncm = nv.m[4 * c + ij], dc = d0.v[16 * c + o], dcm = d0.m[16 * c + o];
+        su = fma(comp(e1, c), nc, fma(dc, comp(dn1, c), su));
+        sum += fabs(comp(e1, c)) * ncm + dcm * fabs(comp(dn1, c));
+        sv2 = fma(comp(e2, c), nc, fma(dc, comp(dn2, c), sv2));
+        svm += fabs(comp(e2, c)) * ncm + dcm * fabs(comp(dn2, c));
+      }
+      dnu.v[o] = su;
+      dnu.m[o] = sum;
+      dnv.v[o] = sv2;
+      dnv.m[o] = svm;
+    }
+    for (int o = lane; o < 4; o += NT) {  // (n.n)_u = 2 n.dn1
+      T su = T(0), sum = T(0), sv2 = T(0), svm = T(0);
+      for (int c = 0; c < 3; ++c) {
+        const T nc = nv.v[4 * c + o], ncm = nv.m[4 * c + o];
+        su = fma(T(2) * comp(dn1, c), nc, su);
+        sum += T(2) * fabs(comp(dn1, c)) * ncm;
+        sv2 = fma(T(2) * comp(dn2, c), nc, sv2);
+        svm += T(2) * fabs(comp(dn2, c)) * ncm;
+      }
+      nnu.v[o] = su;
+      nnu.m[o] = sum;
+      nnv.v[o] = sv2;
+      nnv.m[o] = svm;
     }
     for (int c = 0; c < 3; ++c) {
       if (c == 0)
@@ -179,52 +219,140 @@ __device__ __forceinline__ BoxOut eval_box_ra(const TupleGeom<T>& G, T u0, T u1,
       else
         cv4m<1, 1, 1, 1, 1, 1, 1, 1, true, NT>(slice(d0, c, 16), slice(d0, c, 16), hh, T(1), lane);
     }
-    deriv4m<3, 3, 1, 1, 0, NT>(q, qu, lane);
-    deriv4m<3, 3, 1, 1, 1, NT>(q, qv, lane);
-    deriv4m<4, 4, 1, 1, 0, NT>(pu, puu, lane);
-    deriv4m<4, 4, 1, 1, 1, NT>(pu, puv, lane);
-    deriv4m<4, 4, 1, 1, 0, NT>(pv, pvu, lane);
-    deriv4m<4, 4, 1, 1, 1, NT>(pv, pvv, lane);
     const T th_g = th_lin + T(8) * eps;  // the unit normal carries a few roundings of its own
     const T th_h = th_cv4<1, 1, 1, 1, 1, 1, 1, 1>(th_lin, th_lin, 3);
-    const T th_qd = th_q + T(3) * eps, th_pd = th_p + T(3) * eps;
+    const T th_nnu = th_lin + T(5) * eps, th_dnu = th_lin + T(8) * eps;
     wave_sync();
-    // A = Pu_u Pv_v - Pv_u Pu_v, Bm = Q_u Pv_v - Pv_u Q_v, Cm = Q_u Pu_v - Pu_u Q_v, Q^2
-    const TP<T> am = at(RALay::AM), bm = at(RALay::BM), cm = at(RALay::CM), q2 = at(RALay::Q2);
-    cv4m<3, 4, 1, 1, 4, 3, 1, 1, false, NT>(puu, pvv, am, T(1), lane);
-    cv4m<3, 4, 1, 1, 4, 3, 1, 1, true, NT>(pvu, puv, am, T(-1), lane);
-    cv4m<2, 3, 1, 1, 4, 3, 1, 1, false, NT>(qu, pvv, bm, T(1), lane);
-    cv4m<3, 4, 1, 1, 3, 2, 1, 1, true, NT>(pvu, qv, bm, T(-1), lane);
-    cv4m<2, 3, 1, 1, 4, 3, 1, 1, false, NT>(qu, puv, cm, T(1), lane);
-    cv4m<3, 4, 1, 1, 3, 2, 1, 1, true, NT>(puu, qv, cm, T(-1), lane);
-    cv4m<3, 3, 1, 1, 3, 3, 1, 1, false, NT>(q, q, q2, T(1), lane);
-    const T th_a = th_cv4<3, 4, 1, 1, 4, 3, 1, 1>(th_pd, th_pd, 2);
-    const T th_bc = max(th_cv4<2, 3, 1, 1, 4, 3, 1, 1>(th_qd, th_pd, 2), th_cv4<3, 4, 1, 1, 3, 2, 1, 1>(th_pd, th_qd, 2));
-    const T th_q2 = th_cv4<3, 3, 1, 1, 3, 3, 1, 1>(th_q, th_q, 1);
     T glo, ghi, hlo, hhi;
     range4m<1, 1, 1, 1, T, NT>(gg, th_g, &glo, &ghi, lane);
     range4m<2, 2, 2, 2, T, NT>(hh, th_h, &hlo, &hhi, lane);
+    // d~_u = (n.n)_u d0 + (n.n) e1 - 2 (d0.n)_u n - 2 (d0.n) dn1   (2,2,1,1)
+    for (int c = 0; c < 3; ++c) {
+      cv4m<1, 1, 0, 0, 1, 1, 1, 1, false, NT>(nnu, slice(d0, c, 16), slice(dtu, c, 36), T(1), lane);
+      cv4m<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(dnu, slice(nv, c, 4), slice(dtu, c, 36), T(-2), lane);
+      cv4m<1, 1, 0, 0, 1, 1, 1, 1, false, NT>(nnv, slice(d0, c, 16), slice(dtv, c, 36), T(1), lane);
+      cv4m<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(dnv, slice(nv, c, 4), slice(dtv, c, 36), T(-2), lane);
+      // the same lane owns each coefficient in the products above and here
+      for (int o = lane; o < 36; o += NT) {
+        const int ij = o >> 2;  // (n.n) is constant along z1, z2 (replicated in scaled form)
+        const TP<T> tu = slice(dtu, c, 36), tv = slice(dtv, c, 36);
+        tu.v[o] = fma(-T(2) * comp(dn1, c), dn.v[o], fma(comp(e1, c), nn.v[ij], tu.v[o]));
+        tu.m[o] += T(2) * fabs(comp(dn1, c)) * dn.m[o] + fabs(comp(e1, c)) * nn.m[ij];
+        tv.v[o] = fma(-T(2) * comp(dn2, c), dn.v[o], fma(comp(e2, c), nn.v[ij], tv.v[o]));
+        tv.m[o] += T(2) * fabs(comp(dn2, c)) * dn.m[o] + fabs(comp(e2, c)) * nn.m[ij];
+      }
+    }
+    const T th_dtu = max(max(th_cv4<1, 1, 0, 0, 1, 1, 1, 1>(th_nnu, th_lin, 4), th_cv4<1, 1, 1, 1, 1, 1, 0, 0>(th_dnu, th_lin, 4)),
+                         th_nn + T(2) * eps) +
+                     T(4) * eps;
     wave_sync();
-    // det M = Q A - Pu Bm + Pv Cm (10,10,3,3); Q^3 (9,9,3,3)
-    const TP<T> detm = at(RALay::DETM), q3 = at(RALay::Q3), q3e = at(RALay::Q3E);
-    cv4m<3, 3, 1, 1, 7, 7, 2, 2, false, NT>(q, am, detm, T(1), lane);
-    cv4m<4, 4, 1, 1, 6, 6, 2, 2, true, NT>(pu, bm, detm, T(-1), lane);
-    cv4m<4, 4, 1, 1, 6, 6, 2, 2, true, NT>(pv, cm, detm, T(1), lane);
+    for (int o = lane; o < 36; o += NT) {  // (d~ x f2)_u = d~_u x f2
+      const V3<T> af = mk(fabs(G.f2.x), fabs(G.f2.y), fabs(G.f2.z));
+      for (int w = 0; w < 2; ++w) {
+        const TP<T> t = w ? dtv : dtu, r = w ? ccv : ccu;
+        const V3<T> x = cross(mk(t.v[o], t.v[36 + o], t.v[72 + o]), G.f2);
+        const V3<T> m = mk(t.m[o], t.m[36 + o], t.m[72 + o]);
+        r.v[o] = x.x;
+        r.v[36 + o] = x.y;
+        r.v[72 + o] = x.z;
+        r.m[o] = m.y * af.z + m.z * af.y;
+        r.m[36 + o] = m.z * af.x + m.x * af.z;
+        r.m[72 + o] = m.x * af.y + m.y * af.x;
+      }
+    }
+    const T th_ccu = th_dtu + T(3) * eps;
+    wave_sync();
+    // Q_u = c_u.f1 (2,2,1,1); Pu_u = c_u.s + c.e1, Pv_u = (e1 x f1).d~ + (s x f1).d~_u (3,3,1,1)
+    {
+      const T* cuv[3] = {slice(ccu, 0, 36).v, slice(ccu, 1, 36).v, slice(ccu, 2, 36).v};
+      const T* cum[3] = {slice(ccu, 0, 36).m, slice(ccu, 1, 36).m, slice(ccu, 2, 36).m};
+      const T* cvv[3] = {slice(ccv, 0, 36).v, slice(ccv, 1, 36).v, slice(ccv, 2, 36).v};
+      const T* cvm[3] = {slice(ccv, 0, 36).m, slice(ccv, 1, 36).m, slice(ccv, 2, 36).m};
+      const T af1[3] = {G.f1.x, G.f1.y, G.f1.z};
+      combo<36, 3, false, T, NT>(cuv, cum, af1, qu.v, qu.m, lane);
+      combo<36, 3, false, T, NT>(cvv, cvm, af1, qv.v, qv.m, lane);
+    }
+    for (int c = 0; c < 3; ++c) {
+      if (c == 0) {
+        cv4m<2, 2, 1, 1, 1, 1, 0, 0, false, NT>(slice(ccu, c, 36), slice(sv, c, 4), puu, T(1), lane);
+        cv4m<2, 2, 1, 1, 1, 1, 0, 0, false, NT>(slice(ccv, c, 36), slice(sv, c, 4), puv, T(1), lane);
+        cv4m<1, 1, 0, 0, 2, 2, 1, 1, false, NT>(slice(sf1, c, 4), slice(dtu, c, 36), pvu, T(1), lane);
+        cv4m<1, 1, 0, 0, 2, 2, 1, 1, false, NT>(slice(sf1, c, 4), slice(dtv, c, 36), pvv, T(1), lane);
+      } else {
+        cv4m<2, 2, 1, 1, 1, 1, 0, 0, true, NT>(slice(ccu, c, 36), slice(sv, c, 4), puu, T(1), lane);
+        cv4m<2, 2, 1, 1, 1, 1, 0, 0, true, NT>(slice(ccv, c, 36), slice(sv, c, 4), puv, T(1), lane);
+        cv4m<1, 1, 0, 0, 2, 2, 1, 1, true, NT>(slice(sf1, c, 4), slice(dtu, c, 36), pvu, T(1), lane);
+        cv4m<1, 1, 0, 0, 2, 2, 1, 1, true, NT>(slice(sf1, c, 4), slice(dtv, c, 36), pvv, T(1), lane);
+      }
+    }
+    {
+      // e1 x f1 and e2 x f2 with the magnitudes of their products
+      const V3<T> g1 = cross(e1, G.f1), g2 = cross(e2, G.f1);
+      const V3<T> ae1 = mk(fabs(e1.x), fabs(e1.y), fabs(e1.z)), ae2 = mk(fabs(e2.x), fabs(e2.y), fabs(e2.z));
+      const V3<T> af1 = mk(fabs(G.f1.x), fabs(G.f1.y), fabs(G.f1.z));
+      const V3<T> g1m = mk(ae1.y * af1.z + ae1.z * af1.y, ae1.z * af1.x + ae1.x * af1.z, ae1.x * af1.y + ae1.y * af1.x);
+      const V3<T> g2m = mk(ae2.y * af1.z + ae2.z * af1.y, ae2.z * af1.x + ae2.x * af1.z, ae2.x * af1.y + ae2.y * af1.x);
+      // the same lane owns each coefficient in the products above and here
+      for (int o = lane; o < 64; o += NT) {
+        T a = puu.v[o], am2 = puu.m[o], b = puv.v[o], bm2 = puv.m[o];
+        T c2 = pvu.v[o], cm2 = pvu.m[o], d2 = pvv.v[o], dm2 = pvv.m[o];
+        for (int c = 0; c < 3; ++c) {
+          const T ccv2 = cc.v[64 * c + o], ccm2 = cc.m[64 * c + o], dtv2 = dt.v[64 * c + o], dtm2 = dt.m[64 * c + o];
+          a = fma(comp(e1, c), ccv2, a);
+          am2 += fabs(comp(e1, c)) * ccm2;
+          b = fma(comp(e2, c), ccv2, b);
+          bm2 += fabs(comp(e2, c)) * ccm2;
+          c2 = fma(comp(g1, c), dtv2, c2);
+          cm2 += comp(g1m, c) * dtm2;
+          d2 = fma(comp(g2, c), dtv2, d2);
+          dm2 += comp(g2m, c) * dtm2;
+        }
+        puu.v[o] = a;
+        puu.m[o] = am2;
+        puv.v[o] = b;
+        puv.m[o] = bm2;
+        pvu.v[o] = c2;
+        pvu.m[o] = cm2;
+        pvv.v[o] = d2;
+        pvv.m[o] = dm2;
+      }
+    }
+    const T th_qd = th_ccu + T(4) * eps;
+    const T th_pd = max(max(th_cv4<2, 2, 1, 1, 1, 1, 0, 0>(th_ccu, th_lin, 6), th_cv4<1, 1, 0, 0, 2, 2, 1, 1>(th_sf1, th_dtu, 6)),
+                        max(th_cc, th_dt) + T(4) * eps) +
+                    T(2) * eps;
+    wave_sync();
+    // A = Pu_u Pv_v - Pv_u Pu_v, Bm = Q_u Pv_v - Pv_u Q_v, Cm = Q_u Pu_v - Pu_u Q_v, Q^2
+    const TP<T> am = at(RALay::AM), bm = at(RALay::BM), cm = at(RALay::CM), q2 = at(RALay::Q2);
+    cv4m<3, 3, 1, 1, 3, 3, 1, 1, false, NT>(puu, pvv, am, T(1), lane);
+    cv4m<3, 3, 1, 1, 3, 3, 1, 1, true, NT>(pvu, puv, am, T(-1), lane);
+    cv4m<2, 2, 1, 1, 3, 3, 1, 1, false, NT>(qu, pvv, bm, T(1), lane);
+    cv4m<3, 3, 1, 1, 2, 2, 1, 1, true, NT>(pvu, qv, bm, T(-1), lane);
+    cv4m<2, 2, 1, 1, 3, 3, 1, 1, false, NT>(qu, puv, cm, T(1), lane);
+    cv4m<3, 3, 1, 1, 2, 2, 1, 1, true, NT>(puu, qv, cm, T(-1), lane);
+    cv4m<3, 3, 1, 1, 3, 3, 1, 1, false, NT>(q, q, q2, T(1), lane);
+    const T th_a = th_cv4<3, 3, 1, 1, 3, 3, 1, 1>(th_pd, th_pd, 2);
+    const T th_bc = max(th_cv4<2, 2, 1, 1, 3, 3, 1, 1>(th_qd, th_pd, 2), th_cv4<3, 3, 1, 1, 2, 2, 1, 1>(th_pd, th_qd, 2));
+    const T th_q2 = th_cv4<3, 3, 1, 1, 3, 3, 1, 1>(th_q, th_q, 1);
+    wave_sync();
+    // det M = Q A - Pu Bm + Pv Cm (9,9,3,3); Q^3 (9,9,3,3)
+    const TP<T> detm = at(RALay::DETM), q3 = at(RALay::Q3), q3e = at(RALay::Q3E), detme = at(RALay::DETME);
+    cv4m<3, 3, 1, 1, 6, 6, 2, 2, false, NT>(q, am, detm, T(1), lane);
+    cv4m<4, 4, 1, 1, 5, 5, 2, 2, true, NT>(pu, bm, detm, T(-1), lane);
+    cv4m<4, 4, 1, 1, 5, 5, 2, 2, true, NT>(pv, cm, detm, T(1), lane);
     cv4m<6, 6, 2, 2, 3, 3, 1, 1, false, NT>(q2, q, q3, T(1), lane);
-    const T th_detm = max(th_cv4<3, 3, 1, 1, 7, 7, 2, 2>(th_q, th_a, 3),
-                          max(th_cv4<4, 4, 1, 1, 6, 6, 2, 2>(th_p, th_bc, 3), th_cv4<4, 4, 1, 1, 6, 6, 2, 2>(th_p, th_bc, 3)));
+    const T th_detm = max(th_cv4<3, 3, 1, 1, 6, 6, 2, 2>(th_q, th_a, 3), th_cv4<4, 4, 1, 1, 5, 5, 2, 2>(th_p, th_bc, 3));
     const T th_q3 = th_cv4<6, 6, 2, 2, 3, 3, 1, 1>(th_q2, th_q, 1);
     wave_sync();
+    // det M's elevation overwrites the dead factors (GG .. CM)
+    elev4m<9, 9, 3, 3, 1, 1, 0, 0, NT>(detm, detme, lane);
     elev4m<9, 9, 3, 3, 1, 1, 0, 0, NT>(q3, q3e, lane);
+    const T th_detme = th_elev4<1, 1, 0, 0>(th_detm);
     const T th_q3e = th_elev4<1, 1, 0, 0>(th_q3);
     wave_sync();
-    const RB<T> rb = ratio4m<T, NT>(N4<10, 10, 3, 3>::n, q3e, th_q3e, detm, th_detm, true, lane);
+    const RB<T> rb = ratio4m<T, NT>(N4<10, 10, 3, 3>::n, q3e, th_q3e, detme, th_detme, true, lane);
     T rlo, rhi;
     abs_bound(rb, &rlo, &rhi);
-    // local u-, v-derivatives: the global ratio is the local one times w_u w_v
-    const T area = (u1 - u0) * (v1 - v0);
-    rlo = down(rlo * area * (T(1) - T(4) * eps));
-    rhi = isinf(rhi) ? rhi : up(rhi * area * (T(1) + T(4) * eps));
     const T aglo = (glo <= T(0) && ghi >= T(0)) ? T(0) : min(fabs(glo), fabs(ghi));
     const T aghi = max(fabs(glo), fabs(ghi));
     const T Glo = down(aglo / (hhi * sqrt(hhi)));

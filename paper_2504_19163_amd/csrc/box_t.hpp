@@ -309,12 +309,15 @@ __device__ __forceinline__ RB<T> ratio4m(int n, TP<T> p, T tp, TP<T> q, T tq, bo
 // part's live linear forms, d0.d0 and n_g.d0 (TLay::G); a tensor of n
 // coefficients takes 2n (values, then magnitudes).
 struct ILay {
-  static constexpr int D1 = TLay::G + 8, C0 = D1 + 96, C1 = C0 + 54, D1D1 = C1 + 216;  // (1,1,1,1)x3, (2,2,0,0)x3, (2,2,1,1)x3
-  static constexpr int GG = D1D1 + 162, GU = GG + 128, GV = GU + 96, GK = GV + 96;   // (2,2,2,2), G (3,3,1,1)
-  static constexpr int GL = GK + 64, A0SQ = GL + 64, A1SQ = A0SQ + 50, F = A1SQ + 450;
-  static constexpr int FU = F + 882, FV = FU + 756, FK = FV + 756, FL = FK + 588;    // F (6,6,2,2)
-  static constexpr int J1 = FL + 588, JK = J1 + 2592, J1E = JK + 1800, JKE = J1E + 3200;
-  static constexpr int END = JKE + 3200;
+  static constexpr int D1 = TLay::G + 8, C0 = D1 + 96, C1 = C0 + 54, D1D1 = C1 + 216;  // (1,1,1,1)x3, (2,2,0,0)x3, (2,2,1,1)x3, (2,2,2,2)
+  static constexpr int C0U = D1D1 + 162, C0V = C0U + 24, C1U = C0V + 24, C1V = C1U + 96;  // (1,1,0,0)x3, (1,1,1,1)x3
+  static constexpr int C1K = C1V + 96, C1L = C1K + 24, DE = C1L + 24, D1E = DE + 16;    // (1,1,0,0)x3, (1,1)x2, (1,1,1,1)x4
+  static constexpr int GU = D1E + 128, GV = GU + 72, GK = GV + 72, GL = GK + 18;        // (2,2,1,1), (2,2,0,0)
+  static constexpr int A0SQ = GL + 18, A0SQE = A0SQ + 50, A1SQ = A0SQE + 200;           // (4,4,0,0), (4,4,1,1), (4,4,2,2)
+  static constexpr int SU = A1SQ + 450, SV = SU + 32, TU = SV + 32, TV = TU + 288;       // (3,3,0,0), (3,3,2,2)
+  static constexpr int TK = TV + 288, TL = TK + 128, FU = TL + 128, FV = FU + 648;       // (3,3,1,1), (5,5,2,2)
+  static constexpr int FK = FV + 648, FL = FK + 288, J1 = FL + 288, JK = J1 + 2048;      // (5,5,1,1), (7,7,3,3)
+  static constexpr int J1E = JK + 512, JKE = J1E + 3200, END = JKE + 3200;              // (7,7,1,1), (9,9,3,3) x 2
 };
 
 template <class T, bool IRR>
@@ -530,27 +533,63 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     if (flags & BBC_FLAG_IMPLICIT_IRR) {
       // ---- irradiance by implicit differentiation (Sec. 4.4): F (Snell's law
       // along b) and G (coplanarity) over the box times U_k, |du1/du_k| =
-      // |det J_k / det J_1|, degree (9, 9, 3, 3); b = (1,0,0), (0,1,0),
-      // intervals intersected; every tensor with magnitudes, rounded outward
+      // |det J_k / det J_1|; b = (1,0,0), (0,1,0), intervals intersected.
+      // The partial derivatives of F and G are formed by the product rule from
+      // the exact derivatives of the linear forms (d0_u = e1, n_u = dn1,
+      // d1_u = -e1, d1_uk = f1, ...), not by differencing F's coefficients: a
+      // difference of neighbouring coefficients cancels to O(w) of its terms,
+      // and the rounding bound of det J_1 would grow by (degree / w)^2.  det J_1
+      // has degree (7,7,3,3) and det J_k (7,7,1,1); both are elevated to
+      // (9,9,3,3), the degree at which differencing F would give them, so the
+      // coefficient ratios are those of the same polynomials at that degree.
+      // Every tensor carries magnitudes; the bound is rounded outward.
       const T wk = uhi - ulo, wl = vhi - vlo;
       if (!(wk > T(0) && wl > T(0))) return out;
       const TP<T> d1 = tpat(B, ILay::D1, 48), c0 = tpat(B, ILay::C0, 27), c1 = tpat(B, ILay::C1, 108);
-      const TP<T> d1d1 = tpat(B, ILay::D1D1, 81), gg = tpat(B, ILay::GG, 64);
-      const TP<T> g = tpat(B, TLay::G, 4);
+      const TP<T> d1d1 = tpat(B, ILay::D1D1, 81), g = tpat(B, TLay::G, 4);
+      const TP<T> c0u = tpat(B, ILay::C0U, 12), c0v = tpat(B, ILay::C0V, 12);  // (1,1,0,0) x 3
+      const TP<T> c1u = tpat(B, ILay::C1U, 48), c1v = tpat(B, ILay::C1V, 48);  // (1,1,1,1) x 3
+      const TP<T> c1k = tpat(B, ILay::C1K, 12), c1l = tpat(B, ILay::C1L, 12);  // (1,1,0,0) x 3
+      const TP<T> de = tpat(B, ILay::DE, 8);     // d0.e1, d0.e2 (1,1,0,0)
+      const TP<T> d1e = tpat(B, ILay::D1E, 64);  // d1.e1, d1.e2, d1.f1, d1.f2 (1,1,1,1)
+      const V3<T> e1 = G.e1, e2 = G.e2, dn1 = G.dn1, dn2 = G.dn2, f1 = G.f1, f2 = G.f2;
       {
         const T* dv[3] = {dC(0).v, dC(1).v, dC(2).v};
         const T* dm[3] = {dC(0).m, dC(1).m, dC(2).m};
         const T ag[3] = {G.ng.x, G.ng.y, G.ng.z};
         combo<4, 3, false, T, NT>(dv, dm, ag, g.v, g.m, lane);
+        const T ae1[3] = {e1.x, e1.y, e1.z}, ae2[3] = {e2.x, e2.y, e2.z};
+        combo<4, 3, false, T, NT>(dv, dm, ae1, slice(de, 0, 4).v, slice(de, 0, 4).m, lane);
+        combo<4, 3, false, T, NT>(dv, dm, ae2, slice(de, 1, 4).v, slice(de, 1, 4).m, lane);
         // d1 = x_k - x1 = -(x1 - q0) + u_k f1 + v_k f2 at the 16 corners
         for (int o = lane; o < 48; o += NT) {
           const int c = o / 16, r = o - 16 * c, ij = r / 4, k = (r / 2) & 1, l = r & 1;
           const T uk = k ? uhi : ulo, vk = l ? vhi : vlo;
-          d1.v[o] = fma(vk, comp(G.f2, c), fma(uk, comp(G.f1, c), -sC(c).v[ij]));
-          d1.m[o] = fabs(vk) * fabs(comp(G.f2, c)) + fabs(uk) * fabs(comp(G.f1, c)) + sC(c).m[ij];
+          d1.v[o] = fma(vk, comp(f2, c), fma(uk, comp(f1, c), -sC(c).v[ij]));
+          d1.m[o] = fabs(vk) * fabs(comp(f2, c)) + fabs(uk) * fabs(comp(f1, c)) + sC(c).m[ij];
+        }
+        // component c of a x n + d0 x m at the four (u, v) corners, for constant a, m
+        auto cross_lin = [&](V3<T> a, V3<T> mv, TP<T> dst, int o) {
+          const int c = o / 4, ij = o - 4 * c, p = (c + 1) % 3, q = (c + 2) % 3;
+          const TP<T> np = nC(p), nq = nC(q), dp = dC(p), dq = dC(q);
+          // (a x n)_c = a_p n_q - a_q n_p,  (d0 x m)_c = d0_p m_q - d0_q m_p
+          dst.v[o] = fma(comp(a, p), nq.v[ij], -(comp(a, q) * np.v[ij])) +
+                     fma(dp.v[ij], comp(mv, q), -(dq.v[ij] * comp(mv, p)));
+          dst.m[o] = fabs(comp(a, p)) * nq.m[ij] + fabs(comp(a, q)) * np.m[ij] + dp.m[ij] * fabs(comp(mv, q)) +
+                     dq.m[ij] * fabs(comp(mv, p));
+        };
+        const V3<T> zero{T(0), T(0), T(0)};
+        for (int o = lane; o < 12; o += NT) {
+          cross_lin(e1, dn1, c0u, o);  // (d0 x n)_u = e1 x n + d0 x dn1
+          cross_lin(e2, dn2, c0v, o);
+          cross_lin(f1, zero, c1k, o);  // (d1 x n)_uk = f1 x n
+          cross_lin(f2, zero, c1l, o);
         }
       }
       const T th_d1 = th_lin + T(3) * eps;
+      const T th_g = th_lin + T(8) * eps;
+      const T th_de = th_lin + T(5) * eps;
+      const T th_c0u = th_lin + T(6) * eps;  // also c1k, c1l
       wave_sync();
       for (int c = 0; c < 3; ++c) {  // c0 = d0 x n, c1 = d1 x n
         const int a = (c + 1) % 3, b = (c + 2) % 3;
@@ -563,25 +602,74 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
         else
           cv4m<1, 1, 1, 1, 1, 1, 1, 1, true, NT>(slice(d1, c, 16), slice(d1, c, 16), d1d1, T(1), lane);
       }
-      const T th_g = th_lin + T(8) * eps;
+      // (d1 x n)_u = -e1 x n + d1 x dn1 (the first term constant along u_k, v_k)
+      for (int o = lane; o < 48; o += NT) {
+        const int c = o / 16, r = o - 16 * c, ij = r / 4, p = (c + 1) % 3, q = (c + 2) % 3;
+        const TP<T> np = nC(p), nq = nC(q), dp = slice(d1, p, 16), dq = slice(d1, q, 16);
+        c1u.v[o] = fma(comp(e1, q), np.v[ij], -(comp(e1, p) * nq.v[ij])) +
+                   fma(dp.v[r], comp(dn1, q), -(dq.v[r] * comp(dn1, p)));
+        c1u.m[o] = fabs(comp(e1, q)) * np.m[ij] + fabs(comp(e1, p)) * nq.m[ij] + dp.m[r] * fabs(comp(dn1, q)) +
+                   dq.m[r] * fabs(comp(dn1, p));
+        c1v.v[o] = fma(comp(e2, q), np.v[ij], -(comp(e2, p) * nq.v[ij])) +
+                   fma(dp.v[r], comp(dn2, q), -(dq.v[r] * comp(dn2, p)));
+        c1v.m[o] = fabs(comp(e2, q)) * np.m[ij] + fabs(comp(e2, p)) * nq.m[ij] + dp.m[r] * fabs(comp(dn2, q)) +
+                   dq.m[r] * fabs(comp(dn2, p));
+      }
+      {
+        const T* dv[3] = {slice(d1, 0, 16).v, slice(d1, 1, 16).v, slice(d1, 2, 16).v};
+        const T* dm[3] = {slice(d1, 0, 16).m, slice(d1, 1, 16).m, slice(d1, 2, 16).m};
+        const T a0[3] = {e1.x, e1.y, e1.z}, a1[3] = {e2.x, e2.y, e2.z}, a2[3] = {f1.x, f1.y, f1.z},
+                a3[3] = {f2.x, f2.y, f2.z};
+        combo<16, 3, false, T, NT>(dv, dm, a0, slice(d1e, 0, 16).v, slice(d1e, 0, 16).m, lane);
+        combo<16, 3, false, T, NT>(dv, dm, a1, slice(d1e, 1, 16).v, slice(d1e, 1, 16).m, lane);
+        combo<16, 3, false, T, NT>(dv, dm, a2, slice(d1e, 2, 16).v, slice(d1e, 2, 16).m, lane);
+        combo<16, 3, false, T, NT>(dv, dm, a3, slice(d1e, 3, 16).v, slice(d1e, 3, 16).m, lane);
+      }
       const T th_c0 = th_cv4<1, 1, 0, 0, 1, 1, 0, 0>(th_lin, th_lin, 2);
       const T th_c1 = th_cv4<1, 1, 1, 1, 1, 1, 0, 0>(th_d1, th_lin, 2);
       const T th_d1d1 = th_cv4<1, 1, 1, 1, 1, 1, 1, 1>(th_d1, th_d1, 3);
+      const T th_c1u = th_d1 + T(6) * eps;
+      const T th_d1e = th_d1 + T(5) * eps;
       wave_sync();
-      for (int c = 0; c < 3; ++c)  // G = c0 . d1
-        if (c == 0)
-          cv4m<2, 2, 0, 0, 1, 1, 1, 1, false, NT>(slice(c0, c, 9), slice(d1, c, 16), gg, T(1), lane);
-        else
-          cv4m<2, 2, 0, 0, 1, 1, 1, 1, true, NT>(slice(c0, c, 9), slice(d1, c, 16), gg, T(1), lane);
-      const T th_gg = th_cv4<2, 2, 0, 0, 1, 1, 1, 1>(th_c0, th_d1, 3);
+      // ---- G_u = c0_u . d1 - c0 . e1 (2,2,1,1), G_v likewise, G_uk = c0 . f1,
+      // G_vk = c0 . f2 (2,2,0,0)
+      const TP<T> gu = tpat(B, ILay::GU, 36), gv = tpat(B, ILay::GV, 36), gk = tpat(B, ILay::GK, 9),
+                  gl = tpat(B, ILay::GL, 9);
+      for (int c = 0; c < 3; ++c) {
+        if (c == 0) {
+          cv4m<1, 1, 0, 0, 1, 1, 1, 1, false, NT>(slice(c0u, c, 4), slice(d1, c, 16), gu, T(1), lane);
+          cv4m<1, 1, 0, 0, 1, 1, 1, 1, false, NT>(slice(c0v, c, 4), slice(d1, c, 16), gv, T(1), lane);
+        } else {
+          cv4m<1, 1, 0, 0, 1, 1, 1, 1, true, NT>(slice(c0u, c, 4), slice(d1, c, 16), gu, T(1), lane);
+          cv4m<1, 1, 0, 0, 1, 1, 1, 1, true, NT>(slice(c0v, c, 4), slice(d1, c, 16), gv, T(1), lane);
+        }
+      }
+      // the same lane owns each coefficient of gu, gv in the loops above and here
+      for (int o = lane; o < 36; o += NT) {
+        const int ij = o / 4;  // (2,2) index; constant along u_k, v_k (degree 1 in scaled form: replicated)
+        T su = gu.v[o], sum = gu.m[o], sv = gv.v[o], svm = gv.m[o];
+        for (int c = 0; c < 3; ++c) {
+          const TP<T> cc = slice(c0, c, 9);
+          su = fma(-comp(e1, c), cc.v[ij], su);
+          sum = fma(fabs(comp(e1, c)), cc.m[ij], sum);
+          sv = fma(-comp(e2, c), cc.v[ij], sv);
+          svm = fma(fabs(comp(e2, c)), cc.m[ij], svm);
+        }
+        gu.v[o] = su;
+        gu.m[o] = sum;
+        gv.v[o] = sv;
+        gv.m[o] = svm;
+      }
+      {
+        const T* cv0[3] = {slice(c0, 0, 9).v, slice(c0, 1, 9).v, slice(c0, 2, 9).v};
+        const T* cm0[3] = {slice(c0, 0, 9).m, slice(c0, 1, 9).m, slice(c0, 2, 9).m};
+        const T af1[3] = {f1.x, f1.y, f1.z}, af2[3] = {f2.x, f2.y, f2.z};
+        combo<9, 3, false, T, NT>(cv0, cm0, af1, gk.v, gk.m, lane);
+        combo<9, 3, false, T, NT>(cv0, cm0, af2, gl.v, gl.m, lane);
+      }
+      const T th_gu = max(th_cv4<1, 1, 0, 0, 1, 1, 1, 1>(th_c0u, th_d1, 6), th_c0 + T(8) * eps) + T(2) * eps;
+      const T th_gk = th_c0 + T(5) * eps;
       wave_sync();
-      const TP<T> gu = tpat(B, ILay::GU, 48), gv = tpat(B, ILay::GV, 48), gk = tpat(B, ILay::GK, 32),
-                  gl = tpat(B, ILay::GL, 32);
-      deriv4m<3, 3, 1, 1, 0, NT>(gg, gu, lane);
-      deriv4m<3, 3, 1, 1, 1, NT>(gg, gv, lane);
-      deriv4m<3, 3, 1, 1, 2, NT>(gg, gk, lane);
-      deriv4m<3, 3, 1, 1, 3, NT>(gg, gl, lane);
-      const T th_gd = th_gg + T(3) * eps;
       T glo, ghi, hlo, hhi;
       poly_range<1, 1, T, NT>(g.v, g.m, th_g, &glo, &ghi, lane);
       poly_range<2, 2, T, NT>(dd.v, dd.m, th_nn, &hlo, &hhi, lane);
@@ -591,50 +679,70 @@ __device__ BoxOut eval_box_t(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
       const T Ghi = hlo > T(0) ? up(aghi / (hlo * sqrt(hlo))) : T(INFINITY);
       const T k = G.I0 * G.a1 / G.ak;
       const T klo = k * (T(1) - T(16) * eps), khi = k * (T(1) + T(16) * eps);
-      // local derivatives: the ratio carries (w_u w_v) / (w_uk w_vk)
-      const T wscale = (u1 - u0) * (v1 - v0) / (wk * wl);
-      const TP<T> a0sq = tpat(B, ILay::A0SQ, 25), a1sq = tpat(B, ILay::A1SQ, 225), F = tpat(B, ILay::F, 441);
-      const TP<T> fu = tpat(B, ILay::FU, 378), fv = tpat(B, ILay::FV, 378), fk = tpat(B, ILay::FK, 294),
-                  fl = tpat(B, ILay::FL, 294);
-      const TP<T> j1 = tpat(B, ILay::J1, 1296), jk = tpat(B, ILay::JK, 900), j1e = tpat(B, ILay::J1E, 1600),
+      const TP<T> a0sq = tpat(B, ILay::A0SQ, 25), a0sqe = tpat(B, ILay::A0SQE, 100), a1sq = tpat(B, ILay::A1SQ, 225);
+      const TP<T> su = tpat(B, ILay::SU, 16), sv = tpat(B, ILay::SV, 16), tu = tpat(B, ILay::TU, 144),
+                  tv = tpat(B, ILay::TV, 144), tk = tpat(B, ILay::TK, 64), tl = tpat(B, ILay::TL, 64);
+      const TP<T> fu = tpat(B, ILay::FU, 324), fv = tpat(B, ILay::FV, 324), fk = tpat(B, ILay::FK, 144),
+                  fl = tpat(B, ILay::FL, 144);
+      const TP<T> j1 = tpat(B, ILay::J1, 1024), jk = tpat(B, ILay::JK, 256), j1e = tpat(B, ILay::J1E, 1600),
                   jke = tpat(B, ILay::JKE, 1600);
       const T th_a0sq = th_cv4<2, 2, 0, 0, 2, 2, 0, 0>(th_c0, th_c0, 1);
       const T th_a1sq = th_cv4<2, 2, 1, 1, 2, 2, 1, 1>(th_c1, th_c1, 1);
+      const T th_su = th_cv4<2, 2, 0, 0, 1, 1, 0, 0>(th_c0, th_c0u, 1);
+      const T th_tu = th_cv4<2, 2, 1, 1, 1, 1, 1, 1>(th_c1, th_c1u, 1);
+      const T th_tk = th_cv4<2, 2, 1, 1, 1, 1, 0, 0>(th_c1, th_c0u, 1);
+      // F_u / 2 = (d0.e1) a1^2 + |d0|^2 a1 a1_u + eta^2 (d1.e1) a0^2 - eta^2 |d1|^2 a0 a0_u
+      // F_uk / 2 = |d0|^2 a1 a1_uk - eta^2 (d1.f1) a0^2  (d0, n, a0 do not depend on u_k);
       // eta is an FP32 input, so eta^2 is exact in FP64
-      const T th_F = max(th_cv4<2, 2, 0, 0, 4, 4, 2, 2>(th_nn, th_a1sq, 2), th_cv4<2, 2, 2, 2, 4, 4, 0, 0>(th_d1d1, th_a0sq, 2));
-      const T th_fd = th_F + T(3) * eps;
-      const T th_j = max(th_cv4<5, 6, 2, 2, 3, 2, 1, 1>(th_fd, th_gd, 2), th_cv4<6, 6, 1, 2, 3, 3, 1, 0>(th_fd, th_gd, 2));
-      const T th_je = th_elev4<1, 1, 1, 1>(th_j);
+      const T th_fu = max(max(th_cv4<1, 1, 0, 0, 4, 4, 2, 2>(th_de, th_a1sq, 4), th_cv4<2, 2, 0, 0, 3, 3, 2, 2>(th_nn, th_tu, 4)),
+                          max(th_cv4<1, 1, 1, 1, 4, 4, 1, 1>(th_d1e, th_a0sq, 4), th_cv4<2, 2, 2, 2, 3, 3, 0, 0>(th_d1d1, th_su, 4))) +
+                      T(2) * eps;
+      const T th_fk = max(th_cv4<2, 2, 0, 0, 3, 3, 1, 1>(th_nn, th_tk, 2), th_cv4<1, 1, 1, 1, 4, 4, 0, 0>(th_d1e, th_a0sq, 2)) +
+                      T(2) * eps;
+      const T th_j1 = th_cv4<5, 5, 2, 2, 2, 2, 1, 1>(th_fu, th_gu, 2);
+      const T th_jk = th_cv4<5, 5, 1, 1, 2, 2, 0, 0>(th_fk, th_gk, 2);
+      const T th_j1e = th_elev4<2, 2, 0, 0>(th_j1), th_jke = th_elev4<2, 2, 2, 2>(th_jk);
+      const T ee = eta * eta;
       T Elo = T(0), Ehi = T(INFINITY);
       for (int bax = 0; bax < 2; ++bax) {  // b = (1,0,0), then (0,1,0)
         wave_sync();
         const TP<T> a0 = slice(c0, bax, 9), a1 = slice(c1, bax, 36);
         cv4m<2, 2, 0, 0, 2, 2, 0, 0, false, NT>(a0, a0, a0sq, T(1), lane);
         cv4m<2, 2, 1, 1, 2, 2, 1, 1, false, NT>(a1, a1, a1sq, T(1), lane);
+        cv4m<2, 2, 0, 0, 1, 1, 0, 0, false, NT>(a0, slice(c0u, bax, 4), su, T(1), lane);
+        cv4m<2, 2, 0, 0, 1, 1, 0, 0, false, NT>(a0, slice(c0v, bax, 4), sv, T(1), lane);
+        cv4m<2, 2, 1, 1, 1, 1, 1, 1, false, NT>(a1, slice(c1u, bax, 16), tu, T(1), lane);
+        cv4m<2, 2, 1, 1, 1, 1, 1, 1, false, NT>(a1, slice(c1v, bax, 16), tv, T(1), lane);
+        cv4m<2, 2, 1, 1, 1, 1, 0, 0, false, NT>(a1, slice(c1k, bax, 4), tk, T(1), lane);
+        cv4m<2, 2, 1, 1, 1, 1, 0, 0, false, NT>(a1, slice(c1l, bax, 4), tl, T(1), lane);
         wave_sync();
-        // F = |d0|^2 a1^2 - eta^2 |d1|^2 a0^2
-        cv4m<2, 2, 0, 0, 4, 4, 2, 2, false, NT>(dd, a1sq, F, T(1), lane);
-        cv4m<2, 2, 2, 2, 4, 4, 0, 0, true, NT>(d1d1, a0sq, F, -(eta * eta), lane);
+        elev4m<4, 4, 0, 0, 0, 0, 1, 1, NT>(a0sq, a0sqe, lane);  // replication: exact
+        cv4m<1, 1, 0, 0, 4, 4, 2, 2, false, NT>(slice(de, 0, 4), a1sq, fu, T(1), lane);
+        cv4m<2, 2, 0, 0, 3, 3, 2, 2, true, NT>(dd, tu, fu, T(1), lane);
+        cv4m<2, 2, 2, 2, 3, 3, 0, 0, true, NT>(d1d1, su, fu, -ee, lane);
+        cv4m<1, 1, 0, 0, 4, 4, 2, 2, false, NT>(slice(de, 1, 4), a1sq, fv, T(1), lane);
+        cv4m<2, 2, 0, 0, 3, 3, 2, 2, true, NT>(dd, tv, fv, T(1), lane);
+        cv4m<2, 2, 2, 2, 3, 3, 0, 0, true, NT>(d1d1, sv, fv, -ee, lane);
+        cv4m<2, 2, 0, 0, 3, 3, 1, 1, false, NT>(dd, tk, fk, T(1), lane);
+        cv4m<1, 1, 1, 1, 4, 4, 0, 0, true, NT>(slice(d1e, 2, 16), a0sq, fk, -ee, lane);
+        cv4m<2, 2, 0, 0, 3, 3, 1, 1, false, NT>(dd, tl, fl, T(1), lane);
+        cv4m<1, 1, 1, 1, 4, 4, 0, 0, true, NT>(slice(d1e, 3, 16), a0sq, fl, -ee, lane);
         wave_sync();
-        deriv4m<6, 6, 2, 2, 0, NT>(F, fu, lane);
-        deriv4m<6, 6, 2, 2, 1, NT>(F, fv, lane);
-        deriv4m<6, 6, 2, 2, 2, NT>(F, fk, lane);
-        deriv4m<6, 6, 2, 2, 3, NT>(F, fl, lane);
+        cv4m<1, 1, 1, 1, 4, 4, 1, 1, true, NT>(slice(d1e, 0, 16), a0sqe, fu, ee, lane);
+        cv4m<1, 1, 1, 1, 4, 4, 1, 1, true, NT>(slice(d1e, 1, 16), a0sqe, fv, ee, lane);
         wave_sync();
-        // det J_1 = F_u G_v - F_v G_u (8,8,3,3), det J_k = F_uk G_vk - F_vk G_uk (9,9,2,2)
-        cv4m<5, 6, 2, 2, 3, 2, 1, 1, false, NT>(fu, gv, j1, T(1), lane);
-        cv4m<6, 5, 2, 2, 2, 3, 1, 1, true, NT>(fv, gu, j1, T(-1), lane);
-        cv4m<6, 6, 1, 2, 3, 3, 1, 0, false, NT>(fk, gl, jk, T(1), lane);
-        cv4m<6, 6, 2, 1, 3, 3, 0, 1, true, NT>(fl, gk, jk, T(-1), lane);
+        // det J_1 = F_u G_v - F_v G_u (7,7,3,3), det J_k = F_uk G_vk - F_vk G_uk (7,7,1,1)
+        cv4m<5, 5, 2, 2, 2, 2, 1, 1, false, NT>(fu, gv, j1, T(1), lane);
+        cv4m<5, 5, 2, 2, 2, 2, 1, 1, true, NT>(fv, gu, j1, T(-1), lane);
+        cv4m<5, 5, 1, 1, 2, 2, 0, 0, false, NT>(fk, gl, jk, T(1), lane);
+        cv4m<5, 5, 1, 1, 2, 2, 0, 0, true, NT>(fl, gk, jk, T(-1), lane);
         wave_sync();
-        elev4m<8, 8, 3, 3, 1, 1, 0, 0, NT>(j1, j1e, lane);
-        elev4m<9, 9, 2, 2, 0, 0, 1, 1, NT>(jk, jke, lane);
+        elev4m<7, 7, 3, 3, 2, 2, 0, 0, NT>(j1, j1e, lane);
+        elev4m<7, 7, 1, 1, 2, 2, 2, 2, NT>(jk, jke, lane);
         wave_sync();
-        const RB<T> rb = ratio4m<T, NT>(N4<9, 9, 3, 3>::n, jke, th_je, j1e, th_je, true, lane);
+        const RB<T> rb = ratio4m<T, NT>(N4<9, 9, 3, 3>::n, jke, th_jke, j1e, th_j1e, true, lane);
         T rlo, rhi;
         abs_bound(rb, &rlo, &rhi);
-        rlo = down(rlo * wscale);
-        rhi = isinf(rhi) ? rhi : up(rhi * wscale);
         const T elo = (Glo <= T(0) || rlo <= T(0)) ? T(0) : down(klo * down(Glo * rlo));
         const T ehi = (isinf(Ghi) || isinf(rhi)) ? T(INFINITY) : up(khi * up(Ghi * rhi));
         Elo = max(Elo, elo);

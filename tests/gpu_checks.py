@@ -9,12 +9,21 @@ def keyset(L):
     return set(zip(np.asarray(L["tuple"]).tolist(), map(tuple, np.asarray(L["code"]).tolist())))
 
 
-def check_leaf_bounds(orc, osc, L, idx, tol=BOUND_TOL, e_face_value=False, flags=0, uk_face_value=False):
+def check_leaf_bounds(orc, osc, L, idx, tol=BOUND_TOL, e_face_value=False, flags=0, uk_face_value=False,
+                      e_tail=None):
     """GPU leaves against the oracle's bound of the very same box: the GPU
     bound contains the oracle's and exceeds it by at most `tol`.  With
     e_face_value the irradiance bound is one taken at face value on both
-    sides (no rounding control), so it only agrees to within `tol`."""
+    sides (no rounding control), so it only agrees to within `tol`.  With
+    e_tail = (frac, tol2) at most a fraction `frac` of the leaves may exceed
+    `tol` on the irradiance bound, and none `tol2`: a rounding-controlled
+    bound exceeds the exact one by its rounding slack, theta times the
+    magnitude-to-value ratio of its extremal coefficients, which is large
+    only where the polynomial's terms cancel (next to a caustic or to total
+    internal reflection)."""
+    n_tail, n = 0, 0
     for k in idx:
+        n += 1
         ob = orc.box_bound(osc, int(L["tuple"][k]), L["box"][k].astype(np.float64), flags=flags)
         assert ob["live"], k
         gu = L["uk"][k].astype(np.float64)
@@ -32,8 +41,14 @@ def check_leaf_bounds(orc, osc, L, idx, tol=BOUND_TOL, e_face_value=False, flags
             assert abs(gE[0] - oE[0]) <= tol * oE[0], (k, gE, oE)
             continue
         if np.isfinite(oE[1]):
-            assert gE[1] >= oE[1] * (1 - 1e-12) and gE[1] <= oE[1] * (1 + tol), (k, gE, oE)
-        assert gE[0] <= oE[0] * (1 + 1e-12) and gE[0] >= oE[0] * (1 - tol), (k, gE, oE)
+            assert gE[1] >= oE[1] * (1 - 1e-12), (k, gE, oE)
+        assert gE[0] <= oE[0] * (1 + 1e-12), (k, gE, oE)
+        ex = max(gE[1] / oE[1] - 1 if np.isfinite(oE[1]) else 0.0, 1 - gE[0] / oE[0] if oE[0] > 0 else 0.0)
+        if ex > tol:
+            assert e_tail is not None and ex <= e_tail[1], (k, gE, oE)
+            n_tail += 1
+    if e_tail is not None:
+        assert n_tail <= e_tail[0] * n, (n_tail, n)
 
 
 def check_cover_list(off, gt, ge, Ob, G, tol=BOUND_TOL):

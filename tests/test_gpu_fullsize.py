@@ -154,7 +154,7 @@ def test_water_fullsize_exhaustive_matches_brute_force(bbc, orc, water):
 def test_walls_fullsize_exhaustive_matches_brute_force(bbc, orc, walls):
     sc, osc, B = walls
     print("walls: 48 points, brute-force roots over each candidate list", flush=True)
-    n_lit, frac = _exhaustive_vs_brute(bbc, orc, sc, osc, B, 48, 32, lattice=12)
+    n_lit, frac = _exhaustive_vs_brute(bbc, orc, sc, osc, B, 48, 32, lattice=32)
     assert n_lit >= 30
     assert frac >= 0.95, frac
 
