@@ -409,12 +409,13 @@ static bool pair_candidate(const Tuple& c) {
 // position bound (see irradiance_from).
 static void irradiance_from(const Tuple& c, const BV& d0, const Bern& Q, const Bern& Pu, const Bern& Pv,
                             const Bern& Qu, const Bern& Qv, const Bern& Puu, const Bern& Puv, const Bern& Pvu,
-                            const Bern& Pvv, BoxBound* bb);
+                            const Bern& Pvv, int flags, BoxBound* bb);
 
 static void implicit_irradiance(const Tuple& c, const BV& d0, const BV& x1, const BV& n, double wu, double wv,
                                 BoxBound* bb);
 
-static BoxBound bound_box_rr(const Tuple& c, double u0, double u1, double v0, double v1, bool want_irr) {
+static BoxBound bound_box_rr(const Tuple& c, double u0, double u1, double v0, double v1, bool want_irr,
+                             int flags) {
   BoxBound bb;
   if (!c.front) return bb;
   if (u0 + v0 >= 1.0) return bb;
@@ -469,14 +470,14 @@ static BoxBound bound_box_rr(const Tuple& c, double u0, double u1, double v0, do
   const double wu = u1 - u0, wv = v1 - v0;
   irradiance_from(c, d0, Den, Pu3, Pv3, scale(deriv(Den, 0), 1.0 / wu), scale(deriv(Den, 1), 1.0 / wv),
                   scale(deriv(Pu3, 0), 1.0 / wu), scale(deriv(Pu3, 1), 1.0 / wv), scale(deriv(Pv3, 0), 1.0 / wu),
-                  scale(deriv(Pv3, 1), 1.0 / wv), &bb);
+                  scale(deriv(Pv3, 1), 1.0 / wv), flags, &bb);
   return bb;
 }
 
 // Position and irradiance bound of one box of the barycentric domain of u1
 // (Sec. 4.2: U_k and [E_lo, E_hi] from coefficient ratios).
 static BoxBound bound_box(const Tuple& c, double u0, double u1, double v0, double v1, bool want_irr, int flags) {
-  if (c.chain == 2) return bound_box_rr(c, u0, u1, v0, v1, want_irr);
+  if (c.chain == 2) return bound_box_rr(c, u0, u1, v0, v1, want_irr, flags);
   BoxBound bb;
   if (!c.front) return bb;
   if (u0 + v0 >= 1.0) return bb;  // box lies outside the triangle u + v <= 1
@@ -578,7 +579,7 @@ static BoxBound bound_box(const Tuple& c, double u0, double u1, double v0, doubl
   if (c.chain == 1 && (flags & 4))
     implicit_irradiance(c, d0, x1, n, wu, wv, &bb);
   else
-    irradiance_from(c, d0, Q, Pu, Pv, Qu, Qv, Puu, Puv, Pvu, Pvv, &bb);
+    irradiance_from(c, d0, Q, Pu, Pv, Qu, Qv, Puu, Puv, Pvu, Pvv, flags, &bb);
   return bb;
 }
 
@@ -603,14 +604,38 @@ static void irradiance_factor(const Tuple& c, const BV& d0, double rlo, double r
 // eq_irr_term3a), |du1/du_k| bounded by the ratio of Q^3 to det M, and
 // dOmega0/dA1 = |g| / h^(3/2) with g = n_g . d0 and h = d0 . d0 bounded
 // factor-wise; E = I0 (A1 / A_k) G1 |Q^3 / det M|.
+// Degree reduction (Sec. 6.1, "Degree reduction"; oracle flag 8): a polynomial
+// whose degree along u or v exceeds kReduceAbove (the paper's example
+// threshold, 40) is replaced by its least-squares approximant of degree
+// kReduceTo along those axes (16, the degree of the chain's position
+// numerators) plus a remainder variable:
+// A = X + r (2 s - 1) for some s in [0, 1], r the largest residual coefficient,
+// the remainder riding on a fresh axis `raxis` (each reduction starts from a
+// polynomial without remainder variables, so none has to be absorbed).
+static constexpr int kReduceAbove = 40, kReduceTo = 16;
+static bool needs_reduction(const Bern& A) { return A.deg[0] > kReduceAbove || A.deg[1] > kReduceAbove; }
+static Bern with_remainder(const Bern& A, int raxis) {
+  Deg to = A.deg;
+  to[0] = std::min(to[0], kReduceTo);
+  to[1] = std::min(to[1], kReduceTo);
+  double r = 0.0;
+  const Bern X = reduce_degree(A, to, &r);
+  return add(X, affine_axis(raxis, -r, r));
+}
+
 static void irradiance_from(const Tuple& c, const BV& d0, const Bern& Q, const Bern& Pu, const Bern& Pv,
                             const Bern& Qu, const Bern& Qv, const Bern& Puu, const Bern& Puv, const Bern& Pvu,
-                            const Bern& Pvv, BoxBound* bb) {
+                            const Bern& Pvv, int flags, BoxBound* bb) {
   const Bern detM = add(sub(mul(Q, sub(mul(Puu, Pvv), mul(Pvu, Puv))), mul(Pu, sub(mul(Qu, Pvv), mul(Pvu, Qv)))),
                         mul(Pv, sub(mul(Qu, Puv), mul(Puu, Qv))));
   const Bern Q3 = mul(mul(Q, Q), Q);
   double rlo, rhi;
-  abs_bound(ratio_bound(Q3, detM), &rlo, &rhi);
+  if ((flags & 8) && (needs_reduction(detM) || needs_reduction(Q3))) {
+    // Q^3 / det M over (u, v, s, t): Q^3's remainder on axis 2, det M's on 3
+    abs_bound(ratio_bound(with_remainder(Q3, 2), with_remainder(detM, 3)), &rlo, &rhi);
+  } else {
+    abs_bound(ratio_bound(Q3, detM), &rlo, &rhi);
+  }
   irradiance_factor(c, d0, rlo, rhi, &bb->E[0], &bb->E[1]);
 }
 
@@ -1571,6 +1596,13 @@ int orc_bern_split(const int32_t* da, const double* a, int axis, double t, doubl
   split(from_flat(da, a), axis, t, &l, &r);
   to_flat(l, left);
   to_flat(r, right);
+  return 0;
+}
+int orc_bern_reduce(const int32_t* da, const double* a, const int32_t* dto, double* out, double* rem) {
+  const Deg to{dto[0], dto[1], dto[2], dto[3]};
+  for (int k = 0; k < kAxes; ++k)
+    if (to[k] < 0 || to[k] > da[k]) return -1;
+  to_flat(reduce_degree(from_flat(da, a), to, rem), out);
   return 0;
 }
 double orc_bern_eval(const int32_t* da, const double* a, const double* x) {

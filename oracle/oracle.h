@@ -151,6 +151,10 @@ int orc_bern_elevate(const int32_t* da, const double* a, const int32_t* dto, dou
 int orc_bern_deriv(const int32_t* da, const double* a, int axis, double* out);
 int orc_bern_split(const int32_t* da, const double* a, int axis, double t, double* left, double* right);
 double orc_bern_eval(const int32_t* da, const double* a, const double* x);
+/* Degree reduction (Sec. 6.1): least-squares approximant of degree dto <= da
+   (SVD of the elevation matrix per reduced axis) and in *rem the largest
+   residual coefficient at degree da.  Returns -1 when dto exceeds da. */
+int orc_bern_reduce(const int32_t* da, const double* a, const int32_t* dto, double* out, double* rem);
 /* out[0] = kind (0 direct [lo,hi], 1 split (-inf,lo]U[hi,inf), 2 unbounded), out[1] = lo, out[2] = hi */
 int orc_ratio_bound(const int32_t* dp, const double* p, const int32_t* dq, const double* q, double* out);
 /* Secant approximation of sqrt on [blo, bhi] (0 < blo <= bhi):

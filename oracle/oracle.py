@@ -91,6 +91,7 @@ def _declare(L):
         "orc_bern_deriv": (C.c_int, [vp, vp, C.c_int, vp]),
         "orc_bern_split": (C.c_int, [vp, vp, C.c_int, d, vp, vp]),
         "orc_bern_eval": (d, [vp, vp, vp]),
+        "orc_bern_reduce": (C.c_int, [vp, vp, vp, vp, vp]),
         "orc_ratio_bound": (C.c_int, [vp, vp, vp, vp, vp]),
         "orc_sqrt_secant": (C.c_int, [d, d, vp]),
     }
@@ -379,6 +380,16 @@ def bern_eval(da, a, x):
     xx[:len(x)] = x
     a = _f64(a)
     return lib().orc_bern_eval(_ptr(da), _ptr(a), _ptr(xx))
+
+
+def bern_reduce(da, a, dto):
+    """Least-squares degree reduction (Sec. 6.1): (dto, coefficients, remainder)."""
+    da, dto = _deg(da), _deg(dto)
+    a = _f64(a)
+    out = np.zeros(_n(dto))
+    rem = np.zeros(1)
+    assert lib().orc_bern_reduce(_ptr(da), _ptr(a), _ptr(dto), _ptr(out), _ptr(rem)) == 0
+    return dto, out, float(rem[0])
 
 
 def ratio_bound(dp, p, dq, q):
