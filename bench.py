@@ -459,6 +459,41 @@ def implicit_section(bbc, S, torch, steps=2):
             "leaves": info["n_leaves"], "inf_leaves": info["n_inf_leaves"], "grid_entries": info["n_grid_entries"]}
 
 
+def degree_reduction_section(bbc, S, torch, steps=2, n_side=256, spp=256):
+    """The facing walls built with and without the degree reduction of the
+    irradiance ratio (Sec. 6.1): build and query time, tree, grid and the
+    sampled estimate's RelMSE against the exhaustive sum of the same build."""
+    dev = torch.device("cuda:0")
+    sc = S.facing_walls(64)
+    pts = torch.as_tensor(S.receiver_points(sc, n_side), device=dev)
+    sub = torch.as_tensor(S.receiver_points(sc, 64), device=dev)
+    out = {"workload": "two reflections, facing walls 8192 + 8192 triangles, depth cap 5, E-ratio 10, "
+                       f"{n_side}x{n_side} receiver points, {spp} samples/point; with and without the reduction of "
+                       "Den^3 and det M (46, 46) to degree (16, 16) plus remainders"}
+    for name, flags in (("full_degree", 0), ("reduced", bbc.FLAG_DEGREE_REDUCTION)):
+        B = bbc.Bounds(bbc.DeviceScene(sc), dict(max_depth=5, alpha=10.0, flags=flags))
+        tb, tq = [], []
+        for k in range(steps):
+            t = time.perf_counter()
+            B.rebuild()
+            torch.cuda.synchronize()
+            tb.append(time.perf_counter() - t)
+            t = time.perf_counter()
+            B.query(pts, spp, 1 + k, mode=bbc.QUERY_STAGED)
+            torch.cuda.synchronize()
+            tq.append(time.perf_counter() - t)
+        ex, _ = B.query(sub, 1, 0, mode=bbc.QUERY_STAGED | bbc.QUERY_EXHAUSTIVE)
+        errs = [relmse(B.query(sub, spp, 900 + k, mode=bbc.QUERY_STAGED)[0].double().cpu().numpy(),
+                       ex.double().cpu().numpy()) for k in range(4)]
+        info = B.info()
+        B.free()
+        b, q = float(np.median(tb)), float(np.median(tq))
+        out[name] = {"build_ms": round(1e3 * b, 2), "query_ms": round(1e3 * q, 2), "relmse": float(np.mean(errs)),
+                     "boxes": info["n_boxes"], "leaves": info["n_leaves"], "inf_leaves": info["n_inf_leaves"],
+                     "grid_entries": info["n_grid_entries"]}
+    return out
+
+
 def area_light_section(bbc, S, torch, steps=3):
     """Single reflection off a 65 x 65-vertex heightfield (8192 triangles) lit
     by a 0.4 x 0.4 area light, depth cap 3, 512 x 512 receiver points, 64
@@ -683,7 +718,8 @@ def main():
         out["refraction_implicit"] = implicit_section(bbc, S, torch)
         out["area_light"] = area_light_section(bbc, S, torch)
         out["literal_water"] = literal_water_section(bbc, S, torch)
-        progress("implicit, area-light and literal-water sections done")
+        out["degree_reduction"] = degree_reduction_section(bbc, S, torch)
+        progress("implicit, area-light, literal-water and degree-reduction sections done")
     if not args.no_cpu_baseline:
         timed0 = args.warmup * args.chunk
         out["cpu_baseline"] = cpu_baseline_section(bbc, torch, res, h["trace"][timed0:], h["reqs"][timed0:],

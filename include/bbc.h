@@ -120,9 +120,15 @@ typedef struct {
 #define BBC_FLAG_NO_REMAINDER 2 /* refraction without remainder variables (ablation; bounds may be invalid) */
 /* refraction: irradiance bound by implicit differentiation of the specular
  * polynomials F (Snell's law) and G (coplanarity) over the box times its
- * position bound (Sec. 4.4, "Implicit differentiation"), coefficients taken
- * at face value; the other chains ignore it */
+ * position bound (Sec. 4.4, "Implicit differentiation"), rounded outward;
+ * the other chains ignore it */
 #define BBC_FLAG_IMPLICIT_IRR 4
+/* two reflections: degree reduction (Sec. 6.1, "Degree reduction") of the
+ * irradiance ratio Den^3 / det M, whose degree (46, 46) exceeds the threshold
+ * 40: both polynomials are replaced by least-squares approximants of degree
+ * (16, 16) plus a remainder variable each, and the ratio is bounded over
+ * (16, 16, 1, 1); the other chains ignore it */
+#define BBC_FLAG_DEGREE_REDUCTION 8
 
 typedef struct bbc_bounds bbc_bounds;
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbbc.so")
 OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EUNSUPPORTED, EQUEUE = 0, -1, -2, -3, -4, -5, -6
 CHAIN = {"R": 0, "T": 1, "RR": 2}
 MEM_HOST, MEM_DEVICE = 0, 1
-FLAG_FIXED_DEPTH, FLAG_NO_REMAINDER, FLAG_IMPLICIT_IRR = 1, 2, 4
+FLAG_FIXED_DEPTH, FLAG_NO_REMAINDER, FLAG_IMPLICIT_IRR, FLAG_DEGREE_REDUCTION = 1, 2, 4, 8
 QUERY_FUSED, QUERY_STAGED, QUERY_EXHAUSTIVE = 0, 1, 16
 QUERY_UNIFORM, QUERY_ONE_SAMPLE, QUERY_BINS = 32, 64, 96
 

@@ -69,8 +69,9 @@ static void release_all(Bounds* b) {
                    &b->q[1], &b->fq, &b->lt, &b->lc, &b->lu, &b->le, &b->gl_t, &b->gl_c, &b->gl_u, &b->gl_e, &b->st, &b->sc, &b->su, &b->se, &b->tcount,
                    &b->toff, &b->tcur, &b->lrect, &b->lcoarse, &b->ccount, &b->coff, &b->gt, &b->ge,
                    &b->scan_tmp, &b->trec, &b->pos2, &b->nrm2, &b->box2, &b->rowcount, &b->rowoff, &b->tid,
-                   &b->qw_buf, &b->max_cell_dev, &b->qcounters, &b->cflag, &b->cpos, &b->cE};
+                   &b->qw_buf, &b->max_cell_dev, &b->qcounters, &b->cflag, &b->cpos, &b->cE, &b->red_tab};
   for (DevBuf* d : all) release(*d);
+  b->red_ready = false;
   b->device_bytes = 0;
 }
 
@@ -109,7 +110,8 @@ static bbc_status validate(const bbc_scene* sc, const bbc_emitters* em, const bb
   if (p->grid_res < 1 || p->grid_res > 4096) return invalid("grid_res must be in [1, 4096]");
   if (p->init_pieces < 1 || p->init_pieces > 256) return invalid("init_pieces must be in [1, 256]");
   if (p->init_levels < 0 || p->init_levels > 12) return invalid("init_levels must be in [0, 12]");
-  if (p->flags & ~(BBC_FLAG_FIXED_DEPTH | BBC_FLAG_NO_REMAINDER | BBC_FLAG_IMPLICIT_IRR)) return invalid("unknown flags");
+  if (p->flags & ~(BBC_FLAG_FIXED_DEPTH | BBC_FLAG_NO_REMAINDER | BBC_FLAG_IMPLICIT_IRR | BBC_FLAG_DEGREE_REDUCTION))
+    return invalid("unknown flags");
   if (!(p->cover_frac >= 0.f) || !std::isfinite(p->cover_frac)) return invalid("cover_frac must be finite and >= 0");
   return BBC_OK;
 }

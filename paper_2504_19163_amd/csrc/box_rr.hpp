@@ -49,6 +49,9 @@ struct RRLay {
   static constexpr int DENU = 1088, DENV = 1328;                                 // (14,15), (15,14)
   static constexpr int DETM = 6900, MINOR = 9109;                                // (46,46); A (31,31) | B, C (30,30)
   static constexpr int DEN2 = 0, DEN3 = 9109, DEN3E = 0;                         // (30,30), (45,45), (46,46)
+  // degree reduction work space over dead position tensors and Den^3:
+  // Y [2][17][47], X [2][17][17], then Z and |Z| bounds [2][47][17] per polynomial
+  static constexpr int RED_Y = 2209, RED_X = 3807, RED_Z = 2209, RED_Z2 = 9109;
   static constexpr int END_IRR = 11225;
 };
 
@@ -95,11 +98,102 @@ __device__ __forceinline__ void cv_wide(const T* a, const T* b, T* c, T sgn, int
   }
 }
 
+// Degree reduction (Sec. 6.1, "Degree reduction"): above degree 40 the
+// irradiance ratio's numerator Den^3 and denominator det M (both (46, 46))
+// are replaced by their least-squares approximants of degree (16, 16) plus a
+// remainder variable each, and the ratio is bounded over (16, 16, 1, 1) with
+// the numerator's remainder on the third axis and the denominator's on the
+// fourth.  The table (built once per handle on the host) holds P, the
+// pseudo-inverse of the elevation matrix from degree 16 to 46 (17 x 47), E,
+// that matrix (47 x 17), and C(46, i).  The fit is applied to the plain
+// (unscaled) coefficients along u, then v; the remainder is the largest
+// coefficient of a - E X E^T at degree 46 plus a bound of the rounding of
+// that back-elevation, so it bounds |a(x) - X(x)| on the box for the
+// coefficients a as computed.
+constexpr int kRedFrom = 46, kRedTo = 16;
+constexpr int kRedN = kRedFrom + 1, kRedM = kRedTo + 1;
+constexpr int kRedTable = 2 * kRedM * kRedN + kRedN;
+
+template <class T, int NT>
+__device__ __forceinline__ RB<T> reduced_ratio(T* num, T* den, T* B, const T* __restrict__ tab, int lane) {
+  constexpr int N2 = kRedN * kRedN, MN = kRedM * kRedN, M2 = kRedM * kRedM;
+  const T eps = Eps<T>::u;
+  const T* P = tab;
+  const T* E = tab + MN;
+  const T* bin = tab + 2 * MN;
+  T* const Y = B + RRLay::RED_Y;
+  T* const X = B + RRLay::RED_X;
+  for (int o = lane; o < 2 * N2; o += NT) {  // scaled -> plain coefficients
+    const int f = o < N2 ? o : o - N2, i = f / kRedN, j = f - i * kRedN;
+    T* a = o < N2 ? num : den;
+    a[f] = a[f] / (bin[i] * bin[j]);
+  }
+  wave_sync();
+  for (int o = lane; o < 2 * MN; o += NT) {  // along u: Y = P a
+    const int f = o < MN ? o : o - MN, r = f / kRedN, j = f - r * kRedN;
+    const T* a = o < MN ? num : den;
+    T s = T(0);
+    for (int i = 0; i < kRedN; ++i) s = fma(P[r * kRedN + i], a[i * kRedN + j], s);
+    Y[o] = s;
+  }
+  wave_sync();
+  for (int o = lane; o < 2 * M2; o += NT) {  // along v: X = Y P^T
+    const int f = o < M2 ? o : o - M2, r = f / kRedM, c = f - r * kRedM;
+    const T* y = Y + (o < M2 ? 0 : MN) + r * kRedN;
+    T s = T(0);
+    for (int j = 0; j < kRedN; ++j) s = fma(y[j], P[c * kRedN + j], s);
+    X[o] = s;
+  }
+  wave_sync();
+  for (int o = lane; o < 2 * MN; o += NT) {  // back along u: Z = E X, with E |X|
+    const int f = o < MN ? o : o - MN, i = f / kRedM, c = f - i * kRedM;
+    const T* x = X + (o < MN ? 0 : M2);
+    T* Z = B + (o < MN ? RRLay::RED_Z : RRLay::RED_Z2);
+    T s = T(0), sm = T(0);
+    for (int r = 0; r < kRedM; ++r) {
+      s = fma(E[i * kRedM + r], x[r * kRedM + c], s);
+      sm = fma(E[i * kRedM + r], fabs(x[r * kRedM + c]), sm);
+    }
+    Z[f] = s;
+    Z[MN + f] = sm;
+  }
+  wave_sync();
+  T rn = T(0), rd = T(0);
+  for (int o = lane; o < 2 * N2; o += NT) {  // residual at degree 46
+    const int f = o < N2 ? o : o - N2, i = f / kRedN, j = f - i * kRedN;
+    const T* Z = B + (o < N2 ? RRLay::RED_Z : RRLay::RED_Z2);
+    T w = T(0), wm = T(0);
+    for (int c = 0; c < kRedM; ++c) {
+      w = fma(Z[i * kRedM + c], E[j * kRedM + c], w);
+      wm = fma(Z[MN + i * kRedM + c], E[j * kRedM + c], wm);
+    }
+    const T res = fabs((o < N2 ? num : den)[f] - w) + T(48) * eps * wm;
+    if (o < N2)
+      rn = max(rn, res);
+    else
+      rd = max(rd, res);
+  }
+  rn = up(blk_max<NT>(rn) * (T(1) + T(4) * eps));
+  rd = up(blk_max<NT>(rd) * (T(1) + T(4) * eps));
+  return ratio_bound_fn<T, NT>(
+      4 * M2,
+      [&](int o, T& p, T& ep, T& q, T& eq) {
+        const int f = o >> 2;
+        const T xp = X[f], xq = X[M2 + f];
+        p = (o & 2) ? xp + rn : xp - rn;
+        q = (o & 1) ? xq + rd : xq - rd;
+        ep = eps * (fabs(xp) + rn);
+        eq = eps * (fabs(xq) + rd);
+      },
+      true, lane);
+}
+
 // Always inlined into its kernel: as a separate function, the irradiance
 // instantiation came back with corrupted receiver bounds after its calls to
 // the (non-inlined) ratio-bound helpers, while the same code inlined is exact.
 template <class T, bool IRR = false, int NT = BBC_WAVE>
-__device__ __forceinline__ BoxOut eval_box_rr(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, LdsRR<T, IRR>& L, int lane) {
+__device__ __forceinline__ BoxOut eval_box_rr(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, LdsRR<T, IRR>& L, int lane,
+                                              const T* red = nullptr) {
   const bool final = true;
   const T eps = Eps<T>::u;
   T* B = L.buf;
@@ -449,14 +543,19 @@ __device__ __forceinline__ BoxOut eval_box_rr(const TupleGeom<T>& G, T u0, T u1,
     // |Den^3 / det M| at face value: with rounding control, det M's
     // coefficients (three nested cancellations at degree (46, 46)) leave
     // their signs undecided on most boxes; the bound takes them as computed
-    const RB<T> rb = ratio_bound_fn<T, NT>(
-        2209,
-        [&](int o, T& p, T& ep, T& q, T& eq) {
-          q = detm[o];
-          p = den3e[o];
-          ep = eq = T(0);
-        },
-        final, lane);
+    RB<T> rb;
+    if (red != nullptr) {
+      rb = reduced_ratio<T, NT>(den3e, detm, B, red, lane);
+    } else {
+      rb = ratio_bound_fn<T, NT>(
+          2209,
+          [&](int o, T& p, T& ep, T& q, T& eq) {
+            q = detm[o];
+            p = den3e[o];
+            ep = eq = T(0);
+          },
+          final, lane);
+    }
     T rlo, rhi;
     abs_bound(rb, &rlo, &rhi);
     // det M from local derivatives is w_u w_v times the global one (each

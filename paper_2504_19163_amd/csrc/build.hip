@@ -43,6 +43,7 @@ struct BuildArgs {
   uint32_t* lc;
   float4* lu;
   float2* le;
+  const double* red;  // degree-reduction table (BBC_FLAG_DEGREE_REDUCTION), else null
 };
 
 // Outputs of a workgroup's boxes (queue items for the next depth, leaves,
@@ -699,7 +700,7 @@ __global__ void __launch_bounds__(kSubdivRRThreads) k_subdiv_rr(BuildArgs a, int
   __shared__ Stage S;
   const int lane = threadIdx.x;
   auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
-    return eval_box_rr<double, true, kSubdivRRThreads>(G, u0, u1, v0, v1, L, lane);
+    return eval_box_rr<double, true, kSubdivRRThreads>(G, u0, u1, v0, v1, L, lane, a.red);
   };
   subdiv_loop<kSubdivRRThreads>(a, depth, ev, lane, S);
 }
@@ -764,6 +765,62 @@ static bbc_status resident_grid(K kernel, int slot, int dev, int n_cu, unsigned*
   return BBC_OK;
 }
 
+// The degree-reduction table of eval_box_rr: P, the pseudo-inverse of the
+// elevation matrix E from degree 16 to 46 (least squares through a
+// Householder QR factorisation of E in long double: each column of P solves
+// min |E x - e_t|), then E itself, then C(46, i).
+static std::vector<double> make_reduction_table() {
+  constexpr int n = kRedN, m = kRedM;
+  auto C = [](int a, int b) {
+    long double r = 1.0L;
+    for (int k = 1; k <= b; ++k) r = r * (a - b + k) / k;
+    return r;
+  };
+  std::vector<long double> R(size_t(n) * m, 0.0L);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < m; ++j)
+      if (i - j >= 0 && i - j <= kRedFrom - kRedTo)
+        R[size_t(i) * m + j] = C(kRedFrom - kRedTo, i - j) * C(kRedTo, j) / C(kRedFrom, i);
+  std::vector<double> out(static_cast<size_t>(kRedTable), 0.0);
+  for (int i = 0; i < n * m; ++i) out[size_t(m) * n + i] = double(R[size_t(i)]);
+  std::vector<std::vector<long double>> V(m);
+  std::vector<long double> vn(m);
+  for (int k = 0; k < m; ++k) {  // Householder reflector zeroing column k below the diagonal
+    long double nr = 0.0L;
+    for (int i = k; i < n; ++i) nr += R[size_t(i) * m + k] * R[size_t(i) * m + k];
+    nr = sqrtl(nr);
+    const long double alpha = R[size_t(k) * m + k] > 0 ? -nr : nr;
+    V[k].assign(size_t(n - k), 0.0L);
+    for (int i = k; i < n; ++i) V[k][size_t(i - k)] = R[size_t(i) * m + k];
+    V[k][0] -= alpha;
+    vn[k] = 0.0L;
+    for (long double x : V[k]) vn[k] += x * x;
+    for (int j = k; j < m; ++j) {
+      long double d = 0.0L;
+      for (int i = k; i < n; ++i) d += V[k][size_t(i - k)] * R[size_t(i) * m + j];
+      for (int i = k; i < n; ++i) R[size_t(i) * m + j] -= 2.0L * d * V[k][size_t(i - k)] / vn[k];
+    }
+  }
+  std::vector<long double> y(n), x(m);
+  for (int t = 0; t < n; ++t) {
+    std::fill(y.begin(), y.end(), 0.0L);
+    y[size_t(t)] = 1.0L;
+    for (int k = 0; k < m; ++k) {  // y = Q^T e_t
+      long double d = 0.0L;
+      for (int i = k; i < n; ++i) d += V[k][size_t(i - k)] * y[size_t(i)];
+      for (int i = k; i < n; ++i) y[size_t(i)] -= 2.0L * d * V[k][size_t(i - k)] / vn[k];
+    }
+    for (int r = m - 1; r >= 0; --r) {  // R x = (Q^T e_t)[0, m)
+      long double acc = y[size_t(r)];
+      for (int c = r + 1; c < m; ++c) acc -= R[size_t(r) * m + c] * x[size_t(c)];
+      x[size_t(r)] = acc / R[size_t(r) * m + r];
+    }
+    for (int r = 0; r < m; ++r) out[size_t(r) * n + t] = double(x[size_t(r)]);
+  }
+  for (int i = 0; i < n; ++i) out[size_t(2 * m * n + i)] = double(C(kRedFrom, i));
+  return out;
+}
+
 bbc_status launch_build(Bounds* b, hipStream_t s) {
   BuildArgs a{};
   a.sc = b->scene;
@@ -786,6 +843,17 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   a.lc = static_cast<uint32_t*>(b->lc.p);
   a.lu = static_cast<float4*>(b->lu.p);
   a.le = static_cast<float2*>(b->le.p);
+  a.red = nullptr;
+  if ((a.flags & BBC_FLAG_DEGREE_REDUCTION) && b->scene.chain == BBC_CHAIN_RR) {
+    if (!b->red_ready) {
+      static const std::vector<double> table = make_reduction_table();
+      bbc_status e = ensure(b->red_tab, table.size() * sizeof(double), b);
+      if (e) return e;
+      BBC_HIP(hipMemcpyAsync(b->red_tab.p, table.data(), table.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      b->red_ready = true;
+    }
+    a.red = static_cast<const double*>(b->red_tab.p);
+  }
   int dev = 0;
   BBC_HIP(hipGetDevice(&dev));
   int n_cu = 256;

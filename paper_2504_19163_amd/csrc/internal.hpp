@@ -141,6 +141,8 @@ struct Bounds {
   DevBuf cflag, cpos, cE;     // cover-all decision per tuple, its slot (scan), largest E_hi
   DevBuf scan_tmp;
   DevBuf trec;                // packed per-tuple records for the query [n_tuples][32] float
+  DevBuf red_tab;             // degree-reduction table of the two-reflection irradiance bound
+  bool red_ready = false;
   // host copies of the final counts
   BuildCounters host{};
   int64_t n_leaves = 0, n_entries = 0, max_cell = 0;

@@ -10,7 +10,7 @@ def keyset(L):
 
 
 def check_leaf_bounds(orc, osc, L, idx, tol=BOUND_TOL, e_face_value=False, flags=0, uk_face_value=False,
-                      e_tail=None):
+                      e_tail=None, e_abs=0.0):
     """GPU leaves against the oracle's bound of the very same box: the GPU
     bound contains the oracle's and exceeds it by at most `tol`.  With
     e_face_value the irradiance bound is one taken at face value on both
@@ -20,7 +20,10 @@ def check_leaf_bounds(orc, osc, L, idx, tol=BOUND_TOL, e_face_value=False, flags
     bound exceeds the exact one by its rounding slack, theta times the
     magnitude-to-value ratio of its extremal coefficients, which is large
     only where the polynomial's terms cancel (next to a caustic or to total
-    internal reflection)."""
+    internal reflection).  With e_abs a face-value E_lo may also differ by
+    e_abs times E_hi: a lower bound formed as a difference that nearly cancels
+    (a fitted coefficient minus its remainder) is accurate to the rounding of
+    its terms, not of itself."""
     n_tail, n = 0, 0
     for k in idx:
         n += 1
@@ -38,7 +41,8 @@ def check_leaf_bounds(orc, osc, L, idx, tol=BOUND_TOL, e_face_value=False, flags
         if e_face_value:
             if np.isfinite(oE[1]):
                 assert abs(gE[1] - oE[1]) <= tol * oE[1], (k, gE, oE)
-            assert abs(gE[0] - oE[0]) <= tol * oE[0], (k, gE, oE)
+            slack = e_abs * oE[1] if np.isfinite(oE[1]) else 0.0
+            assert abs(gE[0] - oE[0]) <= tol * oE[0] + slack, (k, gE, oE)
             continue
         if np.isfinite(oE[1]):
             assert gE[1] >= oE[1] * (1 - 1e-12), (k, gE, oE)
