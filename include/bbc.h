@@ -316,6 +316,9 @@ bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points
  *                              and replay it on a stream of the handle's own, ordered
  *                              after the caller's stream; 0 (default) launches directly.
  *                              Not with BBC_TUNE_TIMING (timed queries launch directly)
+ *  BBC_TUNE_RR_OUTLINED        two-reflection subdivision: 1 = run the box evaluation as a
+ *                              called (not inlined) function; 0 (default) inlines it (about
+ *                              4 % faster).  The same arithmetic: builds are identical
  * Applies to later calls on the handle; EINVAL for an unknown knob or value. */
 #define BBC_TUNE_QUERY_WAVES 1
 #define BBC_TUNE_QUERY_GRID 2
@@ -326,6 +329,7 @@ bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points
 #define BBC_TUNE_NEWTON_RESULTS 7
 #define BBC_TUNE_STAGED_PAIRS 8
 #define BBC_TUNE_GRAPH 9
+#define BBC_TUNE_RR_OUTLINED 10
 bbc_status bbc_set_tuning(bbc_bounds* b, int32_t knob, int64_t value);
 bbc_status bbc_get_tuning(const bbc_bounds* b, int32_t knob, int64_t* value);
 

@@ -31,7 +31,7 @@ EXPORTS = [
 ]
 SERVER_PAUSED, SERVER_GRAPH = 1, 2
 TUNE_QUERY_WAVES, TUNE_QUERY_GRID, TUNE_BUILD_GRID_PER_CU, TUNE_QUERY_TILE, TUNE_TIMING = 1, 2, 3, 4, 5
-TUNE_NEWTON_STEPS, TUNE_NEWTON_RESULTS, TUNE_STAGED_PAIRS, TUNE_GRAPH = 6, 7, 8, 9
+TUNE_NEWTON_STEPS, TUNE_NEWTON_RESULTS, TUNE_STAGED_PAIRS, TUNE_GRAPH, TUNE_RR_OUTLINED = 6, 7, 8, 9, 10
 
 
 class BBCError(RuntimeError):

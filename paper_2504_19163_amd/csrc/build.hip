@@ -705,6 +705,24 @@ __global__ void __launch_bounds__(kSubdivRRThreads) k_subdiv_rr(BuildArgs a, int
   subdiv_loop<kSubdivRRThreads>(a, depth, ev, lane, S);
 }
 
+// The same box evaluation as a called function (BBC_TUNE_RR_OUTLINED): the
+// workgroup's LDS block and the reduction buffers of the helpers it calls
+// are then reached through the LDS lowering of non-kernel functions rather
+// than fixed offsets; the builds must be identical.
+__device__ __noinline__ BoxOut eval_box_rr_called(const TupleGeom<double>& G, double u0, double u1, double v0,
+                                                  double v1, LdsRR<double, true>& L, int lane, const double* red) {
+  return eval_box_rr<double, true, kSubdivRRThreads>(G, u0, u1, v0, v1, L, lane, red);
+}
+__global__ void __launch_bounds__(kSubdivRRThreads) k_subdiv_rr_called(BuildArgs a, int depth) {
+  __shared__ LdsRR<double, true> L;
+  __shared__ Stage S;
+  const int lane = threadIdx.x;
+  auto ev = [&](const TupleGeom<double>& G, double u0, double u1, double v0, double v1) {
+    return eval_box_rr_called(G, u0, u1, v0, v1, L, lane, a.red);
+  };
+  subdiv_loop<kSubdivRRThreads>(a, depth, ev, lane, S);
+}
+
 // An area-light reflection box (four axes, det M of degree (10,10,3,3)) takes
 // ~70 KB of LDS: four waves share it.
 constexpr int kSubdivRAThreads = 256;
@@ -910,6 +928,8 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
     a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
     if (area)
       hipLaunchKernelGGL(k_subdiv_ra, dim3(unsigned(n_cu) * 2u), dim3(kSubdivRAThreads), 0, s, a, d);
+    else if (rr && b->tune.rr_outlined)
+      hipLaunchKernelGGL(k_subdiv_rr_called, dim3(unsigned(n_cu)), dim3(kSubdivRRThreads), 0, s, a, d);
     else if (rr)
       hipLaunchKernelGGL(k_subdiv_rr, dim3(unsigned(n_cu)), dim3(kSubdivRRThreads), 0, s, a, d);
     else if (refr && (a.flags & BBC_FLAG_IMPLICIT_IRR))

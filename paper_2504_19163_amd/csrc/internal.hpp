@@ -83,6 +83,7 @@ struct Tuning {
   int newton_results = 96;    // pooled Newton: accepted roots kept per 64 pairs before pairs are redone
   int64_t staged_pairs = int64_t(1) << 28;  // worst-case pairs of one staged launch (slices a larger query)
   int graph = 0;              // staged query: 1 = replay the launches as a HIP graph
+  int rr_outlined = 0;        // two-reflection subdivision: box evaluation as a called function
 };
 
 // A staged query's launches captured into a HIP graph on a stream of the

@@ -99,3 +99,27 @@ def test_rr_exhaustive_close_to_brute_force(bbc, orc, walls):
     Et = orc.true_irradiance(osc, pts, lattice=16)
     assert np.all(E <= Et * (1 + 1e-5) + 1e-12)
     assert np.isclose(E, Et, rtol=1e-5, atol=1e-12).mean() >= 0.95
+
+
+def test_rr_called_box_evaluation_gives_the_same_build(bbc):
+    """The subdivision kernel with the box evaluation as a called function
+    (BBC_TUNE_RR_OUTLINED; the LDS block and the helpers' reduction buffers
+    then go through the lowering of non-kernel functions) builds exactly the
+    tree, bounds and grid of the inlined kernel, with and without the degree
+    reduction."""
+    sc = S.facing_walls(8)
+    for flags in (0, bbc.FLAG_DEGREE_REDUCTION):
+        p = dict(max_depth=5, alpha=10.0, flags=flags)
+        B1, B2 = bbc.Bounds(bbc.DeviceScene(sc), p), bbc.Bounds(bbc.DeviceScene(sc), p)
+        B2.set_tuning(bbc.TUNE_RR_OUTLINED, 1)
+        B2.rebuild()
+        L1, L2 = B1.leaves(), B2.leaves()
+        print("flags", flags, "leaves", len(L1["tuple"]), flush=True)
+        assert len(L1["tuple"]) > 1000
+        for k in ("tuple", "box", "uk", "E"):
+            assert np.array_equal(np.asarray(L1[k]).view(np.uint8), np.asarray(L2[k]).view(np.uint8)), k
+        g1, g2 = B1.grid(), B2.grid()
+        for a, b in zip(g1, g2):
+            assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8))
+        B1.free()
+        B2.free()
