@@ -1227,33 +1227,66 @@ __global__ void k_stage_redo(StagedArgs s, const uint32_t* total, const uint32_t
 
 // Sum of each point's contributions in pair order (entry order of its cell),
 // and the optional per-point statistics: |U|, |S|, roots, sum of E~^2 / P.
-__global__ void k_stage_accum(StagedArgs s) {
+// A group of 16 lanes per point: the group loads 16 consecutive pairs at a
+// time (coalesced) and adds them in list order through shuffles, so the sum is
+// the sequential one, bit for bit (the fused query sums the same way); the
+// trip count is the longest list of the wave's four points, the shorter lists
+// padded with +0.0, which leaves a sum of non-negative terms unchanged.
+__global__ void __launch_bounds__(256) k_stage_accum(StagedArgs s) {
+  constexpr int GL = kSelLanes;
   const QueryArgs& a = s.q;
+  const int lane = threadIdx.x % BBC_WAVE, gl = lane % GL, gb = lane - gl;
   const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
   // the moment bound sum E~^2 / P is reported for the bound-optimal P only
   const int sampler = a.mode & BBC_QUERY_SAMPLERS;
   const bool bound_p = sampler == 0 || sampler == BBC_QUERY_BINS;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x) {
+  const int64_t groups = int64_t(gridDim.x) * (blockDim.x / GL);
+  for (int64_t i0 = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / GL - lane / GL; i0 < a.n;
+       i0 += groups) {
+    // i0: the wave's first point; this group's point
+    const int64_t i = i0 + lane / GL;
+    const bool valid = i < a.n;
+    const uint32_t o0 = valid ? min(s.off[i], s.pair_cap) : 0u, o1 = valid ? min(s.off[i + 1], s.pair_cap) : 0u;
+    const uint32_t len = o1 - o0;
+    uint32_t most = len;
+    most = max(most, uint32_t(__shfl_xor(int(most), 16, BBC_WAVE)));
+    most = max(most, uint32_t(__shfl_xor(int(most), 32, BBC_WAVE)));
     double E = 0.0;
-    const uint32_t o0 = min(s.off[i], s.pair_cap), o1 = min(s.off[i + 1], s.pair_cap);
-    for (uint32_t k = o0; k < o1; ++k) E += s.pair_c[k];
-    a.out[i] = float(E);
-    if (a.stats) {
-      uint32_t roots = 0;
-      for (uint32_t k = o0; k < o1; ++k) roots += s.pair_nr[k];
-      const uint32_t nU = s.cnt[i];
-      const CandList cl = cand_list(a, s.cell_b[i]);
-      const float gamma = s.gamma[i];
+    uint32_t roots = 0;
+    for (uint32_t b = 0; b < most; b += GL) {
+      const bool in = b + gl < len;
+      const double v = in ? s.pair_c[o0 + b + gl] : 0.0;
+      if (a.stats && in) roots += s.pair_nr[o0 + b + gl];
+#pragma unroll
+      for (int j = 0; j < GL; ++j) E += __shfl(v, gb + j, BBC_WAVE);
+    }
+    if (valid && gl == 0) a.out[i] = float(E);
+    if (a.stats) {  // uniform across the launch
+#pragma unroll
+      for (int m = GL / 2; m >= 1; m >>= 1) roots += uint32_t(__shfl_xor(int(roots), m, BBC_WAVE));
+      const uint32_t nU = valid ? s.cnt[i] : 0u;
+      const CandList cl = cand_list(a, valid ? s.cell_b[i] : 0u);
+      const float gamma = valid ? s.gamma[i] : 0.f;
+      uint32_t mostU = nU;
+      mostU = max(mostU, uint32_t(__shfl_xor(int(mostU), 16, BBC_WAVE)));
+      mostU = max(mostU, uint32_t(__shfl_xor(int(mostU), 32, BBC_WAVE)));
       double mu2 = 0.0;
-      for (uint32_t j = 0; j < nU; ++j) {
-        const float e = a.ge[cl.at(j)];
-        const float P = select_prob(e, gamma, exhaustive);
-        if (bound_p && P > 0.f && isfinite(e)) mu2 += double(e) * double(e) / double(P);
+      for (uint32_t b = 0; b < mostU; b += GL) {
+        double t = 0.0;
+        if (b + gl < nU) {
+          const float e = a.ge[cl.at(b + gl)];
+          const float P = select_prob(e, gamma, exhaustive);
+          if (bound_p && P > 0.f && isfinite(e)) t = double(e) * double(e) / double(P);
+        }
+#pragma unroll
+        for (int j = 0; j < GL; ++j) mu2 += __shfl(t, gb + j, BBC_WAVE);
       }
-      a.stats[4 * i + 0] = float(nU);
-      a.stats[4 * i + 1] = float(s.off[i + 1] - s.off[i]);
-      a.stats[4 * i + 2] = float(roots);
-      a.stats[4 * i + 3] = float(mu2);
+      if (valid && gl == 0) {
+        a.stats[4 * i + 0] = float(nU);
+        a.stats[4 * i + 1] = float(s.off[i + 1] - s.off[i]);
+        a.stats[4 * i + 2] = float(roots);
+        a.stats[4 * i + 3] = float(mu2);
+      }
     }
   }
 }
@@ -1400,7 +1433,8 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
       hipLaunchKernelGGL(k_stage_newton<BBC_CHAIN_R>, dim3(gp), dim3(64), 0, st, s, s.off + n);
     if (ev1) BBC_HIP(hipEventRecord(ev1, st));
   }
-  hipLaunchKernelGGL(k_stage_accum, dim3(gpt), dim3(256), 0, st, s);
+  const unsigned ga = unsigned(std::min<int64_t>((n + 15) / 16, 65536));
+  hipLaunchKernelGGL(k_stage_accum, dim3(ga), dim3(256), 0, st, s);
   BBC_HIP(hipGetLastError());
   return BBC_OK;
 }
