@@ -799,6 +799,10 @@ bbc_status bbc_set_tuning(bbc_bounds* h, int32_t knob, int64_t value) {
       if (value != 0 && value != 1) return invalid("rr_outlined must be 0 or 1");
       b->tune.rr_outlined = int(value);
       return BBC_OK;
+    case BBC_TUNE_NEWTON_GRID_PER_CU:
+      if (value < 0 || value > 64) return invalid("newton grid per CU must be in [0, 64]");
+      b->tune.newton_grid_per_cu = int(value);
+      return BBC_OK;
     default:
       return invalid("unknown tuning knob");
   }
@@ -818,6 +822,7 @@ bbc_status bbc_get_tuning(const bbc_bounds* h, int32_t knob, int64_t* value) {
     case BBC_TUNE_STAGED_PAIRS: *value = b->tune.staged_pairs; return BBC_OK;
     case BBC_TUNE_GRAPH: *value = b->tune.graph; return BBC_OK;
     case BBC_TUNE_RR_OUTLINED: *value = b->tune.rr_outlined; return BBC_OK;
+    case BBC_TUNE_NEWTON_GRID_PER_CU: *value = b->tune.newton_grid_per_cu; return BBC_OK;
     default: return invalid("unknown tuning knob");
   }
 }

@@ -84,6 +84,7 @@ struct Tuning {
   int64_t staged_pairs = int64_t(1) << 28;  // worst-case pairs of one staged launch (slices a larger query)
   int graph = 0;              // staged query: 1 = replay the launches as a HIP graph
   int rr_outlined = 0;        // two-reflection subdivision: box evaluation as a called function
+  int newton_grid_per_cu = 0; // pooled Newton workgroups per CU (0: occupancy API)
 };
 
 // A staged query's launches captured into a HIP graph on a stream of the

@@ -30,9 +30,14 @@ __device__ __forceinline__ Dl<T> operator*(Dl<T> x, Dl<T> y) {
 }
 template <class T>
 __device__ __forceinline__ Dl<T> operator*(T s, Dl<T> x) { return Dl<T>{s * x.v, s * x.a, s * x.b}; }
+// Reciprocal: FP64 correctly rounded (the polish); FP32 by the hardware's
+// approximate reciprocal (1 ulp), enough for the FP32 iterations, which only
+// bring a start to the FP64 polish that decides the root.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 template <class T>
 __device__ __forceinline__ Dl<T> operator/(Dl<T> x, Dl<T> y) {
-  const T q = x.v / y.v, iy = T(1) / y.v;
+  const T iy = recip(y.v), q = x.v * iy;
   return Dl<T>{q, (x.a - q * y.a) * iy, (x.b - q * y.b) * iy};
 }
 template <class T>
@@ -146,7 +151,7 @@ __device__ __forceinline__ PathT<T> eval_path(const TupleGeom<T>& G, int chain, 
   const T Pu = dot(c, s), Pu_u = dot(c_u, s) + dot(c, G.e1), Pu_v = dot(c_v, s) + dot(c, G.e2);
   const V3<T> sf1 = cross(s, G.f1), sf1_u = cross(G.e1, G.f1), sf1_v = cross(G.e2, G.f1);
   const T Pv = dot(sf1, dt), Pv_u = dot(sf1_u, dt) + dot(sf1, dt_u), Pv_v = dot(sf1_v, dt) + dot(sf1, dt_v);
-  const T iq = T(1) / Q;
+  const T iq = recip(Q);
   r.uk = Pu * iq;
   r.vk = Pv * iq;
   r.t = dot(sf1, G.f2) * iq;

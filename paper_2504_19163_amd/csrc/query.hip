@@ -270,8 +270,9 @@ __device__ __forceinline__ int newton32(const TupleGeom<float>& Gf, float tu, fl
     const PathT<float> p = eval_path<float>(Gf, CH, st.u, st.v);
     const float ru_ = p.uk - tu, rv_ = p.vk - tv;
     if (!(isfinite(p.det)) || p.det == 0.f) return 1;
-    const float du = (p.J11 * ru_ - p.J01 * rv_) / p.det;
-    const float dv = (-p.J10 * ru_ + p.J00 * rv_) / p.det;
+    const float idet = recip(p.det);
+    const float du = (p.J11 * ru_ - p.J01 * rv_) * idet;
+    const float dv = (-p.J10 * ru_ + p.J00 * rv_) * idet;
     st.u -= du;
     st.v -= dv;
     st.t_last = p.t;
@@ -1329,10 +1330,20 @@ void staged_carve(void* base, int64_t n, size_t pairs, StagedWork& w) {
 // Workgroups of a pooled Newton kernel that fit on the device at once (its
 // LDS and registers allow a few per compute unit), cached per device and chain.
 template <typename K>
-static bbc_status pool_grid(K kernel, int chain, int* out) {
+static bbc_status pool_grid(K kernel, int chain, int per_cu_tuned, int* out) {
   static std::atomic<int> cache[64][4];  // the three chains, then the area-light reflection
+  static std::atomic<int> cus[64];
   int dev = 0;
   BBC_HIP(hipGetDevice(&dev));
+  if (per_cu_tuned > 0) {
+    int n_cu = dev < 64 ? cus[dev].load() : 0;
+    if (n_cu <= 0) {
+      BBC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+      if (dev < 64) cus[dev].store(n_cu);
+    }
+    *out = per_cu_tuned * std::max(1, n_cu);
+    return BBC_OK;
+  }
   if (dev < 64 && chain >= 0 && chain < 4 && cache[dev][chain].load() > 0) {
     *out = cache[dev][chain].load();
     return BBC_OK;
@@ -1348,7 +1359,8 @@ static bbc_status pool_grid(K kernel, int chain, int* out) {
 // The five stage launches of one staged query; events (nullable) bracket the
 // Newton kernel.
 static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pairs, int newton_steps,
-                             int newton_results, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
+                             int newton_results, int newton_grid_per_cu, hipEvent_t ev0, hipEvent_t ev1,
+                             hipStream_t st) {
   const uint32_t res_cap = uint32_t(std::min(std::max(newton_results, 1), kRes));
   const int64_t n = q.n;
   StagedArgs s{};
@@ -1395,28 +1407,28 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
     int nres = 0;
     const unsigned gr = unsigned(std::min<size_t>((pairs + 255) / 256, 128));
     if (q.sc.chain == BBC_CHAIN_RR) {
-      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_RR>, BBC_CHAIN_RR, &nres))) return e;
+      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_RR>, BBC_CHAIN_RR, newton_grid_per_cu, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
       hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_RR>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
                          newton_steps, res_cap);
       if (ev1) BBC_HIP(hipEventRecord(ev1, st));
       hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_RR>, dim3(gr), dim3(256), 0, st, s, s.off + n, s.off + n + 1);
     } else if (q.sc.chain == BBC_CHAIN_T) {
-      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_T>, BBC_CHAIN_T, &nres))) return e;
+      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_T>, BBC_CHAIN_T, newton_grid_per_cu, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
       hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_T>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
                          newton_steps, res_cap);
       if (ev1) BBC_HIP(hipEventRecord(ev1, st));
       hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_T>, dim3(gr), dim3(256), 0, st, s, s.off + n, s.off + n + 1);
     } else if (q.sc.eedge) {
-      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_R, true>, 3, &nres))) return e;
+      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_R, true>, 3, newton_grid_per_cu, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
       hipLaunchKernelGGL((k_stage_newton_pool<BBC_CHAIN_R, true>), dim3(gq), dim3(64), 0, st, s, s.off + n,
                          s.off + n + 1, newton_steps, res_cap);
       if (ev1) BBC_HIP(hipEventRecord(ev1, st));
       hipLaunchKernelGGL(k_stage_redo<BBC_CHAIN_R>, dim3(gr), dim3(256), 0, st, s, s.off + n, s.off + n + 1);
     } else {
-      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_R>, BBC_CHAIN_R, &nres))) return e;
+      if ((e = pool_grid(k_stage_newton_pool<BBC_CHAIN_R>, BBC_CHAIN_R, newton_grid_per_cu, &nres))) return e;
       const unsigned gq = unsigned(std::min<size_t>((pairs + 63) / 64, size_t(nres)));
       hipLaunchKernelGGL(k_stage_newton_pool<BBC_CHAIN_R>, dim3(gq), dim3(64), 0, st, s, s.off + n, s.off + n + 1,
                          newton_steps, res_cap);
@@ -1456,7 +1468,8 @@ static bbc_status staged_slice_run(const Bounds* b, const float* pts, int64_t n,
   QueryArgs q = make_args(b, pts + i0, m, spp, seed, base + i0, mode, out + i0, stats ? stats + 4 * i0 : nullptr,
                           counters);
   q.pstride = n;
-  return run_staged(q, w, w.pairs, b->tune.newton_steps, b->tune.newton_results, ev0, ev1, st);
+  return run_staged(q, w, w.pairs, b->tune.newton_steps, b->tune.newton_results, b->tune.newton_grid_per_cu, ev0,
+                    ev1, st);
 }
 
 bbc_status launch_query_staged(Bounds* b, const float* pts, int64_t n, int32_t spp, uint64_t seed, int64_t base,
@@ -1553,7 +1566,8 @@ bbc_status launch_query_batch(const Bounds* b, const float* pts, int64_t n, cons
     q.reqs = reqs;
     q.ioff = i0;
     const bool ev = i0 == 0;
-    bbc_status e = run_staged(q, w, w.pairs, b->tune.newton_steps, b->tune.newton_results, ev ? ev0 : nullptr,
+    bbc_status e = run_staged(q, w, w.pairs, b->tune.newton_steps, b->tune.newton_results,
+                              b->tune.newton_grid_per_cu, ev ? ev0 : nullptr,
                               ev ? ev1 : nullptr, st);
     if (e) return e;
   }
