@@ -317,6 +317,17 @@ __device__ __forceinline__ bool polish64(const TupleGeom<double>& Gd, double tud
   return true;
 }
 
+// The polish as a called function, for the two-reflection pooled kernel: its
+// FP64 dual-number path evaluation otherwise sets that kernel's register
+// count (256 VGPRs and 88 AGPRs inlined, one wave per SIMD); called, the
+// kernel fits two waves per SIMD (FP32 kernels lose more to the call than
+// they gain, and keep it inlined).
+template <int CH>
+__device__ __noinline__ bool polish64_called(const TupleGeom<double>& Gd, double tud, double tvd, float u, float v,
+                                             double& ud, double& vd, double& E, WorkCount& wc) {
+  return polish64<CH>(Gd, tud, tvd, u, v, ud, vd, E, wc);
+}
+
 // Roots of one tuple taken in start order: a root within 1e-7 (in u1) of one
 // of the first four accepted roots is the same root found again.
 struct RootSum {
@@ -904,7 +915,10 @@ struct NewtonPool {
 // takes its own light point (a separate instantiation, so that the point-light
 // kernel carries none of that code).
 template <int CH, bool AREA = false>
-__global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
+// Two waves per SIMD at most 256 registers each (LDS allows six workgroups per
+// compute unit): the register budget the compiler must meet.
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
                                                           int steps, uint32_t res_cap) {
   constexpr bool RR = CH == BBC_CHAIN_RR;
   using Pool = NewtonPool<CH, AREA>;
@@ -1016,7 +1030,10 @@ __global__ void __launch_bounds__(64) k_stage_newton_pool(StagedArgs s, const ui
         kk = L.ck[lane];
         TupleGeom<double> Gd = tuple_geom_rec<double, RR>(&L.rec[p * RS], a.sc);
         if constexpr (AREA) Gd.x0 = mk(L.lx[p], L.ly[p], L.lz[p]);
-        ok = polish64<CH>(Gd, L.tud[p], L.tvd[p], L.cu[lane], L.cv[lane], ud, vd, E, wc);
+        if constexpr (RR)
+          ok = polish64_called<CH>(Gd, L.tud[p], L.tvd[p], L.cu[lane], L.cv[lane], ud, vd, E, wc);
+        else
+          ok = polish64<CH>(Gd, L.tud[p], L.tvd[p], L.cu[lane], L.cv[lane], ud, vd, E, wc);
       }
       const uint64_t m = __ballot(ok);
       if (ok) {
