@@ -616,6 +616,10 @@ struct StagedArgs {
   double* pair_c;
   uint8_t* pair_nr;   // [pairs] roots found per pair (written when stats are requested)
   uint32_t pair_cap;
+  // the count pass's decisions, one bit per candidate, 16 per word, bit_stride
+  // words per point; held in pair_c's space, which is free until Newton
+  uint16_t* bits;
+  uint32_t bit_stride;
 };
 
 __global__ void k_stage_gamma(StagedArgs s) {
@@ -810,7 +814,9 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
 // candidate (bound-optimal, exhaustive, uniform): a group of GL = 16 lanes per
 // point, four points per wave (a cell list holds ~16 candidates), the
 // candidates of a point in list order in chunks of GL, so the pairs come out
-// in the same order as from the one-wave-per-point kernels above.
+// in the same order as from the one-wave-per-point kernels above.  The count
+// pass draws the Bernoulli decisions (one Philox evaluation per candidate) and
+// keeps them as bits; the fill pass reads the bits instead of drawing again.
 constexpr int kSelLanes = 16;
 template <bool FILL>
 __global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* sel) {
@@ -827,18 +833,20 @@ __global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* s
     const float gamma = valid ? s.gamma[i] : 0.f;
     const PointReq pr = point_req(a, valid ? i : i0);
     const float Pu = fminf(pr.W, float(nU)) / float(nU);
+    uint16_t* bits = s.bits + size_t(valid ? i : 0) * s.bit_stride;
     uint32_t o = FILL && valid ? s.off[i] : 0u, c = 0;
     for (uint32_t j0 = 0; j0 < nU; j0 += GL) {  // the group's lanes run the same trip count
       const uint32_t j = j0 + gl;
       bool take = false;
       float P = 0.f;
       uint32_t T = 0;
-      if (j < nU) {
-        T = a.gt[cl.at(j)];
-        P = uniform ? Pu : select_prob(a.ge[cl.at(j)], gamma, exhaustive);
-        take = selection_uniform(pr.seed, pr.key, tuple_key(a, T)) < P;
-      }
       if constexpr (FILL) {
+        const uint32_t word = bits[j0 / GL];
+        take = j < nU && ((word >> gl) & 1u) != 0u;
+        if (take) {
+          T = a.gt[cl.at(j)];
+          P = uniform ? Pu : select_prob(a.ge[cl.at(j)], gamma, exhaustive);
+        }
         const uint32_t m = uint32_t(__ballot(take) >> (GL * g)) & ((1u << GL) - 1u);
         const uint32_t rank = __popc(m & ((1u << gl) - 1u));
         if (take && o + rank < s.pair_cap) {
@@ -848,6 +856,13 @@ __global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* s
         }
         o += __popc(m);
       } else {
+        if (j < nU) {
+          T = a.gt[cl.at(j)];
+          P = uniform ? Pu : select_prob(a.ge[cl.at(j)], gamma, exhaustive);
+          take = P > 0.f && selection_uniform(pr.seed, pr.key, tuple_key(a, T)) < P;
+        }
+        const uint32_t m = uint32_t(__ballot(take) >> (GL * g)) & ((1u << GL) - 1u);
+        if (gl == 0 && j0 < nU) bits[j0 / GL] = uint16_t(m);
         c += take ? 1u : 0u;
       }
     }
@@ -1394,6 +1409,10 @@ static bbc_status run_staged(const QueryArgs& q, const StagedWork& w, size_t pai
   s.pair_c = w.pair_c;
   s.pair_nr = w.pair_nr;
   s.pair_cap = uint32_t(std::min<size_t>(pairs, 0xffffffffu));
+  // pairs >= n * (the fullest cell's candidates), so n * bit_stride 16-bit
+  // words fit pair_c's 8 * pairs bytes
+  s.bits = reinterpret_cast<uint16_t*>(w.pair_c);
+  s.bit_stride = uint32_t((pairs / size_t(std::max<int64_t>(n, 1)) + kSelLanes - 1) / kSelLanes);
   const unsigned grid = unsigned(std::min<int64_t>(n, 256 * 64));
   const unsigned gpt = unsigned(std::min<int64_t>((n + 255) / 256, 4096));
   hipLaunchKernelGGL(k_stage_gamma, dim3(gpt), dim3(256), 0, st, s);
