@@ -66,20 +66,31 @@ PEAK_UNPACKED = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # tensors (two of degree (10,10): 3630 flop), and 3 flop per coefficient pair
 # of its ratio bounds (Pu/Q and Pv/Q at 25 pairs, t at 16, |Q^3/det M| at 121).
 FLOP_NEWTON_ITER = 150
+# The same counted per chain on the code's path evaluation (value and
+# Jacobian by forward differentiation, the 2x2 step; FMA = 2, a division,
+# reciprocal or square root = 1): single reflection ~256, refraction ~330,
+# two reflections ~670 (two reflected directions with dual-number derivatives
+# and six rational divisions).
+FLOP_ITER_COUNTED = {"sphere131072": 256, "water512x512": 330, "walls64x64": 670}
 FLOP_SUBDIV_BOX = 900 + 3630 + 3 * (25 + 25 + 16 + 121)
 # HBM bytes of one launch of a kernel from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
 # 256 MiB device copy; valid only while the kernel sources hash to the digest
 # they were measured with (null afterwards).
 COUNTERS = {
-    # k_subdiv, per build of the sphere (9 launches, 39,961 boxes):
-    # profiles/subdiv_sphere131072_hbm_sq_counters.md
+    # k_subdiv, per build of the sphere (9 launches, 39,961 boxes; builds 2 and 3
+    # of profiles/subdiv_sphere131072_hbm_sq_counters.md averaged)
     "k_subdiv": dict(
-        sources=["paper_2504_19163_amd/csrc/build.hip", "paper_2504_19163_amd/csrc/box_r.hpp",
-                 "paper_2504_19163_amd/csrc/bern_dev.hpp", "paper_2504_19163_amd/csrc/dev_common.hpp",
-                 "paper_2504_19163_amd/csrc/geom_dev.hpp"],
-        sha256="ceb56336bbb7b99e2f0258878c12fa6c5b81c1ba6a9960e19d4be203cd2bd2c4",
-        fetch_kib=22876.8, write_kib=2835.2, fetch_scale=262144.0 / 131088.5625, write_scale=1.0),
+        sources=['paper_2504_19163_amd/csrc/build.hip', 'paper_2504_19163_amd/csrc/box_r.hpp', 'paper_2504_19163_amd/csrc/bern_dev.hpp', 'paper_2504_19163_amd/csrc/dev_common.hpp', 'paper_2504_19163_amd/csrc/geom_dev.hpp'],
+        sha256="39f9d318bce3459945686e5b90b26138d4862741f563a1c2a59f1d793e1ae2f4",
+        fetch_kib=22873.2, write_kib=2829.9, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
+    # the pooled Newton kernels of the serving stream, mean per launch over the
+    # run's 393 launches of all three chains
+    # (profiles/serving_stream_three_scenes_newton_hbm_counters.md)
+    "newton_stream": dict(
+        sources=['paper_2504_19163_amd/csrc/query.hip', 'paper_2504_19163_amd/csrc/path_dev.hpp', 'paper_2504_19163_amd/csrc/geom_dev.hpp', 'paper_2504_19163_amd/csrc/dev_common.hpp', 'paper_2504_19163_amd/csrc/internal.hpp'],
+        sha256="126b5bc56cc91449a6a0e3949fb3e3345e7192e708cfd911ffd4dbc173d3018a",
+        fetch_kib=126852.7, write_kib=103522.2, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
 }
 
 
@@ -294,7 +305,7 @@ def serving_headline(bbc, torch, res, steps, warmup, chunk, seed=5, sweep=(0.5, 
     # algorithmic work of the plain timed pass: the same requests again with
     # the library's work counters (same seeds, so the same iterations)
     it32 = it64 = pairs = 0
-    per_scene = {r["key"]: dict(requests=0, points=0) for r in res}
+    per_scene = {r["key"]: dict(requests=0, points=0, it32=0, it64=0) for r in res}
     for i in timed:
         r = trace[i]
         _, _, hs = bounds[r["scene"]].query(reqs[i], r["spp"], r["seed"], mode=bbc.QUERY_STAGED, host_stats=True)
@@ -304,6 +315,8 @@ def serving_headline(bbc, torch, res, steps, warmup, chunk, seed=5, sweep=(0.5, 
         ps = per_scene[res[r["scene"]]["key"]]
         ps["requests"] += 1
         ps["points"] += r["n"]
+        ps["it32"] += hs["n_iter_fp32"]
+        ps["it64"] += hs["n_iter_fp64"]
     kms = float(np.sum(kern))
     return dict(
         n_points=n_pts, timed_s=t_timed, served_ms=served_ms, plain_ms=plain_ms, identical=identical,
@@ -658,6 +671,8 @@ def main():
     plain_qs = h["n_points"] / (sum(h["plain_ms"]) / 1e3)
     lat = next((r for r in h["sweep"] if r["rate_x_plain_capacity"] == 1.0), None)
     ach32 = h["it32"] * FLOP_NEWTON_ITER / (h["newton_ms"] * 1e-3) / 1e12
+    counted = sum(v["it32"] * FLOP_ITER_COUNTED[k] for k, v in h["per_scene"].items())
+    ach_counted = counted / (h["newton_ms"] * 1e-3) / 1e12
     ach64 = h["it64"] * FLOP_NEWTON_ITER / (h["newton_ms"] * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -673,7 +688,9 @@ def main():
         "dtype": "fp32+fp64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "requests_per_step": args.chunk, "timed_requests": h["n_timed"],
-                   "timed_points": int(h["n_points"]), "requests_by_scene": h["per_scene"],
+                   "timed_points": int(h["n_points"]),
+                   "requests_by_scene": {k: {"requests": v["requests"], "points": v["points"]}
+                                         for k, v in h["per_scene"].items()},
                    "query_form": "served (continuous batching)", "parallelism": "single GPU"},
         "latency_ms": ({"p50": lat["served"]["p50_ms"], "p99": lat["served"]["p99_ms"],
                         "load": f"Poisson arrivals at the plain form's capacity ({lat['offered_req_s']} requests/s)"}
@@ -690,6 +707,10 @@ def main():
                      "flop_per_iteration": FLOP_NEWTON_ITER, "fp32_iterations": int(h["it32"]),
                      "fp64_polish_iterations": int(h["it64"]),
                      "fp64_polish_achieved_tflops": round(ach64, 5), "fp64_peak": PEAK_FP64,
+                     "flop_per_iteration_counted": FLOP_ITER_COUNTED,
+                     "fp32_iterations_by_scene": {k: int(v["it32"]) for k, v in h["per_scene"].items()},
+                     "achieved_counted_tflops": round(ach_counted, 5),
+                     "frac_counted": round(ach_counted / PEAK_FP32, 6),
                      "unpacked_fp32_peak": round(PEAK_UNPACKED, 1),
                      "kernel_ms_total": round(h["newton_ms"], 3), "avg_launch_ms": round(h["newton_launch_ms"], 4),
                      "timing": "HIP events around every Newton launch of the plain form's timed pass"},
