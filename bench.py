@@ -9,7 +9,7 @@ are built once and stay resident in device memory --
   * single refraction through a water surface (524288 triangles x 4 point
     lights, wave amplitudes scaled by 0.04, depth cap 6),
   * two reflections between two facing rippled walls (8192 + 8192 triangles,
-    67.1 M candidate pairs, depth cap 5, alpha 10) --
+    67.1 M candidate pairs, depth cap 6, alpha 10) --
 
 and a stream of shading-point query requests is answered over them: request
 sizes floor(exp U[ln 256, ln 65536]) points uniform on the chosen receiver,
@@ -50,7 +50,7 @@ METRIC = "shading-point caustic queries/s at matched error; p50/p99 batch latenc
 WORKLOAD = ("serving stream over device-resident bounds of three scenes: displaced sphere 131072 triangles "
             "(single reflection, depth cap 8), water surface 524288 triangles x 4 lights (single refraction, "
             "amplitudes x 0.04, depth cap 6), facing walls 8192 + 8192 triangles (two reflections, 67.1M candidate "
-            "pairs, depth cap 5); requests of floor(exp U[ln 256, ln 65536]) points, W uniform over "
+            "pairs, depth cap 6); requests of floor(exp U[ln 256, ln 65536]) points, W uniform over "
             "{16,32,64,128,256}, scene uniform; 64 GB work-space budget, 4 batch slots")
 # MI355X published vector peaks (TFLOP/s).  FP32 157.3 counts packed FP32
 # (two lanes per instruction); this library compiles without packed FP32, so
@@ -203,8 +203,8 @@ SCENES = [
      lambda S: S.displaced_sphere(7), dict(max_depth=8, sigma=1e-4, alpha=2.0, grid_res=512)),
     ("water512x512", "single refraction, water surface 524288 triangles x 4 lights (amplitudes x 0.04), depth cap 6",
      lambda S: S.water_surface(m=512, amp_scale=0.04), dict(max_depth=6, sigma=1e-4, alpha=2.0, grid_res=512)),
-    ("walls64x64", "two reflections, facing walls 8192 + 8192 triangles (67.1M candidate pairs), depth cap 5",
-     lambda S: S.facing_walls(64), dict(max_depth=5, sigma=1e-4, alpha=10.0, grid_res=512)),
+    ("walls64x64", "two reflections, facing walls 8192 + 8192 triangles (67.1M candidate pairs), depth cap 6",
+     lambda S: S.facing_walls(64), dict(max_depth=6, sigma=1e-4, alpha=10.0, grid_res=512)),
 ]
 
 
@@ -480,11 +480,11 @@ def degree_reduction_section(bbc, S, torch, steps=2, n_side=256, spp=256):
     sc = S.facing_walls(64)
     pts = torch.as_tensor(S.receiver_points(sc, n_side), device=dev)
     sub = torch.as_tensor(S.receiver_points(sc, 64), device=dev)
-    out = {"workload": "two reflections, facing walls 8192 + 8192 triangles, depth cap 5, E-ratio 10, "
+    out = {"workload": "two reflections, facing walls 8192 + 8192 triangles, depth cap 6, E-ratio 10, "
                        f"{n_side}x{n_side} receiver points, {spp} samples/point; with and without the reduction of "
                        "Den^3 and det M (46, 46) to degree (16, 16) plus remainders"}
     for name, flags in (("full_degree", 0), ("reduced", bbc.FLAG_DEGREE_REDUCTION)):
-        B = bbc.Bounds(bbc.DeviceScene(sc), dict(max_depth=5, alpha=10.0, flags=flags))
+        B = bbc.Bounds(bbc.DeviceScene(sc), dict(max_depth=6, alpha=10.0, flags=flags))
         tb, tq = [], []
         for k in range(steps):
             t = time.perf_counter()

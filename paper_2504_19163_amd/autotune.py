@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 WORKLOADS = {
     "sphere131072": (lambda S: S.displaced_sphere(7), dict(max_depth=8, alpha=2.0)),
     "water512x512": (lambda S: S.water_surface(m=512, amp_scale=0.04), dict(max_depth=6, alpha=2.0)),
-    "walls64x64": (lambda S: S.facing_walls(64), dict(max_depth=5, alpha=10.0)),
+    "walls64x64": (lambda S: S.facing_walls(64), dict(max_depth=6, alpha=10.0)),
 }
 
 # staged-query knobs in tuning order, with their candidate values
