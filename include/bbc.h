@@ -319,6 +319,11 @@ bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points
  *  BBC_TUNE_NEWTON_GRID_PER_CU staged query: workgroups per compute unit of the pooled
  *                              Newton kernel (1..64; 0, the default, asks the occupancy
  *                              API how many stay resident)
+ *  BBC_TUNE_BUILD_GRAPH        build and rebuild: 1 = capture the launch sequence (counter
+ *                              reset, level 0, domain initialisation, one subdivision launch
+ *                              per depth) into the handle's HIP graph, updated in place and
+ *                              replayed; 0 (default) launches directly.  Not with
+ *                              BBC_TUNE_TIMING
  *  BBC_TUNE_RR_OUTLINED        two-reflection subdivision: 1 = run the box evaluation as a
  *                              called (not inlined) function; 0 (default) inlines it (about
  *                              4 % faster).  The same arithmetic: builds are identical
@@ -334,6 +339,7 @@ bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points
 #define BBC_TUNE_GRAPH 9
 #define BBC_TUNE_RR_OUTLINED 10
 #define BBC_TUNE_NEWTON_GRID_PER_CU 11
+#define BBC_TUNE_BUILD_GRAPH 12
 bbc_status bbc_set_tuning(bbc_bounds* b, int32_t knob, int64_t value);
 bbc_status bbc_get_tuning(const bbc_bounds* b, int32_t knob, int64_t* value);
 

@@ -498,6 +498,7 @@ bbc_status bbc_free_bounds(bbc_bounds* h) {
   (void)hipDeviceSynchronize();
   release_all(b);
   release_graph(b->qgraph);
+  release_graph(b->bgraph);
   for (hipEvent_t ev : b->tev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : b->bev)
     if (ev) (void)hipEventDestroy(ev);
@@ -803,6 +804,10 @@ bbc_status bbc_set_tuning(bbc_bounds* h, int32_t knob, int64_t value) {
       if (value < 0 || value > 64) return invalid("newton grid per CU must be in [0, 64]");
       b->tune.newton_grid_per_cu = int(value);
       return BBC_OK;
+    case BBC_TUNE_BUILD_GRAPH:
+      if (value != 0 && value != 1) return invalid("build graph must be 0 or 1");
+      b->tune.build_graph = int(value);
+      return BBC_OK;
     default:
       return invalid("unknown tuning knob");
   }
@@ -823,6 +828,7 @@ bbc_status bbc_get_tuning(const bbc_bounds* h, int32_t knob, int64_t* value) {
     case BBC_TUNE_GRAPH: *value = b->tune.graph; return BBC_OK;
     case BBC_TUNE_RR_OUTLINED: *value = b->tune.rr_outlined; return BBC_OK;
     case BBC_TUNE_NEWTON_GRID_PER_CU: *value = b->tune.newton_grid_per_cu; return BBC_OK;
+    case BBC_TUNE_BUILD_GRAPH: *value = b->tune.build_graph; return BBC_OK;
     default: return invalid("unknown tuning knob");
   }
 }

@@ -890,62 +890,70 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   }
   const unsigned persistent = g_sub;
 
-  bbc_status st = launch_fill_u32(static_cast<uint32_t*>(b->counters.p), 0u, sizeof(BuildCounters) / 4, s);
-  if (st) return st;
-  a.qin = nullptr;
-  a.qout = static_cast<QItem*>(b->q[0].p);
-  const unsigned g0 = unsigned(std::max<int64_t>(1, std::min<int64_t>(b->n_tuples, int64_t(n_cu) * 64)));
-  const bool refr = b->scene.chain == BBC_CHAIN_T, rr = b->scene.chain == BBC_CHAIN_RR;
-  const bool area = b->scene.eedge != nullptr;
-  if (area) {
-    hipLaunchKernelGGL(k_level0_ra, dim3(g0), dim3(64), 0, s, a);
-  } else if (rr) {
-    hipLaunchKernelGGL(k_level0_rr, dim3(g0), dim3(kInitRRThreads), 0, s, a);
-  } else if (refr) {
-    hipLaunchKernelGGL(k_level0_t, dim3(g0), dim3(64), 0, s, a);
-  } else {
-    hipLaunchKernelGGL(k_level0, dim3(g0), dim3(64), 0, s, a);
-    BBC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_level0_fp64, dim3(g_fp64), dim3(64), 0, s, a);
-  }
-  BBC_HIP(hipGetLastError());
-  if (a.init_levels > 0) {
-    if (area)
-      hipLaunchKernelGGL(k_init_ra, dim3(persistent), dim3(64), 0, s, a);
-    else if (rr)
-      hipLaunchKernelGGL(k_init_rr, dim3(persistent), dim3(kInitRRThreads), 0, s, a);
-    else if (refr)
-      hipLaunchKernelGGL(k_init_t, dim3(persistent), dim3(64), 0, s, a);
-    else
-      hipLaunchKernelGGL(k_init, dim3(g_init), dim3(64), 0, s, a);
-    BBC_HIP(hipGetLastError());
-  }
   const bool timed = b->tune.timing && b->bev[0];
-  if (timed) BBC_HIP(hipEventRecord(b->bev[0], s));
   b->subdiv_launches = a.max_depth + 1;
-  for (int d = 0; d <= a.max_depth; ++d) {
-    a.qin = static_cast<QItem*>(b->q[d & 1].p);
-    a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
-    if (area)
-      hipLaunchKernelGGL(k_subdiv_ra, dim3(unsigned(n_cu) * 2u), dim3(kSubdivRAThreads), 0, s, a, d);
-    else if (rr && b->tune.rr_outlined)
-      hipLaunchKernelGGL(k_subdiv_rr_called, dim3(unsigned(n_cu)), dim3(kSubdivRRThreads), 0, s, a, d);
-    else if (rr)
-      hipLaunchKernelGGL(k_subdiv_rr, dim3(unsigned(n_cu)), dim3(kSubdivRRThreads), 0, s, a, d);
-    else if (refr && (a.flags & BBC_FLAG_IMPLICIT_IRR))
-      hipLaunchKernelGGL(k_subdiv_t<kSubdivTImplicitThreads>, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTImplicitThreads),
-                         0, s, a, d);
-    else if (refr)
-      hipLaunchKernelGGL(k_subdiv_t<kSubdivTThreads>, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTThreads), 0, s, a, d);
-    else
-      hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, s, a, d);
+  // the whole launch sequence (counter reset, level 0, domain
+  // initialisation, one subdivision launch per depth) on stream cs
+  auto enqueue = [&](hipStream_t cs) -> bbc_status {
+    bbc_status st = launch_fill_u32(static_cast<uint32_t*>(b->counters.p), 0u, sizeof(BuildCounters) / 4, cs);
+    if (st) return st;
+    a.qin = nullptr;
+    a.qout = static_cast<QItem*>(b->q[0].p);
+    const unsigned g0 = unsigned(std::max<int64_t>(1, std::min<int64_t>(b->n_tuples, int64_t(n_cu) * 64)));
+    const bool refr = b->scene.chain == BBC_CHAIN_T, rr = b->scene.chain == BBC_CHAIN_RR;
+    const bool area = b->scene.eedge != nullptr;
+    if (area) {
+      hipLaunchKernelGGL(k_level0_ra, dim3(g0), dim3(64), 0, cs, a);
+    } else if (rr) {
+      hipLaunchKernelGGL(k_level0_rr, dim3(g0), dim3(kInitRRThreads), 0, cs, a);
+    } else if (refr) {
+      hipLaunchKernelGGL(k_level0_t, dim3(g0), dim3(64), 0, cs, a);
+    } else {
+      hipLaunchKernelGGL(k_level0, dim3(g0), dim3(64), 0, cs, a);
+      BBC_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_level0_fp64, dim3(g_fp64), dim3(64), 0, cs, a);
+    }
     BBC_HIP(hipGetLastError());
-  }
-  if (timed) {
-    BBC_HIP(hipEventRecord(b->bev[1], s));
-    b->bev_recorded = true;
-  }
-  return BBC_OK;
+    if (a.init_levels > 0) {
+      if (area)
+        hipLaunchKernelGGL(k_init_ra, dim3(persistent), dim3(64), 0, cs, a);
+      else if (rr)
+        hipLaunchKernelGGL(k_init_rr, dim3(persistent), dim3(kInitRRThreads), 0, cs, a);
+      else if (refr)
+        hipLaunchKernelGGL(k_init_t, dim3(persistent), dim3(64), 0, cs, a);
+      else
+        hipLaunchKernelGGL(k_init, dim3(g_init), dim3(64), 0, cs, a);
+      BBC_HIP(hipGetLastError());
+    }
+    if (timed) BBC_HIP(hipEventRecord(b->bev[0], cs));
+    for (int d = 0; d <= a.max_depth; ++d) {
+      a.qin = static_cast<QItem*>(b->q[d & 1].p);
+      a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
+      if (area)
+        hipLaunchKernelGGL(k_subdiv_ra, dim3(unsigned(n_cu) * 2u), dim3(kSubdivRAThreads), 0, cs, a, d);
+      else if (rr && b->tune.rr_outlined)
+        hipLaunchKernelGGL(k_subdiv_rr_called, dim3(unsigned(n_cu)), dim3(kSubdivRRThreads), 0, cs, a, d);
+      else if (rr)
+        hipLaunchKernelGGL(k_subdiv_rr, dim3(unsigned(n_cu)), dim3(kSubdivRRThreads), 0, cs, a, d);
+      else if (refr && (a.flags & BBC_FLAG_IMPLICIT_IRR))
+        hipLaunchKernelGGL(k_subdiv_t<kSubdivTImplicitThreads>, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTImplicitThreads),
+                           0, cs, a, d);
+      else if (refr)
+        hipLaunchKernelGGL(k_subdiv_t<kSubdivTThreads>, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTThreads), 0, cs, a, d);
+      else
+        hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, cs, a, d);
+      BBC_HIP(hipGetLastError());
+    }
+    if (timed) {
+      BBC_HIP(hipEventRecord(b->bev[1], cs));
+      b->bev_recorded = true;
+    }
+    return BBC_OK;
+  };
+  // BBC_TUNE_BUILD_GRAPH: the sequence captured into the handle's build graph
+  // and replayed (not with timing, whose events stay direct launches)
+  if (b->tune.build_graph && !timed) return run_as_graph(b->bgraph, s, enqueue);
+  return enqueue(s);
 }
 
 }  // namespace bbc

@@ -85,6 +85,7 @@ struct Tuning {
   int graph = 0;              // staged query: 1 = replay the launches as a HIP graph
   int rr_outlined = 0;        // two-reflection subdivision: box evaluation as a called function
   int newton_grid_per_cu = 0; // pooled Newton workgroups per CU (0: occupancy API)
+  int build_graph = 0;        // build: 1 = replay the launch sequence as a HIP graph
 };
 
 // A staged query's launches captured into a HIP graph on a stream of the
@@ -163,6 +164,7 @@ struct Bounds {
   bool bev_recorded = false;
   int subdiv_launches = 0;
   QueryGraph qgraph;          // the staged query as a graph (BBC_TUNE_GRAPH)
+  QueryGraph bgraph;          // the build's launch sequence as a graph (BBC_TUNE_BUILD_GRAPH)
 };
 
 // error plumbing

@@ -83,3 +83,35 @@ def test_served_graph_batches_equal_alone(bbc):
         finally:
             srv.close()
     B.free()
+
+
+@pytest.mark.parametrize("case", ["heightfield", "water", "walls", "area"])
+def test_build_graph_replay_equals_direct(bbc, case):
+    """BBC_TUNE_BUILD_GRAPH: the build's launch sequence captured and replayed
+    gives the directly launched build's leaves and grid, bit for bit, on the
+    first capture and on rebuilds that update the executable graph, with
+    eager work between them."""
+    if case == "heightfield":
+        sc, params = S.heightfield_mirror(16), dict(max_depth=4)
+    elif case == "water":
+        sc, params = S.water_surface(m=8, amp_scale=0.04), dict(max_depth=4)
+    elif case == "walls":
+        sc, params = S.facing_walls(4), dict(max_depth=4, alpha=10.0)
+    else:
+        sc, params = S.area_light(S.heightfield_mirror(8), [0.6, 0.0, 0.0], [0.0, 0.4, 0.0]), dict(max_depth=3)
+    B0 = bbc.Bounds(bbc.DeviceScene(sc), params)
+    L0, g0 = B0.leaves(), B0.grid()
+    B = bbc.Bounds(bbc.DeviceScene(sc), params)
+    B.set_tuning(bbc.TUNE_BUILD_GRAPH, 1)
+    for rep in range(3):
+        B.rebuild()
+        torch.ones(1024, device="cuda").mul_(2.0)
+        torch.cuda.synchronize()
+        L, g = B.leaves(), B.grid()
+        for k in ("tuple", "code", "uk", "E"):
+            assert np.array_equal(np.asarray(L[k]), np.asarray(L0[k])), (case, rep, k)
+        for a, b in zip(g, g0):
+            assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8)), (case, rep)
+    assert B.info()["n_boxes"] == B0.info()["n_boxes"]
+    B.free()
+    B0.free()
