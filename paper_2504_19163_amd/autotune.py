@@ -6,7 +6,8 @@ hierarchy, then tunes one knob at a time (coordinate descent, the other knobs
 at their best value so far), timing each candidate value on a fixed set of
 requests shaped like the serving stream (log-uniform sizes in [256, 65536],
 W over {16, ..., 256}) through the staged query, median of three passes; the
-build knob is timed on rebuilds.  Knobs change launch shapes only, never
+build knobs (workgroups per compute unit, graph replay) are timed on
+rebuilds.  Knobs change launch shapes only, never
 results (the library's tests check that), so the choice is free.  The table
 is written as JSON {arch: {workload: {knob: value, "ms": {...}}}}, by default
 to tuning.json beside this module, where bbc.apply_tuning reads it; the entry
@@ -39,6 +40,7 @@ WORKLOADS = {
 # staged-query knobs in tuning order, with their candidate values
 QUERY_KNOBS = [
     ("newton_steps", "TUNE_NEWTON_STEPS", [1, 2, 4, 8]),
+    ("newton_grid_per_cu", "TUNE_NEWTON_GRID_PER_CU", [0, 8, 12, 16]),
     ("graph", "TUNE_GRAPH", [0, 1]),
 ]
 FUSED_KNOBS = [
@@ -46,7 +48,7 @@ FUSED_KNOBS = [
     ("query_tile", "TUNE_QUERY_TILE", [16, 32, 64]),
     ("query_grid", "TUNE_QUERY_GRID", [4096, 16384, 65536]),
 ]
-BUILD_KNOBS = [("build_grid_per_cu", "TUNE_BUILD_GRID_PER_CU", [0, 4, 8, 16])]
+BUILD_KNOBS = [("build_grid_per_cu", "TUNE_BUILD_GRID_PER_CU", [0, 4, 8, 16]), ("build_graph", "TUNE_BUILD_GRAPH", [0, 1])]
 
 
 def _requests(scene, n_req, seed, torch, S):
@@ -133,7 +135,8 @@ def tune_serving(bbc, torch, S, table_arch, n_req=96, log=print):
         make, params = WORKLOADS[key]
         scene = make(S)
         B = bbc.Bounds(bbc.DeviceScene(scene), params)
-        for knob, name in (("TUNE_NEWTON_STEPS", "newton_steps"), ("TUNE_GRAPH", "graph")):
+        for knob, name in (("TUNE_NEWTON_STEPS", "newton_steps"), ("TUNE_NEWTON_GRID_PER_CU", "newton_grid_per_cu"),
+                           ("TUNE_GRAPH", "graph")):
             if name in table_arch.get(key, {}):
                 B.set_tuning(getattr(bbc, knob), table_arch[key][name])
         bounds.append(B)
