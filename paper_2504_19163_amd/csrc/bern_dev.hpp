@@ -69,6 +69,61 @@ __device__ __forceinline__ void conv(const T* __restrict__ av, const T* __restri
   }
 }
 
+// conv() with the LDS reads of each output batched: the terms go eight at a
+// time through clamped, in-range indices (the loads issued together, a
+// scheduling barrier, then the products), and a select leaves the partial
+// sums unchanged for the terms outside the output's support.  The sums are
+// those of conv(), valid terms in (i, j) order, bit for bit; conv() instead
+// branches around each term and waits for each load, which leaves a box's
+// chain of small steps bound by LDS latency.  The batched form takes more
+// registers (up to 16 doubles of one chunk in flight), so it serves the
+// single-reflection chain, whose kernels keep their occupancy with it.
+template <int A1, int A2, int B1, int B2, bool ACC, class T, int NT = BBC_WAVE>
+__device__ __forceinline__ void conv_b(const T* __restrict__ av, const T* __restrict__ am, const T* __restrict__ bv,
+                                       const T* __restrict__ bm, T* __restrict__ cv, T* __restrict__ cm, T sgn,
+                                       int lane) {
+  if constexpr ((A1 + 1) * (A2 + 1) > (B1 + 1) * (B2 + 1)) {
+    conv_b<B1, B2, A1, A2, ACC, T, NT>(bv, bm, av, am, cv, cm, sgn, lane);
+  } else {
+    constexpr int C2 = A2 + B2;
+    constexpr int N = (A1 + B1 + 1) * (C2 + 1);
+    constexpr int NA = (A1 + 1) * (A2 + 1), CH = 8;
+    for (int o = lane; o < N; o += NT) {
+      const int k = o / (C2 + 1), l = o - k * (C2 + 1);
+      T s = 0, sm = 0;
+#pragma unroll
+      for (int t0 = 0; t0 < NA; t0 += CH) {
+        T xb[CH], xm[CH];
+        bool ok[CH];
+#pragma unroll
+        for (int u = 0; u < CH && t0 + u < NA; ++u) {
+          const int i = (t0 + u) / (A2 + 1), j = (t0 + u) % (A2 + 1);
+          const int kb = k - i, lb = l - j;
+          const int b = min(max(kb, 0), B1) * (B2 + 1) + min(max(lb, 0), B2);
+          ok[u] = kb >= 0 && kb <= B1 && lb >= 0 && lb <= B2;
+          xb[u] = bv[b];
+          xm[u] = bm[b];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < CH && t0 + u < NA; ++u) {
+          const T ts = fma(av[t0 + u], xb[u], s);
+          const T tm = fma(am[t0 + u], xm[u], sm);
+          s = ok[u] ? ts : s;
+          sm = ok[u] ? tm : sm;
+        }
+      }
+      if (ACC) {
+        cv[o] = fma(sgn, s, cv[o]);
+        cm[o] = cm[o] + sm;
+      } else {
+        cv[o] = sgn * s;
+        cm[o] = sm;
+      }
+    }
+  }
+}
+
 // Relative error factor of a convolution result from its operands'.
 template <int A1, int A2, int B1, int B2, class T>
 __device__ __forceinline__ T conv_theta(T ta, T tb) {
@@ -92,6 +147,30 @@ __device__ __forceinline__ void combo(const T* const* av, const T* const* am, co
   }
 }
 
+// combo() with each output's K reads issued together before the sums (the
+// same sums in k order), for the same chain as conv_b.
+template <int N, int K, bool ACC, class T, int NT = BBC_WAVE>
+__device__ __forceinline__ void combo_b(const T* const* av, const T* const* am, const T* alpha, T* __restrict__ ov,
+                                        T* __restrict__ om, int lane) {
+  for (int o = lane; o < N; o += NT) {
+    T x[K], xm[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      x[k] = av[k][o];
+      xm[k] = am[k][o];
+    }
+    T s = ACC ? ov[o] : T(0), sm = ACC ? om[o] : T(0);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      s = fma(alpha[k], x[k], s);
+      sm = fma(fabs(alpha[k]), xm[k], sm);
+    }
+    ov[o] = s;
+    om[o] = sm;
+  }
+}
+
 // Degree elevation by one along both axes: (D1, D2) -> (D1+1, D2+1), scaled form.
 template <int D1, int D2, class T, int NT = BBC_WAVE>
 __device__ __forceinline__ void elev11(const T* __restrict__ iv, const T* __restrict__ im, T* __restrict__ ov,
@@ -106,6 +185,25 @@ __device__ __forceinline__ void elev11(const T* __restrict__ iv, const T* __rest
     if (i >= 1 && j >= 1) { d = iv[(i - 1) * (D2 + 1) + j - 1]; md = im[(i - 1) * (D2 + 1) + j - 1]; }
     ov[o] = (a + b) + (c + d);
     om[o] = (ma + mb) + (mc + md);
+  }
+}
+
+// elev11() with its four reads unconditional (clamped indices; the terms
+// outside the input taken as zero by a select), for the same chain as conv_b.
+template <int D1, int D2, class T, int NT = BBC_WAVE>
+__device__ __forceinline__ void elev11_b(const T* __restrict__ iv, const T* __restrict__ im, T* __restrict__ ov,
+                                         T* __restrict__ om, int lane) {
+  constexpr int E2 = D2 + 1, N = (D1 + 2) * (D2 + 2);
+  for (int o = lane; o < N; o += NT) {
+    const int i = o / (E2 + 1), j = o - i * (E2 + 1);
+    const int i0 = min(i, D1), i1 = max(i - 1, 0), j0 = min(j, D2), j1 = max(j - 1, 0);
+    const bool ka = i <= D1 && j <= D2, kb = i >= 1 && j <= D2, kc = i <= D1 && j >= 1, kd = i >= 1 && j >= 1;
+    const T a = iv[i0 * (D2 + 1) + j0], b = iv[i1 * (D2 + 1) + j0];
+    const T c = iv[i0 * (D2 + 1) + j1], d = iv[i1 * (D2 + 1) + j1];
+    const T ma = im[i0 * (D2 + 1) + j0], mb = im[i1 * (D2 + 1) + j0];
+    const T mc = im[i0 * (D2 + 1) + j1], md = im[i1 * (D2 + 1) + j1];
+    ov[o] = ((ka ? a : T(0)) + (kb ? b : T(0))) + ((kc ? c : T(0)) + (kd ? d : T(0)));
+    om[o] = ((ka ? ma : T(0)) + (kb ? mb : T(0))) + ((kc ? mc : T(0)) + (kd ? md : T(0)));
   }
 }
 

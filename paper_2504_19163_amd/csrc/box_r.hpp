@@ -139,41 +139,41 @@ __device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     const T* sm[3] = {L.s[0].m, L.s[1].m, L.s[2].m};
     const V3<T> f1 = G.f1;
     const T ax[3] = {T(0), f1.z, -f1.y}, ay[3] = {-f1.z, T(0), f1.x}, az[3] = {f1.y, -f1.x, T(0)};
-    combo<4, 3, false, T, NT>(sv, sm, ax, L.sf1[0].v, L.sf1[0].m, lane);
-    combo<4, 3, false, T, NT>(sv, sm, ay, L.sf1[1].v, L.sf1[1].m, lane);
-    combo<4, 3, false, T, NT>(sv, sm, az, L.sf1[2].v, L.sf1[2].m, lane);
+    combo_b<4, 3, false, T, NT>(sv, sm, ax, L.sf1[0].v, L.sf1[0].m, lane);
+    combo_b<4, 3, false, T, NT>(sv, sm, ay, L.sf1[1].v, L.sf1[1].m, lane);
+    combo_b<4, 3, false, T, NT>(sv, sm, az, L.sf1[2].v, L.sf1[2].m, lane);
     for (int c = 0; c < 3; ++c) {
       if (c == 0) {
-        conv<1, 1, 1, 1, false, T, NT>(L.n[c].v, L.n[c].m, L.n[c].v, L.n[c].m, L.nn.v, L.nn.m, T(1), lane);
-        conv<1, 1, 1, 1, false, T, NT>(L.d0[c].v, L.d0[c].m, L.n[c].v, L.n[c].m, L.dn.v, L.dn.m, T(1), lane);
+        conv_b<1, 1, 1, 1, false, T, NT>(L.n[c].v, L.n[c].m, L.n[c].v, L.n[c].m, L.nn.v, L.nn.m, T(1), lane);
+        conv_b<1, 1, 1, 1, false, T, NT>(L.d0[c].v, L.d0[c].m, L.n[c].v, L.n[c].m, L.dn.v, L.dn.m, T(1), lane);
       } else {
-        conv<1, 1, 1, 1, true, T, NT>(L.n[c].v, L.n[c].m, L.n[c].v, L.n[c].m, L.nn.v, L.nn.m, T(1), lane);
-        conv<1, 1, 1, 1, true, T, NT>(L.d0[c].v, L.d0[c].m, L.n[c].v, L.n[c].m, L.dn.v, L.dn.m, T(1), lane);
+        conv_b<1, 1, 1, 1, true, T, NT>(L.n[c].v, L.n[c].m, L.n[c].v, L.n[c].m, L.nn.v, L.nn.m, T(1), lane);
+        conv_b<1, 1, 1, 1, true, T, NT>(L.d0[c].v, L.d0[c].m, L.n[c].v, L.n[c].m, L.dn.v, L.dn.m, T(1), lane);
       }
     }
     if constexpr (IRR) {
       const T* dv[3] = {L.d0[0].v, L.d0[1].v, L.d0[2].v};
       const T* dm[3] = {L.d0[0].m, L.d0[1].m, L.d0[2].m};
       const T ag[3] = {G.ng.x, G.ng.y, G.ng.z};
-      combo<4, 3, false, T, NT>(dv, dm, ag, L.g.v, L.g.m, lane);
+      combo_b<4, 3, false, T, NT>(dv, dm, ag, L.g.v, L.g.m, lane);
       // d(n.n)/du = 2 n.dn1,  d(d0.n)/du = e1.n + d0.dn1  (and the same in v)
       const T* nv[3] = {L.n[0].v, L.n[1].v, L.n[2].v};
       const T* nm[3] = {L.n[0].m, L.n[1].m, L.n[2].m};
       const T a_nnu[3] = {T(2) * G.dn1.x, T(2) * G.dn1.y, T(2) * G.dn1.z};
       const T a_nnv[3] = {T(2) * G.dn2.x, T(2) * G.dn2.y, T(2) * G.dn2.z};
-      combo<4, 3, false, T, NT>(nv, nm, a_nnu, L.nnu.v, L.nnu.m, lane);
-      combo<4, 3, false, T, NT>(nv, nm, a_nnv, L.nnv.v, L.nnv.m, lane);
+      combo_b<4, 3, false, T, NT>(nv, nm, a_nnu, L.nnu.v, L.nnu.m, lane);
+      combo_b<4, 3, false, T, NT>(nv, nm, a_nnv, L.nnv.v, L.nnv.m, lane);
       const T* xv[6] = {L.n[0].v, L.n[1].v, L.n[2].v, L.d0[0].v, L.d0[1].v, L.d0[2].v};
       const T* xm[6] = {L.n[0].m, L.n[1].m, L.n[2].m, L.d0[0].m, L.d0[1].m, L.d0[2].m};
       const T a_dnu[6] = {G.e1.x, G.e1.y, G.e1.z, G.dn1.x, G.dn1.y, G.dn1.z};
       const T a_dnv[6] = {G.e2.x, G.e2.y, G.e2.z, G.dn2.x, G.dn2.y, G.dn2.z};
-      combo<4, 6, false, T, NT>(xv, xm, a_dnu, L.dnu.v, L.dnu.m, lane);
-      combo<4, 6, false, T, NT>(xv, xm, a_dnv, L.dnv.v, L.dnv.m, lane);
+      combo_b<4, 6, false, T, NT>(xv, xm, a_dnu, L.dnu.v, L.dnu.m, lane);
+      combo_b<4, 6, false, T, NT>(xv, xm, a_dnv, L.dnv.v, L.dnv.m, lane);
       for (int c = 0; c < 3; ++c) {
         if (c == 0)
-          conv<1, 1, 1, 1, false, T, NT>(L.d0[c].v, L.d0[c].m, L.d0[c].v, L.d0[c].m, L.h.v, L.h.m, T(1), lane);
+          conv_b<1, 1, 1, 1, false, T, NT>(L.d0[c].v, L.d0[c].m, L.d0[c].v, L.d0[c].m, L.h.v, L.h.m, T(1), lane);
         else
-          conv<1, 1, 1, 1, true, T, NT>(L.d0[c].v, L.d0[c].m, L.d0[c].v, L.d0[c].m, L.h.v, L.h.m, T(1), lane);
+          conv_b<1, 1, 1, 1, true, T, NT>(L.d0[c].v, L.d0[c].m, L.d0[c].v, L.d0[c].m, L.h.v, L.h.m, T(1), lane);
       }
     }
   }
@@ -186,13 +186,13 @@ __device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
   // ---- reflected direction d~ = (n.n) d0 - 2 (d0.n) n, and its derivatives
   //      d~_u = (n.n)_u d0 + (n.n) e1 - 2 ((d0.n)_u n + (d0.n) dn1)
   for (int c = 0; c < 3; ++c) {
-    conv<2, 2, 1, 1, false, T, NT>(L.nn.v, L.nn.m, L.d0[c].v, L.d0[c].m, L.dt[c].v, L.dt[c].m, T(1), lane);
-    conv<2, 2, 1, 1, true, T, NT>(L.dn.v, L.dn.m, L.n[c].v, L.n[c].m, L.dt[c].v, L.dt[c].m, T(-2), lane);
+    conv_b<2, 2, 1, 1, false, T, NT>(L.nn.v, L.nn.m, L.d0[c].v, L.d0[c].m, L.dt[c].v, L.dt[c].m, T(1), lane);
+    conv_b<2, 2, 1, 1, true, T, NT>(L.dn.v, L.dn.m, L.n[c].v, L.n[c].m, L.dt[c].v, L.dt[c].m, T(-2), lane);
     if constexpr (IRR) {
-      conv<1, 1, 1, 1, false, T, NT>(L.nnu.v, L.nnu.m, L.d0[c].v, L.d0[c].m, L.dtu[c].v, L.dtu[c].m, T(1), lane);
-      conv<1, 1, 1, 1, true, T, NT>(L.dnu.v, L.dnu.m, L.n[c].v, L.n[c].m, L.dtu[c].v, L.dtu[c].m, T(-2), lane);
-      conv<1, 1, 1, 1, false, T, NT>(L.nnv.v, L.nnv.m, L.d0[c].v, L.d0[c].m, L.dtv[c].v, L.dtv[c].m, T(1), lane);
-      conv<1, 1, 1, 1, true, T, NT>(L.dnv.v, L.dnv.m, L.n[c].v, L.n[c].m, L.dtv[c].v, L.dtv[c].m, T(-2), lane);
+      conv_b<1, 1, 1, 1, false, T, NT>(L.nnu.v, L.nnu.m, L.d0[c].v, L.d0[c].m, L.dtu[c].v, L.dtu[c].m, T(1), lane);
+      conv_b<1, 1, 1, 1, true, T, NT>(L.dnu.v, L.dnu.m, L.n[c].v, L.n[c].m, L.dtu[c].v, L.dtu[c].m, T(-2), lane);
+      conv_b<1, 1, 1, 1, false, T, NT>(L.nnv.v, L.nnv.m, L.d0[c].v, L.d0[c].m, L.dtv[c].v, L.dtv[c].m, T(1), lane);
+      conv_b<1, 1, 1, 1, true, T, NT>(L.dnv.v, L.dnv.m, L.n[c].v, L.n[c].m, L.dtv[c].v, L.dtv[c].m, T(-2), lane);
     }
   }
   wave_sync();
@@ -203,8 +203,8 @@ __device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
       const T* xm[2] = {L.nn.m, L.dn.m};
       const T au[2] = {comp(G.e1, c), T(-2) * comp(G.dn1, c)};
       const T av[2] = {comp(G.e2, c), T(-2) * comp(G.dn2, c)};
-      combo<9, 2, true, T, NT>(xv, xm, au, L.dtu[c].v, L.dtu[c].m, lane);
-      combo<9, 2, true, T, NT>(xv, xm, av, L.dtv[c].v, L.dtv[c].m, lane);
+      combo_b<9, 2, true, T, NT>(xv, xm, au, L.dtu[c].v, L.dtu[c].m, lane);
+      combo_b<9, 2, true, T, NT>(xv, xm, av, L.dtv[c].v, L.dtv[c].m, lane);
     }
     th_dtu = max(max(conv_theta<1, 1, 1, 1>(th_nnu, th_lin), conv_theta<1, 1, 1, 1>(th_dnu, th_lin)),
                  th_nn + T(2) * eps) +
@@ -220,7 +220,7 @@ __device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     const T* al[3] = {ax, ay, az};
     const T* dv[3] = {L.dt[0].v, L.dt[1].v, L.dt[2].v};
     const T* dm[3] = {L.dt[0].m, L.dt[1].m, L.dt[2].m};
-    for (int c = 0; c < 3; ++c) combo<16, 3, false, T, NT>(dv, dm, al[c], L.cc[c].v, L.cc[c].m, lane);
+    for (int c = 0; c < 3; ++c) combo_b<16, 3, false, T, NT>(dv, dm, al[c], L.cc[c].v, L.cc[c].m, lane);
   }
   const T th_cc = th_dt + T(3) * eps;
   wave_sync();
@@ -228,11 +228,11 @@ __device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
   // ---- Pu = c.s, Pv = (s x f1).d~, Q = c.f1, t numerator Tn = (s x f1).f2
   for (int c = 0; c < 3; ++c) {
     if (c == 0) {
-      conv<3, 3, 1, 1, false, T, NT>(L.cc[c].v, L.cc[c].m, L.s[c].v, L.s[c].m, L.Pu.v, L.Pu.m, T(1), lane);
-      conv<3, 3, 1, 1, false, T, NT>(L.dt[c].v, L.dt[c].m, L.sf1[c].v, L.sf1[c].m, L.Pv.v, L.Pv.m, T(1), lane);
+      conv_b<3, 3, 1, 1, false, T, NT>(L.cc[c].v, L.cc[c].m, L.s[c].v, L.s[c].m, L.Pu.v, L.Pu.m, T(1), lane);
+      conv_b<3, 3, 1, 1, false, T, NT>(L.dt[c].v, L.dt[c].m, L.sf1[c].v, L.sf1[c].m, L.Pv.v, L.Pv.m, T(1), lane);
     } else {
-      conv<3, 3, 1, 1, true, T, NT>(L.cc[c].v, L.cc[c].m, L.s[c].v, L.s[c].m, L.Pu.v, L.Pu.m, T(1), lane);
-      conv<3, 3, 1, 1, true, T, NT>(L.dt[c].v, L.dt[c].m, L.sf1[c].v, L.sf1[c].m, L.Pv.v, L.Pv.m, T(1), lane);
+      conv_b<3, 3, 1, 1, true, T, NT>(L.cc[c].v, L.cc[c].m, L.s[c].v, L.s[c].m, L.Pu.v, L.Pu.m, T(1), lane);
+      conv_b<3, 3, 1, 1, true, T, NT>(L.dt[c].v, L.dt[c].m, L.sf1[c].v, L.sf1[c].m, L.Pv.v, L.Pv.m, T(1), lane);
     }
   }
   {
@@ -241,17 +241,17 @@ __device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     const T* sv[3] = {L.sf1[0].v, L.sf1[1].v, L.sf1[2].v};
     const T* sm[3] = {L.sf1[0].m, L.sf1[1].m, L.sf1[2].m};
     const T af1[3] = {G.f1.x, G.f1.y, G.f1.z}, af2[3] = {G.f2.x, G.f2.y, G.f2.z};
-    combo<16, 3, false, T, NT>(cv, cm, af1, L.Q.v, L.Q.m, lane);
-    combo<4, 3, false, T, NT>(sv, sm, af2, L.Tn.v, L.Tn.m, lane);
+    combo_b<16, 3, false, T, NT>(cv, cm, af1, L.Q.v, L.Q.m, lane);
+    combo_b<4, 3, false, T, NT>(sv, sm, af2, L.Tn.v, L.Tn.m, lane);
   }
   wave_sync();
-  elev11<3, 3, T, NT>(L.Q.v, L.Q.m, L.Qe.v, L.Qe.m, lane);
-  elev11<1, 1, T, NT>(L.Tn.v, L.Tn.m, L.Tn2.v, L.Tn2.m, lane);
+  elev11_b<3, 3, T, NT>(L.Q.v, L.Q.m, L.Qe.v, L.Qe.m, lane);
+  elev11_b<1, 1, T, NT>(L.Tn.v, L.Tn.m, L.Tn2.v, L.Tn2.m, lane);
   const T th_P = conv_theta<3, 3, 1, 1>(th_cc, th_lin) + T(3) * eps;
   const T th_Q = th_cc + T(3) * eps;
   const T th_Tn = th_sf1 + T(3) * eps;
   wave_sync();
-  elev11<2, 2, T, NT>(L.Tn2.v, L.Tn2.m, L.Tne.v, L.Tne.m, lane);
+  elev11_b<2, 2, T, NT>(L.Tn2.v, L.Tn2.m, L.Tne.v, L.Tne.m, lane);
   wave_sync();
 
   // ---- position bound (Sec. 4.2) and the sign of the ray parameter
@@ -284,37 +284,37 @@ __device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
       const T* dv[3] = {L.dt[0].v, L.dt[1].v, L.dt[2].v};
       const T* dm[3] = {L.dt[0].m, L.dt[1].m, L.dt[2].m};
       const T a12[3] = {n12.x, n12.y, n12.z};
-      combo<16, 3, false, T, NT>(dv, dm, a12, L.D0.v, L.D0.m, lane);
+      combo_b<16, 3, false, T, NT>(dv, dm, a12, L.D0.v, L.D0.m, lane);
       // X = e2 x d~
       const T xx[3] = {T(0), -e2.z, e2.y}, xy[3] = {e2.z, T(0), -e2.x}, xz[3] = {-e2.y, e2.x, T(0)};
-      combo<16, 3, false, T, NT>(dv, dm, xx, L.X[0].v, L.X[0].m, lane);
-      combo<16, 3, false, T, NT>(dv, dm, xy, L.X[1].v, L.X[1].m, lane);
-      combo<16, 3, false, T, NT>(dv, dm, xz, L.X[2].v, L.X[2].m, lane);
+      combo_b<16, 3, false, T, NT>(dv, dm, xx, L.X[0].v, L.X[0].m, lane);
+      combo_b<16, 3, false, T, NT>(dv, dm, xy, L.X[1].v, L.X[1].m, lane);
+      combo_b<16, 3, false, T, NT>(dv, dm, xz, L.X[2].v, L.X[2].m, lane);
       // Y = d~_v x d~
       for (int c = 0; c < 3; ++c) {
         const int a = (c + 1) % 3, b = (c + 2) % 3;
-        conv<2, 2, 3, 3, false, T, NT>(L.dtv[a].v, L.dtv[a].m, L.dt[b].v, L.dt[b].m, L.Y[c].v, L.Y[c].m, T(1), lane);
-        conv<2, 2, 3, 3, true, T, NT>(L.dtv[b].v, L.dtv[b].m, L.dt[a].v, L.dt[a].m, L.Y[c].v, L.Y[c].m, T(-1), lane);
+        conv_b<2, 2, 3, 3, false, T, NT>(L.dtv[a].v, L.dtv[a].m, L.dt[b].v, L.dt[b].m, L.Y[c].v, L.Y[c].m, T(1), lane);
+        conv_b<2, 2, 3, 3, true, T, NT>(L.dtv[b].v, L.dtv[b].m, L.dt[a].v, L.dt[a].m, L.Y[c].v, L.Y[c].m, T(-1), lane);
       }
-      conv<3, 3, 3, 3, false, T, NT>(L.Q.v, L.Q.m, L.Q.v, L.Q.m, L.Q2.v, L.Q2.m, T(1), lane);
-      conv<3, 3, 1, 1, false, T, NT>(L.Q.v, L.Q.m, L.Tn.v, L.Tn.m, L.QT.v, L.QT.m, T(1), lane);
-      conv<1, 1, 1, 1, false, T, NT>(L.Tn.v, L.Tn.m, L.Tn.v, L.Tn.m, L.T2.v, L.T2.m, T(1), lane);
+      conv_b<3, 3, 3, 3, false, T, NT>(L.Q.v, L.Q.m, L.Q.v, L.Q.m, L.Q2.v, L.Q2.m, T(1), lane);
+      conv_b<3, 3, 1, 1, false, T, NT>(L.Q.v, L.Q.m, L.Tn.v, L.Tn.m, L.QT.v, L.QT.m, T(1), lane);
+      conv_b<1, 1, 1, 1, false, T, NT>(L.Tn.v, L.Tn.m, L.Tn.v, L.Tn.m, L.T2.v, L.T2.m, T(1), lane);
       wave_sync();
       // D1 = d~_u . (e2 x d~) + e1 . (d~_v x d~),  D2 = d~_u . (d~_v x d~)
       for (int c = 0; c < 3; ++c) {
         if (c == 0) {
-          conv<2, 2, 3, 3, false, T, NT>(L.dtu[c].v, L.dtu[c].m, L.X[c].v, L.X[c].m, L.D1.v, L.D1.m, T(1), lane);
-          conv<2, 2, 5, 5, false, T, NT>(L.dtu[c].v, L.dtu[c].m, L.Y[c].v, L.Y[c].m, L.D2.v, L.D2.m, T(1), lane);
+          conv_b<2, 2, 3, 3, false, T, NT>(L.dtu[c].v, L.dtu[c].m, L.X[c].v, L.X[c].m, L.D1.v, L.D1.m, T(1), lane);
+          conv_b<2, 2, 5, 5, false, T, NT>(L.dtu[c].v, L.dtu[c].m, L.Y[c].v, L.Y[c].m, L.D2.v, L.D2.m, T(1), lane);
         } else {
-          conv<2, 2, 3, 3, true, T, NT>(L.dtu[c].v, L.dtu[c].m, L.X[c].v, L.X[c].m, L.D1.v, L.D1.m, T(1), lane);
-          conv<2, 2, 5, 5, true, T, NT>(L.dtu[c].v, L.dtu[c].m, L.Y[c].v, L.Y[c].m, L.D2.v, L.D2.m, T(1), lane);
+          conv_b<2, 2, 3, 3, true, T, NT>(L.dtu[c].v, L.dtu[c].m, L.X[c].v, L.X[c].m, L.D1.v, L.D1.m, T(1), lane);
+          conv_b<2, 2, 5, 5, true, T, NT>(L.dtu[c].v, L.dtu[c].m, L.Y[c].v, L.Y[c].m, L.D2.v, L.D2.m, T(1), lane);
         }
       }
       wave_sync();
       const T* yv[3] = {L.Y[0].v, L.Y[1].v, L.Y[2].v};
       const T* ym[3] = {L.Y[0].m, L.Y[1].m, L.Y[2].m};
       const T ae1[3] = {e1.x, e1.y, e1.z};
-      combo<36, 3, true, T, NT>(yv, ym, ae1, L.D1.v, L.D1.m, lane);
+      combo_b<36, 3, true, T, NT>(yv, ym, ae1, L.D1.v, L.D1.m, lane);
     }
     const T th_D0 = th_dt + T(4) * eps;
     const T th_X = th_dt + T(3) * eps;
@@ -325,17 +325,17 @@ __device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     const T th_QT = conv_theta<3, 3, 1, 1>(th_Q, th_Tn);
     const T th_T2 = conv_theta<1, 1, 1, 1>(th_Tn, th_Tn);
     wave_sync();
-    conv<6, 6, 3, 3, false, T, NT>(L.Q2.v, L.Q2.m, L.D0.v, L.D0.m, L.detM.v, L.detM.m, T(-1), lane);
-    conv<4, 4, 5, 5, true, T, NT>(L.QT.v, L.QT.m, L.D1.v, L.D1.m, L.detM.v, L.detM.m, T(-1), lane);
-    conv<2, 2, 7, 7, true, T, NT>(L.T2.v, L.T2.m, L.D2.v, L.D2.m, L.detM.v, L.detM.m, T(-1), lane);
-    conv<6, 6, 3, 3, false, T, NT>(L.Q2.v, L.Q2.m, L.Q.v, L.Q.m, L.Q3.v, L.Q3.m, T(1), lane);
+    conv_b<6, 6, 3, 3, false, T, NT>(L.Q2.v, L.Q2.m, L.D0.v, L.D0.m, L.detM.v, L.detM.m, T(-1), lane);
+    conv_b<4, 4, 5, 5, true, T, NT>(L.QT.v, L.QT.m, L.D1.v, L.D1.m, L.detM.v, L.detM.m, T(-1), lane);
+    conv_b<2, 2, 7, 7, true, T, NT>(L.T2.v, L.T2.m, L.D2.v, L.D2.m, L.detM.v, L.detM.m, T(-1), lane);
+    conv_b<6, 6, 3, 3, false, T, NT>(L.Q2.v, L.Q2.m, L.Q.v, L.Q.m, L.Q3.v, L.Q3.m, T(1), lane);
     const T th_detM = max(max(conv_theta<6, 6, 3, 3>(th_Q2, th_D0), conv_theta<4, 4, 5, 5>(th_QT, th_D1)),
                           conv_theta<2, 2, 7, 7>(th_T2, th_D2)) +
                       T(2) * eps;
     const T th_Q3 = conv_theta<6, 6, 3, 3>(th_Q2, th_Q);
     wave_sync();
-    elev11<9, 9, T, NT>(L.detM.v, L.detM.m, L.detMe.v, L.detMe.m, lane);
-    elev11<9, 9, T, NT>(L.Q3.v, L.Q3.m, L.Q3e.v, L.Q3e.m, lane);
+    elev11_b<9, 9, T, NT>(L.detM.v, L.detM.m, L.detMe.v, L.detMe.m, lane);
+    elev11_b<9, 9, T, NT>(L.Q3.v, L.Q3.m, L.Q3e.v, L.Q3e.m, lane);
     wave_sync();
     const RB<T> rb = ratio_bound<121, T, NT>(L.Q3e.v, L.Q3e.m, th_Q3 + T(2) * eps, L.detMe.v, L.detMe.m,
                                       th_detM + T(2) * eps, final, lane);

@@ -680,7 +680,7 @@ __device__ void subdiv_loop(const BuildArgs& a, int depth, Ev ev, int lane, Stag
 // Subdivision boxes carry the irradiance bound, whose denominator det M has
 // coefficients that cancel by two to five orders of magnitude; they are
 // evaluated in FP64, which on this GPU issues at the rate of unpacked FP32.
-__global__ void __launch_bounds__(64) k_subdiv(BuildArgs a, int depth) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_subdiv(BuildArgs a, int depth) {
   __shared__ LdsR<double> L;
   __shared__ Stage S;
   const int lane = threadIdx.x;
