@@ -69,25 +69,27 @@ __device__ __forceinline__ void conv(const T* __restrict__ av, const T* __restri
   }
 }
 
-// conv() with the LDS reads of each output batched: the terms go eight at a
-// time through clamped, in-range indices (the loads issued together, a
-// scheduling barrier, then the products), and a select leaves the partial
-// sums unchanged for the terms outside the output's support.  The sums are
+// conv() with the LDS reads of each output batched: the terms go CH at a
+// time (eight by default) through clamped, in-range indices (the loads issued
+// together, a scheduling barrier, then the products), and a select leaves the
+// partial sums unchanged for the terms outside the output's support.  The sums are
 // those of conv(), valid terms in (i, j) order, bit for bit; conv() instead
 // branches around each term and waits for each load, which leaves a box's
 // chain of small steps bound by LDS latency.  The batched form takes more
-// registers (up to 16 doubles of one chunk in flight), so it serves the
-// single-reflection chain, whose kernels keep their occupancy with it.
-template <int A1, int A2, int B1, int B2, bool ACC, class T, int NT = BBC_WAVE>
+// registers (up to 2 CH doubles of one chunk in flight): the reflection and
+// refraction boxes gain from it (subdivision 14 % and 25 % faster), the
+// two-reflection box, whose kernels then spill, keeps conv() (8 % slower
+// batched).
+template <int A1, int A2, int B1, int B2, bool ACC, class T, int NT = BBC_WAVE, int CH = 8>
 __device__ __forceinline__ void conv_b(const T* __restrict__ av, const T* __restrict__ am, const T* __restrict__ bv,
                                        const T* __restrict__ bm, T* __restrict__ cv, T* __restrict__ cm, T sgn,
                                        int lane) {
   if constexpr ((A1 + 1) * (A2 + 1) > (B1 + 1) * (B2 + 1)) {
-    conv_b<B1, B2, A1, A2, ACC, T, NT>(bv, bm, av, am, cv, cm, sgn, lane);
+    conv_b<B1, B2, A1, A2, ACC, T, NT, CH>(bv, bm, av, am, cv, cm, sgn, lane);
   } else {
     constexpr int C2 = A2 + B2;
     constexpr int N = (A1 + B1 + 1) * (C2 + 1);
-    constexpr int NA = (A1 + 1) * (A2 + 1), CH = 8;
+    constexpr int NA = (A1 + 1) * (A2 + 1);
     for (int o = lane; o < N; o += NT) {
       const int k = o / (C2 + 1), l = o - k * (C2 + 1);
       T s = 0, sm = 0;

@@ -82,11 +82,11 @@ __device__ __forceinline__ BoxOut eval_box_ra(const TupleGeom<T>& G, T u0, T u1,
   const TP<T> nn = at(RALay::NN), dn = at(RALay::DN), sf1 = at(RALay::SF1), tn = at(RALay::TN);
   for (int c = 0; c < 3; ++c) {
     if (c == 0) {
-      cv4m<1, 1, 0, 0, 1, 1, 0, 0, false, NT>(slice(nv, c, 4), slice(nv, c, 4), nn, T(1), lane);
-      cv4m<1, 1, 1, 1, 1, 1, 0, 0, false, NT>(slice(d0, c, 16), slice(nv, c, 4), dn, T(1), lane);
+      cv4m_b<1, 1, 0, 0, 1, 1, 0, 0, false, NT>(slice(nv, c, 4), slice(nv, c, 4), nn, T(1), lane);
+      cv4m_b<1, 1, 1, 1, 1, 1, 0, 0, false, NT>(slice(d0, c, 16), slice(nv, c, 4), dn, T(1), lane);
     } else {
-      cv4m<1, 1, 0, 0, 1, 1, 0, 0, true, NT>(slice(nv, c, 4), slice(nv, c, 4), nn, T(1), lane);
-      cv4m<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(slice(d0, c, 16), slice(nv, c, 4), dn, T(1), lane);
+      cv4m_b<1, 1, 0, 0, 1, 1, 0, 0, true, NT>(slice(nv, c, 4), slice(nv, c, 4), nn, T(1), lane);
+      cv4m_b<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(slice(d0, c, 16), slice(nv, c, 4), dn, T(1), lane);
     }
   }
   for (int o = lane; o < 4; o += NT) {  // s x f1 and (s x f1).f2
@@ -110,10 +110,10 @@ __device__ __forceinline__ BoxOut eval_box_ra(const TupleGeom<T>& G, T u0, T u1,
   // ---- d~ = (n.n) d0 - 2 (d0.n) n, c = d~ x f2, and Tn raised to Q's degree
   const TP<T> dt = at(RALay::DT), cc = at(RALay::CC), tne = at(RALay::TNE);
   for (int c = 0; c < 3; ++c) {
-    cv4m<2, 2, 0, 0, 1, 1, 1, 1, false, NT>(nn, slice(d0, c, 16), slice(dt, c, 64), T(1), lane);
-    cv4m<2, 2, 1, 1, 1, 1, 0, 0, true, NT>(dn, slice(nv, c, 4), slice(dt, c, 64), T(-2), lane);
+    cv4m_b<2, 2, 0, 0, 1, 1, 1, 1, false, NT>(nn, slice(d0, c, 16), slice(dt, c, 64), T(1), lane);
+    cv4m_b<2, 2, 1, 1, 1, 1, 0, 0, true, NT>(dn, slice(nv, c, 4), slice(dt, c, 64), T(-2), lane);
   }
-  elev4m<1, 1, 0, 0, 2, 2, 1, 1, NT>(tn, tne, lane);
+  elev4m_b<1, 1, 0, 0, 2, 2, 1, 1, NT>(tn, tne, lane);
   const T th_dt = th_cv4<2, 2, 1, 1, 1, 1, 0, 0>(th_nn, th_lin, 2);
   const T th_tne = th_elev4<2, 2, 1, 1>(th_tn);
   wave_sync();
@@ -134,11 +134,11 @@ __device__ __forceinline__ BoxOut eval_box_ra(const TupleGeom<T>& G, T u0, T u1,
   const TP<T> pu = at(RALay::PU), pv = at(RALay::PV), q = at(RALay::Q);
   for (int c = 0; c < 3; ++c) {
     if (c == 0) {
-      cv4m<3, 3, 1, 1, 1, 1, 0, 0, false, NT>(slice(cc, c, 64), slice(sv, c, 4), pu, T(1), lane);
-      cv4m<1, 1, 0, 0, 3, 3, 1, 1, false, NT>(slice(sf1, c, 4), slice(dt, c, 64), pv, T(1), lane);
+      cv4m_b<3, 3, 1, 1, 1, 1, 0, 0, false, NT>(slice(cc, c, 64), slice(sv, c, 4), pu, T(1), lane);
+      cv4m_b<1, 1, 0, 0, 3, 3, 1, 1, false, NT>(slice(sf1, c, 4), slice(dt, c, 64), pv, T(1), lane);
     } else {
-      cv4m<3, 3, 1, 1, 1, 1, 0, 0, true, NT>(slice(cc, c, 64), slice(sv, c, 4), pu, T(1), lane);
-      cv4m<1, 1, 0, 0, 3, 3, 1, 1, true, NT>(slice(sf1, c, 4), slice(dt, c, 64), pv, T(1), lane);
+      cv4m_b<3, 3, 1, 1, 1, 1, 0, 0, true, NT>(slice(cc, c, 64), slice(sv, c, 4), pu, T(1), lane);
+      cv4m_b<1, 1, 0, 0, 3, 3, 1, 1, true, NT>(slice(sf1, c, 4), slice(dt, c, 64), pv, T(1), lane);
     }
   }
   for (int o = lane; o < 64; o += NT) {
@@ -149,7 +149,7 @@ __device__ __forceinline__ BoxOut eval_box_ra(const TupleGeom<T>& G, T u0, T u1,
   const T th_q = th_cc + T(4) * eps;
   wave_sync();
   const TP<T> qe = at(RALay::QE);
-  elev4m<3, 3, 1, 1, 1, 1, 0, 0, NT>(q, qe, lane);
+  elev4m_b<3, 3, 1, 1, 1, 1, 0, 0, NT>(q, qe, lane);
   const T th_qe = th_elev4<1, 1, 0, 0>(th_q);
   wave_sync();
   // ---- position bound (Sec. 4.2) over the box and the whole light
@@ -215,9 +215,9 @@ __device__ __forceinline__ BoxOut eval_box_ra(const TupleGeom<T>& G, T u0, T u1,
     }
     for (int c = 0; c < 3; ++c) {
       if (c == 0)
-        cv4m<1, 1, 1, 1, 1, 1, 1, 1, false, NT>(slice(d0, c, 16), slice(d0, c, 16), hh, T(1), lane);
+        cv4m_b<1, 1, 1, 1, 1, 1, 1, 1, false, NT>(slice(d0, c, 16), slice(d0, c, 16), hh, T(1), lane);
       else
-        cv4m<1, 1, 1, 1, 1, 1, 1, 1, true, NT>(slice(d0, c, 16), slice(d0, c, 16), hh, T(1), lane);
+        cv4m_b<1, 1, 1, 1, 1, 1, 1, 1, true, NT>(slice(d0, c, 16), slice(d0, c, 16), hh, T(1), lane);
     }
     const T th_g = th_lin + T(8) * eps;  // the unit normal carries a few roundings of its own
     const T th_h = th_cv4<1, 1, 1, 1, 1, 1, 1, 1>(th_lin, th_lin, 3);
@@ -228,10 +228,10 @@ __device__ __forceinline__ BoxOut eval_box_ra(const TupleGeom<T>& G, T u0, T u1,
     range4m<2, 2, 2, 2, T, NT>(hh, th_h, &hlo, &hhi, lane);
     // d~_u = (n.n)_u d0 + (n.n) e1 - 2 (d0.n)_u n - 2 (d0.n) dn1   (2,2,1,1)
     for (int c = 0; c < 3; ++c) {
-      cv4m<1, 1, 0, 0, 1, 1, 1, 1, false, NT>(nnu, slice(d0, c, 16), slice(dtu, c, 36), T(1), lane);
-      cv4m<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(dnu, slice(nv, c, 4), slice(dtu, c, 36), T(-2), lane);
-      cv4m<1, 1, 0, 0, 1, 1, 1, 1, false, NT>(nnv, slice(d0, c, 16), slice(dtv, c, 36), T(1), lane);
-      cv4m<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(dnv, slice(nv, c, 4), slice(dtv, c, 36), T(-2), lane);
+      cv4m_b<1, 1, 0, 0, 1, 1, 1, 1, false, NT>(nnu, slice(d0, c, 16), slice(dtu, c, 36), T(1), lane);
+      cv4m_b<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(dnu, slice(nv, c, 4), slice(dtu, c, 36), T(-2), lane);
+      cv4m_b<1, 1, 0, 0, 1, 1, 1, 1, false, NT>(nnv, slice(d0, c, 16), slice(dtv, c, 36), T(1), lane);
+      cv4m_b<1, 1, 1, 1, 1, 1, 0, 0, true, NT>(dnv, slice(nv, c, 4), slice(dtv, c, 36), T(-2), lane);
       // the same lane owns each coefficient in the products above and here
       for (int o = lane; o < 36; o += NT) {
         const int ij = o >> 2;  // (n.n) is constant along z1, z2 (replicated in scaled form)
@@ -274,15 +274,15 @@ __device__ __forceinline__ BoxOut eval_box_ra(const TupleGeom<T>& G, T u0, T u1,
     }
     for (int c = 0; c < 3; ++c) {
       if (c == 0) {
-        cv4m<2, 2, 1, 1, 1, 1, 0, 0, false, NT>(slice(ccu, c, 36), slice(sv, c, 4), puu, T(1), lane);
-        cv4m<2, 2, 1, 1, 1, 1, 0, 0, false, NT>(slice(ccv, c, 36), slice(sv, c, 4), puv, T(1), lane);
-        cv4m<1, 1, 0, 0, 2, 2, 1, 1, false, NT>(slice(sf1, c, 4), slice(dtu, c, 36), pvu, T(1), lane);
-        cv4m<1, 1, 0, 0, 2, 2, 1, 1, false, NT>(slice(sf1, c, 4), slice(dtv, c, 36), pvv, T(1), lane);
+        cv4m_b<2, 2, 1, 1, 1, 1, 0, 0, false, NT>(slice(ccu, c, 36), slice(sv, c, 4), puu, T(1), lane);
+        cv4m_b<2, 2, 1, 1, 1, 1, 0, 0, false, NT>(slice(ccv, c, 36), slice(sv, c, 4), puv, T(1), lane);
+        cv4m_b<1, 1, 0, 0, 2, 2, 1, 1, false, NT>(slice(sf1, c, 4), slice(dtu, c, 36), pvu, T(1), lane);
+        cv4m_b<1, 1, 0, 0, 2, 2, 1, 1, false, NT>(slice(sf1, c, 4), slice(dtv, c, 36), pvv, T(1), lane);
       } else {
-        cv4m<2, 2, 1, 1, 1, 1, 0, 0, true, NT>(slice(ccu, c, 36), slice(sv, c, 4), puu, T(1), lane);
-        cv4m<2, 2, 1, 1, 1, 1, 0, 0, true, NT>(slice(ccv, c, 36), slice(sv, c, 4), puv, T(1), lane);
-        cv4m<1, 1, 0, 0, 2, 2, 1, 1, true, NT>(slice(sf1, c, 4), slice(dtu, c, 36), pvu, T(1), lane);
-        cv4m<1, 1, 0, 0, 2, 2, 1, 1, true, NT>(slice(sf1, c, 4), slice(dtv, c, 36), pvv, T(1), lane);
+        cv4m_b<2, 2, 1, 1, 1, 1, 0, 0, true, NT>(slice(ccu, c, 36), slice(sv, c, 4), puu, T(1), lane);
+        cv4m_b<2, 2, 1, 1, 1, 1, 0, 0, true, NT>(slice(ccv, c, 36), slice(sv, c, 4), puv, T(1), lane);
+        cv4m_b<1, 1, 0, 0, 2, 2, 1, 1, true, NT>(slice(sf1, c, 4), slice(dtu, c, 36), pvu, T(1), lane);
+        cv4m_b<1, 1, 0, 0, 2, 2, 1, 1, true, NT>(slice(sf1, c, 4), slice(dtv, c, 36), pvv, T(1), lane);
       }
     }
     {
@@ -324,29 +324,29 @@ __device__ __forceinline__ BoxOut eval_box_ra(const TupleGeom<T>& G, T u0, T u1,
     wave_sync();
     // A = Pu_u Pv_v - Pv_u Pu_v, Bm = Q_u Pv_v - Pv_u Q_v, Cm = Q_u Pu_v - Pu_u Q_v, Q^2
     const TP<T> am = at(RALay::AM), bm = at(RALay::BM), cm = at(RALay::CM), q2 = at(RALay::Q2);
-    cv4m<3, 3, 1, 1, 3, 3, 1, 1, false, NT>(puu, pvv, am, T(1), lane);
-    cv4m<3, 3, 1, 1, 3, 3, 1, 1, true, NT>(pvu, puv, am, T(-1), lane);
-    cv4m<2, 2, 1, 1, 3, 3, 1, 1, false, NT>(qu, pvv, bm, T(1), lane);
-    cv4m<3, 3, 1, 1, 2, 2, 1, 1, true, NT>(pvu, qv, bm, T(-1), lane);
-    cv4m<2, 2, 1, 1, 3, 3, 1, 1, false, NT>(qu, puv, cm, T(1), lane);
-    cv4m<3, 3, 1, 1, 2, 2, 1, 1, true, NT>(puu, qv, cm, T(-1), lane);
-    cv4m<3, 3, 1, 1, 3, 3, 1, 1, false, NT>(q, q, q2, T(1), lane);
+    cv4m_b<3, 3, 1, 1, 3, 3, 1, 1, false, NT>(puu, pvv, am, T(1), lane);
+    cv4m_b<3, 3, 1, 1, 3, 3, 1, 1, true, NT>(pvu, puv, am, T(-1), lane);
+    cv4m_b<2, 2, 1, 1, 3, 3, 1, 1, false, NT>(qu, pvv, bm, T(1), lane);
+    cv4m_b<3, 3, 1, 1, 2, 2, 1, 1, true, NT>(pvu, qv, bm, T(-1), lane);
+    cv4m_b<2, 2, 1, 1, 3, 3, 1, 1, false, NT>(qu, puv, cm, T(1), lane);
+    cv4m_b<3, 3, 1, 1, 2, 2, 1, 1, true, NT>(puu, qv, cm, T(-1), lane);
+    cv4m_b<3, 3, 1, 1, 3, 3, 1, 1, false, NT>(q, q, q2, T(1), lane);
     const T th_a = th_cv4<3, 3, 1, 1, 3, 3, 1, 1>(th_pd, th_pd, 2);
     const T th_bc = max(th_cv4<2, 2, 1, 1, 3, 3, 1, 1>(th_qd, th_pd, 2), th_cv4<3, 3, 1, 1, 2, 2, 1, 1>(th_pd, th_qd, 2));
     const T th_q2 = th_cv4<3, 3, 1, 1, 3, 3, 1, 1>(th_q, th_q, 1);
     wave_sync();
     // det M = Q A - Pu Bm + Pv Cm (9,9,3,3); Q^3 (9,9,3,3)
     const TP<T> detm = at(RALay::DETM), q3 = at(RALay::Q3), q3e = at(RALay::Q3E), detme = at(RALay::DETME);
-    cv4m<3, 3, 1, 1, 6, 6, 2, 2, false, NT>(q, am, detm, T(1), lane);
-    cv4m<4, 4, 1, 1, 5, 5, 2, 2, true, NT>(pu, bm, detm, T(-1), lane);
-    cv4m<4, 4, 1, 1, 5, 5, 2, 2, true, NT>(pv, cm, detm, T(1), lane);
-    cv4m<6, 6, 2, 2, 3, 3, 1, 1, false, NT>(q2, q, q3, T(1), lane);
+    cv4m_b<3, 3, 1, 1, 6, 6, 2, 2, false, NT>(q, am, detm, T(1), lane);
+    cv4m_b<4, 4, 1, 1, 5, 5, 2, 2, true, NT>(pu, bm, detm, T(-1), lane);
+    cv4m_b<4, 4, 1, 1, 5, 5, 2, 2, true, NT>(pv, cm, detm, T(1), lane);
+    cv4m_b<6, 6, 2, 2, 3, 3, 1, 1, false, NT>(q2, q, q3, T(1), lane);
     const T th_detm = max(th_cv4<3, 3, 1, 1, 6, 6, 2, 2>(th_q, th_a, 3), th_cv4<4, 4, 1, 1, 5, 5, 2, 2>(th_p, th_bc, 3));
     const T th_q3 = th_cv4<6, 6, 2, 2, 3, 3, 1, 1>(th_q2, th_q, 1);
     wave_sync();
     // det M's elevation overwrites the dead factors (GG .. CM)
-    elev4m<9, 9, 3, 3, 1, 1, 0, 0, NT>(detm, detme, lane);
-    elev4m<9, 9, 3, 3, 1, 1, 0, 0, NT>(q3, q3e, lane);
+    elev4m_b<9, 9, 3, 3, 1, 1, 0, 0, NT>(detm, detme, lane);
+    elev4m_b<9, 9, 3, 3, 1, 1, 0, 0, NT>(q3, q3e, lane);
     const T th_detme = th_elev4<1, 1, 0, 0>(th_detm);
     const T th_q3e = th_elev4<1, 1, 0, 0>(th_q3);
     wave_sync();
