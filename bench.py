@@ -82,15 +82,15 @@ COUNTERS = {
     # of profiles/subdiv_sphere131072_hbm_sq_counters.md averaged)
     "k_subdiv": dict(
         sources=['paper_2504_19163_amd/csrc/build.hip', 'paper_2504_19163_amd/csrc/box_r.hpp', 'paper_2504_19163_amd/csrc/bern_dev.hpp', 'paper_2504_19163_amd/csrc/dev_common.hpp', 'paper_2504_19163_amd/csrc/geom_dev.hpp'],
-        sha256="39f9d318bce3459945686e5b90b26138d4862741f563a1c2a59f1d793e1ae2f4",
-        fetch_kib=22873.2, write_kib=2829.9, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
+        sha256="c72dad188e5e2ba028311c1a4797d461e426ee37e3ba610caa0e6428424e33fe",
+        fetch_kib=23154.5, write_kib=2837.4, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
     # the pooled Newton kernels of the serving stream, mean per launch over the
-    # run's 393 launches of all three chains
+    # run's 394 (FETCH_SIZE) and 396 (WRITE_SIZE) launches of all three chains
     # (profiles/serving_stream_three_scenes_newton_hbm_counters.md)
     "newton_stream": dict(
         sources=['paper_2504_19163_amd/csrc/query.hip', 'paper_2504_19163_amd/csrc/path_dev.hpp', 'paper_2504_19163_amd/csrc/geom_dev.hpp', 'paper_2504_19163_amd/csrc/dev_common.hpp', 'paper_2504_19163_amd/csrc/internal.hpp'],
-        sha256="126b5bc56cc91449a6a0e3949fb3e3345e7192e708cfd911ffd4dbc173d3018a",
-        fetch_kib=126852.7, write_kib=103522.2, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
+        sha256="b03033761f9a12a26e609529616106ab4630fbf1691613836bde0dbe1789f1da",
+        fetch_kib=134034.8, write_kib=87707.4, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
 }
 
 
