@@ -817,7 +817,7 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
 // in the same order as from the one-wave-per-point kernels above.  The count
 // pass draws the Bernoulli decisions (one Philox evaluation per candidate) and
 // keeps them as bits; the fill pass reads the bits instead of drawing again.
-constexpr int kSelLanes = 16;
+constexpr int kSelLanes = 16, kSelAhead = 4;
 template <bool FILL>
 __global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* sel) {
   constexpr int GL = kSelLanes, NG = BBC_WAVE / GL;
@@ -835,14 +835,14 @@ __global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* s
     const float Pu = fminf(pr.W, float(nU)) / float(nU);
     uint16_t* bits = s.bits + size_t(valid ? i : 0) * s.bit_stride;
     uint32_t o = FILL && valid ? s.off[i] : 0u, c = 0;
-    for (uint32_t j0 = 0; j0 < nU; j0 += GL) {  // the group's lanes run the same trip count
-      const uint32_t j = j0 + gl;
-      bool take = false;
-      float P = 0.f;
-      uint32_t T = 0;
-      if constexpr (FILL) {
+    // the group's lanes run the same trip count
+    if constexpr (FILL) {
+      for (uint32_t j0 = 0; j0 < nU; j0 += GL) {
+        const uint32_t j = j0 + gl;
         const uint32_t word = bits[j0 / GL];
-        take = j < nU && ((word >> gl) & 1u) != 0u;
+        const bool take = j < nU && ((word >> gl) & 1u) != 0u;
+        float P = 0.f;
+        uint32_t T = 0;
         if (take) {
           T = a.gt[cl.at(j)];
           P = uniform ? Pu : select_prob(a.ge[cl.at(j)], gamma, exhaustive);
@@ -855,15 +855,35 @@ __global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* s
           s.pair_p[o + rank] = P;
         }
         o += __popc(m);
-      } else {
-        if (j < nU) {
-          T = a.gt[cl.at(j)];
-          P = uniform ? Pu : select_prob(a.ge[cl.at(j)], gamma, exhaustive);
-          take = P > 0.f && selection_uniform(pr.seed, pr.key, tuple_key(a, T)) < P;
+      }
+    } else {
+      // kSelAhead chunks per trip: their grid entries (tuple and bound, then
+      // the tuple's key) are read together before the draws, through indices
+      // clamped to the list (reads past its end are not used)
+      for (uint32_t j0 = 0; j0 < nU; j0 += GL * kSelAhead) {
+        const uint32_t j = j0 + gl;
+        uint32_t Tq[kSelAhead], Kq[kSelAhead];
+        float Eq[kSelAhead];
+#pragma unroll
+        for (int u = 0; u < kSelAhead; ++u) {
+          const uint32_t x = cl.at(min(j + uint32_t(u * GL), nU - 1u));
+          Tq[u] = a.gt[x];
+          Eq[u] = uniform ? 0.f : a.ge[x];
         }
-        const uint32_t m = uint32_t(__ballot(take) >> (GL * g)) & ((1u << GL) - 1u);
-        if (gl == 0 && j0 < nU) bits[j0 / GL] = uint16_t(m);
-        c += take ? 1u : 0u;
+#pragma unroll
+        for (int u = 0; u < kSelAhead; ++u) Kq[u] = tuple_key(a, Tq[u]);
+#pragma unroll
+        for (int u = 0; u < kSelAhead; ++u) {
+          const uint32_t ju = j + uint32_t(u * GL), j0u = j0 + uint32_t(u * GL);
+          bool take = false;
+          if (ju < nU) {
+            const float P = uniform ? Pu : select_prob(Eq[u], gamma, exhaustive);
+            take = P > 0.f && selection_uniform(pr.seed, pr.key, Kq[u]) < P;
+          }
+          const uint32_t m = uint32_t(__ballot(take) >> (GL * g)) & ((1u << GL) - 1u);
+          if (gl == 0 && j0u < nU) bits[j0u / GL] = uint16_t(m);
+          c += take ? 1u : 0u;
+        }
       }
     }
     if constexpr (!FILL) {
