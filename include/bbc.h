@@ -327,6 +327,17 @@ bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points
  *  BBC_TUNE_RR_OUTLINED        two-reflection subdivision: 1 = run the box evaluation as a
  *                              called (not inlined) function; 0 (default) inlines it (about
  *                              4 % faster).  The same arithmetic: builds are identical
+ *  BBC_TUNE_SUBDIV_SPLIT       single-reflection subdivision (point lights): 1 (default) = a
+ *                              box that is split writes its four children's polynomials
+ *                              (Pu, Pv, Q, Tn, det M, Q^3 and the solid-angle factors, with
+ *                              their magnitudes and error factors), split at the midpoint in
+ *                              scaled Bernstein form (Sec. 4.1), to a record each, and a child
+ *                              is bounded from its record instead of from its corners (4.5 KB
+ *                              of device memory per record, 65536 records per depth parity;
+ *                              children beyond them are evaluated from their corners); n > 1
+ *                              = the same with n records (rounded down to a multiple of 4, at
+ *                              least 4; up to 2^20); 0 = every box from its corners.  The same
+ *                              trees; bounds agree to rounding and remain rounded outward
  * Applies to later calls on the handle; EINVAL for an unknown knob or value. */
 #define BBC_TUNE_QUERY_WAVES 1
 #define BBC_TUNE_QUERY_GRID 2
@@ -340,6 +351,7 @@ bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points
 #define BBC_TUNE_RR_OUTLINED 10
 #define BBC_TUNE_NEWTON_GRID_PER_CU 11
 #define BBC_TUNE_BUILD_GRAPH 12
+#define BBC_TUNE_SUBDIV_SPLIT 13
 bbc_status bbc_set_tuning(bbc_bounds* b, int32_t knob, int64_t value);
 bbc_status bbc_get_tuning(const bbc_bounds* b, int32_t knob, int64_t* value);
 

@@ -32,7 +32,7 @@ EXPORTS = [
 SERVER_PAUSED, SERVER_GRAPH = 1, 2
 TUNE_QUERY_WAVES, TUNE_QUERY_GRID, TUNE_BUILD_GRID_PER_CU, TUNE_QUERY_TILE, TUNE_TIMING = 1, 2, 3, 4, 5
 TUNE_NEWTON_STEPS, TUNE_NEWTON_RESULTS, TUNE_STAGED_PAIRS, TUNE_GRAPH, TUNE_RR_OUTLINED = 6, 7, 8, 9, 10
-TUNE_NEWTON_GRID_PER_CU, TUNE_BUILD_GRAPH = 11, 12
+TUNE_NEWTON_GRID_PER_CU, TUNE_BUILD_GRAPH, TUNE_SUBDIV_SPLIT = 11, 12, 13
 
 
 class BBCError(RuntimeError):
@@ -477,7 +477,8 @@ def apply_tuning(bounds, workload_key, path=TUNING_FILE):
     entry = table.get(dev, {}).get(workload_key, {})
     knobs = {"query_waves": TUNE_QUERY_WAVES, "query_tile": TUNE_QUERY_TILE, "query_grid": TUNE_QUERY_GRID,
              "build_grid_per_cu": TUNE_BUILD_GRID_PER_CU, "newton_steps": TUNE_NEWTON_STEPS, "graph": TUNE_GRAPH,
-             "newton_grid_per_cu": TUNE_NEWTON_GRID_PER_CU, "build_graph": TUNE_BUILD_GRAPH}
+             "newton_grid_per_cu": TUNE_NEWTON_GRID_PER_CU, "build_graph": TUNE_BUILD_GRAPH,
+             "subdiv_split": TUNE_SUBDIV_SPLIT}
     for k, knob in knobs.items():
         if k in entry:
             bounds.set_tuning(knob, entry[k])

@@ -69,9 +69,11 @@ static void release_all(Bounds* b) {
                    &b->q[1], &b->fq, &b->lt, &b->lc, &b->lu, &b->le, &b->gl_t, &b->gl_c, &b->gl_u, &b->gl_e, &b->st, &b->sc, &b->su, &b->se, &b->tcount,
                    &b->toff, &b->tcur, &b->lrect, &b->lcoarse, &b->ccount, &b->coff, &b->gt, &b->ge,
                    &b->scan_tmp, &b->trec, &b->pos2, &b->nrm2, &b->box2, &b->rowcount, &b->rowoff, &b->tid,
-                   &b->qw_buf, &b->max_cell_dev, &b->qcounters, &b->cflag, &b->cpos, &b->cE, &b->red_tab};
+                   &b->qw_buf, &b->max_cell_dev, &b->qcounters, &b->cflag, &b->cpos, &b->cE, &b->red_tab,
+                   &b->srec[0], &b->srec[1]};
   for (DevBuf* d : all) release(*d);
   b->red_ready = false;
+  b->srec_cap = 0;
   b->device_bytes = 0;
 }
 
@@ -808,6 +810,10 @@ bbc_status bbc_set_tuning(bbc_bounds* h, int32_t knob, int64_t value) {
       if (value != 0 && value != 1) return invalid("build graph must be 0 or 1");
       b->tune.build_graph = int(value);
       return BBC_OK;
+    case BBC_TUNE_SUBDIV_SPLIT:
+      if (value < 0 || value > (int64_t(1) << 20)) return invalid("subdivision split must be in [0, 2^20]");
+      b->tune.subdiv_split = int(value);
+      return BBC_OK;
     default:
       return invalid("unknown tuning knob");
   }
@@ -829,6 +835,7 @@ bbc_status bbc_get_tuning(const bbc_bounds* h, int32_t knob, int64_t* value) {
     case BBC_TUNE_RR_OUTLINED: *value = b->tune.rr_outlined; return BBC_OK;
     case BBC_TUNE_NEWTON_GRID_PER_CU: *value = b->tune.newton_grid_per_cu; return BBC_OK;
     case BBC_TUNE_BUILD_GRAPH: *value = b->tune.build_graph; return BBC_OK;
+    case BBC_TUNE_SUBDIV_SPLIT: *value = b->tune.subdiv_split; return BBC_OK;
     default: return invalid("unknown tuning knob");
   }
 }

@@ -34,23 +34,32 @@ struct LdsRPos {
   Ten<T, 25> Pu, Pv, Qe;
   Ten<T, 16> Q, Tne;
 };
-// LDS of the position and irradiance bound (subdivision).  The position
-// tensors that the irradiance part no longer reads share their space with the
-// cofactor parts of det M, and those with the elevated det M and Q^3: 11.3 KB
-// instead of 18.6 KB.
+// LDS of the position and irradiance bound (subdivision).  The polynomials a
+// box's bounds are read from (Pu, Pv, Q, Tn, det M, Q^3, g, h) come first, in
+// the order of a child record in HBM (see split_box_r); the position tensors
+// that the irradiance part no longer reads share their space with the
+// cofactor parts of det M, and those with the elevated det M and Q^3 and with
+// the children's half-split tensors.
 template <class T>
 struct LdsR {
+  struct {  // the box's record
+    Ten<T, 25> Pu, Pv;
+    Ten<T, 16> Q;
+    Ten<T, 4> Tn;
+    Ten<T, 100> detM, Q3;
+    Ten<T, 4> g;
+    Ten<T, 9> h;
+  };
   // live through the whole evaluation
-  Ten<T, 16> dt[3], Q;
-  Ten<T, 4> Tn, g, nnu, nnv, dnu, dnv;
-  Ten<T, 9> h;
+  Ten<T, 16> dt[3];
+  Ten<T, 4> nnu, nnv, dnu, dnv;
   Ten<T, 9> dtu[3], dtv[3];
   union {
     struct {  // position bound
       Ten<T, 4> n[3], d0[3], s[3], sf1[3];
       Ten<T, 9> nn, dn, Tn2;
       Ten<T, 16> cc[3];
-      Ten<T, 25> Pu, Pv, Qe;
+      Ten<T, 25> Qe;
       Ten<T, 16> Tne;
     };
     struct {  // irradiance: the parts of det M
@@ -64,8 +73,44 @@ struct LdsR {
     struct {  // irradiance: the ratio's operands at degree (10, 10)
       Ten<T, 121> detMe, Q3e;
     };
+    T half[1132];  // the children's tensors split along u (split_box_r)
   };
-  Ten<T, 100> detM, Q3;
+};
+
+// LDS of a box bounded from its record (eval_box_r_rec, split_box_r): the
+// record block as in LdsR, then the elevated operands, or the children's
+// half-split tensors.
+template <class T>
+struct LdsRRec {
+  struct {
+    Ten<T, 25> Pu, Pv;
+    Ten<T, 16> Q;
+    Ten<T, 4> Tn;
+    Ten<T, 100> detM, Q3;
+    Ten<T, 4> g;
+    Ten<T, 9> h;
+  };
+  union {
+    struct {
+      Ten<T, 25> Qe;
+      Ten<T, 9> Tn2;
+      Ten<T, 16> Tne;
+    };
+    struct {
+      Ten<T, 121> detMe, Q3e;
+    };
+    T half[1132];
+  };
+};
+
+// A box's record: the scaled Bernstein coefficients and magnitudes of Pu, Pv,
+// Q, Tn, det M, Q^3, g and h in the order of LdsR's first block, then their
+// error factors and the tuple's constant factor; kRecR doubles per box.
+constexpr int kRecCoef = 2 * (25 + 25 + 16 + 4 + 100 + 100 + 4 + 9), kRecR = 576;
+template <class T>
+struct BoxTheta {
+  T P, Q, Tn, detM, Q3, g, h;  // error factors
+  T k;                          // the tuple's constant factor I0 a1 / ak
 };
 
 struct BoxOut {
@@ -89,12 +134,82 @@ __device__ __forceinline__ float out_hi(T x) {
   return f;
 }
 
+// Position bound of a box from Tn, Q, Pu and Pv in L with error factors
+// th_Tn, th_Q, th_P (Sec. 4.2): Q and Tn raised to the degrees of Pu and Q, the
+// ratio bounds of t = Tn/Q, u_k = Pu/Q and v_k = Pv/Q, the clip to the
+// receiver.  False when the box is done (outside its triangle, culled, or to be
+// redone at higher precision: out.status says which).
+template <class T, class Lds, int NT>
+__device__ bool pos_bound_r(Lds& L, T th_P, T th_Q, T th_Tn, bool final, bool outside, BoxOut& out, int lane) {
+  const T eps = Eps<T>::u;
+  elev11_b<3, 3, T, NT>(L.Q.v, L.Q.m, L.Qe.v, L.Qe.m, lane);
+  elev11_b<1, 1, T, NT>(L.Tn.v, L.Tn.m, L.Tn2.v, L.Tn2.m, lane);
+  wave_sync();
+  elev11_b<2, 2, T, NT>(L.Tn2.v, L.Tn2.m, L.Tne.v, L.Tne.m, lane);
+  wave_sync();
+
+  // ---- position bound (Sec. 4.2) and the sign of the ray parameter
+  const RB<T> tb = ratio_bound<16, T, NT>(L.Tne.v, L.Tne.m, th_Tn + T(4) * eps, L.Q.v, L.Q.m, th_Q, final, lane);
+  const RB<T> ub = ratio_bound<25, T, NT>(L.Pu.v, L.Pu.m, th_P, L.Qe.v, L.Qe.m, th_Q + T(2) * eps, final, lane);
+  const RB<T> vb = ratio_bound<25, T, NT>(L.Pv.v, L.Pv.m, th_P, L.Qe.v, L.Qe.m, th_Q + T(2) * eps, final, lane);
+  if (outside) return false;
+  if (tb.uncertain || ub.uncertain || vb.uncertain) {
+    out.status = 2;
+    return false;
+  }
+  if (tb.kind == kDirect && tb.hi <= T(0)) return false;  // every ray points away from the receiver
+  T ulo, uhi, vlo, vhi;
+  if (!clip01(ub, &ulo, &uhi) || !clip01(vb, &vlo, &vhi)) return false;
+  out.uk[0] = out_lo(ulo);
+  out.uk[1] = out_hi(uhi);
+  out.uk[2] = out_lo(vlo);
+  out.uk[3] = out_hi(vhi);
+  out.settled = ub.kind == kDirect && vb.kind == kDirect && ub.lo >= T(0) && ub.hi <= T(1) && vb.lo >= T(0) &&
+                vb.hi <= T(1) && tb.kind == kDirect && tb.lo > T(0);
+  out.status = 1;
+  return true;
+}
+
+// Irradiance bound of a live box from det M, Q^3, g and h in L with their
+// error factors (Sec. 4.4, Eq. eq_dwda): det M and Q^3 raised to (10, 10),
+// the ratio bound of Q^3 / det M, the solid-angle factor |g| / h^(3/2)
+// bounded factor-wise, times the tuple's constant factor k = I0 a1 / ak.
+template <class T, int NT, class Lds>
+__device__ void irr_bound_r(T k, Lds& L, T th_detM, T th_Q3, T th_g, T th_h, bool final, BoxOut& out, int lane) {
+  const T eps = Eps<T>::u;
+  elev11_b<9, 9, T, NT>(L.detM.v, L.detM.m, L.detMe.v, L.detMe.m, lane);
+  elev11_b<9, 9, T, NT>(L.Q3.v, L.Q3.m, L.Q3e.v, L.Q3e.m, lane);
+  wave_sync();
+  const RB<T> rb = ratio_bound<121, T, NT>(L.Q3e.v, L.Q3e.m, th_Q3 + T(2) * eps, L.detMe.v, L.detMe.m,
+                                    th_detM + T(2) * eps, final, lane);
+  if (rb.uncertain) {
+    out.status = 2;
+    return;
+  }
+  T rlo, rhi;
+  abs_bound(rb, &rlo, &rhi);
+  // dOmega0/dA1 = |g| / h^(3/2) with g = n_g . d0 and h = d0 . d0, bounded factor-wise
+  T glo, ghi, hlo, hhi;
+  poly_range<1, 1, T, NT>(L.g.v, L.g.m, th_g, &glo, &ghi, lane);
+  poly_range<2, 2, T, NT>(L.h.v, L.h.m, th_h, &hlo, &hhi, lane);
+  const T aglo = (glo <= T(0) && ghi >= T(0)) ? T(0) : min(fabs(glo), fabs(ghi));
+  const T aghi = max(fabs(glo), fabs(ghi));
+  const T Glo = down(aglo / (hhi * sqrt(hhi)));
+  const T Ghi = hlo > T(0) ? up(aghi / (hlo * sqrt(hlo))) : T(INFINITY);
+  const T klo = k * (T(1) - T(16) * eps), khi = k * (T(1) + T(16) * eps);
+  const T Elo = (Glo <= T(0) || rlo <= T(0)) ? T(0) : down(klo * down(Glo * rlo));
+  const T Ehi = (isinf(Ghi) || isinf(rhi)) ? T(INFINITY) : up(khi * up(Ghi * rhi));
+  out.E[0] = out_lo(Elo);
+  out.E[1] = out_hi(Ehi);
+}
+
 // NT lanes evaluate the box (a wave, or a group of 16 or 32 lanes of one when
 // several boxes share a wave; groups run the same sequence of barriers, so a
 // box outside the triangle is only marked, not returned from, until the last
 // one).
 template <class T, bool IRR, class Lds, int NT = BBC_WAVE>
-__device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool final, Lds& L, int lane) {
+__device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool final, Lds& L, int lane,
+                             BoxTheta<T>* th = nullptr) {
   const T eps = Eps<T>::u;
   BoxOut out;
   out.status = 0;
@@ -245,34 +360,10 @@ __device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
     combo_b<4, 3, false, T, NT>(sv, sm, af2, L.Tn.v, L.Tn.m, lane);
   }
   wave_sync();
-  elev11_b<3, 3, T, NT>(L.Q.v, L.Q.m, L.Qe.v, L.Qe.m, lane);
-  elev11_b<1, 1, T, NT>(L.Tn.v, L.Tn.m, L.Tn2.v, L.Tn2.m, lane);
   const T th_P = conv_theta<3, 3, 1, 1>(th_cc, th_lin) + T(3) * eps;
   const T th_Q = th_cc + T(3) * eps;
   const T th_Tn = th_sf1 + T(3) * eps;
-  wave_sync();
-  elev11_b<2, 2, T, NT>(L.Tn2.v, L.Tn2.m, L.Tne.v, L.Tne.m, lane);
-  wave_sync();
-
-  // ---- position bound (Sec. 4.2) and the sign of the ray parameter
-  const RB<T> tb = ratio_bound<16, T, NT>(L.Tne.v, L.Tne.m, th_Tn + T(4) * eps, L.Q.v, L.Q.m, th_Q, final, lane);
-  const RB<T> ub = ratio_bound<25, T, NT>(L.Pu.v, L.Pu.m, th_P, L.Qe.v, L.Qe.m, th_Q + T(2) * eps, final, lane);
-  const RB<T> vb = ratio_bound<25, T, NT>(L.Pv.v, L.Pv.m, th_P, L.Qe.v, L.Qe.m, th_Q + T(2) * eps, final, lane);
-  if (outside) return out;
-  if (tb.uncertain || ub.uncertain || vb.uncertain) {
-    out.status = 2;
-    return out;
-  }
-  if (tb.kind == kDirect && tb.hi <= T(0)) return out;  // every ray points away from the receiver
-  T ulo, uhi, vlo, vhi;
-  if (!clip01(ub, &ulo, &uhi) || !clip01(vb, &vlo, &vhi)) return out;
-  out.uk[0] = out_lo(ulo);
-  out.uk[1] = out_hi(uhi);
-  out.uk[2] = out_lo(vlo);
-  out.uk[3] = out_hi(vhi);
-  out.settled = ub.kind == kDirect && vb.kind == kDirect && ub.lo >= T(0) && ub.hi <= T(1) && vb.lo >= T(0) &&
-                vb.hi <= T(1) && tb.kind == kDirect && tb.lo > T(0);
-  out.status = 1;
+  if (!pos_bound_r<T, Lds, NT>(L, th_P, th_Q, th_Tn, final, outside, out, lane)) return out;
   if constexpr (!IRR) {
     return out;
   } else {
@@ -334,33 +425,170 @@ __device__ BoxOut eval_box_r(const TupleGeom<T>& G, T u0, T u1, T v0, T v1, bool
                       T(2) * eps;
     const T th_Q3 = conv_theta<6, 6, 3, 3>(th_Q2, th_Q);
     wave_sync();
-    elev11_b<9, 9, T, NT>(L.detM.v, L.detM.m, L.detMe.v, L.detMe.m, lane);
-    elev11_b<9, 9, T, NT>(L.Q3.v, L.Q3.m, L.Q3e.v, L.Q3e.m, lane);
-    wave_sync();
-    const RB<T> rb = ratio_bound<121, T, NT>(L.Q3e.v, L.Q3e.m, th_Q3 + T(2) * eps, L.detMe.v, L.detMe.m,
-                                      th_detM + T(2) * eps, final, lane);
-    if (rb.uncertain) {
-      out.status = 2;
-      return out;
-    }
-    T rlo, rhi;
-    abs_bound(rb, &rlo, &rhi);
-    // dOmega0/dA1 = |g| / h^(3/2) with g = n_g . d0 and h = d0 . d0, bounded factor-wise
-    T glo, ghi, hlo, hhi;
-    poly_range<1, 1, T, NT>(L.g.v, L.g.m, th_g, &glo, &ghi, lane);
-    poly_range<2, 2, T, NT>(L.h.v, L.h.m, th_nn, &hlo, &hhi, lane);
-    const T aglo = (glo <= T(0) && ghi >= T(0)) ? T(0) : min(fabs(glo), fabs(ghi));
-    const T aghi = max(fabs(glo), fabs(ghi));
-    const T Glo = down(aglo / (hhi * sqrt(hhi)));
-    const T Ghi = hlo > T(0) ? up(aghi / (hlo * sqrt(hlo))) : T(INFINITY);
     const T k = G.I0 * G.a1 / G.ak;
-    const T klo = k * (T(1) - T(16) * eps), khi = k * (T(1) + T(16) * eps);
-    const T Elo = (Glo <= T(0) || rlo <= T(0)) ? T(0) : down(klo * down(Glo * rlo));
-    const T Ehi = (isinf(Ghi) || isinf(rhi)) ? T(INFINITY) : up(khi * up(Ghi * rhi));
-    out.E[0] = out_lo(Elo);
-    out.E[1] = out_hi(Ehi);
+    if (th) *th = BoxTheta<T>{th_P, th_Q, th_Tn, th_detM, th_Q3, th_g, th_nn, k};
+    irr_bound_r<T, NT>(k, L, th_detM, th_Q3, th_g, th_nn, final, out, lane);
     return out;
   }
+}
+
+// ---- Subdivision from the parent's polynomials (Sec. 4.1: the Bernstein
+// coefficients of a polynomial on half of its box follow from those on the
+// whole box).  Record layout (doubles): Pu 0, Pv 50, Q 100, Tn 132, det M 140,
+// Q^3 340, g 540, h 548 (each tensor's values, then its magnitudes), the error
+// factors (P, Q, Tn, det M, Q^3, g, h) and the tuple's constant at kRecCoef.
+constexpr int kRecPu = 0, kRecPv = 50, kRecQ = 100, kRecTn = 132, kRecDM = 140, kRecQ3 = 340, kRecG = 540,
+              kRecH = 548;
+static_assert(kRecH + 18 == kRecCoef && kRecCoef + 8 <= kRecR, "record layout");
+
+// Bounds of a box whose polynomials its parent wrote to `rec` (a record of
+// kRecR doubles); the same steps as eval_box_r after its products, so the box
+// ends with its record in L for split_box_r.  `th` receives the error factors
+// and the tuple's constant.  The tuple faces its light (its parent was live).
+template <class T, class Lds, int NT = BBC_WAVE>
+__device__ BoxOut eval_box_r_rec(const T* __restrict__ rec, T u0, T v0, Lds& L, BoxTheta<T>* th, int lane) {
+  static_assert(sizeof(Ten<T, 25>) == 50 * sizeof(T), "tensors are packed");
+  BoxOut out;
+  out.status = 0;
+  out.settled = false;
+  out.uk[0] = 0.f;
+  out.uk[1] = 1.f;
+  out.uk[2] = 0.f;
+  out.uk[3] = 1.f;
+  out.E[0] = 0.f;
+  out.E[1] = INFINITY;
+  if (u0 + v0 >= T(1)) return out;
+  T* dst = L.Pu.v;
+  for (int o = lane; o < kRecCoef; o += NT) dst[o] = rec[o];
+  const BoxTheta<T> t{rec[kRecCoef],     rec[kRecCoef + 1], rec[kRecCoef + 2], rec[kRecCoef + 3],
+                      rec[kRecCoef + 4], rec[kRecCoef + 5], rec[kRecCoef + 6], rec[kRecCoef + 7]};
+  *th = t;
+  wave_sync();
+  if (!pos_bound_r<T, Lds, NT>(L, t.P, t.Q, t.Tn, true, false, out, lane)) return out;
+  wave_sync();
+  irr_bound_r<T, NT>(t.k, L, t.detM, t.Q3, t.g, t.h, true, out, lane);
+  return out;
+}
+
+// One row of a tensor of degree (D1, D2) split along its first axis at the
+// midpoint, in scaled form: left half s'_i = 2^-i sum_{j<=i} C(D1-j, i-j) s_j,
+// right half s'_i = 2^-(D1-i) sum_{j>=i} C(j, i) s_j, along the row of stride
+// `st` and length D1 + 1 starting at `in`; the halves go to out0 and out1 with
+// the same stride.  Magnitudes take the same non-negative weights.
+template <int D1, class T>
+__device__ __forceinline__ void split_row(const T* in, const T* inm, int st, T* o0, T* o0m, T* o1, T* o1m) {
+  T x[D1 + 1], xm[D1 + 1];
+#pragma unroll
+  for (int j = 0; j <= D1; ++j) {
+    x[j] = in[j * st];
+    xm[j] = inm[j * st];
+  }
+#pragma unroll
+  for (int i = 0; i <= D1; ++i) {
+    T a = 0, am = 0, b = 0, bm = 0;
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      const T w = T(binom_i(D1 - j, i - j));
+      a = fma(w, x[j], a);
+      am = fma(w, xm[j], am);
+    }
+#pragma unroll
+    for (int j = i; j <= D1; ++j) {
+      const T w = T(binom_i(j, i));
+      b = fma(w, x[j], b);
+      bm = fma(w, xm[j], bm);
+    }
+    const T sa = T(1) / T(1 << i), sb = T(1) / T(1 << (D1 - i));  // powers of two: exact
+    o0[i * st] = a * sa;
+    o0m[i * st] = am * sa;
+    o1[i * st] = b * sb;
+    o1m[i * st] = bm * sb;
+    __builtin_amdgcn_sched_barrier(0);  // one output pair at a time: bounded registers
+  }
+}
+
+// Tensor (D1, D2) at (v, m): along u into the halves h (values [2][D1+1][D2+1],
+// then magnitudes), one row per lane.
+template <int D1, int D2, class T>
+__device__ __forceinline__ void split_u_rows(const T* v, const T* m, T* h, int r) {
+  constexpr int N2 = D2 + 1, NN = (D1 + 1) * N2;
+  if (r < N2) split_row<D1>(v + r, m + r, N2, h + r, h + 2 * NN + r, h + NN + r, h + 3 * NN + r);
+}
+// Halves h along v into the four children's records at `rec` (child cu << 1 |
+// cv at rec + child * kRecR, tensor at offset `off`: values, then magnitudes);
+// row r = (cu, i) per lane.
+template <int D1, int D2, class T>
+__device__ __forceinline__ void split_v_rows(const T* h, T* rec, int off, int r) {
+  constexpr int N2 = D2 + 1, NN = (D1 + 1) * N2;
+  if (r < 2 * (D1 + 1)) {
+    const int cu = r / (D1 + 1), i = r - cu * (D1 + 1);
+    const T* in = h + cu * NN + i * N2;
+    const T* inm = h + 2 * NN + cu * NN + i * N2;
+    T* c0 = rec + (cu << 1) * kRecR + off + i * N2;        // v half 0
+    T* c1 = rec + ((cu << 1) | 1) * kRecR + off + i * N2;  // v half 1
+    split_row<D2>(in, inm, 1, c0, c0 + NN, c1, c1 + NN);
+  }
+}
+
+// Splits the box whose record is in L (with error factors th) into the
+// records of its four children at rec (kRecR doubles each, child cu << 1 | cv:
+// u half cu, v half cv, as the subdivision codes its children).  Each axis adds
+// (D + 2) eps to a tensor's error factor: D + 1 rounded terms of exact integer
+// weights, times a power of two, and the magnitudes' own rounding.  The
+// tuple's constant is copied.
+template <class T, class Lds, int NT = BBC_WAVE>
+__device__ void split_box_r(Lds& L, const BoxTheta<T>& th, T* __restrict__ rec, int lane) {
+  const T eps = Eps<T>::u;
+  // halves along u, one row per lane; tensors of one degree share a branch
+  // (det M and Q^3: lanes 0-19, Pu and Pv: 20-29, Q: 30-33, Tn and g: 34-37,
+  // h: 38-40)
+  T* H = L.half;
+  constexpr int hDM = 0, hQ3 = 400, hPu = 800, hPv = 900, hQ = 1000, hTn = 1064, hG = 1080, hH = 1096;
+  static_assert(hH + 36 <= int(sizeof(L.half) / sizeof(T)), "half-split buffer");
+  wave_sync();
+  if (lane < 20) {
+    const bool q3 = lane >= 10;
+    split_u_rows<9, 9>(q3 ? L.Q3.v : L.detM.v, q3 ? L.Q3.m : L.detM.m, H + (q3 ? hQ3 : hDM), lane - (q3 ? 10 : 0));
+  } else if (lane < 30) {
+    const bool pv = lane >= 25;
+    split_u_rows<4, 4>(pv ? L.Pv.v : L.Pu.v, pv ? L.Pv.m : L.Pu.m, H + (pv ? hPv : hPu), lane - (pv ? 25 : 20));
+  } else if (lane < 34) {
+    split_u_rows<3, 3>(L.Q.v, L.Q.m, H + hQ, lane - 30);
+  } else if (lane < 38) {
+    const bool g = lane >= 36;
+    split_u_rows<1, 1>(g ? L.g.v : L.Tn.v, g ? L.g.m : L.Tn.m, H + (g ? hG : hTn), lane - (g ? 36 : 34));
+  } else if (lane < 41) {
+    split_u_rows<2, 2>(L.h.v, L.h.m, H + hH, lane - 38);
+  }
+  wave_sync();
+  // halves along v into the records, one row (u half, index) per lane: det M
+  // and Q^3 (lanes 0-39), Pu and Pv (40-59), Tn (60-63); then Q (0-7), g
+  // (8-11), h (12-17)
+  if (lane < 40) {
+    const bool q3 = lane >= 20;
+    split_v_rows<9, 9>(H + (q3 ? hQ3 : hDM), rec, q3 ? kRecQ3 : kRecDM, lane - (q3 ? 20 : 0));
+  } else if (lane < 60) {
+    const bool pv = lane >= 50;
+    split_v_rows<4, 4>(H + (pv ? hPv : hPu), rec, pv ? kRecPv : kRecPu, lane - (pv ? 50 : 40));
+  } else {
+    split_v_rows<1, 1>(H + hTn, rec, kRecTn, lane - 60);
+  }
+  if (lane < 8) {
+    split_v_rows<3, 3>(H + hQ, rec, kRecQ, lane);
+  } else if (lane < 12) {
+    split_v_rows<1, 1>(H + hG, rec, kRecG, lane - 8);
+  } else if (lane < 18) {
+    split_v_rows<2, 2>(H + hH, rec, kRecH, lane - 12);
+  }
+  // error factors
+  if (lane < 32) {
+    const int c = lane / 8, k = lane - 8 * (lane / 8);
+    const T f[8] = {th.P + T(4 + 4 + 4) * eps, th.Q + T(3 + 3 + 4) * eps, th.Tn + T(1 + 1 + 4) * eps,
+                    th.detM + T(9 + 9 + 4) * eps, th.Q3 + T(9 + 9 + 4) * eps, th.g + T(1 + 1 + 4) * eps,
+                    th.h + T(2 + 2 + 4) * eps, th.k};
+    rec[c * kRecR + kRecCoef + k] = f[k];
+  }
+  wave_sync();
 }
 
 }  // namespace bbc

@@ -44,6 +44,11 @@ struct BuildArgs {
   float4* lu;
   float2* le;
   const double* red;  // degree-reduction table (BBC_FLAG_DEGREE_REDUCTION), else null
+  // single-reflection subdivision from split polynomials: the records of this
+  // depth's items (null at depth 0) and of the next depth's, srec_cap each
+  const double* srec_in;
+  double* srec_out;
+  uint32_t srec_cap;
 };
 
 // Outputs of a workgroup's boxes (queue items for the next depth, leaves,
@@ -677,6 +682,85 @@ __device__ void subdiv_loop(const BuildArgs& a, int depth, Ev ev, int lane, Stag
   if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
 }
 
+// The subdivision loop of the single-reflection chain with child records: a
+// box at depth > 0 whose parent wrote its record (the item's index is below
+// srec_cap) is bounded from it (eval_box_r_rec, REC), any other from its corners;
+// a box that is split reserves its children's four queue slots with one
+// atomic and writes their records (split_box_r) next to them.  Decisions,
+// leaves and children are those of subdiv_one.
+template <bool REC, class Lds>
+__device__ void subdiv_loop_split(const BuildArgs& a, int depth, Lds& L, Stage& S, int lane) {
+  __shared__ uint32_t base;
+  stage_reset(S, lane);
+  wave_sync();
+  const uint32_t nq = min(a.C->qcount[depth], a.q_cap);
+  // REC: the items that have records; else the others (all at depth 0)
+  const uint32_t i0 = REC || !a.srec_in ? 0u : a.srec_cap;
+  const uint32_t n = REC ? min(nq, a.srec_cap) : nq;
+  uint32_t boxes = 0;
+  for (uint32_t i = i0 + blockIdx.x; i < n; i += gridDim.x) {
+    const QItem it = a.qin[i];
+    const float4 r = a.root[it.tuple];
+    const uint32_t iu = it.code >> kCodeBits, iv = it.code & ((1u << kCodeBits) - 1);
+    const double fu = (double(r.y) - double(r.x)) * double(ldexpf(1.f, -depth));
+    const double fv = (double(r.w) - double(r.z)) * double(ldexpf(1.f, -depth));
+    const double u0 = double(r.x) + double(iu) * fu, u1 = double(r.x) + double(iu + 1) * fu;
+    const double v0 = double(r.z) + double(iv) * fv, v1 = double(r.z) + double(iv + 1) * fv;
+    BoxTheta<double> th{};
+    BoxOut o;
+    if constexpr (REC)  // the record holds all the box needs from its tuple
+      o = eval_box_r_rec<double>(a.srec_in + size_t(i) * kRecR, u0, v0, L, &th, lane);
+    else
+      o = eval_box_r<double, true>(tuple_geom<double>(a.sc, it.tuple), u0, u1, v0, v1, true, L, lane, &th);
+    ++boxes;
+    bool split = false;
+    if (o.status == 2 && lane == 0) {  // not with final bounds; kept as in subdiv_one
+      const uint32_t k = atomicAdd(&a.C->fcount[depth], 1u);
+      if (k < a.fq_cap)
+        a.fq[k] = it;
+      else
+        atomicOr(&a.C->overflow, 8u);
+    }
+    if (o.status == 1) {
+      const float area = (o.uk[1] - o.uk[0]) * (o.uk[3] - o.uk[2]);
+      bool stop = depth >= a.max_depth;
+      if (!(a.flags & BBC_FLAG_FIXED_DEPTH)) {
+        stop = stop || area < a.sigma;
+        stop = stop || (o.E[0] > 0.f && isfinite(o.E[1]) && o.E[1] < a.alpha * o.E[0]);
+      }
+      if (stop) {
+        if (lane == 0) {
+          const uint32_t k = S.n_leaf++;
+          S.lt[k] = it.tuple;
+          S.lc[k] = uint32_t(depth) << 28 | it.code;
+          S.lu[k] = make_float4(o.uk[0], o.uk[1], o.uk[2], o.uk[3]);
+          S.le[k] = make_float2(o.E[0], o.E[1]);
+          if (isinf(o.E[1])) ++S.n_inf;
+          S.max_depth = max(S.max_depth, uint32_t(depth));
+        }
+      } else {
+        split = true;
+      }
+    }
+    if (split) {  // wave-uniform
+      if (lane == 0) {
+        base = atomicAdd(&a.C->qcount[depth + 1], 4u);
+        if (base + 4u > a.q_cap) atomicOr(&a.C->overflow, 1u);
+      }
+      wave_sync();
+      const uint32_t b0 = base;
+      if (lane < 4 && b0 + uint32_t(lane) < a.q_cap)
+        a.qout[b0 + lane] =
+            QItem{it.tuple, (2 * iu + (uint32_t(lane) >> 1)) << kCodeBits | (2 * iv + (uint32_t(lane) & 1u))};
+      if (a.srec_out && b0 + 4u <= a.srec_cap) split_box_r<double>(L, th, a.srec_out + size_t(b0) * kRecR, lane);
+    }
+    wave_sync();
+    if (stage_full(S)) stage_flush<BBC_WAVE>(a, depth + 1, S, lane);
+  }
+  stage_flush<BBC_WAVE>(a, depth + 1, S, lane);
+  if (lane == 0 && boxes) atomicAdd(&a.C->n_boxes, boxes);
+}
+
 // Subdivision boxes carry the irradiance bound, whose denominator det M has
 // coefficients that cancel by two to five orders of magnitude; they are
 // evaluated in FP64, which on this GPU issues at the rate of unpacked FP32.
@@ -688,6 +772,19 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_
     return eval_box_r<double, true>(G, u0, u1, v0, v1, true, L, lane);
   };
   subdiv_loop<BBC_WAVE>(a, depth, ev, lane, S);
+}
+
+// The same boxes bounded from their parents' split polynomials
+// (BBC_TUNE_SUBDIV_SPLIT).
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_subdiv_split(BuildArgs a, int depth) {
+  __shared__ LdsR<double> L;
+  __shared__ Stage S;
+  subdiv_loop_split<false>(a, depth, L, S, threadIdx.x);
+}
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_subdiv_rec(BuildArgs a, int depth) {
+  __shared__ LdsRRec<double> L;
+  __shared__ Stage S;
+  subdiv_loop_split<true>(a, depth, L, S, threadIdx.x);
 }
 
 // A two-reflection subdivision box also carries the irradiance bound, whose
@@ -862,6 +959,21 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   a.lu = static_cast<float4*>(b->lu.p);
   a.le = static_cast<float2*>(b->le.p);
   a.red = nullptr;
+  a.srec_in = nullptr;
+  a.srec_out = nullptr;
+  a.srec_cap = 0;
+  const bool split_rec = b->tune.subdiv_split && b->scene.chain == BBC_CHAIN_R && !b->scene.eedge;
+  if (split_rec) {
+    // a multiple of four: children come four at a time from qcount 0
+    const size_t want = b->tune.subdiv_split > 1 ? size_t(b->tune.subdiv_split) : size_t(1) << 16;
+    const uint32_t cap = uint32_t(std::max<size_t>(std::min(b->q_cap, want), 4)) & ~3u;
+    for (DevBuf& d : b->srec) {
+      bbc_status e = ensure(d, size_t(cap) * kRecR * sizeof(double), b);
+      if (e) return e;
+    }
+    b->srec_cap = cap;
+    a.srec_cap = cap;
+  }
   if ((a.flags & BBC_FLAG_DEGREE_REDUCTION) && b->scene.chain == BBC_CHAIN_RR) {
     if (!b->red_ready) {
       static const std::vector<double> table = make_reduction_table();
@@ -889,6 +1001,12 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
     if (e) return e;
   }
   const unsigned persistent = g_sub;
+  // the record-path subdivision: one resident round (its own occupancy)
+  unsigned g_rec = 0;
+  if (b->tune.subdiv_split && b->scene.chain == BBC_CHAIN_R && !b->scene.eedge) {
+    bbc_status e = resident_grid(k_subdiv_rec, 3, dev, n_cu, &g_rec);
+    if (e) return e;
+  }
 
   const bool timed = b->tune.timing && b->bev[0];
   b->subdiv_launches = a.max_depth + 1;
@@ -929,6 +1047,10 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
     for (int d = 0; d <= a.max_depth; ++d) {
       a.qin = static_cast<QItem*>(b->q[d & 1].p);
       a.qout = static_cast<QItem*>(b->q[(d + 1) & 1].p);
+      if (split_rec) {  // records follow the queues' parity; none at depth 0
+        a.srec_in = d > 0 ? static_cast<const double*>(b->srec[d & 1].p) : nullptr;
+        a.srec_out = static_cast<double*>(b->srec[(d + 1) & 1].p);
+      }
       if (area)
         hipLaunchKernelGGL(k_subdiv_ra, dim3(unsigned(n_cu) * 2u), dim3(kSubdivRAThreads), 0, cs, a, d);
       else if (rr && b->tune.rr_outlined)
@@ -940,6 +1062,14 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
                            0, cs, a, d);
       else if (refr)
         hipLaunchKernelGGL(k_subdiv_t<kSubdivTThreads>, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTThreads), 0, cs, a, d);
+      else if (split_rec) {
+        // depth > 0: the items with records, then any beyond them from their corners
+        if (d > 0) {
+          hipLaunchKernelGGL(k_subdiv_rec, dim3(g_rec), dim3(64), 0, cs, a, d);
+          BBC_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_subdiv_split, dim3(d > 0 ? unsigned(n_cu) : persistent), dim3(64), 0, cs, a, d);
+      }
       else
         hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, cs, a, d);
       BBC_HIP(hipGetLastError());

@@ -86,6 +86,7 @@ struct Tuning {
   int rr_outlined = 0;        // two-reflection subdivision: box evaluation as a called function
   int newton_grid_per_cu = 0; // pooled Newton workgroups per CU (0: occupancy API)
   int build_graph = 0;        // build: 1 = replay the launch sequence as a HIP graph
+  int subdiv_split = 1;       // reflection subdivision from split polynomials: 0 off, 1 on, n > 1 on with n records per depth
 };
 
 // A staged query's launches captured into a HIP graph on a stream of the
@@ -145,6 +146,8 @@ struct Bounds {
   DevBuf scan_tmp;
   DevBuf trec;                // packed per-tuple records for the query [n_tuples][32] float
   DevBuf red_tab;             // degree-reduction table of the two-reflection irradiance bound
+  DevBuf srec[2];             // reflection subdivision: children's polynomial records, by depth parity
+  uint32_t srec_cap = 0;      // records per depth (queue items beyond it are evaluated from their corners)
   bool red_ready = false;
   // host copies of the final counts
   BuildCounters host{};

@@ -1,0 +1,134 @@
+"""Single-reflection subdivision from split polynomials (BBC_TUNE_SUBDIV_SPLIT;
+Sec. 4.1: the Bernstein coefficients of a polynomial on half of its box
+follow from those on the whole box).  A box that is split writes its four
+children's polynomials (midpoint split in scaled form, magnitudes and error
+factors carried along) and each child is bounded from them instead of from
+its corners.  The polynomials are the same, so the trees must be identical
+and every bound equal to the corner evaluation's up to rounding (one or two
+FP32 units after the outward conversion), with the same unbounded leaves;
+with a record capacity far below a depth's item count the children past it
+are evaluated from their corners, with the same result.  Agreement with the
+FP64 oracle is checked by the parity tests, which build with the default
+(split) setting."""
+import numpy as np
+import pytest
+
+from paper_2504_19163_amd import scenes as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SPLIT = 13  # BBC_TUNE_SUBDIV_SPLIT
+
+
+@pytest.fixture(scope="module")
+def bbc():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2504_19163_amd import bbc as B
+    B.lib()
+    return B
+
+
+SCENES = {
+    "heightfield": (lambda: S.heightfield_mirror(16), dict(max_depth=6, alpha=2.0)),
+    "sphere": (lambda: S.displaced_sphere(5), dict(max_depth=8, alpha=2.0)),
+    "curved": (lambda: S.curved_triangles(4, seed=7), dict(max_depth=7, alpha=1.5)),
+    "flat": (lambda: S.flat_mirror(), dict(max_depth=8, alpha=1.2)),
+}
+
+
+def leaves_with(bbc, sc, params, split):
+    B = bbc.Bounds(bbc.DeviceScene(sc), params)
+    assert B.get_tuning(SPLIT) == 1  # the default
+    B.set_tuning(SPLIT, split)
+    B.rebuild()
+    L, info, grid = B.leaves(), B.info(), B.grid()
+    B.free()
+    return L, info, grid
+
+
+def by_key(L):
+    return {k: i for i, k in enumerate(zip(L["tuple"].tolist(), map(tuple, L["code"].tolist())))}
+
+
+def assert_same_tree_close_bounds(L0, L1, what):
+    k0, k1 = by_key(L0), by_key(L1)
+    assert set(k0) == set(k1), what
+    i0 = np.array([k0[k] for k in k1])
+    i1 = np.array(list(k1.values()))
+    for f in ("uk", "E"):
+        a = L0[f][i0].astype(np.float32)
+        b = L1[f][i1].astype(np.float32)
+        assert np.array_equal(np.isinf(a), np.isinf(b)), (what, f)
+        fin = np.isfinite(a)
+        # the FP64 bounds agree to rounding; after the outward conversion to
+        # FP32 they may differ by an ulp or two
+        ulps = np.abs(a[fin].view(np.int32).astype(np.int64) - b[fin].view(np.int32).astype(np.int64))
+        same_sign = np.sign(a[fin]) == np.sign(b[fin])
+        zero = (a[fin] == 0) | (b[fin] == 0)
+        assert np.all((same_sign & (ulps <= 2)) | (zero & (np.abs(a[fin] - b[fin]) <= 1e-30))), (what, f, ulps.max())
+    return len(k1)
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_split_tree_equals_corner_tree(bbc, name):
+    make, params = SCENES[name]
+    sc = make()
+    L0, info0, g0 = leaves_with(bbc, sc, params, 0)
+    L1, info1, g1 = leaves_with(bbc, sc, params, 1)
+    n = assert_same_tree_close_bounds(L0, L1, name)
+    print(name, "leaves", n, "boxes", info1["n_boxes"], "max depth", info1["max_depth_reached"], flush=True)
+    for k in ("n_boxes", "n_leaves", "n_inf_leaves", "max_depth_reached"):
+        assert info0[k] == info1[k], (name, k)
+    # the grid's cell lists hold the same tuples; their E~ agree to rounding
+    assert np.array_equal(g0[0], g1[0]) and np.array_equal(g0[1], g1[1])
+    e0, e1 = g0[2].astype(np.float64), g1[2].astype(np.float64)
+    fin = np.isfinite(e0)
+    assert np.array_equal(fin, np.isfinite(e1))
+    assert np.all(np.abs(e0[fin] - e1[fin]) <= 1e-6 * np.abs(e0[fin]))
+
+
+@pytest.mark.parametrize("cap", [4, 64, 1000])
+def test_record_capacity_fallback(bbc, cap):
+    """Items past the record capacity are bounded from their corners: the
+    same tree for any capacity."""
+    make, params = SCENES["sphere"]
+    sc = make()
+    L0, info0, _ = leaves_with(bbc, sc, params, 0)
+    Lc, infoc, _ = leaves_with(bbc, sc, params, cap)
+    assert_same_tree_close_bounds(L0, Lc, f"cap {cap}")
+    assert info0["n_boxes"] == infoc["n_boxes"]
+
+
+def test_split_knob_validation(bbc):
+    B = bbc.Bounds(bbc.DeviceScene(S.flat_mirror()), dict(max_depth=3))
+    with pytest.raises(Exception):
+        B.set_tuning(SPLIT, -1)
+    with pytest.raises(Exception):
+        B.set_tuning(SPLIT, (1 << 20) + 1)
+    B.set_tuning(SPLIT, 0)
+    assert B.get_tuning(SPLIT) == 0
+    B.free()
+
+
+def test_split_queries_match_corner_queries(bbc):
+    """Estimates from the two builds: the same grid tuples and bounds equal
+    to rounding, so the same selections but where a probability sits within
+    rounding of its threshold."""
+    make, params = SCENES["heightfield"]
+    sc = make()
+    pts = torch.as_tensor(S.random_points(sc, 20000, seed=4), device="cuda")
+    est = []
+    for split in (0, 1):
+        B = bbc.Bounds(bbc.DeviceScene(sc), params)
+        B.set_tuning(SPLIT, split)
+        B.rebuild()
+        E, st = B.query(pts, 16, 3, mode=bbc.QUERY_STAGED, stats=True)
+        est.append((E.cpu().numpy().astype(np.float64), st.cpu().numpy()))
+        B.free()
+    (E0, s0), (E1, s1) = est
+    assert np.array_equal(s0[:, 0], s1[:, 0])  # candidate counts
+    same = s0[:, 1] == s1[:, 1]
+    assert same.mean() >= 0.999
+    np.testing.assert_allclose(E1[same], E0[same], rtol=1e-5, atol=1e-12)
