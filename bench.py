@@ -390,10 +390,14 @@ def whole_step_section(bbc, torch, r, steps=5, spp=64, n_side=512):
     if r["scene"]["chain"] == "R" and r["scene"].get("eedge") is None:
         flop = info["n_boxes"] * FLOP_SUBDIV_BOX
         ach = flop / (sub_ms * 1e-3) / 1e12
+        split = B.get_tuning(bbc.TUNE_SUBDIV_SPLIT) != 0
+        kern = ("k_subdiv_split + k_subdiv_rec (adaptive subdivision, FP64: depth 0 from the box corners, "
+                "deeper boxes from their parents' split polynomials)" if split else
+                "k_subdiv (adaptive subdivision, FP64, every box from its corners)")
         out["roofline_subdivision"] = {
-            "bound": "alu", "kernel": "k_subdiv (adaptive subdivision, FP64)", "achieved": round(ach, 5),
+            "bound": "alu", "kernel": kern, "achieved": round(ach, 5),
             "peak": PEAK_FP64, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64, 6),
-            "traffic": traffic_bytes("k_subdiv"), "traffic_unit": "HBM bytes per build (all launches)",
+            "traffic": traffic_bytes("k_subdiv" if split else None), "traffic_unit": "HBM bytes per build (all launches)",
             "boxes_per_build": info["n_boxes"], "flop_per_box": FLOP_SUBDIV_BOX,
             "kernel_ms_per_build": round(sub_ms, 4), "launches_per_build": sub[0][1]}
     return out

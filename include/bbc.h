@@ -333,11 +333,12 @@ bbc_status bbc_query_irradiance_noalloc(const bbc_bounds* b, const float* points
  *                              their magnitudes and error factors), split at the midpoint in
  *                              scaled Bernstein form (Sec. 4.1), to a record each, and a child
  *                              is bounded from its record instead of from its corners (4.5 KB
- *                              of device memory per record, 65536 records per depth parity;
- *                              children beyond them are evaluated from their corners); n > 1
- *                              = the same with n records (rounded down to a multiple of 4, at
- *                              least 4; up to 2^20); 0 = every box from its corners.  The same
- *                              trees; bounds agree to rounding and remain rounded outward
+ *                              of device memory per record, room for 65536 records per depth
+ *                              parity at first; a build that needs more is redone with room
+ *                              for them); n > 1 = the same with room for n records at first
+ *                              (rounded down to a multiple of 4, at least 4; up to 2^20);
+ *                              0 = every box from its corners.  The same trees; bounds agree
+ *                              to rounding and remain rounded outward
  * Applies to later calls on the handle; EINVAL for an unknown knob or value. */
 #define BBC_TUNE_QUERY_WAVES 1
 #define BBC_TUNE_QUERY_GRID 2

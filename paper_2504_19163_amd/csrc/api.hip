@@ -171,6 +171,11 @@ static bbc_status run_build(Bounds* b, hipStream_t s) {
       b->leaf_cap *= 4;
     }
     if (ov & 4u) b->grid_cap = std::max<size_t>(b->grid_cap * 2, size_t(b->host.n_triples) + 1024);
+    if (ov & 32u) {  // a depth had more items than subdivision records: room for the most seen, and more
+      size_t need = 4 * size_t(b->srec_cap);
+      for (uint32_t c : b->host.qcount) need = std::max<size_t>(need, c);
+      b->srec_cap = uint32_t(std::min(need + 3, b->q_cap)) & ~3u;
+    }
     if (b->q_cap > (size_t(1) << 31) || b->grid_cap > (size_t(1) << 31)) break;
   }
   const uint32_t ov = b->host.overflow;
@@ -180,6 +185,7 @@ static bbc_status run_build(Bounds* b, hipStream_t s) {
   if (ov & 4u) what += " grid entries (" + std::to_string(b->host.n_triples) + " cell-tuple pairs);";
   if (ov & 8u) what += " FP64 queue;";
   if (ov & 16u) what += " domain initialisation;";
+  if (ov & 32u) what += " subdivision records;";
   set_error("device work queues overflowed their maximum capacity:" + what);
   return BBC_EQUEUE;
 }
@@ -813,6 +819,7 @@ bbc_status bbc_set_tuning(bbc_bounds* h, int32_t knob, int64_t value) {
     case BBC_TUNE_SUBDIV_SPLIT:
       if (value < 0 || value > (int64_t(1) << 20)) return invalid("subdivision split must be in [0, 2^20]");
       b->tune.subdiv_split = int(value);
+      b->srec_cap = 0;  // sized again by the next build
       return BBC_OK;
     default:
       return invalid("unknown tuning knob");

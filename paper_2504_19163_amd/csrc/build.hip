@@ -683,8 +683,8 @@ __device__ void subdiv_loop(const BuildArgs& a, int depth, Ev ev, int lane, Stag
 }
 
 // The subdivision loop of the single-reflection chain with child records: a
-// box at depth > 0 whose parent wrote its record (the item's index is below
-// srec_cap) is bounded from it (eval_box_r_rec, REC), any other from its corners;
+// box at depth > 0 is bounded from the record its parent wrote (REC,
+// eval_box_r_rec), a box at depth 0 from its corners;
 // a box that is split reserves its children's four queue slots with one
 // atomic and writes their records (split_box_r) next to them.  Decisions,
 // leaves and children are those of subdiv_one.
@@ -694,11 +694,12 @@ __device__ void subdiv_loop_split(const BuildArgs& a, int depth, Lds& L, Stage& 
   stage_reset(S, lane);
   wave_sync();
   const uint32_t nq = min(a.C->qcount[depth], a.q_cap);
-  // REC: the items that have records; else the others (all at depth 0)
-  const uint32_t i0 = REC || !a.srec_in ? 0u : a.srec_cap;
+  // REC: items past the record capacity have no record: the build is redone
+  // with room for them
+  if (REC && nq > a.srec_cap && blockIdx.x == 0 && lane == 0) atomicOr(&a.C->overflow, 32u);
   const uint32_t n = REC ? min(nq, a.srec_cap) : nq;
   uint32_t boxes = 0;
-  for (uint32_t i = i0 + blockIdx.x; i < n; i += gridDim.x) {
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
     const QItem it = a.qin[i];
     const float4 r = a.root[it.tuple];
     const uint32_t iu = it.code >> kCodeBits, iv = it.code & ((1u << kCodeBits) - 1);
@@ -965,8 +966,11 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
   const bool split_rec = b->tune.subdiv_split && b->scene.chain == BBC_CHAIN_R && !b->scene.eedge;
   if (split_rec) {
     // a multiple of four: children come four at a time from qcount 0
-    const size_t want = b->tune.subdiv_split > 1 ? size_t(b->tune.subdiv_split) : size_t(1) << 16;
-    const uint32_t cap = uint32_t(std::max<size_t>(std::min(b->q_cap, want), 4)) & ~3u;
+    if (b->srec_cap == 0) {
+      const size_t want = b->tune.subdiv_split > 1 ? size_t(b->tune.subdiv_split) : size_t(1) << 16;
+      b->srec_cap = uint32_t(std::max<size_t>(std::min(b->q_cap, want), 4)) & ~3u;
+    }
+    const uint32_t cap = b->srec_cap;
     for (DevBuf& d : b->srec) {
       bbc_status e = ensure(d, size_t(cap) * kRecR * sizeof(double), b);
       if (e) return e;
@@ -1062,14 +1066,10 @@ bbc_status launch_build(Bounds* b, hipStream_t s) {
                            0, cs, a, d);
       else if (refr)
         hipLaunchKernelGGL(k_subdiv_t<kSubdivTThreads>, dim3(unsigned(n_cu) * 2u), dim3(kSubdivTThreads), 0, cs, a, d);
-      else if (split_rec) {
-        // depth > 0: the items with records, then any beyond them from their corners
-        if (d > 0) {
-          hipLaunchKernelGGL(k_subdiv_rec, dim3(g_rec), dim3(64), 0, cs, a, d);
-          BBC_HIP(hipGetLastError());
-        }
-        hipLaunchKernelGGL(k_subdiv_split, dim3(d > 0 ? unsigned(n_cu) : persistent), dim3(64), 0, cs, a, d);
-      }
+      else if (split_rec && d > 0)
+        hipLaunchKernelGGL(k_subdiv_rec, dim3(g_rec), dim3(64), 0, cs, a, d);
+      else if (split_rec)
+        hipLaunchKernelGGL(k_subdiv_split, dim3(persistent), dim3(64), 0, cs, a, d);
       else
         hipLaunchKernelGGL(k_subdiv, dim3(persistent), dim3(64), 0, cs, a, d);
       BBC_HIP(hipGetLastError());

@@ -39,7 +39,8 @@ struct BuildCounters {
   uint32_t n_boxes;
   uint32_t n_fp64;
   uint32_t n_live;                 // tuples with a root box
-  uint32_t overflow;               // bit flags: 1 queue, 2 leaves, 4 grid entries, 8 fp64 queue, 16 init
+  uint32_t overflow;               // bit flags: 1 queue, 2 leaves, 4 grid entries, 8 fp64 queue, 16 init,
+                                   // 32 subdivision records
   uint32_t max_depth;
   uint32_t n_triples;              // grid entries wanted when they overflowed the capacity
   uint32_t n_entries;              // (cell, tuple) entries of the grid
@@ -86,7 +87,7 @@ struct Tuning {
   int rr_outlined = 0;        // two-reflection subdivision: box evaluation as a called function
   int newton_grid_per_cu = 0; // pooled Newton workgroups per CU (0: occupancy API)
   int build_graph = 0;        // build: 1 = replay the launch sequence as a HIP graph
-  int subdiv_split = 1;       // reflection subdivision from split polynomials: 0 off, 1 on, n > 1 on with n records per depth
+  int subdiv_split = 1;       // reflection subdivision from split polynomials: 0 off, 1 on, n > 1 on with room for n records at first
 };
 
 // A staged query's launches captured into a HIP graph on a stream of the
@@ -147,7 +148,7 @@ struct Bounds {
   DevBuf trec;                // packed per-tuple records for the query [n_tuples][32] float
   DevBuf red_tab;             // degree-reduction table of the two-reflection irradiance bound
   DevBuf srec[2];             // reflection subdivision: children's polynomial records, by depth parity
-  uint32_t srec_cap = 0;      // records per depth (queue items beyond it are evaluated from their corners)
+  uint32_t srec_cap = 0;      // records per depth parity (0: not sized yet); grown when a depth needs more
   bool red_ready = false;
   // host copies of the final counts
   BuildCounters host{};

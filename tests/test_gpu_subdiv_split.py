@@ -6,10 +6,9 @@ factors carried along) and each child is bounded from them instead of from
 its corners.  The polynomials are the same, so the trees must be identical
 and every bound equal to the corner evaluation's up to rounding (one or two
 FP32 units after the outward conversion), with the same unbounded leaves;
-with a record capacity far below a depth's item count the children past it
-are evaluated from their corners, with the same result.  Agreement with the
-FP64 oracle is checked by the parity tests, which build with the default
-(split) setting."""
+a build whose depths need more records than there is room for is redone with
+room for them, with the same result.  Agreement with the FP64 oracle is
+checked by the parity tests, which build with the default (split) setting."""
 import numpy as np
 import pytest
 
@@ -90,9 +89,9 @@ def test_split_tree_equals_corner_tree(bbc, name):
 
 
 @pytest.mark.parametrize("cap", [4, 64, 1000])
-def test_record_capacity_fallback(bbc, cap):
-    """Items past the record capacity are bounded from their corners: the
-    same tree for any capacity."""
+def test_record_capacity_regrowth(bbc, cap):
+    """A depth with more items than records flags the build, which is redone
+    with room for the most items seen: the same tree for any first capacity."""
     make, params = SCENES["sphere"]
     sc = make()
     L0, info0, _ = leaves_with(bbc, sc, params, 0)
