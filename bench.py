@@ -78,19 +78,20 @@ FLOP_SUBDIV_BOX = 900 + 3630 + 3 * (25 + 25 + 16 + 121)
 # 256 MiB device copy; valid only while the kernel sources hash to the digest
 # they were measured with (null afterwards).
 COUNTERS = {
-    # k_subdiv, per build of the sphere (9 launches, 39,961 boxes; builds 2 and 3
-    # of profiles/subdiv_sphere131072_hbm_sq_counters.md averaged)
+    # the subdivision, per build of the sphere (k_subdiv_split at depth 0 and
+    # k_subdiv_rec below: 9 launches, 39,961 boxes; builds 2 and 3 of
+    # profiles/subdiv_sphere131072_hbm_sq_counters.md averaged)
     "k_subdiv": dict(
         sources=['paper_2504_19163_amd/csrc/build.hip', 'paper_2504_19163_amd/csrc/box_r.hpp', 'paper_2504_19163_amd/csrc/bern_dev.hpp', 'paper_2504_19163_amd/csrc/dev_common.hpp', 'paper_2504_19163_amd/csrc/geom_dev.hpp'],
-        sha256="c72dad188e5e2ba028311c1a4797d461e426ee37e3ba610caa0e6428424e33fe",
-        fetch_kib=23154.5, write_kib=2837.4, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
+        sha256="eb464fb04893e205ad4607add0176d99dceaf7aef2c4d220a13869eb957bcb37",
+        fetch_kib=75086.6, write_kib=157378.1, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
     # the pooled Newton kernels of the serving stream, mean per launch over the
-    # run's 394 (FETCH_SIZE) and 396 (WRITE_SIZE) launches of all three chains
+    # run's 396 launches of all three chains
     # (profiles/serving_stream_three_scenes_newton_hbm_counters.md)
     "newton_stream": dict(
         sources=['paper_2504_19163_amd/csrc/query.hip', 'paper_2504_19163_amd/csrc/path_dev.hpp', 'paper_2504_19163_amd/csrc/geom_dev.hpp', 'paper_2504_19163_amd/csrc/dev_common.hpp', 'paper_2504_19163_amd/csrc/internal.hpp'],
-        sha256="b03033761f9a12a26e609529616106ab4630fbf1691613836bde0dbe1789f1da",
-        fetch_kib=134034.8, write_kib=87707.4, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
+        sha256="678f82d57dae5b8e724b9684723bfd36d8cb213974dea323e3dfccc257d1b3f6",
+        fetch_kib=133420.5, write_kib=87719.8, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
 }
 
 
