@@ -139,6 +139,9 @@ __device__ float solve_gamma(const float* ge, const CandList& cl, float W) {
   const uint32_t nU = cl.n;
   uint32_t n_inf = 0, n_fin = 0;
   float S = 0.f;
+  // the loops over U are unrolled so that a thread's reads go out several at
+  // a time (the sums keep list order)
+#pragma unroll 8
   for (uint32_t j = 0; j < nU; ++j) {
     const float e = ge[cl.at(j)];
     n_inf += isinf(e) ? 1u : 0u;
@@ -155,6 +158,7 @@ __device__ float solve_gamma(const float* ge, const CandList& cl, float W) {
   for (uint32_t iter = 0; iter <= n_fin; ++iter) {
     uint32_t kn = 0;
     float Sn = 0.f;
+#pragma unroll 8
     for (uint32_t j = 0; j < nU; ++j) {
       const float e = ge[cl.at(j)];
       if (isfinite(e) && e > 0.f) {
@@ -837,24 +841,43 @@ __global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* s
     uint32_t o = FILL && valid ? s.off[i] : 0u, c = 0;
     // the group's lanes run the same trip count
     if constexpr (FILL) {
-      for (uint32_t j0 = 0; j0 < nU; j0 += GL) {
+      // kSelAhead chunks per trip: their decision words, then the taken
+      // entries' tuples and bounds, are read together; the pairs are written
+      // chunk by chunk in list order
+      for (uint32_t j0 = 0; j0 < nU; j0 += GL * kSelAhead) {
         const uint32_t j = j0 + gl;
-        const uint32_t word = bits[j0 / GL];
-        const bool take = j < nU && ((word >> gl) & 1u) != 0u;
-        float P = 0.f;
-        uint32_t T = 0;
-        if (take) {
-          T = a.gt[cl.at(j)];
-          P = uniform ? Pu : select_prob(a.ge[cl.at(j)], gamma, exhaustive);
+        uint32_t word[kSelAhead], Tq[kSelAhead];
+        float Eq[kSelAhead];
+        bool take[kSelAhead];
+#pragma unroll
+        for (int u = 0; u < kSelAhead; ++u) {
+          const uint32_t j0u = j0 + uint32_t(u * GL);
+          word[u] = j0u < nU ? bits[j0u / GL] : 0u;
         }
-        const uint32_t m = uint32_t(__ballot(take) >> (GL * g)) & ((1u << GL) - 1u);
-        const uint32_t rank = __popc(m & ((1u << gl) - 1u));
-        if (take && o + rank < s.pair_cap) {
-          s.pair_pt[o + rank] = uint32_t(i);
-          s.pair_t[o + rank] = T;
-          s.pair_p[o + rank] = P;
+#pragma unroll
+        for (int u = 0; u < kSelAhead; ++u) {
+          const uint32_t ju = j + uint32_t(u * GL);
+          take[u] = ju < nU && ((word[u] >> gl) & 1u) != 0u;
+          Tq[u] = 0u;
+          Eq[u] = 0.f;
+          if (take[u]) {
+            const uint32_t x = cl.at(ju);
+            Tq[u] = a.gt[x];
+            if (!uniform) Eq[u] = a.ge[x];
+          }
         }
-        o += __popc(m);
+#pragma unroll
+        for (int u = 0; u < kSelAhead; ++u) {
+          const float P = take[u] ? (uniform ? Pu : select_prob(Eq[u], gamma, exhaustive)) : 0.f;
+          const uint32_t m = uint32_t(__ballot(take[u]) >> (GL * g)) & ((1u << GL) - 1u);
+          const uint32_t rank = __popc(m & ((1u << gl) - 1u));
+          if (take[u] && o + rank < s.pair_cap) {
+            s.pair_pt[o + rank] = uint32_t(i);
+            s.pair_t[o + rank] = Tq[u];
+            s.pair_p[o + rank] = P;
+          }
+          o += __popc(m);
+        }
       }
     } else {
       // kSelAhead chunks per trip: their grid entries (tuple and bound, then
