@@ -186,6 +186,7 @@ __device__ float solve_gamma_wave(const float* ge, const CandList& cl, float W, 
   const uint32_t nU = cl.n;
   uint32_t n_inf = 0, n_fin = 0;
   float S = 0.f;
+#pragma unroll 4
   for (uint32_t j = uint32_t(lane); j < nU; j += BBC_WAVE) {
     const float e = ge[cl.at(j)];
     n_inf += isinf(e) ? 1u : 0u;
@@ -205,6 +206,7 @@ __device__ float solve_gamma_wave(const float* ge, const CandList& cl, float W, 
   for (uint32_t iter = 0; iter <= n_fin; ++iter) {
     uint32_t kn = 0;
     float Sn = 0.f;
+#pragma unroll 4
     for (uint32_t j = uint32_t(lane); j < nU; j += BBC_WAVE) {
       const float e = ge[cl.at(j)];
       if (isfinite(e) && e > 0.f) {
