@@ -13,6 +13,7 @@
 // results in HBM: gamma per point, selection count + scan + compaction into
 // (point, tuple, P) pairs, Newton per pair, accumulation per point.
 #include <atomic>
+#include <utility>
 
 #include "internal.hpp"
 #include "path_dev.hpp"
@@ -1310,10 +1311,25 @@ __global__ void k_stage_redo(StagedArgs s, const uint32_t* total, const uint32_t
 // the sequential one, bit for bit (the fused query sums the same way); the
 // trip count is the longest list of the wave's four points, the shorter lists
 // padded with +0.0, which leaves a sum of non-negative terms unchanged.
+// Lane J of each row of 16 lanes to the whole row (DPP row_newbcast, a VALU
+// move: no LDS round trip as with a shuffle), for an FP64 value.
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(x), 0x150 + J, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(x >> 32), 0x150 + J, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+// E += the row's 16 values in lane order (every lane of the row gets the same sum).
+template <int... J>
+__device__ __forceinline__ void add_row(double& E, double v, std::integer_sequence<int, J...>) {
+  ((E += row_bcast<J>(v)), ...);
+}
+
 __global__ void __launch_bounds__(256) k_stage_accum(StagedArgs s) {
   constexpr int GL = kSelLanes;
   const QueryArgs& a = s.q;
-  const int lane = threadIdx.x % BBC_WAVE, gl = lane % GL, gb = lane - gl;
+  const int lane = threadIdx.x % BBC_WAVE, gl = lane % GL;
   const bool exhaustive = (a.mode & BBC_QUERY_EXHAUSTIVE) != 0;
   // the moment bound sum E~^2 / P is reported for the bound-optimal P only
   const int sampler = a.mode & BBC_QUERY_SAMPLERS;
@@ -1335,8 +1351,8 @@ __global__ void __launch_bounds__(256) k_stage_accum(StagedArgs s) {
       const bool in = b + gl < len;
       const double v = in ? s.pair_c[o0 + b + gl] : 0.0;
       if (a.stats && in) roots += s.pair_nr[o0 + b + gl];
-#pragma unroll
-      for (int j = 0; j < GL; ++j) E += __shfl(v, gb + j, BBC_WAVE);
+      static_assert(GL == 16, "a group is a DPP row");
+      add_row(E, v, std::make_integer_sequence<int, GL>{});
     }
     if (valid && gl == 0) a.out[i] = float(E);
     if (a.stats) {  // uniform across the launch
@@ -1356,8 +1372,7 @@ __global__ void __launch_bounds__(256) k_stage_accum(StagedArgs s) {
           const float P = select_prob(e, gamma, exhaustive);
           if (bound_p && P > 0.f && isfinite(e)) t = double(e) * double(e) / double(P);
         }
-#pragma unroll
-        for (int j = 0; j < GL; ++j) mu2 += __shfl(t, gb + j, BBC_WAVE);
+        add_row(mu2, t, std::make_integer_sequence<int, GL>{});
       }
       if (valid && gl == 0) {
         a.stats[4 * i + 0] = float(nU);
