@@ -45,6 +45,57 @@ __device__ __forceinline__ T wave_sum(T v) {
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, BBC_WAVE);
   return v;
 }
+// FP32 and FP64 minima and maxima over the wave through DPP moves (VALU, no
+// LDS round trip): butterflies within each row of 16 lanes (quad_perm
+// [1,0,3,2], quad_perm [2,3,0,1], half-row mirror, row mirror), then the four
+// row results through readlane.  Every lane gets the result; all 64 lanes
+// must be active.  min and max are exact, so the result does not depend on
+// the order in which the lanes are combined.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(x >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(x), l), hi = __builtin_amdgcn_readlane(int(x >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+template <bool MAX, class T>
+__device__ __forceinline__ T wave_minmax_dpp(T v) {
+  auto op = [](T a, T b) { return MAX ? max(a, b) : min(a, b); };
+  v = op(v, dpp_mov<0xB1>(v));
+  v = op(v, dpp_mov<0x4E>(v));
+  v = op(v, dpp_mov<0x141>(v));
+  v = op(v, dpp_mov<0x140>(v));
+  return op(op(read_lane(v, 0), read_lane(v, 16)), op(read_lane(v, 32), read_lane(v, 48)));
+}
+template <>
+__device__ __forceinline__ double wave_min<double>(double v) {
+  return wave_minmax_dpp<false>(v);
+}
+template <>
+__device__ __forceinline__ double wave_max<double>(double v) {
+  return wave_minmax_dpp<true>(v);
+}
+template <>
+__device__ __forceinline__ float wave_min<float>(float v) {
+  return wave_minmax_dpp<false>(v);
+}
+template <>
+__device__ __forceinline__ float wave_max<float>(float v) {
+  return wave_minmax_dpp<true>(v);
+}
+
 __device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0ull; }
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
