@@ -83,15 +83,16 @@ COUNTERS = {
     # profiles/subdiv_sphere131072_hbm_sq_counters.md averaged)
     "k_subdiv": dict(
         sources=['paper_2504_19163_amd/csrc/build.hip', 'paper_2504_19163_amd/csrc/box_r.hpp', 'paper_2504_19163_amd/csrc/bern_dev.hpp', 'paper_2504_19163_amd/csrc/dev_common.hpp', 'paper_2504_19163_amd/csrc/geom_dev.hpp'],
-        sha256="eb464fb04893e205ad4607add0176d99dceaf7aef2c4d220a13869eb957bcb37",
-        fetch_kib=75086.6, write_kib=157378.1, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
+        sha256="43fa6aa2f1af37c4b7bee41c7be93125528047cd0c57e94723b898cb2dc79ec6",
+        fetch_kib=71004.8, write_kib=149273.8, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
     # the pooled Newton kernels of the serving stream, mean per launch over the
-    # run's 396 launches of all three chains
+    # run's launches of all three chains (394 counted for FETCH_SIZE, 396 for
+    # WRITE_SIZE)
     # (profiles/serving_stream_three_scenes_newton_hbm_counters.md)
     "newton_stream": dict(
         sources=['paper_2504_19163_amd/csrc/query.hip', 'paper_2504_19163_amd/csrc/path_dev.hpp', 'paper_2504_19163_amd/csrc/geom_dev.hpp', 'paper_2504_19163_amd/csrc/dev_common.hpp', 'paper_2504_19163_amd/csrc/internal.hpp'],
-        sha256="678f82d57dae5b8e724b9684723bfd36d8cb213974dea323e3dfccc257d1b3f6",
-        fetch_kib=133420.5, write_kib=87719.8, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
+        sha256="27e4fd427703dfaa50b9c13a60cfb8660f2768506677b9d02bf08379ad439f89",
+        fetch_kib=134229.0, write_kib=87675.1, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
 }
 
 
