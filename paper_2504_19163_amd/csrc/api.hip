@@ -66,7 +66,7 @@ void release(DevBuf& b) {
 
 static void release_all(Bounds* b) {
   DevBuf* all[] = {&b->pos, &b->nrm, &b->epos, &b->eI, &b->eedge, &b->counters, &b->root, &b->init_q, &b->l0f_q, &b->q[0],
-                   &b->q[1], &b->fq, &b->lt, &b->lc, &b->lu, &b->le, &b->gl_t, &b->gl_c, &b->gl_u, &b->gl_e, &b->st, &b->sc, &b->su, &b->se, &b->tcount,
+                   &b->q[1], &b->fq, &b->lt, &b->lc, &b->lu, &b->le, &b->gl_t, &b->gl_c, &b->gl_u, &b->gl_e, &b->st, &b->sc, &b->su, &b->sug, &b->se, &b->tcount,
                    &b->toff, &b->tcur, &b->lrect, &b->lcoarse, &b->ccount, &b->coff, &b->gt, &b->ge,
                    &b->scan_tmp, &b->trec, &b->pos2, &b->nrm2, &b->box2, &b->rowcount, &b->rowoff, &b->tid,
                    &b->qw_buf, &b->max_cell_dev, &b->qcounters, &b->cflag, &b->cpos, &b->cE, &b->red_tab,
@@ -430,6 +430,7 @@ static bbc_status load_file(FILE* f, Bounds* b, hipStream_t s) {
   BBC_HIP(hipGetDevice(&b->device));
   for (size_t i = 0; i < secs.size(); ++i)
     if ((e = copy_in(*secs[i].buf, data[i].data(), secs[i].bytes, BBC_MEM_HOST, b, s))) return e;
+  if ((e = launch_leaf_groups(b, nullptr, uint32_t(fh.n_leaves), s))) return e;
   BBC_HIP(hipStreamSynchronize(s));  // the host staging vectors go out of scope below
   DevScene& d = b->scene;
   d.n_tri = fh.n_tri;

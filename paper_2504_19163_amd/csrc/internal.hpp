@@ -135,6 +135,7 @@ struct Bounds {
   DevBuf lt, lc, lu, le;      // tuple u32, code u32, ukbox float4, E float2
   DevBuf gl_t, gl_c, gl_u, gl_e;  // grouped by tuple
   DevBuf st, sc, su, se;      // grouped by tuple, ordered by code
+  DevBuf sug;                 // union of the receiver bounds of each run of kLeafGroup sorted leaves
   size_t leaf_cap = 0;
   DevBuf tcount, toff, tcur;  // per-tuple counts / offsets [n_tuples + 1] / cursors
   // receiver grid
@@ -186,6 +187,12 @@ void release(DevBuf& b);
 // stage launchers (stream-ordered, no host synchronisation)
 bbc_status launch_build(Bounds* b, hipStream_t s);
 bbc_status launch_record(Bounds* b, hipStream_t s);
+// Sorted leaves in runs of kLeafGroup (leaf i in run i / kLeafGroup, runs may
+// span tuples): sug[g] is the union of the receiver bounds of run g, which
+// lets the query test a run before its leaves.  n_leaves is read from the
+// build counters when `counters` is given, else taken from `n_host`.
+constexpr uint32_t kLeafGroup = 8;
+bbc_status launch_leaf_groups(Bounds* b, const BuildCounters* counters, uint32_t n_host, hipStream_t s);
 bbc_status launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
 bbc_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);

@@ -28,6 +28,7 @@ struct QueryArgs {
   const uint32_t* toff;
   const uint32_t* lcode;
   const float4* luk;
+  const float4* lgu;  // union of the bounds of each run of kLeafGroup leaves
   const uint32_t* coff;
   const uint32_t* gt;
   const float* ge;
@@ -553,6 +554,7 @@ static QueryArgs make_args(const Bounds* b, const float* pts, int64_t n, int32_t
   a.toff = static_cast<const uint32_t*>(b->toff.p);
   a.lcode = static_cast<const uint32_t*>(b->sc.p);
   a.luk = static_cast<const float4*>(b->su.p);
+  a.lgu = static_cast<const float4*>(b->sug.p);
   a.coff = static_cast<const uint32_t*>(b->coff.p);
   a.gt = static_cast<const uint32_t*>(b->gt.p);
   a.ge = static_cast<const float*>(b->ge.p);
@@ -953,6 +955,16 @@ constexpr int kPool = 128;  // FP32 starts (ring); at most 127 are held
 constexpr int kCand = 128;  // FP32 roots waiting for the polish; at most 127
 constexpr int kRes = 96;    // accepted roots of the 64 pairs (about 7 on average)
 constexpr uint32_t kRedoCap = 16384;  // listed pairs to redo per query
+constexpr int kRunQ = 128;  // queued runs (ring); at most 71 are held
+constexpr uint32_t kRunsPerTrip = BBC_WAVE / kLeafGroup;
+// In the two-reflection kernel, a pair whose tuple has at least kRunMin
+// leaves scans the unions of its leaves' runs of kLeafGroup first and tests
+// only the leaves of runs whose union holds its target; smaller tuples test
+// their leaves directly.  The other chains' tuples hold a few leaves each
+// (about one on a refracting surface), and their kernels do without the
+// run queue's LDS, which would cost them a resident workgroup per compute
+// unit.
+constexpr uint32_t kRunMin = 12;
 
 template <int CH, bool AREA = false>
 struct NewtonPool {
@@ -962,8 +974,13 @@ struct NewtonPool {
   double lx[AREA ? BBC_WAVE : 1], ly[AREA ? BBC_WAVE : 1], lz[AREA ? BBC_WAVE : 1];  // FP64 light points
   float tu[BBC_WAVE], tv[BBC_WAVE];
   double tud[BBC_WAVE], tvd[BBC_WAVE];
+  static constexpr bool RUNS = CH == BBC_CHAIN_RR;
+  static constexpr int NQ = RUNS ? kRunQ : 1, NW = RUNS ? BBC_WAVE : 1;
   uint32_t lb[BBC_WAVE], lscan[BBC_WAVE + 1];
+  uint32_t lend[NW], lg0[NW];  // leaf range end, first run (or none)
   uint32_t redo[BBC_WAVE];
+  uint32_t gq[NQ];  // runs whose union holds their pair's target, leaves not tested yet
+  uint8_t gp[NQ];
   float pu[kPool], pv[kPool], plu0[kPool], plu1[kPool], plv0[kPool], plv1[kPool], pprev[kPool], ptl[kPool];
   uint32_t pk[kPool], pmeta[kPool];  // leaf index; pair | iterations done << 8
   float cu[kCand], cv[kCand];
@@ -984,6 +1001,7 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
   constexpr bool RR = CH == BBC_CHAIN_RR;
   using Pool = NewtonPool<CH, AREA>;
   constexpr int NF = Pool::NF, RS = Pool::RS, NREC = RR ? kRecFloatsRR : kRecFloats;
+  constexpr bool RUNS = Pool::RUNS;
   __shared__ Pool L;
   const QueryArgs& a = s.q;
   const int lane = int(threadIdx.x);
@@ -1023,6 +1041,10 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
     const uint32_t k = batch * uint32_t(BBC_WAVE) + uint32_t(lane);
     const bool valid = k < np;
     const uint32_t T = nT, Pt = nPt, cnt = valid ? nCnt : 0u;
+    // the pair's scan units: its leaves, or the runs of kLeafGroup leaves
+    // that hold them when it has kRunMin leaves or more
+    const bool runs = RUNS && cnt >= kRunMin;
+    const uint32_t units = runs ? (nLb + cnt - 1u) / kLeafGroup - nLb / kLeafGroup + 1u : cnt;
     Target tg{};
     tg.ud = nTgt.x;
     tg.vd = nTgt.y;
@@ -1045,14 +1067,18 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
       R[26] = nRoot.z;
       R[27] = nRoot.w;
       L.lb[lane] = nLb;
+      if constexpr (RUNS) {
+        L.lend[lane] = nLb + cnt;
+        L.lg0[lane] = runs ? nLb / kLeafGroup : 0xffffffffu;
+      }
       L.tu[lane] = tg.u;
       L.tv[lane] = tg.v;
       L.tud[lane] = tg.ud;
       L.tvd[lane] = tg.vd;
     }
     fetch_pair(batch + stride);
-    const uint32_t ex = wave_excl_scan(cnt, lane);
-    const uint32_t tot = __shfl(ex + cnt, BBC_WAVE - 1, BBC_WAVE);
+    const uint32_t ex = wave_excl_scan(units, lane);
+    const uint32_t tot = __shfl(ex + units, BBC_WAVE - 1, BBC_WAVE);
     L.lscan[lane] = ex;
     if (lane == BBC_WAVE - 1) L.lscan[BBC_WAVE] = tot;
     __syncthreads();
@@ -1079,9 +1105,9 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
       stored = true;
     };
 
-    // wave-uniform counters: leaf slots scanned, pool ring head and size,
-    // queued candidates, stored roots
-    uint32_t scan = 0, head = 0, pn = 0, cn = 0, rn = 0;
+    // wave-uniform counters: unit slots scanned, pool ring head and size,
+    // queued candidates, stored roots, queued runs' ring head and size
+    uint32_t scan = 0, head = 0, pn = 0, cn = 0, rn = 0, ghead = 0, gn = 0;
     auto polish = [&](uint32_t n) {
       bool ok = false, keep = false;
       double ud = 0, vd = 0, E = 0;
@@ -1134,20 +1160,17 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
     };
 
     while (true) {
-      // refill the pool from the next 64 leaf slots until it holds a pass
-      while (pn < uint32_t(BBC_WAVE) && scan < tot) {
-        const uint32_t j = scan + uint32_t(lane);
+      // refill the pool until it holds a pass: each trip either scans the
+      // next 64 unit slots (a leaf of a small tuple is tested at once, a run
+      // whose union holds the target is queued) or tests the leaves of up to
+      // kRunsPerTrip queued runs, kLeafGroup lanes per run.  Every leaf whose
+      // bound holds the target becomes a start, as in a scan of all leaves;
+      // the order of the starts in the pool does not change any result.
+      while (pn < uint32_t(BBC_WAVE) && (scan < tot || gn > 0u)) {
         bool take = false;
         Start32 st{};
         uint32_t p = 0, kk = 0;
-        if (j < tot) {
-          int lo = 0, hi = BBC_WAVE - 1;  // the pair whose slots hold j: the last with lscan[p] <= j
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (L.lscan[mid] <= j) lo = mid; else hi = mid - 1;
-          }
-          p = uint32_t(lo);
-          kk = L.lb[p] + (j - L.lscan[p]);
+        auto test_leaf = [&]() {
           const float4 uk = a.luk[kk];
           const uint32_t code = a.lcode[kk];  // loaded with the bound (one round trip)
           const double ud = L.tud[p], vd = L.tvd[p];
@@ -1157,6 +1180,57 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
             st = start_of(code, R[24], R[25], R[26], R[27]);
             ++wc.starts;
           }
+        };
+        if (RUNS && (gn >= kRunsPerTrip || (gn > 0u && scan >= tot))) {
+          const uint32_t used = min(gn, kRunsPerTrip);
+          const uint32_t slot = uint32_t(lane) / kLeafGroup;
+          if (slot < used) {
+            const uint32_t q = (ghead + slot) % uint32_t(kRunQ);
+            p = L.gp[q];
+            kk = L.gq[q] * kLeafGroup + uint32_t(lane) % kLeafGroup;
+            if (kk >= L.lb[p] && kk < L.lend[p]) test_leaf();  // the run may hold other tuples' leaves
+          }
+          ghead = (ghead + used) % uint32_t(kRunQ);
+          gn -= used;
+        } else {
+          const uint32_t j = scan + uint32_t(lane);
+          bool hit = false;
+          uint32_t g = 0;
+          if (j < tot) {
+            int lo = 0, hi = BBC_WAVE - 1;  // the pair whose slots hold j: the last with lscan[p] <= j
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (L.lscan[mid] <= j) lo = mid; else hi = mid - 1;
+            }
+            p = uint32_t(lo);
+            const uint32_t off = j - L.lscan[p];
+            if constexpr (RUNS) {
+              const uint32_t g0 = L.lg0[p];
+              if (g0 != 0xffffffffu) {
+                g = g0 + off;
+                const float4 gu = a.lgu[g];
+                const double ud = L.tud[p], vd = L.tvd[p];
+                hit = ud >= gu.x && ud <= gu.y && vd >= gu.z && vd <= gu.w;
+              } else {
+                kk = L.lb[p] + off;
+                test_leaf();
+              }
+            } else {
+              kk = L.lb[p] + off;
+              test_leaf();
+            }
+          }
+          if constexpr (RUNS) {
+            const uint64_t mg = __ballot(hit);
+            if (hit) {
+              const uint32_t q = (ghead + gn + uint32_t(__popcll(mg & below))) % uint32_t(kRunQ);
+              L.gq[q] = g;
+              L.gp[q] = uint8_t(p);
+            }
+            if (mg) __syncthreads();  // queued runs are read by other lanes in a later trip
+            gn += uint32_t(__popcll(mg));
+          }
+          scan += uint32_t(BBC_WAVE);
         }
         const uint64_t m = __ballot(take);
         if (take) {
@@ -1173,7 +1247,6 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
           L.pmeta[q] = p;
         }
         pn += uint32_t(__popcll(m));
-        scan += uint32_t(BBC_WAVE);
       }
       if (!stored) store_rec();
       if (pn == 0u) break;

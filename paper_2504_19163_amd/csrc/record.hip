@@ -171,6 +171,36 @@ __global__ void k_leaf_rank(RecArgs a) {
   }
 }
 
+// Union of the receiver bounds of each run of kLeafGroup sorted leaves (the
+// last run may be shorter).  fminf / fmaxf take the non-NaN operand, so a leaf
+// whose bound holds a target makes its run's union hold it too.
+__global__ void k_leaf_groups(const float4* su, const BuildCounters* C, uint32_t n_host, uint32_t cap, float4* sug) {
+  const uint32_t n = C ? min(C->n_leaves, cap) : n_host;
+  const uint32_t ng = (n + kLeafGroup - 1) / kLeafGroup;
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
+    float4 r = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+    const uint32_t e = min(n, (g + 1) * kLeafGroup);
+    for (uint32_t i = g * kLeafGroup; i < e; ++i) {
+      const float4 u = su[i];
+      r.x = fminf(r.x, u.x);
+      r.y = fmaxf(r.y, u.y);
+      r.z = fminf(r.z, u.z);
+      r.w = fmaxf(r.w, u.w);
+    }
+    sug[g] = r;
+  }
+}
+
+bbc_status launch_leaf_groups(Bounds* b, const BuildCounters* counters, uint32_t n_host, hipStream_t s) {
+  const size_t cap = counters ? b->leaf_cap : size_t(n_host);
+  bbc_status e;
+  if ((e = ensure(b->sug, (cap / kLeafGroup + 1) * 16, b))) return e;
+  hipLaunchKernelGGL(k_leaf_groups, dim3(512), dim3(256), 0, s, static_cast<const float4*>(b->su.p), counters,
+                     n_host, uint32_t(std::min<size_t>(cap, 0xffffffffu)), static_cast<float4*>(b->sug.p));
+  BBC_HIP(hipGetLastError());
+  return BBC_OK;
+}
+
 // ---------------------------------------------------------------- receiver grid
 // Cell of a receiver coordinate: the product x G is exact in FP64 (24-bit
 // significand times G <= 4096), so a bound's edge is never rounded into the
@@ -485,6 +515,7 @@ bbc_status launch_record(Bounds* b, hipStream_t s) {
   if ((st = launch_scan_u32(a.tcount, a.toff, b->n_tuples, b->scan_tmp.p, s))) return st;
   hipLaunchKernelGGL(k_leaf_scatter, dim3(gl), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_leaf_rank, dim3(gl), dim3(256), 0, s, a);
+  if ((st = launch_leaf_groups(b, a.C, 0, s))) return st;
   const unsigned gt_ = unsigned(std::max<int64_t>(1, std::min<int64_t>((b->n_tuples + 255) / 256, 4096)));
   hipLaunchKernelGGL(k_tuple_cover, dim3(gt_), dim3(256), 0, s, a);
   if ((st = launch_scan_u32(a.cflag, a.cpos, b->n_tuples, b->scan_tmp.p, s))) return st;

@@ -16,6 +16,8 @@ CASES = {
     "R_grid128": (lambda: S.curved_triangles(4, seed=7), dict(max_depth=4, grid_res=128)),
     "T": (lambda: S.curved_triangles(4, seed=7, chain="T", eta=1.0 / 1.5), dict(max_depth=4)),
     "RR": (lambda: S.double_mirror(), dict(max_depth=4)),
+    # many leaves per tuple: the query's run bounds are rebuilt on load
+    "RR_walls": (lambda: S.facing_walls(4), dict(max_depth=4)),
     "R_area": (lambda: S.area_light(S.flat_mirror(), [0.5, 0.0, 0.0], [0.0, 0.3, 0.0]), dict(max_depth=3)),
 }
 

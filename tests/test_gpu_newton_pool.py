@@ -3,7 +3,9 @@ over a wave's lanes, FP32 passes of a few iterations, FP64 polish 64 at a
 time) against the kernel that gives each lane one pair for all of its starts:
 the per-start arithmetic, the start order of the per-pair root sum and the
 deduplication are the same, so estimates, per-point statistics and work
-counters must agree bit for bit, for every pass length and chain."""
+counters must agree bit for bit, for every pass length and chain (and, for
+two reflections, with the pooled kernel testing runs of leaves before their
+leaves)."""
 import numpy as np
 import pytest
 
@@ -48,6 +50,11 @@ def test_pooled_newton_matches_lane_per_pair(bbc, name, exhaustive):
     pts = torch.as_tensor(S.receiver_points(sc, grid), device="cuda")
     mode = bbc.QUERY_STAGED | (bbc.QUERY_EXHAUSTIVE if exhaustive else 0)
     print(name, "exhaustive" if exhaustive else "sampled", "points", pts.shape[1], flush=True)
+    if name == "walls":
+        # tuples of 12 leaves or more: the two-reflection kernel tests the
+        # unions of their runs of 8 leaves before the leaves themselves
+        t = B.leaves()["tuple"]
+        assert np.bincount(t).max() >= 12
     E0, st0, h0 = _run(bbc, B, pts, spp, 0, mode)
     assert h0["n_roots"] > 0
     for steps, results in ((1, 96), (3, 96), (4, 96), (20, 96), (4, 1), (2, 5)):
