@@ -422,6 +422,23 @@ __device__ double tuple_irradiance(const QueryArgs& a, uint32_t T, const Target&
   return rs.ET;
 }
 
+// Inclusive prefix maximum over the 64 lanes: shifts within each row of 16
+// lanes, then the last lane of row 0 (row 2) into rows 1 and 3 and the last
+// lane of row 1 into rows 2 and 3 (DPP row_bcast); lanes without a source get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROWS, 0xF, false));
+}
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+  v = max(v, dpp_u32<0x111, 0xF>(v));  // row_shr:1
+  v = max(v, dpp_u32<0x112, 0xF>(v));  // row_shr:2
+  v = max(v, dpp_u32<0x114, 0xF>(v));  // row_shr:4
+  v = max(v, dpp_u32<0x118, 0xF>(v));  // row_shr:8
+  v = max(v, dpp_u32<0x142, 0xA>(v));  // row_bcast:15
+  v = max(v, dpp_u32<0x143, 0xC>(v));  // row_bcast:31
+  return v;
+}
+
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, int lane) {
   uint32_t inc = v;
 #pragma unroll
@@ -977,6 +994,7 @@ struct NewtonPool {
   static constexpr bool RUNS = CH == BBC_CHAIN_RR;
   static constexpr int NQ = RUNS ? kRunQ : 1, NW = RUNS ? BBC_WAVE : 1;
   uint32_t lb[BBC_WAVE], lscan[BBC_WAVE + 1];
+  uint32_t mark[BBC_WAVE];  // pair + 1 at the lane offset where its units start in a window
   uint32_t lend[NW], lg0[NW];  // leaf range end, first run (or none)
   uint32_t redo[BBC_WAVE];
   uint32_t gq[NQ];  // runs whose union holds their pair's target, leaves not tested yet
@@ -1196,13 +1214,18 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
           const uint32_t j = scan + uint32_t(lane);
           bool hit = false;
           uint32_t g = 0;
+          // the pair whose units hold j, the last with lscan[p] <= j (unit
+          // starts are non-decreasing over the pairs): each pair with units
+          // that start inside the window marks its offset, and the lanes take
+          // the largest mark at or before them, or else the count of pairs
+          // that start at or before the window's first slot
+          L.mark[lane] = 0u;
+          if (units > 0u && ex - scan < uint32_t(BBC_WAVE)) L.mark[ex - scan] = uint32_t(lane) + 1u;
+          const uint32_t c0 = uint32_t(__popcll(__ballot(ex <= scan)));
+          __syncthreads();
+          const uint32_t pm = wave_incl_max(max(L.mark[lane], c0));
           if (j < tot) {
-            int lo = 0, hi = BBC_WAVE - 1;  // the pair whose slots hold j: the last with lscan[p] <= j
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (L.lscan[mid] <= j) lo = mid; else hi = mid - 1;
-            }
-            p = uint32_t(lo);
+            p = pm - 1u;
             const uint32_t off = j - L.lscan[p];
             if constexpr (RUNS) {
               const uint32_t g0 = L.lg0[p];
