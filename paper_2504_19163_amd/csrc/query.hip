@@ -987,7 +987,14 @@ template <int CH, bool AREA = false>
 struct NewtonPool {
   static constexpr int NF = CH == BBC_CHAIN_RR ? 48 : 28;  // record floats Newton reads
   static constexpr int RS = NF + 1;                         // odd row stride: rows of different pairs do not share banks
-  float rec[BBC_WAVE * RS];
+  // the two-reflection kernel reads its pairs' records from global memory
+  // (cache hits: 64 records of 256 bytes per batch) and keeps only their root
+  // boxes and tuples here, which lets eight of its workgroups share a
+  // compute unit's LDS instead of six
+  static constexpr bool GREC = CH == BBC_CHAIN_RR;
+  float rec[GREC ? 1 : BBC_WAVE * RS];
+  float4 root[GREC ? BBC_WAVE : 1];
+  uint32_t tT[GREC ? BBC_WAVE : 1];
   double lx[AREA ? BBC_WAVE : 1], ly[AREA ? BBC_WAVE : 1], lz[AREA ? BBC_WAVE : 1];  // FP64 light points
   float tu[BBC_WAVE], tv[BBC_WAVE];
   double tud[BBC_WAVE], tvd[BBC_WAVE];
@@ -1019,7 +1026,7 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
   constexpr bool RR = CH == BBC_CHAIN_RR;
   using Pool = NewtonPool<CH, AREA>;
   constexpr int NF = Pool::NF, RS = Pool::RS, NREC = RR ? kRecFloatsRR : kRecFloats;
-  constexpr bool RUNS = Pool::RUNS;
+  constexpr bool RUNS = Pool::RUNS, GREC = Pool::GREC;
   __shared__ Pool L;
   const QueryArgs& a = s.q;
   const int lane = int(threadIdx.x);
@@ -1073,17 +1080,22 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
     L.redo[lane] = 0u;
     // the rest of the record (the root box is already here) stays in
     // registers until the first refill is under way
-    float4 rq[NF / 4];
+    float4 rq[GREC ? 1 : NF / 4];
     if (valid) {
-      const float4* r4 = reinterpret_cast<const float4*>(a.rec + size_t(T) * NREC);
+      if constexpr (GREC) {
+        L.root[lane] = nRoot;
+        L.tT[lane] = T;
+      } else {
+        const float4* r4 = reinterpret_cast<const float4*>(a.rec + size_t(T) * NREC);
 #pragma unroll
-      for (int q = 0; q < NF / 4; ++q)
-        if (q != 6) rq[q] = r4[q];
-      float* R = &L.rec[lane * RS];
-      R[24] = nRoot.x;
-      R[25] = nRoot.y;
-      R[26] = nRoot.z;
-      R[27] = nRoot.w;
+        for (int q = 0; q < NF / 4; ++q)
+          if (q != 6) rq[q] = r4[q];
+        float* R = &L.rec[lane * RS];
+        R[24] = nRoot.x;
+        R[25] = nRoot.y;
+        R[26] = nRoot.z;
+        R[27] = nRoot.w;
+      }
       L.lb[lane] = nLb;
       if constexpr (RUNS) {
         L.lend[lane] = nLb + cnt;
@@ -1101,8 +1113,15 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
     if (lane == BBC_WAVE - 1) L.lscan[BBC_WAVE] = tot;
     __syncthreads();
     bool stored = false;
+    // the tuple record of pair p (the root box at floats 24-27)
+    auto recp = [&](uint32_t p) -> const float* {
+      if constexpr (GREC)
+        return a.rec + size_t(L.tT[p]) * NREC;
+      else
+        return &L.rec[p * RS];
+    };
     auto store_rec = [&]() {
-      if (valid) {
+      if (!GREC && valid) {
         float* R = &L.rec[lane * RS];
 #pragma unroll
         for (int q = 0; q < NF / 4; ++q) {
@@ -1133,7 +1152,7 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
       if (uint32_t(lane) < n) {
         p = L.cp[lane];
         kk = L.ck[lane];
-        TupleGeom<double> Gd = tuple_geom_rec<double, RR>(&L.rec[p * RS], a.sc);
+        TupleGeom<double> Gd = tuple_geom_rec<double, RR>(recp(p), a.sc);
         if constexpr (AREA) Gd.x0 = mk(L.lx[p], L.ly[p], L.lz[p]);
         if constexpr (RR)
           ok = polish64_called<CH>(Gd, L.tud[p], L.tvd[p], L.cu[lane], L.cv[lane], ud, vd, E, wc);
@@ -1194,8 +1213,13 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
           const double ud = L.tud[p], vd = L.tvd[p];
           if (ud >= uk.x && ud <= uk.y && vd >= uk.z && vd <= uk.w) {
             take = true;
-            const float* R = &L.rec[p * RS];
-            st = start_of(code, R[24], R[25], R[26], R[27]);
+            if constexpr (GREC) {
+              const float4 r = L.root[p];
+              st = start_of(code, r.x, r.y, r.z, r.w);
+            } else {
+              const float* R = &L.rec[p * RS];
+              st = start_of(code, R[24], R[25], R[26], R[27]);
+            }
             ++wc.starts;
           }
         };
@@ -1294,7 +1318,7 @@ k_stage_newton_pool(StagedArgs s, const uint32_t* total, uint32_t* redo_n,
         const uint32_t meta = L.pmeta[q];
         p = meta & 0xffu;
         st.it = int(meta >> 8);
-        const TupleGeom<float> Gf = tuple_geom_rec<float, RR>(&L.rec[p * RS], a.sc);
+        const TupleGeom<float> Gf = tuple_geom_rec<float, RR>(recp(p), a.sc);
         status = newton32<CH>(Gf, L.tu[p], L.tv[p], st, steps, wc);
       }
       head = (head + tk) % uint32_t(kPool);
