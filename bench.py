@@ -86,13 +86,13 @@ COUNTERS = {
         sha256="43fa6aa2f1af37c4b7bee41c7be93125528047cd0c57e94723b898cb2dc79ec6",
         fetch_kib=71004.8, write_kib=149273.8, fetch_scale=262144.0 / 131088.625, write_scale=1.0),
     # the pooled Newton kernels of the serving stream, mean per launch over the
-    # run's launches of all three chains (394 counted for FETCH_SIZE, 393 for
+    # run's launches of all three chains (394 counted for FETCH_SIZE and for
     # WRITE_SIZE)
     # (profiles/serving_stream_three_scenes_newton_hbm_counters.md)
     "newton_stream": dict(
         sources=['paper_2504_19163_amd/csrc/query.hip', 'paper_2504_19163_amd/csrc/path_dev.hpp', 'paper_2504_19163_amd/csrc/geom_dev.hpp', 'paper_2504_19163_amd/csrc/dev_common.hpp', 'paper_2504_19163_amd/csrc/internal.hpp'],
-        sha256="efcc746f7311078f4d578a35c7fe2f5ae4497341f6ba0c1cfab77ebd3ef544bc",
-        fetch_kib=131869.5, write_kib=87877.2, fetch_scale=262144.0 / 131088.75, write_scale=1.0),
+        sha256="09ca6a363267e6405bb5aebd4cb86e3cf93830e5c84fb2236b09f23d8036dfd5",
+        fetch_kib=136089.3, write_kib=89214.7, fetch_scale=262144.0 / 131088.9375, write_scale=1.0),
 }
 
 
