@@ -988,7 +988,7 @@ struct NewtonPool {
   static constexpr int NF = CH == BBC_CHAIN_RR ? 48 : 28;  // record floats Newton reads
   static constexpr int RS = NF + 1;                         // odd row stride: rows of different pairs do not share banks
   // the two-reflection kernel reads its pairs' records from global memory
-  // (cache hits: 64 records of 256 bytes per batch) and keeps only their root
+  // (cache hits: 64 records of 192 bytes per batch) and keeps only their root
   // boxes and tuples here, which lets eight of its workgroups share a
   // compute unit's LDS instead of six
   static constexpr bool GREC = CH == BBC_CHAIN_RR;
