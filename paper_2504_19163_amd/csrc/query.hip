@@ -843,7 +843,7 @@ __global__ void __launch_bounds__(64) k_stage_fill(StagedArgs s) {
 // in the same order as from the one-wave-per-point kernels above.  The count
 // pass draws the Bernoulli decisions (one Philox evaluation per candidate) and
 // keeps them as bits; the fill pass reads the bits instead of drawing again.
-constexpr int kSelLanes = 16, kSelAhead = 4;
+constexpr int kSelLanes = 16, kSelAhead = 8;  // chunks whose reads go out together
 template <bool FILL>
 __global__ void __launch_bounds__(64) k_stage_select16(StagedArgs s, uint32_t* sel) {
   constexpr int GL = kSelLanes, NG = BBC_WAVE / GL;
