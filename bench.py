@@ -91,8 +91,8 @@ COUNTERS = {
     # (profiles/serving_stream_three_scenes_newton_hbm_counters.md)
     "newton_stream": dict(
         sources=['paper_2504_19163_amd/csrc/query.hip', 'paper_2504_19163_amd/csrc/path_dev.hpp', 'paper_2504_19163_amd/csrc/geom_dev.hpp', 'paper_2504_19163_amd/csrc/dev_common.hpp', 'paper_2504_19163_amd/csrc/internal.hpp'],
-        sha256="4ca865f6b0355727b39df9bcb0802770d8fbc3cc9108b8faacf4b41119dae3d8",
-        fetch_kib=136089.3, write_kib=89214.7, fetch_scale=262144.0 / 131088.9375, write_scale=1.0),
+        sha256="eecbcd64d127a02780a320f12d58cca114571f7c3bfa99498cce820dcaa700ce",
+        fetch_kib=135773.6, write_kib=89223.6, fetch_scale=262144.0 / 131088.9375, write_scale=1.0),
 }
 
 
